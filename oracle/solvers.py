@@ -1,0 +1,260 @@
+"""Oracle: MR smoother, CGNR coarsest solve, null-vector setup, V-cycle, FGCR(8).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+Paper sources:
+  * V(m,n)-cycle: m pre- and n post-relaxations per level, recursion down to
+    a solve on the coarsest grid ("Adaptive Multigrid").
+  * Relaxation: a minimal-residual Krylov smoother with under-relaxation
+    omega = 0.9 that reduces the residual in the D^dag D norm ("Formulating an
+    algorithm").  Here each step is GMRES(1), i.e. MR, a fixed number of
+    times (4 pre, 4 post).
+  * Coarsest grid: CG on the normal equations to relative accuracy 1e-3
+    ("Numerical Results").  D_c^dag is the plain adjoint of the stencil.
+  * Outer solver: flexible GCR with restart length 8, because the
+    preconditioner is non-stationary ("Formulating an algorithm").
+  * Setup stage 1: relaxation applied to random vectors on A x = 0 gives
+    the initial prototypes, which are then block-orthonormalised.
+Readings: one setup round = one smoother application (n_s MR steps) on
+D e = 0 started from the current vector, i.e. v <- v - MR(D, D v), then
+v <- v / ||v||; the pre-smoother residual entering restriction is the MR
+recursion's residual; FGCR restarts every 8 with the true residual b - D x
+and orthogonalises by modified Gram-Schmidt.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import coarse as co
+from . import transfer as tr
+from . import wilson
+
+
+def _dot(a, b):
+    return np.vdot(a.ravel(), b.ravel())
+
+
+def _nrm2(a):
+    return float(np.real(np.vdot(a.ravel(), a.ravel())))
+
+
+def mr(A, b, steps: int, omega: float = 0.9):
+    """MR from x = 0: q = A r, alpha = <q,r>/<q,q>, x += w alpha r, r -= w alpha q.
+    Returns (x, r) with r the recursively updated residual."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    for _ in range(steps):
+        q = A(r)
+        qq = _nrm2(q)
+        if qq == 0.0:
+            break
+        a = omega * _dot(q, r) / qq
+        x = x + a * r
+        r = r - a * q
+    return x, r
+
+
+def mr_batch(A, b, steps: int, omega: float = 0.9):
+    """MR applied independently to each b[k] of a batch (per-vector scalars)."""
+    xs, rs = [], []
+    for k in range(b.shape[0]):
+        x, r = mr(A, b[k], steps, omega)
+        xs.append(x)
+        rs.append(r)
+    return np.stack(xs), np.stack(rs)
+
+
+def cgnr(A, Adag, b, tol: float = 1e-3, maxiter: int = 1000):
+    """CG on A^dag A e = A^dag b from e = 0; stop when ||b - A e|| <= tol ||b||
+    (recursive residual).  Returns (e, iterations)."""
+    e = np.zeros_like(b)
+    r = b.copy()
+    nb = np.sqrt(_nrm2(b))
+    if nb == 0.0:
+        return e, 0
+    z = Adag(r)
+    p = z.copy()
+    zz = _nrm2(z)
+    it = 0
+    while it < maxiter:
+        w = A(p)
+        ww = _nrm2(w)
+        if ww == 0.0:
+            break
+        alpha = zz / ww
+        e = e + alpha * p
+        r = r - alpha * w
+        it += 1
+        if np.sqrt(_nrm2(r)) <= tol * nb:
+            break
+        z = Adag(r)
+        zz_new = _nrm2(z)
+        beta = zz_new / zz
+        zz = zz_new
+        p = z + beta * p
+    return e, it
+
+
+def relax_nullspace(A, starts, rounds: int, steps: int, omega: float = 0.9):
+    """Setup stage 1: v <- v - MR(A, A v, steps), then v <- v/||v||, `rounds` times."""
+    V = np.array(starts, dtype=np.complex128, copy=True)
+    for _ in range(rounds):
+        for k in range(V.shape[0]):
+            x, _r = mr(A, A(V[k]), steps, omega)
+            V[k] = V[k] - x
+            V[k] = V[k] / np.sqrt(_nrm2(V[k]))
+    return V
+
+
+@dataclass
+class MGParams:
+    blocks: list = field(default_factory=lambda: [(4, 4, 4, 4)])
+    nv: list = field(default_factory=lambda: [8])
+    setup_rounds: int = 5
+    setup_mr_steps: int = 4
+    omega: float = 0.9
+    pre: int = 4
+    post: int = 4
+    coarse_tol: float = 1e-3
+    coarse_maxiter: int = 1000
+    gcr_restart: int = 8
+    max_iter: int = 10000
+    antiperiodic_t: bool = True
+
+
+@dataclass
+class Level:
+    geom: tr.BlockGeometry      # aggregation of this level's lattice
+    Pb: np.ndarray              # [Vc, 2, rows, Nv]
+    Rc: np.ndarray              # coarse coefficients V_c (QR R factors)
+    X: np.ndarray               # coarse operator of the next level
+    Y: np.ndarray
+    nullvecs: np.ndarray
+
+
+class Hierarchy:
+    """Adaptive MG hierarchy: level 0 = fine Wilson operator, level l >= 1 =
+    Galerkin coarse stencil of level l-1."""
+
+    def __init__(self, U, m, params: MGParams, levels):
+        self.U, self.m, self.p, self.levels = U, m, params, levels
+        self.stats = dict(fine_D=0, coarse_apply=0, cgnr_iters=[])
+
+    # operators ------------------------------------------------------------
+    def op(self, lvl: int):
+        if lvl == 0:
+            def A(v):
+                self.stats["fine_D"] += 1
+                return wilson.apply_D(self.U, v, self.m, self.p.antiperiodic_t)
+            return A
+        L = self.levels[lvl - 1]
+
+        def Ac(v):
+            self.stats["coarse_apply"] += 1
+            return co.coarse_apply(L.X, L.Y, v)
+        return Ac
+
+    def op_dag(self, lvl: int):
+        L = self.levels[lvl - 1]
+
+        def Acd(v):
+            self.stats["coarse_apply"] += 1
+            return co.coarse_apply_dag(L.X, L.Y, v)
+        return Acd
+
+    def restrict(self, lvl, f):
+        L = self.levels[lvl]
+        g = tr.fine_to_generic(f) if lvl == 0 else f
+        return tr.restrict(L.Pb, L.geom, g)
+
+    def prolong(self, lvl, ec):
+        L = self.levels[lvl]
+        g = tr.prolong(L.Pb, L.geom, ec)
+        return tr.generic_to_fine(g) if lvl == 0 else g
+
+    # V-cycle (a12) --------------------------------------------------------
+    def vcycle(self, r, lvl: int = 0):
+        p = self.p
+        nlev = len(self.levels) + 1
+        if lvl == nlev - 1:
+            e, it = cgnr(self.op(lvl), self.op_dag(lvl), r, p.coarse_tol, p.coarse_maxiter)
+            self.stats["cgnr_iters"].append(it)
+            return e
+        A = self.op(lvl)
+        x, rho = mr(A, r, p.pre, p.omega)
+        ec = self.vcycle(self.restrict(lvl, rho), lvl + 1)
+        x = x + self.prolong(lvl, ec)
+        rho = r - A(x)
+        x2, _ = mr(A, rho, p.post, p.omega)
+        return x + x2
+
+
+def mg_setup(U, m, params: MGParams, starts, coarse_starts=None):
+    """Two- or three-level setup: relaxation of random starts, block QR, Galerkin."""
+    levels = []
+    h = Hierarchy(U, m, params, levels)
+    L = tuple(reversed(U.shape[1:5]))
+    geom = tr.BlockGeometry(L, params.blocks[0])
+    V = relax_nullspace(h.op(0), starts, params.setup_rounds, params.setup_mr_steps, params.omega)
+    Pb, Rc = tr.block_qr(np.moveaxis(geom.blockify(tr.fine_to_generic(V)), 0, -1))
+    X, Y = co.galerkin_fine(U, m, Pb, geom, params.antiperiodic_t)
+    levels.append(Level(geom, Pb, Rc, X, Y, V))
+    for lv in range(1, len(params.blocks)):
+        geom2 = tr.BlockGeometry(levels[-1].geom.Lc, params.blocks[lv])
+        V2 = relax_nullspace(h.op(lv), coarse_starts, params.setup_rounds,
+                             params.setup_mr_steps, params.omega)
+        Pb2, Rc2 = tr.block_qr(np.moveaxis(geom2.blockify(V2), 0, -1))
+        X2, Y2 = co.galerkin_coarse(levels[-1].X, levels[-1].Y, Pb2, geom2)
+        levels.append(Level(geom2, Pb2, Rc2, X2, Y2, V2))
+    h.stats = dict(fine_D=0, coarse_apply=0, cgnr_iters=[])
+    return h
+
+
+def fgcr(A, K, b, tol: float, restart: int = 8, max_iter: int = 10000, x0=None):
+    """Flexible GCR(restart): z_j = K(r), w_j = A z_j, MGS against previous w,
+    normalise, alpha = <w_j, r>, x += alpha z_j, r -= alpha w_j; restart with
+    the true residual.  Converged when ||b - A x|| <= tol ||b||.
+    Returns (x, iterations, converged, residual history)."""
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    nb = np.sqrt(_nrm2(b))
+    r = b - A(x) if x0 is not None else b.copy()
+    hist = [np.sqrt(_nrm2(r)) / nb]
+    it = 0
+    if hist[0] <= tol:
+        return x, 0, True, hist
+    while it < max_iter:
+        Z, W = [], []
+        for j in range(restart):
+            z = K(r)
+            w = A(z)
+            for i in range(j):
+                beta = _dot(W[i], w)
+                w = w - beta * W[i]
+                z = z - beta * Z[i]
+            nw = np.sqrt(_nrm2(w))
+            w = w / nw
+            z = z / nw
+            W.append(w)
+            Z.append(z)
+            alpha = _dot(w, r)
+            x = x + alpha * z
+            r = r - alpha * w
+            it += 1
+            rn = np.sqrt(_nrm2(r)) / nb
+            hist.append(rn)
+            if rn <= tol or it >= max_iter:
+                break
+        r = b - A(x)
+        rn = np.sqrt(_nrm2(r)) / nb
+        hist[-1] = rn
+        if rn <= tol:
+            return x, it, True, hist
+    return x, it, False, hist
+
+
+def mg_solve(h: Hierarchy, b, tol: float = 1e-10):
+    p = h.p
+    A = h.op(0)
+    return fgcr(A, lambda r: h.vcycle(r, 0), b, tol, p.gcr_restart, p.max_iter)

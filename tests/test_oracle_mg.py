@@ -1,0 +1,274 @@
+"""Pins of the oracle's multigrid pieces against definitions, invariants and
+brute force: aggregate maps, block QR (Eq. 4), R = P^dag with the chirality
+split (P^dag gamma_5 = sigma_3 P^dag), the Galerkin stencil against dense
+P^dag D P, sigma_3-Hermiticity, gauge invariance, the mass shift, the
+two-grid Galerkin orthogonality (Eq. 3), square-P exactness, MR/CGNR/FGCR
+against their defining properties and dense LU."""
+import itertools
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import coarse as co
+from oracle import solvers as so
+from oracle import transfer as tr
+from oracle import wilson as wi
+
+
+def _setup(L, b, nv, m=-0.2, eps=0.3, seed=0, rounds=2):
+    U = W.gauge_field(L, eps, seed)
+    p = so.MGParams(blocks=[b], nv=[nv], setup_rounds=rounds)
+    h = so.mg_setup(U, m, p, W.setup_starts(L, nv, seed))
+    return U, h
+
+
+# ---------------------------------------------------------------- maps (a4)
+@pytest.mark.parametrize("L,b", [((4, 4, 4, 4), (2, 2, 2, 2)), ((6, 4, 2, 8), (3, 2, 1, 4)), ((4, 4, 4, 4), (4, 4, 4, 4))])
+def test_maps_brute_force(L, b):
+    g = tr.BlockGeometry(L, b)
+    f2c, f2l, nbr, face = g.maps()
+    Lc = g.Lc
+    for i, (t, z, y, x) in enumerate(itertools.product(range(L[3]), range(L[2]), range(L[1]), range(L[0]))):
+        X = [x, y, z, t]
+        assert i == X[0] + L[0] * (X[1] + L[1] * (X[2] + L[2] * X[3]))
+        cc = [X[mu] // b[mu] for mu in range(4)]
+        o = [X[mu] % b[mu] for mu in range(4)]
+        assert f2c[i] == cc[0] + Lc[0] * (cc[1] + Lc[1] * (cc[2] + Lc[2] * cc[3]))
+        assert f2l[i] == o[0] + b[0] * (o[1] + b[1] * (o[2] + b[2] * o[3]))
+        for mu in range(4):
+            assert bool(face[i] >> (2 * mu) & 1) == (o[mu] == b[mu] - 1)
+            assert bool(face[i] >> (2 * mu + 1) & 1) == (o[mu] == 0)
+    for ic in range(g.Vc):
+        cc = [ic % Lc[0], ic // Lc[0] % Lc[1], ic // (Lc[0] * Lc[1]) % Lc[2], ic // (Lc[0] * Lc[1] * Lc[2])]
+        for mu in range(4):
+            for d, st in ((0, 1), (1, -1)):
+                n = list(cc)
+                n[mu] = (n[mu] + st) % Lc[mu]
+                assert nbr[ic, 2 * mu + d] == n[0] + Lc[0] * (n[1] + Lc[1] * (n[2] + Lc[2] * n[3]))
+
+
+def test_blockify_roundtrip_and_rows():
+    L, b = (4, 6, 2, 4), (2, 3, 1, 2)
+    g = tr.BlockGeometry(L, b)
+    f = W.gaussian_spinor(L, 3)
+    F = tr.fine_to_generic(f)
+    B = g.blockify(F)
+    assert np.array_equal(g.unblockify(B), F)
+    f2c, f2l, _, _ = g.maps()
+    flat = F.reshape(-1, 12)
+    for i in range(g.V):
+        for comp in range(12):
+            chi, j = divmod(comp, 6)
+            assert B[f2c[i], chi, f2l[i] * 6 + j] == flat[i, comp]
+
+
+# ---------------------------------------------------------------- block QR (a6)
+def test_block_qr_matches_library_qr():
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((5, 2, 30, 7)) + 1j * rng.standard_normal((5, 2, 30, 7))
+    Q, R = tr.block_qr(A)
+    for c in range(5):
+        for x in range(2):
+            q, r = np.linalg.qr(A[c, x])
+            ph = np.diag(r) / np.abs(np.diag(r))          # make diag(R) positive real
+            q = q * ph[None, :]
+            r = np.conj(ph)[:, None] * r
+            assert np.abs(Q[c, x] - q).max() < 1e-13
+            assert np.abs(R[c, x] - r).max() < 1e-12
+            assert np.allclose(np.triu(R[c, x]), R[c, x])
+            assert np.all(np.diag(R[c, x]).real > 0) and np.all(np.diag(R[c, x]).imag == 0)
+
+
+def test_block_qr_rank_deficient():
+    A = np.ones((1, 2, 6, 3), dtype=np.complex128)
+    with pytest.raises(ValueError):
+        tr.block_qr(A)
+
+
+# ---------------------------------------------------------------- P, R (a7, a8)
+def test_prolongator_invariants():
+    L, b, nv = (4, 4, 4, 4), (2, 2, 2, 2), 4
+    U, h = _setup(L, b, nv)
+    lv = h.levels[0]
+    g = lv.geom
+    P = tr.P_dense(lv.Pb, g)
+    assert np.abs(P.conj().T @ P - np.eye(P.shape[1])).max() < 1e-14          # Eq. 4
+    Vn = tr.fine_to_generic(lv.nullvecs).reshape(nv, -1).T                     # P V_c = V
+    Vc = np.zeros((P.shape[1], nv), dtype=np.complex128)
+    for c in range(g.Vc):
+        for x in range(2):
+            Vc[(c * 2 + x) * nv:(c * 2 + x + 1) * nv, :] = lv.Rc[c, x]
+    assert np.abs(P @ Vc - Vn).max() < 1e-13
+    g5 = np.kron(np.eye(g.V), np.kron(wi.GAMMA5, np.eye(3)))
+    s3 = np.kron(np.eye(g.Vc), np.diag([1.0] * nv + [-1.0] * nv))
+    assert np.abs(P.conj().T @ g5 - s3 @ P.conj().T).max() < 1e-15            # chirality kept
+    r = W.gaussian_spinor(L, 5)
+    rc = h.restrict(0, r)
+    assert np.abs(rc.ravel() - P.conj().T @ r.ravel()).max() < 1e-13          # R = P^dag
+    e = h.prolong(0, rc)
+    assert np.abs(e.ravel() - P @ rc.ravel()).max() < 1e-13
+    assert np.abs(h.restrict(0, e) - rc).max() < 1e-13                         # P^dag P = I
+
+
+# ---------------------------------------------------------------- Galerkin (a9, a10)
+@pytest.mark.parametrize("L,b,nv", [((4, 4, 4, 4), (2, 2, 2, 2), 4), ((2, 2, 2, 4), (1, 1, 1, 2), 3),
+                                    ((4, 2, 4, 4), (4, 2, 2, 4), 5)])
+def test_galerkin_equals_dense(L, b, nv):
+    U, h = _setup(L, b, nv, m=-0.3, rounds=1)
+    lv = h.levels[0]
+    P = tr.P_dense(lv.Pb, lv.geom)
+    D = wi.D_dense(U, -0.3)
+    Dc = co.coarse_dense(lv.X, lv.Y)
+    ref = P.conj().T @ D @ P
+    assert np.abs(Dc - ref).max() < 1e-13 * np.abs(ref).max()
+    # sigma_3 Hermiticity of the assembled operator, and blockwise per face pair
+    s3 = np.kron(np.eye(lv.geom.Vc), np.diag([1.0] * nv + [-1.0] * nv))
+    assert np.abs(Dc.conj().T - s3 @ Dc @ s3).max() < 1e-13
+    sig = np.diag([1.0] * nv + [-1.0] * nv)
+    for mu in range(4):
+        Yp, Ym = lv.Y[2 * mu], lv.Y[2 * mu + 1]
+        Ymsh = np.roll(Ym, -1, axis=co.SITE_AXIS[mu] - 1)    # Y_-mu(x_c + mu)
+        assert np.abs(Ymsh - sig @ np.conj(np.swapaxes(Yp, -1, -2)) @ sig).max() < 1e-13
+
+
+def test_coarse_dagger_is_adjoint():
+    U, h = _setup((4, 4, 4, 4), (2, 2, 2, 2), 3, rounds=1)
+    lv = h.levels[0]
+    Dc = co.coarse_dense(lv.X, lv.Y)
+    v = np.random.default_rng(2).standard_normal(Dc.shape[0]) + 0j
+    got = co.coarse_apply_dag(lv.X, lv.Y, v.reshape(lv.X.shape[:-1])).ravel()
+    assert np.abs(got - Dc.conj().T @ v).max() < 1e-13
+    got2 = co.sigma3(co.coarse_apply(lv.X, lv.Y, co.sigma3(v.reshape(lv.X.shape[:-1])))).ravel()
+    assert np.abs(got2 - Dc.conj().T @ v).max() < 1e-13
+
+
+def test_coarse_gauge_invariance():
+    """D_c(U^g, g V) = D_c(U, V): g is block-diagonal unitary, P -> g P."""
+    L, b, nv = (4, 4, 4, 4), (2, 2, 2, 2), 3
+    U = W.gauge_field(L, 0.3, 1)
+    V = W.setup_starts(L, nv, 1)
+    g = W.gauge_transform(L, 2)
+    geom = tr.BlockGeometry(L, b)
+
+    def build(Uu, Vv):
+        Pb, _ = tr.block_qr(np.moveaxis(geom.blockify(tr.fine_to_generic(Vv)), 0, -1))
+        return co.galerkin_fine(Uu, -0.2, Pb, geom)
+    X1, Y1 = build(U, V)
+    X2, Y2 = build(wi.gauge_transform_links(U, g), wi.gauge_transform_spinor(g, V))
+    assert np.abs(X1 - X2).max() < 1e-13 and np.abs(Y1 - Y2).max() < 1e-13
+
+
+def test_mass_shift():
+    """X(m + d) - X(m) = d I and Y unchanged (P^dag P = I)."""
+    L, b, nv = (4, 4, 4, 4), (2, 2, 2, 2), 3
+    U, h = _setup(L, b, nv, rounds=1)
+    lv = h.levels[0]
+    X2, Y2 = co.galerkin_fine(U, -0.2 + 0.37, lv.Pb, lv.geom)
+    assert np.abs(X2 - lv.X - 0.37 * np.eye(2 * nv)).max() < 1e-13
+    assert np.abs(Y2 - lv.Y).max() < 1e-14
+
+
+# ---------------------------------------------------------------- two-grid (Eq. 3)
+def test_galerkin_orthogonality_exact_coarse_solve():
+    """With an exact coarse solve, P^dag (r - D P D_c^{-1} P^dag r) = 0."""
+    L, b, nv = (4, 4, 4, 4), (2, 2, 2, 2), 4
+    U, h = _setup(L, b, nv, rounds=1)
+    lv = h.levels[0]
+    P = tr.P_dense(lv.Pb, lv.geom)
+    D = wi.D_dense(U, -0.2)
+    Dc = co.coarse_dense(lv.X, lv.Y)
+    r = W.gaussian_spinor(L, 7).ravel()
+    e = P @ np.linalg.solve(Dc, P.conj().T @ r)
+    assert np.abs(P.conj().T @ (r - D @ e)).max() < 1e-12 * np.abs(r).max()
+
+
+def test_square_prolongator_exact():
+    """Blocks of one site with Nv = 6 make P unitary: one V-cycle with an
+    (exactly solved) coarse grid reproduces D^{-1} b."""
+    L = (2, 2, 2, 4)
+    m = -0.1
+    U = W.gauge_field(L, 0.3, 0)
+    p = so.MGParams(blocks=[(1, 1, 1, 1)], nv=[6], setup_rounds=1, coarse_tol=1e-14,
+                    coarse_maxiter=5000, pre=0, post=0)
+    h = so.mg_setup(U, m, p, W.setup_starts(L, 6, 0))
+    b = W.gaussian_spinor(L, 1)
+    x, it, conv, _ = so.mg_solve(h, b, 1e-12)
+    xe = np.linalg.solve(wi.D_dense(U, m), b.ravel())
+    assert conv and it <= 2
+    assert np.linalg.norm(x.ravel() - xe) / np.linalg.norm(xe) < 1e-11
+
+
+# ---------------------------------------------------------------- smoother / Krylov
+def test_mr_residual_nonincreasing_and_step():
+    L = (4, 4, 2, 4)
+    U = W.gauge_field(L, 0.3, 0)
+    A = lambda v: wi.apply_D(U, v, -0.2)  # noqa: E731
+    b = W.gaussian_spinor(L, 1)
+    prev = np.linalg.norm(b)
+    for n in range(1, 6):
+        x, r = so.mr(A, b, n, 0.9)
+        rn = np.linalg.norm(b - A(x))
+        assert np.abs(r - (b - A(x))).max() < 1e-12 * prev
+        assert rn <= prev * (1 + 1e-14)
+        prev = rn
+    # one step equals the minimiser of ||b - a A b|| (closed form) times omega
+    q = A(b)
+    a = np.vdot(q.ravel(), b.ravel()) / np.vdot(q.ravel(), q.ravel())
+    x1, _ = so.mr(A, b, 1, 0.9)
+    assert np.abs(x1 - 0.9 * a * b).max() < 1e-14
+
+
+def test_cgnr_matches_lu():
+    U, h = _setup((4, 4, 4, 4), (2, 2, 2, 2), 3, rounds=1)
+    lv = h.levels[0]
+    Dc = co.coarse_dense(lv.X, lv.Y)
+    rng = np.random.default_rng(3)
+    r = (rng.standard_normal(Dc.shape[0]) + 1j * rng.standard_normal(Dc.shape[0])).reshape(lv.X.shape[:-1])
+    A = lambda v: co.coarse_apply(lv.X, lv.Y, v)  # noqa: E731
+    Ad = lambda v: co.coarse_apply_dag(lv.X, lv.Y, v)  # noqa: E731
+    e, it = so.cgnr(A, Ad, r, tol=1e-3)
+    assert np.linalg.norm(r - A(e)) <= 1e-3 * np.linalg.norm(r)
+    e2, _ = so.cgnr(A, Ad, r, tol=1e-12, maxiter=5000)
+    ex = np.linalg.solve(Dc, r.ravel())
+    assert np.linalg.norm(e2.ravel() - ex) / np.linalg.norm(ex) < 1e-9
+
+
+def test_fgcr_mg_matches_lu_4444():
+    """Two-level FGCR(8)-MG on 4^4 against a dense LU solve."""
+    L, m = (4, 4, 4, 4), -0.2
+    U = W.gauge_field(L, 0.3, 0)
+    p = so.MGParams(blocks=[(2, 2, 2, 2)], nv=[4])
+    h = so.mg_setup(U, m, p, W.setup_starts(L, 4, 0))
+    b = W.gaussian_spinor(L, 0)
+    x, it, conv, hist = so.mg_solve(h, b, 1e-10)
+    D = wi.D_dense(U, m)
+    xe = np.linalg.solve(D, b.ravel())
+    kappa = np.linalg.cond(D)
+    assert conv
+    assert np.linalg.norm(b.ravel() - D @ x.ravel()) <= 1e-10 * np.linalg.norm(b) * 1.0001
+    assert np.linalg.norm(x.ravel() - xe) / np.linalg.norm(xe) < kappa * 1e-10
+    # residual non-increasing within each restart cycle (minimal residual property)
+    for j in range(1, len(hist)):
+        if j % 8 != 0:
+            assert hist[j] <= hist[j - 1] * (1 + 1e-12)
+
+
+def test_three_level_hierarchy_galerkin():
+    """Second-level Galerkin on the coarse stencil equals dense P2^dag D_c P2."""
+    L, m = (4, 4, 4, 8), -0.2
+    U = W.gauge_field(L, 0.3, 0)
+    p = so.MGParams(blocks=[(2, 2, 2, 2), (1, 1, 1, 2)], nv=[4, 3], setup_rounds=1)
+    starts = W.setup_starts(L, 4, 0)
+    cst = W.coarse_setup_starts((2, 2, 2, 4), 8, 3, 0)
+    h = so.mg_setup(U, m, p, starts, cst)
+    l1, l2 = h.levels
+    Dc1 = co.coarse_dense(l1.X, l1.Y)
+    P2 = tr.P_dense(l2.Pb, l2.geom)
+    assert np.abs(P2.conj().T @ P2 - np.eye(P2.shape[1])).max() < 1e-14
+    ref = P2.conj().T @ Dc1 @ P2
+    assert np.abs(co.coarse_dense(l2.X, l2.Y) - ref).max() < 1e-13 * np.abs(ref).max()
+    b = W.gaussian_spinor(L, 2)
+    x, it, conv, _ = so.mg_solve(h, b, 1e-10)
+    assert conv
+    assert np.linalg.norm(b - wi.apply_D(U, x, m)) <= 1.0001e-10 * np.linalg.norm(b)

@@ -1,0 +1,174 @@
+"""Seeded synthetic inputs for the Wilson-Dirac multigrid workloads.
+
+This module is shared by the CPU oracle tests and the GPU path.  It holds
+no arithmetic of the solver itself: it only draws random numbers and shapes
+them into gauge fields, sources and setup start vectors, and it lists the
+workload configurations (lattice, smearing width, Nv, block sizes, targets).
+
+Layouts (canonical, complex128, numpy C order, x fastest):
+  gauge field  U[mu, t, z, y, x, a, b]   mu = 0..3 = x, y, z, t
+  spinor       psi[..., t, z, y, x, s, c]
+Random streams: numpy PCG64 ``default_rng([seed, stream])`` with
+  stream 0 = gauge field, 1 = source, 2 = fine setup starts,
+  3 = network noise, 4 = level-1 setup starts, 5 = gauge transformations.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+
+STREAM_GAUGE = 0
+STREAM_SOURCE = 1
+STREAM_SETUP = 2
+STREAM_NOISE = 3
+STREAM_SETUP_L1 = 4
+STREAM_GTRANS = 5
+
+# Gell-Mann matrices, normalised tr(l_a l_b) = 2 delta_ab.
+_GM = np.zeros((8, 3, 3), dtype=np.complex128)
+_GM[0][0, 1] = _GM[0][1, 0] = 1
+_GM[1][0, 1] = -1j
+_GM[1][1, 0] = 1j
+_GM[2][0, 0] = 1
+_GM[2][1, 1] = -1
+_GM[3][0, 2] = _GM[3][2, 0] = 1
+_GM[4][0, 2] = -1j
+_GM[4][2, 0] = 1j
+_GM[5][1, 2] = _GM[5][2, 1] = 1
+_GM[6][1, 2] = -1j
+_GM[6][2, 1] = 1j
+_GM[7][0, 0] = _GM[7][1, 1] = 1 / np.sqrt(3)
+_GM[7][2, 2] = -2 / np.sqrt(3)
+GELL_MANN = _GM
+
+
+def rng(seed: int, stream: int) -> np.random.Generator:
+    return np.random.default_rng([int(seed), int(stream)])
+
+
+def _su3_from_algebra(a: np.ndarray, eps: float) -> np.ndarray:
+    """exp(i eps sum_k a_k lambda_k) for a batch of coefficient vectors
+    a[..., 8], via the eigen-decomposition of the Hermitian generator, then
+    projected onto SU(3): Gram-Schmidt of rows 0 and 1, row 2 = conj(r0 x r1).
+    """
+    shp = a.shape[:-1]
+    H = eps * np.tensordot(a.reshape(-1, 8), GELL_MANN, axes=([1], [0]))
+    w, W = np.linalg.eigh(H)
+    U = (W * np.exp(1j * w)[:, None, :]) @ np.conj(np.swapaxes(W, -1, -2))
+    r0 = U[:, 0, :]
+    r0 = r0 / np.linalg.norm(r0, axis=-1, keepdims=True)
+    r1 = U[:, 1, :]
+    r1 = r1 - np.sum(np.conj(r0) * r1, axis=-1, keepdims=True) * r0
+    r1 = r1 / np.linalg.norm(r1, axis=-1, keepdims=True)
+    r2 = np.conj(np.cross(r0, r1))
+    out = np.stack([r0, r1, r2], axis=1)
+    return out.reshape(shp + (3, 3))
+
+
+def gauge_field(L, eps: float, seed: int) -> np.ndarray:
+    """Random SU(3) links U = P_SU3 exp(i eps sum_k a_k lambda_k), a_k ~ N(0,1).
+
+    L = (Lx, Ly, Lz, Lt).  Returns complex128 [4, Lt, Lz, Ly, Lx, 3, 3].
+    Row index = colour at x, column index = colour at x + mu.
+    """
+    Lx, Ly, Lz, Lt = L
+    a = rng(seed, STREAM_GAUGE).standard_normal((4, Lt, Lz, Ly, Lx, 8))
+    return _su3_from_algebra(a, eps)
+
+
+def unit_gauge_field(L) -> np.ndarray:
+    Lx, Ly, Lz, Lt = L
+    U = np.zeros((4, Lt, Lz, Ly, Lx, 3, 3), dtype=np.complex128)
+    U[..., 0, 0] = U[..., 1, 1] = U[..., 2, 2] = 1.0
+    return U
+
+
+def gauge_transform(L, seed: int, eps: float = 1.0) -> np.ndarray:
+    """Random site-local SU(3) matrices g[t, z, y, x, 3, 3] (wide spread)."""
+    Lx, Ly, Lz, Lt = L
+    a = rng(seed, STREAM_GTRANS).standard_normal((Lt, Lz, Ly, Lx, 8))
+    return _su3_from_algebra(a, eps)
+
+
+def gaussian_spinor(L, seed: int, stream: int = STREAM_SOURCE, batch=()) -> np.ndarray:
+    """Complex Gaussian spinor(s), re and im ~ N(0,1): [*batch, Lt, Lz, Ly, Lx, 4, 3]."""
+    Lx, Ly, Lz, Lt = L
+    g = rng(seed, stream)
+    shp = tuple(batch) + (Lt, Lz, Ly, Lx, 4, 3)
+    re = g.standard_normal(shp)
+    im = g.standard_normal(shp)
+    return re + 1j * im
+
+
+def setup_starts(L, nv: int, seed: int) -> np.ndarray:
+    """Nv Gaussian start vectors for the null-space relaxation: [Nv, Lt, Lz, Ly, Lx, 4, 3]."""
+    return gaussian_spinor(L, seed, STREAM_SETUP, batch=(nv,))
+
+
+def coarse_setup_starts(Lc, n_c: int, nv: int, seed: int) -> np.ndarray:
+    """Nv Gaussian start vectors on a coarse lattice: [Nv, Lct, Lcz, Lcy, Lcx, n_c]."""
+    Lx, Ly, Lz, Lt = Lc
+    g = rng(seed, STREAM_SETUP_L1)
+    shp = (nv, Lt, Lz, Ly, Lx, n_c)
+    return g.standard_normal(shp) + 1j * g.standard_normal(shp)
+
+
+def point_sources(L) -> np.ndarray:
+    """The 12 spin-colour point sources at the origin: [12, Lt, Lz, Ly, Lx, 4, 3],
+    source k = 3*s0 + c0 has a single 1 at (x=0, s0, c0)."""
+    Lx, Ly, Lz, Lt = L
+    b = np.zeros((12, Lt, Lz, Ly, Lx, 4, 3), dtype=np.complex128)
+    for k in range(12):
+        b[k, 0, 0, 0, 0, k // 3, k % 3] = 1.0
+    return b
+
+
+def noise_spinor(L, seed: int, step: int = 0) -> np.ndarray:
+    """Gaussian noise input of the null-vector proposal network."""
+    Lx, Ly, Lz, Lt = L
+    g = np.random.default_rng([int(seed), STREAM_NOISE, int(step)])
+    shp = (Lt, Lz, Ly, Lx, 4, 3)
+    return g.standard_normal(shp) + 1j * g.standard_normal(shp)
+
+
+# ---------------------------------------------------------------------------
+# Workload table.  Masses are stored in masses.json (written by the oracle's
+# Arnoldi mass-tuning script); "target" is the requested min Re lambda(D).
+# ---------------------------------------------------------------------------
+CONFIGS = {
+    "C0": dict(L=(8, 8, 8, 8), eps=0.2, seed=0, nv=[8], blocks=[(4, 4, 4, 4)],
+               targets=[0.05], source="gaussian", nrhs=1),
+    "C1": dict(L=(16, 16, 16, 32), eps=0.3, seed=0, nv=[20], blocks=[(4, 4, 4, 4)],
+               targets=[0.01], source="gaussian", nrhs=1),
+    "C2": dict(L=(24, 24, 24, 48), eps=0.3, seed=0, nv=[24], blocks=[(4, 4, 4, 4)],
+               targets=[0.005], source="point", nrhs=12),
+    "C3": dict(L=(32, 32, 32, 64), eps=0.35, seed=0, nv=[24, 24],
+               blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], targets=[0.1, 0.01, 0.001],
+               source="point", nrhs=12),
+}
+
+_MASS_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "masses.json")
+
+
+def load_masses() -> dict:
+    if not os.path.exists(_MASS_FILE):
+        return {}
+    with open(_MASS_FILE) as f:
+        return json.load(f)
+
+
+def mass_for(name: str, target: float | None = None) -> float:
+    """Mass giving min Re lambda(D) = target for workload `name`.
+
+    Uses the stored Arnoldi estimate of min Re lambda(D(m=0)); D(m) = D(0) + m,
+    so m = target - Re lambda_min(D(0)).
+    """
+    cfg = CONFIGS[name]
+    if target is None:
+        target = cfg["targets"][0]
+    rec = load_masses().get(name)
+    if rec is None:
+        raise KeyError(f"no stored Arnoldi estimate for workload {name}")
+    return float(target) - float(rec["re_lambda_min_m0"])
