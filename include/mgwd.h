@@ -1,0 +1,200 @@
+/* mgwd.h - C ABI of the MI355X adaptive multigrid solver for the lattice
+ * Wilson-Dirac system D(U) psi = b (Babich et al., "Adaptive multigrid
+ * algorithm for the lattice Wilson-Dirac operator", 2010).
+ *
+ * Plain C: every argument is a plain pointer (host or device, as stated per
+ * function), a size or a small struct.  No exception crosses this boundary;
+ * every entry point returns an int status (MG_OK = 0, MG_NOT_CONVERGED = 1,
+ * negative = error) and mg_last_error() gives a message for the calling
+ * thread.
+ *
+ * Canonical layouts at the boundary (complex128 = two doubles re, im; C
+ * order; x fastest; mu = 0,1,2,3 = x,y,z,t):
+ *   gauge field   U[4][Lt][Lz][Ly][Lx][3][3]   row = colour at x,
+ *                                               column = colour at x + mu
+ *   fine spinor   psi[nrhs][Lt][Lz][Ly][Lx][4][3]
+ *   coarse vector v[nrhs][Lct][Lcz][Lcy][Lcx][2*Nv]  component chi*Nv + k,
+ *                 chi = coarse chirality (sigma_3 = diag(+1_Nv, -1_Nv))
+ * Gamma matrices (chiral basis): gamma_k = [[0, -i s_k], [i s_k, 0]],
+ * gamma_4 = [[0, 1], [1, 0]], gamma_5 = diag(1, 1, -1, -1); chirality 0 =
+ * spins {0, 1}.  Time boundary antiperiodic when t_antiperiodic != 0: a hop
+ * across it carries a factor -1.
+ *
+ * Ownership: the caller owns every buffer it passes; device buffers need to
+ * stay valid only for the duration of the call (asynchronous calls: until
+ * the work enqueued on the stream has run).  mg_setup copies U into its own
+ * layout.  The context owns its prolongators, coarse operators, work
+ * vectors and graphs; mg_destroy frees them.
+ * Streams: work is enqueued on the hipStream_t argument (NULL = default
+ * stream).  wilson_apply, mg_restrict, mg_prolong and coarse_apply are
+ * asynchronous; mg_setup and mg_solve return after completion because their
+ * convergence decisions are taken on the host.
+ */
+#ifndef MGWD_H
+#define MGWD_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MG_OK 0
+#define MG_NOT_CONVERGED 1
+#define MG_EINVAL (-1)     /* null pointer, argument out of range          */
+#define MG_ESHAPE (-2)     /* block does not divide L, Nv too large, level  */
+#define MG_EHIP (-3)       /* HIP runtime error                             */
+#define MG_ENOMEM (-4)     /* device allocation failed                      */
+#define MG_ENONFINITE (-5) /* NaN/Inf in an input or a reduction            */
+#define MG_ENOTSUP (-6)    /* precision or feature combination not built    */
+#define MG_ERANK (-7)      /* rank-deficient aggregate in block QR          */
+
+#define MG_MAX_LEVELS 3
+#define MG_MAX_RHS 16
+
+typedef struct {
+  int L[4];            /* Lx, Ly, Lz, Lt                                    */
+  int t_antiperiodic;  /* 1: antiperiodic time boundary, 0: periodic       */
+} mg_lattice_t;
+
+typedef enum { MG_F64 = 0, MG_F32 = 1, MG_F16 = 2, MG_BF16 = 3 } mg_prec_t;
+
+typedef struct mg_ctx mg_ctx_t;
+
+typedef struct {
+  int n_levels;                      /* 2 or 3 (fine + coarse levels)        */
+  int block[MG_MAX_LEVELS - 1][4];   /* aggregate shape level l -> l+1       */
+  int nv[MG_MAX_LEVELS - 1];         /* null vectors defining level l -> l+1 */
+  int setup_rounds;                  /* relaxation rounds per vector (5)     */
+  int setup_mr_steps;                /* MR steps per round (4)               */
+  double omega;                      /* MR under-relaxation (0.9)            */
+  int pre, post;                     /* MR smoothing steps (4, 4)            */
+  double coarse_tol;                 /* coarsest CGNR relative tol (1e-3)    */
+  int coarse_maxiter;                /* coarsest CGNR cap (1000)             */
+  int gcr_restart;                   /* flexible GCR restart length (8)      */
+  int max_iter;                      /* outer iteration cap                  */
+  mg_prec_t precond_prec;            /* MG_F64, MG_F32 or MG_F16             */
+  int max_rhs;                       /* largest nrhs passed to mg_solve      */
+  /* Setup start vectors, DEVICE complex128, required:
+   *   init_vectors[0]: [nv[0]][Lt][Lz][Ly][Lx][4][3]
+   *   init_vectors[1]: [nv[1]][Lct][Lcz][Lcy][Lcx][2*nv[0]] (3 levels)    */
+  const void *init_vectors[MG_MAX_LEVELS - 1];
+} mg_params_t;
+
+typedef struct {
+  int iters[MG_MAX_RHS];        /* outer FGCR iterations per RHS             */
+  double rel_resid[MG_MAX_RHS]; /* final true ||b - D x|| / ||b|| per RHS    */
+  int n_fine_dslash;            /* fine D applications (per RHS summed)      */
+  int n_coarse_apply;           /* coarse stencil applications, all levels   */
+  int n_cgnr_iters;             /* coarsest CGNR iterations, summed          */
+  int n_vcycles;                /* preconditioner applications               */
+  double t_setup_s, t_solve_s;  /* wall time of the last setup / solve       */
+  /* Kernel timing (filled when mg_set_timing(ctx, 1) is on): summed device
+   * time in ms and launch counts of the fine stencil and coarse stencil.    */
+  double dslash_ms;   int dslash_launches;   int dslash_prec;
+  double coarse_ms;   int coarse_launches;   int coarse_prec;
+} mg_info_t;
+
+/* Fine Wilson operator out = D(U) in (Eq. 2) on nrhs canonical spinors.
+ * U, in, out: DEVICE complex128 canonical layouts (in and out may not
+ * alias).  prec selects the arithmetic of the stencil (MG_F64 or MG_F32;
+ * inputs and outputs stay complex128).  Stateless: converts to the
+ * library's internal site-blocked SoA layout and back on every call.     */
+int wilson_apply(const mg_lattice_t *lat, const void *U, double mass,
+                 const void *in, void *out, int nrhs, mg_prec_t prec,
+                 hipStream_t stream);
+
+/* Adaptive MG setup (paper: "Adaptive Multigrid", "Formulating an
+ * algorithm", setup stage one in "Numerical Results"): relax the start
+ * vectors on D x = 0 (setup_rounds x setup_mr_steps MR steps each,
+ * normalising after each round), QR them per (aggregate, chirality) with a
+ * positive real R diagonal to form P (P^dag P = I, Eq. 4), and build
+ * D_c = P^dag D P as a 9-point stencil of 2Nv x 2Nv blocks; repeated on
+ * D_c for 3 levels.  U: DEVICE complex128 canonical.  *ctx receives a new
+ * context.  Returns MG_ESHAPE if a block does not divide the lattice or
+ * Nv > 6 * block volume (fine) / Nv * block volume (coarse), MG_ERANK if an
+ * aggregate is rank deficient.  Synchronous.                            */
+int mg_setup(const mg_lattice_t *lat, const void *U, double mass,
+             const mg_params_t *params, mg_ctx_t **ctx, hipStream_t stream);
+
+/* Choose the preconditioner precision for later solves (MG_F64, MG_F32,
+ * MG_F16); lower-precision copies of U, P and D_c are made on first use.  */
+int mg_set_precond_prec(mg_ctx_t *ctx, mg_prec_t prec);
+
+/* Turn per-kernel device timing on (1) or off (0) for later solves.       */
+int mg_set_timing(mg_ctx_t *ctx, int on);
+
+/* Restriction r_c = P^dag r from level `level` to level+1 (R = P^dag,
+ * Eq. 8 with chirality kept: P^dag gamma_5 = sigma_3 P^dag).
+ * level 0: fine canonical spinors in, coarse canonical vectors out;
+ * level 1: coarse level-1 vectors in, level-2 vectors out.  DEVICE
+ * complex128 buffers, nrhs vectors each.  Asynchronous.                  */
+int mg_restrict(mg_ctx_t *ctx, int level, const void *fine, void *coarse,
+                int nrhs, hipStream_t stream);
+
+/* Prolongation e = P e_c from level+1 to level (layouts as mg_restrict).   */
+int mg_prolong(mg_ctx_t *ctx, int level, const void *coarse, void *fine,
+               int nrhs, hipStream_t stream);
+
+/* Coarse operator of level `level` (1 or 2) applied to nrhs canonical
+ * coarse vectors: out(x_c) = X(x_c) in(x_c) + sum_mu [Y_+mu(x_c)
+ * in(x_c+mu) + Y_-mu(x_c) in(x_c-mu)], periodic on the coarse lattice.
+ * dagger != 0 applies D_c^dag = sigma_3 D_c sigma_3.  FP64.  Async.       */
+int coarse_apply(mg_ctx_t *ctx, int level, const void *in, void *out,
+                 int nrhs, int dagger, hipStream_t stream);
+
+/* Solve D x = b for nrhs canonical spinors (DEVICE complex128) with
+ * flexible GCR(gcr_restart) preconditioned by one MG V-cycle (MR pre/post
+ * smoothing, CGNR on the coarsest level), to ||b - D x|| <= tol ||b|| per
+ * RHS, restarting with the true residual.  x is overwritten (zero start).
+ * info (HOST, may be NULL) receives iteration counts and timings.
+ * Returns MG_NOT_CONVERGED when max_iter is reached (x = last iterate).
+ * Synchronous.                                                           */
+int mg_solve(mg_ctx_t *ctx, const void *b, void *x, int nrhs, double tol,
+             mg_info_t *info, hipStream_t stream);
+
+/* Device time of `reps` back-to-back fine-stencil launches on the
+ * context's internal layouts (nrhs vectors, precision prec), measured with
+ * HIP events on `stream`.  avg_ms (HOST) receives the mean per launch.    */
+int mg_time_dslash(mg_ctx_t *ctx, mg_prec_t prec, int nrhs, int reps,
+                   double *avg_ms, hipStream_t stream);
+
+/* Device time of `reps` coarse-stencil launches of level `level`.        */
+int mg_time_coarse(mg_ctx_t *ctx, int level, mg_prec_t prec, int nrhs,
+                   int reps, double *avg_ms, hipStream_t stream);
+
+int mg_destroy(mg_ctx_t *ctx);
+
+/* Message describing the last error on the calling thread ("" if none).   */
+const char *mg_last_error(void);
+
+/* ---- Exports for parity checks (HOST output buffers) ------------------- */
+/* Aggregate maps of level `level` (int32, canonical lexicographic order of
+ * the level's sites): f2c[V] coarse site, f2l[V] index within the block
+ * (o_x + b_x (o_y + b_y (o_z + b_z o_t))), cnbr[Vc][8] coarse neighbour in
+ * slot 2 mu + dir (dir 0 = +mu, 1 = -mu), face[V] bit 2 mu + dir set when
+ * that hop leaves the block.  Any pointer may be NULL.                    */
+int mg_export_maps(mg_ctx_t *ctx, int level, int32_t *f2c, int32_t *f2l,
+                   int32_t *cnbr, int32_t *face);
+
+/* Prolongator of level `level` as complex128 [Vc][2][rows][Nv] with row =
+ * l * h + j (h = 6 on the fine level: j = 3 s' + c for spin 2 chi + s';
+ * h = Nv(level) on coarse levels).                                       */
+int mg_export_P(mg_ctx_t *ctx, int level, void *P_host);
+
+/* Coarse operator of level `level` (1 or 2): X[Vc][n][n] and Y[8][Vc][n][n]
+ * complex128, coarse sites lexicographic, [row][col].                     */
+int mg_export_coarse_op(mg_ctx_t *ctx, int level, void *X_host, void *Y_host);
+
+/* Relaxed null vectors of level `level` before orthonormalisation, in the
+ * canonical layout of that level (complex128, nv vectors).               */
+int mg_export_nullvecs(mg_ctx_t *ctx, int level, void *V_host);
+
+/* Geometry of level `level`: L (4 ints) and component count per site.   */
+int mg_level_info(mg_ctx_t *ctx, int level, int *L_out, int *ncomp_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGWD_H */

@@ -1,0 +1,304 @@
+"""Python binding of libmgwd: the MI355X adaptive multigrid Wilson-Dirac solver.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library behind the C ABI declared in include/mgwd.h.  PyTorch supplies device
+memory (complex128 CUDA/HIP tensors) and the current stream.  If the shared
+library is missing or cannot be loaded the functions raise; there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmgwd.so")
+
+MG_OK, MG_NOT_CONVERGED = 0, 1
+PREC = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+MAX_LEVELS = 3
+MAX_RHS = 16
+
+EXPORTED = ["wilson_apply", "mg_setup", "mg_set_precond_prec", "mg_set_timing", "mg_restrict",
+            "mg_prolong", "coarse_apply", "mg_solve", "mg_time_dslash", "mg_time_coarse",
+            "mg_destroy", "mg_last_error", "mg_export_maps", "mg_export_P",
+            "mg_export_coarse_op", "mg_export_nullvecs", "mg_level_info"]
+
+
+class MGError(RuntimeError):
+    def __init__(self, rc, msg):
+        super().__init__(f"mgwd error {rc}: {msg}")
+        self.rc = rc
+
+
+class Lattice(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int * 4), ("t_antiperiodic", ctypes.c_int)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int),
+                ("block", (ctypes.c_int * 4) * (MAX_LEVELS - 1)),
+                ("nv", ctypes.c_int * (MAX_LEVELS - 1)),
+                ("setup_rounds", ctypes.c_int),
+                ("setup_mr_steps", ctypes.c_int),
+                ("omega", ctypes.c_double),
+                ("pre", ctypes.c_int), ("post", ctypes.c_int),
+                ("coarse_tol", ctypes.c_double),
+                ("coarse_maxiter", ctypes.c_int),
+                ("gcr_restart", ctypes.c_int),
+                ("max_iter", ctypes.c_int),
+                ("precond_prec", ctypes.c_int),
+                ("max_rhs", ctypes.c_int),
+                ("init_vectors", ctypes.c_void_p * (MAX_LEVELS - 1))]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int * MAX_RHS),
+                ("rel_resid", ctypes.c_double * MAX_RHS),
+                ("n_fine_dslash", ctypes.c_int),
+                ("n_coarse_apply", ctypes.c_int),
+                ("n_cgnr_iters", ctypes.c_int),
+                ("n_vcycles", ctypes.c_int),
+                ("t_setup_s", ctypes.c_double), ("t_solve_s", ctypes.c_double),
+                ("dslash_ms", ctypes.c_double), ("dslash_launches", ctypes.c_int),
+                ("dslash_prec", ctypes.c_int),
+                ("coarse_ms", ctypes.c_double), ("coarse_launches", ctypes.c_int),
+                ("coarse_prec", ctypes.c_int)]
+
+    def as_dict(self, nrhs=1):
+        return dict(iters=list(self.iters[:nrhs]), rel_resid=list(self.rel_resid[:nrhs]),
+                    n_fine_dslash=self.n_fine_dslash, n_coarse_apply=self.n_coarse_apply,
+                    n_cgnr_iters=self.n_cgnr_iters, n_vcycles=self.n_vcycles,
+                    t_setup_s=self.t_setup_s, t_solve_s=self.t_solve_s,
+                    dslash_ms=self.dslash_ms, dslash_launches=self.dslash_launches,
+                    coarse_ms=self.coarse_ms, coarse_launches=self.coarse_launches)
+
+
+_lib = None
+
+
+def lib():
+    """The loaded shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_1005_3043_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, ci, cd = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        sig = {
+            "wilson_apply": [ctypes.POINTER(Lattice), vp, cd, vp, vp, ci, ci, vp],
+            "mg_setup": [ctypes.POINTER(Lattice), vp, cd, ctypes.POINTER(Params), ctypes.POINTER(vp), vp],
+            "mg_set_precond_prec": [vp, ci],
+            "mg_set_timing": [vp, ci],
+            "mg_restrict": [vp, ci, vp, vp, ci, vp],
+            "mg_prolong": [vp, ci, vp, vp, ci, vp],
+            "coarse_apply": [vp, ci, vp, vp, ci, ci, vp],
+            "mg_solve": [vp, vp, vp, ci, cd, ctypes.POINTER(Info), vp],
+            "mg_time_dslash": [vp, ci, ci, ci, ctypes.POINTER(cd), vp],
+            "mg_time_coarse": [vp, ci, ci, ci, ci, ctypes.POINTER(cd), vp],
+            "mg_destroy": [vp],
+            "mg_last_error": [],
+            "mg_export_maps": [vp, ci, vp, vp, vp, vp],
+            "mg_export_P": [vp, ci, vp],
+            "mg_export_coarse_op": [vp, ci, vp, vp],
+            "mg_export_nullvecs": [vp, ci, vp],
+            "mg_level_info": [vp, ci, vp, vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_char_p if name == "mg_last_error" else ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc, allow_not_converged=False):
+    if rc == MG_OK or (allow_not_converged and rc == MG_NOT_CONVERGED):
+        return rc
+    raise MGError(rc, lib().mg_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str):
+    if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous complex128 device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def lattice(L, t_antiperiodic=True) -> Lattice:
+    return Lattice((ctypes.c_int * 4)(*[int(v) for v in L]), int(bool(t_antiperiodic)))
+
+
+def dims_of_spinor(psi: torch.Tensor):
+    Lt, Lz, Ly, Lx = psi.shape[-6:-2]
+    return (Lx, Ly, Lz, Lt)
+
+
+def wilson_apply(U: torch.Tensor, psi: torch.Tensor, mass: float, prec: str = "f64",
+                 t_antiperiodic: bool = True, out: torch.Tensor | None = None) -> torch.Tensor:
+    """out = D(U) psi (Eq. 2) for psi[..., t, z, y, x, 4, 3] (leading axes = RHS)."""
+    L = dims_of_spinor(psi)
+    nrhs = int(psi.numel() // (12 * L[0] * L[1] * L[2] * L[3]))
+    if out is None:
+        out = torch.empty_like(psi)
+    lat = lattice(L, t_antiperiodic)
+    _check(lib().wilson_apply(ctypes.byref(lat), _dev(U, "U"), float(mass), _dev(psi, "psi"),
+                              _dev(out, "out"), nrhs, PREC[prec], _stream()))
+    return out
+
+
+class MG:
+    """Owning handle of an mg_ctx_t (setup done on construction)."""
+
+    def __init__(self, U: torch.Tensor, mass: float, blocks, nv, init_vectors, *,
+                 t_antiperiodic=True, setup_rounds=5, setup_mr_steps=4, omega=0.9, pre=4,
+                 post=4, coarse_tol=1e-3, coarse_maxiter=1000, gcr_restart=8, max_iter=10000,
+                 precond_prec="f64", max_rhs=1):
+        Lt, Lz, Ly, Lx = U.shape[1:5]
+        self.L = (Lx, Ly, Lz, Lt)
+        self.nv = list(nv)
+        self.blocks = [tuple(b) for b in blocks]
+        p = Params()
+        p.n_levels = len(blocks) + 1
+        for i, b in enumerate(blocks):
+            for mu in range(4):
+                p.block[i][mu] = int(b[mu])
+            p.nv[i] = int(nv[i])
+        p.setup_rounds, p.setup_mr_steps, p.omega = setup_rounds, setup_mr_steps, omega
+        p.pre, p.post, p.coarse_tol, p.coarse_maxiter = pre, post, coarse_tol, coarse_maxiter
+        p.gcr_restart, p.max_iter = gcr_restart, max_iter
+        p.precond_prec, p.max_rhs = PREC[precond_prec], max_rhs
+        self._keep = list(init_vectors)
+        for i, v in enumerate(init_vectors):
+            p.init_vectors[i] = _dev(v, f"init_vectors[{i}]").value
+        self.params = p
+        lat = lattice(self.L, t_antiperiodic)
+        h = ctypes.c_void_p()
+        _check(lib().mg_setup(ctypes.byref(lat), _dev(U, "U"), float(mass), ctypes.byref(p),
+                              ctypes.byref(h), _stream()))
+        self.ctx = h
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            lib().mg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def level_info(self, level):
+        L = (ctypes.c_int * 4)()
+        n = ctypes.c_int()
+        _check(lib().mg_level_info(self.ctx, level, L, ctypes.byref(n)))
+        return tuple(L), n.value
+
+    def set_precond_prec(self, prec: str):
+        _check(lib().mg_set_precond_prec(self.ctx, PREC[prec]))
+
+    def set_timing(self, on: bool):
+        _check(lib().mg_set_timing(self.ctx, int(bool(on))))
+
+    def restrict(self, level, fine, nrhs=None):
+        Lc, n = self.level_info(level + 1)
+        if nrhs is None:
+            nrhs = self._nvec(level, fine)
+        out = torch.empty((nrhs, Lc[3], Lc[2], Lc[1], Lc[0], n), dtype=torch.complex128, device=fine.device)
+        _check(lib().mg_restrict(self.ctx, level, _dev(fine, "fine"), _dev(out, "coarse"), nrhs, _stream()))
+        return out
+
+    def prolong(self, level, coarse, nrhs=None):
+        Lf, n = self.level_info(level)
+        if nrhs is None:
+            nrhs = self._nvec(level + 1, coarse)
+        shape = (nrhs, Lf[3], Lf[2], Lf[1], Lf[0]) + ((4, 3) if level == 0 else (n,))
+        out = torch.empty(shape, dtype=torch.complex128, device=coarse.device)
+        _check(lib().mg_prolong(self.ctx, level, _dev(coarse, "coarse"), _dev(out, "fine"), nrhs, _stream()))
+        return out
+
+    def coarse_apply(self, level, v, dagger=False, nrhs=None):
+        if nrhs is None:
+            nrhs = self._nvec(level, v)
+        out = torch.empty_like(v)
+        _check(lib().coarse_apply(self.ctx, level, _dev(v, "in"), _dev(out, "out"), nrhs, int(bool(dagger)),
+                                  _stream()))
+        return out
+
+    def solve(self, b, tol=1e-10, nrhs=None, x=None):
+        if nrhs is None:
+            nrhs = self._nvec(0, b)
+        if x is None:
+            x = torch.empty_like(b)
+        info = Info()
+        rc = _check(lib().mg_solve(self.ctx, _dev(b, "b"), _dev(x, "x"), nrhs, float(tol), ctypes.byref(info),
+                                   _stream()), allow_not_converged=True)
+        return x, info.as_dict(nrhs), rc
+
+    def time_dslash(self, prec="f64", nrhs=1, reps=20):
+        ms = ctypes.c_double()
+        _check(lib().mg_time_dslash(self.ctx, PREC[prec], nrhs, reps, ctypes.byref(ms), _stream()))
+        return ms.value
+
+    def time_coarse(self, level=1, prec="f64", nrhs=1, reps=20):
+        ms = ctypes.c_double()
+        _check(lib().mg_time_coarse(self.ctx, level, PREC[prec], nrhs, reps, ctypes.byref(ms), _stream()))
+        return ms.value
+
+    def _nvec(self, level, t):
+        L, n = self.level_info(level)
+        per = L[0] * L[1] * L[2] * L[3] * n
+        return int(t.numel() // per)
+
+    # parity exports --------------------------------------------------------
+    def export_maps(self, level):
+        import numpy as np
+        L, _ = self.level_info(level)
+        Lc, _ = self.level_info(level + 1)
+        V = L[0] * L[1] * L[2] * L[3]
+        Vc = Lc[0] * Lc[1] * Lc[2] * Lc[3]
+        f2c = np.zeros(V, np.int32)
+        f2l = np.zeros(V, np.int32)
+        nbr = np.zeros((Vc, 8), np.int32)
+        face = np.zeros(V, np.int32)
+        p = lambda a: ctypes.c_void_p(a.ctypes.data)  # noqa: E731
+        _check(lib().mg_export_maps(self.ctx, level, p(f2c), p(f2l), p(nbr), p(face)))
+        return f2c, f2l, nbr, face
+
+    def export_P(self, level):
+        import numpy as np
+        Lc, n_c = self.level_info(level + 1)
+        L, n = self.level_info(level)
+        nv = n_c // 2
+        vb = 1
+        for mu in range(4):
+            vb *= self.blocks[level][mu]
+        Vc = Lc[0] * Lc[1] * Lc[2] * Lc[3]
+        P = np.zeros((Vc, 2, vb * n // 2, nv), np.complex128)
+        _check(lib().mg_export_P(self.ctx, level, ctypes.c_void_p(P.ctypes.data)))
+        return P
+
+    def export_coarse_op(self, level):
+        import numpy as np
+        Lc, n = self.level_info(level)
+        X = np.zeros((Lc[3], Lc[2], Lc[1], Lc[0], n, n), np.complex128)
+        Y = np.zeros((8, Lc[3], Lc[2], Lc[1], Lc[0], n, n), np.complex128)
+        _check(lib().mg_export_coarse_op(self.ctx, level, ctypes.c_void_p(X.ctypes.data),
+                                         ctypes.c_void_p(Y.ctypes.data)))
+        return X, Y
+
+    def export_nullvecs(self, level):
+        import numpy as np
+        L, n = self.level_info(level)
+        nv = self.nv[level]
+        shape = (nv, L[3], L[2], L[1], L[0]) + ((4, 3) if level == 0 else (n,))
+        V = np.zeros(shape, np.complex128)
+        _check(lib().mg_export_nullvecs(self.ctx, level, ctypes.c_void_p(V.ctypes.data)))
+        return V

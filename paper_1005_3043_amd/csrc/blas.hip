@@ -1,0 +1,51 @@
+// Streaming level-1 kernels on flat complex arrays (any layout: these are
+// elementwise).  Grid-stride loops over n complex entries.
+#include "kernels.h"
+
+namespace mg {
+
+static inline int stream_grid(size_t n) {
+  size_t b = (n + 255) / 256;
+  return (int)(b < 16384 ? (b == 0 ? 1 : b) : 16384);
+}
+
+template <typename C> __global__ __launch_bounds__(256) void k_zero(C *x, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    x[i] = mk<C>(0, 0);
+}
+template <typename C> __global__ __launch_bounds__(256) void k_copy(C *y, const C *x, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = x[i];
+}
+template <typename Cd, typename Cs> __global__ __launch_bounds__(256) void k_convert(Cd *y, const Cs *x, size_t n) {
+  using Rd = decltype(Cd::x);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    Cs v = x[i];
+    y[i] = mk<Cd>((Rd)v.x, (Rd)v.y);
+  }
+}
+
+template <typename R> hipError_t zero(c_t<R> *x, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero<c_t<R>>, dim3(stream_grid(n)), dim3(256), 0, st, x, n);
+  return hipGetLastError();
+}
+template <typename R> hipError_t copy(c_t<R> *y, const c_t<R> *x, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy<c_t<R>>, dim3(stream_grid(n)), dim3(256), 0, st, y, x, n);
+  return hipGetLastError();
+}
+template <typename Rd, typename Rs> hipError_t convert(c_t<Rd> *y, const c_t<Rs> *x, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_convert<c_t<Rd>, c_t<Rs>>), dim3(stream_grid(n)), dim3(256), 0, st, y, x, n);
+  return hipGetLastError();
+}
+
+template hipError_t zero<double>(double2 *, size_t, hipStream_t);
+template hipError_t zero<float>(float2 *, size_t, hipStream_t);
+template hipError_t copy<double>(double2 *, const double2 *, size_t, hipStream_t);
+template hipError_t copy<float>(float2 *, const float2 *, size_t, hipStream_t);
+template hipError_t convert<double, float>(double2 *, const float2 *, size_t, hipStream_t);
+template hipError_t convert<float, double>(float2 *, const double2 *, size_t, hipStream_t);
+
+}  // namespace mg

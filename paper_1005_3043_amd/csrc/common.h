@@ -1,0 +1,204 @@
+// Internal definitions shared by the HIP kernels and the host orchestration.
+//
+// Internal data layout (all levels): sites are ordered aggregate-major
+// ("site-blocked"): s = B * vol_b + l, where B is the lexicographic index of
+// the aggregate on the coarse lattice and l = o_x + b_x (o_y + b_y (o_z +
+// b_z o_t)) the lexicographic index inside it.  Every per-site quantity is
+// stored structure-of-arrays: component plane k holds entry k of all sites
+// contiguously, so a wavefront reading one component of 64 consecutive sites
+// issues one contiguous, fully coalesced load.  The fine stencil then walks a
+// 4D tile (neighbours stay in the same or the adjacent aggregate), and the
+// transfer kernels see each aggregate as one contiguous range per plane.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+#include <string>
+
+#include "../../include/mgwd.h"
+
+namespace mg {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+std::string hip_error_string(hipError_t e, const char *what);
+
+#define MG_HIP(call)                                                      \
+  do {                                                                    \
+    hipError_t _e = (call);                                               \
+    if (_e != hipSuccess) {                                               \
+      ::mg::set_error(::mg::hip_error_string(_e, #call));                 \
+      return MG_EHIP;                                                     \
+    }                                                                     \
+  } while (0)
+
+#define MG_TRY(call)                                                      \
+  do {                                                                    \
+    int _rc = (call);                                                     \
+    if (_rc < 0) return _rc;                                              \
+  } while (0)
+
+// ---------------------------------------------------------------- complex
+template <typename R> struct cpx;
+template <> struct cpx<double> { using t = double2; };
+template <> struct cpx<float> { using t = float2; };
+template <typename R> using c_t = typename cpx<R>::t;
+
+template <typename C> __host__ __device__ __forceinline__ C mk(decltype(C::x) a, decltype(C::x) b) {
+  C c; c.x = a; c.y = b; return c;
+}
+template <typename C> __host__ __device__ __forceinline__ C cadd(C a, C b) { return mk<C>(a.x + b.x, a.y + b.y); }
+template <typename C> __host__ __device__ __forceinline__ C csub(C a, C b) { return mk<C>(a.x - b.x, a.y - b.y); }
+template <typename C> __host__ __device__ __forceinline__ C cmul(C a, C b) {
+  return mk<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * b accumulated: acc += a * b
+template <typename C> __host__ __device__ __forceinline__ C cfma(C a, C b, C acc) {
+  acc.x = fma(a.x, b.x, acc.x); acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y); acc.y = fma(a.y, b.x, acc.y);
+  return acc;
+}
+// conj(a) * b accumulated
+template <typename C> __host__ __device__ __forceinline__ C cfmac(C a, C b, C acc) {
+  acc.x = fma(a.x, b.x, acc.x); acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y); acc.y = fma(-a.y, b.x, acc.y);
+  return acc;
+}
+template <typename C> __host__ __device__ __forceinline__ C cscale(C a, decltype(C::x) s) { return mk<C>(a.x * s, a.y * s); }
+// multiply by i^k (k = 0: 1, 1: i, 2: -1, 3: -i)
+template <int k, typename C> __host__ __device__ __forceinline__ C mul_ipow(C a) {
+  if constexpr (k == 0) return a;
+  else if constexpr (k == 1) return mk<C>(-a.y, a.x);
+  else if constexpr (k == 2) return mk<C>(-a.x, -a.y);
+  else return mk<C>(a.y, -a.x);
+}
+
+// ---------------------------------------------------------------- fast div
+// Division of 32-bit unsigned n by a runtime-invariant d with a multiply-high
+// and shifts (Granlund & Montgomery, "Division by invariant integers using
+// multiplication", 1994).
+struct FastDiv {
+  uint32_t d = 1, m = 0, s1 = 0, s2 = 0;
+  FastDiv() = default;
+  explicit FastDiv(uint32_t dd) : d(dd) {
+    uint32_t l = 0;
+    while ((1ull << l) < dd) ++l;
+    uint64_t mm = ((1ull << 32) * ((1ull << l) - dd)) / dd + 1;
+    m = (uint32_t)mm;
+    s1 = l > 0 ? 1 : 0;
+    s2 = l > 0 ? l - 1 : 0;
+  }
+  __host__ __device__ __forceinline__ uint32_t div(uint32_t n) const {
+#ifdef __HIP_DEVICE_COMPILE__
+    uint32_t t = __umulhi(n, m);
+#else
+    uint32_t t = (uint32_t)(((uint64_t)n * m) >> 32);
+#endif
+    return (t + ((n - t) >> s1)) >> s2;
+  }
+};
+
+// ---------------------------------------------------------------- geometry
+// Site-blocked ordering of one lattice level.  L = lattice, b = aggregate
+// (tile) shape, C = L / b = coarse lattice.
+struct Geom {
+  int L[4], b[4], C[4];
+  uint32_t V, vb, Vc;
+  int Sl[4];   // stride of o_mu inside an aggregate
+  int Sb[4];   // stride of c_mu between aggregates (in sites)
+  FastDiv fvb, fb[3], fC[3];
+  int antiperiodic;
+};
+
+Geom make_geom(const int L[4], const int b[4], int antiperiodic);
+
+struct Coords { int o[4]; int c[4]; uint32_t B, l; };
+
+__host__ __device__ __forceinline__ Coords decode(const Geom &g, uint32_t s) {
+  Coords r;
+  r.B = g.fvb.div(s);
+  r.l = s - r.B * g.vb;
+  uint32_t q = r.l;
+#pragma unroll
+  for (int mu = 0; mu < 3; ++mu) {
+    uint32_t q2 = g.fb[mu].div(q);
+    r.o[mu] = (int)(q - q2 * (uint32_t)g.b[mu]);
+    q = q2;
+  }
+  r.o[3] = (int)q;
+  q = r.B;
+#pragma unroll
+  for (int mu = 0; mu < 3; ++mu) {
+    uint32_t q2 = g.fC[mu].div(q);
+    r.c[mu] = (int)(q - q2 * (uint32_t)g.C[mu]);
+    q = q2;
+  }
+  r.c[3] = (int)q;
+  return r;
+}
+
+// Site index of the forward (+mu) neighbour, periodic.
+__host__ __device__ __forceinline__ uint32_t nbr_fwd(const Geom &g, uint32_t s, const Coords &k, int mu) {
+  if (k.o[mu] + 1 < g.b[mu]) return s + g.Sl[mu];
+  int64_t t = (int64_t)s - (int64_t)(g.b[mu] - 1) * g.Sl[mu];
+  t += (k.c[mu] + 1 < g.C[mu]) ? (int64_t)g.Sb[mu] : -(int64_t)(g.C[mu] - 1) * g.Sb[mu];
+  return (uint32_t)t;
+}
+// Site index of the backward (-mu) neighbour, periodic.
+__host__ __device__ __forceinline__ uint32_t nbr_bwd(const Geom &g, uint32_t s, const Coords &k, int mu) {
+  if (k.o[mu] > 0) return s - g.Sl[mu];
+  int64_t t = (int64_t)s + (int64_t)(g.b[mu] - 1) * g.Sl[mu];
+  t += (k.c[mu] > 0) ? -(int64_t)g.Sb[mu] : (int64_t)(g.C[mu] - 1) * g.Sb[mu];
+  return (uint32_t)t;
+}
+// Lexicographic (canonical) index of an internal site.
+__host__ __device__ __forceinline__ uint32_t canon_index(const Geom &g, const Coords &k) {
+  uint32_t x[4];
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) x[mu] = (uint32_t)(k.c[mu] * g.b[mu] + k.o[mu]);
+  return x[0] + (uint32_t)g.L[0] * (x[1] + (uint32_t)g.L[1] * (x[2] + (uint32_t)g.L[2] * x[3]));
+}
+
+// XCD-aware block remapping: the hardware hands consecutive workgroup ids
+// round-robin to the 8 XCDs (each with its own L2).  Remapping so that every
+// XCD walks one contiguous range of tiles keeps stencil neighbours that are
+// shared between adjacent tiles inside one L2.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nblk) {
+  if ((nblk & 7u) != 0u) return bid;
+  return (bid & 7u) * (nblk >> 3) + (bid >> 3);
+}
+
+// ---------------------------------------------------------------- reductions
+// Wavefront (64 lanes) sum via cross-lane shuffles.
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block sum of NV doubles: result valid in thread 0.  blockDim.x <= 1024,
+// multiple of 64.  Fixed order -> deterministic.
+template <int NV> __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) lds[w * NV + i] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double a = 0.0;
+      for (int j = 0; j < nw; ++j) a += lds[j * NV + i];
+      v[i] = a;
+    }
+  }
+}
+
+inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace mg

@@ -1,0 +1,43 @@
+"""The C-ABI library loads without a GPU and exports every function that
+include/mgwd.h declares (no compute calls here)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "mgwd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while")))
+
+
+def test_header_declares_boundary():
+    names = declared_functions()
+    for n in ("wilson_apply", "mg_setup", "mg_restrict", "mg_prolong", "coarse_apply", "mg_solve",
+              "mg_destroy", "mg_last_error"):
+        assert n in names
+
+
+def test_library_exports_all_symbols():
+    import paper_1005_3043_amd as mgwd
+    lib = ctypes.CDLL(mgwd.LIB_PATH)
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    assert sorted(mgwd.EXPORTED) == sorted(declared_functions())
+
+
+def test_argument_errors_without_gpu():
+    """Host-side argument validation returns error codes, never aborts."""
+    import paper_1005_3043_amd as mgwd
+    lib = mgwd.lib()
+    lat = mgwd.lattice((4, 4, 4, 0))
+    rc = lib.wilson_apply(ctypes.byref(lat), None, 0.0, None, None, 1, 0, None)
+    assert rc == -1
+    assert b"positive" in lib.mg_last_error()
+    lat = mgwd.lattice((4, 4, 4, 4))
+    rc = lib.wilson_apply(ctypes.byref(lat), None, 0.0, None, None, 1, 0, None)
+    assert rc == -1
