@@ -1,36 +1,426 @@
-// C ABI: multigrid context entry points.
-#include "kernels.h"
+// C ABI: multigrid context entry points (argument validation, layout
+// conversion at the boundary, dispatch to the orchestration in mg.cpp).
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "mg_internal.h"
 
 using namespace mg;
 
-static int notsup(const char *f) {
-  set_error(std::string(f) + ": not built yet");
-  return MG_ENOTSUP;
+namespace {
+
+int hip_rc(hipError_t e, const char *what) {
+  if (e == hipSuccess) return MG_OK;
+  set_error(hip_error_string(e, what));
+  return MG_EHIP;
+}
+#define HIPK(expr) MG_TRY(hip_rc((expr), #expr))
+
+int bad(int rc, const char *msg) {
+  set_error(msg);
+  return rc;
 }
 
-extern "C" int mg_setup(const mg_lattice_t *, const void *, double, const mg_params_t *, mg_ctx_t **,
-                        hipStream_t) { return notsup("mg_setup"); }
-extern "C" int mg_set_precond_prec(mg_ctx_t *, mg_prec_t) { return notsup("mg_set_precond_prec"); }
-extern "C" int mg_set_timing(mg_ctx_t *, int) { return notsup("mg_set_timing"); }
-extern "C" int mg_restrict(mg_ctx_t *, int, const void *, void *, int, hipStream_t) { return notsup("mg_restrict"); }
-extern "C" int mg_prolong(mg_ctx_t *, int, const void *, void *, int, hipStream_t) { return notsup("mg_prolong"); }
-extern "C" int coarse_apply(mg_ctx_t *, int, const void *, void *, int, int, hipStream_t) {
-  return notsup("coarse_apply");
+int check_params(const mg_lattice_t *lat, const mg_params_t *p) {
+  if (p->n_levels < 2 || p->n_levels > MG_MAX_LEVELS) return bad(MG_EINVAL, "n_levels must be 2 or 3");
+  int L[4] = {lat->L[0], lat->L[1], lat->L[2], lat->L[3]};
+  int n = 12;
+  for (int l = 0; l < p->n_levels - 1; ++l) {
+    long vb = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+      const int b = p->block[l][mu];
+      if (b < 1 || L[mu] % b != 0) return bad(MG_ESHAPE, "aggregate shape does not divide the lattice");
+      vb *= b;
+      L[mu] /= b;
+    }
+    const int nv = p->nv[l];
+    if (nv < 1 || 2 * nv > COARSE_NMAX) return bad(MG_ESHAPE, "Nv must be in [1, 32]");
+    if (l == 0) {
+      if (vb > 256) return bad(MG_ESHAPE, "fine aggregates larger than 256 sites are not supported");
+      if (nv > 6 * vb) return bad(MG_ESHAPE, "Nv exceeds 6 x aggregate volume");
+    } else {
+      if (vb * n > 2048) return bad(MG_ESHAPE, "coarse aggregate volume x components exceeds 2048");
+      if (nv > (n / 2) * vb) return bad(MG_ESHAPE, "Nv exceeds (n/2) x aggregate volume");
+    }
+    if (!p->init_vectors[l]) return bad(MG_EINVAL, "init_vectors missing for a level");
+    n = 2 * nv;
+  }
+  if (p->setup_rounds < 0 || p->setup_mr_steps < 0 || p->pre < 0 || p->post < 0)
+    return bad(MG_EINVAL, "negative step count");
+  if (!std::isfinite(p->omega) || !(p->coarse_tol > 0) || p->coarse_maxiter < 1)
+    return bad(MG_EINVAL, "bad omega / coarse tolerance / coarse iteration cap");
+  if (p->gcr_restart < 1 || p->gcr_restart > 64 || p->max_iter < 1) return bad(MG_EINVAL, "bad GCR parameters");
+  if (p->max_rhs < 1 || p->max_rhs > MG_MAX_RHS) return bad(MG_EINVAL, "max_rhs out of range");
+  if (p->precond_prec != MG_F64 && p->precond_prec != MG_F32)
+    return bad(MG_ENOTSUP, "precond_prec must be MG_F64 or MG_F32");
+  return MG_OK;
 }
-extern "C" int mg_solve(mg_ctx_t *, const void *, void *, int, double, mg_info_t *, hipStream_t) {
-  return notsup("mg_solve");
+
+int check_ctx_level(mg_ctx_t *ctx, int level, int lo, int hi) {
+  if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
+  if (level < lo || level > hi) return bad(MG_ESHAPE, "level out of range");
+  return MG_OK;
 }
-extern "C" int mg_time_dslash(mg_ctx_t *, mg_prec_t, int, int, double *, hipStream_t) {
-  return notsup("mg_time_dslash");
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
-extern "C" int mg_time_coarse(mg_ctx_t *, int, mg_prec_t, int, int, double *, hipStream_t) {
-  return notsup("mg_time_coarse");
+
+template <typename T> struct AsyncBuf {
+  T *p = nullptr;
+  hipStream_t st;
+  explicit AsyncBuf(hipStream_t s) : st(s) {}
+  ~AsyncBuf() {
+    if (p) (void)hipFreeAsync(p, st);
+  }
+  hipError_t alloc(size_t n) { return hipMallocAsync((void **)&p, n * sizeof(T), st); }
+};
+
+// canonical <-> internal for a vector of level l (FP64)
+hipError_t pack_level(mg_ctx *c, int l, const void *canon, double2 *internal, int nvec, hipStream_t st) {
+  const Level &L = c->lev[l];
+  if (l == 0) return pack_field<double>(L.g, (const double2 *)canon, internal, 12, nvec, st);
+  return pack_aos<double>(L.g, (const double2 *)canon, internal, L.n, nvec, st);
 }
-extern "C" int mg_destroy(mg_ctx_t *) { return MG_OK; }
-extern "C" int mg_export_maps(mg_ctx_t *, int, int32_t *, int32_t *, int32_t *, int32_t *) {
-  return notsup("mg_export_maps");
+hipError_t unpack_level(mg_ctx *c, int l, const double2 *internal, void *canon, int nvec, hipStream_t st) {
+  const Level &L = c->lev[l];
+  if (l == 0) return unpack_field<double>(L.g, internal, (double2 *)canon, 12, nvec, st);
+  return unpack_aos<double>(L.g, internal, (double2 *)canon, L.n, nvec, st);
 }
-extern "C" int mg_export_P(mg_ctx_t *, int, void *) { return notsup("mg_export_P"); }
-extern "C" int mg_export_coarse_op(mg_ctx_t *, int, void *, void *) { return notsup("mg_export_coarse_op"); }
-extern "C" int mg_export_nullvecs(mg_ctx_t *, int, void *) { return notsup("mg_export_nullvecs"); }
-extern "C" int mg_level_info(mg_ctx_t *, int, int *, int *) { return notsup("mg_level_info"); }
+
+}  // namespace
+
+extern "C" int mg_setup(const mg_lattice_t *lat, const void *U, double mass, const mg_params_t *params,
+                        mg_ctx_t **ctx, hipStream_t stream) {
+  set_error("");
+  MG_TRY(check_lattice(lat));
+  if (!U || !params || !ctx) return bad(MG_EINVAL, "mg_setup: NULL argument");
+  if (!std::isfinite(mass)) return bad(MG_ENONFINITE, "mg_setup: non-finite mass");
+  MG_TRY(check_params(lat, params));
+  mg_ctx *c = new (std::nothrow) mg_ctx();
+  if (!c) return bad(MG_ENOMEM, "mg_setup: out of host memory");
+  c->lat = *lat;
+  c->p = *params;
+  c->mass = mass;
+  c->prec = params->precond_prec;
+  const double t0 = now_s();
+  int rc = setup(c, U, stream);
+  if (rc == MG_OK) rc = ensure_prec(c, c->prec, stream);
+  if (rc == MG_OK) rc = hip_rc(hipStreamSynchronize(stream), "mg_setup");
+  if (rc != MG_OK) {
+    mg_destroy(c);
+    return rc;
+  }
+  c->t_setup = now_s() - t0;
+  *ctx = c;
+  return MG_OK;
+}
+
+extern "C" int mg_set_precond_prec(mg_ctx_t *ctx, mg_prec_t prec) {
+  set_error("");
+  if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
+  MG_TRY(ensure_prec(ctx, prec, nullptr));
+  HIPK(hipStreamSynchronize(nullptr));
+  ctx->prec = prec;
+  return MG_OK;
+}
+
+extern "C" int mg_set_timing(mg_ctx_t *ctx, int on) {
+  if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
+  ctx->timing = on ? 1 : 0;
+  return MG_OK;
+}
+
+extern "C" int mg_restrict(mg_ctx_t *ctx, int level, const void *fine, void *coarse, int nrhs, hipStream_t st) {
+  set_error("");
+  if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
+  MG_TRY(check_ctx_level(ctx, level, 0, ctx->nlev - 2));
+  if (!fine || !coarse || nrhs < 1) return bad(MG_EINVAL, "mg_restrict: bad buffers or nrhs");
+  MG_TRY(ensure_scalars(ctx, part_need(ctx, 1)));
+  AsyncBuf<double2> a(st), b(st);
+  HIPK(a.alloc(ctx->lev[level].vsize() * nrhs));
+  HIPK(b.alloc(ctx->lev[level + 1].vsize() * nrhs));
+  HIPK(pack_level(ctx, level, fine, a.p, nrhs, st));
+  MG_TRY(transfer_restrict<double>(ctx, level, a.p, b.p, nrhs, st));
+  HIPK(unpack_level(ctx, level + 1, b.p, coarse, nrhs, st));
+  return MG_OK;
+}
+
+extern "C" int mg_prolong(mg_ctx_t *ctx, int level, const void *coarse, void *fine, int nrhs, hipStream_t st) {
+  set_error("");
+  if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
+  MG_TRY(check_ctx_level(ctx, level, 0, ctx->nlev - 2));
+  if (!fine || !coarse || nrhs < 1) return bad(MG_EINVAL, "mg_prolong: bad buffers or nrhs");
+  AsyncBuf<double2> a(st), b(st);
+  HIPK(a.alloc(ctx->lev[level].vsize() * nrhs));
+  HIPK(b.alloc(ctx->lev[level + 1].vsize() * nrhs));
+  HIPK(pack_level(ctx, level + 1, coarse, b.p, nrhs, st));
+  MG_TRY(transfer_prolong<double>(ctx, level, b.p, a.p, nrhs, 0, st));
+  HIPK(unpack_level(ctx, level, a.p, fine, nrhs, st));
+  return MG_OK;
+}
+
+extern "C" int coarse_apply(mg_ctx_t *ctx, int level, const void *in, void *out, int nrhs, int dagger,
+                            hipStream_t st) {
+  set_error("");
+  if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
+  MG_TRY(check_ctx_level(ctx, level, 1, ctx->nlev - 1));
+  if (!in || !out || in == out || nrhs < 1) return bad(MG_EINVAL, "coarse_apply: bad buffers or nrhs");
+  const Level &L = ctx->lev[level];
+  AsyncBuf<double2> a(st), b(st);
+  HIPK(a.alloc(L.vsize() * nrhs));
+  HIPK(b.alloc(L.vsize() * nrhs));
+  HIPK(pack_level(ctx, level, in, a.p, nrhs, st));
+  HIPK(coarse_apply_k<double>(L.g, L.n, L.L64, a.p, b.p, nrhs, dagger ? 1 : 0, nullptr, 1, nullptr, st));
+  HIPK(unpack_level(ctx, level, b.p, out, nrhs, st));
+  return MG_OK;
+}
+
+extern "C" int mg_solve(mg_ctx_t *ctx, const void *b, void *x, int nrhs, double tol, mg_info_t *info,
+                        hipStream_t st) {
+  set_error("");
+  if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
+  if (!b || !x || b == x) return bad(MG_EINVAL, "mg_solve: bad buffers");
+  if (nrhs < 1 || nrhs > ctx->p.max_rhs) return bad(MG_EINVAL, "mg_solve: nrhs out of range (max_rhs)");
+  if (!(tol > 0.0)) return bad(MG_EINVAL, "mg_solve: tol must be positive");
+  mg_ctx *c = ctx;
+  const size_t n = c->lev[0].vsize() * nrhs;
+  MG_TRY(c->gx.alloc(n));
+  MG_TRY(c->gr.alloc(n));
+  MG_TRY(c->gb.alloc(n));
+  MG_TRY(c->gZ.alloc(n * c->p.gcr_restart));
+  MG_TRY(c->gW.alloc(n * c->p.gcr_restart));
+  MG_TRY(c->skip.alloc(MG_MAX_RHS));
+  MG_TRY(ensure_prec(c, c->prec, st));
+  if (c->prec == MG_F64) MG_TRY(ensure_work<double>(c, nrhs));
+  else MG_TRY(ensure_work<float>(c, nrhs));
+  MG_TRY(ensure_scalars(c, part_need(c, nrhs)));
+  c->n_fine = c->n_coarse = c->n_cgnr = c->n_vcyc = 0;
+  c->tm_dslash.reset();
+  c->tm_coarse.reset();
+  HIPK(hipStreamSynchronize(st));
+  const double t0 = now_s();
+  HIPK(pack_field<double>(c->lev[0].g, (const double2 *)b, c->gb, 12, nrhs, st));
+  int iters[MG_MAX_RHS];
+  double relres[MG_MAX_RHS];
+  const int rc = fgcr(c, c->gb, c->gx, nrhs, tol, iters, relres, st);
+  if (rc < 0) return rc;
+  HIPK(unpack_field<double>(c->lev[0].g, c->gx, (double2 *)x, 12, nrhs, st));
+  HIPK(hipStreamSynchronize(st));
+  const double t1 = now_s();
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    for (int i = 0; i < nrhs; ++i) {
+      info->iters[i] = iters[i];
+      info->rel_resid[i] = relres[i];
+    }
+    info->n_fine_dslash = (int)c->n_fine;
+    info->n_coarse_apply = (int)c->n_coarse;
+    info->n_cgnr_iters = (int)c->n_cgnr;
+    info->n_vcycles = (int)c->n_vcyc;
+    info->t_setup_s = c->t_setup;
+    info->t_solve_s = t1 - t0;
+    if (c->timing) {
+      info->dslash_ms = c->tm_dslash.total_ms();
+      info->dslash_launches = c->tm_dslash.launches();
+      info->coarse_ms = c->tm_coarse.total_ms();
+      info->coarse_launches = c->tm_coarse.launches();
+    }
+    info->dslash_prec = (int)MG_F64;
+    info->coarse_prec = (int)c->prec;
+  }
+  return rc;
+}
+
+extern "C" int mg_time_dslash(mg_ctx_t *ctx, mg_prec_t prec, int nrhs, int reps, double *avg_ms, hipStream_t st) {
+  set_error("");
+  if (!ctx || !avg_ms || nrhs < 1 || reps < 1) return bad(MG_EINVAL, "mg_time_dslash: bad arguments");
+  mg_ctx *c = ctx;
+  MG_TRY(ensure_prec(c, prec, st));
+  MG_TRY(ensure_scalars(c, part_need(c, nrhs)));
+  Level &L = c->lev[0];
+  const size_t n = L.vsize() * nrhs;
+  hipEvent_t e0, e1;
+  HIPK(hipEventCreate(&e0));
+  HIPK(hipEventCreate(&e1));
+  int rc = MG_OK;
+  if (prec == MG_F64) {
+    DevBuf<double2> a, b;
+    MG_TRY(a.alloc(n));
+    MG_TRY(b.alloc(n));
+    HIPK(copy<double>(a, L.P64, std::min(n, L.P64.n), st));
+    for (int i = 0; i < 2; ++i) HIPK(dslash<double>(L.g, L.U64, a, b, nullptr, 4.0 + c->mass, nrhs, DS_PLAIN, nullptr, st));
+    HIPK(hipEventRecord(e0, st));
+    for (int i = 0; i < reps; ++i)
+      HIPK(dslash<double>(L.g, L.U64, a, b, nullptr, 4.0 + c->mass, nrhs, DS_PLAIN, nullptr, st));
+    HIPK(hipEventRecord(e1, st));
+    HIPK(hipEventSynchronize(e1));
+  } else if (prec == MG_F32) {
+    DevBuf<float2> a, b;
+    MG_TRY(a.alloc(n));
+    MG_TRY(b.alloc(n));
+    HIPK(copy<float>(a, L.P32, std::min(n, L.P32.n), st));
+    for (int i = 0; i < 2; ++i) HIPK(dslash<float>(L.g, L.U32, a, b, nullptr, 4.0 + c->mass, nrhs, DS_PLAIN, nullptr, st));
+    HIPK(hipEventRecord(e0, st));
+    for (int i = 0; i < reps; ++i)
+      HIPK(dslash<float>(L.g, L.U32, a, b, nullptr, 4.0 + c->mass, nrhs, DS_PLAIN, nullptr, st));
+    HIPK(hipEventRecord(e1, st));
+    HIPK(hipEventSynchronize(e1));
+  } else {
+    rc = bad(MG_ENOTSUP, "mg_time_dslash: precision not built");
+  }
+  float ms = 0.f;
+  if (rc == MG_OK) HIPK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *avg_ms = ms / reps;
+  return rc;
+}
+
+extern "C" int mg_time_coarse(mg_ctx_t *ctx, int level, mg_prec_t prec, int nrhs, int reps, double *avg_ms,
+                              hipStream_t st) {
+  set_error("");
+  if (!ctx || !avg_ms || nrhs < 1 || reps < 1) return bad(MG_EINVAL, "mg_time_coarse: bad arguments");
+  MG_TRY(check_ctx_level(ctx, level, 1, ctx->nlev - 1));
+  mg_ctx *c = ctx;
+  MG_TRY(ensure_prec(c, prec, st));
+  Level &L = c->lev[level];
+  const size_t n = L.vsize() * nrhs;
+  hipEvent_t e0, e1;
+  HIPK(hipEventCreate(&e0));
+  HIPK(hipEventCreate(&e1));
+  int rc = MG_OK;
+  if (prec == MG_F64) {
+    DevBuf<double2> a, b;
+    MG_TRY(a.alloc(n));
+    MG_TRY(b.alloc(n));
+    HIPK(zero<double>(a, n, st));
+    for (int i = 0; i < 2; ++i) HIPK(coarse_apply_k<double>(L.g, L.n, L.L64, a, b, nrhs, 0, nullptr, 1, nullptr, st));
+    HIPK(hipEventRecord(e0, st));
+    for (int i = 0; i < reps; ++i)
+      HIPK(coarse_apply_k<double>(L.g, L.n, L.L64, a, b, nrhs, 0, nullptr, 1, nullptr, st));
+    HIPK(hipEventRecord(e1, st));
+    HIPK(hipEventSynchronize(e1));
+  } else if (prec == MG_F32) {
+    DevBuf<float2> a, b;
+    MG_TRY(a.alloc(n));
+    MG_TRY(b.alloc(n));
+    HIPK(zero<float>(a, n, st));
+    for (int i = 0; i < 2; ++i) HIPK(coarse_apply_k<float>(L.g, L.n, L.L32, a, b, nrhs, 0, nullptr, 1, nullptr, st));
+    HIPK(hipEventRecord(e0, st));
+    for (int i = 0; i < reps; ++i)
+      HIPK(coarse_apply_k<float>(L.g, L.n, L.L32, a, b, nrhs, 0, nullptr, 1, nullptr, st));
+    HIPK(hipEventRecord(e1, st));
+    HIPK(hipEventSynchronize(e1));
+  } else {
+    rc = bad(MG_ENOTSUP, "mg_time_coarse: precision not built");
+  }
+  float ms = 0.f;
+  if (rc == MG_OK) HIPK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *avg_ms = ms / reps;
+  return rc;
+}
+
+extern "C" int mg_destroy(mg_ctx_t *ctx) {
+  if (!ctx) return MG_OK;
+  (void)hipDeviceSynchronize();
+  if (ctx->h_done) (void)hipHostFree(ctx->h_done);
+  if (ctx->h_rr) (void)hipHostFree(ctx->h_rr);
+  if (ctx->h_it) (void)hipHostFree(ctx->h_it);
+  delete ctx;
+  return MG_OK;
+}
+
+extern "C" int mg_level_info(mg_ctx_t *ctx, int level, int *L_out, int *ncomp_out) {
+  if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
+  MG_TRY(check_ctx_level(ctx, level, 0, ctx->nlev - 1));
+  if (L_out)
+    for (int mu = 0; mu < 4; ++mu) L_out[mu] = ctx->lev[level].g.L[mu];
+  if (ncomp_out) *ncomp_out = ctx->lev[level].n;
+  return MG_OK;
+}
+
+extern "C" int mg_export_maps(mg_ctx_t *ctx, int level, int32_t *f2c, int32_t *f2l, int32_t *cnbr, int32_t *face) {
+  set_error("");
+  if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
+  MG_TRY(check_ctx_level(ctx, level, 0, ctx->nlev - 2));
+  const Geom &g = ctx->lev[level].g, &gc = ctx->lev[level + 1].g;
+  DevBuf<int32_t> d;
+  MG_TRY(d.alloc(3 * (size_t)g.V + 8 * (size_t)gc.V));
+  int32_t *df2c = d.p, *df2l = d.p + g.V, *dface = d.p + 2 * (size_t)g.V, *dn = d.p + 3 * (size_t)g.V;
+  HIPK(export_maps_k(g, gc, df2c, df2l, dface, dn, nullptr));
+  HIPK(hipStreamSynchronize(nullptr));
+  if (f2c) HIPK(hipMemcpy(f2c, df2c, sizeof(int32_t) * g.V, hipMemcpyDeviceToHost));
+  if (f2l) HIPK(hipMemcpy(f2l, df2l, sizeof(int32_t) * g.V, hipMemcpyDeviceToHost));
+  if (face) HIPK(hipMemcpy(face, dface, sizeof(int32_t) * g.V, hipMemcpyDeviceToHost));
+  if (cnbr) HIPK(hipMemcpy(cnbr, dn, sizeof(int32_t) * 8 * gc.V, hipMemcpyDeviceToHost));
+  return MG_OK;
+}
+
+extern "C" int mg_export_P(mg_ctx_t *ctx, int level, void *P_host) {
+  set_error("");
+  if (!ctx || !P_host) return bad(MG_EINVAL, "mg_export_P: NULL argument");
+  MG_TRY(check_ctx_level(ctx, level, 0, ctx->nlev - 2));
+  const Level &L = ctx->lev[level];
+  const size_t cnt = L.P64.n;
+  std::vector<double2> h(cnt);
+  HIPK(hipDeviceSynchronize());
+  HIPK(hipMemcpy(h.data(), L.P64, cnt * sizeof(double2), hipMemcpyDeviceToHost));
+  double2 *out = (double2 *)P_host;
+  const int nv = L.nv, n = L.n, h2 = n / 2;
+  const size_t V = L.g.V, vb = L.g.vb, rows = vb * h2;
+  for (int k = 0; k < nv; ++k)
+    for (size_t s = 0; s < V; ++s) {
+      const size_t B = s / vb, l = s % vb;
+      for (int c = 0; c < n; ++c) {
+        const double2 v = (level == 0) ? h[((size_t)k * 12 + c) * V + s] : h[((size_t)k * V + s) * n + c];
+        const int chi = c / h2, j = c % h2;
+        out[((B * 2 + chi) * rows + l * h2 + j) * nv + k] = v;
+      }
+    }
+  return MG_OK;
+}
+
+extern "C" int mg_export_coarse_op(mg_ctx_t *ctx, int level, void *X_host, void *Y_host) {
+  set_error("");
+  if (!ctx || !X_host || !Y_host) return bad(MG_EINVAL, "mg_export_coarse_op: NULL argument");
+  MG_TRY(check_ctx_level(ctx, level, 1, ctx->nlev - 1));
+  const Level &L = ctx->lev[level];
+  const size_t cnt = L.L64.n;
+  std::vector<double2> h(cnt);
+  HIPK(hipDeviceSynchronize());
+  HIPK(hipMemcpy(h.data(), L.L64, cnt * sizeof(double2), hipMemcpyDeviceToHost));
+  const size_t V = L.g.V;
+  const int n = L.n;
+  double2 *X = (double2 *)X_host, *Y = (double2 *)Y_host;
+  for (uint32_t s = 0; s < V; ++s) {
+    const Coords k = decode(L.g, s);
+    const size_t i = canon_index(L.g, k);
+    for (int slot = 0; slot < 9; ++slot)
+      for (int j = 0; j < n; ++j)
+        for (int r = 0; r < n; ++r) {
+          const double2 v = h[(((size_t)s * 9 + slot) * n + j) * n + r];
+          if (slot == 0) X[(i * n + r) * n + j] = v;
+          else Y[((((size_t)(slot - 1)) * V + i) * n + r) * n + j] = v;
+        }
+  }
+  return MG_OK;
+}
+
+extern "C" int mg_export_nullvecs(mg_ctx_t *ctx, int level, void *V_host) {
+  set_error("");
+  if (!ctx || !V_host) return bad(MG_EINVAL, "mg_export_nullvecs: NULL argument");
+  MG_TRY(check_ctx_level(ctx, level, 0, ctx->nlev - 2));
+  const Level &L = ctx->lev[level];
+  DevBuf<double2> d;
+  MG_TRY(d.alloc(L.NV.n));
+  HIPK(unpack_level(ctx, level, L.NV, d.p, L.nv, nullptr));
+  HIPK(hipStreamSynchronize(nullptr));
+  HIPK(hipMemcpy(V_host, d.p, L.NV.n * sizeof(double2), hipMemcpyDeviceToHost));
+  return MG_OK;
+}

@@ -160,6 +160,19 @@ __host__ __device__ __forceinline__ uint32_t canon_index(const Geom &g, const Co
   return x[0] + (uint32_t)g.L[0] * (x[1] + (uint32_t)g.L[1] * (x[2] + (uint32_t)g.L[2] * x[3]));
 }
 
+// Site-blocked index of the site with lattice coordinates x[4].
+__host__ __device__ __forceinline__ uint32_t encode(const Geom &g, const int x[4]) {
+  int c[4], o[4];
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    c[mu] = x[mu] / g.b[mu];
+    o[mu] = x[mu] - c[mu] * g.b[mu];
+  }
+  const uint32_t B = (uint32_t)(c[0] + g.C[0] * (c[1] + g.C[1] * (c[2] + g.C[2] * c[3])));
+  const uint32_t l = (uint32_t)(o[0] + g.b[0] * (o[1] + g.b[1] * (o[2] + g.b[2] * o[3])));
+  return B * g.vb + l;
+}
+
 // XCD-aware block remapping: the hardware hands consecutive workgroup ids
 // round-robin to the 8 XCDs (each with its own L2).  Remapping so that every
 // XCD walks one contiguous range of tiles keeps stencil neighbours that are

@@ -1,0 +1,211 @@
+// Galerkin coarse operator D_c = P^dag D P as a nearest-neighbour stencil of
+// n x n blocks, n = 2 Nv (paper: A_c = P^dag A P; uniform aggregates keep the
+// coarse operator nearest neighbour with 2Nv x 2Nv link matrices).
+//
+// For coarse column j = (chi_j, k_j) let W = P e_j, i.e. null vector k_j
+// restricted to spin half chi_j on every aggregate.  Every hop of D applied to
+// W at site x reads W from one neighbour; it contributes to X(x_c) when the
+// hop stays inside the aggregate and to the stencil slot of the face it
+// crosses otherwise.  So
+//   X(x_c)[:, j]   = P^dag [ diag W + sum of intra-aggregate hops of W ] on x_c
+//   Y_d(x_c)[:, j] = P^dag [ hops of W in slot d that leave the aggregate ]
+// with P^dag the block-local restriction.  One workgroup per (coarse site,
+// column j); threads over the sites (fine) or elements (coarse) of the
+// aggregate; the 2Nv row inner products of each of the 9 slots are wavefront
+// shuffle reductions plus a fixed-order sum over waves.  FP64.
+// Output layout L[site][slot][j][i] (column-major blocks), slot 0 = X,
+// slot 1 + (2 mu + dir) = Y (dir 0: couples to x_c + mu).
+#include "kernels.h"
+#include "wilson_site.h"
+
+namespace mg {
+
+__device__ __forceinline__ uint32_t coarse_site_of(const Geom &gc, uint32_t B, const Geom &g) {
+  const int x[4] = {(int)(B % g.C[0]), (int)((B / g.C[0]) % g.C[1]), (int)((B / (g.C[0] * g.C[1])) % g.C[2]),
+                    (int)(B / (g.C[0] * g.C[1] * g.C[2]))};
+  return encode(gc, x);
+}
+
+// ------------------------------------------------------------------ fine
+// Hop d of W at site s (W = field k masked to chirality chi), times -1/2.
+__device__ __forceinline__ void fine_hop(double2 (&f)[12], const Geom &g, uint32_t s, const Coords &k, int d,
+                                         const double2 *__restrict__ U, const double2 *__restrict__ Pk, int chi) {
+  const size_t V = g.V;
+  const int mu = d >> 1;
+  const bool fwd = (d & 1) == 0;
+  uint32_t sn;
+  double eta = 1.0;
+  if (fwd) {
+    sn = nbr_fwd(g, s, k, mu);
+    if (mu == 3 && g.antiperiodic && k.o[3] == g.b[3] - 1 && k.c[3] == g.C[3] - 1) eta = -1.0;
+  } else {
+    sn = nbr_bwd(g, s, k, mu);
+    if (mu == 3 && g.antiperiodic && k.o[3] == 0 && k.c[3] == 0) eta = -1.0;
+  }
+  double2 psi[12], u[9], acc[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const bool on = (c / 6) == chi;
+    psi[c] = on ? Pk[(size_t)c * V + sn] : make_double2(0, 0);
+    acc[c] = make_double2(0, 0);
+  }
+  load_link(u, U, mu, fwd ? s : sn, V);
+  if (fwd) hop_dispatch<true>(mu, acc, psi, u, eta);
+  else hop_dispatch<false>(mu, acc, psi, u, eta);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) f[c] = cfma(make_double2(-0.5, 0.0), acc[c], f[c]);
+}
+
+__global__ __launch_bounds__(256) void k_galerkin_fine(Geom g, Geom gc, double diag, const double2 *__restrict__ U,
+                                                       int nv, const double2 *__restrict__ P,
+                                                       double2 *__restrict__ Lc) {
+  __shared__ double2 part[4][2 * COARSE_NMAX];
+  const size_t V = g.V;
+  const uint32_t B = blockIdx.x;
+  const int jcol = blockIdx.y, chi = jcol / nv, kj = jcol % nv;
+  const int n = 2 * nv;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = (blockDim.x + 63) >> 6;
+  const bool act = (uint32_t)tid < g.vb;
+  const uint32_t s = B * g.vb + (act ? tid : 0);
+  const Coords k = decode(g, s);
+  const double2 *Pj = P + (size_t)kj * 12 * V;
+  const uint32_t ic = coarse_site_of(gc, B, g);
+  for (int slot = 0; slot < 9; ++slot) {
+    double2 f[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) f[c] = make_double2(0, 0);
+    if (act) {
+      if (slot == 0) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c)
+          if ((c / 6) == chi) f[c] = cscale(Pj[(size_t)c * V + s], diag);
+        for (int d = 0; d < 8; ++d) {
+          const int mu = d >> 1;
+          const bool face = (d & 1) == 0 ? (k.o[mu] == g.b[mu] - 1) : (k.o[mu] == 0);
+          if (!face) fine_hop(f, g, s, k, d, U, Pj, chi);
+        }
+      } else {
+        const int d = slot - 1, mu = d >> 1;
+        const bool face = (d & 1) == 0 ? (k.o[mu] == g.b[mu] - 1) : (k.o[mu] == 0);
+        if (face) fine_hop(f, g, s, k, d, U, Pj, chi);
+      }
+    }
+    for (int ki = 0; ki < nv; ++ki) {
+      const double2 *Pi = P + (size_t)ki * 12 * V;
+      double2 d0 = make_double2(0, 0), d1 = make_double2(0, 0);
+      if (act) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) d0 = cfmac(Pi[(size_t)c * V + s], f[c], d0);
+#pragma unroll
+        for (int c = 6; c < 12; ++c) d1 = cfmac(Pi[(size_t)c * V + s], f[c], d1);
+      }
+      const double a0 = wave_sum(d0.x), b0 = wave_sum(d0.y), a1 = wave_sum(d1.x), b1 = wave_sum(d1.y);
+      if (lane == 0) {
+        part[w][ki] = make_double2(a0, b0);
+        part[w][nv + ki] = make_double2(a1, b1);
+      }
+    }
+    __syncthreads();
+    if (tid < n) {
+      double2 a = part[0][tid];
+      for (int q = 1; q < nw; ++q) {
+        a.x += part[q][tid].x;
+        a.y += part[q][tid].y;
+      }
+      Lc[(((size_t)ic * 9 + slot) * n + jcol) * n + tid] = a;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t galerkin_fine(const Geom &g, const Geom &gc, double mass, const double2 *U, int nv, const double2 *P,
+                         double2 *Lc, hipStream_t st) {
+  const int th = (int)((g.vb + 63) / 64 * 64);
+  hipLaunchKernelGGL(k_galerkin_fine, dim3(g.Vc, 2 * nv), dim3(th), 0, st, g, gc, 4.0 + mass, U, nv, P, Lc);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ coarse
+constexpr int GC_EMAX = 8;
+
+__global__ __launch_bounds__(256) void k_galerkin_coarse(Geom g, Geom gc, int n, const double2 *__restrict__ L1,
+                                                         int nv, const double2 *__restrict__ P,
+                                                         double2 *__restrict__ Lc) {
+  __shared__ double2 part[4][2 * COARSE_NMAX];
+  const size_t V = g.V;
+  const uint32_t B = blockIdx.x;
+  const int jcol = blockIdx.y, chi = jcol / nv, kj = jcol % nv;
+  const int nc = 2 * nv, half = n >> 1;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = (blockDim.x + 63) >> 6;
+  const int ne = (int)g.vb * n;
+  const double2 *Pj = P + (size_t)kj * V * n;
+  const uint32_t ic = coarse_site_of(gc, B, g);
+  for (int slot = 0; slot < 9; ++slot) {
+    double2 f[GC_EMAX];
+#pragma unroll
+    for (int q = 0; q < GC_EMAX; ++q) {
+      f[q] = make_double2(0, 0);
+      const int e = tid + q * (int)blockDim.x;
+      if (e >= ne) continue;
+      const uint32_t t = (uint32_t)(e / n);
+      const int ii = e - (int)t * n;
+      const uint32_t s = B * g.vb + t;
+      const Coords k = decode(g, s);
+      // (L1[s][slot1] W(site))_ii summed over the needed slots
+      for (int s1 = 0; s1 < 9; ++s1) {
+        bool use;
+        uint32_t src = s;
+        if (s1 == 0) {
+          use = (slot == 0);
+        } else {
+          const int d = s1 - 1, mu = d >> 1;
+          const bool face = (d & 1) == 0 ? (k.o[mu] == g.b[mu] - 1) : (k.o[mu] == 0);
+          use = (slot == 0) ? !face : (slot == s1 && face);
+          src = (d & 1) ? nbr_bwd(g, s, k, mu) : nbr_fwd(g, s, k, mu);
+        }
+        if (!use) continue;
+        const double2 *Lb = L1 + ((size_t)s * 9 + s1) * n * n + ii;
+        const double2 *Wv = Pj + (size_t)src * n;
+        double2 a = f[q];
+        const int j0 = chi * half;
+        for (int jj = j0; jj < j0 + half; ++jj) a = cfma(Lb[(size_t)jj * n], Wv[jj], a);
+        f[q] = a;
+      }
+    }
+    for (int ki = 0; ki < nv; ++ki) {
+      const double2 *Pi = P + (size_t)ki * V * n + (size_t)B * g.vb * n;
+      double2 d0 = make_double2(0, 0), d1 = make_double2(0, 0);
+#pragma unroll
+      for (int q = 0; q < GC_EMAX; ++q) {
+        const int e = tid + q * (int)blockDim.x;
+        if (e < ne) {
+          if ((e % n) < half) d0 = cfmac(Pi[e], f[q], d0);
+          else d1 = cfmac(Pi[e], f[q], d1);
+        }
+      }
+      const double a0 = wave_sum(d0.x), b0 = wave_sum(d0.y), a1 = wave_sum(d1.x), b1 = wave_sum(d1.y);
+      if (lane == 0) {
+        part[w][ki] = make_double2(a0, b0);
+        part[w][nv + ki] = make_double2(a1, b1);
+      }
+    }
+    __syncthreads();
+    if (tid < nc) {
+      double2 a = part[0][tid];
+      for (int q = 1; q < nw; ++q) {
+        a.x += part[q][tid].x;
+        a.y += part[q][tid].y;
+      }
+      Lc[(((size_t)ic * 9 + slot) * nc + jcol) * nc + tid] = a;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t galerkin_coarse(const Geom &g, const Geom &gc, int n, const double2 *L1, int nv, const double2 *P,
+                           double2 *Lc, hipStream_t st) {
+  hipLaunchKernelGGL(k_galerkin_coarse, dim3(g.Vc, 2 * nv), dim3(256), 0, st, g, gc, n, L1, nv, P, Lc);
+  return hipGetLastError();
+}
+
+}  // namespace mg

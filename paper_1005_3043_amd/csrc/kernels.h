@@ -32,3 +32,49 @@ template <typename Rd, typename Rs>
 hipError_t convert(c_t<Rd> *y, const c_t<Rs> *x, size_t n, hipStream_t st);
 
 }  // namespace mg
+
+namespace mg {
+
+// ---- coarse.hip: 9-point coarse stencil on site-major coarse vectors.
+constexpr int COARSE_NMAX = 64;
+int coarse_threads(int n);
+// out = D_c in (dagger: sigma3 D_c sigma3).  When partials != nullptr each
+// site writes pw doubles at partials[(rhs*V + site)*pw]: pw = 1: ||out||^2;
+// pw = 3: <out, in>, ||out||^2.  A right-hand side with done[rhs] != 0 is
+// skipped (done may be nullptr).
+template <typename R>
+hipError_t coarse_apply_k(const Geom &g, int n, const c_t<R> *L, const c_t<R> *in, c_t<R> *out, int nrhs,
+                          int dagger, double *partials, int pw, const int *done, hipStream_t st);
+
+// ---- transfer.hip
+// Fine level: P = nv null-vector fields in fine SoA layout [nv][12][V].
+// g = geometry of the finer level (tile = aggregate), gc = geometry of the
+// coarser level (its own site-blocked order).
+template <typename R>
+hipError_t restrict_fine(const Geom &g, const Geom &gc, int nv, const c_t<R> *P, const c_t<R> *fine,
+                         c_t<R> *coarse, int nrhs, hipStream_t st);
+// fine (+)= P coarse  (accumulate != 0: add into fine)
+template <typename R>
+hipError_t prolong_fine(const Geom &g, const Geom &gc, int nv, const c_t<R> *P, const c_t<R> *coarse,
+                        c_t<R> *fine, int nrhs, int accumulate, hipStream_t st);
+// Coarse level l -> l+1: P = nv vectors in coarse AoS layout [nv][V][n];
+// requires block volume * n <= 2048.
+template <typename R>
+hipError_t restrict_coarse(const Geom &g, const Geom &gc, int n, int nv, const c_t<R> *P, const c_t<R> *fine,
+                           c_t<R> *coarse, int nrhs, hipStream_t st);
+template <typename R>
+hipError_t prolong_coarse(const Geom &g, const Geom &gc, int n, int nv, const c_t<R> *P, const c_t<R> *coarse,
+                          c_t<R> *fine, int nrhs, int accumulate, hipStream_t st);
+
+// ---- ortho.hip: in-place block orthonormalisation (MGS applied twice) per
+// (aggregate, chirality); rank-deficiency sets *flag = 1.
+hipError_t ortho_fine(const Geom &g, int nv, double2 *V, int *flag, hipStream_t st);
+hipError_t ortho_coarse(const Geom &g, int n, int nv, double2 *V, int *flag, hipStream_t st);
+
+// ---- galerkin.hip: D_c = P^dag D P into L[Vc][9][n][n] (column-major blocks).
+hipError_t galerkin_fine(const Geom &g, const Geom &gc, double mass, const double2 *U, int nv, const double2 *P,
+                         double2 *Lc, hipStream_t st);
+hipError_t galerkin_coarse(const Geom &g, const Geom &gc, int n, const double2 *L1, int nv, const double2 *P,
+                           double2 *Lc, hipStream_t st);
+
+}  // namespace mg

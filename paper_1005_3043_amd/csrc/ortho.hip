@@ -1,0 +1,165 @@
+// Block orthonormalisation of the null-space candidates (Eq. 4): per
+// (aggregate, chirality) block B = Q R with Q having orthonormal columns and
+// R upper triangular with a positive real diagonal (this fixes Q uniquely).
+// Modified Gram-Schmidt applied twice, in place, FP64.
+//
+// One workgroup per aggregate handles both chirality halves: each thread
+// keeps its site's (fine) or elements' (coarse) part of the current column in
+// registers; each projection coefficient is a block reduction (wavefront
+// shuffles, then a fixed-order sum of the per-wave partials in LDS that every
+// thread evaluates identically).
+#include "kernels.h"
+
+namespace mg {
+
+// Sum of 4 doubles over the workgroup, result in every thread.
+__device__ __forceinline__ void block_allsum4(double (&v)[4], double (*lds)[4]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) lds[w][i] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double a = lds[0][i];
+    for (int q = 1; q < nw; ++q) a += lds[q][i];
+    v[i] = a;
+  }
+  __syncthreads();
+}
+
+constexpr double RANK_TOL = 1e-14;
+
+// Fine level: V[k][c][s] (SoA), aggregate of vb <= 256 sites, comps 0..5 =
+// chirality 0, 6..11 = chirality 1.
+__global__ __launch_bounds__(256) void k_ortho_fine(Geom g, int nv, double2 *__restrict__ V, int *flag) {
+  __shared__ double lds[4][4];
+  const size_t Vn = g.V;
+  const uint32_t t = threadIdx.x;
+  const bool act = t < g.vb;
+  const uint32_t s = blockIdx.x * g.vb + (act ? t : 0);
+  for (int kk = 0; kk < nv; ++kk) {
+    double2 *Vk = V + (size_t)kk * 12 * Vn;
+    double2 v[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) v[c] = act ? Vk[(size_t)c * Vn + s] : make_double2(0, 0);
+    double n0[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < 12; ++c) n0[c / 6] += v[c].x * v[c].x + v[c].y * v[c].y;
+    block_allsum4(n0, lds);
+    for (int sweep = 0; sweep < 2; ++sweep) {
+      for (int j = 0; j < kk; ++j) {
+        const double2 *Vj = V + (size_t)j * 12 * Vn;
+        double2 q[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) q[c] = act ? Vj[(size_t)c * Vn + s] : make_double2(0, 0);
+        double2 c0 = make_double2(0, 0), c1 = make_double2(0, 0);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) c0 = cfmac(q[c], v[c], c0);
+#pragma unroll
+        for (int c = 6; c < 12; ++c) c1 = cfmac(q[c], v[c], c1);
+        double cc[4] = {c0.x, c0.y, c1.x, c1.y};
+        block_allsum4(cc, lds);
+        const double2 a0 = make_double2(-cc[0], -cc[1]), a1 = make_double2(-cc[2], -cc[3]);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] = cfma(a0, q[c], v[c]);
+#pragma unroll
+        for (int c = 6; c < 12; ++c) v[c] = cfma(a1, q[c], v[c]);
+      }
+    }
+    double nn[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < 12; ++c) nn[c / 6] += v[c].x * v[c].x + v[c].y * v[c].y;
+    block_allsum4(nn, lds);
+    const double r0 = sqrt(nn[0]), r1 = sqrt(nn[1]);
+    if (t == 0 && (!(r0 > RANK_TOL * sqrt(n0[0])) || !(r1 > RANK_TOL * sqrt(n0[1])))) *flag = 1;
+    const double i0 = r0 > 0 ? 1.0 / r0 : 0.0, i1 = r1 > 0 ? 1.0 / r1 : 0.0;
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) Vk[(size_t)c * Vn + s] = cscale(v[c], c < 6 ? i0 : i1);
+    }
+    __syncthreads();
+  }
+}
+
+// Coarse level: V[k][s][j] (site-major), elements e = t * n + j of the
+// aggregate (vb * n <= 2048), chirality = (j >= n / 2).
+constexpr int OC_EMAX = 8;
+
+__global__ __launch_bounds__(256) void k_ortho_coarse(Geom g, int n, int nv, double2 *__restrict__ V, int *flag) {
+  __shared__ double lds[4][4];
+  const size_t Vn = g.V;
+  const int tid = threadIdx.x;
+  const int ne = (int)g.vb * n, half = n >> 1;
+  const size_t base = (size_t)blockIdx.x * g.vb * n;
+  for (int kk = 0; kk < nv; ++kk) {
+    double2 *Vk = V + (size_t)kk * Vn * n + base;
+    double2 v[OC_EMAX];
+#pragma unroll
+    for (int q = 0; q < OC_EMAX; ++q) {
+      const int e = tid + q * (int)blockDim.x;
+      v[q] = e < ne ? Vk[e] : make_double2(0, 0);
+    }
+    double n0[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < OC_EMAX; ++q) {
+      const int e = tid + q * (int)blockDim.x;
+      n0[(e % n) < half ? 0 : 1] += v[q].x * v[q].x + v[q].y * v[q].y;
+    }
+    block_allsum4(n0, lds);
+    for (int sweep = 0; sweep < 2; ++sweep) {
+      for (int j = 0; j < kk; ++j) {
+        const double2 *Vj = V + (size_t)j * Vn * n + base;
+        double2 qv[OC_EMAX];
+        double2 c0 = make_double2(0, 0), c1 = make_double2(0, 0);
+#pragma unroll
+        for (int q = 0; q < OC_EMAX; ++q) {
+          const int e = tid + q * (int)blockDim.x;
+          qv[q] = e < ne ? Vj[e] : make_double2(0, 0);
+          if ((e % n) < half) c0 = cfmac(qv[q], v[q], c0);
+          else c1 = cfmac(qv[q], v[q], c1);
+        }
+        double cc[4] = {c0.x, c0.y, c1.x, c1.y};
+        block_allsum4(cc, lds);
+        const double2 a0 = make_double2(-cc[0], -cc[1]), a1 = make_double2(-cc[2], -cc[3]);
+#pragma unroll
+        for (int q = 0; q < OC_EMAX; ++q) {
+          const int e = tid + q * (int)blockDim.x;
+          v[q] = cfma((e % n) < half ? a0 : a1, qv[q], v[q]);
+        }
+      }
+    }
+    double nn[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < OC_EMAX; ++q) {
+      const int e = tid + q * (int)blockDim.x;
+      nn[(e % n) < half ? 0 : 1] += v[q].x * v[q].x + v[q].y * v[q].y;
+    }
+    block_allsum4(nn, lds);
+    const double r0 = sqrt(nn[0]), r1 = sqrt(nn[1]);
+    if (tid == 0 && (!(r0 > RANK_TOL * sqrt(n0[0])) || !(r1 > RANK_TOL * sqrt(n0[1])))) *flag = 1;
+    const double i0 = r0 > 0 ? 1.0 / r0 : 0.0, i1 = r1 > 0 ? 1.0 / r1 : 0.0;
+#pragma unroll
+    for (int q = 0; q < OC_EMAX; ++q) {
+      const int e = tid + q * (int)blockDim.x;
+      if (e < ne) Vk[e] = cscale(v[q], (e % n) < half ? i0 : i1);
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t ortho_fine(const Geom &g, int nv, double2 *V, int *flag, hipStream_t st) {
+  const int th = (int)((g.vb + 63) / 64 * 64);
+  hipLaunchKernelGGL(k_ortho_fine, dim3(g.Vc), dim3(th), 0, st, g, nv, V, flag);
+  return hipGetLastError();
+}
+
+hipError_t ortho_coarse(const Geom &g, int n, int nv, double2 *V, int *flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_ortho_coarse, dim3(g.Vc), dim3(256), 0, st, g, n, nv, V, flag);
+  return hipGetLastError();
+}
+
+}  // namespace mg

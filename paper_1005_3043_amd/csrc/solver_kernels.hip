@@ -1,0 +1,382 @@
+// Streaming kernels of the Krylov / smoothing loops.  Scalars (inner
+// products, step lengths, convergence flags) stay on the device: reductions
+// write per-block partials, a one-workgroup finisher per right-hand side sums
+// them in a fixed order and derives the coefficient, and the consuming kernel
+// reads it.  The host only reads residual norms for convergence decisions.
+// Vectors are flat complex arrays of N entries per right-hand side
+// (blockIdx.y = right-hand side); any site layout works.
+#include "solver.h"
+
+namespace mg {
+
+static inline int sgrid(size_t n) {
+  size_t b = (n + 255) / 256;
+  return (int)(b < RED_BLOCKS ? (b == 0 ? 1 : b) : RED_BLOCKS);
+}
+#define GSTRIDE(i, n) \
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (n); i += (size_t)gridDim.x * blockDim.x)
+
+// --------------------------------------------------------------- finishers
+// Sum np partials of width w (stride w) for the RHS blockIdx.y into tot[0..w).
+template <int W>
+__device__ __forceinline__ void finish_sum(const double *__restrict__ part, int np, double (&tot)[W]) {
+  __shared__ double lds[4 * W];
+  part += (size_t)blockIdx.y * np * W;
+#pragma unroll
+  for (int q = 0; q < W; ++q) tot[q] = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+#pragma unroll
+    for (int q = 0; q < W; ++q) tot[q] += part[(size_t)i * W + q];
+  }
+  block_sum<W>(tot, lds);
+}
+
+// MR: alpha = omega <q,r> / <q,q>  (stored as complex; 0 when q = 0)
+__global__ void k_fin_mr(const double *part, int np, double omega, double2 *alpha) {
+  double t[3];
+  finish_sum<3>(part, np, t);
+  if (threadIdx.x == 0) {
+    double2 a = make_double2(0.0, 0.0);
+    if (t[2] > 0.0) a = make_double2(omega * t[0] / t[2], omega * t[1] / t[2]);
+    alpha[blockIdx.y] = a;
+  }
+}
+
+// plain sums: out[rhs*W + q]
+template <int W> __global__ void k_fin_sum(const double *part, int np, double *out) {
+  double t[W];
+  finish_sum<W>(part, np, t);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < W; ++q) out[(size_t)blockIdx.y * W + q] = t[q];
+  }
+}
+
+// CGNR scalars per RHS: cg[0] = zz, cg[1] = alpha, cg[2] = beta, cg[3] = nb2,
+// cg[4] = tol^2, cg[5] = rr; it[rhs] = iterations; done[rhs] = converged.
+__global__ void k_fin_cg_alpha(const double *part, int np, double *cg, int *done) {
+  if (done[blockIdx.y]) return;
+  double t[1];
+  finish_sum<1>(part, np, t);
+  if (threadIdx.x == 0) {
+    double *c = cg + (size_t)blockIdx.y * CG_NS;
+    if (t[0] > 0.0) c[1] = c[0] / t[0];
+    else { c[1] = 0.0; done[blockIdx.y] = 1; }
+  }
+}
+__global__ void k_fin_cg_rr(const double *part, int np, double *cg, int *done, int *it, int maxit) {
+  if (done[blockIdx.y]) return;
+  double t[1];
+  finish_sum<1>(part, np, t);
+  if (threadIdx.x == 0) {
+    double *c = cg + (size_t)blockIdx.y * CG_NS;
+    c[5] = t[0];
+    const int n = ++it[blockIdx.y];
+    if (!(t[0] > c[4] * c[3]) || n >= maxit) done[blockIdx.y] = 1;
+  }
+}
+__global__ void k_fin_cg_beta(const double *part, int np, double *cg, int *done) {
+  if (done[blockIdx.y]) return;
+  double t[1];
+  finish_sum<1>(part, np, t);
+  if (threadIdx.x == 0) {
+    double *c = cg + (size_t)blockIdx.y * CG_NS;
+    c[2] = c[0] > 0.0 ? t[0] / c[0] : 0.0;
+    c[0] = t[0];
+  }
+}
+__global__ void k_fin_cg_init(const double *part_z, int npz, const double *part_b, int npb, double *cg, int *done,
+                              int *it, double tol2) {
+  double t[1], tb[1];
+  finish_sum<1>(part_z, npz, t);
+  __syncthreads();
+  finish_sum<1>(part_b, npb, tb);
+  if (threadIdx.x == 0) {
+    double *c = cg + (size_t)blockIdx.y * CG_NS;
+    c[0] = t[0];
+    c[3] = tb[0];
+    c[4] = tol2;
+    c[5] = tb[0];
+    it[blockIdx.y] = 0;
+    done[blockIdx.y] = (tb[0] > 0.0 && t[0] > 0.0) ? 0 : 1;
+  }
+}
+
+// --------------------------------------------------------------- reductions
+template <typename R>
+__global__ __launch_bounds__(256) void k_norm2(const c_t<R> *a, size_t n, double *part) {
+  __shared__ double lds[4];
+  a += (size_t)blockIdx.y * n;
+  double t[1] = {0.0};
+  GSTRIDE(i, n) {
+    const c_t<R> v = a[i];
+    t[0] += (double)v.x * v.x + (double)v.y * v.y;
+  }
+  block_sum<1>(t, lds);
+  if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = t[0];
+}
+
+// <a, b> = sum conj(a) b -> 2 doubles per block
+template <typename R>
+__global__ __launch_bounds__(256) void k_dot(const c_t<R> *a, const c_t<R> *b, size_t n, double *part) {
+  __shared__ double lds[8];
+  a += (size_t)blockIdx.y * n;
+  b += (size_t)blockIdx.y * n;
+  double t[2] = {0.0, 0.0};
+  GSTRIDE(i, n) {
+    const c_t<R> u = a[i], v = b[i];
+    t[0] += (double)u.x * v.x + (double)u.y * v.y;
+    t[1] += (double)u.x * v.y - (double)u.y * v.x;
+  }
+  block_sum<2>(t, lds);
+  if (threadIdx.x == 0) {
+    double *p = part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 2;
+    p[0] = t[0];
+    p[1] = t[1];
+  }
+}
+
+// --------------------------------------------------------------- updates
+// MR: x = (first ? 0 : x) + alpha r;  r -= alpha q
+template <typename R>
+__global__ __launch_bounds__(256) void k_mr_update(c_t<R> *x, c_t<R> *r, const c_t<R> *q, size_t n,
+                                                   const double2 *alpha, int first) {
+  using C = c_t<R>;
+  const size_t off = (size_t)blockIdx.y * n;
+  x += off; r += off; q += off;
+  const double2 ad = alpha[blockIdx.y];
+  const C a = mk<C>((R)ad.x, (R)ad.y), ma = mk<C>((R)-ad.x, (R)-ad.y);
+  GSTRIDE(i, n) {
+    const C rv = r[i];
+    x[i] = first ? cmul(a, rv) : cfma(a, rv, x[i]);
+    r[i] = cfma(ma, q[i], rv);
+  }
+}
+
+// CGNR: e += alpha p; r -= alpha w; partial ||r||^2
+template <typename R>
+__global__ __launch_bounds__(256) void k_cg_update(c_t<R> *e, const c_t<R> *p, c_t<R> *r, const c_t<R> *w, size_t n,
+                                                   const double *cg, const int *done, double *part) {
+  using C = c_t<R>;
+  __shared__ double lds[4];
+  if (done[blockIdx.y]) return;
+  const size_t off = (size_t)blockIdx.y * n;
+  e += off; p += off; r += off; w += off;
+  const R a = (R)cg[(size_t)blockIdx.y * CG_NS + 1];
+  double t[1] = {0.0};
+  GSTRIDE(i, n) {
+    e[i] = cfma(mk<C>(a, 0), p[i], e[i]);
+    const C rv = cfma(mk<C>(-a, 0), w[i], r[i]);
+    r[i] = rv;
+    t[0] += (double)rv.x * rv.x + (double)rv.y * rv.y;
+  }
+  block_sum<1>(t, lds);
+  if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = t[0];
+}
+
+// CGNR: p = z + beta p
+template <typename R>
+__global__ __launch_bounds__(256) void k_cg_p(c_t<R> *p, const c_t<R> *z, size_t n, const double *cg,
+                                              const int *done) {
+  using C = c_t<R>;
+  if (done[blockIdx.y]) return;
+  const size_t off = (size_t)blockIdx.y * n;
+  p += off; z += off;
+  const R b = (R)cg[(size_t)blockIdx.y * CG_NS + 2];
+  GSTRIDE(i, n) p[i] = cfma(mk<C>(b, 0), p[i], z[i]);
+}
+
+// y -= c x and v -= c u with c = sc[rhs] (complex)  (FGCR Gram-Schmidt)
+__global__ __launch_bounds__(256) void k_sub2(double2 *y, const double2 *x, double2 *v, const double2 *u, size_t n,
+                                              const double2 *sc, const int *skip) {
+  if (skip && skip[blockIdx.y]) return;
+  const size_t off = (size_t)blockIdx.y * n;
+  y += off; x += off; v += off; u += off;
+  const double2 c = sc[blockIdx.y];
+  const double2 mc = make_double2(-c.x, -c.y);
+  GSTRIDE(i, n) {
+    y[i] = cfma(mc, x[i], y[i]);
+    v[i] = cfma(mc, u[i], v[i]);
+  }
+}
+
+// y *= 1/sqrt(nrm2[rhs]), v *= same
+__global__ __launch_bounds__(256) void k_scale2(double2 *y, double2 *v, size_t n, const double *nrm2,
+                                                const int *skip) {
+  if (skip && skip[blockIdx.y]) return;
+  const size_t off = (size_t)blockIdx.y * n;
+  y += off; v += off;
+  const double nn = nrm2[blockIdx.y];
+  const double s = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+  GSTRIDE(i, n) {
+    y[i] = cscale(y[i], s);
+    v[i] = cscale(v[i], s);
+  }
+}
+
+// x += a z; r -= a w (a = sc[rhs]); partial ||r||^2
+__global__ __launch_bounds__(256) void k_gcr_update(double2 *x, const double2 *z, double2 *r, const double2 *w,
+                                                    size_t n, const double2 *sc, const int *skip, double *part) {
+  __shared__ double lds[4];
+  const size_t off = (size_t)blockIdx.y * n;
+  double t[1] = {0.0};
+  const bool sk = skip && skip[blockIdx.y];
+  if (!sk) {
+    x += off; z += off; r += off; w += off;
+    const double2 a = sc[blockIdx.y];
+    const double2 ma = make_double2(-a.x, -a.y);
+    GSTRIDE(i, n) {
+      x[i] = cfma(a, z[i], x[i]);
+      const double2 rv = cfma(ma, w[i], r[i]);
+      r[i] = rv;
+      t[0] += rv.x * rv.x + rv.y * rv.y;
+    }
+  } else {
+    r += off;
+    GSTRIDE(i, n) {
+      const double2 rv = r[i];
+      t[0] += rv.x * rv.x + rv.y * rv.y;
+    }
+  }
+  block_sum<1>(t, lds);
+  if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = t[0];
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_sub(c_t<R> *v, const c_t<R> *x, size_t n) {
+  const size_t off = (size_t)blockIdx.y * n;
+  v += off; x += off;
+  GSTRIDE(i, n) v[i] = csub(v[i], x[i]);
+}
+template <typename R>
+__global__ __launch_bounds__(256) void k_scale_rsqrt(c_t<R> *v, size_t n, const double *nrm2) {
+  v += (size_t)blockIdx.y * n;
+  const double nn = nrm2[blockIdx.y];
+  const R s = (R)(nn > 0.0 ? 1.0 / sqrt(nn) : 0.0);
+  GSTRIDE(i, n) v[i] = cscale(v[i], s);
+}
+template <typename R>
+__global__ __launch_bounds__(256) void k_resid_from(c_t<R> *out, const c_t<R> *b, size_t n) {
+  const size_t off = (size_t)blockIdx.y * n;
+  out += off; b += off;
+  GSTRIDE(i, n) out[i] = csub(b[i], out[i]);
+}
+
+// ====================================================================== host
+template <typename R> hipError_t sub_inplace(c_t<R> *v, const c_t<R> *x, size_t n, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_sub<R>, dim3(sgrid(n), nrhs), dim3(256), 0, st, v, x, n);
+  return hipGetLastError();
+}
+template <typename R> hipError_t scale_rsqrt(c_t<R> *v, size_t n, int nrhs, const double *nrm2, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_rsqrt<R>, dim3(sgrid(n), nrhs), dim3(256), 0, st, v, n, nrm2);
+  return hipGetLastError();
+}
+template <typename R> hipError_t resid_from(c_t<R> *out, const c_t<R> *b, size_t n, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_resid_from<R>, dim3(sgrid(n), nrhs), dim3(256), 0, st, out, b, n);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t mr_update(c_t<R> *x, c_t<R> *r, const c_t<R> *q, size_t n, int nrhs, const double *part, int np,
+                     double omega, double2 *alpha, int first, hipStream_t st) {
+  hipLaunchKernelGGL(k_fin_mr, dim3(1, nrhs), dim3(256), 0, st, part, np, omega, alpha);
+  hipLaunchKernelGGL(k_mr_update<R>, dim3(sgrid(n), nrhs), dim3(256), 0, st, x, r, q, n, alpha, first);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t norm2(const c_t<R> *a, size_t n, int nrhs, double *part, double *out, hipStream_t st) {
+  const int g = sgrid(n);
+  hipLaunchKernelGGL(k_norm2<R>, dim3(g, nrhs), dim3(256), 0, st, a, n, part);
+  hipLaunchKernelGGL(k_fin_sum<1>, dim3(1, nrhs), dim3(256), 0, st, part, g, out);
+  return hipGetLastError();
+}
+
+template <typename R> int norm2_partials(const c_t<R> *a, size_t n, int nrhs, double *part, hipStream_t st) {
+  const int g = sgrid(n);
+  hipLaunchKernelGGL(k_norm2<R>, dim3(g, nrhs), dim3(256), 0, st, a, n, part);
+  return g;
+}
+
+template <typename R>
+hipError_t dot(const c_t<R> *a, const c_t<R> *b, size_t n, int nrhs, double *part, double2 *out, hipStream_t st) {
+  const int g = sgrid(n);
+  hipLaunchKernelGGL(k_dot<R>, dim3(g, nrhs), dim3(256), 0, st, a, b, n, part);
+  hipLaunchKernelGGL(k_fin_sum<2>, dim3(1, nrhs), dim3(256), 0, st, part, g, (double *)out);
+  return hipGetLastError();
+}
+
+hipError_t finish_sum1(const double *part, int np, int nrhs, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_fin_sum<1>, dim3(1, nrhs), dim3(256), 0, st, part, np, out);
+  return hipGetLastError();
+}
+
+hipError_t cg_init_scalars(const double *part_z, int npz, const double *part_b, int npb, int nrhs, double *cg,
+                           int *done, int *it, double tol, hipStream_t st) {
+  hipLaunchKernelGGL(k_fin_cg_init, dim3(1, nrhs), dim3(256), 0, st, part_z, npz, part_b, npb, cg, done, it,
+                     tol * tol);
+  return hipGetLastError();
+}
+
+hipError_t cg_alpha(const double *part, int np, int nrhs, double *cg, int *done, hipStream_t st) {
+  hipLaunchKernelGGL(k_fin_cg_alpha, dim3(1, nrhs), dim3(256), 0, st, part, np, cg, done);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t cg_update(c_t<R> *e, const c_t<R> *p, c_t<R> *r, const c_t<R> *w, size_t n, int nrhs, double *cg,
+                     int *done, int *it, int maxit, double *part, hipStream_t st) {
+  const int g = sgrid(n);
+  hipLaunchKernelGGL(k_cg_update<R>, dim3(g, nrhs), dim3(256), 0, st, e, p, r, w, n, cg, done, part);
+  hipLaunchKernelGGL(k_fin_cg_rr, dim3(1, nrhs), dim3(256), 0, st, part, g, cg, done, it, maxit);
+  return hipGetLastError();
+}
+
+hipError_t cg_beta(const double *part, int np, int nrhs, double *cg, int *done, hipStream_t st) {
+  hipLaunchKernelGGL(k_fin_cg_beta, dim3(1, nrhs), dim3(256), 0, st, part, np, cg, done);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t cg_p(c_t<R> *p, const c_t<R> *z, size_t n, int nrhs, const double *cg, const int *done, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_p<R>, dim3(sgrid(n), nrhs), dim3(256), 0, st, p, z, n, cg, done);
+  return hipGetLastError();
+}
+
+hipError_t gcr_sub2(double2 *y, const double2 *x, double2 *v, const double2 *u, size_t n, int nrhs,
+                    const double2 *sc, const int *skip, hipStream_t st) {
+  hipLaunchKernelGGL(k_sub2, dim3(sgrid(n), nrhs), dim3(256), 0, st, y, x, v, u, n, sc, skip);
+  return hipGetLastError();
+}
+
+hipError_t gcr_scale2(double2 *y, double2 *v, size_t n, int nrhs, const double *nrm2, const int *skip,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_scale2, dim3(sgrid(n), nrhs), dim3(256), 0, st, y, v, n, nrm2, skip);
+  return hipGetLastError();
+}
+
+hipError_t gcr_update(double2 *x, const double2 *z, double2 *r, const double2 *w, size_t n, int nrhs,
+                      const double2 *sc, const int *skip, double *part, double *rr, hipStream_t st) {
+  const int g = sgrid(n);
+  hipLaunchKernelGGL(k_gcr_update, dim3(g, nrhs), dim3(256), 0, st, x, z, r, w, n, sc, skip, part);
+  hipLaunchKernelGGL(k_fin_sum<1>, dim3(1, nrhs), dim3(256), 0, st, part, g, rr);
+  return hipGetLastError();
+}
+
+#define INST(R)                                                                                                     \
+  template hipError_t mr_update<R>(c_t<R> *, c_t<R> *, const c_t<R> *, size_t, int, const double *, int, double,    \
+                                   double2 *, int, hipStream_t);                                                    \
+  template hipError_t norm2<R>(const c_t<R> *, size_t, int, double *, double *, hipStream_t);                       \
+  template int norm2_partials<R>(const c_t<R> *, size_t, int, double *, hipStream_t);                               \
+  template hipError_t dot<R>(const c_t<R> *, const c_t<R> *, size_t, int, double *, double2 *, hipStream_t);        \
+  template hipError_t cg_update<R>(c_t<R> *, const c_t<R> *, c_t<R> *, const c_t<R> *, size_t, int, double *,       \
+                                   int *, int *, int, double *, hipStream_t);                                       \
+  template hipError_t cg_p<R>(c_t<R> *, const c_t<R> *, size_t, int, const double *, const int *, hipStream_t);      \
+  template hipError_t sub_inplace<R>(c_t<R> *, const c_t<R> *, size_t, int, hipStream_t);                           \
+  template hipError_t scale_rsqrt<R>(c_t<R> *, size_t, int, const double *, hipStream_t);                           \
+  template hipError_t resid_from<R>(c_t<R> *, const c_t<R> *, size_t, int, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace mg

@@ -1,0 +1,229 @@
+// Restriction R = P^dag and prolongation P through the block-orthonormalised,
+// chirality-split prolongator (P^dag gamma_5 = sigma_3 P^dag, so R = P^dag;
+// Eq. 8 with the gamma_5 factors cancelled).
+//
+// Fine level: P is held as the Nv orthonormalised null-vector fields in the
+// fine SoA layout [Nv][12][V]; column (chi, k) of P on aggregate B is field k
+// restricted to the spin half chi (components 6 chi .. 6 chi + 5) on the
+// sites of B.  With the site-blocked order the sites of one aggregate are one
+// contiguous range in every plane, so a workgroup per aggregate streams P and
+// the residual with fully coalesced loads and reduces 2 Nv inner products.
+// Coarse level l -> l+1: vectors are site-major [V][n]; P is [Nv][V][n] and
+// chirality is the upper / lower half of the n components (sigma_3).
+#include "kernels.h"
+
+namespace mg {
+
+// Coarse lexicographic coordinates of the aggregate holding fine site s,
+// mapped to the site-blocked index of the coarse level.
+__device__ __forceinline__ uint32_t coarse_index(const Geom &g, const Geom &gc, uint32_t s) {
+  const Coords k = decode(g, s);
+  return encode(gc, k.c);
+}
+
+// ------------------------------------------------------------------ fine
+template <typename R>
+__global__ __launch_bounds__(256) void k_restrict_fine(Geom g, Geom gc, int nv, const c_t<R> *__restrict__ P,
+                                                       const c_t<R> *__restrict__ fine, c_t<R> *__restrict__ coarse) {
+  using C = c_t<R>;
+  __shared__ double2 part[4][2 * COARSE_NMAX];
+  const size_t V = g.V;
+  const uint32_t B = blockIdx.x;
+  fine += (size_t)blockIdx.y * 12 * V;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int k = lane; k < 2 * nv; k += 64) part[w][k] = make_double2(0.0, 0.0);
+  __syncthreads();
+  for (uint32_t t0 = 0; t0 < g.vb; t0 += blockDim.x) {
+    const uint32_t t = t0 + tid;
+    const bool act = t < g.vb;
+    const uint32_t s = B * g.vb + (act ? t : 0);
+    C r[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) r[c] = act ? fine[(size_t)c * V + s] : mk<C>(0, 0);
+    for (int kk = 0; kk < nv; ++kk) {
+      const C *Pk = P + (size_t)kk * 12 * V;
+      C d0 = mk<C>(0, 0), d1 = mk<C>(0, 0);
+      if (act) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) d0 = cfmac(Pk[(size_t)c * V + s], r[c], d0);
+#pragma unroll
+        for (int c = 6; c < 12; ++c) d1 = cfmac(Pk[(size_t)c * V + s], r[c], d1);
+      }
+      double a0 = wave_sum((double)d0.x), b0 = wave_sum((double)d0.y);
+      double a1 = wave_sum((double)d1.x), b1 = wave_sum((double)d1.y);
+      if (lane == 0) {
+        part[w][kk].x += a0;
+        part[w][kk].y += b0;
+        part[w][nv + kk].x += a1;
+        part[w][nv + kk].y += b1;
+      }
+    }
+  }
+  __syncthreads();
+  const int nw = (blockDim.x + 63) >> 6;
+  uint32_t ic = 0;
+  if (tid < 2 * nv) {
+    const int x[4] = {(int)(B % gc.L[0]), (int)((B / gc.L[0]) % gc.L[1]),
+                      (int)((B / (gc.L[0] * gc.L[1])) % gc.L[2]), (int)(B / (gc.L[0] * gc.L[1] * gc.L[2]))};
+    ic = encode(gc, x);
+    double2 a = part[0][tid];
+    for (int q = 1; q < nw; ++q) {
+      a.x += part[q][tid].x;
+      a.y += part[q][tid].y;
+    }
+    coarse[((size_t)blockIdx.y * gc.V + ic) * (2 * nv) + tid] = mk<C>((R)a.x, (R)a.y);
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_prolong_fine(Geom g, Geom gc, int nv, const c_t<R> *__restrict__ P,
+                                                      const c_t<R> *__restrict__ coarse, c_t<R> *__restrict__ fine,
+                                                      int accumulate) {
+  using C = c_t<R>;
+  const size_t V = g.V;
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  fine += (size_t)blockIdx.y * 12 * V;
+  const uint32_t ic = coarse_index(g, gc, s);
+  const C *ec = coarse + ((size_t)blockIdx.y * gc.V + ic) * (2 * nv);
+  C acc[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = mk<C>(0, 0);
+  for (int kk = 0; kk < nv; ++kk) {
+    const C *Pk = P + (size_t)kk * 12 * V;
+    const C e0 = ec[kk], e1 = ec[nv + kk];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[c] = cfma(Pk[(size_t)c * V + s], e0, acc[c]);
+#pragma unroll
+    for (int c = 6; c < 12; ++c) acc[c] = cfma(Pk[(size_t)c * V + s], e1, acc[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    C v = acc[c];
+    if (accumulate) v = cadd(fine[(size_t)c * V + s], v);
+    fine[(size_t)c * V + s] = v;
+  }
+}
+
+template <typename R>
+hipError_t restrict_fine(const Geom &g, const Geom &gc, int nv, const c_t<R> *P, const c_t<R> *fine,
+                         c_t<R> *coarse, int nrhs, hipStream_t st) {
+  const int th = g.vb >= 256 ? 256 : (int)((g.vb + 63) / 64 * 64);
+  hipLaunchKernelGGL(k_restrict_fine<R>, dim3(g.Vc, nrhs), dim3(th), 0, st, g, gc, nv, P, fine, coarse);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t prolong_fine(const Geom &g, const Geom &gc, int nv, const c_t<R> *P, const c_t<R> *coarse,
+                        c_t<R> *fine, int nrhs, int accumulate, hipStream_t st) {
+  hipLaunchKernelGGL(k_prolong_fine<R>, dim3(div_up(g.V, 256), nrhs), dim3(256), 0, st, g, gc, nv, P, coarse, fine,
+                     accumulate);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ coarse
+// Elements of aggregate B: e = t * n + j (site t of the block, component j),
+// contiguous in the site-major layout.  Chirality of j: j >= n/2.
+constexpr int RC_EMAX = 8;  // elements per thread (block volume * n <= 2048)
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_restrict_coarse(Geom g, Geom gc, int n, int nv,
+                                                         const c_t<R> *__restrict__ P, const c_t<R> *__restrict__ fine,
+                                                         c_t<R> *__restrict__ coarse) {
+  using C = c_t<R>;
+  __shared__ double2 part[4][2 * COARSE_NMAX];
+  const uint32_t B = blockIdx.x;
+  const size_t V = g.V;
+  fine += (size_t)blockIdx.y * V * n;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int ne = (int)g.vb * n;
+  const size_t base = (size_t)B * g.vb * n;
+  C r[RC_EMAX];
+#pragma unroll
+  for (int q = 0; q < RC_EMAX; ++q) {
+    const int e = tid + q * (int)blockDim.x;
+    r[q] = e < ne ? fine[base + e] : mk<C>(0, 0);
+  }
+  const int half = n >> 1;
+  for (int kk = 0; kk < nv; ++kk) {
+    const C *Pk = P + (size_t)kk * V * n + base;
+    C d0 = mk<C>(0, 0), d1 = mk<C>(0, 0);
+#pragma unroll
+    for (int q = 0; q < RC_EMAX; ++q) {
+      const int e = tid + q * (int)blockDim.x;
+      if (e < ne) {
+        const int j = e % n;
+        if (j < half) d0 = cfmac(Pk[e], r[q], d0);
+        else d1 = cfmac(Pk[e], r[q], d1);
+      }
+    }
+    double a0 = wave_sum((double)d0.x), b0 = wave_sum((double)d0.y);
+    double a1 = wave_sum((double)d1.x), b1 = wave_sum((double)d1.y);
+    if (lane == 0) {
+      part[w][kk] = make_double2(a0, b0);
+      part[w][nv + kk] = make_double2(a1, b1);
+    }
+  }
+  __syncthreads();
+  const int nw = (blockDim.x + 63) >> 6;
+  if (tid < 2 * nv) {
+    const int x[4] = {(int)(B % gc.L[0]), (int)((B / gc.L[0]) % gc.L[1]),
+                      (int)((B / (gc.L[0] * gc.L[1])) % gc.L[2]), (int)(B / (gc.L[0] * gc.L[1] * gc.L[2]))};
+    const uint32_t ic = encode(gc, x);
+    double2 a = part[0][tid];
+    for (int q = 1; q < nw; ++q) {
+      a.x += part[q][tid].x;
+      a.y += part[q][tid].y;
+    }
+    coarse[((size_t)blockIdx.y * gc.V + ic) * (2 * nv) + tid] = mk<C>((R)a.x, (R)a.y);
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_prolong_coarse(Geom g, Geom gc, int n, int nv, const c_t<R> *__restrict__ P,
+                                                        const c_t<R> *__restrict__ coarse, c_t<R> *__restrict__ fine,
+                                                        int accumulate) {
+  using C = c_t<R>;
+  const size_t V = g.V;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= V * n) return;
+  fine += (size_t)blockIdx.y * V * n;
+  const uint32_t s = (uint32_t)(e / n);
+  const int j = (int)(e - (size_t)s * n);
+  const uint32_t ic = coarse_index(g, gc, s);
+  const C *ec = coarse + ((size_t)blockIdx.y * gc.V + ic) * (2 * nv) + (j < (n >> 1) ? 0 : nv);
+  C acc = mk<C>(0, 0);
+  for (int kk = 0; kk < nv; ++kk) acc = cfma(P[(size_t)kk * V * n + e], ec[kk], acc);
+  if (accumulate) acc = cadd(fine[e], acc);
+  fine[e] = acc;
+}
+
+template <typename R>
+hipError_t restrict_coarse(const Geom &g, const Geom &gc, int n, int nv, const c_t<R> *P, const c_t<R> *fine,
+                           c_t<R> *coarse, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_restrict_coarse<R>, dim3(g.Vc, nrhs), dim3(256), 0, st, g, gc, n, nv, P, fine, coarse);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t prolong_coarse(const Geom &g, const Geom &gc, int n, int nv, const c_t<R> *P, const c_t<R> *coarse,
+                          c_t<R> *fine, int nrhs, int accumulate, hipStream_t st) {
+  hipLaunchKernelGGL(k_prolong_coarse<R>, dim3(div_up((long)g.V * n, 256), nrhs), dim3(256), 0, st, g, gc, n, nv,
+                     P, coarse, fine, accumulate);
+  return hipGetLastError();
+}
+
+#define INST(R)                                                                                                   \
+  template hipError_t restrict_fine<R>(const Geom &, const Geom &, int, const c_t<R> *, const c_t<R> *, c_t<R> *,  \
+                                       int, hipStream_t);                                                          \
+  template hipError_t prolong_fine<R>(const Geom &, const Geom &, int, const c_t<R> *, const c_t<R> *, c_t<R> *,   \
+                                      int, int, hipStream_t);                                                      \
+  template hipError_t restrict_coarse<R>(const Geom &, const Geom &, int, int, const c_t<R> *, const c_t<R> *,     \
+                                         c_t<R> *, int, hipStream_t);                                              \
+  template hipError_t prolong_coarse<R>(const Geom &, const Geom &, int, int, const c_t<R> *, const c_t<R> *,      \
+                                        c_t<R> *, int, int, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace mg
