@@ -28,7 +28,8 @@
  * Streams: work is enqueued on the hipStream_t argument (NULL = default
  * stream).  wilson_apply, mg_restrict, mg_prolong and coarse_apply are
  * asynchronous; mg_setup and mg_solve return after completion because their
- * convergence decisions are taken on the host.
+ * convergence decisions are taken on the host.  mg_solve runs on a stream
+ * owned by the context, ordered after prior work on the argument stream.
  */
 #ifndef MGWD_H
 #define MGWD_H
@@ -76,6 +77,8 @@ typedef struct {
   int max_iter;                      /* outer iteration cap                  */
   mg_prec_t precond_prec;            /* MG_F64, MG_F32 or MG_F16             */
   int max_rhs;                       /* largest nrhs passed to mg_solve      */
+  int use_graph;                     /* 1: replay the coarsest-level CGNR
+                                        iterations from captured hipGraphs  */
   /* Setup start vectors, DEVICE complex128, required:
    *   init_vectors[0]: [nv[0]][Lt][Lz][Ly][Lx][4][3]
    *   init_vectors[1]: [nv[1]][Lct][Lcz][Lcy][Lcx][2*nv[0]] (3 levels)    */
@@ -91,9 +94,13 @@ typedef struct {
   int n_vcycles;                /* preconditioner applications               */
   double t_setup_s, t_solve_s;  /* wall time of the last setup / solve       */
   /* Kernel timing (filled when mg_set_timing(ctx, 1) is on): summed device
-   * time in ms and launch counts of the fine stencil and coarse stencil.    */
-  double dslash_ms;   int dslash_launches;   int dslash_prec;
-  double coarse_ms;   int coarse_launches;   int coarse_prec;
+   * time in ms, launch count and sites x right-hand sides processed, per
+   * kernel class: 0 = fine stencil FP64, 1 = fine stencil FP32,
+   * 2 = coarse stencil FP64, 3 = coarse stencil FP32 (coarsest level and
+   * intermediate levels together).                                         */
+  double kernel_ms[4];
+  int kernel_launches[4];
+  double kernel_sites[4];
 } mg_info_t;
 
 /* Fine Wilson operator out = D(U) in (Eq. 2) on nrhs canonical spinors.

@@ -4,7 +4,10 @@ TEST INFRASTRUCTURE ONLY: writes the stored masses used by every workload.
 
 D(m) = D(0) + m 1 (Eq. 2), so every eigenvalue shifts by m and one Arnoldi
 run per gauge field fixes the mass for any target min Re lambda:
-m = target - Re lambda_min(D(0)).  gamma_5-Hermiticity makes the spectrum
+m = target - Re lambda_min(D(0)).  k = 12 wanted eigenvalues cover the
+lowest free-field cluster (momentum (0, 0, 0, +-pi/Lt), 6-fold each), which
+converges far faster than asking for fewer or more; tol = 1e-5 relative gives
+Re lambda to ~1e-5, well inside the mass targets (>= 1e-3).  gamma_5-Hermiticity makes the spectrum
 closed under complex conjugation, so Re lambda_min is well defined.
 
 Usage:  python -m oracle.tune_mass C0 C1 ...
@@ -23,7 +26,7 @@ import workloads
 from . import cref
 
 
-def re_lambda_min(U, tol=1e-9, k=16, ncv=64, maxiter=100000):
+def re_lambda_min(U, tol=1e-5, k=12, ncv=64, maxiter=100000):
     shp = (U.shape[1], U.shape[2], U.shape[3], U.shape[4], 4, 3)
     n = int(np.prod(shp))
     count = [0]
@@ -50,7 +53,7 @@ def main(names):
         lam = vals[np.argmin(vals.real)]
         rec[name] = dict(L=list(cfg["L"]), eps=cfg["eps"], seed=cfg["seed"],
                          re_lambda_min_m0=float(lam.real), im_lambda_min_m0=float(abs(lam.imag)),
-                         arnoldi=dict(k=16, ncv=64, which="SR", tol=1e-9, matvecs=nmv),
+                         arnoldi=dict(k=12, ncv=64, which="SR", tol=1e-5, matvecs=nmv),
                          seconds=round(time.time() - t0, 1))
         print(name, rec[name], flush=True)
         with open(path, "w") as f:

@@ -51,6 +51,7 @@ class Params(ctypes.Structure):
                 ("max_iter", ctypes.c_int),
                 ("precond_prec", ctypes.c_int),
                 ("max_rhs", ctypes.c_int),
+                ("use_graph", ctypes.c_int),
                 ("init_vectors", ctypes.c_void_p * (MAX_LEVELS - 1))]
 
 
@@ -62,18 +63,19 @@ class Info(ctypes.Structure):
                 ("n_cgnr_iters", ctypes.c_int),
                 ("n_vcycles", ctypes.c_int),
                 ("t_setup_s", ctypes.c_double), ("t_solve_s", ctypes.c_double),
-                ("dslash_ms", ctypes.c_double), ("dslash_launches", ctypes.c_int),
-                ("dslash_prec", ctypes.c_int),
-                ("coarse_ms", ctypes.c_double), ("coarse_launches", ctypes.c_int),
-                ("coarse_prec", ctypes.c_int)]
+                ("kernel_ms", ctypes.c_double * 4),
+                ("kernel_launches", ctypes.c_int * 4),
+                ("kernel_sites", ctypes.c_double * 4)]
+
+    KERNELS = ("dslash_f64", "dslash_f32", "coarse_f64", "coarse_f32")
 
     def as_dict(self, nrhs=1):
         return dict(iters=list(self.iters[:nrhs]), rel_resid=list(self.rel_resid[:nrhs]),
                     n_fine_dslash=self.n_fine_dslash, n_coarse_apply=self.n_coarse_apply,
                     n_cgnr_iters=self.n_cgnr_iters, n_vcycles=self.n_vcycles,
                     t_setup_s=self.t_setup_s, t_solve_s=self.t_solve_s,
-                    dslash_ms=self.dslash_ms, dslash_launches=self.dslash_launches,
-                    coarse_ms=self.coarse_ms, coarse_launches=self.coarse_launches)
+                    kernels={k: dict(ms=self.kernel_ms[i], launches=self.kernel_launches[i],
+                                     sites=self.kernel_sites[i]) for i, k in enumerate(self.KERNELS)})
 
 
 _lib = None
@@ -158,7 +160,7 @@ class MG:
     def __init__(self, U: torch.Tensor, mass: float, blocks, nv, init_vectors, *,
                  t_antiperiodic=True, setup_rounds=5, setup_mr_steps=4, omega=0.9, pre=4,
                  post=4, coarse_tol=1e-3, coarse_maxiter=1000, gcr_restart=8, max_iter=10000,
-                 precond_prec="f64", max_rhs=1):
+                 precond_prec="f64", max_rhs=1, use_graph=True):
         Lt, Lz, Ly, Lx = U.shape[1:5]
         self.L = (Lx, Ly, Lz, Lt)
         self.nv = list(nv)
@@ -172,7 +174,7 @@ class MG:
         p.setup_rounds, p.setup_mr_steps, p.omega = setup_rounds, setup_mr_steps, omega
         p.pre, p.post, p.coarse_tol, p.coarse_maxiter = pre, post, coarse_tol, coarse_maxiter
         p.gcr_restart, p.max_iter = gcr_restart, max_iter
-        p.precond_prec, p.max_rhs = PREC[precond_prec], max_rhs
+        p.precond_prec, p.max_rhs, p.use_graph = PREC[precond_prec], max_rhs, int(bool(use_graph))
         self._keep = list(init_vectors)
         for i, v in enumerate(init_vectors):
             p.init_vectors[i] = _dev(v, f"init_vectors[{i}]").value

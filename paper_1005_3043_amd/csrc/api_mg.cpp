@@ -106,8 +106,14 @@ extern "C" int mg_setup(const mg_lattice_t *lat, const void *U, double mass, con
   c->p = *params;
   c->mass = mass;
   c->prec = params->precond_prec;
+  c->use_graph = params->use_graph ? 1 : 0;
   const double t0 = now_s();
-  int rc = setup(c, U, stream);
+  int rc = hip_rc(hipStreamCreateWithFlags(&c->sti, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+  if (rc == MG_OK) rc = hip_rc(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming), "hipEventCreate");
+  if (rc == MG_OK) rc = hip_rc(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming), "hipEventCreate");
+  for (int i = 0; i < 2 && rc == MG_OK; ++i)
+    rc = hip_rc(hipEventCreateWithFlags(&c->ev_chunk[i], hipEventDisableTiming), "hipEventCreate");
+  if (rc == MG_OK) rc = setup(c, U, stream);
   if (rc == MG_OK) rc = ensure_prec(c, c->prec, stream);
   if (rc == MG_OK) rc = hip_rc(hipStreamSynchronize(stream), "mg_setup");
   if (rc != MG_OK) {
@@ -199,18 +205,26 @@ extern "C" int mg_solve(mg_ctx_t *ctx, const void *b, void *x, int nrhs, double 
   else MG_TRY(ensure_work<float>(c, nrhs));
   MG_TRY(ensure_scalars(c, part_need(c, nrhs)));
   c->n_fine = c->n_coarse = c->n_cgnr = c->n_vcyc = 0;
-  c->tm_dslash.reset();
-  c->tm_coarse.reset();
+  for (auto &t : c->tm) t.reset();
   HIPK(hipStreamSynchronize(st));
   const double t0 = now_s();
-  HIPK(pack_field<double>(c->lev[0].g, (const double2 *)b, c->gb, 12, nrhs, st));
+  hipStream_t s2 = c->sti;
+  HIPK(hipEventRecord(c->ev_in, st));
+  HIPK(hipStreamWaitEvent(s2, c->ev_in, 0));
+  HIPK(pack_field<double>(c->lev[0].g, (const double2 *)b, c->gb, 12, nrhs, s2));
   int iters[MG_MAX_RHS];
   double relres[MG_MAX_RHS];
-  const int rc = fgcr(c, c->gb, c->gx, nrhs, tol, iters, relres, st);
-  if (rc < 0) return rc;
-  HIPK(unpack_field<double>(c->lev[0].g, c->gx, (double2 *)x, 12, nrhs, st));
-  HIPK(hipStreamSynchronize(st));
+  const int rc = fgcr(c, c->gb, c->gx, nrhs, tol, iters, relres, s2);
+  if (rc < 0) {
+    (void)hipStreamSynchronize(s2);
+    return rc;
+  }
+  HIPK(unpack_field<double>(c->lev[0].g, c->gx, (double2 *)x, 12, nrhs, s2));
+  HIPK(hipEventRecord(c->ev_out, s2));
+  HIPK(hipStreamWaitEvent(st, c->ev_out, 0));
+  HIPK(hipStreamSynchronize(s2));
   const double t1 = now_s();
+  for (auto &t : c->tm) t.harvest();
   if (info) {
     std::memset(info, 0, sizeof(*info));
     for (int i = 0; i < nrhs; ++i) {
@@ -224,13 +238,12 @@ extern "C" int mg_solve(mg_ctx_t *ctx, const void *b, void *x, int nrhs, double 
     info->t_setup_s = c->t_setup;
     info->t_solve_s = t1 - t0;
     if (c->timing) {
-      info->dslash_ms = c->tm_dslash.total_ms();
-      info->dslash_launches = c->tm_dslash.launches();
-      info->coarse_ms = c->tm_coarse.total_ms();
-      info->coarse_launches = c->tm_coarse.launches();
+      for (int k = 0; k < 4; ++k) {
+        info->kernel_ms[k] = c->tm[k].ms;
+        info->kernel_launches[k] = (int)c->tm[k].launches;
+        info->kernel_sites[k] = c->tm[k].sites;
+      }
     }
-    info->dslash_prec = (int)MG_F64;
-    info->coarse_prec = (int)c->prec;
   }
   return rc;
 }
@@ -252,10 +265,11 @@ extern "C" int mg_time_dslash(mg_ctx_t *ctx, mg_prec_t prec, int nrhs, int reps,
     MG_TRY(a.alloc(n));
     MG_TRY(b.alloc(n));
     HIPK(copy<double>(a, L.P64, std::min(n, L.P64.n), st));
-    for (int i = 0; i < 2; ++i) HIPK(dslash<double>(L.g, L.U64, a, b, nullptr, 4.0 + c->mass, nrhs, DS_PLAIN, nullptr, st));
+    for (int i = 0; i < 2; ++i)
+      HIPK(dslash<double>(L.g, L.links64(), L.nl, a, b, nullptr, 4.0 + c->mass, nrhs, DS_PLAIN, nullptr, st));
     HIPK(hipEventRecord(e0, st));
     for (int i = 0; i < reps; ++i)
-      HIPK(dslash<double>(L.g, L.U64, a, b, nullptr, 4.0 + c->mass, nrhs, DS_PLAIN, nullptr, st));
+      HIPK(dslash<double>(L.g, L.links64(), L.nl, a, b, nullptr, 4.0 + c->mass, nrhs, DS_PLAIN, nullptr, st));
     HIPK(hipEventRecord(e1, st));
     HIPK(hipEventSynchronize(e1));
   } else if (prec == MG_F32) {
@@ -263,10 +277,11 @@ extern "C" int mg_time_dslash(mg_ctx_t *ctx, mg_prec_t prec, int nrhs, int reps,
     MG_TRY(a.alloc(n));
     MG_TRY(b.alloc(n));
     HIPK(copy<float>(a, L.P32, std::min(n, L.P32.n), st));
-    for (int i = 0; i < 2; ++i) HIPK(dslash<float>(L.g, L.U32, a, b, nullptr, 4.0 + c->mass, nrhs, DS_PLAIN, nullptr, st));
+    for (int i = 0; i < 2; ++i)
+      HIPK(dslash<float>(L.g, L.U32, L.nl, a, b, nullptr, 4.0 + c->mass, nrhs, DS_PLAIN, nullptr, st));
     HIPK(hipEventRecord(e0, st));
     for (int i = 0; i < reps; ++i)
-      HIPK(dslash<float>(L.g, L.U32, a, b, nullptr, 4.0 + c->mass, nrhs, DS_PLAIN, nullptr, st));
+      HIPK(dslash<float>(L.g, L.U32, L.nl, a, b, nullptr, 4.0 + c->mass, nrhs, DS_PLAIN, nullptr, st));
     HIPK(hipEventRecord(e1, st));
     HIPK(hipEventSynchronize(e1));
   } else {
@@ -329,6 +344,12 @@ extern "C" int mg_time_coarse(mg_ctx_t *ctx, int level, mg_prec_t prec, int nrhs
 extern "C" int mg_destroy(mg_ctx_t *ctx) {
   if (!ctx) return MG_OK;
   (void)hipDeviceSynchronize();
+  clear_graphs(ctx);
+  if (ctx->sti) (void)hipStreamDestroy(ctx->sti);
+  if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
+  if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
+  for (auto e : ctx->ev_chunk)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->h_done) (void)hipHostFree(ctx->h_done);
   if (ctx->h_rr) (void)hipHostFree(ctx->h_rr);
   if (ctx->h_it) (void)hipHostFree(ctx->h_it);
@@ -378,7 +399,8 @@ extern "C" int mg_export_P(mg_ctx_t *ctx, int level, void *P_host) {
     for (size_t s = 0; s < V; ++s) {
       const size_t B = s / vb, l = s % vb;
       for (int c = 0; c < n; ++c) {
-        const double2 v = (level == 0) ? h[((size_t)k * 12 + c) * V + s] : h[((size_t)k * V + s) * n + c];
+        const double2 v = (level == 0) ? h[(size_t)k * 12 * L.g.Vpad + fidx((uint32_t)s, c, 12)]
+                                       : h[((size_t)k * V + s) * n + c];
         const int chi = c / h2, j = c % h2;
         out[((B * 2 + chi) * rows + l * h2 + j) * nv + k] = v;
       }

@@ -27,13 +27,13 @@ static int wilson_apply_t(const mg_lattice_t *lat, const void *U, double mass, c
   Geom g = make_geom(lat->L, b, lat->t_antiperiodic ? 1 : 0);
   using C = c_t<T>;
   C *Ui = nullptr, *xi = nullptr, *yi = nullptr;
-  const size_t V = g.V;
-  MG_HIP(hipMallocAsync((void **)&Ui, sizeof(C) * 36 * V, st));
-  hipError_t e = hipMallocAsync((void **)&xi, sizeof(C) * 12 * V * nrhs, st);
-  if (e == hipSuccess) e = hipMallocAsync((void **)&yi, sizeof(C) * 12 * V * nrhs, st);
-  if (e == hipSuccess) e = pack_field<T>(g, (const double2 *)U, Ui, 9, 4, st);
+  const size_t Vp = g.Vpad;
+  MG_HIP(hipMallocAsync((void **)&Ui, sizeof(C) * 36 * Vp, st));
+  hipError_t e = hipMallocAsync((void **)&xi, sizeof(C) * 12 * Vp * nrhs, st);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&yi, sizeof(C) * 12 * Vp * nrhs, st);
+  if (e == hipSuccess) e = pack_gauge<T>(g, (const double2 *)U, Ui, st);
   if (e == hipSuccess) e = pack_field<T>(g, (const double2 *)in, xi, 12, nrhs, st);
-  if (e == hipSuccess) e = dslash<T>(g, Ui, xi, yi, nullptr, 4.0 + mass, nrhs, DS_PLAIN, nullptr, st);
+  if (e == hipSuccess) e = dslash<T>(g, Ui, 9, xi, yi, nullptr, 4.0 + mass, nrhs, DS_PLAIN, nullptr, st);
   if (e == hipSuccess) e = unpack_field<T>(g, yi, (double2 *)out, 12, nrhs, st);
   if (yi) (void)hipFreeAsync(yi, st);
   if (xi) (void)hipFreeAsync(xi, st);

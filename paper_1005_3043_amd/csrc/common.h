@@ -3,12 +3,13 @@
 // Internal data layout (all levels): sites are ordered aggregate-major
 // ("site-blocked"): s = B * vol_b + l, where B is the lexicographic index of
 // the aggregate on the coarse lattice and l = o_x + b_x (o_y + b_y (o_z +
-// b_z o_t)) the lexicographic index inside it.  Every per-site quantity is
-// stored structure-of-arrays: component plane k holds entry k of all sites
-// contiguously, so a wavefront reading one component of 64 consecutive sites
-// issues one contiguous, fully coalesced load.  The fine stencil then walks a
-// 4D tile (neighbours stay in the same or the adjacent aggregate), and the
-// transfer kernels see each aggregate as one contiguous range per plane.
+// b_z o_t)) the lexicographic index inside it.  Fine-level fields are stored
+// in 64-site tiles (one tile per wavefront): entry (s, c) of an ncomp-component
+// field sits at ((s / 64) * ncomp + c) * 64 + s % 64, so a wavefront reading
+// one component of 64 consecutive sites issues one contiguous 1 KiB (FP64)
+// load and all components of a tile share a few DRAM pages.  The fine stencil
+// walks a 4D tile (neighbours stay in the same or the adjacent aggregate), and
+// the transfer kernels see each aggregate as a contiguous run of tiles.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -105,6 +106,7 @@ struct FastDiv {
 struct Geom {
   int L[4], b[4], C[4];
   uint32_t V, vb, Vc;
+  uint32_t Vpad;  // V rounded up to whole 64-site tiles
   int Sl[4];   // stride of o_mu inside an aggregate
   int Sb[4];   // stride of c_mu between aggregates (in sites)
   FastDiv fvb, fb[3], fC[3];
@@ -114,6 +116,12 @@ struct Geom {
 Geom make_geom(const int L[4], const int b[4], int antiperiodic);
 
 struct Coords { int o[4]; int c[4]; uint32_t B, l; };
+
+// Tile-interleaved index of entry c of site s in an ncomp-component field.
+constexpr int TILE = 64;
+__host__ __device__ __forceinline__ size_t fidx(uint32_t s, int c, int ncomp) {
+  return ((size_t)(s >> 6) * ncomp + c) * TILE + (s & (TILE - 1));
+}
 
 __host__ __device__ __forceinline__ Coords decode(const Geom &g, uint32_t s) {
   Coords r;

@@ -6,49 +6,69 @@
 // The spin projection (wilson_site.h) reduces each hop to a half spinor and
 // two SU(3) mat-vecs: 1320 flops per site for all eight hops.
 //
-// One thread per site of the site-blocked SoA layout: each wavefront reads 64
-// consecutive sites of a 4D tile per component plane (coalesced), and the
-// neighbour reads of adjacent tiles hit L2 / the last-level cache.
+// One thread per site of the site-blocked, tile-interleaved layout.  The loop
+// over mu is rolled (wave-uniform): both hops of one direction issue their 42
+// (or 36 with compressed links) loads together, then compute, which keeps the
+// FP64 kernel free of spills while doubling the loads in flight per wave
+// compared with one hop at a time.  Links are either stored in full (9
+// complex) or as their first two rows (6 complex, NL = 6); the third row of an
+// SU(3) matrix is the complex conjugate of the cross product of the first two,
+// which trades 42 flops per link for a third less link traffic.
 #include "kernels.h"
 #include "wilson_site.h"
 
 namespace mg {
 
-// Full stencil at one site: returns D psi at s in `res` and the centre value
-// psi(s) in `ctr`.
+template <typename C> __host__ __device__ __forceinline__ void reconstruct_row2(C (&u)[9]) {
+  // row 2 = conj(row0 x row1)
+  const C a = csub(cmul(u[1], u[5]), cmul(u[2], u[4]));
+  const C b = csub(cmul(u[2], u[3]), cmul(u[0], u[5]));
+  const C c = csub(cmul(u[0], u[4]), cmul(u[1], u[3]));
+  u[6] = mk<C>(a.x, -a.y);
+  u[7] = mk<C>(b.x, -b.y);
+  u[8] = mk<C>(c.x, -c.y);
+}
+
+template <int NL, typename C>
+__host__ __device__ __forceinline__ void load_link_t(C (&u)[9], const C *__restrict__ U, int mu, uint32_t s) {
+#pragma unroll
+  for (int e = 0; e < NL; ++e) u[e] = U[fidx(s, mu * NL + e, 4 * NL)];
+  if constexpr (NL == 6) reconstruct_row2(u);
+}
+
 template <typename C>
+__host__ __device__ __forceinline__ void load_spinor_t(C (&psi)[12], const C *__restrict__ in, uint32_t s) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) psi[c] = in[fidx(s, c, 12)];
+}
+
+// Full stencil at one site: res = D psi at s, ctr = psi(s).
+template <int NL, typename C>
 __host__ __device__ __forceinline__ void dslash_site(C (&res)[12], C (&ctr)[12], const Geom &g, uint32_t s,
                                                      const C *__restrict__ U, const C *__restrict__ in,
                                                      decltype(C::x) diag) {
   using R = decltype(C::x);
-  const size_t V = g.V;
   const Coords k = decode(g, s);
   C acc[12];
 #pragma unroll
   for (int i = 0; i < 12; ++i) acc[i] = mk<C>(0, 0);
-  // A rolled loop over the eight hops (wave-uniform branch on mu): the loads
-  // of one hop cannot be hoisted above the previous hop's arithmetic, which
-  // keeps the FP64 kernel within ~130 registers; other waves hide latency.
 #pragma unroll 1
-  for (int h = 0; h < 8; ++h) {
-    const int mu = h >> 1;
-    const bool fwd = (h & 1) == 0;
-    C psi[12], u[9];
-    R eta = 1;
-    uint32_t sn;
-    if (fwd) {
-      sn = nbr_fwd(g, s, k, mu);
-      if (mu == 3 && g.antiperiodic && k.o[3] == g.b[3] - 1 && k.c[3] == g.C[3] - 1) eta = -1;
-    } else {
-      sn = nbr_bwd(g, s, k, mu);
-      if (mu == 3 && g.antiperiodic && k.o[3] == 0 && k.c[3] == 0) eta = -1;
+  for (int mu = 0; mu < 4; ++mu) {
+    C pf[12], pb[12], uf[9], ub[9];
+    const uint32_t sf = nbr_fwd(g, s, k, mu), sb = nbr_bwd(g, s, k, mu);
+    R ef = 1, eb = 1;
+    if (mu == 3 && g.antiperiodic) {
+      if (k.o[3] == g.b[3] - 1 && k.c[3] == g.C[3] - 1) ef = -1;
+      if (k.o[3] == 0 && k.c[3] == 0) eb = -1;
     }
-    load_spinor(psi, in, sn, V);
-    load_link(u, U, mu, fwd ? s : sn, V);
-    if (fwd) hop_dispatch<true>(mu, acc, psi, u, eta);
-    else hop_dispatch<false>(mu, acc, psi, u, eta);
+    load_spinor_t(pf, in, sf);
+    load_spinor_t(pb, in, sb);
+    load_link_t<NL>(uf, U, mu, s);
+    load_link_t<NL>(ub, U, mu, sb);
+    hop_dispatch<true>(mu, acc, pf, uf, ef);
+    hop_dispatch<false>(mu, acc, pb, ub, eb);
   }
-  load_spinor(ctr, in, s, V);
+  load_spinor_t(ctr, in, s);
 #pragma unroll
   for (int i = 0; i < 12; ++i) {
     res[i].x = fma(diag, ctr[i].x, (R)-0.5 * acc[i].x);
@@ -56,14 +76,24 @@ __host__ __device__ __forceinline__ void dslash_site(C (&res)[12], C (&ctr)[12],
   }
 }
 
-template <typename R, int MODE>
-__global__ __launch_bounds__(256) void k_dslash(Geom g, const c_t<R> *__restrict__ U,
+// Minimum waves per SIMD requested from the register allocator (0 = none).
+#ifndef MG_DSLASH_WAVES_F64
+#define MG_DSLASH_WAVES_F64 0
+#endif
+#ifndef MG_DSLASH_WAVES_F32
+#define MG_DSLASH_WAVES_F32 0
+#endif
+template <typename R> constexpr int dslash_waves() {
+  return sizeof(R) == 8 ? MG_DSLASH_WAVES_F64 : MG_DSLASH_WAVES_F32;
+}
+
+template <typename R, int MODE, int NL>
+__global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash(Geom g, const c_t<R> *__restrict__ U,
                                                 const c_t<R> *__restrict__ in, c_t<R> *__restrict__ out,
                                                 const c_t<R> *__restrict__ b, R diag,
                                                 double *__restrict__ partials) {
   using C = c_t<R>;
-  const size_t V = g.V;
-  const size_t off = (size_t)blockIdx.y * 12 * V;
+  const size_t off = (size_t)blockIdx.y * 12 * g.Vpad;
   in += off;
   out += off;
   const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -71,14 +101,14 @@ __global__ __launch_bounds__(256) void k_dslash(Geom g, const c_t<R> *__restrict
   double red[3] = {0.0, 0.0, 0.0};
   if (s < g.V) {
     C res[12], ctr[12];
-    dslash_site(res, ctr, g, s, U, in, diag);
+    dslash_site<NL>(res, ctr, g, s, U, in, diag);
     if constexpr (MODE == DS_RESID) {
       const C *bb = b + off;
 #pragma unroll
-      for (int i = 0; i < 12; ++i) res[i] = csub(bb[(size_t)i * V + s], res[i]);
+      for (int i = 0; i < 12; ++i) res[i] = csub(bb[fidx(s, i, 12)], res[i]);
     }
 #pragma unroll
-    for (int i = 0; i < 12; ++i) out[(size_t)i * V + s] = res[i];
+    for (int i = 0; i < 12; ++i) out[fidx(s, i, 12)] = res[i];
     if constexpr (MODE == DS_MR) {
 #pragma unroll
       for (int i = 0; i < 12; ++i) {
@@ -103,27 +133,75 @@ __global__ __launch_bounds__(256) void k_dslash(Geom g, const c_t<R> *__restrict
 
 int dslash_blocks(const Geom &g) { return div_up(g.V, 256); }
 
-template <typename R>
-hipError_t dslash(const Geom &g, const c_t<R> *U, const c_t<R> *in, c_t<R> *out, const c_t<R> *b,
-                  double diag, int nrhs, DslashMode mode, double *partials, hipStream_t st) {
+template <typename R, int NL>
+static hipError_t launch(const Geom &g, const c_t<R> *U, const c_t<R> *in, c_t<R> *out, const c_t<R> *b,
+                         double diag, int nrhs, DslashMode mode, double *partials, hipStream_t st) {
   dim3 grid(dslash_blocks(g), nrhs);
   switch (mode) {
     case DS_PLAIN:
-      hipLaunchKernelGGL((k_dslash<R, DS_PLAIN>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag, partials);
+      hipLaunchKernelGGL((k_dslash<R, DS_PLAIN, NL>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag, partials);
       break;
     case DS_RESID:
-      hipLaunchKernelGGL((k_dslash<R, DS_RESID>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag, partials);
+      hipLaunchKernelGGL((k_dslash<R, DS_RESID, NL>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag, partials);
       break;
     case DS_MR:
-      hipLaunchKernelGGL((k_dslash<R, DS_MR>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag, partials);
+      hipLaunchKernelGGL((k_dslash<R, DS_MR, NL>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag, partials);
       break;
   }
   return hipGetLastError();
 }
 
-template hipError_t dslash<double>(const Geom &, const double2 *, const double2 *, double2 *, const double2 *,
-                                   double, int, DslashMode, double *, hipStream_t);
-template hipError_t dslash<float>(const Geom &, const float2 *, const float2 *, float2 *, const float2 *,
+template <typename R>
+hipError_t dslash(const Geom &g, const c_t<R> *U, int nl, const c_t<R> *in, c_t<R> *out, const c_t<R> *b,
+                  double diag, int nrhs, DslashMode mode, double *partials, hipStream_t st) {
+  if (nl == 6) return launch<R, 6>(g, U, in, out, b, diag, nrhs, mode, partials, st);
+  return launch<R, 9>(g, U, in, out, b, diag, nrhs, mode, partials, st);
+}
+
+// ---------------------------------------------------------------- links
+// Copy of the first two rows of every link (NL = 6 layout), and the largest
+// deviation |row2 - conj(row0 x row1)| over all links (per-block maxima).
+template <typename R>
+__global__ __launch_bounds__(256) void k_compress_links(Geom g, const double2 *__restrict__ U,
+                                                        c_t<R> *__restrict__ Uc, double *__restrict__ blockmax) {
+  __shared__ double lds[4];
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  double dev = 0.0;
+  if (s < g.V) {
+    for (int mu = 0; mu < 4; ++mu) {
+      double2 u[9], w[9];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) u[e] = U[fidx(s, mu * 9 + e, 36)];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) w[e] = u[e];
+      reconstruct_row2(w);
+      for (int e = 6; e < 9; ++e) dev = fmax(dev, fabs(w[e].x - u[e].x) + fabs(w[e].y - u[e].y));
+#pragma unroll
+      for (int e = 0; e < 6; ++e) Uc[fidx(s, mu * 6 + e, 24)] = mk<c_t<R>>((R)u[e].x, (R)u[e].y);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) dev = fmax(dev, __shfl_xor(dev, off, 64));
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = dev;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = lds[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, lds[w]);
+    blockmax[blockIdx.x] = m;
+  }
+}
+
+template <typename R>
+hipError_t compress_links(const Geom &g, const double2 *U, c_t<R> *Uc, double *blockmax, hipStream_t st) {
+  hipLaunchKernelGGL(k_compress_links<R>, dim3(div_up(g.V, 256)), dim3(256), 0, st, g, U, Uc, blockmax);
+  return hipGetLastError();
+}
+
+template hipError_t dslash<double>(const Geom &, const double2 *, int, const double2 *, double2 *,
+                                   const double2 *, double, int, DslashMode, double *, hipStream_t);
+template hipError_t dslash<float>(const Geom &, const float2 *, int, const float2 *, float2 *, const float2 *,
                                   double, int, DslashMode, double *, hipStream_t);
+template hipError_t compress_links<double>(const Geom &, const double2 *, double2 *, double *, hipStream_t);
+template hipError_t compress_links<float>(const Geom &, const double2 *, float2 *, double *, hipStream_t);
 
 }  // namespace mg

@@ -30,7 +30,6 @@ __device__ __forceinline__ uint32_t coarse_site_of(const Geom &gc, uint32_t B, c
 // Hop d of W at site s (W = field k masked to chirality chi), times -1/2.
 __device__ __forceinline__ void fine_hop(double2 (&f)[12], const Geom &g, uint32_t s, const Coords &k, int d,
                                          const double2 *__restrict__ U, const double2 *__restrict__ Pk, int chi) {
-  const size_t V = g.V;
   const int mu = d >> 1;
   const bool fwd = (d & 1) == 0;
   uint32_t sn;
@@ -46,10 +45,12 @@ __device__ __forceinline__ void fine_hop(double2 (&f)[12], const Geom &g, uint32
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
     const bool on = (c / 6) == chi;
-    psi[c] = on ? Pk[(size_t)c * V + sn] : make_double2(0, 0);
+    psi[c] = on ? Pk[fidx(sn, c, 12)] : make_double2(0, 0);
     acc[c] = make_double2(0, 0);
   }
-  load_link(u, U, mu, fwd ? s : sn, V);
+  const uint32_t sl = fwd ? s : sn;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) u[e] = U[fidx(sl, mu * 9 + e, 36)];
   if (fwd) hop_dispatch<true>(mu, acc, psi, u, eta);
   else hop_dispatch<false>(mu, acc, psi, u, eta);
 #pragma unroll
@@ -60,7 +61,7 @@ __global__ __launch_bounds__(256) void k_galerkin_fine(Geom g, Geom gc, double d
                                                        int nv, const double2 *__restrict__ P,
                                                        double2 *__restrict__ Lc) {
   __shared__ double2 part[4][2 * COARSE_NMAX];
-  const size_t V = g.V;
+  const size_t V = g.Vpad;
   const uint32_t B = blockIdx.x;
   const int jcol = blockIdx.y, chi = jcol / nv, kj = jcol % nv;
   const int n = 2 * nv;
@@ -78,7 +79,7 @@ __global__ __launch_bounds__(256) void k_galerkin_fine(Geom g, Geom gc, double d
       if (slot == 0) {
 #pragma unroll
         for (int c = 0; c < 12; ++c)
-          if ((c / 6) == chi) f[c] = cscale(Pj[(size_t)c * V + s], diag);
+          if ((c / 6) == chi) f[c] = cscale(Pj[fidx(s, c, 12)], diag);
         for (int d = 0; d < 8; ++d) {
           const int mu = d >> 1;
           const bool face = (d & 1) == 0 ? (k.o[mu] == g.b[mu] - 1) : (k.o[mu] == 0);
@@ -95,9 +96,9 @@ __global__ __launch_bounds__(256) void k_galerkin_fine(Geom g, Geom gc, double d
       double2 d0 = make_double2(0, 0), d1 = make_double2(0, 0);
       if (act) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) d0 = cfmac(Pi[(size_t)c * V + s], f[c], d0);
+        for (int c = 0; c < 6; ++c) d0 = cfmac(Pi[fidx(s, c, 12)], f[c], d0);
 #pragma unroll
-        for (int c = 6; c < 12; ++c) d1 = cfmac(Pi[(size_t)c * V + s], f[c], d1);
+        for (int c = 6; c < 12; ++c) d1 = cfmac(Pi[fidx(s, c, 12)], f[c], d1);
       }
       const double a0 = wave_sum(d0.x), b0 = wave_sum(d0.y), a1 = wave_sum(d1.x), b1 = wave_sum(d1.y);
       if (lane == 0) {

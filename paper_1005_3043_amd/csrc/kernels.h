@@ -7,22 +7,29 @@
 namespace mg {
 
 // ---- pack.hip: canonical complex128 [nvec][sites lex][ncomp] <-> internal
-//      [nvec][ncomp][V] site-blocked planes of complex<T>.
+//      tile-interleaved fine fields (fidx), nvec fields of ncomp * Vpad entries.
 template <typename T>
 hipError_t pack_field(const Geom &g, const double2 *canon, c_t<T> *internal, int ncomp, int nvec,
                       hipStream_t st);
 template <typename T>
 hipError_t unpack_field(const Geom &g, const c_t<T> *internal, double2 *canon, int ncomp, int nvec,
                         hipStream_t st);
+// canonical gauge field U[4][lex site][3][3] -> internal 36-component field
+template <typename T> hipError_t pack_gauge(const Geom &g, const double2 *canon, c_t<T> *internal, hipStream_t st);
 
-// ---- dslash.hip: fine Wilson operator on internal spinors (12 planes).
+// ---- dslash.hip: fine Wilson operator on internal spinors (12 components).
+// nl = 9: full links [36 components]; nl = 6: first two rows [24 components].
 enum DslashMode { DS_PLAIN = 0, DS_RESID = 1, DS_MR = 2 };
 // out = diag*in - 1/2 hop(in)              (DS_PLAIN)
 // out = b - (diag*in - 1/2 hop(in))        (DS_RESID)
 // out = D in; partials[blk] += (<out,in>, ||out||^2)  (DS_MR, 3 doubles / block)
 template <typename R>
-hipError_t dslash(const Geom &g, const c_t<R> *U, const c_t<R> *in, c_t<R> *out, const c_t<R> *b,
+hipError_t dslash(const Geom &g, const c_t<R> *U, int nl, const c_t<R> *in, c_t<R> *out, const c_t<R> *b,
                   double diag, int nrhs, DslashMode mode, double *partials, hipStream_t st);
+// Uc = first two rows of every link of U (full FP64 links); blockmax[blk] =
+// max |row2 - conj(row0 x row1)| (dslash_blocks(g) entries).
+template <typename R>
+hipError_t compress_links(const Geom &g, const double2 *U, c_t<R> *Uc, double *blockmax, hipStream_t st);
 int dslash_blocks(const Geom &g);  // number of partial slots per RHS of DS_MR
 
 // ---- blas.hip
@@ -37,17 +44,37 @@ namespace mg {
 
 // ---- coarse.hip: 9-point coarse stencil on site-major coarse vectors.
 constexpr int COARSE_NMAX = 64;
-int coarse_threads(int n);
+int coarse_threads(int n, uint32_t V);
+// workgroups per coarse site; partial-sum producers of the coarse stencil
+// write V * coarse_split(n, V) entries (times pw) per right-hand side
+int coarse_split(int n, uint32_t V);
+// Optional CGNR convergence prologue of the coarse stencil: every workgroup
+// sums the np_r residual partials of its right-hand side, reads the number of
+// completed iterations it_in[rhs], tests ||r||^2 <= tol^2 ||b||^2 (cg scalars
+// [3] = ||b||^2, [4] = tol^2) or it_in + 1 >= maxit, and returns when
+// converged; workgroup 0 writes it_out[rhs] = it_in[rhs] + 1 and done[rhs].
+// it_in and it_out are distinct slots (alternating by iteration parity) so
+// no workgroup reads a value written by the same launch.
+struct CgCheck {
+  const double *part_r = nullptr;
+  int np_r = 0;
+  const double *cg = nullptr;
+  int *done = nullptr;
+  const int *it_in = nullptr;
+  int *it_out = nullptr;
+  int maxit = 0;
+};
 // out = D_c in (dagger: sigma3 D_c sigma3).  When partials != nullptr each
-// site writes pw doubles at partials[(rhs*V + site)*pw]: pw = 1: ||out||^2;
-// pw = 3: <out, in>, ||out||^2.  A right-hand side with done[rhs] != 0 is
+// workgroup writes pw doubles at partials[(rhs*V*RS + wg)*pw] (RS =
+// coarse_split): pw = 1: ||out||^2; pw = 3: <out, in>, ||out||^2.  A right-hand side with done[rhs] != 0 is
 // skipped (done may be nullptr).
 template <typename R>
 hipError_t coarse_apply_k(const Geom &g, int n, const c_t<R> *L, const c_t<R> *in, c_t<R> *out, int nrhs,
-                          int dagger, double *partials, int pw, const int *done, hipStream_t st);
+                          int dagger, double *partials, int pw, const int *done, hipStream_t st,
+                          const CgCheck *chk = nullptr);
 
 // ---- transfer.hip
-// Fine level: P = nv null-vector fields in fine SoA layout [nv][12][V].
+// Fine level: P = nv null-vector fields in the fine layout [nv][12 * Vpad].
 // g = geometry of the finer level (tile = aggregate), gc = geometry of the
 // coarser level (its own site-blocked order).
 template <typename R>

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "mg_internal.h"
 
@@ -41,11 +42,14 @@ int ensure_scalars(mg_ctx *c, size_t part_count) {
   return MG_OK;
 }
 
+// Partial sums written per RHS by one coarse-stencil launch of a level.
+size_t np_coarse(const Level &L) { return (size_t)L.g.V * coarse_split(L.n, L.g.V); }
+
 // Partial-sum slots needed by a batch of nrhs vectors on every level.
 size_t part_need(mg_ctx *c, int nrhs) {
   size_t m = (size_t)RED_BLOCKS * 2;
   m = std::max(m, (size_t)dslash_blocks(c->lev[0].g) * 3);
-  for (int l = 1; l < c->nlev; ++l) m = std::max(m, (size_t)c->lev[l].g.V * 3);
+  for (int l = 1; l < c->nlev; ++l) m = std::max(m, np_coarse(c->lev[l]) * 3);
   return m * (size_t)nrhs;
 }
 
@@ -57,8 +61,9 @@ int ensure_prec(mg_ctx *c, mg_prec_t prec, hipStream_t st) {
   }
   Level &L0 = c->lev[0];
   if (!L0.U32.p) {
-    MG_TRY(L0.U32.alloc(36 * (size_t)L0.g.V));
-    HIPK((convert<float, double>(L0.U32, L0.U64, 36 * (size_t)L0.g.V, st)));
+    MG_TRY(L0.U32.alloc(4 * (size_t)L0.nl * L0.g.Vpad));
+    if (L0.nl == 6) HIPK(compress_links<float>(L0.g, L0.U64, L0.U32, c->part, st));
+    else HIPK((convert<float, double>(L0.U32, L0.U64, 36 * (size_t)L0.g.Vpad, st)));
   }
   for (int l = 0; l < c->nlev; ++l) {
     Level &L = c->lev[l];
@@ -74,6 +79,13 @@ int ensure_prec(mg_ctx *c, mg_prec_t prec, hipStream_t st) {
   return MG_OK;
 }
 
+void clear_graphs(mg_ctx *c) {
+  for (auto &g : c->graphs) {
+    delete g;
+    g = nullptr;
+  }
+}
+
 template <typename R> int ensure_work(mg_ctx *c, int nrhs) {
   Work<R> &w = work<R>(c);
   if (w.nrhs >= nrhs) return MG_OK;
@@ -84,7 +96,9 @@ template <typename R> int ensure_work(mg_ctx *c, int nrhs) {
     MG_TRY(w.q[l].alloc(n));
     MG_TRY(w.rin[l].alloc(n));
   }
+  clear_graphs(c);
   const size_t n = c->lev[c->nlev - 1].vsize() * nrhs;
+  MG_TRY(c->cgp.alloc(3 * np_coarse(c->lev[c->nlev - 1]) * MG_MAX_RHS + 2 * (size_t)RED_BLOCKS * MG_MAX_RHS));
   MG_TRY(w.ce.alloc(n));
   MG_TRY(w.cr.alloc(n));
   MG_TRY(w.cz.alloc(n));
@@ -98,28 +112,40 @@ template int ensure_work<double>(mg_ctx *, int);
 template int ensure_work<float>(mg_ctx *, int);
 
 // ------------------------------------------------------------ operators
-template <typename R> const c_t<R> *U_of(Level &L) { return PrecBufs<R>::pick(L.U64, L.U32).p; }
+template <typename R> const c_t<R> *U_of(Level &L);
+template <> const double2 *U_of<double>(Level &L) { return L.links64(); }
+template <> const float2 *U_of<float>(Level &L) { return L.U32.p; }
 template <typename R> const c_t<R> *L_of(Level &L) { return PrecBufs<R>::pick(L.L64, L.L32).p; }
 template <typename R> const c_t<R> *P_of(Level &L) { return PrecBufs<R>::pick(L.P64, L.P32).p; }
 
-int np_mr(mg_ctx *c, int l) { return l == 0 ? dslash_blocks(c->lev[0].g) : (int)c->lev[l].g.V; }
+int np_mr(mg_ctx *c, int l) { return l == 0 ? dslash_blocks(c->lev[0].g) : (int)np_coarse(c->lev[l]); }
 
+template <typename R> constexpr int tclass(bool coarse) { return (coarse ? 2 : 0) + (sizeof(R) == 4 ? 1 : 0); }
+
+// Records a (start, stop) event pair around the launches in its scope when
+// timing is on.  Inside a stream capture the events are recorded as external
+// event nodes, so every replay of the graph re-records them.
 struct TimerScope {
   EventTimer *t = nullptr;
   hipEvent_t e1 = nullptr;
   hipStream_t st;
-  TimerScope(mg_ctx *c, EventTimer &tm, hipStream_t s) : st(s) {
+  unsigned flags = 0;
+  TimerScope(mg_ctx *c, EventTimer &tm, hipStream_t s, double sites) : st(s) {
     if (c->timing) {
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive)
+        flags = hipEventRecordExternal;
       hipEvent_t e0 = tm.next();
       e1 = tm.next();
       if (e0 && e1) {
-        (void)hipEventRecord(e0, st);
+        (void)hipEventRecordWithFlags(e0, st, flags);
         t = &tm;
+        tm.pair_sites.push_back(sites);
       }
     }
   }
   ~TimerScope() {
-    if (t) (void)hipEventRecord(e1, st);
+    if (t) (void)hipEventRecordWithFlags(e1, st, flags);
   }
 };
 
@@ -129,12 +155,12 @@ int apply_A(mg_ctx *c, int l, const c_t<R> *in, c_t<R> *out, int nrhs, DslashMod
             hipStream_t st) {
   Level &L = c->lev[l];
   if (l == 0) {
-    TimerScope ts(c, c->tm_dslash, st);
-    HIPK(dslash<R>(L.g, U_of<R>(L), in, out, b, 4.0 + c->mass, nrhs, mode, c->part, st));
+    TimerScope ts(c, c->tm[tclass<R>(false)], st, (double)L.g.V * nrhs);
+    HIPK(dslash<R>(L.g, U_of<R>(L), L.nl, in, out, b, 4.0 + c->mass, nrhs, mode, c->part, st));
     c->n_fine += nrhs;
   } else {
     {
-      TimerScope ts(c, c->tm_coarse, st);
+      TimerScope ts(c, c->tm[tclass<R>(true)], st, (double)L.g.V * nrhs);
       HIPK(coarse_apply_k<R>(L.g, L.n, L_of<R>(L), in, out, nrhs, 0, mode == DS_MR ? c->part.p : nullptr, 3,
                              nullptr, st));
     }
@@ -148,7 +174,7 @@ template <typename R>
 int coarse_dag_or_not(mg_ctx *c, int l, const c_t<R> *in, c_t<R> *out, int nrhs, int dagger, double *part,
                       const int *done, hipStream_t st) {
   Level &L = c->lev[l];
-  TimerScope ts(c, c->tm_coarse, st);
+  TimerScope ts(c, c->tm[tclass<R>(true)], st, (double)L.g.V * nrhs);
   HIPK(coarse_apply_k<R>(L.g, L.n, L_of<R>(L), in, out, nrhs, dagger, part, 1, done, st));
   return MG_OK;
 }
@@ -186,41 +212,130 @@ int transfer_prolong(mg_ctx *c, int l, const c_t<R> *coarse, c_t<R> *fine, int n
 }
 
 // CGNR on A^dag A e = A^dag b (coarsest level), A^dag = sigma3 A sigma3,
-// stopping at ||b - A e|| <= tol ||b|| (recursive residual).
+// stopping at ||b - A e|| <= tol ||b|| (recursive residual) or after
+// coarse_maxiter iterations.  Four launches per iteration and no host round
+// trip: w = A p (partials ||w||^2); update of e and r with alpha from the
+// partials (partials ||r||^2); convergence test fused into z = A^dag r
+// (partials ||z||^2); p = z + beta p.  Iterations run in chunks of CG_CHUNK
+// (captured once into a hipGraph when enabled); the host reads the done flags
+// of one chunk while the next is already queued, and kernels of converged
+// right-hand sides return at once.
+struct CgPtrs {
+  double *pw, *pz[2], *pr, *pb;
+};
+static CgPtrs cg_ptrs(mg_ctx *c, int l, int nrhs) {
+  const size_t stride = np_coarse(c->lev[l]) * nrhs;
+  CgPtrs q;
+  q.pw = c->cgp;
+  q.pz[0] = c->cgp + stride;
+  q.pz[1] = c->cgp + 2 * stride;
+  q.pr = c->cgp + 3 * stride;
+  q.pb = q.pr + (size_t)RED_BLOCKS * nrhs;
+  return q;
+}
+
+template <typename R> int cgnr_chunk(mg_ctx *c, int l, c_t<R> *e, int nrhs, hipStream_t st, EventTimer &tm) {
+  Work<R> &w = work<R>(c);
+  Level &L = c->lev[l];
+  const size_t n = L.vsize();
+  const double sites = (double)L.g.V * nrhs;
+  const int npc = (int)np_coarse(L);
+  c_t<R> *r = w.cr, *z = w.cz, *p = w.cp, *ww = w.cw;
+  const c_t<R> *Lop = L_of<R>(L);
+  const CgPtrs q = cg_ptrs(c, l, nrhs);
+  for (int k = 0; k < CG_CHUNK; ++k) {
+    {
+      TimerScope ts(c, tm, st, sites);
+      HIPK(coarse_apply_k<R>(L.g, L.n, Lop, p, ww, nrhs, 0, q.pw, 1, c->done, st));
+    }
+    const int npr = cg2_update<R>(e, p, r, ww, n, nrhs, q.pw, q.pz[k & 1], npc, c->done, q.pr, st);
+    HIPK(hipGetLastError());
+    CgCheck chk;
+    chk.part_r = q.pr;
+    chk.np_r = npr;
+    chk.cg = c->cg;
+    chk.done = c->done;
+    chk.it_in = c->it + (size_t)(k & 1) * nrhs;
+    chk.it_out = c->it + (size_t)((k + 1) & 1) * nrhs;
+    chk.maxit = c->p.coarse_maxiter;
+    {
+      TimerScope ts(c, tm, st, sites);
+      HIPK(coarse_apply_k<R>(L.g, L.n, Lop, r, z, nrhs, 1, q.pz[(k + 1) & 1], 1, c->done, st, &chk));
+    }
+    HIPK(cg2_p<R>(p, z, n, nrhs, q.pz[(k + 1) & 1], q.pz[k & 1], npc, c->done, st));
+  }
+  return MG_OK;
+}
+
+template <typename R> ChunkGraph *chunk_graph(mg_ctx *c, int l, c_t<R> *e, int nrhs, hipStream_t st) {
+  const int prec = sizeof(R) == 8 ? 0 : 1;
+  for (ChunkGraph *g : c->graphs)
+    if (g && g->level == l && g->prec == prec && g->nrhs == nrhs && g->timing == c->timing) return g;
+  ChunkGraph *g = new ChunkGraph();
+  g->level = l;
+  g->prec = prec;
+  g->nrhs = nrhs;
+  g->timing = c->timing;
+  bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) == hipSuccess;
+  if (ok) {
+    const int rc = cgnr_chunk<R>(c, l, e, nrhs, st, g->tm);
+    ok = hipStreamEndCapture(st, &g->graph) == hipSuccess && rc == MG_OK;
+  }
+  if (ok) ok = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    delete g;
+    return nullptr;
+  }
+  for (auto &slot : c->graphs)
+    if (!slot) {
+      slot = g;
+      return g;
+    }
+  delete c->graphs[0];
+  c->graphs[0] = g;
+  return g;
+}
+
 template <typename R> int cgnr(mg_ctx *c, int l, const c_t<R> *b, c_t<R> *e, int nrhs, hipStream_t st) {
   Work<R> &w = work<R>(c);
   Level &L = c->lev[l];
   const size_t n = L.vsize();
-  const int V = (int)L.g.V;
-  c_t<R> *r = w.cr, *z = w.cz, *p = w.cp, *ww = w.cw;
+  const CgPtrs q = cg_ptrs(c, l, nrhs);
+  EventTimer &tm = c->tm[tclass<R>(true)];
   HIPK(zero<R>(e, n * nrhs, st));
-  HIPK(copy<R>(r, b, n * nrhs, st));
-  const int npb = norm2_partials<R>(b, n, nrhs, c->part2, st);
-  MG_TRY(coarse_dag_or_not<R>(c, l, r, z, nrhs, 1, c->part, nullptr, st));
-  HIPK(cg_init_scalars(c->part, V, c->part2, npb, nrhs, c->cg, c->done, c->it, c->p.coarse_tol, st));
-  HIPK(copy<R>(p, z, n * nrhs, st));
-  const int maxit = c->p.coarse_maxiter;
-  const int chunk = 8;
-  for (int it0 = 0; it0 < maxit; it0 += chunk) {
-    for (int k = 0; k < chunk; ++k) {
-      MG_TRY(coarse_dag_or_not<R>(c, l, p, ww, nrhs, 0, c->part, c->done, st));
-      HIPK(cg_alpha(c->part, V, nrhs, c->cg, c->done, st));
-      HIPK(cg_update<R>(e, p, r, ww, n, nrhs, c->cg, c->done, c->it, maxit, c->part2, st));
-      MG_TRY(coarse_dag_or_not<R>(c, l, r, z, nrhs, 1, c->part, c->done, st));
-      HIPK(cg_beta(c->part, V, nrhs, c->cg, c->done, st));
-      HIPK(cg_p<R>(p, z, n, nrhs, c->cg, c->done, st));
-    }
-    HIPK(hipMemcpyAsync(c->h_done, c->done, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
-    HIPK(hipStreamSynchronize(st));
+  HIPK(copy<R>(w.cr, b, n * nrhs, st));
+  const int npb = norm2_partials<R>(b, n, nrhs, q.pb, st);
+  HIPK(cg2_init(q.pb, npb, nrhs, c->cg, c->done, c->it, c->p.coarse_tol, st));
+  {
+    TimerScope ts(c, tm, st, (double)L.g.V * nrhs);
+    HIPK(coarse_apply_k<R>(L.g, L.n, L_of<R>(L), w.cr, w.cz, nrhs, 1, q.pz[0], 1, c->done, st));
+  }
+  HIPK(copy<R>(w.cp, w.cz, n * nrhs, st));
+  ChunkGraph *gph = c->use_graph ? chunk_graph<R>(c, l, e, nrhs, st) : nullptr;
+  const int nchunks = (c->p.coarse_maxiter + CG_CHUNK - 1) / CG_CHUNK;
+  const bool pipeline = !c->timing;
+  for (int ch = 0; ch < nchunks; ++ch) {
+    if (gph) HIPK(hipGraphLaunch(gph->exec, st));
+    else MG_TRY(cgnr_chunk<R>(c, l, e, nrhs, st, tm));
+    int *hd = c->h_done + (size_t)(ch & 1) * MG_MAX_RHS;
+    HIPK(hipMemcpyAsync(hd, c->done, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
+    HIPK(hipEventRecord(c->ev_chunk[ch & 1], st));
+    const int look = pipeline ? ch - 1 : ch;
+    if (look < 0) continue;
+    HIPK(hipEventSynchronize(c->ev_chunk[look & 1]));
+    if (gph && c->timing) gph->tm.harvest(&tm, true);
+    const int *hl = c->h_done + (size_t)(look & 1) * MG_MAX_RHS;
     bool all = true;
-    for (int i = 0; i < nrhs; ++i) all = all && c->h_done[i];
+    for (int i = 0; i < nrhs; ++i) all = all && hl[i];
     if (all) break;
   }
-  HIPK(hipMemcpyAsync(c->h_it, c->it, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
+  HIPK(hipMemcpyAsync(c->h_it, c->it, sizeof(int) * 2 * nrhs, hipMemcpyDeviceToHost, st));
   HIPK(hipStreamSynchronize(st));
   for (int i = 0; i < nrhs; ++i) {
-    c->n_cgnr += c->h_it[i];
-    c->n_coarse += 1 + 2L * c->h_it[i];
+    const long it = std::max(c->h_it[i], c->h_it[nrhs + i]);
+    c->n_cgnr += it;
+    c->n_coarse += 1 + 2L * it;
   }
   return MG_OK;
 }
@@ -293,8 +408,9 @@ int fgcr(mg_ctx *c, const double2 *b, double2 *x, int nrhs, double tol, int *ite
       double2 *Zj = Z + (size_t)j * nn, *Wj = W + (size_t)j * nn;
       MG_TRY(precondition(c, r, Zj, nrhs, st));
       {
-        TimerScope ts(c, c->tm_dslash, st);
-        HIPK(dslash<double>(L0.g, L0.U64, Zj, Wj, nullptr, 4.0 + c->mass, nrhs, DS_PLAIN, nullptr, st));
+        TimerScope ts(c, c->tm[0], st, (double)L0.g.V * nrhs);
+        HIPK(dslash<double>(L0.g, L0.links64(), L0.nl, Zj, Wj, nullptr, 4.0 + c->mass, nrhs, DS_PLAIN, nullptr,
+                            st));
       }
       c->n_fine += nrhs;
       for (int i = 0; i < j; ++i) {
@@ -329,8 +445,8 @@ int fgcr(mg_ctx *c, const double2 *b, double2 *x, int nrhs, double tol, int *ite
     }
     // true residual r = b - D x
     {
-      TimerScope ts(c, c->tm_dslash, st);
-      HIPK(dslash<double>(L0.g, L0.U64, x, r, b, 4.0 + c->mass, nrhs, DS_RESID, nullptr, st));
+      TimerScope ts(c, c->tm[0], st, (double)L0.g.V * nrhs);
+      HIPK(dslash<double>(L0.g, L0.links64(), L0.nl, x, r, b, 4.0 + c->mass, nrhs, DS_RESID, nullptr, st));
     }
     c->n_fine += nrhs;
     HIPK(norm2<double>(r, n, nrhs, c->part, rr, st));
@@ -384,6 +500,7 @@ int setup(mg_ctx *c, const void *U, hipStream_t st) {
     Level &Lv = c->lev[l];
     const int *tile = (l < c->nlev - 1) ? p.block[l] : one;
     Lv.g = make_geom(L, tile, l == 0 ? anti : 0);
+    Lv.fine = (l == 0);
     Lv.n = (l == 0) ? 12 : 2 * p.nv[l - 1];
     Lv.nv = (l < c->nlev - 1) ? p.nv[l] : 0;
     for (int mu = 0; mu < 4; ++mu) L[mu] = Lv.g.C[mu];
@@ -391,13 +508,30 @@ int setup(mg_ctx *c, const void *U, hipStream_t st) {
   size_t pn = part_need(c, 1);
   for (int l = 0; l < c->nlev - 1; ++l) {
     const Level &Lv = c->lev[l];
-    const size_t per = (l == 0) ? (size_t)dslash_blocks(Lv.g) * 3 : (size_t)Lv.g.V * 3;
+    const size_t per = (l == 0) ? (size_t)dslash_blocks(Lv.g) * 3 : np_coarse(Lv) * 3;
     pn = std::max(pn, std::max(per, (size_t)RED_BLOCKS * 2) * Lv.nv);
   }
   MG_TRY(ensure_scalars(c, pn));
   Level &L0 = c->lev[0];
-  MG_TRY(L0.U64.alloc(36 * (size_t)L0.g.V));
-  HIPK(pack_field<double>(L0.g, (const double2 *)U, L0.U64, 9, 4, st));
+  MG_TRY(L0.U64.alloc(36 * (size_t)L0.g.Vpad));
+  HIPK(pack_gauge<double>(L0.g, (const double2 *)U, L0.U64, st));
+  // Compressed (two-row) links when every link is SU(3) to rounding.
+  MG_TRY(L0.U64c.alloc(24 * (size_t)L0.g.Vpad));
+  {
+    const int nb = dslash_blocks(L0.g);
+    HIPK(compress_links<double>(L0.g, L0.U64, L0.U64c, c->part, st));
+    std::vector<double> bm(nb);
+    HIPK(hipMemcpyAsync(bm.data(), c->part, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+    HIPK(hipStreamSynchronize(st));
+    double dev = 0.0;
+    for (double v : bm) dev = std::max(dev, v);
+    if (!std::isfinite(dev)) {
+      set_error("mg_setup: non-finite gauge field");
+      return MG_ENONFINITE;
+    }
+    L0.nl = dev <= 1e-12 ? 6 : 9;
+    if (L0.nl == 9) L0.U64c.release();
+  }
   int *flag = c->done;  // reused as rank-deficiency flag during setup
   for (int l = 0; l < c->nlev - 1; ++l) {
     Level &Lv = c->lev[l], &Lc = c->lev[l + 1];

@@ -7,6 +7,8 @@ namespace mg {
 
 template <typename R> Work<R> &work(mg_ctx *c);
 int ensure_scalars(mg_ctx *c, size_t part_count);
+void clear_graphs(mg_ctx *c);
+size_t np_coarse(const Level &L);
 size_t part_need(mg_ctx *c, int nrhs);
 int ensure_prec(mg_ctx *c, mg_prec_t prec, hipStream_t st);
 template <typename R> int ensure_work(mg_ctx *c, int nrhs);

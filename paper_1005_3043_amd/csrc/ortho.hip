@@ -33,11 +33,11 @@ __device__ __forceinline__ void block_allsum4(double (&v)[4], double (*lds)[4]) 
 
 constexpr double RANK_TOL = 1e-14;
 
-// Fine level: V[k][c][s] (SoA), aggregate of vb <= 256 sites, comps 0..5 =
+// Fine level: V[k][fidx(s, c)], aggregate of vb <= 256 sites, comps 0..5 =
 // chirality 0, 6..11 = chirality 1.
 __global__ __launch_bounds__(256) void k_ortho_fine(Geom g, int nv, double2 *__restrict__ V, int *flag) {
   __shared__ double lds[4][4];
-  const size_t Vn = g.V;
+  const size_t Vn = g.Vpad;
   const uint32_t t = threadIdx.x;
   const bool act = t < g.vb;
   const uint32_t s = blockIdx.x * g.vb + (act ? t : 0);
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void k_ortho_fine(Geom g, int nv, double2 *__r
     double2 *Vk = V + (size_t)kk * 12 * Vn;
     double2 v[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) v[c] = act ? Vk[(size_t)c * Vn + s] : make_double2(0, 0);
+    for (int c = 0; c < 12; ++c) v[c] = act ? Vk[fidx(s, c, 12)] : make_double2(0, 0);
     double n0[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int c = 0; c < 12; ++c) n0[c / 6] += v[c].x * v[c].x + v[c].y * v[c].y;
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void k_ortho_fine(Geom g, int nv, double2 *__r
         const double2 *Vj = V + (size_t)j * 12 * Vn;
         double2 q[12];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) q[c] = act ? Vj[(size_t)c * Vn + s] : make_double2(0, 0);
+        for (int c = 0; c < 12; ++c) q[c] = act ? Vj[fidx(s, c, 12)] : make_double2(0, 0);
         double2 c0 = make_double2(0, 0), c1 = make_double2(0, 0);
 #pragma unroll
         for (int c = 0; c < 6; ++c) c0 = cfmac(q[c], v[c], c0);
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void k_ortho_fine(Geom g, int nv, double2 *__r
     const double i0 = r0 > 0 ? 1.0 / r0 : 0.0, i1 = r1 > 0 ? 1.0 / r1 : 0.0;
     if (act) {
 #pragma unroll
-      for (int c = 0; c < 12; ++c) Vk[(size_t)c * Vn + s] = cscale(v[c], c < 6 ? i0 : i1);
+      for (int c = 0; c < 12; ++c) Vk[fidx(s, c, 12)] = cscale(v[c], c < 6 ? i0 : i1);
     }
     __syncthreads();
   }

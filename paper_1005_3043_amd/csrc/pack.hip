@@ -14,10 +14,10 @@ __global__ __launch_bounds__(256) void k_pack(Geom g, const double2 *__restrict_
   const Coords k = decode(g, s);
   const uint32_t i = canon_index(g, k);
   const double2 *src = canon + (vec * g.V + i) * (size_t)ncomp;
-  c_t<T> *dst = internal + vec * (size_t)ncomp * g.V + s;
+  c_t<T> *dst = internal + vec * (size_t)ncomp * g.Vpad;
   for (int c = 0; c < ncomp; ++c) {
     double2 v = src[c];
-    dst[(size_t)c * g.V] = mk<c_t<T>>((T)v.x, (T)v.y);
+    dst[fidx(s, c, ncomp)] = mk<c_t<T>>((T)v.x, (T)v.y);
   }
 }
 
@@ -30,9 +30,9 @@ __global__ __launch_bounds__(256) void k_unpack(Geom g, const c_t<T> *__restrict
   const Coords k = decode(g, s);
   const uint32_t i = canon_index(g, k);
   double2 *dst = canon + (vec * g.V + i) * (size_t)ncomp;
-  const c_t<T> *src = internal + vec * (size_t)ncomp * g.V + s;
+  const c_t<T> *src = internal + vec * (size_t)ncomp * g.Vpad;
   for (int c = 0; c < ncomp; ++c) {
-    c_t<T> v = src[(size_t)c * g.V];
+    c_t<T> v = src[fidx(s, c, ncomp)];
     dst[c] = make_double2((double)v.x, (double)v.y);
   }
 }
@@ -54,6 +54,27 @@ hipError_t unpack_field(const Geom &g, const c_t<T> *internal, double2 *canon, i
   hipLaunchKernelGGL(k_unpack<T>, grid, dim3(256), 0, st, g, internal, canon, ncomp);
   return hipGetLastError();
 }
+
+// Gauge field: canonical U[mu][lex site][3][3] -> internal 36-component
+// fine field, component mu * 9 + (3 a + b).
+template <typename T>
+__global__ __launch_bounds__(256) void k_pack_gauge(Geom g, const double2 *__restrict__ canon,
+                                                    c_t<T> *__restrict__ internal) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  const Coords k = decode(g, s);
+  const uint32_t i = canon_index(g, k);
+  for (int mu = 0; mu < 4; ++mu) {
+    const double2 *src = canon + ((size_t)mu * g.V + i) * 9;
+    for (int e = 0; e < 9; ++e) internal[fidx(s, mu * 9 + e, 36)] = mk<c_t<T>>((T)src[e].x, (T)src[e].y);
+  }
+}
+template <typename T> hipError_t pack_gauge(const Geom &g, const double2 *canon, c_t<T> *internal, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_gauge<T>, dim3(div_up(g.V, 256)), dim3(256), 0, st, g, canon, internal);
+  return hipGetLastError();
+}
+template hipError_t pack_gauge<double>(const Geom &, const double2 *, double2 *, hipStream_t);
+template hipError_t pack_gauge<float>(const Geom &, const double2 *, float2 *, hipStream_t);
 
 // Site-major (coarse) vectors: canonical [vec][lex site][n] <-> internal
 // [vec][site-blocked s][n].

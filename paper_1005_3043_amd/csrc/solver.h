@@ -20,21 +20,23 @@ template <typename R> int norm2_partials(const c_t<R> *a, size_t n, int nrhs, do
 template <typename R>
 hipError_t dot(const c_t<R> *a, const c_t<R> *b, size_t n, int nrhs, double *part, double2 *out, hipStream_t st);
 hipError_t finish_sum1(const double *part, int np, int nrhs, double *out, hipStream_t st);
-hipError_t cg_init_scalars(const double *part_z, int npz, const double *part_b, int npb, int nrhs, double *cg,
-                           int *done, int *it, double tol, hipStream_t st);
-hipError_t cg_alpha(const double *part, int np, int nrhs, double *cg, int *done, hipStream_t st);
-template <typename R>
-hipError_t cg_update(c_t<R> *e, const c_t<R> *p, c_t<R> *r, const c_t<R> *w, size_t n, int nrhs, double *cg,
-                     int *done, int *it, int maxit, double *part, hipStream_t st);
-hipError_t cg_beta(const double *part, int np, int nrhs, double *cg, int *done, hipStream_t st);
-template <typename R>
-hipError_t cg_p(c_t<R> *p, const c_t<R> *z, size_t n, int nrhs, const double *cg, const int *done, hipStream_t st);
 hipError_t gcr_sub2(double2 *y, const double2 *x, double2 *v, const double2 *u, size_t n, int nrhs,
                     const double2 *sc, const int *skip, hipStream_t st);
 hipError_t gcr_scale2(double2 *y, double2 *v, size_t n, int nrhs, const double *nrm2, const int *skip,
                       hipStream_t st);
 hipError_t gcr_update(double2 *x, const double2 *z, double2 *r, const double2 *w, size_t n, int nrhs,
                       const double2 *sc, const int *skip, double *part, double *rr, hipStream_t st);
+// Fused CGNR steps (no finisher kernels): scalars are re-derived from the
+// per-block partials by every consuming workgroup in a fixed order.
+hipError_t cg2_init(const double *part_b, int npb, int nrhs, double *cg, int *done, int *it, double tol,
+                    hipStream_t st);
+// returns the number of residual partials written per RHS
+template <typename R>
+int cg2_update(c_t<R> *e, const c_t<R> *p, c_t<R> *r, const c_t<R> *w, size_t n, int nrhs, const double *part_w,
+               const double *part_z, int npc, int *done, double *part_r, hipStream_t st);
+template <typename R>
+hipError_t cg2_p(c_t<R> *p, const c_t<R> *z, size_t n, int nrhs, const double *part_znew, const double *part_zold,
+                 int npc, const int *done, hipStream_t st);
 // v -= x
 template <typename R> hipError_t sub_inplace(c_t<R> *v, const c_t<R> *x, size_t n, int nrhs, hipStream_t st);
 // v *= 1 / sqrt(nrm2[rhs])
@@ -69,7 +71,9 @@ template <typename T> struct DevBuf {
     release();
     if (count == 0) return MG_OK;
     hipError_t e = hipMalloc((void **)&p, count * sizeof(T));
+    if (e == hipSuccess) e = hipMemset(p, 0, count * sizeof(T));  // padding entries stay zero
     if (e != hipSuccess) {
+      if (p) (void)hipFree(p);
       p = nullptr;
       set_error(hip_error_string(e, "hipMalloc"));
       return e == hipErrorOutOfMemory ? MG_ENOMEM : MG_EHIP;
@@ -89,14 +93,20 @@ template <> struct PrecBufs<float> {
 };
 
 struct Level {
-  Geom g;     // this level's lattice; tile = aggregate shape to the next level
-  int n = 0;  // complex components per site (12 on the fine level)
-  int nv = 0; // null vectors defining the next level (0 on the coarsest)
-  DevBuf<double2> U64;  DevBuf<float2> U32;   // fine links [36][V]
+  Geom g;            // this level's lattice; tile = aggregate shape to the next level
+  bool fine = false; // fine level: tile-interleaved fields of Vpad sites
+  int n = 0;         // complex components per site (12 on the fine level)
+  int nv = 0;        // null vectors defining the next level (0 on the coarsest)
+  int nl = 9;        // fine links stored with 9 (full) or 6 (two rows) entries
+  DevBuf<double2> U64;   // fine links, full, FP64 [36 components]
+  DevBuf<double2> U64c;  // fine links, two rows, FP64 [24 components] (nl = 6)
+  DevBuf<float2> U32;    // fine links in FP32, nl entries per direction
   DevBuf<double2> L64;  DevBuf<float2> L32;   // coarse stencil [V][9][n][n]
   DevBuf<double2> P64;  DevBuf<float2> P32;   // prolongator to next level
   DevBuf<double2> NV;                         // relaxed candidates before QR
-  size_t vsize() const { return (size_t)g.V * n; }  // complex entries per vector
+  // complex entries per vector
+  size_t vsize() const { return (size_t)(fine ? g.Vpad : g.V) * n; }
+  const double2 *links64() const { return nl == 6 ? U64c.p : U64.p; }
 };
 
 template <typename R> struct Work {
@@ -107,9 +117,19 @@ template <typename R> struct Work {
   int nrhs = 0;
 };
 
+// Device-side timing of one kernel class: (start, stop) event pairs recorded
+// around launches; harvest() adds the elapsed times of the recorded pairs to
+// the accumulators (after the work has completed).  A timer owned by a
+// captured graph keeps its events (they are re-recorded by every replay).
 struct EventTimer {
   std::vector<hipEvent_t> ev;
+  std::vector<double> pair_sites;  // sites x right-hand sides of each pair
   size_t used = 0;
+  double ms = 0.0, sites = 0.0;    // accumulated
+  long launches = 0;
+  EventTimer() = default;
+  EventTimer(const EventTimer &) = delete;
+  EventTimer &operator=(const EventTimer &) = delete;
   ~EventTimer() {
     for (auto e : ev) (void)hipEventDestroy(e);
   }
@@ -121,17 +141,43 @@ struct EventTimer {
     }
     return ev[used++];
   }
-  double total_ms() {  // pairs (start, stop); call after synchronisation
-    double t = 0.0;
+  // accumulate the recorded pairs into dst (default: this timer)
+  void harvest(EventTimer *dst = nullptr, bool keep = false) {
+    if (!dst) dst = this;
     for (size_t i = 0; i + 1 < used; i += 2) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) t += ms;
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) continue;
+      dst->ms += t;
+      dst->launches += 1;
+      if (i / 2 < pair_sites.size()) dst->sites += pair_sites[i / 2];
     }
-    return t;
+    if (!keep) {
+      used = 0;
+      pair_sites.clear();
+    }
+    (void)hipGetLastError();  // a failed elapsed-time query must not latch into later launches
   }
-  int launches() const { return (int)(used / 2); }
-  void reset() { used = 0; }
+  void reset() {
+    used = 0;
+    pair_sites.clear();
+    ms = sites = 0.0;
+    launches = 0;
+  }
 };
+
+// A captured chunk of CGNR iterations for one (level, precision, nrhs).
+struct ChunkGraph {
+  int level = -1, prec = -1, nrhs = 0, timing = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  EventTimer tm;  // coarse-stencil timing events inside the graph (timing on)
+  ~ChunkGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+constexpr int CG_CHUNK = 8;  // CGNR iterations per chunk (even: parity slots repeat)
 
 }  // namespace mg
 
@@ -145,6 +191,11 @@ struct mg_ctx {
   int timing = 0;
   // scalars and partials
   mg::DevBuf<double> part, part2, dsc, cg;
+  mg::DevBuf<double> cgp;  // CGNR partials: w, z[2], r, b
+  hipStream_t sti = nullptr;                  // library-owned stream of mg_solve
+  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_chunk[2] = {nullptr, nullptr};
+  int use_graph = 1;
+  mg::ChunkGraph *graphs[8] = {};             // captured CGNR chunks
   mg::DevBuf<double2> csc;
   mg::DevBuf<int> done, it;
   int *h_done = nullptr;   // pinned host mirrors
@@ -158,6 +209,6 @@ struct mg_ctx {
   int gcr_rhs = 0;
   // statistics
   long n_fine = 0, n_coarse = 0, n_cgnr = 0, n_vcyc = 0;
-  mg::EventTimer tm_dslash, tm_coarse;
+  mg::EventTimer tm[4];  // fine FP64, fine FP32, coarse FP64, coarse FP32
   double t_setup = 0.0;
 };

@@ -52,56 +52,6 @@ template <int W> __global__ void k_fin_sum(const double *part, int np, double *o
   }
 }
 
-// CGNR scalars per RHS: cg[0] = zz, cg[1] = alpha, cg[2] = beta, cg[3] = nb2,
-// cg[4] = tol^2, cg[5] = rr; it[rhs] = iterations; done[rhs] = converged.
-__global__ void k_fin_cg_alpha(const double *part, int np, double *cg, int *done) {
-  if (done[blockIdx.y]) return;
-  double t[1];
-  finish_sum<1>(part, np, t);
-  if (threadIdx.x == 0) {
-    double *c = cg + (size_t)blockIdx.y * CG_NS;
-    if (t[0] > 0.0) c[1] = c[0] / t[0];
-    else { c[1] = 0.0; done[blockIdx.y] = 1; }
-  }
-}
-__global__ void k_fin_cg_rr(const double *part, int np, double *cg, int *done, int *it, int maxit) {
-  if (done[blockIdx.y]) return;
-  double t[1];
-  finish_sum<1>(part, np, t);
-  if (threadIdx.x == 0) {
-    double *c = cg + (size_t)blockIdx.y * CG_NS;
-    c[5] = t[0];
-    const int n = ++it[blockIdx.y];
-    if (!(t[0] > c[4] * c[3]) || n >= maxit) done[blockIdx.y] = 1;
-  }
-}
-__global__ void k_fin_cg_beta(const double *part, int np, double *cg, int *done) {
-  if (done[blockIdx.y]) return;
-  double t[1];
-  finish_sum<1>(part, np, t);
-  if (threadIdx.x == 0) {
-    double *c = cg + (size_t)blockIdx.y * CG_NS;
-    c[2] = c[0] > 0.0 ? t[0] / c[0] : 0.0;
-    c[0] = t[0];
-  }
-}
-__global__ void k_fin_cg_init(const double *part_z, int npz, const double *part_b, int npb, double *cg, int *done,
-                              int *it, double tol2) {
-  double t[1], tb[1];
-  finish_sum<1>(part_z, npz, t);
-  __syncthreads();
-  finish_sum<1>(part_b, npb, tb);
-  if (threadIdx.x == 0) {
-    double *c = cg + (size_t)blockIdx.y * CG_NS;
-    c[0] = t[0];
-    c[3] = tb[0];
-    c[4] = tol2;
-    c[5] = tb[0];
-    it[blockIdx.y] = 0;
-    done[blockIdx.y] = (tb[0] > 0.0 && t[0] > 0.0) ? 0 : 1;
-  }
-}
-
 // --------------------------------------------------------------- reductions
 template <typename R>
 __global__ __launch_bounds__(256) void k_norm2(const c_t<R> *a, size_t n, double *part) {
@@ -151,39 +101,6 @@ __global__ __launch_bounds__(256) void k_mr_update(c_t<R> *x, c_t<R> *r, const c
     x[i] = first ? cmul(a, rv) : cfma(a, rv, x[i]);
     r[i] = cfma(ma, q[i], rv);
   }
-}
-
-// CGNR: e += alpha p; r -= alpha w; partial ||r||^2
-template <typename R>
-__global__ __launch_bounds__(256) void k_cg_update(c_t<R> *e, const c_t<R> *p, c_t<R> *r, const c_t<R> *w, size_t n,
-                                                   const double *cg, const int *done, double *part) {
-  using C = c_t<R>;
-  __shared__ double lds[4];
-  if (done[blockIdx.y]) return;
-  const size_t off = (size_t)blockIdx.y * n;
-  e += off; p += off; r += off; w += off;
-  const R a = (R)cg[(size_t)blockIdx.y * CG_NS + 1];
-  double t[1] = {0.0};
-  GSTRIDE(i, n) {
-    e[i] = cfma(mk<C>(a, 0), p[i], e[i]);
-    const C rv = cfma(mk<C>(-a, 0), w[i], r[i]);
-    r[i] = rv;
-    t[0] += (double)rv.x * rv.x + (double)rv.y * rv.y;
-  }
-  block_sum<1>(t, lds);
-  if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = t[0];
-}
-
-// CGNR: p = z + beta p
-template <typename R>
-__global__ __launch_bounds__(256) void k_cg_p(c_t<R> *p, const c_t<R> *z, size_t n, const double *cg,
-                                              const int *done) {
-  using C = c_t<R>;
-  if (done[blockIdx.y]) return;
-  const size_t off = (size_t)blockIdx.y * n;
-  p += off; z += off;
-  const R b = (R)cg[(size_t)blockIdx.y * CG_NS + 2];
-  GSTRIDE(i, n) p[i] = cfma(mk<C>(b, 0), p[i], z[i]);
 }
 
 // y -= c x and v -= c u with c = sc[rhs] (complex)  (FGCR Gram-Schmidt)
@@ -262,7 +179,102 @@ __global__ __launch_bounds__(256) void k_resid_from(c_t<R> *out, const c_t<R> *b
   GSTRIDE(i, n) out[i] = csub(b[i], out[i]);
 }
 
+// --------------------------------------------------------------- CGNR (fused)
+// Sum of np partials of RHS blockIdx.y over the workgroup, in every thread
+// (fixed order: identical in every workgroup).
+__device__ __forceinline__ double allsum(const double *__restrict__ p, int np, double *lds) {
+  p += (size_t)blockIdx.y * np;
+  double a = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) a += p[i];
+  a = wave_sum(a);
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds[w] = a;
+  __syncthreads();
+  double t = 0.0;
+  for (int q = 0; q < nw; ++q) t += lds[q];
+  __syncthreads();
+  return t;
+}
+
+// ||b||^2, tol^2, done = (b == 0), both iteration-count slots = 0
+__global__ void k_cg2_init(const double *part_b, int npb, double *cg, int *done, int *it, double tol2) {
+  __shared__ double lds[4];
+  const double nb2 = allsum(part_b, npb, lds);
+  if (threadIdx.x == 0) {
+    double *c = cg + (size_t)blockIdx.y * CG_NS;
+    c[3] = nb2;
+    c[4] = tol2;
+    it[blockIdx.y] = 0;
+    it[gridDim.y + blockIdx.y] = 0;
+    done[blockIdx.y] = nb2 > 0.0 ? 0 : 1;
+  }
+}
+
+// alpha = zz / ww from the partials; e += alpha p; r -= alpha w; partial ||r||^2
+template <typename R>
+__global__ __launch_bounds__(256) void k_cg2_update(c_t<R> *e, const c_t<R> *p, c_t<R> *r, const c_t<R> *w, size_t n,
+                                                    const double *part_w, const double *part_z, int npc, int *done,
+                                                    double *part_r) {
+  using C = c_t<R>;
+  __shared__ double lds[4];
+  if (done[blockIdx.y]) return;
+  const double ww = allsum(part_w, npc, lds);
+  const double zz = allsum(part_z, npc, lds);
+  if (!(ww > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) done[blockIdx.y] = 1;
+    return;
+  }
+  const R a = (R)(zz / ww);
+  const size_t off = (size_t)blockIdx.y * n;
+  e += off; p += off; r += off; w += off;
+  double t[1] = {0.0};
+  GSTRIDE(i, n) {
+    e[i] = cfma(mk<C>(a, 0), p[i], e[i]);
+    const C rv = cfma(mk<C>(-a, 0), w[i], r[i]);
+    r[i] = rv;
+    t[0] += (double)rv.x * rv.x + (double)rv.y * rv.y;
+  }
+  block_sum<1>(t, lds);
+  if (threadIdx.x == 0) part_r[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = t[0];
+}
+
+// beta = zz_new / zz_old from the partials; p = z + beta p
+template <typename R>
+__global__ __launch_bounds__(256) void k_cg2_p(c_t<R> *p, const c_t<R> *z, size_t n, const double *part_znew,
+                                               const double *part_zold, int npc, const int *done) {
+  using C = c_t<R>;
+  __shared__ double lds[4];
+  if (done[blockIdx.y]) return;
+  const double zn = allsum(part_znew, npc, lds);
+  const double zo = allsum(part_zold, npc, lds);
+  const R b = (R)(zo > 0.0 ? zn / zo : 0.0);
+  const size_t off = (size_t)blockIdx.y * n;
+  p += off; z += off;
+  GSTRIDE(i, n) p[i] = cfma(mk<C>(b, 0), p[i], z[i]);
+}
+
 // ====================================================================== host
+hipError_t cg2_init(const double *part_b, int npb, int nrhs, double *cg, int *done, int *it, double tol,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_cg2_init, dim3(1, nrhs), dim3(256), 0, st, part_b, npb, cg, done, it, tol * tol);
+  return hipGetLastError();
+}
+template <typename R>
+int cg2_update(c_t<R> *e, const c_t<R> *p, c_t<R> *r, const c_t<R> *w, size_t n, int nrhs, const double *part_w,
+               const double *part_z, int npc, int *done, double *part_r, hipStream_t st) {
+  const int g = sgrid(n);
+  hipLaunchKernelGGL(k_cg2_update<R>, dim3(g, nrhs), dim3(256), 0, st, e, p, r, w, n, part_w, part_z, npc, done,
+                     part_r);
+  return g;
+}
+template <typename R>
+hipError_t cg2_p(c_t<R> *p, const c_t<R> *z, size_t n, int nrhs, const double *part_znew, const double *part_zold,
+                 int npc, const int *done, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg2_p<R>, dim3(sgrid(n), nrhs), dim3(256), 0, st, p, z, n, part_znew, part_zold, npc, done);
+  return hipGetLastError();
+}
+
 template <typename R> hipError_t sub_inplace(c_t<R> *v, const c_t<R> *x, size_t n, int nrhs, hipStream_t st) {
   hipLaunchKernelGGL(k_sub<R>, dim3(sgrid(n), nrhs), dim3(256), 0, st, v, x, n);
   return hipGetLastError();
@@ -311,38 +323,6 @@ hipError_t finish_sum1(const double *part, int np, int nrhs, double *out, hipStr
   return hipGetLastError();
 }
 
-hipError_t cg_init_scalars(const double *part_z, int npz, const double *part_b, int npb, int nrhs, double *cg,
-                           int *done, int *it, double tol, hipStream_t st) {
-  hipLaunchKernelGGL(k_fin_cg_init, dim3(1, nrhs), dim3(256), 0, st, part_z, npz, part_b, npb, cg, done, it,
-                     tol * tol);
-  return hipGetLastError();
-}
-
-hipError_t cg_alpha(const double *part, int np, int nrhs, double *cg, int *done, hipStream_t st) {
-  hipLaunchKernelGGL(k_fin_cg_alpha, dim3(1, nrhs), dim3(256), 0, st, part, np, cg, done);
-  return hipGetLastError();
-}
-
-template <typename R>
-hipError_t cg_update(c_t<R> *e, const c_t<R> *p, c_t<R> *r, const c_t<R> *w, size_t n, int nrhs, double *cg,
-                     int *done, int *it, int maxit, double *part, hipStream_t st) {
-  const int g = sgrid(n);
-  hipLaunchKernelGGL(k_cg_update<R>, dim3(g, nrhs), dim3(256), 0, st, e, p, r, w, n, cg, done, part);
-  hipLaunchKernelGGL(k_fin_cg_rr, dim3(1, nrhs), dim3(256), 0, st, part, g, cg, done, it, maxit);
-  return hipGetLastError();
-}
-
-hipError_t cg_beta(const double *part, int np, int nrhs, double *cg, int *done, hipStream_t st) {
-  hipLaunchKernelGGL(k_fin_cg_beta, dim3(1, nrhs), dim3(256), 0, st, part, np, cg, done);
-  return hipGetLastError();
-}
-
-template <typename R>
-hipError_t cg_p(c_t<R> *p, const c_t<R> *z, size_t n, int nrhs, const double *cg, const int *done, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_p<R>, dim3(sgrid(n), nrhs), dim3(256), 0, st, p, z, n, cg, done);
-  return hipGetLastError();
-}
-
 hipError_t gcr_sub2(double2 *y, const double2 *x, double2 *v, const double2 *u, size_t n, int nrhs,
                     const double2 *sc, const int *skip, hipStream_t st) {
   hipLaunchKernelGGL(k_sub2, dim3(sgrid(n), nrhs), dim3(256), 0, st, y, x, v, u, n, sc, skip);
@@ -369,12 +349,13 @@ hipError_t gcr_update(double2 *x, const double2 *z, double2 *r, const double2 *w
   template hipError_t norm2<R>(const c_t<R> *, size_t, int, double *, double *, hipStream_t);                       \
   template int norm2_partials<R>(const c_t<R> *, size_t, int, double *, hipStream_t);                               \
   template hipError_t dot<R>(const c_t<R> *, const c_t<R> *, size_t, int, double *, double2 *, hipStream_t);        \
-  template hipError_t cg_update<R>(c_t<R> *, const c_t<R> *, c_t<R> *, const c_t<R> *, size_t, int, double *,       \
-                                   int *, int *, int, double *, hipStream_t);                                       \
-  template hipError_t cg_p<R>(c_t<R> *, const c_t<R> *, size_t, int, const double *, const int *, hipStream_t);      \
   template hipError_t sub_inplace<R>(c_t<R> *, const c_t<R> *, size_t, int, hipStream_t);                           \
   template hipError_t scale_rsqrt<R>(c_t<R> *, size_t, int, const double *, hipStream_t);                           \
-  template hipError_t resid_from<R>(c_t<R> *, const c_t<R> *, size_t, int, hipStream_t);
+  template hipError_t resid_from<R>(c_t<R> *, const c_t<R> *, size_t, int, hipStream_t);                           \
+  template int cg2_update<R>(c_t<R> *, const c_t<R> *, c_t<R> *, const c_t<R> *, size_t, int, const double *,        \
+                             const double *, int, int *, double *, hipStream_t);                                    \
+  template hipError_t cg2_p<R>(c_t<R> *, const c_t<R> *, size_t, int, const double *, const double *, int,          \
+                               const int *, hipStream_t);
 INST(double)
 INST(float)
 #undef INST

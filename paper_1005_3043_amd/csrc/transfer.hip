@@ -3,11 +3,11 @@
 // Eq. 8 with the gamma_5 factors cancelled).
 //
 // Fine level: P is held as the Nv orthonormalised null-vector fields in the
-// fine SoA layout [Nv][12][V]; column (chi, k) of P on aggregate B is field k
+// fine layout [Nv][12 * Vpad]; column (chi, k) of P on aggregate B is field k
 // restricted to the spin half chi (components 6 chi .. 6 chi + 5) on the
-// sites of B.  With the site-blocked order the sites of one aggregate are one
-// contiguous range in every plane, so a workgroup per aggregate streams P and
-// the residual with fully coalesced loads and reduces 2 Nv inner products.
+// sites of B.  With the site-blocked order the sites of one aggregate are a
+// contiguous run of tiles, so a workgroup per aggregate streams P and the
+// residual with fully coalesced loads and reduces 2 Nv inner products.
 // Coarse level l -> l+1: vectors are site-major [V][n]; P is [Nv][V][n] and
 // chirality is the upper / lower half of the n components (sigma_3).
 #include "kernels.h"
@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void k_restrict_fine(Geom g, Geom gc, int nv, 
                                                        const c_t<R> *__restrict__ fine, c_t<R> *__restrict__ coarse) {
   using C = c_t<R>;
   __shared__ double2 part[4][2 * COARSE_NMAX];
-  const size_t V = g.V;
+  const size_t V = g.Vpad;
   const uint32_t B = blockIdx.x;
   fine += (size_t)blockIdx.y * 12 * V;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -39,15 +39,15 @@ __global__ __launch_bounds__(256) void k_restrict_fine(Geom g, Geom gc, int nv, 
     const uint32_t s = B * g.vb + (act ? t : 0);
     C r[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) r[c] = act ? fine[(size_t)c * V + s] : mk<C>(0, 0);
+    for (int c = 0; c < 12; ++c) r[c] = act ? fine[fidx(s, c, 12)] : mk<C>(0, 0);
     for (int kk = 0; kk < nv; ++kk) {
       const C *Pk = P + (size_t)kk * 12 * V;
       C d0 = mk<C>(0, 0), d1 = mk<C>(0, 0);
       if (act) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) d0 = cfmac(Pk[(size_t)c * V + s], r[c], d0);
+        for (int c = 0; c < 6; ++c) d0 = cfmac(Pk[fidx(s, c, 12)], r[c], d0);
 #pragma unroll
-        for (int c = 6; c < 12; ++c) d1 = cfmac(Pk[(size_t)c * V + s], r[c], d1);
+        for (int c = 6; c < 12; ++c) d1 = cfmac(Pk[fidx(s, c, 12)], r[c], d1);
       }
       double a0 = wave_sum((double)d0.x), b0 = wave_sum((double)d0.y);
       double a1 = wave_sum((double)d1.x), b1 = wave_sum((double)d1.y);
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void k_prolong_fine(Geom g, Geom gc, int nv, c
                                                       const c_t<R> *__restrict__ coarse, c_t<R> *__restrict__ fine,
                                                       int accumulate) {
   using C = c_t<R>;
-  const size_t V = g.V;
+  const size_t V = g.Vpad;
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= g.V) return;
   fine += (size_t)blockIdx.y * 12 * V;
@@ -93,15 +93,15 @@ __global__ __launch_bounds__(256) void k_prolong_fine(Geom g, Geom gc, int nv, c
     const C *Pk = P + (size_t)kk * 12 * V;
     const C e0 = ec[kk], e1 = ec[nv + kk];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) acc[c] = cfma(Pk[(size_t)c * V + s], e0, acc[c]);
+    for (int c = 0; c < 6; ++c) acc[c] = cfma(Pk[fidx(s, c, 12)], e0, acc[c]);
 #pragma unroll
-    for (int c = 6; c < 12; ++c) acc[c] = cfma(Pk[(size_t)c * V + s], e1, acc[c]);
+    for (int c = 6; c < 12; ++c) acc[c] = cfma(Pk[fidx(s, c, 12)], e1, acc[c]);
   }
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
     C v = acc[c];
-    if (accumulate) v = cadd(fine[(size_t)c * V + s], v);
-    fine[(size_t)c * V + s] = v;
+    if (accumulate) v = cadd(fine[fidx(s, c, 12)], v);
+    fine[fidx(s, c, 12)] = v;
   }
 }
 

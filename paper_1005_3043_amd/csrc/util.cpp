@@ -28,6 +28,7 @@ Geom make_geom(const int L[4], const int b[4], int antiperiodic) {
     Vc *= (uint64_t)g.C[mu];
   }
   g.V = (uint32_t)V;
+  g.Vpad = (uint32_t)((V + 63) / 64 * 64);
   g.vb = (uint32_t)vb;
   g.Vc = (uint32_t)Vc;
   g.Sl[0] = 1;

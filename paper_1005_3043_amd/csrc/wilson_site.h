@@ -65,20 +65,6 @@ __host__ __device__ __forceinline__ void hop_site(C (&acc)[12], const C (&psi)[1
   }
 }
 
-template <typename C>
-__host__ __device__ __forceinline__ void load_spinor(C (&psi)[12], const C *__restrict__ in, uint32_t s,
-                                                     size_t V) {
-#pragma unroll
-  for (int k = 0; k < 12; ++k) psi[k] = in[(size_t)k * V + s];
-}
-
-template <typename C>
-__host__ __device__ __forceinline__ void load_link(C (&u)[9], const C *__restrict__ U, int mu, uint32_t s,
-                                                   size_t V) {
-#pragma unroll
-  for (int e = 0; e < 9; ++e) u[e] = U[(size_t)(mu * 9 + e) * V + s];
-}
-
 template <bool fwd, typename C>
 __host__ __device__ __forceinline__ void hop_dispatch(int mu, C (&acc)[12], const C (&psi)[12], const C (&u)[9],
                                                       decltype(C::x) eta) {

@@ -182,3 +182,49 @@ def test_setup_errors(cuda):
     with pytest.raises(mgwd.MGError) as e:
         mgwd.MG(U, -0.3, [(4, 4, 4, 4)], [4], [same])
     assert e.value.rc == -7
+
+
+def test_graph_replay_matches_eager(cuda):
+    """CGNR chunks replayed from a captured hipGraph give bit-identical
+    solutions to eager launches, across repeated solves with eager work and
+    synchronisations between them (same kernels, same order)."""
+    import paper_1005_3043_amd as mgwd
+    L, blocks, nv, eps, m, seed = CASES["8^4 b4^4 nv8"]
+    U = torch.from_numpy(W.gauge_field(L, eps, seed)).cuda()
+    st = torch.from_numpy(W.setup_starts(L, nv[0], seed)).cuda()
+    ctx_g = mgwd.MG(U, m, blocks, nv, [st], use_graph=True, max_rhs=2)
+    ctx_e = mgwd.MG(U, m, blocks, nv, [st], use_graph=False, max_rhs=2)
+    for seed_b in (0, 1, 2):
+        b = torch.from_numpy(W.gaussian_spinor(L, seed_b, batch=(2,))).cuda()
+        xe, ie, _ = ctx_e.solve(b, 1e-10)
+        torch.cuda.synchronize()
+        xg, ig, _ = ctx_g.solve(b, 1e-10)
+        torch.cuda.synchronize()
+        assert torch.equal(xe, xg), seed_b
+        assert ie["iters"] == ig["iters"] and ie["n_cgnr_iters"] == ig["n_cgnr_iters"]
+    for prec in ("f32",):
+        ctx_g.set_precond_prec(prec)
+        ctx_e.set_precond_prec(prec)
+        xe, _, _ = ctx_e.solve(b, 1e-10)
+        xg, _, _ = ctx_g.solve(b, 1e-10)
+        assert torch.equal(xe, xg)
+
+
+def test_timing_does_not_change_results(cuda):
+    import paper_1005_3043_amd as mgwd
+    L, blocks, nv, eps, m, seed = CASES["8^4 b4^4 nv8"]
+    U = torch.from_numpy(W.gauge_field(L, eps, seed)).cuda()
+    st = torch.from_numpy(W.setup_starts(L, nv[0], seed)).cuda()
+    ctx = mgwd.MG(U, m, blocks, nv, [st])
+    b = torch.from_numpy(W.gaussian_spinor(L, 3)).cuda()
+    x0, i0, _ = ctx.solve(b, 1e-10)
+    ctx.set_timing(True)
+    x1, i1, _ = ctx.solve(b, 1e-10)
+    assert torch.equal(x0, x1)
+    k = i1["kernels"]
+    # dispatches include the early-exit ones queued after CGNR convergence
+    # (at most one chunk of 8 iterations = 16 coarse launches per V-cycle)
+    extra = k["coarse_f64"]["launches"] - i1["n_coarse_apply"]
+    assert 0 <= extra <= 16 * i1["n_vcycles"]
+    assert k["dslash_f64"]["launches"] == i1["n_fine_dslash"]
+    assert k["coarse_f64"]["ms"] > 0 and k["dslash_f64"]["ms"] > 0
