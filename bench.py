@@ -30,16 +30,21 @@ HBM_PEAK_GBPS = 8000.0
 WORKLOAD = "C1"
 
 
+# bytes per real of (vectors, operators) for each precision class; "f16" keeps
+# FP32 vectors and stores the operators (links, P, D_c) in binary16
+WIDTH = {"f64": (8.0, 8.0), "f32": (4.0, 4.0), "f16": (4.0, 2.0)}
+
+
 def dslash_bytes(prec, compressed=False):
     """Algorithmic bytes per site: spinor in (24 reals) + 4 links (18 reals, or
     12 when stored as two rows) + spinor out (24 reals)."""
-    w = {"f64": 8.0, "f32": 4.0}[prec]
-    return (24 + 4 * (12 if compressed else 18) + 24) * w
+    wv, wl = WIDTH[prec]
+    return 48 * wv + 4 * (12 if compressed else 18) * wl
 
 
-def coarse_bytes(n, prec):    # 9 n^2 link entries + vector in/out, per coarse site
-    w = 16.0 if prec == "f64" else 8.0
-    return (9 * n * n + 2 * n) * w
+def coarse_bytes(n, prec):    # 9 n^2 operator entries + vector in/out, per coarse site
+    wv, wl = WIDTH[prec]
+    return 2 * (9 * n * n * wl + 2 * n * wv)
 
 
 def dslash_flops(compressed=False):
@@ -56,7 +61,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precond", default="f32", choices=["f64", "f32"])
+    ap.add_argument("--precond", default="f32", choices=["f64", "f32", "f16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     return ap.parse_args()
@@ -98,7 +103,7 @@ def large_dslash(mgwd, torch):
     ctx = mgwd.MG(U, 0.1, [(4, 4, 4, 4)], [1], [v], setup_rounds=0)
     out = {}
     V = L[0] * L[1] * L[2] * L[3]
-    for prec in ("f64", "f32"):
+    for prec in ("f64", "f32", "f16"):
         ms = ctx.time_dslash(prec, 1, 30)
         gbs = dslash_bytes(prec) * V / (ms * 1e-3) / 1e9
         gbs_fmt = dslash_bytes(prec, compressed=True) * V / (ms * 1e-3) / 1e9

@@ -75,7 +75,8 @@ typedef struct {
   int coarse_maxiter;                /* coarsest CGNR cap (1000)             */
   int gcr_restart;                   /* flexible GCR restart length (8)      */
   int max_iter;                      /* outer iteration cap                  */
-  mg_prec_t precond_prec;            /* MG_F64, MG_F32 or MG_F16             */
+  mg_prec_t precond_prec;            /* MG_F64, MG_F32 or MG_F16 (FP16-stored
+                                        links, P and D_c; FP32 arithmetic)   */
   int max_rhs;                       /* largest nrhs passed to mg_solve      */
   int use_graph;                     /* 1: replay the coarsest-level CGNR
                                         iterations from captured hipGraphs  */
@@ -95,12 +96,13 @@ typedef struct {
   double t_setup_s, t_solve_s;  /* wall time of the last setup / solve       */
   /* Kernel timing (filled when mg_set_timing(ctx, 1) is on): summed device
    * time in ms, launch count and sites x right-hand sides processed, per
-   * kernel class: 0 = fine stencil FP64, 1 = fine stencil FP32,
-   * 2 = coarse stencil FP64, 3 = coarse stencil FP32 (coarsest level and
-   * intermediate levels together).                                         */
-  double kernel_ms[4];
-  int kernel_launches[4];
-  double kernel_sites[4];
+   * kernel class 2 p + k: p = 0 FP64, 1 FP32, 2 FP16-stored operators with
+   * FP32 arithmetic; k = 0 fine stencil, 1 coarse stencil (all coarse
+   * levels).  Launch counts include dispatches that returned early because
+   * their right-hand side had converged.                                   */
+  double kernel_ms[6];
+  int kernel_launches[6];
+  double kernel_sites[6];
 } mg_info_t;
 
 /* Fine Wilson operator out = D(U) in (Eq. 2) on nrhs canonical spinors.
@@ -150,6 +152,20 @@ int mg_prolong(mg_ctx_t *ctx, int level, const void *coarse, void *fine,
  * dagger != 0 applies D_c^dag = sigma_3 D_c sigma_3.  FP64.  Async.       */
 int coarse_apply(mg_ctx_t *ctx, int level, const void *in, void *out,
                  int nrhs, int dagger, hipStream_t stream);
+
+/* The operator of level `level` as the preconditioner applies it: level 0
+ * is the fine Wilson operator of Eq. 2 with the context's links (two-row
+ * compressed when they are SU(3)), level >= 1 the Galerkin coarse operator
+ * D_c = P^dag D P ("Formulating an algorithm").  prec selects the stored
+ * copies: MG_F64; MG_F32 (FP32 operators and arithmetic); MG_F16 (operators
+ * stored as binary16 complex, FP32 arithmetic), the mixed-precision scheme
+ * of "Numerical Results".  in/out are canonical DEVICE complex128 arrays of
+ * the level (layouts as mg_restrict), converted to and from the working
+ * precision on the device.  Builds the low-precision copies on first use.
+ * Async.  Errors: MG_EINVAL (NULL/aliased buffers, nrhs < 1), MG_ESHAPE
+ * (level out of range), MG_ENOTSUP (prec).                                  */
+int mg_apply_op(mg_ctx_t *ctx, int level, mg_prec_t prec, const void *in,
+                void *out, int nrhs, hipStream_t stream);
 
 /* Solve D x = b for nrhs canonical spinors (DEVICE complex128) with
  * flexible GCR(gcr_restart) preconditioned by one MG V-cycle (MR pre/post

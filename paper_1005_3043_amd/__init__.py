@@ -22,7 +22,7 @@ MAX_LEVELS = 3
 MAX_RHS = 16
 
 EXPORTED = ["wilson_apply", "mg_setup", "mg_set_precond_prec", "mg_set_timing", "mg_restrict",
-            "mg_prolong", "coarse_apply", "mg_solve", "mg_time_dslash", "mg_time_coarse",
+            "mg_prolong", "coarse_apply", "mg_apply_op", "mg_solve", "mg_time_dslash", "mg_time_coarse",
             "mg_destroy", "mg_last_error", "mg_export_maps", "mg_export_P",
             "mg_export_coarse_op", "mg_export_nullvecs", "mg_level_info"]
 
@@ -63,11 +63,11 @@ class Info(ctypes.Structure):
                 ("n_cgnr_iters", ctypes.c_int),
                 ("n_vcycles", ctypes.c_int),
                 ("t_setup_s", ctypes.c_double), ("t_solve_s", ctypes.c_double),
-                ("kernel_ms", ctypes.c_double * 4),
-                ("kernel_launches", ctypes.c_int * 4),
-                ("kernel_sites", ctypes.c_double * 4)]
+                ("kernel_ms", ctypes.c_double * 6),
+                ("kernel_launches", ctypes.c_int * 6),
+                ("kernel_sites", ctypes.c_double * 6)]
 
-    KERNELS = ("dslash_f64", "dslash_f32", "coarse_f64", "coarse_f32")
+    KERNELS = ("dslash_f64", "coarse_f64", "dslash_f32", "coarse_f32", "dslash_f16", "coarse_f16")
 
     def as_dict(self, nrhs=1):
         return dict(iters=list(self.iters[:nrhs]), rel_resid=list(self.rel_resid[:nrhs]),
@@ -97,6 +97,7 @@ def lib():
             "mg_restrict": [vp, ci, vp, vp, ci, vp],
             "mg_prolong": [vp, ci, vp, vp, ci, vp],
             "coarse_apply": [vp, ci, vp, vp, ci, ci, vp],
+            "mg_apply_op": [vp, ci, ci, vp, vp, ci, vp],
             "mg_solve": [vp, vp, vp, ci, cd, ctypes.POINTER(Info), vp],
             "mg_time_dslash": [vp, ci, ci, ci, ctypes.POINTER(cd), vp],
             "mg_time_coarse": [vp, ci, ci, ci, ci, ctypes.POINTER(cd), vp],
@@ -232,6 +233,15 @@ class MG:
         out = torch.empty_like(v)
         _check(lib().coarse_apply(self.ctx, level, _dev(v, "in"), _dev(out, "out"), nrhs, int(bool(dagger)),
                                   _stream()))
+        return out
+
+    def apply_op(self, level, v, prec="f64", nrhs=None):
+        """Level operator (fine Wilson D at level 0, D_c above) with the stored
+        copies of precision `prec`; canonical complex128 in and out."""
+        if nrhs is None:
+            nrhs = self._nvec(level, v)
+        out = torch.empty_like(v)
+        _check(lib().mg_apply_op(self.ctx, level, PREC[prec], _dev(v, "in"), _dev(out, "out"), nrhs, _stream()))
         return out
 
     def solve(self, b, tol=1e-10, nrhs=None, x=None):

@@ -54,8 +54,8 @@ int check_params(const mg_lattice_t *lat, const mg_params_t *p) {
     return bad(MG_EINVAL, "bad omega / coarse tolerance / coarse iteration cap");
   if (p->gcr_restart < 1 || p->gcr_restart > 64 || p->max_iter < 1) return bad(MG_EINVAL, "bad GCR parameters");
   if (p->max_rhs < 1 || p->max_rhs > MG_MAX_RHS) return bad(MG_EINVAL, "max_rhs out of range");
-  if (p->precond_prec != MG_F64 && p->precond_prec != MG_F32)
-    return bad(MG_ENOTSUP, "precond_prec must be MG_F64 or MG_F32");
+  if (p->precond_prec != MG_F64 && p->precond_prec != MG_F32 && p->precond_prec != MG_F16)
+    return bad(MG_ENOTSUP, "precond_prec must be MG_F64, MG_F32 or MG_F16");
   return MG_OK;
 }
 
@@ -150,7 +150,7 @@ extern "C" int mg_restrict(mg_ctx_t *ctx, int level, const void *fine, void *coa
   HIPK(a.alloc(ctx->lev[level].vsize() * nrhs));
   HIPK(b.alloc(ctx->lev[level + 1].vsize() * nrhs));
   HIPK(pack_level(ctx, level, fine, a.p, nrhs, st));
-  MG_TRY(transfer_restrict<double>(ctx, level, a.p, b.p, nrhs, st));
+  MG_TRY(transfer_restrict<PF64>(ctx, level, a.p, b.p, nrhs, st));
   HIPK(unpack_level(ctx, level + 1, b.p, coarse, nrhs, st));
   return MG_OK;
 }
@@ -164,7 +164,7 @@ extern "C" int mg_prolong(mg_ctx_t *ctx, int level, const void *coarse, void *fi
   HIPK(a.alloc(ctx->lev[level].vsize() * nrhs));
   HIPK(b.alloc(ctx->lev[level + 1].vsize() * nrhs));
   HIPK(pack_level(ctx, level + 1, coarse, b.p, nrhs, st));
-  MG_TRY(transfer_prolong<double>(ctx, level, b.p, a.p, nrhs, 0, st));
+  MG_TRY(transfer_prolong<PF64>(ctx, level, b.p, a.p, nrhs, 0, st));
   HIPK(unpack_level(ctx, level, a.p, fine, nrhs, st));
   return MG_OK;
 }
@@ -180,7 +180,48 @@ extern "C" int coarse_apply(mg_ctx_t *ctx, int level, const void *in, void *out,
   HIPK(a.alloc(L.vsize() * nrhs));
   HIPK(b.alloc(L.vsize() * nrhs));
   HIPK(pack_level(ctx, level, in, a.p, nrhs, st));
-  HIPK(coarse_apply_k<double>(L.g, L.n, L.L64, a.p, b.p, nrhs, dagger ? 1 : 0, nullptr, 1, nullptr, st));
+  HIPK((coarse_apply_k<double, double2>(L.g, L.n, L.L64, a.p, b.p, nrhs, dagger ? 1 : 0, nullptr, 1, nullptr, st)));
+  HIPK(unpack_level(ctx, level, b.p, out, nrhs, st));
+  return MG_OK;
+}
+
+namespace {
+template <typename P> int apply_op_t(mg_ctx *c, int level, const double2 *a, double2 *b, int nrhs, hipStream_t st) {
+  using R = typename P::R;
+  if constexpr (sizeof(R) == 8) {
+    return apply_A<P>(c, level, a, b, nrhs, DS_PLAIN, nullptr, st);
+  } else {
+    const size_t n = c->lev[level].vsize() * nrhs;
+    AsyncBuf<float2> x(st), y(st);
+    HIPK(x.alloc(n));
+    HIPK(y.alloc(n));
+    HIPK((convert<float, double>(x.p, a, n, st)));
+    MG_TRY(apply_A<P>(c, level, x.p, y.p, nrhs, DS_PLAIN, nullptr, st));
+    HIPK((convert<double, float>(b, y.p, n, st)));
+    return MG_OK;
+  }
+}
+}  // namespace
+
+extern "C" int mg_apply_op(mg_ctx_t *ctx, int level, mg_prec_t prec, const void *in, void *out, int nrhs,
+                           hipStream_t st) {
+  set_error("");
+  if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
+  MG_TRY(check_ctx_level(ctx, level, 0, ctx->nlev - 1));
+  if (!in || !out || in == out || nrhs < 1) return bad(MG_EINVAL, "mg_apply_op: bad buffers or nrhs");
+  if (prec != MG_F64 && prec != MG_F32 && prec != MG_F16)
+    return bad(MG_ENOTSUP, "mg_apply_op: prec must be MG_F64, MG_F32 or MG_F16");
+  MG_TRY(ensure_prec(ctx, prec, st));
+  const Level &L = ctx->lev[level];
+  AsyncBuf<double2> a(st), b(st);
+  HIPK(a.alloc(L.vsize() * nrhs));
+  HIPK(b.alloc(L.vsize() * nrhs));
+  HIPK(pack_level(ctx, level, in, a.p, nrhs, st));
+  int rc;
+  if (prec == MG_F64) rc = apply_op_t<PF64>(ctx, level, a.p, b.p, nrhs, st);
+  else if (prec == MG_F32) rc = apply_op_t<PF32>(ctx, level, a.p, b.p, nrhs, st);
+  else rc = apply_op_t<PF16>(ctx, level, a.p, b.p, nrhs, st);
+  MG_TRY(rc);
   HIPK(unpack_level(ctx, level, b.p, out, nrhs, st));
   return MG_OK;
 }
@@ -238,7 +279,7 @@ extern "C" int mg_solve(mg_ctx_t *ctx, const void *b, void *x, int nrhs, double 
     info->t_setup_s = c->t_setup;
     info->t_solve_s = t1 - t0;
     if (c->timing) {
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < 6; ++k) {
         info->kernel_ms[k] = c->tm[k].ms;
         info->kernel_launches[k] = (int)c->tm[k].launches;
         info->kernel_sites[k] = c->tm[k].sites;
@@ -248,47 +289,61 @@ extern "C" int mg_solve(mg_ctx_t *ctx, const void *b, void *x, int nrhs, double 
   return rc;
 }
 
+namespace {
+template <typename P> int time_dslash_t(mg_ctx *c, int nrhs, int reps, hipEvent_t e0, hipEvent_t e1, hipStream_t st) {
+  using R = typename P::R;
+  using S = typename P::S;
+  Level &L = c->lev[0];
+  const size_t n = L.vsize() * nrhs;
+  DevBuf<vec_t<P>> a, b;
+  MG_TRY(a.alloc(n));
+  MG_TRY(b.alloc(n));
+  if constexpr (sizeof(R) == 8) HIPK(copy<double>(a, L.P64, std::min(n, L.P64.n), st));
+  else HIPK((convert<float, double>(a, L.P64, std::min(n, L.P64.n), st)));
+  const S *U = links_of_level<P>(L);
+  for (int i = 0; i < 2; ++i)
+    HIPK((dslash<R, S>(L.g, U, L.nl, a, b, nullptr, 4.0 + c->mass, nrhs, DS_PLAIN, nullptr, st)));
+  HIPK(hipEventRecord(e0, st));
+  for (int i = 0; i < reps; ++i)
+    HIPK((dslash<R, S>(L.g, U, L.nl, a, b, nullptr, 4.0 + c->mass, nrhs, DS_PLAIN, nullptr, st)));
+  HIPK(hipEventRecord(e1, st));
+  HIPK(hipEventSynchronize(e1));
+  return MG_OK;
+}
+template <typename P>
+int time_coarse_t(mg_ctx *c, int level, int nrhs, int reps, hipEvent_t e0, hipEvent_t e1, hipStream_t st) {
+  using R = typename P::R;
+  using S = typename P::S;
+  Level &L = c->lev[level];
+  const size_t n = L.vsize() * nrhs;
+  DevBuf<vec_t<P>> a, b;
+  MG_TRY(a.alloc(n));
+  MG_TRY(b.alloc(n));
+  const S *Lop = cop_of_level<P>(L);
+  for (int i = 0; i < 2; ++i)
+    HIPK((coarse_apply_k<R, S>(L.g, L.n, Lop, a, b, nrhs, 0, nullptr, 1, nullptr, st)));
+  HIPK(hipEventRecord(e0, st));
+  for (int i = 0; i < reps; ++i)
+    HIPK((coarse_apply_k<R, S>(L.g, L.n, Lop, a, b, nrhs, 0, nullptr, 1, nullptr, st)));
+  HIPK(hipEventRecord(e1, st));
+  HIPK(hipEventSynchronize(e1));
+  return MG_OK;
+}
+}  // namespace
+
 extern "C" int mg_time_dslash(mg_ctx_t *ctx, mg_prec_t prec, int nrhs, int reps, double *avg_ms, hipStream_t st) {
   set_error("");
   if (!ctx || !avg_ms || nrhs < 1 || reps < 1) return bad(MG_EINVAL, "mg_time_dslash: bad arguments");
-  mg_ctx *c = ctx;
-  MG_TRY(ensure_prec(c, prec, st));
-  MG_TRY(ensure_scalars(c, part_need(c, nrhs)));
-  Level &L = c->lev[0];
-  const size_t n = L.vsize() * nrhs;
+  MG_TRY(ensure_prec(ctx, prec, st));
   hipEvent_t e0, e1;
   HIPK(hipEventCreate(&e0));
   HIPK(hipEventCreate(&e1));
-  int rc = MG_OK;
-  if (prec == MG_F64) {
-    DevBuf<double2> a, b;
-    MG_TRY(a.alloc(n));
-    MG_TRY(b.alloc(n));
-    HIPK(copy<double>(a, L.P64, std::min(n, L.P64.n), st));
-    for (int i = 0; i < 2; ++i)
-      HIPK(dslash<double>(L.g, L.links64(), L.nl, a, b, nullptr, 4.0 + c->mass, nrhs, DS_PLAIN, nullptr, st));
-    HIPK(hipEventRecord(e0, st));
-    for (int i = 0; i < reps; ++i)
-      HIPK(dslash<double>(L.g, L.links64(), L.nl, a, b, nullptr, 4.0 + c->mass, nrhs, DS_PLAIN, nullptr, st));
-    HIPK(hipEventRecord(e1, st));
-    HIPK(hipEventSynchronize(e1));
-  } else if (prec == MG_F32) {
-    DevBuf<float2> a, b;
-    MG_TRY(a.alloc(n));
-    MG_TRY(b.alloc(n));
-    HIPK(copy<float>(a, L.P32, std::min(n, L.P32.n), st));
-    for (int i = 0; i < 2; ++i)
-      HIPK(dslash<float>(L.g, L.U32, L.nl, a, b, nullptr, 4.0 + c->mass, nrhs, DS_PLAIN, nullptr, st));
-    HIPK(hipEventRecord(e0, st));
-    for (int i = 0; i < reps; ++i)
-      HIPK(dslash<float>(L.g, L.U32, L.nl, a, b, nullptr, 4.0 + c->mass, nrhs, DS_PLAIN, nullptr, st));
-    HIPK(hipEventRecord(e1, st));
-    HIPK(hipEventSynchronize(e1));
-  } else {
-    rc = bad(MG_ENOTSUP, "mg_time_dslash: precision not built");
-  }
+  int rc;
+  if (prec == MG_F64) rc = time_dslash_t<PF64>(ctx, nrhs, reps, e0, e1, st);
+  else if (prec == MG_F32) rc = time_dslash_t<PF32>(ctx, nrhs, reps, e0, e1, st);
+  else rc = time_dslash_t<PF16>(ctx, nrhs, reps, e0, e1, st);
   float ms = 0.f;
-  if (rc == MG_OK) HIPK(hipEventElapsedTime(&ms, e0, e1));
+  if (rc == MG_OK) rc = hip_rc(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *avg_ms = ms / reps;
@@ -300,41 +355,16 @@ extern "C" int mg_time_coarse(mg_ctx_t *ctx, int level, mg_prec_t prec, int nrhs
   set_error("");
   if (!ctx || !avg_ms || nrhs < 1 || reps < 1) return bad(MG_EINVAL, "mg_time_coarse: bad arguments");
   MG_TRY(check_ctx_level(ctx, level, 1, ctx->nlev - 1));
-  mg_ctx *c = ctx;
-  MG_TRY(ensure_prec(c, prec, st));
-  Level &L = c->lev[level];
-  const size_t n = L.vsize() * nrhs;
+  MG_TRY(ensure_prec(ctx, prec, st));
   hipEvent_t e0, e1;
   HIPK(hipEventCreate(&e0));
   HIPK(hipEventCreate(&e1));
-  int rc = MG_OK;
-  if (prec == MG_F64) {
-    DevBuf<double2> a, b;
-    MG_TRY(a.alloc(n));
-    MG_TRY(b.alloc(n));
-    HIPK(zero<double>(a, n, st));
-    for (int i = 0; i < 2; ++i) HIPK(coarse_apply_k<double>(L.g, L.n, L.L64, a, b, nrhs, 0, nullptr, 1, nullptr, st));
-    HIPK(hipEventRecord(e0, st));
-    for (int i = 0; i < reps; ++i)
-      HIPK(coarse_apply_k<double>(L.g, L.n, L.L64, a, b, nrhs, 0, nullptr, 1, nullptr, st));
-    HIPK(hipEventRecord(e1, st));
-    HIPK(hipEventSynchronize(e1));
-  } else if (prec == MG_F32) {
-    DevBuf<float2> a, b;
-    MG_TRY(a.alloc(n));
-    MG_TRY(b.alloc(n));
-    HIPK(zero<float>(a, n, st));
-    for (int i = 0; i < 2; ++i) HIPK(coarse_apply_k<float>(L.g, L.n, L.L32, a, b, nrhs, 0, nullptr, 1, nullptr, st));
-    HIPK(hipEventRecord(e0, st));
-    for (int i = 0; i < reps; ++i)
-      HIPK(coarse_apply_k<float>(L.g, L.n, L.L32, a, b, nrhs, 0, nullptr, 1, nullptr, st));
-    HIPK(hipEventRecord(e1, st));
-    HIPK(hipEventSynchronize(e1));
-  } else {
-    rc = bad(MG_ENOTSUP, "mg_time_coarse: precision not built");
-  }
+  int rc;
+  if (prec == MG_F64) rc = time_coarse_t<PF64>(ctx, level, nrhs, reps, e0, e1, st);
+  else if (prec == MG_F32) rc = time_coarse_t<PF32>(ctx, level, nrhs, reps, e0, e1, st);
+  else rc = time_coarse_t<PF16>(ctx, level, nrhs, reps, e0, e1, st);
   float ms = 0.f;
-  if (rc == MG_OK) HIPK(hipEventElapsedTime(&ms, e0, e1));
+  if (rc == MG_OK) rc = hip_rc(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *avg_ms = ms / reps;

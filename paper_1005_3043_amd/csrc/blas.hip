@@ -41,6 +41,18 @@ template <typename Rd, typename Rs> hipError_t convert(c_t<Rd> *y, const c_t<Rs>
   return hipGetLastError();
 }
 
+template <typename S> __global__ __launch_bounds__(256) void k_store_convert(S *y, const double2 *x, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = cvt<S>(x[i]);
+}
+template <typename S> hipError_t store_convert(S *y, const double2 *x, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_store_convert<S>, dim3(stream_grid(n)), dim3(256), 0, st, y, x, n);
+  return hipGetLastError();
+}
+template hipError_t store_convert<float2>(float2 *, const double2 *, size_t, hipStream_t);
+template hipError_t store_convert<chalf>(chalf *, const double2 *, size_t, hipStream_t);
+
 template hipError_t zero<double>(double2 *, size_t, hipStream_t);
 template hipError_t zero<float>(float2 *, size_t, hipStream_t);
 template hipError_t copy<double>(double2 *, const double2 *, size_t, hipStream_t);

@@ -22,9 +22,33 @@ namespace mg {
 
 constexpr int CO_CHUNK = 8;   // operator loads in flight per thread
 
-template <typename R> struct RowVec;
-template <> struct RowVec<double> { static constexpr int RW = 1; using V = double2; };
-template <> struct RowVec<float> { static constexpr int RW = 2; using V = float4; };
+// 16-byte (or 8-byte) load of RW consecutive operator entries in storage S.
+template <typename S, int RW> struct OpVec;
+template <> struct OpVec<double2, 1> {
+  using V = double2;
+  template <typename C> __device__ static void get(const V &v, C (&o)[1]) { o[0] = cvt<C>(v); }
+};
+template <> struct OpVec<float2, 2> {
+  using V = float4;
+  template <typename C> __device__ static void get(const V &v, C (&o)[2]) {
+    o[0] = mk<C>(v.x, v.y);
+    o[1] = mk<C>(v.z, v.w);
+  }
+};
+template <> struct OpVec<chalf, 2> {
+  using V = chalf2;
+  template <typename C> __device__ static void get(const V &v, C (&o)[2]) {
+    o[0] = cvt<C>(v.v[0]);
+    o[1] = cvt<C>(v.v[1]);
+  }
+};
+template <> struct OpVec<chalf, 4> {
+  using V = chalf4;
+  template <typename C> __device__ static void get(const V &v, C (&o)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) o[q] = cvt<C>(v.v[q]);
+  }
+};
 
 // Sum of np partials over the workgroup; result in every thread.
 __device__ __forceinline__ double block_allsum_partials(const double *__restrict__ p, int np, double *lds) {
@@ -41,14 +65,13 @@ __device__ __forceinline__ double block_allsum_partials(const double *__restrict
   return t;
 }
 
-template <typename R>
-__global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const c_t<R> *__restrict__ L,
+template <typename R, typename S, int RW>
+__global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restrict__ L,
                                                  const c_t<R> *__restrict__ in, c_t<R> *__restrict__ out,
                                                  int dagger, double *__restrict__ partials, int pw,
                                                  const int *__restrict__ done, CgCheck chk) {
   using C = c_t<R>;
-  constexpr int RW = RowVec<R>::RW;
-  using VT = typename RowVec<R>::V;
+  using VT = typename OpVec<S, RW>::V;
   __shared__ C vin[9 * COARSE_NMAX];
   __shared__ C red[512 * RW];
   __shared__ double wred[8 * 3];
@@ -118,13 +141,10 @@ __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const c_t<R> *__r
       const int p = base + q * G;
       if (p < nP) {
         const C x = vin[p];
-        const VT v = lv[q];
-        if constexpr (RW == 1) {
-          acc[0] = cfma(mk<C>(v.x, v.y), x, acc[0]);
-        } else {
-          acc[0] = cfma(mk<C>(v.x, v.y), x, acc[0]);
-          acc[RW - 1] = cfma(mk<C>(v.z, v.w), x, acc[RW - 1]);
-        }
+        C o[RW];
+        OpVec<S, RW>::get(lv[q], o);
+#pragma unroll
+        for (int t = 0; t < RW; ++t) acc[t] = cfma(o[t], x, acc[t]);
       }
     }
   }
@@ -175,20 +195,34 @@ int coarse_threads(int n, uint32_t V) {
   return (G * nr + 63) / 64 * 64;
 }
 
-template <typename R>
-hipError_t coarse_apply_k(const Geom &g, int n, const c_t<R> *L, const c_t<R> *in, c_t<R> *out, int nrhs,
-                          int dagger, double *partials, int pw, const int *done, hipStream_t st, const CgCheck *chk) {
+template <typename R, typename S>
+hipError_t coarse_apply_k(const Geom &g, int n, const S *L, const c_t<R> *in, c_t<R> *out, int nrhs, int dagger,
+                          double *partials, int pw, const int *done, hipStream_t st, const CgCheck *chk) {
   dim3 grid(g.V * coarse_split(n, g.V), nrhs);
+  dim3 block(coarse_threads(n, g.V));
   CgCheck c{};
   if (chk) c = *chk;
-  hipLaunchKernelGGL(k_coarse<R>, grid, dim3(coarse_threads(n, g.V)), 0, st, g, n, L, in, out, dagger, partials,
-                     pw, done, c);
+  if constexpr (sizeof(S) == 16) {
+    hipLaunchKernelGGL((k_coarse<R, S, 1>), grid, block, 0, st, g, n, L, in, out, dagger, partials, pw, done, c);
+  } else if constexpr (sizeof(S) == 8) {
+    hipLaunchKernelGGL((k_coarse<R, S, 2>), grid, block, 0, st, g, n, L, in, out, dagger, partials, pw, done, c);
+  } else {
+    // half storage: four rows per 16-byte load when the rows of a workgroup
+    // come in multiples of four, else two rows per 8-byte load
+    if ((n / coarse_split(n, g.V)) % 4 == 0)
+      hipLaunchKernelGGL((k_coarse<R, S, 4>), grid, block, 0, st, g, n, L, in, out, dagger, partials, pw, done, c);
+    else
+      hipLaunchKernelGGL((k_coarse<R, S, 2>), grid, block, 0, st, g, n, L, in, out, dagger, partials, pw, done, c);
+  }
   return hipGetLastError();
 }
 
-template hipError_t coarse_apply_k<double>(const Geom &, int, const double2 *, const double2 *, double2 *, int,
-                                           int, double *, int, const int *, hipStream_t, const CgCheck *);
-template hipError_t coarse_apply_k<float>(const Geom &, int, const float2 *, const float2 *, float2 *, int, int,
-                                          double *, int, const int *, hipStream_t, const CgCheck *);
+template hipError_t coarse_apply_k<double, double2>(const Geom &, int, const double2 *, const double2 *, double2 *,
+                                                    int, int, double *, int, const int *, hipStream_t,
+                                                    const CgCheck *);
+template hipError_t coarse_apply_k<float, float2>(const Geom &, int, const float2 *, const float2 *, float2 *, int,
+                                                  int, double *, int, const int *, hipStream_t, const CgCheck *);
+template hipError_t coarse_apply_k<float, chalf>(const Geom &, int, const chalf *, const float2 *, float2 *, int,
+                                                 int, double *, int, const int *, hipStream_t, const CgCheck *);
 
 }  // namespace mg

@@ -67,6 +67,20 @@ template <typename C> __host__ __device__ __forceinline__ C cfmac(C a, C b, C ac
   return acc;
 }
 template <typename C> __host__ __device__ __forceinline__ C cscale(C a, decltype(C::x) s) { return mk<C>(a.x * s, a.y * s); }
+
+// Complex number stored in IEEE half precision (operator storage of the
+// FP16 preconditioner; arithmetic is done after conversion to FP32).
+struct __align__(4) chalf { _Float16 x, y; };
+struct __align__(8) chalf2 { chalf v[2]; };
+struct __align__(16) chalf4 { chalf v[4]; };
+// Conversion between complex storage types (narrowing conversions round to
+// nearest even in one step).
+template <typename C, typename S> __host__ __device__ __forceinline__ C cvt(S v) {
+  C c;
+  c.x = static_cast<decltype(C::x)>(v.x);
+  c.y = static_cast<decltype(C::x)>(v.y);
+  return c;
+}
 // multiply by i^k (k = 0: 1, 1: i, 2: -1, 3: -i)
 template <int k, typename C> __host__ __device__ __forceinline__ C mul_ipow(C a) {
   if constexpr (k == 0) return a;

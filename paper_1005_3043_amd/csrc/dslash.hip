@@ -29,10 +29,10 @@ template <typename C> __host__ __device__ __forceinline__ void reconstruct_row2(
   u[8] = mk<C>(c.x, -c.y);
 }
 
-template <int NL, typename C>
-__host__ __device__ __forceinline__ void load_link_t(C (&u)[9], const C *__restrict__ U, int mu, uint32_t s) {
+template <int NL, typename C, typename S>
+__host__ __device__ __forceinline__ void load_link_t(C (&u)[9], const S *__restrict__ U, int mu, uint32_t s) {
 #pragma unroll
-  for (int e = 0; e < NL; ++e) u[e] = U[fidx(s, mu * NL + e, 4 * NL)];
+  for (int e = 0; e < NL; ++e) u[e] = cvt<C>(U[fidx(s, mu * NL + e, 4 * NL)]);
   if constexpr (NL == 6) reconstruct_row2(u);
 }
 
@@ -43,9 +43,9 @@ __host__ __device__ __forceinline__ void load_spinor_t(C (&psi)[12], const C *__
 }
 
 // Full stencil at one site: res = D psi at s, ctr = psi(s).
-template <int NL, typename C>
+template <int NL, typename C, typename S>
 __host__ __device__ __forceinline__ void dslash_site(C (&res)[12], C (&ctr)[12], const Geom &g, uint32_t s,
-                                                     const C *__restrict__ U, const C *__restrict__ in,
+                                                     const S *__restrict__ U, const C *__restrict__ in,
                                                      decltype(C::x) diag) {
   using R = decltype(C::x);
   const Coords k = decode(g, s);
@@ -87,8 +87,8 @@ template <typename R> constexpr int dslash_waves() {
   return sizeof(R) == 8 ? MG_DSLASH_WAVES_F64 : MG_DSLASH_WAVES_F32;
 }
 
-template <typename R, int MODE, int NL>
-__global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash(Geom g, const c_t<R> *__restrict__ U,
+template <typename R, int MODE, int NL, typename S>
+__global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash(Geom g, const S *__restrict__ U,
                                                 const c_t<R> *__restrict__ in, c_t<R> *__restrict__ out,
                                                 const c_t<R> *__restrict__ b, R diag,
                                                 double *__restrict__ partials) {
@@ -133,37 +133,39 @@ __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash(Geom g, const
 
 int dslash_blocks(const Geom &g) { return div_up(g.V, 256); }
 
-template <typename R, int NL>
-static hipError_t launch(const Geom &g, const c_t<R> *U, const c_t<R> *in, c_t<R> *out, const c_t<R> *b,
-                         double diag, int nrhs, DslashMode mode, double *partials, hipStream_t st) {
+template <typename R, int NL, typename S>
+static hipError_t launch(const Geom &g, const S *U, const c_t<R> *in, c_t<R> *out, const c_t<R> *b, double diag,
+                         int nrhs, DslashMode mode, double *partials, hipStream_t st) {
   dim3 grid(dslash_blocks(g), nrhs);
   switch (mode) {
     case DS_PLAIN:
-      hipLaunchKernelGGL((k_dslash<R, DS_PLAIN, NL>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag, partials);
+      hipLaunchKernelGGL((k_dslash<R, DS_PLAIN, NL, S>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag,
+                         partials);
       break;
     case DS_RESID:
-      hipLaunchKernelGGL((k_dslash<R, DS_RESID, NL>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag, partials);
+      hipLaunchKernelGGL((k_dslash<R, DS_RESID, NL, S>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag,
+                         partials);
       break;
     case DS_MR:
-      hipLaunchKernelGGL((k_dslash<R, DS_MR, NL>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag, partials);
+      hipLaunchKernelGGL((k_dslash<R, DS_MR, NL, S>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag, partials);
       break;
   }
   return hipGetLastError();
 }
 
-template <typename R>
-hipError_t dslash(const Geom &g, const c_t<R> *U, int nl, const c_t<R> *in, c_t<R> *out, const c_t<R> *b,
-                  double diag, int nrhs, DslashMode mode, double *partials, hipStream_t st) {
-  if (nl == 6) return launch<R, 6>(g, U, in, out, b, diag, nrhs, mode, partials, st);
-  return launch<R, 9>(g, U, in, out, b, diag, nrhs, mode, partials, st);
+template <typename R, typename S>
+hipError_t dslash(const Geom &g, const S *U, int nl, const c_t<R> *in, c_t<R> *out, const c_t<R> *b, double diag,
+                  int nrhs, DslashMode mode, double *partials, hipStream_t st) {
+  if (nl == 6) return launch<R, 6, S>(g, U, in, out, b, diag, nrhs, mode, partials, st);
+  return launch<R, 9, S>(g, U, in, out, b, diag, nrhs, mode, partials, st);
 }
 
 // ---------------------------------------------------------------- links
 // Copy of the first two rows of every link (NL = 6 layout), and the largest
 // deviation |row2 - conj(row0 x row1)| over all links (per-block maxima).
-template <typename R>
+template <typename S>
 __global__ __launch_bounds__(256) void k_compress_links(Geom g, const double2 *__restrict__ U,
-                                                        c_t<R> *__restrict__ Uc, double *__restrict__ blockmax) {
+                                                        S *__restrict__ Uc, double *__restrict__ blockmax) {
   __shared__ double lds[4];
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   double dev = 0.0;
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(256) void k_compress_links(Geom g, const double2 *_
       reconstruct_row2(w);
       for (int e = 6; e < 9; ++e) dev = fmax(dev, fabs(w[e].x - u[e].x) + fabs(w[e].y - u[e].y));
 #pragma unroll
-      for (int e = 0; e < 6; ++e) Uc[fidx(s, mu * 6 + e, 24)] = mk<c_t<R>>((R)u[e].x, (R)u[e].y);
+      for (int e = 0; e < 6; ++e) Uc[fidx(s, mu * 6 + e, 24)] = cvt<S>(u[e]);
     }
   }
 #pragma unroll
@@ -191,17 +193,20 @@ __global__ __launch_bounds__(256) void k_compress_links(Geom g, const double2 *_
   }
 }
 
-template <typename R>
-hipError_t compress_links(const Geom &g, const double2 *U, c_t<R> *Uc, double *blockmax, hipStream_t st) {
-  hipLaunchKernelGGL(k_compress_links<R>, dim3(div_up(g.V, 256)), dim3(256), 0, st, g, U, Uc, blockmax);
+template <typename S>
+hipError_t compress_links(const Geom &g, const double2 *U, S *Uc, double *blockmax, hipStream_t st) {
+  hipLaunchKernelGGL(k_compress_links<S>, dim3(div_up(g.V, 256)), dim3(256), 0, st, g, U, Uc, blockmax);
   return hipGetLastError();
 }
 
-template hipError_t dslash<double>(const Geom &, const double2 *, int, const double2 *, double2 *,
-                                   const double2 *, double, int, DslashMode, double *, hipStream_t);
-template hipError_t dslash<float>(const Geom &, const float2 *, int, const float2 *, float2 *, const float2 *,
-                                  double, int, DslashMode, double *, hipStream_t);
-template hipError_t compress_links<double>(const Geom &, const double2 *, double2 *, double *, hipStream_t);
-template hipError_t compress_links<float>(const Geom &, const double2 *, float2 *, double *, hipStream_t);
+template hipError_t dslash<double, double2>(const Geom &, const double2 *, int, const double2 *, double2 *,
+                                            const double2 *, double, int, DslashMode, double *, hipStream_t);
+template hipError_t dslash<float, float2>(const Geom &, const float2 *, int, const float2 *, float2 *,
+                                          const float2 *, double, int, DslashMode, double *, hipStream_t);
+template hipError_t dslash<float, chalf>(const Geom &, const chalf *, int, const float2 *, float2 *,
+                                         const float2 *, double, int, DslashMode, double *, hipStream_t);
+template hipError_t compress_links<double2>(const Geom &, const double2 *, double2 *, double *, hipStream_t);
+template hipError_t compress_links<float2>(const Geom &, const double2 *, float2 *, double *, hipStream_t);
+template hipError_t compress_links<chalf>(const Geom &, const double2 *, chalf *, double *, hipStream_t);
 
 }  // namespace mg

@@ -23,13 +23,15 @@ enum DslashMode { DS_PLAIN = 0, DS_RESID = 1, DS_MR = 2 };
 // out = diag*in - 1/2 hop(in)              (DS_PLAIN)
 // out = b - (diag*in - 1/2 hop(in))        (DS_RESID)
 // out = D in; partials[blk] += (<out,in>, ||out||^2)  (DS_MR, 3 doubles / block)
-template <typename R>
-hipError_t dslash(const Geom &g, const c_t<R> *U, int nl, const c_t<R> *in, c_t<R> *out, const c_t<R> *b,
-                  double diag, int nrhs, DslashMode mode, double *partials, hipStream_t st);
-// Uc = first two rows of every link of U (full FP64 links); blockmax[blk] =
-// max |row2 - conj(row0 x row1)| (dslash_blocks(g) entries).
-template <typename R>
-hipError_t compress_links(const Geom &g, const double2 *U, c_t<R> *Uc, double *blockmax, hipStream_t st);
+// R = arithmetic precision of vectors and accumulation, S = link storage
+// (double2, float2 or chalf).
+template <typename R, typename S>
+hipError_t dslash(const Geom &g, const S *U, int nl, const c_t<R> *in, c_t<R> *out, const c_t<R> *b, double diag,
+                  int nrhs, DslashMode mode, double *partials, hipStream_t st);
+// Uc = first two rows of every link of U (full FP64 links) in storage type S;
+// blockmax[blk] = max |row2 - conj(row0 x row1)| (dslash_blocks(g) entries).
+template <typename S>
+hipError_t compress_links(const Geom &g, const double2 *U, S *Uc, double *blockmax, hipStream_t st);
 int dslash_blocks(const Geom &g);  // number of partial slots per RHS of DS_MR
 
 // ---- blas.hip
@@ -37,6 +39,8 @@ template <typename R> hipError_t zero(c_t<R> *x, size_t n, hipStream_t st);
 template <typename R> hipError_t copy(c_t<R> *y, const c_t<R> *x, size_t n, hipStream_t st);
 template <typename Rd, typename Rs>
 hipError_t convert(c_t<Rd> *y, const c_t<Rs> *x, size_t n, hipStream_t st);
+// operator storage: y[i] = x[i] rounded to storage type S (nearest even)
+template <typename S> hipError_t store_convert(S *y, const double2 *x, size_t n, hipStream_t st);
 
 }  // namespace mg
 
@@ -68,29 +72,29 @@ struct CgCheck {
 // workgroup writes pw doubles at partials[(rhs*V*RS + wg)*pw] (RS =
 // coarse_split): pw = 1: ||out||^2; pw = 3: <out, in>, ||out||^2.  A right-hand side with done[rhs] != 0 is
 // skipped (done may be nullptr).
-template <typename R>
-hipError_t coarse_apply_k(const Geom &g, int n, const c_t<R> *L, const c_t<R> *in, c_t<R> *out, int nrhs,
-                          int dagger, double *partials, int pw, const int *done, hipStream_t st,
-                          const CgCheck *chk = nullptr);
+template <typename R, typename S>
+hipError_t coarse_apply_k(const Geom &g, int n, const S *L, const c_t<R> *in, c_t<R> *out, int nrhs, int dagger,
+                          double *partials, int pw, const int *done, hipStream_t st, const CgCheck *chk = nullptr);
 
 // ---- transfer.hip
 // Fine level: P = nv null-vector fields in the fine layout [nv][12 * Vpad].
 // g = geometry of the finer level (tile = aggregate), gc = geometry of the
 // coarser level (its own site-blocked order).
-template <typename R>
-hipError_t restrict_fine(const Geom &g, const Geom &gc, int nv, const c_t<R> *P, const c_t<R> *fine,
-                         c_t<R> *coarse, int nrhs, hipStream_t st);
+// S = storage type of P (double2, float2 or chalf); vectors in c_t<R>.
+template <typename R, typename S>
+hipError_t restrict_fine(const Geom &g, const Geom &gc, int nv, const S *P, const c_t<R> *fine, c_t<R> *coarse,
+                         int nrhs, hipStream_t st);
 // fine (+)= P coarse  (accumulate != 0: add into fine)
-template <typename R>
-hipError_t prolong_fine(const Geom &g, const Geom &gc, int nv, const c_t<R> *P, const c_t<R> *coarse,
-                        c_t<R> *fine, int nrhs, int accumulate, hipStream_t st);
+template <typename R, typename S>
+hipError_t prolong_fine(const Geom &g, const Geom &gc, int nv, const S *P, const c_t<R> *coarse, c_t<R> *fine,
+                        int nrhs, int accumulate, hipStream_t st);
 // Coarse level l -> l+1: P = nv vectors in coarse AoS layout [nv][V][n];
 // requires block volume * n <= 2048.
-template <typename R>
-hipError_t restrict_coarse(const Geom &g, const Geom &gc, int n, int nv, const c_t<R> *P, const c_t<R> *fine,
+template <typename R, typename S>
+hipError_t restrict_coarse(const Geom &g, const Geom &gc, int n, int nv, const S *P, const c_t<R> *fine,
                            c_t<R> *coarse, int nrhs, hipStream_t st);
-template <typename R>
-hipError_t prolong_coarse(const Geom &g, const Geom &gc, int n, int nv, const c_t<R> *P, const c_t<R> *coarse,
+template <typename R, typename S>
+hipError_t prolong_coarse(const Geom &g, const Geom &gc, int n, int nv, const S *P, const c_t<R> *coarse,
                           c_t<R> *fine, int nrhs, int accumulate, hipStream_t st);
 
 // ---- ortho.hip: in-place block orthonormalisation (MGS applied twice) per

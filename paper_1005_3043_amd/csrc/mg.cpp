@@ -53,30 +53,37 @@ size_t part_need(mg_ctx *c, int nrhs) {
   return m * (size_t)nrhs;
 }
 
-int ensure_prec(mg_ctx *c, mg_prec_t prec, hipStream_t st) {
-  if (prec == MG_F64) return MG_OK;
-  if (prec != MG_F32) {
-    set_error("preconditioner precision must be MG_F64 or MG_F32");
-    return MG_ENOTSUP;
-  }
+// Operator copies in storage type S (rounded to nearest even): links (two
+// rows or full, as the FP64 set-up chose), prolongators, coarse stencils.
+template <typename S>
+static int make_copies(mg_ctx *c, DevBuf<S> &U, DevBuf<S> Level::*Pm, DevBuf<S> Level::*Lm, hipStream_t st) {
   Level &L0 = c->lev[0];
-  if (!L0.U32.p) {
-    MG_TRY(L0.U32.alloc(4 * (size_t)L0.nl * L0.g.Vpad));
-    if (L0.nl == 6) HIPK(compress_links<float>(L0.g, L0.U64, L0.U32, c->part, st));
-    else HIPK((convert<float, double>(L0.U32, L0.U64, 36 * (size_t)L0.g.Vpad, st)));
+  if (!U.p) {
+    MG_TRY(U.alloc(4 * (size_t)L0.nl * L0.g.Vpad));
+    if (L0.nl == 6) HIPK(compress_links<S>(L0.g, L0.U64, U, c->part, st));
+    else HIPK(store_convert<S>(U, L0.U64, 36 * (size_t)L0.g.Vpad, st));
   }
   for (int l = 0; l < c->nlev; ++l) {
     Level &L = c->lev[l];
-    if (L.nv > 0 && !L.P32.p) {
-      MG_TRY(L.P32.alloc(L.P64.n));
-      HIPK((convert<float, double>(L.P32, L.P64, L.P64.n, st)));
+    DevBuf<S> &P = L.*Pm, &Lc = L.*Lm;
+    if (L.nv > 0 && !P.p) {
+      MG_TRY(P.alloc(L.P64.n));
+      HIPK(store_convert<S>(P, L.P64, L.P64.n, st));
     }
-    if (l > 0 && !L.L32.p) {
-      MG_TRY(L.L32.alloc(L.L64.n));
-      HIPK((convert<float, double>(L.L32, L.L64, L.L64.n, st)));
+    if (l > 0 && !Lc.p) {
+      MG_TRY(Lc.alloc(L.L64.n));
+      HIPK(store_convert<S>(Lc, L.L64, L.L64.n, st));
     }
   }
   return MG_OK;
+}
+
+int ensure_prec(mg_ctx *c, mg_prec_t prec, hipStream_t st) {
+  if (prec == MG_F64) return MG_OK;
+  if (prec == MG_F32) return make_copies<float2>(c, c->lev[0].U32, &Level::P32, &Level::L32, st);
+  if (prec == MG_F16) return make_copies<chalf>(c, c->lev[0].U16, &Level::P16, &Level::L16, st);
+  set_error("preconditioner precision must be MG_F64, MG_F32 or MG_F16");
+  return MG_ENOTSUP;
 }
 
 void clear_graphs(mg_ctx *c) {
@@ -112,15 +119,32 @@ template int ensure_work<double>(mg_ctx *, int);
 template int ensure_work<float>(mg_ctx *, int);
 
 // ------------------------------------------------------------ operators
-template <typename R> const c_t<R> *U_of(Level &L);
-template <> const double2 *U_of<double>(Level &L) { return L.links64(); }
-template <> const float2 *U_of<float>(Level &L) { return L.U32.p; }
-template <typename R> const c_t<R> *L_of(Level &L) { return PrecBufs<R>::pick(L.L64, L.L32).p; }
-template <typename R> const c_t<R> *P_of(Level &L) { return PrecBufs<R>::pick(L.P64, L.P32).p; }
+template <typename P> const typename P::S *links_of(Level &L);
+template <> const double2 *links_of<PF64>(Level &L) { return L.links64(); }
+template <> const float2 *links_of<PF32>(Level &L) { return L.U32.p; }
+template <> const chalf *links_of<PF16>(Level &L) { return L.U16.p; }
+template <typename P> const typename P::S *cop_of(Level &L);
+template <> const double2 *cop_of<PF64>(Level &L) { return L.L64.p; }
+template <> const float2 *cop_of<PF32>(Level &L) { return L.L32.p; }
+template <> const chalf *cop_of<PF16>(Level &L) { return L.L16.p; }
+template <typename P> const typename P::S *P_of(Level &L);
+template <> const double2 *P_of<PF64>(Level &L) { return L.P64.p; }
+template <> const float2 *P_of<PF32>(Level &L) { return L.P32.p; }
+template <> const chalf *P_of<PF16>(Level &L) { return L.P16.p; }
+
+template <typename P> const typename P::S *links_of_level(Level &L) { return links_of<P>(L); }
+template <typename P> const typename P::S *cop_of_level(Level &L) { return cop_of<P>(L); }
+template const double2 *links_of_level<PF64>(Level &);
+template const float2 *links_of_level<PF32>(Level &);
+template const chalf *links_of_level<PF16>(Level &);
+template const double2 *cop_of_level<PF64>(Level &);
+template const float2 *cop_of_level<PF32>(Level &);
+template const chalf *cop_of_level<PF16>(Level &);
 
 int np_mr(mg_ctx *c, int l) { return l == 0 ? dslash_blocks(c->lev[0].g) : (int)np_coarse(c->lev[l]); }
 
-template <typename R> constexpr int tclass(bool coarse) { return (coarse ? 2 : 0) + (sizeof(R) == 4 ? 1 : 0); }
+// kernel-class index of the timers: 2 * precision id + (coarse ? 1 : 0)
+template <typename P> constexpr int tclass(bool coarse) { return 2 * P::id + (coarse ? 1 : 0); }
 
 // Records a (start, stop) event pair around the launches in its scope when
 // timing is on.  Inside a stream capture the events are recorded as external
@@ -150,19 +174,21 @@ struct TimerScope {
 };
 
 // out = A_l in  (DS_MR: MR partials into c->part; DS_RESID: out = b - A_l in)
-template <typename R>
-int apply_A(mg_ctx *c, int l, const c_t<R> *in, c_t<R> *out, int nrhs, DslashMode mode, const c_t<R> *b,
+template <typename P>
+int apply_A(mg_ctx *c, int l, const vec_t<P> *in, vec_t<P> *out, int nrhs, DslashMode mode, const vec_t<P> *b,
             hipStream_t st) {
+  using R = typename P::R;
+  using S = typename P::S;
   Level &L = c->lev[l];
   if (l == 0) {
-    TimerScope ts(c, c->tm[tclass<R>(false)], st, (double)L.g.V * nrhs);
-    HIPK(dslash<R>(L.g, U_of<R>(L), L.nl, in, out, b, 4.0 + c->mass, nrhs, mode, c->part, st));
+    TimerScope ts(c, c->tm[tclass<P>(false)], st, (double)L.g.V * nrhs);
+    HIPK((dslash<R, S>(L.g, links_of<P>(L), L.nl, in, out, b, 4.0 + c->mass, nrhs, mode, c->part, st)));
     c->n_fine += nrhs;
   } else {
     {
-      TimerScope ts(c, c->tm[tclass<R>(true)], st, (double)L.g.V * nrhs);
-      HIPK(coarse_apply_k<R>(L.g, L.n, L_of<R>(L), in, out, nrhs, 0, mode == DS_MR ? c->part.p : nullptr, 3,
-                             nullptr, st));
+      TimerScope ts(c, c->tm[tclass<P>(true)], st, (double)L.g.V * nrhs);
+      HIPK((coarse_apply_k<R, S>(L.g, L.n, cop_of<P>(L), in, out, nrhs, 0, mode == DS_MR ? c->part.p : nullptr, 3,
+                                 nullptr, st)));
     }
     if (mode == DS_RESID) HIPK(resid_from<R>(out, b, L.vsize(), nrhs, st));
     c->n_coarse += nrhs;
@@ -170,44 +196,41 @@ int apply_A(mg_ctx *c, int l, const c_t<R> *in, c_t<R> *out, int nrhs, DslashMod
   return MG_OK;
 }
 
-template <typename R>
-int coarse_dag_or_not(mg_ctx *c, int l, const c_t<R> *in, c_t<R> *out, int nrhs, int dagger, double *part,
-                      const int *done, hipStream_t st) {
-  Level &L = c->lev[l];
-  TimerScope ts(c, c->tm[tclass<R>(true)], st, (double)L.g.V * nrhs);
-  HIPK(coarse_apply_k<R>(L.g, L.n, L_of<R>(L), in, out, nrhs, dagger, part, 1, done, st));
-  return MG_OK;
-}
-
 // MR smoothing of A_l x = r0 from x = 0 (accumulate: add into x): on return
 // r holds the recursively updated residual.
-template <typename R>
-int mr(mg_ctx *c, int l, c_t<R> *x, c_t<R> *r, c_t<R> *q, int steps, bool accumulate, int nrhs, hipStream_t st) {
+template <typename P>
+int mr(mg_ctx *c, int l, vec_t<P> *x, vec_t<P> *r, vec_t<P> *q, int steps, bool accumulate, int nrhs,
+       hipStream_t st) {
+  using R = typename P::R;
   Level &L = c->lev[l];
   const size_t n = L.vsize();
   if (steps == 0 && !accumulate) HIPK(zero<R>(x, n * nrhs, st));
   for (int k = 0; k < steps; ++k) {
-    MG_TRY(apply_A<R>(c, l, r, q, nrhs, DS_MR, nullptr, st));
+    MG_TRY(apply_A<P>(c, l, r, q, nrhs, DS_MR, nullptr, st));
     HIPK(mr_update<R>(x, r, q, n, nrhs, c->part, np_mr(c, l), c->p.omega, c->csc, (!accumulate && k == 0) ? 1 : 0,
                       st));
   }
   return MG_OK;
 }
 
-template <typename R>
-int transfer_restrict(mg_ctx *c, int l, const c_t<R> *fine, c_t<R> *coarse, int nrhs, hipStream_t st) {
+template <typename P>
+int transfer_restrict(mg_ctx *c, int l, const vec_t<P> *fine, vec_t<P> *coarse, int nrhs, hipStream_t st) {
+  using R = typename P::R;
+  using S = typename P::S;
   Level &L = c->lev[l], &Lc = c->lev[l + 1];
-  if (l == 0) HIPK(restrict_fine<R>(L.g, Lc.g, L.nv, P_of<R>(L), fine, coarse, nrhs, st));
-  else HIPK(restrict_coarse<R>(L.g, Lc.g, L.n, L.nv, P_of<R>(L), fine, coarse, nrhs, st));
+  if (l == 0) HIPK((restrict_fine<R, S>(L.g, Lc.g, L.nv, P_of<P>(L), fine, coarse, nrhs, st)));
+  else HIPK((restrict_coarse<R, S>(L.g, Lc.g, L.n, L.nv, P_of<P>(L), fine, coarse, nrhs, st)));
   return MG_OK;
 }
 
-template <typename R>
-int transfer_prolong(mg_ctx *c, int l, const c_t<R> *coarse, c_t<R> *fine, int nrhs, int accumulate,
+template <typename P>
+int transfer_prolong(mg_ctx *c, int l, const vec_t<P> *coarse, vec_t<P> *fine, int nrhs, int accumulate,
                      hipStream_t st) {
+  using R = typename P::R;
+  using S = typename P::S;
   Level &L = c->lev[l], &Lc = c->lev[l + 1];
-  if (l == 0) HIPK(prolong_fine<R>(L.g, Lc.g, L.nv, P_of<R>(L), coarse, fine, nrhs, accumulate, st));
-  else HIPK(prolong_coarse<R>(L.g, Lc.g, L.n, L.nv, P_of<R>(L), coarse, fine, nrhs, accumulate, st));
+  if (l == 0) HIPK((prolong_fine<R, S>(L.g, Lc.g, L.nv, P_of<P>(L), coarse, fine, nrhs, accumulate, st)));
+  else HIPK((prolong_coarse<R, S>(L.g, Lc.g, L.n, L.nv, P_of<P>(L), coarse, fine, nrhs, accumulate, st)));
   return MG_OK;
 }
 
@@ -234,19 +257,21 @@ static CgPtrs cg_ptrs(mg_ctx *c, int l, int nrhs) {
   return q;
 }
 
-template <typename R> int cgnr_chunk(mg_ctx *c, int l, c_t<R> *e, int nrhs, hipStream_t st, EventTimer &tm) {
+template <typename P> int cgnr_chunk(mg_ctx *c, int l, vec_t<P> *e, int nrhs, hipStream_t st, EventTimer &tm) {
+  using R = typename P::R;
+  using S = typename P::S;
   Work<R> &w = work<R>(c);
   Level &L = c->lev[l];
   const size_t n = L.vsize();
   const double sites = (double)L.g.V * nrhs;
   const int npc = (int)np_coarse(L);
   c_t<R> *r = w.cr, *z = w.cz, *p = w.cp, *ww = w.cw;
-  const c_t<R> *Lop = L_of<R>(L);
+  const S *Lop = cop_of<P>(L);
   const CgPtrs q = cg_ptrs(c, l, nrhs);
   for (int k = 0; k < CG_CHUNK; ++k) {
     {
       TimerScope ts(c, tm, st, sites);
-      HIPK(coarse_apply_k<R>(L.g, L.n, Lop, p, ww, nrhs, 0, q.pw, 1, c->done, st));
+      HIPK((coarse_apply_k<R, S>(L.g, L.n, Lop, p, ww, nrhs, 0, q.pw, 1, c->done, st)));
     }
     const int npr = cg2_update<R>(e, p, r, ww, n, nrhs, q.pw, q.pz[k & 1], npc, c->done, q.pr, st);
     HIPK(hipGetLastError());
@@ -260,15 +285,15 @@ template <typename R> int cgnr_chunk(mg_ctx *c, int l, c_t<R> *e, int nrhs, hipS
     chk.maxit = c->p.coarse_maxiter;
     {
       TimerScope ts(c, tm, st, sites);
-      HIPK(coarse_apply_k<R>(L.g, L.n, Lop, r, z, nrhs, 1, q.pz[(k + 1) & 1], 1, c->done, st, &chk));
+      HIPK((coarse_apply_k<R, S>(L.g, L.n, Lop, r, z, nrhs, 1, q.pz[(k + 1) & 1], 1, c->done, st, &chk)));
     }
     HIPK(cg2_p<R>(p, z, n, nrhs, q.pz[(k + 1) & 1], q.pz[k & 1], npc, c->done, st));
   }
   return MG_OK;
 }
 
-template <typename R> ChunkGraph *chunk_graph(mg_ctx *c, int l, c_t<R> *e, int nrhs, hipStream_t st) {
-  const int prec = sizeof(R) == 8 ? 0 : 1;
+template <typename P> ChunkGraph *chunk_graph(mg_ctx *c, int l, vec_t<P> *e, int nrhs, hipStream_t st) {
+  const int prec = P::id;
   for (ChunkGraph *g : c->graphs)
     if (g && g->level == l && g->prec == prec && g->nrhs == nrhs && g->timing == c->timing) return g;
   ChunkGraph *g = new ChunkGraph();
@@ -278,7 +303,7 @@ template <typename R> ChunkGraph *chunk_graph(mg_ctx *c, int l, c_t<R> *e, int n
   g->timing = c->timing;
   bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) == hipSuccess;
   if (ok) {
-    const int rc = cgnr_chunk<R>(c, l, e, nrhs, st, g->tm);
+    const int rc = cgnr_chunk<P>(c, l, e, nrhs, st, g->tm);
     ok = hipStreamEndCapture(st, &g->graph) == hipSuccess && rc == MG_OK;
   }
   if (ok) ok = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) == hipSuccess;
@@ -297,27 +322,29 @@ template <typename R> ChunkGraph *chunk_graph(mg_ctx *c, int l, c_t<R> *e, int n
   return g;
 }
 
-template <typename R> int cgnr(mg_ctx *c, int l, const c_t<R> *b, c_t<R> *e, int nrhs, hipStream_t st) {
+template <typename P> int cgnr(mg_ctx *c, int l, const vec_t<P> *b, vec_t<P> *e, int nrhs, hipStream_t st) {
+  using R = typename P::R;
+  using S = typename P::S;
   Work<R> &w = work<R>(c);
   Level &L = c->lev[l];
   const size_t n = L.vsize();
   const CgPtrs q = cg_ptrs(c, l, nrhs);
-  EventTimer &tm = c->tm[tclass<R>(true)];
+  EventTimer &tm = c->tm[tclass<P>(true)];
   HIPK(zero<R>(e, n * nrhs, st));
   HIPK(copy<R>(w.cr, b, n * nrhs, st));
   const int npb = norm2_partials<R>(b, n, nrhs, q.pb, st);
   HIPK(cg2_init(q.pb, npb, nrhs, c->cg, c->done, c->it, c->p.coarse_tol, st));
   {
     TimerScope ts(c, tm, st, (double)L.g.V * nrhs);
-    HIPK(coarse_apply_k<R>(L.g, L.n, L_of<R>(L), w.cr, w.cz, nrhs, 1, q.pz[0], 1, c->done, st));
+    HIPK((coarse_apply_k<R, S>(L.g, L.n, cop_of<P>(L), w.cr, w.cz, nrhs, 1, q.pz[0], 1, c->done, st)));
   }
   HIPK(copy<R>(w.cp, w.cz, n * nrhs, st));
-  ChunkGraph *gph = c->use_graph ? chunk_graph<R>(c, l, e, nrhs, st) : nullptr;
+  ChunkGraph *gph = c->use_graph ? chunk_graph<P>(c, l, e, nrhs, st) : nullptr;
   const int nchunks = (c->p.coarse_maxiter + CG_CHUNK - 1) / CG_CHUNK;
   const bool pipeline = !c->timing;
   for (int ch = 0; ch < nchunks; ++ch) {
     if (gph) HIPK(hipGraphLaunch(gph->exec, st));
-    else MG_TRY(cgnr_chunk<R>(c, l, e, nrhs, st, tm));
+    else MG_TRY(cgnr_chunk<P>(c, l, e, nrhs, st, tm));
     int *hd = c->h_done + (size_t)(ch & 1) * MG_MAX_RHS;
     HIPK(hipMemcpyAsync(hd, c->done, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
     HIPK(hipEventRecord(c->ev_chunk[ch & 1], st));
@@ -341,31 +368,33 @@ template <typename R> int cgnr(mg_ctx *c, int l, const c_t<R> *b, c_t<R> *e, int
 }
 
 // One V-cycle K_l(rin) -> x (levels l..coarsest).
-template <typename R> int vcycle(mg_ctx *c, int l, const c_t<R> *rin, c_t<R> *x, int nrhs, hipStream_t st) {
-  if (l == c->nlev - 1) return cgnr<R>(c, l, rin, x, nrhs, st);
+template <typename P> int vcycle(mg_ctx *c, int l, const vec_t<P> *rin, vec_t<P> *x, int nrhs, hipStream_t st) {
+  using R = typename P::R;
+  if (l == c->nlev - 1) return cgnr<P>(c, l, rin, x, nrhs, st);
   Work<R> &w = work<R>(c);
   Level &L = c->lev[l];
   const size_t n = L.vsize();
-  c_t<R> *r = w.r[l], *q = w.q[l];
+  vec_t<P> *r = w.r[l], *q = w.q[l];
   HIPK(copy<R>(r, rin, n * nrhs, st));
-  MG_TRY(mr<R>(c, l, x, r, q, c->p.pre, false, nrhs, st));
-  MG_TRY(transfer_restrict<R>(c, l, r, w.rin[l + 1], nrhs, st));
-  MG_TRY(vcycle<R>(c, l + 1, w.rin[l + 1], w.x[l + 1], nrhs, st));
-  MG_TRY(transfer_prolong<R>(c, l, w.x[l + 1], x, nrhs, 1, st));
-  MG_TRY(apply_A<R>(c, l, x, r, nrhs, DS_RESID, rin, st));
-  MG_TRY(mr<R>(c, l, x, r, q, c->p.post, true, nrhs, st));
+  MG_TRY(mr<P>(c, l, x, r, q, c->p.pre, false, nrhs, st));
+  MG_TRY(transfer_restrict<P>(c, l, r, w.rin[l + 1], nrhs, st));
+  MG_TRY(vcycle<P>(c, l + 1, w.rin[l + 1], w.x[l + 1], nrhs, st));
+  MG_TRY(transfer_prolong<P>(c, l, w.x[l + 1], x, nrhs, 1, st));
+  MG_TRY(apply_A<P>(c, l, x, r, nrhs, DS_RESID, rin, st));
+  MG_TRY(mr<P>(c, l, x, r, q, c->p.post, true, nrhs, st));
   return MG_OK;
 }
 
 // z = K(r) in the context's preconditioner precision (FP64 in and out).
 int precondition(mg_ctx *c, const double2 *r, double2 *z, int nrhs, hipStream_t st) {
   c->n_vcyc += nrhs;
-  if (c->prec == MG_F64) return vcycle<double>(c, 0, r, z, nrhs, st);
+  if (c->prec == MG_F64) return vcycle<PF64>(c, 0, r, z, nrhs, st);
   Work<float> &w = c->w32;
   const size_t n = c->lev[0].vsize() * nrhs;
   float2 *rin = w.rin[0], *x = w.x[0];
   HIPK((convert<float, double>(rin, r, n, st)));
-  MG_TRY(vcycle<float>(c, 0, rin, x, nrhs, st));
+  if (c->prec == MG_F16) MG_TRY(vcycle<PF16>(c, 0, rin, x, nrhs, st));
+  else MG_TRY(vcycle<PF32>(c, 0, rin, x, nrhs, st));
   HIPK((convert<double, float>(z, x, n, st)));
   return MG_OK;
 }
@@ -409,8 +438,8 @@ int fgcr(mg_ctx *c, const double2 *b, double2 *x, int nrhs, double tol, int *ite
       MG_TRY(precondition(c, r, Zj, nrhs, st));
       {
         TimerScope ts(c, c->tm[0], st, (double)L0.g.V * nrhs);
-        HIPK(dslash<double>(L0.g, L0.links64(), L0.nl, Zj, Wj, nullptr, 4.0 + c->mass, nrhs, DS_PLAIN, nullptr,
-                            st));
+        HIPK((dslash<double, double2>(L0.g, L0.links64(), L0.nl, Zj, Wj, nullptr, 4.0 + c->mass, nrhs, DS_PLAIN,
+                                      nullptr, st)));
       }
       c->n_fine += nrhs;
       for (int i = 0; i < j; ++i) {
@@ -446,7 +475,8 @@ int fgcr(mg_ctx *c, const double2 *b, double2 *x, int nrhs, double tol, int *ite
     // true residual r = b - D x
     {
       TimerScope ts(c, c->tm[0], st, (double)L0.g.V * nrhs);
-      HIPK(dslash<double>(L0.g, L0.links64(), L0.nl, x, r, b, 4.0 + c->mass, nrhs, DS_RESID, nullptr, st));
+      HIPK((dslash<double, double2>(L0.g, L0.links64(), L0.nl, x, r, b, 4.0 + c->mass, nrhs, DS_RESID, nullptr,
+                                    st)));
     }
     c->n_fine += nrhs;
     HIPK(norm2<double>(r, n, nrhs, c->part, rr, st));
@@ -479,8 +509,8 @@ int relax(mg_ctx *c, int l, double2 *V, int nv, hipStream_t st) {
   MG_TRY(r.alloc(n * nv));
   MG_TRY(q.alloc(n * nv));
   for (int round = 0; round < c->p.setup_rounds; ++round) {
-    MG_TRY(apply_A<double>(c, l, V, r, nv, DS_PLAIN, nullptr, st));
-    MG_TRY(mr<double>(c, l, x, r, q, c->p.setup_mr_steps, false, nv, st));
+    MG_TRY(apply_A<PF64>(c, l, V, r, nv, DS_PLAIN, nullptr, st));
+    MG_TRY(mr<PF64>(c, l, x, r, q, c->p.setup_mr_steps, false, nv, st));
     HIPK(sub_inplace<double>(V, x, n, nv, st));
     HIPK(norm2<double>(V, n, nv, c->part, c->dsc, st));
     HIPK(scale_rsqrt<double>(V, n, nv, c->dsc, st));
@@ -519,7 +549,7 @@ int setup(mg_ctx *c, const void *U, hipStream_t st) {
   MG_TRY(L0.U64c.alloc(24 * (size_t)L0.g.Vpad));
   {
     const int nb = dslash_blocks(L0.g);
-    HIPK(compress_links<double>(L0.g, L0.U64, L0.U64c, c->part, st));
+    HIPK(compress_links<double2>(L0.g, L0.U64, L0.U64c, c->part, st));
     std::vector<double> bm(nb);
     HIPK(hipMemcpyAsync(bm.data(), c->part, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
     HIPK(hipStreamSynchronize(st));
@@ -559,13 +589,15 @@ int setup(mg_ctx *c, const void *U, hipStream_t st) {
   return MG_OK;
 }
 
-#define INST(R)                                                                                              \
-  template int vcycle<R>(mg_ctx *, int, const c_t<R> *, c_t<R> *, int, hipStream_t);                         \
-  template int apply_A<R>(mg_ctx *, int, const c_t<R> *, c_t<R> *, int, DslashMode, const c_t<R> *, hipStream_t); \
-  template int transfer_restrict<R>(mg_ctx *, int, const c_t<R> *, c_t<R> *, int, hipStream_t);              \
-  template int transfer_prolong<R>(mg_ctx *, int, const c_t<R> *, c_t<R> *, int, int, hipStream_t);
-INST(double)
-INST(float)
+#define INST(P)                                                                                               \
+  template int vcycle<P>(mg_ctx *, int, const vec_t<P> *, vec_t<P> *, int, hipStream_t);                        \
+  template int apply_A<P>(mg_ctx *, int, const vec_t<P> *, vec_t<P> *, int, DslashMode, const vec_t<P> *,       \
+                          hipStream_t);                                                                          \
+  template int transfer_restrict<P>(mg_ctx *, int, const vec_t<P> *, vec_t<P> *, int, hipStream_t);             \
+  template int transfer_prolong<P>(mg_ctx *, int, const vec_t<P> *, vec_t<P> *, int, int, hipStream_t);
+INST(PF64)
+INST(PF32)
+INST(PF16)
 #undef INST
 
 }  // namespace mg

@@ -84,13 +84,12 @@ template <typename T> struct DevBuf {
   operator T *() const { return p; }
 };
 
-template <typename R> struct PrecBufs;
-template <> struct PrecBufs<double> {
-  static DevBuf<double2> &pick(DevBuf<double2> &a, DevBuf<float2> &) { return a; }
-};
-template <> struct PrecBufs<float> {
-  static DevBuf<float2> &pick(DevBuf<double2> &, DevBuf<float2> &b) { return b; }
-};
+// Preconditioner precisions: R = arithmetic of vectors and accumulation,
+// S = storage of the operators (links, prolongator, coarse stencil).
+struct PF64 { using R = double; using S = double2; static constexpr int id = 0; };
+struct PF32 { using R = float; using S = float2; static constexpr int id = 1; };
+struct PF16 { using R = float; using S = chalf; static constexpr int id = 2; };
+template <typename P> using vec_t = c_t<typename P::R>;
 
 struct Level {
   Geom g;            // this level's lattice; tile = aggregate shape to the next level
@@ -101,8 +100,9 @@ struct Level {
   DevBuf<double2> U64;   // fine links, full, FP64 [36 components]
   DevBuf<double2> U64c;  // fine links, two rows, FP64 [24 components] (nl = 6)
   DevBuf<float2> U32;    // fine links in FP32, nl entries per direction
-  DevBuf<double2> L64;  DevBuf<float2> L32;   // coarse stencil [V][9][n][n]
-  DevBuf<double2> P64;  DevBuf<float2> P32;   // prolongator to next level
+  DevBuf<chalf> U16;     // fine links in FP16, nl entries per direction
+  DevBuf<double2> L64;  DevBuf<float2> L32;  DevBuf<chalf> L16;  // coarse stencil [V][9][n][n]
+  DevBuf<double2> P64;  DevBuf<float2> P32;  DevBuf<chalf> P16;  // prolongator to next level
   DevBuf<double2> NV;                         // relaxed candidates before QR
   // complex entries per vector
   size_t vsize() const { return (size_t)(fine ? g.Vpad : g.V) * n; }
@@ -209,6 +209,6 @@ struct mg_ctx {
   int gcr_rhs = 0;
   // statistics
   long n_fine = 0, n_coarse = 0, n_cgnr = 0, n_vcyc = 0;
-  mg::EventTimer tm[4];  // fine FP64, fine FP32, coarse FP64, coarse FP32
+  mg::EventTimer tm[6];  // (fine, coarse) x (FP64, FP32, FP16 storage)
   double t_setup = 0.0;
 };

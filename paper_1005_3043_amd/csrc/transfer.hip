@@ -22,8 +22,8 @@ __device__ __forceinline__ uint32_t coarse_index(const Geom &g, const Geom &gc, 
 }
 
 // ------------------------------------------------------------------ fine
-template <typename R>
-__global__ __launch_bounds__(256) void k_restrict_fine(Geom g, Geom gc, int nv, const c_t<R> *__restrict__ P,
+template <typename R, typename S>
+__global__ __launch_bounds__(256) void k_restrict_fine(Geom g, Geom gc, int nv, const S *__restrict__ P,
                                                        const c_t<R> *__restrict__ fine, c_t<R> *__restrict__ coarse) {
   using C = c_t<R>;
   __shared__ double2 part[4][2 * COARSE_NMAX];
@@ -41,13 +41,13 @@ __global__ __launch_bounds__(256) void k_restrict_fine(Geom g, Geom gc, int nv, 
 #pragma unroll
     for (int c = 0; c < 12; ++c) r[c] = act ? fine[fidx(s, c, 12)] : mk<C>(0, 0);
     for (int kk = 0; kk < nv; ++kk) {
-      const C *Pk = P + (size_t)kk * 12 * V;
+      const S *Pk = P + (size_t)kk * 12 * V;
       C d0 = mk<C>(0, 0), d1 = mk<C>(0, 0);
       if (act) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) d0 = cfmac(Pk[fidx(s, c, 12)], r[c], d0);
+        for (int c = 0; c < 6; ++c) d0 = cfmac(cvt<C>(Pk[fidx(s, c, 12)]), r[c], d0);
 #pragma unroll
-        for (int c = 6; c < 12; ++c) d1 = cfmac(Pk[fidx(s, c, 12)], r[c], d1);
+        for (int c = 6; c < 12; ++c) d1 = cfmac(cvt<C>(Pk[fidx(s, c, 12)]), r[c], d1);
       }
       double a0 = wave_sum((double)d0.x), b0 = wave_sum((double)d0.y);
       double a1 = wave_sum((double)d1.x), b1 = wave_sum((double)d1.y);
@@ -75,8 +75,8 @@ __global__ __launch_bounds__(256) void k_restrict_fine(Geom g, Geom gc, int nv, 
   }
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_prolong_fine(Geom g, Geom gc, int nv, const c_t<R> *__restrict__ P,
+template <typename R, typename S>
+__global__ __launch_bounds__(256) void k_prolong_fine(Geom g, Geom gc, int nv, const S *__restrict__ P,
                                                       const c_t<R> *__restrict__ coarse, c_t<R> *__restrict__ fine,
                                                       int accumulate) {
   using C = c_t<R>;
@@ -90,12 +90,12 @@ __global__ __launch_bounds__(256) void k_prolong_fine(Geom g, Geom gc, int nv, c
 #pragma unroll
   for (int c = 0; c < 12; ++c) acc[c] = mk<C>(0, 0);
   for (int kk = 0; kk < nv; ++kk) {
-    const C *Pk = P + (size_t)kk * 12 * V;
+    const S *Pk = P + (size_t)kk * 12 * V;
     const C e0 = ec[kk], e1 = ec[nv + kk];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) acc[c] = cfma(Pk[fidx(s, c, 12)], e0, acc[c]);
+    for (int c = 0; c < 6; ++c) acc[c] = cfma(cvt<C>(Pk[fidx(s, c, 12)]), e0, acc[c]);
 #pragma unroll
-    for (int c = 6; c < 12; ++c) acc[c] = cfma(Pk[fidx(s, c, 12)], e1, acc[c]);
+    for (int c = 6; c < 12; ++c) acc[c] = cfma(cvt<C>(Pk[fidx(s, c, 12)]), e1, acc[c]);
   }
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
@@ -105,19 +105,19 @@ __global__ __launch_bounds__(256) void k_prolong_fine(Geom g, Geom gc, int nv, c
   }
 }
 
-template <typename R>
-hipError_t restrict_fine(const Geom &g, const Geom &gc, int nv, const c_t<R> *P, const c_t<R> *fine,
-                         c_t<R> *coarse, int nrhs, hipStream_t st) {
+template <typename R, typename S>
+hipError_t restrict_fine(const Geom &g, const Geom &gc, int nv, const S *P, const c_t<R> *fine, c_t<R> *coarse,
+                         int nrhs, hipStream_t st) {
   const int th = g.vb >= 256 ? 256 : (int)((g.vb + 63) / 64 * 64);
-  hipLaunchKernelGGL(k_restrict_fine<R>, dim3(g.Vc, nrhs), dim3(th), 0, st, g, gc, nv, P, fine, coarse);
+  hipLaunchKernelGGL((k_restrict_fine<R, S>), dim3(g.Vc, nrhs), dim3(th), 0, st, g, gc, nv, P, fine, coarse);
   return hipGetLastError();
 }
 
-template <typename R>
-hipError_t prolong_fine(const Geom &g, const Geom &gc, int nv, const c_t<R> *P, const c_t<R> *coarse,
-                        c_t<R> *fine, int nrhs, int accumulate, hipStream_t st) {
-  hipLaunchKernelGGL(k_prolong_fine<R>, dim3(div_up(g.V, 256), nrhs), dim3(256), 0, st, g, gc, nv, P, coarse, fine,
-                     accumulate);
+template <typename R, typename S>
+hipError_t prolong_fine(const Geom &g, const Geom &gc, int nv, const S *P, const c_t<R> *coarse, c_t<R> *fine,
+                        int nrhs, int accumulate, hipStream_t st) {
+  hipLaunchKernelGGL((k_prolong_fine<R, S>), dim3(div_up(g.V, 256), nrhs), dim3(256), 0, st, g, gc, nv, P, coarse,
+                     fine, accumulate);
   return hipGetLastError();
 }
 
@@ -126,9 +126,9 @@ hipError_t prolong_fine(const Geom &g, const Geom &gc, int nv, const c_t<R> *P, 
 // contiguous in the site-major layout.  Chirality of j: j >= n/2.
 constexpr int RC_EMAX = 8;  // elements per thread (block volume * n <= 2048)
 
-template <typename R>
+template <typename R, typename S>
 __global__ __launch_bounds__(256) void k_restrict_coarse(Geom g, Geom gc, int n, int nv,
-                                                         const c_t<R> *__restrict__ P, const c_t<R> *__restrict__ fine,
+                                                         const S *__restrict__ P, const c_t<R> *__restrict__ fine,
                                                          c_t<R> *__restrict__ coarse) {
   using C = c_t<R>;
   __shared__ double2 part[4][2 * COARSE_NMAX];
@@ -146,15 +146,15 @@ __global__ __launch_bounds__(256) void k_restrict_coarse(Geom g, Geom gc, int n,
   }
   const int half = n >> 1;
   for (int kk = 0; kk < nv; ++kk) {
-    const C *Pk = P + (size_t)kk * V * n + base;
+    const S *Pk = P + (size_t)kk * V * n + base;
     C d0 = mk<C>(0, 0), d1 = mk<C>(0, 0);
 #pragma unroll
     for (int q = 0; q < RC_EMAX; ++q) {
       const int e = tid + q * (int)blockDim.x;
       if (e < ne) {
         const int j = e % n;
-        if (j < half) d0 = cfmac(Pk[e], r[q], d0);
-        else d1 = cfmac(Pk[e], r[q], d1);
+        if (j < half) d0 = cfmac(cvt<C>(Pk[e]), r[q], d0);
+        else d1 = cfmac(cvt<C>(Pk[e]), r[q], d1);
       }
     }
     double a0 = wave_sum((double)d0.x), b0 = wave_sum((double)d0.y);
@@ -179,8 +179,8 @@ __global__ __launch_bounds__(256) void k_restrict_coarse(Geom g, Geom gc, int n,
   }
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_prolong_coarse(Geom g, Geom gc, int n, int nv, const c_t<R> *__restrict__ P,
+template <typename R, typename S>
+__global__ __launch_bounds__(256) void k_prolong_coarse(Geom g, Geom gc, int n, int nv, const S *__restrict__ P,
                                                         const c_t<R> *__restrict__ coarse, c_t<R> *__restrict__ fine,
                                                         int accumulate) {
   using C = c_t<R>;
@@ -193,37 +193,38 @@ __global__ __launch_bounds__(256) void k_prolong_coarse(Geom g, Geom gc, int n, 
   const uint32_t ic = coarse_index(g, gc, s);
   const C *ec = coarse + ((size_t)blockIdx.y * gc.V + ic) * (2 * nv) + (j < (n >> 1) ? 0 : nv);
   C acc = mk<C>(0, 0);
-  for (int kk = 0; kk < nv; ++kk) acc = cfma(P[(size_t)kk * V * n + e], ec[kk], acc);
+  for (int kk = 0; kk < nv; ++kk) acc = cfma(cvt<C>(P[(size_t)kk * V * n + e]), ec[kk], acc);
   if (accumulate) acc = cadd(fine[e], acc);
   fine[e] = acc;
 }
 
-template <typename R>
-hipError_t restrict_coarse(const Geom &g, const Geom &gc, int n, int nv, const c_t<R> *P, const c_t<R> *fine,
+template <typename R, typename S>
+hipError_t restrict_coarse(const Geom &g, const Geom &gc, int n, int nv, const S *P, const c_t<R> *fine,
                            c_t<R> *coarse, int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL(k_restrict_coarse<R>, dim3(g.Vc, nrhs), dim3(256), 0, st, g, gc, n, nv, P, fine, coarse);
+  hipLaunchKernelGGL((k_restrict_coarse<R, S>), dim3(g.Vc, nrhs), dim3(256), 0, st, g, gc, n, nv, P, fine, coarse);
   return hipGetLastError();
 }
 
-template <typename R>
-hipError_t prolong_coarse(const Geom &g, const Geom &gc, int n, int nv, const c_t<R> *P, const c_t<R> *coarse,
+template <typename R, typename S>
+hipError_t prolong_coarse(const Geom &g, const Geom &gc, int n, int nv, const S *P, const c_t<R> *coarse,
                           c_t<R> *fine, int nrhs, int accumulate, hipStream_t st) {
-  hipLaunchKernelGGL(k_prolong_coarse<R>, dim3(div_up((long)g.V * n, 256), nrhs), dim3(256), 0, st, g, gc, n, nv,
-                     P, coarse, fine, accumulate);
+  hipLaunchKernelGGL((k_prolong_coarse<R, S>), dim3(div_up((long)g.V * n, 256), nrhs), dim3(256), 0, st, g, gc, n,
+                     nv, P, coarse, fine, accumulate);
   return hipGetLastError();
 }
 
-#define INST(R)                                                                                                   \
-  template hipError_t restrict_fine<R>(const Geom &, const Geom &, int, const c_t<R> *, const c_t<R> *, c_t<R> *,  \
-                                       int, hipStream_t);                                                          \
-  template hipError_t prolong_fine<R>(const Geom &, const Geom &, int, const c_t<R> *, const c_t<R> *, c_t<R> *,   \
-                                      int, int, hipStream_t);                                                      \
-  template hipError_t restrict_coarse<R>(const Geom &, const Geom &, int, int, const c_t<R> *, const c_t<R> *,     \
-                                         c_t<R> *, int, hipStream_t);                                              \
-  template hipError_t prolong_coarse<R>(const Geom &, const Geom &, int, int, const c_t<R> *, const c_t<R> *,      \
-                                        c_t<R> *, int, int, hipStream_t);
-INST(double)
-INST(float)
+#define INST(R, S)                                                                                                \
+  template hipError_t restrict_fine<R, S>(const Geom &, const Geom &, int, const S *, const c_t<R> *, c_t<R> *, int,  \
+                                          hipStream_t);                                                             \
+  template hipError_t prolong_fine<R, S>(const Geom &, const Geom &, int, const S *, const c_t<R> *, c_t<R> *, int,   \
+                                         int, hipStream_t);                                                         \
+  template hipError_t restrict_coarse<R, S>(const Geom &, const Geom &, int, int, const S *, const c_t<R> *,          \
+                                            c_t<R> *, int, hipStream_t);                                            \
+  template hipError_t prolong_coarse<R, S>(const Geom &, const Geom &, int, int, const S *, const c_t<R> *,           \
+                                           c_t<R> *, int, int, hipStream_t);
+INST(double, double2)
+INST(float, float2)
+INST(float, chalf)
 #undef INST
 
 }  // namespace mg

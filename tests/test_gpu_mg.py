@@ -109,6 +109,18 @@ def test_coarse_apply_and_dagger(built):
     assert e1 < 1e-10 and e2 < 1e-10
 
 
+def test_apply_op_fp64(built):
+    """The level operators through mg_apply_op in FP64 equal the oracle's."""
+    name, U, m, ctx, h = built
+    v = W.gaussian_spinor(h.levels[0].geom.L, 4)
+    e0 = _rel(ctx.apply_op(0, torch.from_numpy(v).cuda()).cpu().numpy(), wi.apply_D(U, v, m))
+    lv = h.levels[0]
+    rng = np.random.default_rng(7)
+    vc = rng.standard_normal(lv.X.shape[:-1]) + 1j * rng.standard_normal(lv.X.shape[:-1])
+    e1 = _rel(ctx.apply_op(1, torch.from_numpy(vc).cuda()).cpu().numpy(), co.coarse_apply(lv.X, lv.Y, vc))
+    assert e0 < 1e-12 and e1 < 1e-12
+
+
 def test_solve_fp64(built):
     name, U, m, ctx, h = built
     L = h.levels[0].geom.L
@@ -124,18 +136,53 @@ def test_solve_fp64(built):
     assert abs(info["iters"][0] - it_ref) <= 1
 
 
-def test_solve_fp32_precond(built):
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_solve_lowprec_precond(built, prec):
+    """Mixed precision: FP64 outer FGCR around a V-cycle in FP32 (or with
+    FP16-stored operators) still reaches 1e-10, with an outer iteration count
+    close to the FP64 preconditioner's (the flexible outer method absorbs the
+    preconditioner's rounding)."""
     name, U, m, ctx, h = built
     L = h.levels[0].geom.L
     b = W.gaussian_spinor(L, 0)
-    ctx.set_precond_prec("f32")
+    _, it_ref, _, _ = so.mg_solve(h, b, 1e-10)
+    ctx.set_precond_prec(prec)
     try:
         x, info, rc = ctx.solve(torch.from_numpy(b).cuda(), 1e-10)
     finally:
         ctx.set_precond_prec("f64")
     res = np.linalg.norm(b - wi.apply_D(U, x.cpu().numpy(), m)) / np.linalg.norm(b)
-    print(f"{name}: FP32-preconditioned solve true rel resid {res:.2e}, iters {info['iters'][0]}")
+    print(f"{name}: {prec}-preconditioned solve true rel resid {res:.2e}, iters {info['iters'][0]} "
+          f"(FP64 oracle {it_ref})")
     assert rc == 0 and res <= 1e-10 * 1.001
+    assert info["iters"][0] <= it_ref + (1 if prec == "f32" else 3)
+
+
+# Relative error bounds of one operator application from stored copies.
+# FP32: unit roundoff 2^-24 ~ 6e-8 per operation, summed over ~100-term
+# dot products; FP16 storage: 2^-11 ~ 4.9e-4 relative rounding of every
+# operator entry (FP32 arithmetic), averaged over many terms.
+PREC_BOUND = {"f32": 1e-6, "f16": 1e-3}
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_operator_precision(built, prec):
+    """Stored-precision fine and coarse operators against the oracle's FP64
+    operators: the error is the storage rounding, no more."""
+    name, U, m, ctx, h = built
+    L = h.levels[0].geom.L
+    v = W.gaussian_spinor(L, 5)
+    y = ctx.apply_op(0, torch.from_numpy(v).cuda(), prec).cpu().numpy()
+    e0 = _rel(y, wi.apply_D(U, v, m))
+    lv = h.levels[0]
+    rng = np.random.default_rng(6)
+    vc = rng.standard_normal(lv.X.shape[:-1]) + 1j * rng.standard_normal(lv.X.shape[:-1])
+    yc = ctx.apply_op(1, torch.from_numpy(vc).cuda(), prec).cpu().numpy()
+    e1 = _rel(yc, co.coarse_apply(lv.X, lv.Y, vc))
+    print(f"{name}: {prec} fine D rel err {e0:.2e}, coarse D_c rel err {e1:.2e}")
+    assert e0 < PREC_BOUND[prec] and e1 < PREC_BOUND[prec]
+    if prec == "f16":
+        assert e0 > 1e-6 and e1 > 1e-6   # really rounded to binary16
 
 
 def test_solve_multi_rhs(built):
@@ -202,7 +249,7 @@ def test_graph_replay_matches_eager(cuda):
         torch.cuda.synchronize()
         assert torch.equal(xe, xg), seed_b
         assert ie["iters"] == ig["iters"] and ie["n_cgnr_iters"] == ig["n_cgnr_iters"]
-    for prec in ("f32",):
+    for prec in ("f32", "f16"):
         ctx_g.set_precond_prec(prec)
         ctx_e.set_precond_prec(prec)
         xe, _, _ = ctx_e.solve(b, 1e-10)
