@@ -167,6 +167,22 @@ int coarse_apply(mg_ctx_t *ctx, int level, const void *in, void *out,
 int mg_apply_op(mg_ctx_t *ctx, int level, mg_prec_t prec, const void *in,
                 void *out, int nrhs, hipStream_t stream);
 
+/* Coarse-stencil kernel choice.  For FP32 arithmetic (MG_F32, MG_F16) the
+ * coarse operator D_c ("Formulating an algorithm") can be applied either by
+ * one workgroup per (site, right-hand side) (variant 0) or, for a batch of
+ * right-hand sides, as one complex GEMM per coarse site on the FP32 matrix
+ * cores with the K range split over 1, 2 or 4 wavefront groups (variants
+ * 1, 2, 4).  By default the library times the candidates once per
+ * (operator size, coarse volume, nrhs, precision) on first use and keeps the
+ * fastest for the process.  mg_set_coarse_variant forces a variant
+ * (-1 restores tuning; a variant that cannot run a shape falls back to 0).
+ * mg_coarse_variant reports the tuned choice (-1: not tuned yet) and its
+ * time in microseconds (0 when forced or FP64).  MG_EINVAL on bad
+ * arguments, MG_ESHAPE on a bad level, MG_ENOTSUP on prec.                */
+int mg_set_coarse_variant(mg_ctx_t *ctx, int variant);
+int mg_coarse_variant(mg_ctx_t *ctx, int level, mg_prec_t prec, int nrhs,
+                      int *variant, double *us);
+
 /* Solve D x = b for nrhs canonical spinors (DEVICE complex128) with
  * flexible GCR(gcr_restart) preconditioned by one MG V-cycle (MR pre/post
  * smoothing, CGNR on the coarsest level), to ||b - D x|| <= tol ||b|| per

@@ -22,7 +22,7 @@ MAX_LEVELS = 3
 MAX_RHS = 16
 
 EXPORTED = ["wilson_apply", "mg_setup", "mg_set_precond_prec", "mg_set_timing", "mg_restrict",
-            "mg_prolong", "coarse_apply", "mg_apply_op", "mg_solve", "mg_time_dslash", "mg_time_coarse",
+            "mg_prolong", "coarse_apply", "mg_apply_op", "mg_set_coarse_variant", "mg_coarse_variant", "mg_solve", "mg_time_dslash", "mg_time_coarse",
             "mg_destroy", "mg_last_error", "mg_export_maps", "mg_export_P",
             "mg_export_coarse_op", "mg_export_nullvecs", "mg_level_info"]
 
@@ -98,6 +98,8 @@ def lib():
             "mg_prolong": [vp, ci, vp, vp, ci, vp],
             "coarse_apply": [vp, ci, vp, vp, ci, ci, vp],
             "mg_apply_op": [vp, ci, ci, vp, vp, ci, vp],
+            "mg_set_coarse_variant": [vp, ci],
+            "mg_coarse_variant": [vp, ci, ci, ci, ctypes.POINTER(ci), ctypes.POINTER(cd)],
             "mg_solve": [vp, vp, vp, ci, cd, ctypes.POINTER(Info), vp],
             "mg_time_dslash": [vp, ci, ci, ci, ctypes.POINTER(cd), vp],
             "mg_time_coarse": [vp, ci, ci, ci, ci, ctypes.POINTER(cd), vp],
@@ -243,6 +245,16 @@ class MG:
         out = torch.empty_like(v)
         _check(lib().mg_apply_op(self.ctx, level, PREC[prec], _dev(v, "in"), _dev(out, "out"), nrhs, _stream()))
         return out
+
+    def set_coarse_variant(self, variant):
+        """Force the coarse-stencil kernel (0 per-RHS, 1/2/4 matrix-core GEMM
+        with that K split) or restore autotuning (-1)."""
+        _check(lib().mg_set_coarse_variant(self.ctx, int(variant)))
+
+    def coarse_variant(self, level=1, prec="f32", nrhs=1):
+        v, us = ctypes.c_int(), ctypes.c_double()
+        _check(lib().mg_coarse_variant(self.ctx, level, PREC[prec], nrhs, ctypes.byref(v), ctypes.byref(us)))
+        return v.value, us.value
 
     def solve(self, b, tol=1e-10, nrhs=None, x=None):
         if nrhs is None:

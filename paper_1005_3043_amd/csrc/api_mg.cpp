@@ -107,6 +107,7 @@ extern "C" int mg_setup(const mg_lattice_t *lat, const void *U, double mass, con
   c->mass = mass;
   c->prec = params->precond_prec;
   c->use_graph = params->use_graph ? 1 : 0;
+  std::memset(c->cvar, 0xff, sizeof(c->cvar));  // -1: not tuned
   const double t0 = now_s();
   int rc = hip_rc(hipStreamCreateWithFlags(&c->sti, hipStreamNonBlocking), "hipStreamCreateWithFlags");
   if (rc == MG_OK) rc = hip_rc(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming), "hipEventCreate");
@@ -137,6 +138,26 @@ extern "C" int mg_set_precond_prec(mg_ctx_t *ctx, mg_prec_t prec) {
 extern "C" int mg_set_timing(mg_ctx_t *ctx, int on) {
   if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
   ctx->timing = on ? 1 : 0;
+  return MG_OK;
+}
+
+extern "C" int mg_set_coarse_variant(mg_ctx_t *ctx, int variant) {
+  if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
+  if (variant != -1 && variant != 0 && variant != 1 && variant != 2 && variant != 4)
+    return bad(MG_EINVAL, "mg_set_coarse_variant: variant must be -1, 0, 1, 2 or 4");
+  ctx->cvar_force = variant;
+  clear_graphs(ctx);
+  return MG_OK;
+}
+
+extern "C" int mg_coarse_variant(mg_ctx_t *ctx, int level, mg_prec_t prec, int nrhs, int *variant, double *us) {
+  if (!ctx || !variant || !us) return bad(MG_EINVAL, "mg_coarse_variant: NULL argument");
+  MG_TRY(check_ctx_level(ctx, level, 1, ctx->nlev - 1));
+  if (nrhs < 1 || nrhs > MG_MAX_RHS) return bad(MG_EINVAL, "mg_coarse_variant: nrhs out of range");
+  if (prec != MG_F64 && prec != MG_F32 && prec != MG_F16) return bad(MG_ENOTSUP, "mg_coarse_variant: prec");
+  const int pi = prec == MG_F64 ? 0 : prec == MG_F32 ? 1 : 2;
+  *variant = pi == 0 ? 0 : ctx->cvar[level][pi][nrhs];
+  *us = pi == 0 ? 0.0 : (*variant >= 0 ? (double)ctx->cvar_us[level][pi][nrhs] : 0.0);
   return MG_OK;
 }
 
@@ -180,7 +201,7 @@ extern "C" int coarse_apply(mg_ctx_t *ctx, int level, const void *in, void *out,
   HIPK(a.alloc(L.vsize() * nrhs));
   HIPK(b.alloc(L.vsize() * nrhs));
   HIPK(pack_level(ctx, level, in, a.p, nrhs, st));
-  HIPK((coarse_apply_k<double, double2>(L.g, L.n, L.L64, a.p, b.p, nrhs, dagger ? 1 : 0, nullptr, 1, nullptr, st)));
+  HIPK((coarse_apply_k<double, double2>(L.g, L.n, L.L64, a.p, b.p, nrhs, dagger ? 1 : 0, CoarseArgs{}, st)));
   HIPK(unpack_level(ctx, level, b.p, out, nrhs, st));
   return MG_OK;
 }
@@ -320,11 +341,12 @@ int time_coarse_t(mg_ctx *c, int level, int nrhs, int reps, hipEvent_t e0, hipEv
   MG_TRY(a.alloc(n));
   MG_TRY(b.alloc(n));
   const S *Lop = cop_of_level<P>(L);
-  for (int i = 0; i < 2; ++i)
-    HIPK((coarse_apply_k<R, S>(L.g, L.n, Lop, a, b, nrhs, 0, nullptr, 1, nullptr, st)));
+  CoarseArgs ca;
+  ca.variant = coarse_variant<P>(c, level, nrhs, st);
+  if (ca.variant < 0) return ca.variant;
+  for (int i = 0; i < 2; ++i) HIPK((coarse_apply_k<R, S>(L.g, L.n, Lop, a, b, nrhs, 0, ca, st)));
   HIPK(hipEventRecord(e0, st));
-  for (int i = 0; i < reps; ++i)
-    HIPK((coarse_apply_k<R, S>(L.g, L.n, Lop, a, b, nrhs, 0, nullptr, 1, nullptr, st)));
+  for (int i = 0; i < reps; ++i) HIPK((coarse_apply_k<R, S>(L.g, L.n, Lop, a, b, nrhs, 0, ca, st)));
   HIPK(hipEventRecord(e1, st));
   HIPK(hipEventSynchronize(e1));
   return MG_OK;

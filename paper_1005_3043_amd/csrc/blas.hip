@@ -41,6 +41,18 @@ template <typename Rd, typename Rs> hipError_t convert(c_t<Rd> *y, const c_t<Rs>
   return hipGetLastError();
 }
 
+template <typename C> __global__ __launch_bounds__(256) void k_fill(C *x, size_t n, C v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+template <typename R> hipError_t fill_const(c_t<R> *x, size_t n, R v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill<c_t<R>>, dim3(stream_grid(n)), dim3(256), 0, st, x, n, mk<c_t<R>>(v, (R)0));
+  return hipGetLastError();
+}
+template hipError_t fill_const<float>(float2 *, size_t, float, hipStream_t);
+template hipError_t fill_const<double>(double2 *, size_t, double, hipStream_t);
+
 template <typename S> __global__ __launch_bounds__(256) void k_store_convert(S *y, const double2 *x, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     y[i] = cvt<S>(x[i]);

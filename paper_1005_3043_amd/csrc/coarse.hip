@@ -16,6 +16,12 @@
 // operator loads is issued before the input vectors are staged so the two
 // memory phases overlap.  The G partial row sums are combined in LDS in a
 // fixed order (deterministic).
+//
+// The matrix-core variant (k_coarse_mma) handles all right-hand sides of a
+// site in one workgroup: out[:, 0:nrhs] = A [B_0 .. B_8], a complex GEMM with
+// M = n rows, N = nrhs (padded to 16) and K = 9n, where A is the site's
+// operator (loaded once for every right-hand side) and B the nine staged
+// input blocks.  Each complex product is four real 16x16x4 FP32 MFMAs.
 #include "solver.h"
 
 namespace mg {
@@ -64,6 +70,7 @@ __device__ __forceinline__ double block_allsum_partials(const double *__restrict
   __syncthreads();
   return t;
 }
+
 
 template <typename R, typename S, int RW>
 __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restrict__ L,
@@ -179,6 +186,226 @@ __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restri
   }
 }
 
+
+// ------------------------------------------------------------ matrix cores
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+template <typename S> __device__ __forceinline__ float2 op_f32(const S &v) { return cvt<float2>(v); }
+
+constexpr int MMA_NR = 16;  // right-hand sides per GEMM tile (N of the MFMA)
+constexpr int MMA_U = 8;    // operator k-steps per load batch
+
+// Sums of nr partial vectors (np entries each) over the workgroup, all in one
+// pass; results in every thread.
+__device__ __forceinline__ void block_allsum_multi(const double *__restrict__ p, int np, int nr,
+                                                   double (&out)[MMA_NR], double (*lds)[MMA_NR]) {
+#pragma unroll
+  for (int r = 0; r < MMA_NR; ++r) out[r] = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+#pragma unroll
+    for (int r = 0; r < MMA_NR; ++r)
+      if (r < nr) out[r] += p[(size_t)r * np + i];
+  }
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int r = 0; r < MMA_NR; ++r) out[r] = wave_sum(out[r]);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int r = 0; r < MMA_NR; ++r) lds[w][r] = out[r];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < MMA_NR; ++r) {
+    double t = 0.0;
+    for (int q = 0; q < nw; ++q) t += lds[q][r];
+    out[r] = t;
+  }
+  __syncthreads();
+}
+
+// One workgroup per coarse site, MT = ceil(n / 16) row tiles times KS groups
+// of the K range: wavefront (mt, ks) accumulates rows 16 mt .. 16 mt + 15 of
+// all right-hand sides over the k-steps ks, ks + KS, ... (4 of the 9n
+// (slot, column) pairs per step).  MFMA lane layouts (16x16x4, FP32):
+// A lane l = (row l % 16, k l / 16); B lane l = (k l / 16, column l % 16);
+// C lane l = (rows 4 (l / 16) + 0..3, column l % 16).
+template <typename S, int KS>
+__global__ __launch_bounds__(1024) void k_coarse_mma(Geom g, int n, const S *__restrict__ L,
+                                                     const float2 *__restrict__ in, float2 *__restrict__ out,
+                                                     int nrhs, int dagger, double *__restrict__ part, int pw,
+                                                     const int *__restrict__ done, CgCheck chk) {
+  extern __shared__ float2 bl[];  // staged inputs [9n][nrhs]; reused for the K-split reduction
+  __shared__ double wred[16][MMA_NR];
+  __shared__ double pr[4][64][3];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (done != nullptr) {
+    bool all = true;
+    for (int r = 0; r < nrhs; ++r) all = all && done[r] != 0;
+    if (all) return;
+  }
+  if (chk.part_r != nullptr) {
+    double rr[MMA_NR];
+    block_allsum_multi(chk.part_r, chk.np_r, nrhs, rr, wred);
+    bool allconv = true;
+    for (int r = 0; r < nrhs; ++r) {
+      if (chk.done[r]) continue;
+      const double *cg = chk.cg + (size_t)r * CG_NS;
+      const int iter = chk.it_in[r];
+      const bool conv = !(rr[r] > cg[4] * cg[3]) || iter + 1 >= chk.maxit;
+      if (blockIdx.x == 0 && tid == 0) {
+        chk.it_out[r] = iter + 1;
+        if (conv) chk.done[r] = 1;
+      }
+      allconv = allconv && conv;
+    }
+    if (allconv) return;
+  }
+  const uint32_t s = xcd_remap(blockIdx.x, gridDim.x);
+  const int K = 9 * n, half = n >> 1;
+  const int MT = (n + 15) >> 4;
+  const int mt = wv % MT, ks = wv / MT;
+  const int arow = mt * 16 + (lane & 15), kq = lane >> 4, col = lane & 15;
+  const bool arow_ok = arow < n, col_ok = col < nrhs;
+  const int colc = col_ok ? col : 0;
+  // Operator loads are unconditional (indices clamped into the site's block,
+  // out-of-range values zeroed afterwards) and double-buffered MMA_U k-steps
+  // ahead, so every wavefront keeps MMA_U loads in flight; the first batch is
+  // issued before the input staging.
+  const S *La = L + (size_t)s * K * n + (arow_ok ? arow : 0);
+  const int KQ = (K + 3) >> 2;
+  const int nq = (KQ - ks + KS - 1) / KS;  // k-steps of this wavefront
+  float2 abuf[2][MMA_U];
+  auto load_batch = [&](float2 (&dst)[MMA_U], int q0) {
+#pragma unroll
+    for (int u = 0; u < MMA_U; ++u) {
+      const int kk = min(4 * (ks + (q0 + u) * KS) + kq, K - 1);
+      dst[u] = op_f32(La[(size_t)kk * n]);
+    }
+  };
+  load_batch(abuf[0], 0);
+  const Coords k = decode(g, s);
+  {
+    const int jj = tid % n, tstep = (int)blockDim.x / n;
+    for (int t = tid / n; t < 9 * nrhs && jj < n && tid < tstep * n; t += tstep) {
+      const int r = t % nrhs, slot = t / nrhs;
+      uint32_t site = s;
+      if (slot > 0) {
+        const int d = slot - 1, mu = d >> 1;
+        site = (d & 1) ? nbr_bwd(g, s, k, mu) : nbr_fwd(g, s, k, mu);
+      }
+      float2 v = in[((size_t)r * g.V + site) * n + jj];
+      if (dagger && jj >= half) v = make_float2(-v.x, -v.y);
+      bl[(slot * n + jj) * nrhs + r] = v;
+    }
+  }
+  __syncthreads();
+  floatx4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+  for (int q0 = 0; q0 < nq; q0 += 2 * MMA_U) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int qb = q0 + h * MMA_U;
+      if (qb >= nq) break;
+      if (qb + MMA_U < nq) load_batch(abuf[h ^ 1], qb + MMA_U);
+#pragma unroll
+      for (int u = 0; u < MMA_U; ++u) {
+        const int kk = 4 * (ks + (qb + u) * KS) + kq;
+        const bool kok = qb + u < nq && kk < K;
+        const float2 a = (kok && arow_ok) ? abuf[h][u] : make_float2(0.f, 0.f);
+        const float2 bv = bl[min(kk, K - 1) * nrhs + colc];
+        const float2 b = (kok && col_ok) ? bv : make_float2(0.f, 0.f);
+        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, cim, 0, 0, 0);
+        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.y, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, cim, 0, 0, 0);
+      }
+    }
+  }
+  // centre inputs of this lane's output rows (for the <out, in> partial)
+  float2 ctr[4];
+#pragma unroll
+  for (int r4 = 0; r4 < 4; ++r4) {
+    const int row = mt * 16 + 4 * kq + r4;
+    ctr[r4] = (row < n && col_ok) ? bl[row * nrhs + col] : make_float2(0.f, 0.f);
+  }
+  if (KS > 1) {
+    __syncthreads();
+    float *red = reinterpret_cast<float *>(bl);
+    if (ks > 0) {
+      float *d = red + (((size_t)(ks - 1) * MT + mt) * 64 + lane) * 8;
+#pragma unroll
+      for (int r4 = 0; r4 < 4; ++r4) {
+        d[r4] = cre[r4];
+        d[4 + r4] = cim[r4];
+      }
+    }
+    __syncthreads();
+    if (ks == 0) {
+      for (int q = 1; q < KS; ++q) {
+        const float *d = red + (((size_t)(q - 1) * MT + mt) * 64 + lane) * 8;
+#pragma unroll
+        for (int r4 = 0; r4 < 4; ++r4) {
+          cre[r4] += d[r4];
+          cim[r4] += d[4 + r4];
+        }
+      }
+    }
+  }
+  double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+  if (ks == 0) {
+#pragma unroll
+    for (int r4 = 0; r4 < 4; ++r4) {
+      const int row = mt * 16 + 4 * kq + r4;
+      if (row < n && col_ok) {
+        float2 o = make_float2(cre[r4], cim[r4]);
+        if (dagger && row >= half) o = make_float2(-o.x, -o.y);
+        out[((size_t)col * g.V + s) * n + row] = o;
+        const float2 c = ctr[r4];
+        t0 += (double)o.x * c.x + (double)o.y * c.y;
+        t1 += (double)o.x * c.y - (double)o.y * c.x;
+        t2 += (double)o.x * o.x + (double)o.y * o.y;
+      }
+    }
+  }
+  if (part == nullptr) return;
+  if (ks == 0) {
+    pr[mt][lane][0] = t0;
+    pr[mt][lane][1] = t1;
+    pr[mt][lane][2] = t2;
+  }
+  __syncthreads();
+  if (tid < nrhs) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int m = 0; m < MT; ++m)
+      for (int g4 = 0; g4 < 4; ++g4) {
+        a0 += pr[m][g4 * 16 + tid][0];
+        a1 += pr[m][g4 * 16 + tid][1];
+        a2 += pr[m][g4 * 16 + tid][2];
+      }
+    double *p = part + ((size_t)tid * gridDim.x + blockIdx.x) * pw;
+    if (pw == 1) {
+      p[0] = a2;
+    } else {
+      p[0] = a0;
+      p[1] = a1;
+      p[2] = a2;
+    }
+  }
+}
+
+static size_t mma_lds_bytes(int n, int nrhs, int ks) {
+  const size_t b = (size_t)9 * n * nrhs * sizeof(float2);
+  const size_t r = (size_t)(ks - 1) * ((n + 15) / 16) * 64 * 8 * sizeof(float);
+  return b > r ? b : r;
+}
+
+bool coarse_mma_ok(int n, int nrhs, int ks) {
+  if (n > COARSE_NMAX || nrhs < 1 || nrhs > MMA_NR) return false;
+  if (ks != 1 && ks != 2 && ks != 4) return false;
+  if (((n + 15) / 16) * ks * 64 > 1024) return false;
+  return mma_lds_bytes(n, nrhs, ks) <= 56 * 1024;  // + 8 KB static LDS
+}
+
 // Workgroups per coarse site.  Splitting a site's rows over several
 // workgroups was measured slower at every coarse-lattice size here (it halves
 // the contiguous column segments), so each site is one workgroup; the
@@ -197,32 +424,55 @@ int coarse_threads(int n, uint32_t V) {
 
 template <typename R, typename S>
 hipError_t coarse_apply_k(const Geom &g, int n, const S *L, const c_t<R> *in, c_t<R> *out, int nrhs, int dagger,
-                          double *partials, int pw, const int *done, hipStream_t st, const CgCheck *chk) {
+                          const CoarseArgs &a, hipStream_t st) {
+  CgCheck c{};
+  if (a.chk) c = *a.chk;
+  if constexpr (sizeof(R) == 4) {
+    if (a.variant > 0) {
+      const int ks = a.variant;
+      if (!coarse_mma_ok(n, nrhs, ks)) return hipErrorInvalidValue;
+      const dim3 block(64 * ((n + 15) / 16) * ks);
+      const size_t lds = mma_lds_bytes(n, nrhs, ks);
+      if (ks == 1)
+        hipLaunchKernelGGL((k_coarse_mma<S, 1>), dim3(g.V), block, lds, st, g, n, L, in, out, nrhs, dagger, a.part,
+                           a.pw, a.done, c);
+      else if (ks == 2)
+        hipLaunchKernelGGL((k_coarse_mma<S, 2>), dim3(g.V), block, lds, st, g, n, L, in, out, nrhs, dagger, a.part,
+                           a.pw, a.done, c);
+      else
+        hipLaunchKernelGGL((k_coarse_mma<S, 4>), dim3(g.V), block, lds, st, g, n, L, in, out, nrhs, dagger, a.part,
+                           a.pw, a.done, c);
+      return hipGetLastError();
+    }
+  } else {
+    if (a.variant > 0) return hipErrorInvalidValue;
+  }
   dim3 grid(g.V * coarse_split(n, g.V), nrhs);
   dim3 block(coarse_threads(n, g.V));
-  CgCheck c{};
-  if (chk) c = *chk;
   if constexpr (sizeof(S) == 16) {
-    hipLaunchKernelGGL((k_coarse<R, S, 1>), grid, block, 0, st, g, n, L, in, out, dagger, partials, pw, done, c);
+    hipLaunchKernelGGL((k_coarse<R, S, 1>), grid, block, 0, st, g, n, L, in, out, dagger, a.part, a.pw, a.done,
+                       c);
   } else if constexpr (sizeof(S) == 8) {
-    hipLaunchKernelGGL((k_coarse<R, S, 2>), grid, block, 0, st, g, n, L, in, out, dagger, partials, pw, done, c);
+    hipLaunchKernelGGL((k_coarse<R, S, 2>), grid, block, 0, st, g, n, L, in, out, dagger, a.part, a.pw, a.done,
+                       c);
   } else {
     // half storage: four rows per 16-byte load when the rows of a workgroup
     // come in multiples of four, else two rows per 8-byte load
     if ((n / coarse_split(n, g.V)) % 4 == 0)
-      hipLaunchKernelGGL((k_coarse<R, S, 4>), grid, block, 0, st, g, n, L, in, out, dagger, partials, pw, done, c);
+      hipLaunchKernelGGL((k_coarse<R, S, 4>), grid, block, 0, st, g, n, L, in, out, dagger, a.part, a.pw, a.done,
+                         c);
     else
-      hipLaunchKernelGGL((k_coarse<R, S, 2>), grid, block, 0, st, g, n, L, in, out, dagger, partials, pw, done, c);
+      hipLaunchKernelGGL((k_coarse<R, S, 2>), grid, block, 0, st, g, n, L, in, out, dagger, a.part, a.pw, a.done,
+                         c);
   }
   return hipGetLastError();
 }
 
 template hipError_t coarse_apply_k<double, double2>(const Geom &, int, const double2 *, const double2 *, double2 *,
-                                                    int, int, double *, int, const int *, hipStream_t,
-                                                    const CgCheck *);
+                                                    int, int, const CoarseArgs &, hipStream_t);
 template hipError_t coarse_apply_k<float, float2>(const Geom &, int, const float2 *, const float2 *, float2 *, int,
-                                                  int, double *, int, const int *, hipStream_t, const CgCheck *);
+                                                  int, const CoarseArgs &, hipStream_t);
 template hipError_t coarse_apply_k<float, chalf>(const Geom &, int, const chalf *, const float2 *, float2 *, int,
-                                                 int, double *, int, const int *, hipStream_t, const CgCheck *);
+                                                 int, const CoarseArgs &, hipStream_t);
 
 }  // namespace mg

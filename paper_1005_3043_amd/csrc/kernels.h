@@ -40,6 +40,8 @@ template <typename R> hipError_t copy(c_t<R> *y, const c_t<R> *x, size_t n, hipS
 template <typename Rd, typename Rs>
 hipError_t convert(c_t<Rd> *y, const c_t<Rs> *x, size_t n, hipStream_t st);
 // operator storage: y[i] = x[i] rounded to storage type S (nearest even)
+// x[i] = v + 0 i
+template <typename R> hipError_t fill_const(c_t<R> *x, size_t n, R v, hipStream_t st);
 template <typename S> hipError_t store_convert(S *y, const double2 *x, size_t n, hipStream_t st);
 
 }  // namespace mg
@@ -68,13 +70,30 @@ struct CgCheck {
   int *it_out = nullptr;
   int maxit = 0;
 };
-// out = D_c in (dagger: sigma3 D_c sigma3).  When partials != nullptr each
-// workgroup writes pw doubles at partials[(rhs*V*RS + wg)*pw] (RS =
-// coarse_split): pw = 1: ||out||^2; pw = 3: <out, in>, ||out||^2.  A right-hand side with done[rhs] != 0 is
-// skipped (done may be nullptr).
+// Reduction outputs and options of the coarse stencil.
+//  part/pw: when part != nullptr each workgroup writes pw doubles at
+//    part[(rhs * nwg + wg) * pw] (nwg = workgroups per right-hand side = V):
+//    pw = 1: ||out||^2;  pw = 3: <out, in>, ||out||^2 (in = centre input).
+//  done: a right-hand side with done[rhs] != 0 is skipped (may be nullptr).
+//  chk: CGNR convergence prologue (see CgCheck).
+//  variant: 0 = one workgroup per (site, right-hand side), FP vector FMA;
+//    KS = 1, 2, 4 = one workgroup per site for all right-hand sides, a
+//    complex GEMM on FP32 matrix cores with the K dimension split over KS
+//    wavefront groups (FP32 arithmetic only).
+struct CoarseArgs {
+  double *part = nullptr;
+  int pw = 1;
+  const int *done = nullptr;
+  const CgCheck *chk = nullptr;
+  int variant = 0;
+};
+// out = D_c in (dagger: sigma3 D_c sigma3) for nrhs right-hand sides
+// (site-major vectors [nrhs][V][n]).
 template <typename R, typename S>
 hipError_t coarse_apply_k(const Geom &g, int n, const S *L, const c_t<R> *in, c_t<R> *out, int nrhs, int dagger,
-                          double *partials, int pw, const int *done, hipStream_t st, const CgCheck *chk = nullptr);
+                          const CoarseArgs &a, hipStream_t st);
+// Whether the matrix-core variant can run this shape (LDS and thread limits).
+bool coarse_mma_ok(int n, int nrhs, int ks);
 
 // ---- transfer.hip
 // Fine level: P = nv null-vector fields in the fine layout [nv][12 * Vpad].

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "mg_internal.h"
@@ -173,6 +174,96 @@ struct TimerScope {
   }
 };
 
+// ------------------------------------------------------------ autotuner
+// Coarse-stencil variant for (operator size, coarse volume, right-hand
+// sides, precision): the per-RHS kernel (0) or the matrix-core GEMM with K
+// split 1, 2 or 4.  Each candidate is timed on the level's own operator with
+// its partial sums and final reduction, as the CGNR uses it; the fastest is
+// kept for the process (shapes, not contexts, decide it).  Never called
+// under stream capture.
+namespace {
+struct TuneKey {
+  int n, prec, nrhs;
+  uint32_t V;
+  bool operator==(const TuneKey &o) const { return n == o.n && prec == o.prec && nrhs == o.nrhs && V == o.V; }
+};
+struct TuneVal {
+  TuneKey k;
+  int variant;
+  float us;
+};
+std::mutex tune_mu;
+std::vector<TuneVal> tune_cache;
+}  // namespace
+
+template <typename P> int coarse_variant(mg_ctx *c, int l, int nrhs, hipStream_t st) {
+  using R = typename P::R;
+  using S = typename P::S;
+  if constexpr (sizeof(R) == 8) {
+    return 0;
+  } else {
+    Level &L = c->lev[l];
+    if (c->cvar_force >= 0)
+      return (c->cvar_force == 0 || coarse_mma_ok(L.n, nrhs, c->cvar_force)) ? c->cvar_force : 0;
+    int &v = c->cvar[l][P::id][nrhs];
+    if (v >= 0) return v;
+    const TuneKey key{L.n, P::id, nrhs, L.g.V};
+    {
+      std::lock_guard<std::mutex> lk(tune_mu);
+      for (const TuneVal &t : tune_cache)
+        if (t.k == key) {
+          v = t.variant;
+          c->cvar_us[l][P::id][nrhs] = t.us;
+          return v;
+        }
+    }
+    const size_t nn = L.vsize() * nrhs;
+    DevBuf<float2> a, b;
+    MG_TRY(a.alloc(nn));
+    MG_TRY(b.alloc(nn));
+    MG_TRY(ensure_scalars(c, part_need(c, nrhs)));
+    HIPK(fill_const<float>(a, nn, 1.0f, st));
+    hipEvent_t e0, e1;
+    HIPK(hipEventCreate(&e0));
+    HIPK(hipEventCreate(&e1));
+    int best = 0;
+    float best_t = 1e30f;
+    const int cands[4] = {0, 1, 2, 4};
+    int rc = MG_OK;
+    for (int ci = 0; ci < 4 && rc == MG_OK; ++ci) {
+      const int cv = cands[ci];
+      if (cv > 0 && !coarse_mma_ok(L.n, nrhs, cv)) continue;
+      CoarseArgs ca;
+      ca.part = c->part;
+      ca.pw = 1;
+      ca.variant = cv;
+      const int reps = 8;
+      for (int i = 0; i < 2 + reps && rc == MG_OK; ++i) {
+        if (i == 2) rc = hip_rc(hipEventRecord(e0, st), "hipEventRecord");
+        if (rc == MG_OK)
+          rc = hip_rc((coarse_apply_k<R, S>(L.g, L.n, cop_of<P>(L), a.p, b.p, nrhs, 0, ca, st)), "coarse tune");
+      }
+      if (rc == MG_OK) rc = hip_rc(hipEventRecord(e1, st), "hipEventRecord");
+      if (rc == MG_OK) rc = hip_rc(hipEventSynchronize(e1), "hipEventSynchronize");
+      float ms = 0.f;
+      if (rc == MG_OK) rc = hip_rc(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+      const float us = ms * 1e3f / reps;
+      if (rc == MG_OK && us < best_t) {
+        best_t = us;
+        best = cv;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    MG_TRY(rc);
+    v = best;
+    c->cvar_us[l][P::id][nrhs] = best_t;
+    std::lock_guard<std::mutex> lk(tune_mu);
+    tune_cache.push_back(TuneVal{key, best, best_t});
+    return v;
+  }
+}
+
 // out = A_l in  (DS_MR: MR partials into c->part; DS_RESID: out = b - A_l in)
 template <typename P>
 int apply_A(mg_ctx *c, int l, const vec_t<P> *in, vec_t<P> *out, int nrhs, DslashMode mode, const vec_t<P> *b,
@@ -185,10 +276,17 @@ int apply_A(mg_ctx *c, int l, const vec_t<P> *in, vec_t<P> *out, int nrhs, Dslas
     HIPK((dslash<R, S>(L.g, links_of<P>(L), L.nl, in, out, b, 4.0 + c->mass, nrhs, mode, c->part, st)));
     c->n_fine += nrhs;
   } else {
+    const int var = coarse_variant<P>(c, l, nrhs, st);
+    if (var < 0) return var;
+    CoarseArgs ca;
+    if (mode == DS_MR) {
+      ca.part = c->part;
+      ca.pw = 3;
+    }
+    ca.variant = var;
     {
       TimerScope ts(c, c->tm[tclass<P>(true)], st, (double)L.g.V * nrhs);
-      HIPK((coarse_apply_k<R, S>(L.g, L.n, cop_of<P>(L), in, out, nrhs, 0, mode == DS_MR ? c->part.p : nullptr, 3,
-                                 nullptr, st)));
+      HIPK((coarse_apply_k<R, S>(L.g, L.n, cop_of<P>(L), in, out, nrhs, 0, ca, st)));
     }
     if (mode == DS_RESID) HIPK(resid_from<R>(out, b, L.vsize(), nrhs, st));
     c->n_coarse += nrhs;
@@ -257,21 +355,26 @@ static CgPtrs cg_ptrs(mg_ctx *c, int l, int nrhs) {
   return q;
 }
 
-template <typename P> int cgnr_chunk(mg_ctx *c, int l, vec_t<P> *e, int nrhs, hipStream_t st, EventTimer &tm) {
+template <typename P>
+int cgnr_chunk(mg_ctx *c, int l, vec_t<P> *e, int nrhs, int var, hipStream_t st, EventTimer &tm) {
   using R = typename P::R;
   using S = typename P::S;
   Work<R> &w = work<R>(c);
   Level &L = c->lev[l];
   const size_t n = L.vsize();
   const double sites = (double)L.g.V * nrhs;
-  const int npc = (int)np_coarse(L);
   c_t<R> *r = w.cr, *z = w.cz, *p = w.cp, *ww = w.cw;
   const S *Lop = cop_of<P>(L);
   const CgPtrs q = cg_ptrs(c, l, nrhs);
+  const int npc = (int)np_coarse(L);
   for (int k = 0; k < CG_CHUNK; ++k) {
+    CoarseArgs ca;
+    ca.part = q.pw;
+    ca.done = c->done;
+    ca.variant = var;
     {
       TimerScope ts(c, tm, st, sites);
-      HIPK((coarse_apply_k<R, S>(L.g, L.n, Lop, p, ww, nrhs, 0, q.pw, 1, c->done, st)));
+      HIPK((coarse_apply_k<R, S>(L.g, L.n, Lop, p, ww, nrhs, 0, ca, st)));
     }
     const int npr = cg2_update<R>(e, p, r, ww, n, nrhs, q.pw, q.pz[k & 1], npc, c->done, q.pr, st);
     HIPK(hipGetLastError());
@@ -283,27 +386,31 @@ template <typename P> int cgnr_chunk(mg_ctx *c, int l, vec_t<P> *e, int nrhs, hi
     chk.it_in = c->it + (size_t)(k & 1) * nrhs;
     chk.it_out = c->it + (size_t)((k + 1) & 1) * nrhs;
     chk.maxit = c->p.coarse_maxiter;
+    ca.part = q.pz[(k + 1) & 1];
+    ca.chk = &chk;
     {
       TimerScope ts(c, tm, st, sites);
-      HIPK((coarse_apply_k<R, S>(L.g, L.n, Lop, r, z, nrhs, 1, q.pz[(k + 1) & 1], 1, c->done, st, &chk)));
+      HIPK((coarse_apply_k<R, S>(L.g, L.n, Lop, r, z, nrhs, 1, ca, st)));
     }
     HIPK(cg2_p<R>(p, z, n, nrhs, q.pz[(k + 1) & 1], q.pz[k & 1], npc, c->done, st));
   }
   return MG_OK;
 }
 
-template <typename P> ChunkGraph *chunk_graph(mg_ctx *c, int l, vec_t<P> *e, int nrhs, hipStream_t st) {
+template <typename P> ChunkGraph *chunk_graph(mg_ctx *c, int l, vec_t<P> *e, int nrhs, int var, hipStream_t st) {
   const int prec = P::id;
   for (ChunkGraph *g : c->graphs)
-    if (g && g->level == l && g->prec == prec && g->nrhs == nrhs && g->timing == c->timing) return g;
+    if (g && g->level == l && g->prec == prec && g->nrhs == nrhs && g->timing == c->timing && g->variant == var)
+      return g;
   ChunkGraph *g = new ChunkGraph();
   g->level = l;
   g->prec = prec;
   g->nrhs = nrhs;
   g->timing = c->timing;
+  g->variant = var;
   bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) == hipSuccess;
   if (ok) {
-    const int rc = cgnr_chunk<P>(c, l, e, nrhs, st, g->tm);
+    const int rc = cgnr_chunk<P>(c, l, e, nrhs, var, st, g->tm);
     ok = hipStreamEndCapture(st, &g->graph) == hipSuccess && rc == MG_OK;
   }
   if (ok) ok = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) == hipSuccess;
@@ -330,21 +437,27 @@ template <typename P> int cgnr(mg_ctx *c, int l, const vec_t<P> *b, vec_t<P> *e,
   const size_t n = L.vsize();
   const CgPtrs q = cg_ptrs(c, l, nrhs);
   EventTimer &tm = c->tm[tclass<P>(true)];
+  const int var = coarse_variant<P>(c, l, nrhs, st);
+  if (var < 0) return var;
   HIPK(zero<R>(e, n * nrhs, st));
   HIPK(copy<R>(w.cr, b, n * nrhs, st));
   const int npb = norm2_partials<R>(b, n, nrhs, q.pb, st);
   HIPK(cg2_init(q.pb, npb, nrhs, c->cg, c->done, c->it, c->p.coarse_tol, st));
   {
+    CoarseArgs ca;
+    ca.part = q.pz[0];
+    ca.done = c->done;
+    ca.variant = var;
     TimerScope ts(c, tm, st, (double)L.g.V * nrhs);
-    HIPK((coarse_apply_k<R, S>(L.g, L.n, cop_of<P>(L), w.cr, w.cz, nrhs, 1, q.pz[0], 1, c->done, st)));
+    HIPK((coarse_apply_k<R, S>(L.g, L.n, cop_of<P>(L), w.cr, w.cz, nrhs, 1, ca, st)));
   }
   HIPK(copy<R>(w.cp, w.cz, n * nrhs, st));
-  ChunkGraph *gph = c->use_graph ? chunk_graph<P>(c, l, e, nrhs, st) : nullptr;
+  ChunkGraph *gph = c->use_graph ? chunk_graph<P>(c, l, e, nrhs, var, st) : nullptr;
   const int nchunks = (c->p.coarse_maxiter + CG_CHUNK - 1) / CG_CHUNK;
   const bool pipeline = !c->timing;
   for (int ch = 0; ch < nchunks; ++ch) {
     if (gph) HIPK(hipGraphLaunch(gph->exec, st));
-    else MG_TRY(cgnr_chunk<P>(c, l, e, nrhs, st, tm));
+    else MG_TRY(cgnr_chunk<P>(c, l, e, nrhs, var, st, tm));
     int *hd = c->h_done + (size_t)(ch & 1) * MG_MAX_RHS;
     HIPK(hipMemcpyAsync(hd, c->done, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
     HIPK(hipEventRecord(c->ev_chunk[ch & 1], st));
@@ -594,7 +707,8 @@ int setup(mg_ctx *c, const void *U, hipStream_t st) {
   template int apply_A<P>(mg_ctx *, int, const vec_t<P> *, vec_t<P> *, int, DslashMode, const vec_t<P> *,       \
                           hipStream_t);                                                                          \
   template int transfer_restrict<P>(mg_ctx *, int, const vec_t<P> *, vec_t<P> *, int, hipStream_t);             \
-  template int transfer_prolong<P>(mg_ctx *, int, const vec_t<P> *, vec_t<P> *, int, int, hipStream_t);
+  template int transfer_prolong<P>(mg_ctx *, int, const vec_t<P> *, vec_t<P> *, int, int, hipStream_t);       \
+  template int coarse_variant<P>(mg_ctx *, int, int, hipStream_t);
 INST(PF64)
 INST(PF32)
 INST(PF16)

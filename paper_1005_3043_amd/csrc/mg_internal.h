@@ -6,6 +6,7 @@
 namespace mg {
 
 template <typename R> Work<R> &work(mg_ctx *c);
+template <typename P> int coarse_variant(mg_ctx *c, int l, int nrhs, hipStream_t st);
 int ensure_scalars(mg_ctx *c, size_t part_count);
 void clear_graphs(mg_ctx *c);
 size_t np_coarse(const Level &L);

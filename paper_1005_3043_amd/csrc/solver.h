@@ -167,7 +167,7 @@ struct EventTimer {
 
 // A captured chunk of CGNR iterations for one (level, precision, nrhs).
 struct ChunkGraph {
-  int level = -1, prec = -1, nrhs = 0, timing = 0;
+  int level = -1, prec = -1, nrhs = 0, timing = 0, variant = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   EventTimer tm;  // coarse-stencil timing events inside the graph (timing on)
@@ -192,6 +192,11 @@ struct mg_ctx {
   // scalars and partials
   mg::DevBuf<double> part, part2, dsc, cg;
   mg::DevBuf<double> cgp;  // CGNR partials: w, z[2], r, b
+  // coarse-stencil variant per (level, precision class, nrhs): -1 = not yet
+  // tuned; 0 = per right-hand side; 1, 2, 4 = matrix-core GEMM K split
+  int cvar[MG_MAX_LEVELS][3][MG_MAX_RHS + 1];
+  float cvar_us[MG_MAX_LEVELS][3][MG_MAX_RHS + 1];
+  int cvar_force = -1;  // >= 0: use this variant wherever it can run
   hipStream_t sti = nullptr;                  // library-owned stream of mg_solve
   hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_chunk[2] = {nullptr, nullptr};
   int use_graph = 1;

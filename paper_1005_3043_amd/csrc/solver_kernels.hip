@@ -5,6 +5,8 @@
 // reads it.  The host only reads residual norms for convergence decisions.
 // Vectors are flat complex arrays of N entries per right-hand side
 // (blockIdx.y = right-hand side); any site layout works.
+#include <algorithm>
+
 #include "solver.h"
 
 namespace mg {
@@ -260,10 +262,15 @@ hipError_t cg2_init(const double *part_b, int npb, int nrhs, double *cg, int *do
   hipLaunchKernelGGL(k_cg2_init, dim3(1, nrhs), dim3(256), 0, st, part_b, npb, cg, done, it, tol * tol);
   return hipGetLastError();
 }
+// The CGNR update kernels re-derive alpha and beta from the stencil's
+// per-workgroup partials in every workgroup, so their grids are kept small.
+constexpr int CG_BLOCKS = 64;
+static inline int cgrid(size_t n) { return std::min(sgrid(n), CG_BLOCKS); }
+
 template <typename R>
 int cg2_update(c_t<R> *e, const c_t<R> *p, c_t<R> *r, const c_t<R> *w, size_t n, int nrhs, const double *part_w,
                const double *part_z, int npc, int *done, double *part_r, hipStream_t st) {
-  const int g = sgrid(n);
+  const int g = cgrid(n);
   hipLaunchKernelGGL(k_cg2_update<R>, dim3(g, nrhs), dim3(256), 0, st, e, p, r, w, n, part_w, part_z, npc, done,
                      part_r);
   return g;
@@ -271,7 +278,7 @@ int cg2_update(c_t<R> *e, const c_t<R> *p, c_t<R> *r, const c_t<R> *w, size_t n,
 template <typename R>
 hipError_t cg2_p(c_t<R> *p, const c_t<R> *z, size_t n, int nrhs, const double *part_znew, const double *part_zold,
                  int npc, const int *done, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg2_p<R>, dim3(sgrid(n), nrhs), dim3(256), 0, st, p, z, n, part_znew, part_zold, npc, done);
+  hipLaunchKernelGGL(k_cg2_p<R>, dim3(cgrid(n), nrhs), dim3(256), 0, st, p, z, n, part_znew, part_zold, npc, done);
   return hipGetLastError();
 }
 

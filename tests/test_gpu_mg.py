@@ -185,6 +185,56 @@ def test_operator_precision(built, prec):
         assert e0 > 1e-6 and e1 > 1e-6   # really rounded to binary16
 
 
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_coarse_variants(built, prec):
+    """Every coarse-stencil kernel variant (per-RHS FMA, matrix-core GEMM with
+    K split 1/2/4) applies the stored-precision D_c to a batch of right-hand
+    sides with the storage rounding error only, and the variants agree with
+    each other to FP32 rounding (they differ in summation order)."""
+    name, U, m, ctx, h = built
+    lv = h.levels[0]
+    rng = np.random.default_rng(11)
+    nr = 5
+    vc = rng.standard_normal((nr,) + lv.X.shape[:-1]) + 1j * rng.standard_normal((nr,) + lv.X.shape[:-1])
+    ref = np.stack([co.coarse_apply(lv.X, lv.Y, vc[i]) for i in range(nr)])
+    outs = {}
+    try:
+        for var in (0, 1, 2, 4):
+            ctx.set_coarse_variant(var)
+            outs[var] = ctx.apply_op(1, torch.from_numpy(vc).cuda(), prec).cpu().numpy()
+    finally:
+        ctx.set_coarse_variant(-1)
+    for var, y in outs.items():
+        e = max(_rel(y[i], ref[i]) for i in range(nr))
+        d = max(_rel(y[i], outs[0][i]) for i in range(nr))
+        print(f"{name}: {prec} variant {var}: rel err vs FP64 oracle {e:.2e}, vs variant 0 {d:.2e}")
+        assert e < PREC_BOUND[prec]
+        assert d < 2e-6
+
+
+def test_solve_multi_rhs_variants(built):
+    """Multi-RHS solves with the matrix-core coarse stencil (and with the
+    autotuned choice) reach 1e-10 on every right-hand side."""
+    name, U, m, ctx, h = built
+    L = h.levels[0].geom.L
+    b = W.gaussian_spinor(L, 9, batch=(4,))
+    ctx.set_precond_prec("f32")
+    try:
+        for var in (2, -1):
+            ctx.set_coarse_variant(var)
+            x, info, rc = ctx.solve(torch.from_numpy(b).cuda(), 1e-10)
+            xn = x.cpu().numpy()
+            res = [np.linalg.norm(b[i] - wi.apply_D(U, xn[i], m)) / np.linalg.norm(b[i]) for i in range(4)]
+            print(f"{name}: 4-RHS f32 solve, coarse variant {var}: max resid {max(res):.2e}, iters {info['iters'][:4]}")
+            assert rc == 0 and max(res) <= 1e-10 * 1.001
+        v, us = ctx.coarse_variant(1, "f32", 4)
+        print(f"{name}: autotuned coarse variant for 4 RHS: {v} ({us:.1f} us)")
+        assert v in (0, 1, 2, 4) and us > 0
+    finally:
+        ctx.set_coarse_variant(-1)
+        ctx.set_precond_prec("f64")
+
+
 def test_solve_multi_rhs(built):
     name, U, m, ctx, h = built
     L = h.levels[0].geom.L
