@@ -172,3 +172,27 @@ def mass_for(name: str, target: float | None = None) -> float:
     if rec is None:
         raise KeyError(f"no stored Arnoldi estimate for workload {name}")
     return float(target) - float(rec["re_lambda_min_m0"])
+
+
+STREAM_PTC_WEIGHTS = 6
+PTC_HOPS = 9
+
+
+def ptc_init_weights(n_hidden: int, n_out: int, seed: int):
+    """Initial weights of the two-layer parallel-transport network
+    ([c_out, c_in, 9, 4, 4] complex): W2 complex Gaussian scaled by
+    1/sqrt(2 fan-in); W1 the identity on the T_0 term plus a Gaussian part of
+    scale 0.1/sqrt(2 fan-in), so the first layer starts near a copy of the
+    noise."""
+    g = rng(seed, STREAM_PTC_WEIGHTS)
+    s1 = (n_hidden, 1, PTC_HOPS, 4, 4)
+    W1 = (g.standard_normal(s1) + 1j * g.standard_normal(s1)) * (0.1 / np.sqrt(2 * PTC_HOPS * 4))
+    W1[:, 0, 0] += np.eye(4)
+    s2 = (n_out, n_hidden, PTC_HOPS, 4, 4)
+    W2 = (g.standard_normal(s2) + 1j * g.standard_normal(s2)) / np.sqrt(2 * n_hidden * PTC_HOPS * 4)
+    return W1, W2
+
+
+def noise_spinor(L, seed: int, batch=()) -> np.ndarray:
+    """Complex Gaussian noise field for the network input (stream 3)."""
+    return gaussian_spinor(L, seed, STREAM_NOISE, batch)
