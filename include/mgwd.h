@@ -34,6 +34,7 @@
 #ifndef MGWD_H
 #define MGWD_H
 
+#include <stddef.h>
 #include <stdint.h>
 #include <hip/hip_runtime_api.h>
 
@@ -232,6 +233,51 @@ int mg_export_nullvecs(mg_ctx_t *ctx, int level, void *V_host);
 
 /* Geometry of level `level`: L (4 ints) and component count per site.   */
 int mg_level_info(mg_ctx_t *ctx, int level, int *L_out, int *ncomp_out);
+
+/* ---- Learned proposal of near-null vectors ---------------------------
+ * A two-layer gauge-equivariant network of parallel-transport convolutions
+ * maps a noise spinor eta and the links U to n_out candidate vectors that
+ * replace the random start vectors of the setup relaxation ("Adaptive
+ * Multigrid"; the network itself is an extension the paper does not
+ * have).  Hops T_0 = 1 and, for k = 1 + 2 mu + dir, the parallel transport
+ * of the hopping term of Eq. 2 (dir 0 from x + mu with U_mu(x), dir 1 from
+ * x - mu with U_mu(x - mu)^dag, sign -1 across the antiperiodic time
+ * boundary).  Layer: out_a = sum_{b,k} W_abk T_k in_b with W_abk a complex
+ * 4x4 spin matrix; psi1 = layer(W1, eta) (1 -> n_hidden), Y = layer(W2,
+ * psi1) (n_hidden -> n_out); no nonlinearity.
+ *
+ * Weights: DEVICE complex64, W1 [n_hidden][1][9][4][4], W2
+ * [n_out][n_hidden][9][4][4] (row-major, [s][t] spin matrices).  Fields:
+ * DEVICE complex128 canonical spinors.  FP32 arithmetic.
+ *
+ * ptc_create: block = aggregate shape of the subspace-fit loss (must divide
+ *   the lattice).  Owns its buffers until ptc_destroy.
+ * ptc_set_links: packs U (canonical complex128 links) for later calls.
+ * ptc_set_targets: the nv target vectors of the loss (the null vectors of
+ *   the plain setup), canonical complex128 [nv][sites][4][3].
+ * ptc_forward: Y [n_out][sites][4][3] from eta [sites][4][3].
+ * ptc_loss_grad: forward pass, loss L = sum over chirality-split
+ *   aggregates of the least-squares residual of the targets in the span of
+ *   Y, divided by sum ||V||^2 (host double), and the gradients
+ *   gW = dL/dRe W + i dL/dIm W (device complex64, layouts of W).  Synchronous.
+ *   MG_ERANK if Y is rank deficient on a block.
+ * ptc_adam: one Adam step on n complex parameters (real and imaginary parts
+ *   separately): m (complex64) and v (2n floats, interleaved re/im) are the
+ *   moment buffers (zero before step 1), step counts from 1.  Async.
+ * Errors: MG_EINVAL (NULL, ranges), MG_ESHAPE (block does not divide L).  */
+typedef struct ptc_ctx ptc_ctx_t;
+int ptc_create(const mg_lattice_t *lat, const int block[4], int n_hidden,
+               int n_out, ptc_ctx_t **ctx);
+int ptc_set_links(ptc_ctx_t *ctx, const void *U, hipStream_t stream);
+int ptc_set_targets(ptc_ctx_t *ctx, const void *V, int nv, hipStream_t stream);
+int ptc_forward(ptc_ctx_t *ctx, const void *W1, const void *W2, const void *eta,
+                void *Y, hipStream_t stream);
+int ptc_loss_grad(ptc_ctx_t *ctx, const void *W1, const void *W2,
+                  const void *eta, double *loss, void *gW1, void *gW2,
+                  hipStream_t stream);
+int ptc_adam(void *W, const void *g, void *m, void *v, size_t n, int step,
+             double lr, double b1, double b2, double eps, hipStream_t stream);
+int ptc_destroy(ptc_ctx_t *ctx);
 
 #ifdef __cplusplus
 }

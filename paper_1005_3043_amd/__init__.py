@@ -24,7 +24,9 @@ MAX_RHS = 16
 EXPORTED = ["wilson_apply", "mg_setup", "mg_set_precond_prec", "mg_set_timing", "mg_restrict",
             "mg_prolong", "coarse_apply", "mg_apply_op", "mg_set_coarse_variant", "mg_coarse_variant", "mg_solve", "mg_time_dslash", "mg_time_coarse",
             "mg_destroy", "mg_last_error", "mg_export_maps", "mg_export_P",
-            "mg_export_coarse_op", "mg_export_nullvecs", "mg_level_info"]
+            "mg_export_coarse_op", "mg_export_nullvecs", "mg_level_info",
+            "ptc_create", "ptc_set_links", "ptc_set_targets", "ptc_forward", "ptc_loss_grad", "ptc_adam",
+            "ptc_destroy"]
 
 
 class MGError(RuntimeError):
@@ -110,6 +112,13 @@ def lib():
             "mg_export_coarse_op": [vp, ci, vp, vp],
             "mg_export_nullvecs": [vp, ci, vp],
             "mg_level_info": [vp, ci, vp, vp],
+            "ptc_create": [ctypes.POINTER(Lattice), ctypes.POINTER(ci), ci, ci, ctypes.POINTER(vp)],
+            "ptc_set_links": [vp, vp, vp],
+            "ptc_set_targets": [vp, vp, ci, vp],
+            "ptc_forward": [vp, vp, vp, vp, vp, vp],
+            "ptc_loss_grad": [vp, vp, vp, vp, ctypes.POINTER(cd), vp, vp, vp],
+            "ptc_adam": [vp, vp, vp, vp, ctypes.c_size_t, ci, cd, cd, cd, cd, vp],
+            "ptc_destroy": [vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -326,3 +335,64 @@ class MG:
         V = np.zeros(shape, np.complex128)
         _check(lib().mg_export_nullvecs(self.ctx, level, ctypes.c_void_p(V.ctypes.data)))
         return V
+
+
+def _dev64(t: torch.Tensor, name: str):
+    if not (t.is_cuda and t.dtype == torch.complex64 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous complex64 device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class PTC:
+    """Owning handle of a ptc_ctx_t: the parallel-transport network that
+    proposes near-null vectors (weights complex64 [c_out][c_in][9][4][4])."""
+
+    def __init__(self, L, block, n_hidden=8, n_out=24, t_antiperiodic=True):
+        self.L = tuple(int(v) for v in L)
+        self.n_hidden, self.n_out = int(n_hidden), int(n_out)
+        lat = lattice(self.L, t_antiperiodic)
+        h = ctypes.c_void_p()
+        _check(lib().ptc_create(ctypes.byref(lat), (ctypes.c_int * 4)(*[int(b) for b in block]), self.n_hidden,
+                                self.n_out, ctypes.byref(h)))
+        self.ctx = h
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().ptc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_links(self, U):
+        _check(lib().ptc_set_links(self.ctx, _dev(U, "U"), _stream()))
+
+    def set_targets(self, V):
+        nv = int(V.shape[0])
+        _check(lib().ptc_set_targets(self.ctx, _dev(V, "V"), nv, _stream()))
+
+    def forward(self, W1, W2, eta):
+        Lx, Ly, Lz, Lt = self.L
+        Y = torch.empty((self.n_out, Lt, Lz, Ly, Lx, 4, 3), dtype=torch.complex128, device=eta.device)
+        _check(lib().ptc_forward(self.ctx, _dev64(W1, "W1"), _dev64(W2, "W2"), _dev(eta, "eta"), _dev(Y, "Y"),
+                                 _stream()))
+        return Y
+
+    def loss_grad(self, W1, W2, eta):
+        g1, g2 = torch.empty_like(W1), torch.empty_like(W2)
+        loss = ctypes.c_double()
+        _check(lib().ptc_loss_grad(self.ctx, _dev64(W1, "W1"), _dev64(W2, "W2"), _dev(eta, "eta"),
+                                   ctypes.byref(loss), _dev64(g1, "gW1"), _dev64(g2, "gW2"), _stream()))
+        return loss.value, g1, g2
+
+
+def ptc_adam(W, g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In-place Adam step on complex64 W with moments m (complex64) and v
+    (float32, 2 entries per parameter)."""
+    if not (v.is_cuda and v.dtype == torch.float32 and v.numel() == 2 * W.numel()):
+        raise ValueError("v must be a float32 device tensor with 2 entries per parameter")
+    _check(lib().ptc_adam(_dev64(W, "W"), _dev64(g, "g"), _dev64(m, "m"), ctypes.c_void_p(v.data_ptr()),
+                          W.numel(), int(step), float(lr), float(b1), float(b2), float(eps), _stream()))
