@@ -1,25 +1,31 @@
 #!/usr/bin/env python
 """Benchmark of the adaptive-MG Wilson-Dirac hot path on one MI355X.
 
-One step = one pass of the whole hot path on the two-level 16^3x32 workload
-(random SU(3) links with eps = 0.3, mass for min Re lambda(D) = 0.01,
-aggregates 4^4, Nv = 20, one complex Gaussian right-hand side):
-mg_setup (null-vector relaxation, block orthonormalisation, Galerkin D_c)
-followed by mg_solve to a 1e-10 relative residual with the FP32
-preconditioner (FP64 outer FGCR).  Inputs are generated on the host and
-resident in device memory before the timed region.
+One step = one pass of the whole hot path on the two-level 16^3 x 32 workload
+(random SU(3) links of generator width eps = 0.3, mass for min Re lambda(D) =
+0.01 from the oracle's Arnoldi estimate, aggregates 4^4, Nv = 20, one complex
+Gaussian right-hand side): mg_setup (null-vector relaxation, block
+orthonormalisation, Galerkin D_c) followed by mg_solve to a 1e-10 relative
+residual with the mixed-precision preconditioner (FP16-stored operators and
+FP32 arithmetic by default; FP64 outer FGCR).  Inputs are generated on the
+host and resident in device memory before the timed region.
 
-Prints one JSON line.  Besides the step throughput it reports the plain FP64
-MG time-to-solution on the same setup, the fine-stencil (dslash) GB/s
-measured live in the timed solves, the roofline of the dominant kernel, the
-dslash on the 32^3x64 lattice (working set far above the last-level cache),
-and the CPU oracle timed on a bounded sample.
+Prints one JSON line: the step throughput, time-to-solution against plain
+FP64 MG on the same setup, the roofline of the dominant kernel of the timed
+solves (device time from HIP events on the library's stream), the fine
+stencil on 32^3 x 64 (working set above the last-level cache) and the CPU
+oracle on a bounded sample.
+
+--kernel-probe runs fixed launches of the profiled kernels (a 1 GiB device
+copy for counter calibration, the coarse stencil of the workload in every
+precision, the 32^3 x 64 fine stencil) for rocprofv3 counter runs.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -28,10 +34,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 WORKLOAD = "C1"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "coarse_c1_traffic.txt")
 
-
-# bytes per real of (vectors, operators) for each precision class; "f16" keeps
-# FP32 vectors and stores the operators (links, P, D_c) in binary16
+# bytes per real of (vectors, operators) for each precision class; "f16"
+# keeps FP32 vectors and stores the operators (links, P, D_c) in binary16
 WIDTH = {"f64": (8.0, 8.0), "f32": (4.0, 4.0), "f16": (4.0, 2.0)}
 
 
@@ -42,7 +48,8 @@ def dslash_bytes(prec, compressed=False):
     return 48 * wv + 4 * (12 if compressed else 18) * wl
 
 
-def coarse_bytes(n, prec):    # 9 n^2 operator entries + vector in/out, per coarse site
+def coarse_bytes(n, prec):
+    """Per coarse site: 9 n^2 operator entries + vector in and out."""
     wv, wl = WIDTH[prec]
     return 2 * (9 * n * n * wl + 2 * n * wv)
 
@@ -61,26 +68,41 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precond", default="f32", choices=["f64", "f32", "f16"])
+    ap.add_argument("--precond", default="f16", choices=["f64", "f32", "f16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--kernel-probe", action="store_true")
     return ap.parse_args()
 
 
-def cpu_baseline(U_np, psi_np, mass):
-    """The numpy FP64 oracle Wilson operator on the same lattice (bounded sample)."""
+def workload(torch, W):
+    cfg = W.CONFIGS[WORKLOAD]
+    L = cfg["L"]
+    U_np = W.gauge_field(L, cfg["eps"], cfg["seed"])
+    b_np = W.gaussian_spinor(L, cfg["seed"])
+    st_np = W.setup_starts(L, cfg["nv"][0], cfg["seed"])
+    dev = torch.device("cuda:0")
+    return cfg, U_np, b_np, torch.from_numpy(U_np).to(dev), torch.from_numpy(b_np).to(dev), \
+        torch.from_numpy(st_np).to(dev)
+
+
+def cpu_baseline(U_np, psi_np, mass, n_d_per_step):
+    """Numpy FP64 oracle Wilson operator on the workload lattice; the oracle's
+    step rate is bounded above by 1 / (fine-D applications per step x time
+    per application)."""
     from oracle import wilson as wi
-    V = psi_np.size // 12
     wi.apply_D(U_np, psi_np, mass)
     n, t0 = 0, time.perf_counter()
-    while n < 3 or time.perf_counter() - t0 < 10.0:
+    while n < 3 or time.perf_counter() - t0 < 15.0:
         wi.apply_D(U_np, psi_np, mass)
         n += 1
     dt = (time.perf_counter() - t0) / n
-    return {"value": round(dslash_bytes("f64") * V / dt / 1e9, 3), "unit": "GB/s", "cores": 1,
+    return {"value": round(1.0 / (n_d_per_step * dt), 6), "unit": "solves/s (upper bound)", "cores": 1,
             "kind": "oracle",
             "sample": f"{n} applications of the numpy FP64 oracle Wilson operator on 16^3x32 "
-                      f"({dt * 1e3:.0f} ms each; numpy elementwise work is single-threaded)"}
+                      f"({dt * 1e3:.0f} ms each, numpy elementwise work on one core); rate = 1 / "
+                      f"({n_d_per_step} fine-D applications per step, setup + solve, as counted on the "
+                      f"GPU run x time per application), ignoring the oracle's coarse-level work"}
 
 
 def random_su3(torch, shape, g):
@@ -94,50 +116,86 @@ def random_su3(torch, shape, g):
     return torch.stack([r0, r1, r2], dim=-2).contiguous()
 
 
-def large_dslash(mgwd, torch):
-    """Fine stencil on the 32^3x64 lattice (links and vectors 2-4x the last-level cache)."""
+def large_ctx(mgwd, torch):
     L = (32, 32, 32, 64)
     g = torch.Generator(device="cuda").manual_seed(0)
     U = random_su3(torch, (4, L[3], L[2], L[1], L[0]), g)
     v = torch.randn((1, L[3], L[2], L[1], L[0], 4, 3), dtype=torch.complex128, device="cuda", generator=g)
     ctx = mgwd.MG(U, 0.1, [(4, 4, 4, 4)], [1], [v], setup_rounds=0)
+    return L, ctx
+
+
+def large_dslash(mgwd, torch):
+    """Fine stencil on the 32^3x64 lattice (links and vectors 2-4x the last-level cache)."""
+    L, ctx = large_ctx(mgwd, torch)
     out = {}
     V = L[0] * L[1] * L[2] * L[3]
     for prec in ("f64", "f32", "f16"):
         ms = ctx.time_dslash(prec, 1, 30)
-        gbs = dslash_bytes(prec) * V / (ms * 1e-3) / 1e9
         gbs_fmt = dslash_bytes(prec, compressed=True) * V / (ms * 1e-3) / 1e9
-        out[prec] = {"ms": round(ms, 4), "GBps_18real_equiv": round(gbs, 1),
-                     "GBps_stored_format": round(gbs_fmt, 1), "frac_hbm": round(gbs_fmt / HBM_PEAK_GBPS, 3),
-                     "TFLOPs": round(dslash_flops(True) * V / (ms * 1e-3) / 1e12, 2)}
+        out[prec] = {"ms": round(ms, 4), "GBps": round(gbs_fmt, 1), "frac_hbm": round(gbs_fmt / HBM_PEAK_GBPS, 3),
+                     "TFLOPs": round(dslash_flops(True) * V / (ms * 1e-3) / 1e12, 2),
+                     "bytes_per_site": dslash_bytes(prec, True)}
     ctx.close()
-    del U, v
     torch.cuda.empty_cache()
     return out
+
+
+def stored_traffic(kernel, workload_name):
+    """Per-launch HBM traffic of the dominant kernel from the committed
+    rocprofv3 counter summary, if it was taken on this kernel and workload."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                m = re.match(r"^TRAFFIC\s+(\S+)\s+(\S+)\s+bytes_per_launch=(\S+)", line)
+                if m and m.group(1) == kernel and m.group(2) == workload_name:
+                    return float(m.group(3))
+    except OSError:
+        pass
+    return None
+
+
+def kernel_probe(mgwd, torch, W):
+    """Fixed launches for counter runs (one process, printed as they go)."""
+    n = 1 << 27  # 1 GiB of float64
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "copy", "bytes_read": n * 8, "bytes_written": n * 8, "launches": 5}), flush=True)
+    del a, b
+    cfg, U_np, b_np, U, b, starts = workload(torch, W)
+    ctx = mgwd.MG(U, W.mass_for(WORKLOAD), cfg["blocks"], cfg["nv"], [starts])
+    for prec in ("f64", "f32", "f16"):
+        ms = ctx.time_coarse(1, prec, 1, 20)
+        print(json.dumps({"probe": f"coarse_{prec}", "launches": 22, "avg_ms": ms}), flush=True)
+    ctx.close()
+    Lg, lctx = large_ctx(mgwd, torch)
+    for prec in ("f64", "f32", "f16"):
+        ms = lctx.time_dslash(prec, 1, 20)
+        print(json.dumps({"probe": f"dslash_{prec}_32^3x64", "launches": 22, "avg_ms": ms}), flush=True)
+    lctx.close()
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU path is design-only.",
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); multi-GPU execution is not built.",
               file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     import paper_1005_3043_amd as mgwd
     import workloads as W
 
-    cfg = W.CONFIGS[WORKLOAD]
+    if a.kernel_probe:
+        kernel_probe(mgwd, torch, W)
+        return
+
+    cfg, U_np, b_np, U, b, starts = workload(torch, W)
     L, nv, blocks = cfg["L"], cfg["nv"], cfg["blocks"]
     mass = W.mass_for(WORKLOAD)
-    U_np = W.gauge_field(L, cfg["eps"], cfg["seed"])
-    b_np = W.gaussian_spinor(L, cfg["seed"])
-    st_np = W.setup_starts(L, nv[0], cfg["seed"])
-    dev = torch.device("cuda:0")
-    U = torch.from_numpy(U_np).to(dev)
-    b = torch.from_numpy(b_np).to(dev)
-    starts = torch.from_numpy(st_np).to(dev)
     V = L[0] * L[1] * L[2] * L[3]
     n_c = 2 * nv[0]
     Vc = V // 256
@@ -169,8 +227,9 @@ def main():
     r = b - mgwd.wilson_apply(U, x, mass)
     true_res = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b))
 
-    # plain FP64 MG on the same workload (time-to-solution reference)
+    # plain FP64 MG and the FP32 preconditioner on the same workload
     _, info64 = step("f64", True)
+    _, info32 = step("f32", True)
 
     # kernel-class aggregates over the timed steps.  Coarse-stencil bytes
     # count only effective applications (n_coarse_apply); the time includes
@@ -199,14 +258,17 @@ def main():
     kern = {k: achieved(k) for k in agg if achieved(k) is not None}
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     kd = kern[dom]
-    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(kd["GBps"], 1), "peak": HBM_PEAK_GBPS,
-                "unit": "GB/s", "frac": round(kd["GBps"] / HBM_PEAK_GBPS, 4), "traffic": None,
-                "avg_launch_us": round(kd["avg_us"], 2), "bytes_per_launch": kd["bytes_per_launch"]}
+    traffic = stored_traffic(dom, WORKLOAD)
+    roofline = {"bound": "hbm", "achieved": round(kd["GBps"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(kd["GBps"] / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                "kernel": dom, "avg_launch_us": round(kd["avg_us"], 2),
+                "bytes_per_launch": round(kd["bytes_per_launch"])}
 
     solve_s = sum(i["t_solve_s"] for i in infos) / len(infos)
     setup_s = sum(i["t_setup_s"] for i in infos) / len(infos)
     dsl = {k: {"GBps": round(v["GBps"], 1), "avg_us": round(v["avg_us"], 2), "launches": v["launches"]}
            for k, v in kern.items()}
+    n_d_setup = 5 * (1 + 4) * nv[0]
     out = {
         "metric": "dslash HBM GB/s; MG time-to-solution to 1e-10 rel. residual vs plain FP64 MG",
         "value": round(1e3 / ms_step, 4),
@@ -214,7 +276,8 @@ def main():
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": round(ms_step, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64 outer / " + a.precond + " preconditioner",
+        "dtype": "f64 outer / " + {"f16": "f16-stored operators, f32 arithmetic", "f32": "f32",
+                                   "f64": "f64"}[a.precond] + " preconditioner",
         "data": "synthetic (seeded random SU(3) links, Gaussian source)",
         "config": {"workload": f"two-level MG, {L[0]}^3x{L[3]}, eps {cfg['eps']}, min Re lambda "
                                f"{cfg['targets'][0]}, aggregates 4^4, Nv {nv[0]}, 1 RHS",
@@ -222,8 +285,9 @@ def main():
         "time_to_solution_s": round(solve_s, 4),
         "setup_s": round(setup_s, 4),
         "fp64_plain_time_to_solution_s": round(info64["t_solve_s"], 4),
+        "fp32_time_to_solution_s": round(info32["t_solve_s"], 4),
         "speedup_vs_plain_fp64": round(info64["t_solve_s"] / solve_s, 3),
-        "iters": infos[-1]["iters"][0], "iters_fp64": info64["iters"][0],
+        "iters": infos[-1]["iters"][0], "iters_fp64": info64["iters"][0], "iters_fp32": info32["iters"][0],
         "true_rel_resid": true_res,
         "fine_dslash_per_solve": infos[-1]["n_fine_dslash"],
         "cgnr_iters_per_solve": infos[-1]["n_cgnr_iters"],
@@ -233,7 +297,7 @@ def main():
     if not a.no_large:
         out["dslash_32^3x64"] = large_dslash(mgwd, torch)
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(U_np, b_np, mass)
+        out["cpu_baseline"] = cpu_baseline(U_np, b_np, mass, n_d_setup + infos[-1]["n_fine_dslash"])
     print(json.dumps(out), flush=True)
 
 

@@ -56,6 +56,24 @@ template <> struct OpVec<chalf, 4> {
   }
 };
 
+// Site read by stencil slot `slot` of coarse site s: slot 0 = s, slot
+// 1 + 2 mu + dir = the neighbour in direction mu (dir 0 forward, 1 backward).
+// The switch keeps every coordinate index a constant (no private arrays).
+__device__ __forceinline__ uint32_t slot_site(const Geom &g, uint32_t s, int slot) {
+  const Coords k = decode(g, s);
+  switch (slot) {
+    case 1: return nbr_fwd(g, s, k, 0);
+    case 2: return nbr_bwd(g, s, k, 0);
+    case 3: return nbr_fwd(g, s, k, 1);
+    case 4: return nbr_bwd(g, s, k, 1);
+    case 5: return nbr_fwd(g, s, k, 2);
+    case 6: return nbr_bwd(g, s, k, 2);
+    case 7: return nbr_fwd(g, s, k, 3);
+    case 8: return nbr_bwd(g, s, k, 3);
+    default: return s;
+  }
+}
+
 // Sum of np partials over the workgroup; result in every thread.
 __device__ __forceinline__ double block_allsum_partials(const double *__restrict__ p, int np, double *lds) {
   double a = 0.0;
@@ -119,15 +137,12 @@ __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restri
     const int p = grp + q * G;
     lv[q] = (on && p < nP) ? Ls[(size_t)p * nu] : VT{};
   }
-  const Coords k = decode(g, s);
+  __shared__ uint32_t nbs[9];
+  if (tid < 9) nbs[tid] = slot_site(g, s, tid);
+  __syncthreads();
   for (int idx = tid; idx < nP; idx += blockDim.x) {
     const int slot = idx / n, j = idx - slot * n;
-    uint32_t site = s;
-    if (slot > 0) {
-      const int d = slot - 1, mu = d >> 1;
-      site = (d & 1) ? nbr_bwd(g, s, k, mu) : nbr_fwd(g, s, k, mu);
-    }
-    C v = in[(size_t)site * n + j];
+    C v = in[(size_t)nbs[slot] * n + j];
     if (dagger && j >= (n >> 1)) v = mk<C>(-v.x, -v.y);
     vin[idx] = v;
   }
@@ -284,17 +299,14 @@ __global__ __launch_bounds__(1024) void k_coarse_mma(Geom g, int n, const S *__r
     }
   };
   load_batch(abuf[0], 0);
-  const Coords k = decode(g, s);
+  __shared__ uint32_t nbs[9];
+  if (tid < 9) nbs[tid] = slot_site(g, s, tid);
+  __syncthreads();
   {
     const int jj = tid % n, tstep = (int)blockDim.x / n;
     for (int t = tid / n; t < 9 * nrhs && jj < n && tid < tstep * n; t += tstep) {
       const int r = t % nrhs, slot = t / nrhs;
-      uint32_t site = s;
-      if (slot > 0) {
-        const int d = slot - 1, mu = d >> 1;
-        site = (d & 1) ? nbr_bwd(g, s, k, mu) : nbr_fwd(g, s, k, mu);
-      }
-      float2 v = in[((size_t)r * g.V + site) * n + jj];
+      float2 v = in[((size_t)r * g.V + nbs[slot]) * n + jj];
       if (dagger && jj >= half) v = make_float2(-v.x, -v.y);
       bl[(slot * n + jj) * nrhs + r] = v;
     }
