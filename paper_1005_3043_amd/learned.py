@@ -1,0 +1,192 @@
+"""Learned proposal of near-null vectors: training on the plain setup's vectors
+and use inside mg_setup, with the plain relaxation as fallback.
+
+Orchestration of library calls only: the network's forward and backward
+passes, the subspace-fit loss and the Adam step run in the library's kernels
+(ptc_*), the targets come from mg_setup's relaxation (mg_export_nullvecs) and
+the evaluation from mg_setup / mg_solve.
+
+    python -m paper_1005_3043_amd.learned [--quick]
+
+trains on seeded 16^3 x 32 fields (generator width 0.3) and evaluates setup
+time and outer FGCR iterations on held-out 24^3 x 48 fields against the plain
+relaxation setup, printing one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import MG, PTC, ptc_adam
+
+
+def plain_nullvecs(U, mass, block, nv, starts, rounds=5):
+    """The relaxed null-space candidates of the plain setup (device complex128)."""
+    ctx = MG(U, mass, [block], [nv], [starts], setup_rounds=rounds)
+    V = torch.from_numpy(ctx.export_nullvecs(0)).to(U.device)
+    ctx.close()
+    return V
+
+
+class Proposal:
+    """Weights of the two-layer network (device complex64) and its optimiser state."""
+
+    def __init__(self, W1, W2):
+        self.W1 = torch.as_tensor(W1).to(torch.complex64).cuda().contiguous()
+        self.W2 = torch.as_tensor(W2).to(torch.complex64).cuda().contiguous()
+        self.m = [torch.zeros_like(self.W1), torch.zeros_like(self.W2)]
+        self.v = [torch.zeros(2 * self.W1.numel(), dtype=torch.float32, device="cuda"),
+                  torch.zeros(2 * self.W2.numel(), dtype=torch.float32, device="cuda")]
+        self.step = 0
+
+    @property
+    def n_hidden(self):
+        return self.W1.shape[0]
+
+    @property
+    def n_out(self):
+        return self.W2.shape[0]
+
+
+def train(prop: Proposal, net: PTC, fields, noise, steps, lr=1e-3, log=None):
+    """Adam on the subspace-fit loss, cycling over (U, V) training fields with
+    fresh noise every step; returns the loss history."""
+    hist = []
+    for it in range(steps):
+        U, V = fields[it % len(fields)]
+        net.set_links(U)
+        net.set_targets(V)
+        loss, g1, g2 = net.loss_grad(prop.W1, prop.W2, noise(it))
+        prop.step += 1
+        ptc_adam(prop.W1, g1, prop.m[0], prop.v[0], prop.step, lr=lr)
+        ptc_adam(prop.W2, g2, prop.m[1], prop.v[1], prop.step, lr=lr)
+        hist.append(loss)
+        if log and (it % 50 == 0 or it == steps - 1):
+            log(f"step {it}: loss {loss:.5f}")
+    return hist
+
+
+def learned_setup(U, mass, block, prop: Proposal, net: PTC, eta, rounds, **kw):
+    """mg_setup started from the network's proposal with `rounds` relaxation
+    rounds (0 = use the proposal as is)."""
+    net.set_links(U)
+    Y = net.forward(prop.W1, prop.W2, eta)
+    return MG(U, mass, [block], [prop.n_out], [Y], setup_rounds=rounds, **kw)
+
+
+def solve_with_fallback(U, mass, block, prop, net, eta, rounds, b, plain_starts, max_iters, tol=1e-10,
+                        precond="f16"):
+    """Learned setup judged by its outer iteration count: if the solve needs
+    more than max_iters iterations (or fails), redo it with the plain
+    relaxation setup.  Returns (x, info, used_fallback, setup_s)."""
+    t0 = time.perf_counter()
+    ctx = learned_setup(U, mass, block, prop, net, eta, rounds)
+    setup_s = time.perf_counter() - t0
+    ctx.set_precond_prec(precond)
+    x, info, rc = ctx.solve(b, tol)
+    ctx.close()
+    if rc == 0 and info["iters"][0] <= max_iters:
+        return x, info, False, setup_s
+    t0 = time.perf_counter()
+    ctx = MG(U, mass, [block], [prop.n_out], [plain_starts])
+    setup_s += time.perf_counter() - t0
+    ctx.set_precond_prec(precond)
+    x, info, rc = ctx.solve(b, tol)
+    ctx.close()
+    return x, info, True, setup_s
+
+
+def evaluate(prop, U, mass, block, eta, b, starts, rounds_list, precond="f16"):
+    """Setup time and outer iterations: Gaussian starts with 0, 1, 2 and 5
+    relaxation rounds (5 = the plain setup) and the learned proposal with each
+    number of rounds in rounds_list."""
+    from . import PTC as _PTC
+    Lt, Lz, Ly, Lx = U.shape[1:5]
+    net = _PTC((Lx, Ly, Lz, Lt), block, prop.n_hidden, prop.n_out)
+    out = {}
+
+    def run(make):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx = make()
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        ctx.set_precond_prec(precond)
+        _, info, rc = ctx.solve(b, 1e-10)
+        ctx.close()
+        return {"setup_s": round(ts, 4), "iters": info["iters"][0], "solve_s": round(info["t_solve_s"], 4),
+                "converged": rc == 0}
+
+    for r in (0, 1, 2, 5):
+        out[f"plain_r{r}"] = run(lambda r=r: MG(U, mass, [block], [prop.n_out], [starts], setup_rounds=r))
+    for r in rounds_list:
+        out[f"learned_r{r}"] = run(lambda r=r: learned_setup(U, mass, block, prop, net, eta, r))
+    net.close()
+    return out
+
+
+def main():
+    import workloads as W
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--quick", action="store_true", help="small lattices and few steps")
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--neval", type=int, default=None)
+    a = ap.parse_args()
+    if a.quick:
+        Ltr, Lev, nfields, neval, steps, nout = (8, 8, 8, 16), (8, 8, 8, 16), 4, 2, 200, 12
+    else:
+        Ltr, Lev, nfields, neval, steps, nout = (16, 16, 16, 32), (24, 24, 24, 48), 20, 10, 600, 24
+    if a.steps:
+        steps = a.steps
+    if a.neval:
+        neval = a.neval
+    block = (4, 4, 4, 4)
+    n_hidden = 8
+    mass_tr = W.mass_for("C1")
+    mass_ev = W.mass_for("C2")
+    t0 = time.perf_counter()
+    fields = []
+    for i in range(nfields):
+        seed = 1000 + i
+        U = torch.from_numpy(W.gauge_field(Ltr, 0.3, seed)).cuda()
+        st = torch.from_numpy(W.setup_starts(Ltr, nout, seed)).cuda()
+        fields.append((U, plain_nullvecs(U, mass_tr, block, nout, st)))
+    t_targets = time.perf_counter() - t0
+    prop = Proposal(*W.ptc_init_weights(n_hidden, nout, 0))
+    net = PTC(Ltr, block, n_hidden, nout)
+    noise = lambda it: torch.from_numpy(W.noise_spinor(Ltr, 10_000 + it)).cuda()
+    t0 = time.perf_counter()
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)
+    log(f"targets from the plain setup on {nfields} fields: {t_targets:.1f} s")
+    hist = train(prop, net, fields, noise, steps, lr=a.lr, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    net.close()
+    evals = []
+    for i in range(neval):
+        seed = 2000 + i
+        U = torch.from_numpy(W.gauge_field(Lev, 0.3, seed)).cuda()
+        st = torch.from_numpy(W.setup_starts(Lev, nout, seed)).cuda()
+        b = torch.from_numpy(W.gaussian_spinor(Lev, seed)).cuda()
+        eta = torch.from_numpy(W.noise_spinor(Lev, seed)).cuda()
+        evals.append(evaluate(prop, U, mass_ev, block, eta, b, st, (0, 1, 2)))
+        log(f"evaluated field {seed}: " + ", ".join(f"{k} {v['iters']}" for k, v in evals[-1].items()))
+    keys = evals[0].keys()
+    summary = {k: {"setup_s": round(float(np.mean([e[k]["setup_s"] for e in evals])), 4),
+                   "iters": round(float(np.mean([e[k]["iters"] for e in evals])), 2),
+                   "solve_s": round(float(np.mean([e[k]["solve_s"] for e in evals])), 4)} for k in keys}
+    print(json.dumps({"train": {"lattice": Ltr, "fields": nfields, "steps": steps, "n_out": nout, "lr": a.lr,
+                                "loss_first": hist[0], "loss_last": float(np.mean(hist[-len(fields):])),
+                                "targets_s": round(t_targets, 2), "train_s": round(t_train, 2),
+                                "ms_per_step": round(1e3 * t_train / steps, 2)},
+                      "eval": {"lattice": Lev, "fields": neval, "mass": mass_ev, "mean": summary}}), flush=True)
+
+
+if __name__ == "__main__":
+    main()
