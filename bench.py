@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--kernel-probe", action="store_true")
+    ap.add_argument("--workload", default="C1", choices=["C1", "C2", "C3"],
+                    help="C1: the benchmark step; C2: 12 batched point sources on 24^3x48 against 12 plain "
+                         "FP64 single-RHS solves; C3: three-level 32^3x64, 12 point sources, mass sweep")
     return ap.parse_args()
 
 
@@ -178,6 +181,66 @@ def kernel_probe(mgwd, torch, W):
     lctx.close()
 
 
+def multi_rhs_report(mgwd, torch, W):
+    """12 point sources on 24^3x48 in one batched FP16-preconditioned solve
+    against plain FP64 MG run once per source on the same setup."""
+    cfg = W.CONFIGS["C2"]
+    L, nv, blocks = cfg["L"], cfg["nv"], cfg["blocks"]
+    U = torch.from_numpy(W.gauge_field(L, cfg["eps"], cfg["seed"])).cuda()
+    st = torch.from_numpy(W.setup_starts(L, nv[0], cfg["seed"])).cuda()
+    mass = W.mass_for("C2")
+    b = torch.from_numpy(W.point_sources(L)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx = mgwd.MG(U, mass, blocks, nv, [st], max_rhs=12)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    ctx.set_precond_prec("f16")
+    ctx.solve(b[:12], 1e-10)  # warm-up: graphs, autotuning
+    x, info, rc = ctx.solve(b, 1e-10)
+    var, us = ctx.coarse_variant(1, "f16", 12)
+    ctx.set_precond_prec("f64")
+    t64, it64 = 0.0, []
+    for i in range(12):
+        _, i1, _ = ctx.solve(b[i:i + 1].contiguous(), 1e-10)
+        t64 += i1["t_solve_s"]
+        it64.append(i1["iters"][0])
+    ctx.close()
+    return {"workload": "24^3x48, eps 0.3, aggregates 4^4, Nv 24, 12 point sources", "mass": mass,
+            "setup_s": round(setup_s, 3), "batched_f16_solve_s": round(info["t_solve_s"], 3),
+            "batched_iters": info["iters"][:12], "plain_f64_12_solves_s": round(t64, 3), "plain_f64_iters": it64,
+            "speedup": round(t64 / info["t_solve_s"], 2), "coarse_variant_12rhs": var,
+            "coarse_12rhs_us": round(us, 1), "converged": rc == 0}
+
+
+def three_level_report(mgwd, torch, W):
+    """Three-level MG on 32^3x64 with 12 point sources at the three nominal
+    masses: outer iterations and time-to-solution (FP32 preconditioner)."""
+    cfg = W.CONFIGS["C3"]
+    L, nv, blocks = cfg["L"], cfg["nv"], cfg["blocks"]
+    U = torch.from_numpy(W.gauge_field(L, cfg["eps"], cfg["seed"])).cuda()
+    st = torch.from_numpy(W.setup_starts(L, nv[0], cfg["seed"])).cuda()
+    Lc = tuple(L[mu] // blocks[0][mu] for mu in range(4))
+    st1 = torch.from_numpy(W.coarse_setup_starts(Lc, 2 * nv[0], nv[1], cfg["seed"])).cuda()
+    b = torch.from_numpy(W.point_sources(L)).cuda()
+    rows = []
+    for target in cfg["targets"]:
+        mass = W.mass_for("C3", target)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx = mgwd.MG(U, mass, blocks, nv, [st, st1], max_rhs=12, precond_prec="f32")
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        x, info, rc = ctx.solve(b, 1e-10)
+        ctx.close()
+        rows.append({"min_re_lambda_nominal": target, "mass": mass, "setup_s": round(setup_s, 3),
+                     "solve_s": round(info["t_solve_s"], 3), "iters_mean": round(float(sum(info["iters"][:12])) / 12, 1),
+                     "iters_max": max(info["iters"][:12]), "converged": rc == 0})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    return {"workload": "32^3x64, eps 0.35, aggregates 4^4 then 2^4, Nv 24/24, 12 point sources, FP32 "
+                        "preconditioner", "sweep": rows, "dslash_32^3x64": large_dslash(mgwd, torch)}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -191,6 +254,12 @@ def main():
 
     if a.kernel_probe:
         kernel_probe(mgwd, torch, W)
+        return
+    if a.workload == "C2":
+        print(json.dumps(multi_rhs_report(mgwd, torch, W)), flush=True)
+        return
+    if a.workload == "C3":
+        print(json.dumps(three_level_report(mgwd, torch, W)), flush=True)
         return
 
     cfg, U_np, b_np, U, b, starts = workload(torch, W)
