@@ -57,7 +57,131 @@ __device__ __forceinline__ void fine_hop(double2 (&f)[12], const Geom &g, uint32
   for (int c = 0; c < 12; ++c) f[c] = cfma(make_double2(-0.5, 0.0), acc[c], f[c]);
 }
 
+// One workgroup per (aggregate, column j); one thread per site of the
+// aggregate.  Each thread forms the slot-0 vector (diagonal plus the hops
+// that stay inside the aggregate) and the face hops of its site; since an
+// aggregate is at least two sites wide in every direction a site lies on at
+// most one face per direction, so direction mu contributes one hop vector,
+// credited to slot 1 + 2 mu (upper face) or 2 + 2 mu (lower face).  The
+// projections onto the nv null vectors then load P_ki once per pass for all
+// slots of the pass (pass 0: slot 0 and directions x, y; pass 1: directions
+// z, t) instead of once per slot.
+template <int PASS>
+__device__ __forceinline__ void galerkin_pass(const Geom &g, uint32_t s, const Coords &k, bool act, int chi,
+                                              double diag, const double2 *__restrict__ U,
+                                              const double2 *__restrict__ Pj, const double2 *__restrict__ P,
+                                              int nv, int jcol, int n, uint32_t ic, double2 (*part)[2 * COARSE_NMAX],
+                                              double2 *__restrict__ Lc) {
+  constexpr int NS = PASS == 0 ? 3 : 2;  // vectors of this pass: [slot0,] mu, mu + 1
+  constexpr int MU0 = PASS == 0 ? 0 : 2;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = (blockDim.x + 63) >> 6;
+  const size_t V = g.Vpad;
+  double2 f[NS][12];
+  bool up[NS];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    up[q] = false;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) f[q][c] = make_double2(0, 0);
+  }
+  if (act) {
+    int q0 = 0;
+    if constexpr (PASS == 0) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c)
+        if ((c / 6) == chi) f[0][c] = cscale(Pj[fidx(s, c, 12)], diag);
+#pragma unroll
+      for (int d = 0; d < 8; ++d) {
+        const int mu = d >> 1;
+        const bool face = (d & 1) == 0 ? (k.o[mu] == g.b[mu] - 1) : (k.o[mu] == 0);
+        if (!face) fine_hop(f[0], g, s, k, d, U, Pj, chi);
+      }
+      q0 = 1;
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int mu = MU0 + m;
+      if (k.o[mu] == g.b[mu] - 1) {
+        fine_hop(f[q0 + m], g, s, k, 2 * mu, U, Pj, chi);
+        up[q0 + m] = true;
+      } else if (k.o[mu] == 0) {
+        fine_hop(f[q0 + m], g, s, k, 2 * mu + 1, U, Pj, chi);
+      }
+    }
+  }
+  // slots of this pass: slot 0 (pass 0), then (up, down) per direction
+  constexpr int NSLOT = PASS == 0 ? 5 : 4;
+  for (int ki = 0; ki < nv; ++ki) {
+    const double2 *Pi = P + (size_t)ki * 12 * V;
+    double2 pi[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) pi[c] = act ? Pi[fidx(s, c, 12)] : make_double2(0, 0);
+    double2 dv[NS][2];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      double2 d0 = make_double2(0, 0), d1 = make_double2(0, 0);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) d0 = cfmac(pi[c], f[q][c], d0);
+#pragma unroll
+      for (int c = 6; c < 12; ++c) d1 = cfmac(pi[c], f[q][c], d1);
+      dv[q][0] = d0;
+      dv[q][1] = d1;
+    }
+#pragma unroll
+    for (int sl = 0; sl < NSLOT; ++sl) {
+      // value of slot sl for this lane
+      double2 v0, v1;
+      if (PASS == 0 && sl == 0) {
+        v0 = dv[0][0];
+        v1 = dv[0][1];
+      } else {
+        const int qi = (PASS == 0 ? 1 : 0) + (sl - (PASS == 0 ? 1 : 0)) / 2;
+        const bool want_up = ((sl - (PASS == 0 ? 1 : 0)) % 2) == 0;
+        const bool mine = up[qi] == want_up;
+        v0 = mine ? dv[qi][0] : make_double2(0, 0);
+        v1 = mine ? dv[qi][1] : make_double2(0, 0);
+      }
+      const double a0 = wave_sum(v0.x), b0 = wave_sum(v0.y), a1 = wave_sum(v1.x), b1 = wave_sum(v1.y);
+      if (lane == 0) {
+        part[w * NSLOT + sl][ki] = make_double2(a0, b0);
+        part[w * NSLOT + sl][nv + ki] = make_double2(a1, b1);
+      }
+    }
+  }
+  __syncthreads();
+  for (int o = tid; o < NSLOT * n; o += blockDim.x) {
+    const int sl = o / n, i = o % n;
+    double2 a = part[sl][i];
+    for (int q = 1; q < nw; ++q) {
+      a.x += part[q * NSLOT + sl][i].x;
+      a.y += part[q * NSLOT + sl][i].y;
+    }
+    const int slot = PASS == 0 ? sl : 5 + sl;
+    Lc[(((size_t)ic * 9 + slot) * n + jcol) * n + i] = a;
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(256) void k_galerkin_fine(Geom g, Geom gc, double diag, const double2 *__restrict__ U,
+                                                       int nv, const double2 *__restrict__ P,
+                                                       double2 *__restrict__ Lc) {
+  __shared__ double2 part[4 * 5][2 * COARSE_NMAX];
+  const uint32_t B = blockIdx.x;
+  const int jcol = blockIdx.y, chi = jcol / nv, kj = jcol % nv;
+  const int n = 2 * nv;
+  const int tid = threadIdx.x;
+  const bool act = (uint32_t)tid < g.vb;
+  const uint32_t s = B * g.vb + (act ? tid : 0);
+  const Coords k = decode(g, s);
+  const double2 *Pj = P + (size_t)kj * 12 * g.Vpad;
+  const uint32_t ic = coarse_site_of(gc, B, g);
+  galerkin_pass<0>(g, s, k, act, chi, diag, U, Pj, P, nv, jcol, n, ic, part, Lc);
+  galerkin_pass<1>(g, s, k, act, chi, diag, U, Pj, P, nv, jcol, n, ic, part, Lc);
+}
+
+// Any aggregate shape (also one site wide in some direction, where a site
+// lies on both faces): one slot at a time.
+__global__ __launch_bounds__(256) void k_galerkin_fine_generic(Geom g, Geom gc, double diag, const double2 *__restrict__ U,
                                                        int nv, const double2 *__restrict__ P,
                                                        double2 *__restrict__ Lc) {
   __shared__ double2 part[4][2 * COARSE_NMAX];
@@ -122,7 +246,12 @@ __global__ __launch_bounds__(256) void k_galerkin_fine(Geom g, Geom gc, double d
 hipError_t galerkin_fine(const Geom &g, const Geom &gc, double mass, const double2 *U, int nv, const double2 *P,
                          double2 *Lc, hipStream_t st) {
   const int th = (int)((g.vb + 63) / 64 * 64);
-  hipLaunchKernelGGL(k_galerkin_fine, dim3(g.Vc, 2 * nv), dim3(th), 0, st, g, gc, 4.0 + mass, U, nv, P, Lc);
+  const bool wide = g.b[0] > 1 && g.b[1] > 1 && g.b[2] > 1 && g.b[3] > 1;
+  if (wide)
+    hipLaunchKernelGGL(k_galerkin_fine, dim3(g.Vc, 2 * nv), dim3(th), 0, st, g, gc, 4.0 + mass, U, nv, P, Lc);
+  else
+    hipLaunchKernelGGL(k_galerkin_fine_generic, dim3(g.Vc, 2 * nv), dim3(th), 0, st, g, gc, 4.0 + mass, U, nv, P,
+                       Lc);
   return hipGetLastError();
 }
 
