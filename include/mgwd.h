@@ -92,6 +92,9 @@ typedef struct {
   double rel_resid[MG_MAX_RHS]; /* final true ||b - D x|| / ||b|| per RHS    */
   int n_fine_dslash;            /* fine D applications (per RHS summed)      */
   int n_coarse_apply;           /* coarse stencil applications, all levels   */
+  int n_coarse_dispatch;        /* coarse stencil applications dispatched,
+                                   including those that returned at once
+                                   because their RHS had converged        */
   int n_cgnr_iters;             /* coarsest CGNR iterations, summed          */
   int n_vcycles;                /* preconditioner applications               */
   double t_setup_s, t_solve_s;  /* wall time of the last setup / solve       */

@@ -62,6 +62,7 @@ class Info(ctypes.Structure):
                 ("rel_resid", ctypes.c_double * MAX_RHS),
                 ("n_fine_dslash", ctypes.c_int),
                 ("n_coarse_apply", ctypes.c_int),
+                ("n_coarse_dispatch", ctypes.c_int),
                 ("n_cgnr_iters", ctypes.c_int),
                 ("n_vcycles", ctypes.c_int),
                 ("t_setup_s", ctypes.c_double), ("t_solve_s", ctypes.c_double),
@@ -74,6 +75,7 @@ class Info(ctypes.Structure):
     def as_dict(self, nrhs=1):
         return dict(iters=list(self.iters[:nrhs]), rel_resid=list(self.rel_resid[:nrhs]),
                     n_fine_dslash=self.n_fine_dslash, n_coarse_apply=self.n_coarse_apply,
+                    n_coarse_dispatch=self.n_coarse_dispatch,
                     n_cgnr_iters=self.n_cgnr_iters, n_vcycles=self.n_vcycles,
                     t_setup_s=self.t_setup_s, t_solve_s=self.t_solve_s,
                     kernels={k: dict(ms=self.kernel_ms[i], launches=self.kernel_launches[i],

@@ -266,7 +266,7 @@ extern "C" int mg_solve(mg_ctx_t *ctx, const void *b, void *x, int nrhs, double 
   if (c->prec == MG_F64) MG_TRY(ensure_work<double>(c, nrhs));
   else MG_TRY(ensure_work<float>(c, nrhs));
   MG_TRY(ensure_scalars(c, part_need(c, nrhs)));
-  c->n_fine = c->n_coarse = c->n_cgnr = c->n_vcyc = 0;
+  c->n_fine = c->n_coarse = c->n_coarse_disp = c->n_cgnr = c->n_vcyc = 0;
   for (auto &t : c->tm) t.reset();
   HIPK(hipStreamSynchronize(st));
   const double t0 = now_s();
@@ -296,6 +296,7 @@ extern "C" int mg_solve(mg_ctx_t *ctx, const void *b, void *x, int nrhs, double 
     info->n_fine_dslash = (int)c->n_fine;
     info->n_coarse_apply = (int)c->n_coarse;
     info->n_cgnr_iters = (int)c->n_cgnr;
+    info->n_coarse_dispatch = (int)c->n_coarse_disp;
     info->n_vcycles = (int)c->n_vcyc;
     info->t_setup_s = c->t_setup;
     info->t_solve_s = t1 - t0;

@@ -27,6 +27,7 @@
 namespace mg {
 
 constexpr int CO_CHUNK = 8;   // operator loads in flight per thread
+constexpr int CO_PARTS = 8;   // first-stage partial sums per row of the group reduction
 
 // 16-byte (or 8-byte) load of RW consecutive operator entries in storage S.
 template <typename S, int RW> struct OpVec;
@@ -99,6 +100,7 @@ __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restri
   using VT = typename OpVec<S, RW>::V;
   __shared__ C vin[9 * COARSE_NMAX];
   __shared__ C red[512 * RW];
+  __shared__ C red2[CO_PARTS * COARSE_NMAX];
   __shared__ double wred[8 * 3];
   const int rhs = blockIdx.y;
   if (done != nullptr && done[rhs]) return;
@@ -173,12 +175,24 @@ __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restri
 #pragma unroll
   for (int q = 0; q < RW; ++q) red[tid * RW + q] = acc[q];
   __syncthreads();
+  // Sum of the G group partials of every row in two fixed-order stages:
+  // CO_PARTS threads per row add every CO_PARTS-th group, then one thread
+  // per row adds the CO_PARTS results (short dependent chains in LDS).
+  if (tid < nr * CO_PARTS) {
+    const int i = tid % nr, part = tid / nr;
+    const int ipr = i / RW, sub = i % RW;
+    C sum = mk<C>(0, 0);
+    for (int q = part; q < G; q += CO_PARTS) sum = cadd(sum, red[(q * npr + ipr) * RW + sub]);
+    red2[part * COARSE_NMAX + i] = sum;
+  }
+  __syncthreads();
   // partials (pw = 1): ||out||^2;  (pw = 3): <out, in>, ||out||^2 (in = centre)
   double t[3] = {0.0, 0.0, 0.0};
   if (tid < nr) {
-    const int ipr = tid / RW, sub = tid % RW, row = r0 + tid;
-    C sum = red[ipr * RW + sub];
-    for (int q = 1; q < G; ++q) sum = cadd(sum, red[(q * npr + ipr) * RW + sub]);
+    const int row = r0 + tid;
+    C sum = red2[tid];
+#pragma unroll
+    for (int q = 1; q < CO_PARTS; ++q) sum = cadd(sum, red2[q * COARSE_NMAX + tid]);
     if (dagger && row >= (n >> 1)) sum = mk<C>(-sum.x, -sum.y);
     out[(size_t)s * n + row] = sum;
     const C c = vin[row];

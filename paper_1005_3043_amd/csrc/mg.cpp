@@ -155,8 +155,8 @@ struct TimerScope {
   hipEvent_t e1 = nullptr;
   hipStream_t st;
   unsigned flags = 0;
-  TimerScope(mg_ctx *c, EventTimer &tm, hipStream_t s, double sites) : st(s) {
-    if (c->timing) {
+  TimerScope(mg_ctx *c, EventTimer &tm, hipStream_t s, double sites, bool sample = true) : st(s) {
+    if (c->timing && sample) {
       hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
       if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive)
         flags = hipEventRecordExternal;
@@ -290,6 +290,7 @@ int apply_A(mg_ctx *c, int l, const vec_t<P> *in, vec_t<P> *out, int nrhs, Dslas
     }
     if (mode == DS_RESID) HIPK(resid_from<R>(out, b, L.vsize(), nrhs, st));
     c->n_coarse += nrhs;
+    c->n_coarse_disp += nrhs;
   }
   return MG_OK;
 }
@@ -373,7 +374,7 @@ int cgnr_chunk(mg_ctx *c, int l, vec_t<P> *e, int nrhs, int var, hipStream_t st,
     ca.done = c->done;
     ca.variant = var;
     {
-      TimerScope ts(c, tm, st, sites);
+      TimerScope ts(c, tm, st, sites, k == 0);
       HIPK((coarse_apply_k<R, S>(L.g, L.n, Lop, p, ww, nrhs, 0, ca, st)));
     }
     const int npr = cg2_update<R>(e, p, r, ww, n, nrhs, q.pw, q.pz[k & 1], npc, c->done, q.pr, st);
@@ -389,7 +390,7 @@ int cgnr_chunk(mg_ctx *c, int l, vec_t<P> *e, int nrhs, int var, hipStream_t st,
     ca.part = q.pz[(k + 1) & 1];
     ca.chk = &chk;
     {
-      TimerScope ts(c, tm, st, sites);
+      TimerScope ts(c, tm, st, sites, k == 0);
       HIPK((coarse_apply_k<R, S>(L.g, L.n, Lop, r, z, nrhs, 1, ca, st)));
     }
     HIPK(cg2_p<R>(p, z, n, nrhs, q.pz[(k + 1) & 1], q.pz[k & 1], npc, c->done, st));
@@ -397,10 +398,12 @@ int cgnr_chunk(mg_ctx *c, int l, vec_t<P> *e, int nrhs, int var, hipStream_t st,
   return MG_OK;
 }
 
-template <typename P> ChunkGraph *chunk_graph(mg_ctx *c, int l, vec_t<P> *e, int nrhs, int var, hipStream_t st) {
+template <typename P>
+ChunkGraph *chunk_graph(mg_ctx *c, int l, vec_t<P> *e, int nrhs, int var, int phase, hipStream_t st) {
   const int prec = P::id;
   for (ChunkGraph *g : c->graphs)
-    if (g && g->level == l && g->prec == prec && g->nrhs == nrhs && g->timing == c->timing && g->variant == var)
+    if (g && g->level == l && g->prec == prec && g->nrhs == nrhs && g->timing == c->timing && g->variant == var &&
+        g->phase == phase)
       return g;
   ChunkGraph *g = new ChunkGraph();
   g->level = l;
@@ -408,6 +411,7 @@ template <typename P> ChunkGraph *chunk_graph(mg_ctx *c, int l, vec_t<P> *e, int
   g->nrhs = nrhs;
   g->timing = c->timing;
   g->variant = var;
+  g->phase = phase;
   bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) == hipSuccess;
   if (ok) {
     const int rc = cgnr_chunk<P>(c, l, e, nrhs, var, st, g->tm);
@@ -452,19 +456,29 @@ template <typename P> int cgnr(mg_ctx *c, int l, const vec_t<P> *b, vec_t<P> *e,
     HIPK((coarse_apply_k<R, S>(L.g, L.n, cop_of<P>(L), w.cr, w.cz, nrhs, 1, ca, st)));
   }
   HIPK(copy<R>(w.cp, w.cz, n * nrhs, st));
-  ChunkGraph *gph = c->use_graph ? chunk_graph<P>(c, l, e, nrhs, var, st) : nullptr;
+  // With timing on, chunks alternate between two captured graphs so that the
+  // event pairs of one are read while the other runs.
+  ChunkGraph *gph[2] = {nullptr, nullptr};
+  if (c->use_graph) {
+    gph[0] = chunk_graph<P>(c, l, e, nrhs, var, 0, st);
+    gph[1] = c->timing ? chunk_graph<P>(c, l, e, nrhs, var, 1, st) : gph[0];
+    if (!gph[0] || !gph[1]) gph[0] = gph[1] = nullptr;
+  }
   const int nchunks = (c->p.coarse_maxiter + CG_CHUNK - 1) / CG_CHUNK;
-  const bool pipeline = !c->timing;
+  c->n_coarse_disp += nrhs;  // the initial application above
+  int last = 0;
   for (int ch = 0; ch < nchunks; ++ch) {
-    if (gph) HIPK(hipGraphLaunch(gph->exec, st));
+    last = ch;
+    if (gph[0]) HIPK(hipGraphLaunch(gph[ch & 1]->exec, st));
     else MG_TRY(cgnr_chunk<P>(c, l, e, nrhs, var, st, tm));
+    c->n_coarse_disp += 2L * CG_CHUNK * nrhs;
     int *hd = c->h_done + (size_t)(ch & 1) * MG_MAX_RHS;
     HIPK(hipMemcpyAsync(hd, c->done, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
     HIPK(hipEventRecord(c->ev_chunk[ch & 1], st));
-    const int look = pipeline ? ch - 1 : ch;
+    const int look = ch - 1;  // one chunk stays queued ahead of the host's check
     if (look < 0) continue;
     HIPK(hipEventSynchronize(c->ev_chunk[look & 1]));
-    if (gph && c->timing) gph->tm.harvest(&tm, true);
+    if (gph[0] && c->timing) gph[look & 1]->tm.harvest(&tm, true);
     const int *hl = c->h_done + (size_t)(look & 1) * MG_MAX_RHS;
     bool all = true;
     for (int i = 0; i < nrhs; ++i) all = all && hl[i];
@@ -472,6 +486,7 @@ template <typename P> int cgnr(mg_ctx *c, int l, const vec_t<P> *b, vec_t<P> *e,
   }
   HIPK(hipMemcpyAsync(c->h_it, c->it, sizeof(int) * 2 * nrhs, hipMemcpyDeviceToHost, st));
   HIPK(hipStreamSynchronize(st));
+  if (gph[0] && c->timing) gph[last & 1]->tm.harvest(&tm, true);
   for (int i = 0; i < nrhs; ++i) {
     const long it = std::max(c->h_it[i], c->h_it[nrhs + i]);
     c->n_cgnr += it;

@@ -167,7 +167,7 @@ struct EventTimer {
 
 // A captured chunk of CGNR iterations for one (level, precision, nrhs).
 struct ChunkGraph {
-  int level = -1, prec = -1, nrhs = 0, timing = 0, variant = 0;
+  int level = -1, prec = -1, nrhs = 0, timing = 0, variant = 0, phase = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   EventTimer tm;  // coarse-stencil timing events inside the graph (timing on)
@@ -200,7 +200,7 @@ struct mg_ctx {
   hipStream_t sti = nullptr;                  // library-owned stream of mg_solve
   hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_chunk[2] = {nullptr, nullptr};
   int use_graph = 1;
-  mg::ChunkGraph *graphs[8] = {};             // captured CGNR chunks
+  mg::ChunkGraph *graphs[16] = {};            // captured CGNR chunks
   mg::DevBuf<double2> csc;
   mg::DevBuf<int> done, it;
   int *h_done = nullptr;   // pinned host mirrors
@@ -213,7 +213,7 @@ struct mg_ctx {
   mg::DevBuf<int> skip;
   int gcr_rhs = 0;
   // statistics
-  long n_fine = 0, n_coarse = 0, n_cgnr = 0, n_vcyc = 0;
+  long n_fine = 0, n_coarse = 0, n_coarse_disp = 0, n_cgnr = 0, n_vcyc = 0;
   mg::EventTimer tm[6];  // (fine, coarse) x (FP64, FP32, FP16 storage)
   double t_setup = 0.0;
 };
