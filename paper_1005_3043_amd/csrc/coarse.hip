@@ -95,7 +95,7 @@ template <typename R, typename S, int RW>
 __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restrict__ L,
                                                  const c_t<R> *__restrict__ in, c_t<R> *__restrict__ out,
                                                  int dagger, double *__restrict__ partials, int pw,
-                                                 const int *__restrict__ done, CgCheck chk) {
+                                                 const int *__restrict__ done, CgCheck chk, CgFuse fz) {
   using C = c_t<R>;
   using VT = typename OpVec<S, RW>::V;
   __shared__ C vin[9 * COARSE_NMAX];
@@ -104,18 +104,6 @@ __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restri
   __shared__ double wred[8 * 3];
   const int rhs = blockIdx.y;
   if (done != nullptr && done[rhs]) return;
-  if (chk.part_r != nullptr) {
-    // CGNR convergence test on the residual of the update just made
-    const double rr = block_allsum_partials(chk.part_r + (size_t)rhs * chk.np_r, chk.np_r, wred);
-    const double *cg = chk.cg + (size_t)rhs * CG_NS;
-    const int iter = chk.it_in[rhs];
-    const bool conv = !(rr > cg[4] * cg[3]) || iter + 1 >= chk.maxit;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      chk.it_out[rhs] = iter + 1;
-      if (conv) chk.done[rhs] = 1;
-    }
-    if (conv) return;
-  }
   const uint32_t ws = xcd_remap(blockIdx.x, gridDim.x);
   const int RS = (int)(gridDim.x / g.V);
   const uint32_t s = ws / RS;
@@ -141,12 +129,64 @@ __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restri
   }
   __shared__ uint32_t nbs[9];
   if (tid < 9) nbs[tid] = slot_site(g, s, tid);
+  if (chk.part_r != nullptr) {
+    // CGNR convergence test on the residual of the update just made (the
+    // operator loads above are already in flight)
+    const double rr = block_allsum_partials(chk.part_r + (size_t)rhs * chk.np_r, chk.np_r, wred);
+    const double *cg = chk.cg + (size_t)rhs * CG_NS;
+    const int iter = chk.it_in[rhs];
+    bool conv;
+    if (chk.fused) conv = (iter > 0 && !(rr > cg[4] * cg[3])) || iter >= chk.maxit;
+    else conv = !(rr > cg[4] * cg[3]) || iter + 1 >= chk.maxit;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      chk.it_out[rhs] = (chk.fused && conv) ? iter : iter + 1;
+      if (conv) chk.done[rhs] = 1;
+    }
+    if (conv) return;
+  }
+  R coef = 0;
+  if (fz.kind != 0) {
+    const bool first = fz.kind == 1 && fz.it0[rhs] == 0;
+    const double nu = first ? 0.0 : block_allsum_partials(fz.num + (size_t)rhs * fz.np, fz.np, wred);
+    const double de = first ? 1.0 : block_allsum_partials(fz.den + (size_t)rhs * fz.np, fz.np, wred);
+    if (!(de > 0.0)) {
+      if (fz.kind == 2) {
+        if (blockIdx.x == 0 && tid == 0) fz.done_w[rhs] = 1;
+        return;
+      }
+    } else {
+      coef = (R)(nu / de);
+    }
+  }
   __syncthreads();
-  for (int idx = tid; idx < nP; idx += blockDim.x) {
-    const int slot = idx / n, j = idx - slot * n;
-    C v = in[(size_t)nbs[slot] * n + j];
-    if (dagger && j >= (n >> 1)) v = mk<C>(-v.x, -v.y);
-    vin[idx] = v;
+  double own_sq = 0.0;
+  if (fz.kind == 0) {
+    for (int idx = tid; idx < nP; idx += blockDim.x) {
+      const int slot = idx / n, j = idx - slot * n;
+      C v = in[(size_t)nbs[slot] * n + j];
+      if (dagger && j >= (n >> 1)) v = mk<C>(-v.x, -v.y);
+      vin[idx] = v;
+    }
+  } else {
+    const C *fa = reinterpret_cast<const C *>(fz.a) + rhs_off;
+    const C *fb = reinterpret_cast<const C *>(fz.b) + rhs_off;
+    const R sc = fz.kind == 1 ? coef : -coef;
+    for (int idx = tid; idx < nP; idx += blockDim.x) {
+      const int slot = idx / n, j = idx - slot * n;
+      const size_t o = (size_t)nbs[slot] * n + j;
+      C v = cfma(mk<C>(sc, 0), fb[o], fa[o]);
+      if (slot == 0) {
+        reinterpret_cast<C *>(fz.own)[rhs_off + o] = v;
+        if (fz.kind == 2) {
+          C *e = reinterpret_cast<C *>(fz.e) + rhs_off;
+          const C *pp = reinterpret_cast<const C *>(fz.p) + rhs_off;
+          e[o] = cfma(mk<C>(coef, 0), pp[o], e[o]);
+          own_sq += (double)v.x * v.x + (double)v.y * v.y;
+        }
+      }
+      if (dagger && j >= (n >> 1)) v = mk<C>(-v.x, -v.y);
+      vin[idx] = v;
+    }
   }
   __syncthreads();
   C acc[RW];
@@ -212,6 +252,11 @@ __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restri
         p[2] = t[2];
       }
     }
+  }
+  if (fz.kind == 2) {
+    double q[1] = {own_sq};
+    block_sum<1>(q, wred);
+    if (tid == 0) fz.part_own[(size_t)rhs * gridDim.x + blockIdx.x] = q[0];
   }
 }
 
@@ -455,6 +500,7 @@ hipError_t coarse_apply_k(const Geom &g, int n, const S *L, const c_t<R> *in, c_
   if (a.chk) c = *a.chk;
   if constexpr (sizeof(R) == 4) {
     if (a.variant > 0) {
+      if (a.fuse && a.fuse->kind) return hipErrorInvalidValue;  // fusion is per-RHS kernel only
       const int ks = a.variant;
       if (!coarse_mma_ok(n, nrhs, ks)) return hipErrorInvalidValue;
       const dim3 block(64 * ((n + 15) / 16) * ks);
@@ -475,21 +521,23 @@ hipError_t coarse_apply_k(const Geom &g, int n, const S *L, const c_t<R> *in, c_
   }
   dim3 grid(g.V * coarse_split(n, g.V), nrhs);
   dim3 block(coarse_threads(n, g.V));
+  CgFuse f{};
+  if (a.fuse) f = *a.fuse;
   if constexpr (sizeof(S) == 16) {
     hipLaunchKernelGGL((k_coarse<R, S, 1>), grid, block, 0, st, g, n, L, in, out, dagger, a.part, a.pw, a.done,
-                       c);
+                       c, f);
   } else if constexpr (sizeof(S) == 8) {
     hipLaunchKernelGGL((k_coarse<R, S, 2>), grid, block, 0, st, g, n, L, in, out, dagger, a.part, a.pw, a.done,
-                       c);
+                       c, f);
   } else {
     // half storage: four rows per 16-byte load when the rows of a workgroup
     // come in multiples of four, else two rows per 8-byte load
     if ((n / coarse_split(n, g.V)) % 4 == 0)
       hipLaunchKernelGGL((k_coarse<R, S, 4>), grid, block, 0, st, g, n, L, in, out, dagger, a.part, a.pw, a.done,
-                         c);
+                         c, f);
     else
       hipLaunchKernelGGL((k_coarse<R, S, 2>), grid, block, 0, st, g, n, L, in, out, dagger, a.part, a.pw, a.done,
-                         c);
+                         c, f);
   }
   return hipGetLastError();
 }

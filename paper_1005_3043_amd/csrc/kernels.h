@@ -61,6 +61,10 @@ int coarse_split(int n, uint32_t V);
 // converged; workgroup 0 writes it_out[rhs] = it_in[rhs] + 1 and done[rhs].
 // it_in and it_out are distinct slots (alternating by iteration parity) so
 // no workgroup reads a value written by the same launch.
+// With fused = 1 (the fused CGNR step below) the test runs before the p
+// update of iteration it_in and checks the residual after it_in updates:
+// nothing is tested at it_in = 0, a converged right-hand side records it_in
+// iterations, otherwise it_out = it_in + 1; iterations stop at maxit.
 struct CgCheck {
   const double *part_r = nullptr;
   int np_r = 0;
@@ -69,6 +73,27 @@ struct CgCheck {
   const int *it_in = nullptr;
   int *it_out = nullptr;
   int maxit = 0;
+  int fused = 0;
+};
+// Fused CGNR vector updates of the per-RHS coarse stencil: the stencil's
+// input is formed while staging, in = a + sgn c b with the coefficient c =
+// (sum num) / (sum den) over np partials per right-hand side, and the
+// workgroup of site s also stores that combination at s:
+//   kind 1 (w = A p):       p_new = z + beta p_old, beta = 0 when it0 = 0;
+//   kind 2 (z = A^dag r):   r_new = r_old - alpha w, e += alpha p_new at s,
+//                           ||r_new||^2 per workgroup into part_own; den <= 0
+//                           marks the right-hand side done.
+struct CgFuse {
+  int kind = 0;
+  const void *a = nullptr, *b = nullptr;
+  void *own = nullptr;
+  void *e = nullptr;
+  const void *p = nullptr;
+  const double *num = nullptr, *den = nullptr;
+  int np = 0;
+  double *part_own = nullptr;
+  int *done_w = nullptr;
+  const int *it0 = nullptr;
 };
 // Reduction outputs and options of the coarse stencil.
 //  part/pw: when part != nullptr each workgroup writes pw doubles at
@@ -85,6 +110,7 @@ struct CoarseArgs {
   int pw = 1;
   const int *done = nullptr;
   const CgCheck *chk = nullptr;
+  const CgFuse *fuse = nullptr;  // per-RHS kernel (variant 0) only
   int variant = 0;
 };
 // out = D_c in (dagger: sigma3 D_c sigma3) for nrhs right-hand sides

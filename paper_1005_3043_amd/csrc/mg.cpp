@@ -112,6 +112,8 @@ template <typename R> int ensure_work(mg_ctx *c, int nrhs) {
   MG_TRY(w.cz.alloc(n));
   MG_TRY(w.cp.alloc(n));
   MG_TRY(w.cw.alloc(n));
+  MG_TRY(w.cp2.alloc(n));
+  MG_TRY(w.cr2.alloc(n));
   MG_TRY(ensure_scalars(c, part_need(c, nrhs)));
   w.nrhs = nrhs;
   return MG_OK;
@@ -357,7 +359,7 @@ static CgPtrs cg_ptrs(mg_ctx *c, int l, int nrhs) {
 }
 
 template <typename P>
-int cgnr_chunk(mg_ctx *c, int l, vec_t<P> *e, int nrhs, int var, hipStream_t st, EventTimer &tm) {
+int cgnr_chunk(mg_ctx *c, int l, vec_t<P> *e, int nrhs, int var, bool fused, hipStream_t st, EventTimer &tm) {
   using R = typename P::R;
   using S = typename P::S;
   Work<R> &w = work<R>(c);
@@ -368,6 +370,63 @@ int cgnr_chunk(mg_ctx *c, int l, vec_t<P> *e, int nrhs, int var, hipStream_t st,
   const S *Lop = cop_of<P>(L);
   const CgPtrs q = cg_ptrs(c, l, nrhs);
   const int npc = (int)np_coarse(L);
+  if (fused) {
+    // Two launches per iteration: w = A p with p = z + beta p_old formed
+    // while staging (and the convergence test of the previous update), then
+    // z = A^dag r with r = r_old - alpha w formed while staging (and e +=
+    // alpha p).  p and r alternate between two buffers by iteration parity.
+    c_t<R> *Pb[2] = {w.cp, w.cp2}, *Rb[2] = {w.cr, w.cr2};
+    for (int k = 0; k < CG_CHUNK; ++k) {
+      CgCheck chk;
+      chk.part_r = q.pr;
+      chk.np_r = npc;
+      chk.cg = c->cg;
+      chk.done = c->done;
+      chk.it_in = c->it + (size_t)(k & 1) * nrhs;
+      chk.it_out = c->it + (size_t)((k + 1) & 1) * nrhs;
+      chk.maxit = c->p.coarse_maxiter;
+      chk.fused = 1;
+      CgFuse f1;
+      f1.kind = 1;
+      f1.a = z;
+      f1.b = Pb[(k + 1) & 1];
+      f1.own = Pb[k & 1];
+      f1.num = q.pz[k & 1];
+      f1.den = q.pz[(k + 1) & 1];
+      f1.np = npc;
+      f1.it0 = chk.it_in;
+      CoarseArgs ca;
+      ca.part = q.pw;
+      ca.done = c->done;
+      ca.chk = &chk;
+      ca.fuse = &f1;
+      {
+        TimerScope ts(c, tm, st, sites, k == 0);
+        HIPK((coarse_apply_k<R, S>(L.g, L.n, Lop, z, ww, nrhs, 0, ca, st)));
+      }
+      CgFuse f2;
+      f2.kind = 2;
+      f2.a = Rb[k & 1];
+      f2.b = ww;
+      f2.own = Rb[(k + 1) & 1];
+      f2.e = e;
+      f2.p = Pb[k & 1];
+      f2.num = q.pz[k & 1];
+      f2.den = q.pw;
+      f2.np = npc;
+      f2.part_own = q.pr;
+      f2.done_w = c->done;
+      CoarseArgs cb;
+      cb.part = q.pz[(k + 1) & 1];
+      cb.done = c->done;
+      cb.fuse = &f2;
+      {
+        TimerScope ts(c, tm, st, sites, k == 0);
+        HIPK((coarse_apply_k<R, S>(L.g, L.n, Lop, Rb[k & 1], z, nrhs, 1, cb, st)));
+      }
+    }
+    return MG_OK;
+  }
   for (int k = 0; k < CG_CHUNK; ++k) {
     CoarseArgs ca;
     ca.part = q.pw;
@@ -399,11 +458,11 @@ int cgnr_chunk(mg_ctx *c, int l, vec_t<P> *e, int nrhs, int var, hipStream_t st,
 }
 
 template <typename P>
-ChunkGraph *chunk_graph(mg_ctx *c, int l, vec_t<P> *e, int nrhs, int var, int phase, hipStream_t st) {
+ChunkGraph *chunk_graph(mg_ctx *c, int l, vec_t<P> *e, int nrhs, int var, bool fused, int phase, hipStream_t st) {
   const int prec = P::id;
   for (ChunkGraph *g : c->graphs)
     if (g && g->level == l && g->prec == prec && g->nrhs == nrhs && g->timing == c->timing && g->variant == var &&
-        g->phase == phase)
+        g->phase == phase && g->fused == (int)fused)
       return g;
   ChunkGraph *g = new ChunkGraph();
   g->level = l;
@@ -412,9 +471,10 @@ ChunkGraph *chunk_graph(mg_ctx *c, int l, vec_t<P> *e, int nrhs, int var, int ph
   g->timing = c->timing;
   g->variant = var;
   g->phase = phase;
+  g->fused = fused ? 1 : 0;
   bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) == hipSuccess;
   if (ok) {
-    const int rc = cgnr_chunk<P>(c, l, e, nrhs, var, st, g->tm);
+    const int rc = cgnr_chunk<P>(c, l, e, nrhs, var, fused, st, g->tm);
     ok = hipStreamEndCapture(st, &g->graph) == hipSuccess && rc == MG_OK;
   }
   if (ok) ok = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) == hipSuccess;
@@ -443,8 +503,12 @@ template <typename P> int cgnr(mg_ctx *c, int l, const vec_t<P> *b, vec_t<P> *e,
   EventTimer &tm = c->tm[tclass<P>(true)];
   const int var = coarse_variant<P>(c, l, nrhs, st);
   if (var < 0) return var;
+  // Fused updates when the per-RHS stencil runs and every workgroup can sum
+  // the V partials of the step lengths cheaply.
+  const bool fused = var == 0 && L.g.V <= (uint32_t)CG_FUSE_MAXV;
   HIPK(zero<R>(e, n * nrhs, st));
   HIPK(copy<R>(w.cr, b, n * nrhs, st));
+  if (fused) HIPK(zero<R>(w.cp2, n * nrhs, st));
   const int npb = norm2_partials<R>(b, n, nrhs, q.pb, st);
   HIPK(cg2_init(q.pb, npb, nrhs, c->cg, c->done, c->it, c->p.coarse_tol, st));
   {
@@ -455,13 +519,13 @@ template <typename P> int cgnr(mg_ctx *c, int l, const vec_t<P> *b, vec_t<P> *e,
     TimerScope ts(c, tm, st, (double)L.g.V * nrhs);
     HIPK((coarse_apply_k<R, S>(L.g, L.n, cop_of<P>(L), w.cr, w.cz, nrhs, 1, ca, st)));
   }
-  HIPK(copy<R>(w.cp, w.cz, n * nrhs, st));
+  if (!fused) HIPK(copy<R>(w.cp, w.cz, n * nrhs, st));
   // With timing on, chunks alternate between two captured graphs so that the
   // event pairs of one are read while the other runs.
   ChunkGraph *gph[2] = {nullptr, nullptr};
   if (c->use_graph) {
-    gph[0] = chunk_graph<P>(c, l, e, nrhs, var, 0, st);
-    gph[1] = c->timing ? chunk_graph<P>(c, l, e, nrhs, var, 1, st) : gph[0];
+    gph[0] = chunk_graph<P>(c, l, e, nrhs, var, fused, 0, st);
+    gph[1] = c->timing ? chunk_graph<P>(c, l, e, nrhs, var, fused, 1, st) : gph[0];
     if (!gph[0] || !gph[1]) gph[0] = gph[1] = nullptr;
   }
   const int nchunks = (c->p.coarse_maxiter + CG_CHUNK - 1) / CG_CHUNK;
@@ -470,7 +534,7 @@ template <typename P> int cgnr(mg_ctx *c, int l, const vec_t<P> *b, vec_t<P> *e,
   for (int ch = 0; ch < nchunks; ++ch) {
     last = ch;
     if (gph[0]) HIPK(hipGraphLaunch(gph[ch & 1]->exec, st));
-    else MG_TRY(cgnr_chunk<P>(c, l, e, nrhs, var, st, tm));
+    else MG_TRY(cgnr_chunk<P>(c, l, e, nrhs, var, fused, st, tm));
     c->n_coarse_disp += 2L * CG_CHUNK * nrhs;
     int *hd = c->h_done + (size_t)(ch & 1) * MG_MAX_RHS;
     HIPK(hipMemcpyAsync(hd, c->done, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));

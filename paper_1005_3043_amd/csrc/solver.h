@@ -113,7 +113,7 @@ template <typename R> struct Work {
   // per level: x, r, q (smoother / cycle), rin (cycle input)
   DevBuf<c_t<R>> x[MG_MAX_LEVELS], r[MG_MAX_LEVELS], q[MG_MAX_LEVELS], rin[MG_MAX_LEVELS];
   // coarsest CGNR
-  DevBuf<c_t<R>> ce, cr, cz, cp, cw;
+  DevBuf<c_t<R>> ce, cr, cz, cp, cw, cp2, cr2;  // cp2, cr2: second p, r of the fused CGNR
   int nrhs = 0;
 };
 
@@ -167,7 +167,7 @@ struct EventTimer {
 
 // A captured chunk of CGNR iterations for one (level, precision, nrhs).
 struct ChunkGraph {
-  int level = -1, prec = -1, nrhs = 0, timing = 0, variant = 0, phase = 0;
+  int level = -1, prec = -1, nrhs = 0, timing = 0, variant = 0, phase = 0, fused = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   EventTimer tm;  // coarse-stencil timing events inside the graph (timing on)
@@ -177,6 +177,7 @@ struct ChunkGraph {
   }
 };
 
+constexpr int CG_FUSE_MAXV = 1024;  // fused CGNR up to this many coarse sites (<= RED_BLOCKS)
 constexpr int CG_CHUNK = 8;  // CGNR iterations per chunk (even: parity slots repeat)
 
 }  // namespace mg
