@@ -135,6 +135,13 @@ int mg_setup(const mg_lattice_t *lat, const void *U, double mass,
  * MG_F16); lower-precision copies of U, P and D_c are made on first use.  */
 int mg_set_precond_prec(mg_ctx_t *ctx, mg_prec_t prec);
 
+/* Reuse a setup at another mass ("Numerical Results": a setup made near the
+ * critical mass serves heavier masses).  D(m') = D(m) + (m' - m), and P has
+ * orthonormal columns per block (Eq. 4), so every Galerkin operator shifts
+ * exactly: X(m') = X(m) + (m' - m) I, Y unchanged.  The null vectors and P
+ * are kept.  Synchronous.  MG_EINVAL for a NULL ctx or non-finite mass.    */
+int mg_set_mass(mg_ctx_t *ctx, double mass);
+
 /* Turn per-kernel device timing on (1) or off (0) for later solves.       */
 int mg_set_timing(mg_ctx_t *ctx, int on);
 

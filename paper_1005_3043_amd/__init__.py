@@ -21,7 +21,7 @@ PREC = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 MAX_LEVELS = 3
 MAX_RHS = 16
 
-EXPORTED = ["wilson_apply", "mg_setup", "mg_set_precond_prec", "mg_set_timing", "mg_restrict",
+EXPORTED = ["wilson_apply", "mg_setup", "mg_set_precond_prec", "mg_set_mass", "mg_set_timing", "mg_restrict",
             "mg_prolong", "coarse_apply", "mg_apply_op", "mg_set_coarse_variant", "mg_coarse_variant", "mg_solve", "mg_time_dslash", "mg_time_coarse",
             "mg_destroy", "mg_last_error", "mg_export_maps", "mg_export_P",
             "mg_export_coarse_op", "mg_export_nullvecs", "mg_level_info",
@@ -97,6 +97,7 @@ def lib():
             "wilson_apply": [ctypes.POINTER(Lattice), vp, cd, vp, vp, ci, ci, vp],
             "mg_setup": [ctypes.POINTER(Lattice), vp, cd, ctypes.POINTER(Params), ctypes.POINTER(vp), vp],
             "mg_set_precond_prec": [vp, ci],
+            "mg_set_mass": [vp, cd],
             "mg_set_timing": [vp, ci],
             "mg_restrict": [vp, ci, vp, vp, ci, vp],
             "mg_prolong": [vp, ci, vp, vp, ci, vp],
@@ -219,6 +220,11 @@ class MG:
 
     def set_precond_prec(self, prec: str):
         _check(lib().mg_set_precond_prec(self.ctx, PREC[prec]))
+
+    def set_mass(self, mass: float):
+        """Shift the setup to another mass (exact: X += (m' - m) I on every level)."""
+        _check(lib().mg_set_mass(self.ctx, float(mass)))
+        self.mass = float(mass)
 
     def set_timing(self, on: bool):
         _check(lib().mg_set_timing(self.ctx, int(bool(on))))

@@ -135,6 +135,26 @@ extern "C" int mg_set_precond_prec(mg_ctx_t *ctx, mg_prec_t prec) {
   return MG_OK;
 }
 
+extern "C" int mg_set_mass(mg_ctx_t *ctx, double mass) {
+  set_error("");
+  if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
+  if (!std::isfinite(mass)) return bad(MG_EINVAL, "mg_set_mass: mass must be finite");
+  const double delta = mass - ctx->mass;
+  HIPK(hipStreamSynchronize(ctx->sti));
+  for (int l = 1; l < ctx->nlev; ++l) {
+    Level &L = ctx->lev[l];
+    HIPK(shift_diag(L.L64, L.g.V, L.n, delta, nullptr));
+    L.L32.release();  // low-precision copies are rebuilt from the shifted FP64 stencil
+    L.L16.release();
+  }
+  clear_graphs(ctx);
+  HIPK(hipStreamSynchronize(nullptr));
+  ctx->mass = mass;
+  if (ctx->prec != MG_F64) MG_TRY(ensure_prec(ctx, ctx->prec, nullptr));
+  HIPK(hipStreamSynchronize(nullptr));
+  return MG_OK;
+}
+
 extern "C" int mg_set_timing(mg_ctx_t *ctx, int on) {
   if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
   ctx->timing = on ? 1 : 0;

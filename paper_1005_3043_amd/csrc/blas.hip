@@ -51,6 +51,21 @@ template <typename R> hipError_t fill_const(c_t<R> *x, size_t n, R v, hipStream_
   return hipGetLastError();
 }
 template hipError_t fill_const<float>(float2 *, size_t, float, hipStream_t);
+
+// X += delta * I on the diagonal block (slot 0) of every site of a coarse
+// stencil L[site][slot][j][i] (n x n blocks).
+__global__ __launch_bounds__(256) void k_shift_diag(double2 *L, uint32_t V, int n, double delta) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i >= (size_t)V * n) return;
+  const size_t site = i / n, j = i % n;
+  double2 &x = L[(site * 9) * n * n + j * n + j];
+  x.x += delta;
+}
+hipError_t shift_diag(double2 *L, uint32_t V, int n, double delta, hipStream_t st) {
+  if (V == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_shift_diag, dim3(stream_grid((size_t)V * n)), dim3(256), 0, st, L, V, n, delta);
+  return hipGetLastError();
+}
 template hipError_t fill_const<double>(double2 *, size_t, double, hipStream_t);
 
 template <typename S> __global__ __launch_bounds__(256) void k_store_convert(S *y, const double2 *x, size_t n) {

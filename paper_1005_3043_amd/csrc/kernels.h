@@ -43,6 +43,8 @@ hipError_t convert(c_t<Rd> *y, const c_t<Rs> *x, size_t n, hipStream_t st);
 // x[i] = v + 0 i
 template <typename R> hipError_t fill_const(c_t<R> *x, size_t n, R v, hipStream_t st);
 template <typename S> hipError_t store_convert(S *y, const double2 *x, size_t n, hipStream_t st);
+// diagonal shift X += delta I of a coarse stencil's slot-0 blocks
+hipError_t shift_diag(double2 *L, uint32_t V, int n, double delta, hipStream_t st);
 
 }  // namespace mg
 

@@ -105,19 +105,141 @@ __global__ __launch_bounds__(256) void k_prolong_fine(Geom g, Geom gc, int nv, c
   }
 }
 
+// Several right-hand sides per workgroup (TR_RG of them): every null-vector
+// entry loaded from memory serves TR_RG vectors instead of one.
+constexpr int TR_RG = 4;
+
+template <typename R, typename S>
+__global__ __launch_bounds__(256) void k_restrict_fine_mrhs(Geom g, Geom gc, int nv, int nrhs,
+                                                            const S *__restrict__ P, const c_t<R> *__restrict__ fine,
+                                                            c_t<R> *__restrict__ coarse) {
+  using C = c_t<R>;
+  __shared__ double2 part[4][TR_RG][2 * COARSE_NMAX];
+  const size_t V = g.Vpad;
+  const uint32_t B = blockIdx.x;
+  const int r0 = blockIdx.y * TR_RG;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int k = lane; k < 2 * nv; k += 64)
+#pragma unroll
+    for (int q = 0; q < TR_RG; ++q) part[w][q][k] = make_double2(0.0, 0.0);
+  __syncthreads();
+  for (uint32_t t0 = 0; t0 < g.vb; t0 += blockDim.x) {
+    const uint32_t t = t0 + tid;
+    const bool act = t < g.vb;
+    const uint32_t s = B * g.vb + (act ? t : 0);
+    C f[TR_RG][12];
+#pragma unroll
+    for (int q = 0; q < TR_RG; ++q) {
+      const bool on = act && r0 + q < nrhs;
+      const C *fr = fine + (size_t)(on ? r0 + q : 0) * 12 * V;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) f[q][c] = on ? fr[fidx(s, c, 12)] : mk<C>(0, 0);
+    }
+    for (int kk = 0; kk < nv; ++kk) {
+      const S *Pk = P + (size_t)kk * 12 * V;
+      C pk[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) pk[c] = act ? cvt<C>(Pk[fidx(s, c, 12)]) : mk<C>(0, 0);
+#pragma unroll
+      for (int q = 0; q < TR_RG; ++q) {
+        C d0 = mk<C>(0, 0), d1 = mk<C>(0, 0);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) d0 = cfmac(pk[c], f[q][c], d0);
+#pragma unroll
+        for (int c = 6; c < 12; ++c) d1 = cfmac(pk[c], f[q][c], d1);
+        const double a0 = wave_sum((double)d0.x), b0 = wave_sum((double)d0.y);
+        const double a1 = wave_sum((double)d1.x), b1 = wave_sum((double)d1.y);
+        if (lane == 0) {
+          part[w][q][kk].x += a0;
+          part[w][q][kk].y += b0;
+          part[w][q][nv + kk].x += a1;
+          part[w][q][nv + kk].y += b1;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int nw = (blockDim.x + 63) >> 6;
+  for (int o = tid; o < TR_RG * 2 * nv; o += blockDim.x) {
+    const int q = o / (2 * nv), k = o % (2 * nv);
+    if (r0 + q >= nrhs) continue;
+    const int x[4] = {(int)(B % gc.L[0]), (int)((B / gc.L[0]) % gc.L[1]),
+                      (int)((B / (gc.L[0] * gc.L[1])) % gc.L[2]), (int)(B / (gc.L[0] * gc.L[1] * gc.L[2]))};
+    const uint32_t ic = encode(gc, x);
+    double2 a = part[0][q][k];
+    for (int qq = 1; qq < nw; ++qq) {
+      a.x += part[qq][q][k].x;
+      a.y += part[qq][q][k].y;
+    }
+    coarse[((size_t)(r0 + q) * gc.V + ic) * (2 * nv) + k] = mk<C>((R)a.x, (R)a.y);
+  }
+}
+
+template <typename R, typename S>
+__global__ __launch_bounds__(256) void k_prolong_fine_mrhs(Geom g, Geom gc, int nv, int nrhs,
+                                                           const S *__restrict__ P, const c_t<R> *__restrict__ coarse,
+                                                           c_t<R> *__restrict__ fine, int accumulate) {
+  using C = c_t<R>;
+  const size_t V = g.Vpad;
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  const int r0 = blockIdx.y * TR_RG;
+  const uint32_t ic = coarse_index(g, gc, s);
+  C acc[TR_RG][12];
+#pragma unroll
+  for (int q = 0; q < TR_RG; ++q)
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[q][c] = mk<C>(0, 0);
+  for (int kk = 0; kk < nv; ++kk) {
+    const S *Pk = P + (size_t)kk * 12 * V;
+    C pk[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) pk[c] = cvt<C>(Pk[fidx(s, c, 12)]);
+#pragma unroll
+    for (int q = 0; q < TR_RG; ++q) {
+      const int r = min(r0 + q, nrhs - 1);
+      const C *ec = coarse + ((size_t)r * gc.V + ic) * (2 * nv);
+      const C e0 = ec[kk], e1 = ec[nv + kk];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) acc[q][c] = cfma(pk[c], e0, acc[q][c]);
+#pragma unroll
+      for (int c = 6; c < 12; ++c) acc[q][c] = cfma(pk[c], e1, acc[q][c]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < TR_RG; ++q) {
+    if (r0 + q >= nrhs) break;
+    C *fr = fine + (size_t)(r0 + q) * 12 * V;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      C v = acc[q][c];
+      if (accumulate) v = cadd(fr[fidx(s, c, 12)], v);
+      fr[fidx(s, c, 12)] = v;
+    }
+  }
+}
+
 template <typename R, typename S>
 hipError_t restrict_fine(const Geom &g, const Geom &gc, int nv, const S *P, const c_t<R> *fine, c_t<R> *coarse,
                          int nrhs, hipStream_t st) {
   const int th = g.vb >= 256 ? 256 : (int)((g.vb + 63) / 64 * 64);
-  hipLaunchKernelGGL((k_restrict_fine<R, S>), dim3(g.Vc, nrhs), dim3(th), 0, st, g, gc, nv, P, fine, coarse);
+  if (nrhs > 1)
+    hipLaunchKernelGGL((k_restrict_fine_mrhs<R, S>), dim3(g.Vc, (nrhs + TR_RG - 1) / TR_RG), dim3(th), 0, st, g, gc,
+                       nv, nrhs, P, fine, coarse);
+  else
+    hipLaunchKernelGGL((k_restrict_fine<R, S>), dim3(g.Vc, nrhs), dim3(th), 0, st, g, gc, nv, P, fine, coarse);
   return hipGetLastError();
 }
 
 template <typename R, typename S>
 hipError_t prolong_fine(const Geom &g, const Geom &gc, int nv, const S *P, const c_t<R> *coarse, c_t<R> *fine,
                         int nrhs, int accumulate, hipStream_t st) {
-  hipLaunchKernelGGL((k_prolong_fine<R, S>), dim3(div_up(g.V, 256), nrhs), dim3(256), 0, st, g, gc, nv, P, coarse,
-                     fine, accumulate);
+  if (nrhs > 1)
+    hipLaunchKernelGGL((k_prolong_fine_mrhs<R, S>), dim3(div_up(g.V, 256), (nrhs + TR_RG - 1) / TR_RG), dim3(256), 0,
+                       st, g, gc, nv, nrhs, P, coarse, fine, accumulate);
+  else
+    hipLaunchKernelGGL((k_prolong_fine<R, S>), dim3(div_up(g.V, 256), nrhs), dim3(256), 0, st, g, gc, nv, P, coarse,
+                       fine, accumulate);
   return hipGetLastError();
 }
 

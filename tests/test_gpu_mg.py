@@ -79,18 +79,21 @@ def test_coarse_operator(built):
     assert ex < 1e-10 and ey < 1e-10
 
 
-def test_restrict_prolong(built):
+@pytest.mark.parametrize("nrhs", [1, 2, 5])
+def test_restrict_prolong(built, nrhs):
+    """One vector (per-RHS kernels) and batches of 2 and 5 (the kernels that
+    serve four right-hand sides per workgroup, with a ragged last group)."""
     name, U, m, ctx, h = built
     L = h.levels[0].geom.L
-    r = W.gaussian_spinor(L, 11, batch=(2,))
+    r = W.gaussian_spinor(L, 11, batch=(nrhs,))
     rc = ctx.restrict(0, torch.from_numpy(r).cuda()).cpu().numpy()
-    ref = np.stack([h.restrict(0, r[i]) for i in range(2)])
+    ref = np.stack([h.restrict(0, r[i]) for i in range(nrhs)])
     e1 = _rel(rc, ref)
     ec = np.random.default_rng(3).standard_normal(ref.shape) + 1j * np.random.default_rng(4).standard_normal(ref.shape)
     f = ctx.prolong(0, torch.from_numpy(ec).cuda()).cpu().numpy()
-    ref2 = np.stack([h.prolong(0, ec[i]) for i in range(2)])
+    ref2 = np.stack([h.prolong(0, ec[i]) for i in range(nrhs)])
     e2 = _rel(f, ref2)
-    print(f"{name}: restrict rel err {e1:.2e}, prolong rel err {e2:.2e}")
+    print(f"{name}: {nrhs} vectors: restrict rel err {e1:.2e}, prolong rel err {e2:.2e}")
     assert e1 < 1e-10 and e2 < 1e-10
 
 
@@ -264,6 +267,30 @@ def test_three_level(cuda):
     assert e < 1e-9 and eP < 1e-9
     assert rc == 0 and res <= 1e-10 * 1.001
     assert abs(info["iters"][0] - it_ref) <= 1
+
+
+def test_set_mass(cuda):
+    """A setup reused at a heavier mass: the GPU's shifted Galerkin operator
+    equals the oracle's Galerkin construction at the new mass with the same
+    P (X + delta I, Y unchanged), and the solve at the new mass reaches
+    1e-10 by the oracle's operator."""
+    L, blocks, nv, eps, m, seed = CASES["8^4 b4^4 nv8"]
+    U, m, ctx, h = _build("8^4 b4^4 nv8")
+    X0, Y0 = ctx.export_coarse_op(1)
+    m2 = m + 0.05
+    ctx.set_mass(m2)
+    X1, Y1 = ctx.export_coarse_op(1)
+    lv = h.levels[0]
+    Xr, Yr = co.galerkin_fine(U, m2, lv.Pb, lv.geom)
+    assert np.array_equal(Y1, Y0)
+    assert _rel(X1, Xr) < 1e-10 and _rel(Y1, Yr) < 1e-10
+    b = W.gaussian_spinor(L, 5)
+    for prec in ("f64", "f16"):
+        ctx.set_precond_prec(prec)
+        x, info, rc = ctx.solve(torch.from_numpy(b).cuda(), 1e-10)
+        res = np.linalg.norm(b - wi.apply_D(U, x.cpu().numpy(), m2)) / np.linalg.norm(b)
+        print(f"set_mass {m} -> {m2}: {prec} solve {info['iters'][0]} iterations, true rel resid {res:.2e}")
+        assert rc == 0 and res <= 1e-10 * 1.001
 
 
 def test_setup_errors(cuda):
