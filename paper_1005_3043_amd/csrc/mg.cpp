@@ -157,7 +157,7 @@ struct TimerScope {
   hipEvent_t e1 = nullptr;
   hipStream_t st;
   unsigned flags = 0;
-  TimerScope(mg_ctx *c, EventTimer &tm, hipStream_t s, double sites, bool sample = true) : st(s) {
+  TimerScope(mg_ctx *c, EventTimer &tm, hipStream_t s, double sites, bool sample = true, int nlaunch = 1) : st(s) {
     if (c->timing && sample) {
       hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
       if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive)
@@ -168,6 +168,7 @@ struct TimerScope {
         (void)hipEventRecordWithFlags(e0, st, flags);
         t = &tm;
         tm.pair_sites.push_back(sites);
+        tm.pair_launches.push_back(nlaunch);
       }
     }
   }
@@ -376,6 +377,9 @@ int cgnr_chunk(mg_ctx *c, int l, vec_t<P> *e, int nrhs, int var, bool fused, hip
     // z = A^dag r with r = r_old - alpha w formed while staging (and e +=
     // alpha p).  p and r alternate between two buffers by iteration parity.
     c_t<R> *Pb[2] = {w.cp, w.cp2}, *Rb[2] = {w.cr, w.cr2};
+    // the chunk is 2 CG_CHUNK consecutive stencil launches: one event pair
+    // times them all
+    TimerScope ts(c, tm, st, sites * 2 * CG_CHUNK, true, 2 * CG_CHUNK);
     for (int k = 0; k < CG_CHUNK; ++k) {
       CgCheck chk;
       chk.part_r = q.pr;
@@ -400,10 +404,7 @@ int cgnr_chunk(mg_ctx *c, int l, vec_t<P> *e, int nrhs, int var, bool fused, hip
       ca.done = c->done;
       ca.chk = &chk;
       ca.fuse = &f1;
-      {
-        TimerScope ts(c, tm, st, sites, k == 0);
-        HIPK((coarse_apply_k<R, S>(L.g, L.n, Lop, z, ww, nrhs, 0, ca, st)));
-      }
+      HIPK((coarse_apply_k<R, S>(L.g, L.n, Lop, z, ww, nrhs, 0, ca, st)));
       CgFuse f2;
       f2.kind = 2;
       f2.a = Rb[k & 1];
@@ -420,10 +421,7 @@ int cgnr_chunk(mg_ctx *c, int l, vec_t<P> *e, int nrhs, int var, bool fused, hip
       cb.part = q.pz[(k + 1) & 1];
       cb.done = c->done;
       cb.fuse = &f2;
-      {
-        TimerScope ts(c, tm, st, sites, k == 0);
-        HIPK((coarse_apply_k<R, S>(L.g, L.n, Lop, Rb[k & 1], z, nrhs, 1, cb, st)));
-      }
+      HIPK((coarse_apply_k<R, S>(L.g, L.n, Lop, Rb[k & 1], z, nrhs, 1, cb, st)));
     }
     return MG_OK;
   }

@@ -124,6 +124,7 @@ template <typename R> struct Work {
 struct EventTimer {
   std::vector<hipEvent_t> ev;
   std::vector<double> pair_sites;  // sites x right-hand sides of each pair
+  std::vector<int> pair_launches;  // kernel launches covered by each pair
   size_t used = 0;
   double ms = 0.0, sites = 0.0;    // accumulated
   long launches = 0;
@@ -148,18 +149,20 @@ struct EventTimer {
       float t = 0.f;
       if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) continue;
       dst->ms += t;
-      dst->launches += 1;
+      dst->launches += i / 2 < pair_launches.size() ? pair_launches[i / 2] : 1;
       if (i / 2 < pair_sites.size()) dst->sites += pair_sites[i / 2];
     }
     if (!keep) {
       used = 0;
       pair_sites.clear();
+      pair_launches.clear();
     }
     (void)hipGetLastError();  // a failed elapsed-time query must not latch into later launches
   }
   void reset() {
     used = 0;
     pair_sites.clear();
+    pair_launches.clear();
     ms = sites = 0.0;
     launches = 0;
   }
