@@ -75,6 +75,35 @@ __device__ __forceinline__ uint32_t slot_site(const Geom &g, uint32_t s, int slo
   }
 }
 
+// Sums of up to three partial arrays over the workgroup in one pass: out[0]
+// = sum a[0..na), out[1] = sum b[0..nb), out[2] = sum c[0..nb) (NULL arrays
+// give 0).  Fixed order; result in every thread.
+__device__ __forceinline__ void block_allsum3(const double *__restrict__ a, int na, const double *__restrict__ b,
+                                              const double *__restrict__ c, int nb, double (&out)[3],
+                                              double *lds) {
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < na; i += blockDim.x) v[0] += a[i];
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    v[1] += b[i];
+    v[2] += c[i];
+  }
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) v[q] = wave_sum(v[q]);
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) lds[w * 3 + q] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    double t = 0.0;
+    for (int k = 0; k < nw; ++k) t += lds[k * 3 + q];
+    out[q] = t;
+  }
+  __syncthreads();
+}
+
 // Sum of np partials over the workgroup; result in every thread.
 __device__ __forceinline__ double block_allsum_partials(const double *__restrict__ p, int np, double *lds) {
   double a = 0.0;
@@ -101,7 +130,7 @@ __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restri
   __shared__ C vin[9 * COARSE_NMAX];
   __shared__ C red[512 * RW];
   __shared__ C red2[CO_PARTS * COARSE_NMAX];
-  __shared__ double wred[8 * 3];
+  __shared__ double wred[8 * 4];
   const int rhs = blockIdx.y;
   if (done != nullptr && done[rhs]) return;
   const uint32_t ws = xcd_remap(blockIdx.x, gridDim.x);
@@ -129,33 +158,41 @@ __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restri
   }
   __shared__ uint32_t nbs[9];
   if (tid < 9) nbs[tid] = slot_site(g, s, tid);
-  if (chk.part_r != nullptr) {
-    // CGNR convergence test on the residual of the update just made (the
-    // operator loads above are already in flight)
-    const double rr = block_allsum_partials(chk.part_r + (size_t)rhs * chk.np_r, chk.np_r, wred);
-    const double *cg = chk.cg + (size_t)rhs * CG_NS;
-    const int iter = chk.it_in[rhs];
-    bool conv;
-    if (chk.fused) conv = (iter > 0 && !(rr > cg[4] * cg[3])) || iter >= chk.maxit;
-    else conv = !(rr > cg[4] * cg[3]) || iter + 1 >= chk.maxit;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      chk.it_out[rhs] = (chk.fused && conv) ? iter : iter + 1;
-      if (conv) chk.done[rhs] = 1;
-    }
-    if (conv) return;
-  }
+  // Scalars of this launch, summed from per-workgroup partials in one pass
+  // (one round trip): the CGNR convergence test on the residual of the
+  // update just made, and the fused update's coefficient.
+  const bool check = chk.part_r != nullptr;
+  const bool first = fz.kind == 1 && fz.it0[rhs] == 0;
+  const bool coef_on = fz.kind != 0 && !first;
   R coef = 0;
-  if (fz.kind != 0) {
-    const bool first = fz.kind == 1 && fz.it0[rhs] == 0;
-    const double nu = first ? 0.0 : block_allsum_partials(fz.num + (size_t)rhs * fz.np, fz.np, wred);
-    const double de = first ? 1.0 : block_allsum_partials(fz.den + (size_t)rhs * fz.np, fz.np, wred);
-    if (!(de > 0.0)) {
-      if (fz.kind == 2) {
-        if (blockIdx.x == 0 && tid == 0) fz.done_w[rhs] = 1;
-        return;
+  if (check || coef_on) {
+    const double *pa = check ? chk.part_r + (size_t)rhs * chk.np_r : nullptr;
+    const double *pn = coef_on ? fz.num + (size_t)rhs * fz.np : nullptr;
+    const double *pd = coef_on ? fz.den + (size_t)rhs * fz.np : nullptr;
+    double sums[3];
+    block_allsum3(pa, check ? chk.np_r : 0, pn, pd, coef_on ? fz.np : 0, sums, wred);
+    if (check) {
+      const double rr = sums[0];
+      const double *cg = chk.cg + (size_t)rhs * CG_NS;
+      const int iter = chk.it_in[rhs];
+      bool conv;
+      if (chk.fused) conv = (iter > 0 && !(rr > cg[4] * cg[3])) || iter >= chk.maxit;
+      else conv = !(rr > cg[4] * cg[3]) || iter + 1 >= chk.maxit;
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        chk.it_out[rhs] = (chk.fused && conv) ? iter : iter + 1;
+        if (conv) chk.done[rhs] = 1;
       }
-    } else {
-      coef = (R)(nu / de);
+      if (conv) return;
+    }
+    if (coef_on) {
+      if (!(sums[2] > 0.0)) {
+        if (fz.kind == 2) {
+          if (blockIdx.x == 0 && tid == 0) fz.done_w[rhs] = 1;
+          return;
+        }
+      } else {
+        coef = (R)(sums[1] / sums[2]);
+      }
     }
   }
   __syncthreads();
@@ -240,26 +277,24 @@ __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restri
     t[1] = (double)sum.x * c.y - (double)sum.y * c.x;
     t[2] = (double)sum.x * sum.x + (double)sum.y * sum.y;
   }
-  if (partials != nullptr) {
-    block_sum<3>(t, wred);
+  if (partials != nullptr || fz.kind == 2) {
+    double v4[4] = {t[0], t[1], t[2], own_sq};
+    block_sum<4>(v4, wred);
     if (tid == 0) {
-      double *p = partials + ((size_t)rhs * gridDim.x + blockIdx.x) * pw;
-      if (pw == 1) {
-        p[0] = t[2];
-      } else {
-        p[0] = t[0];
-        p[1] = t[1];
-        p[2] = t[2];
+      if (partials != nullptr) {
+        double *p = partials + ((size_t)rhs * gridDim.x + blockIdx.x) * pw;
+        if (pw == 1) {
+          p[0] = v4[2];
+        } else {
+          p[0] = v4[0];
+          p[1] = v4[1];
+          p[2] = v4[2];
+        }
       }
+      if (fz.kind == 2) fz.part_own[(size_t)rhs * gridDim.x + blockIdx.x] = v4[3];
     }
   }
-  if (fz.kind == 2) {
-    double q[1] = {own_sq};
-    block_sum<1>(q, wred);
-    if (tid == 0) fz.part_own[(size_t)rhs * gridDim.x + blockIdx.x] = q[0];
-  }
 }
-
 
 // ------------------------------------------------------------ matrix cores
 typedef float floatx4 __attribute__((ext_vector_type(4)));
