@@ -85,6 +85,16 @@ typedef struct {
    *   init_vectors[0]: [nv[0]][Lt][Lz][Ly][Lx][4][3]
    *   init_vectors[1]: [nv[1]][Lct][Lcz][Lcy][Lcx][2*nv[0]] (3 levels)    */
   const void *init_vectors[MG_MAX_LEVELS - 1];
+  /* Setup stage two ("Numerical Results"), level 0 only: the relaxed
+   * prototypes are refined in groups of refine_group (0 = off; at most 16
+   * and below nv[0]).  Each group is taken out, a truncated two-level method
+   * is built from the other prototypes (block orthonormalisation and
+   * Galerkin operator as in stage one, FP64), refine_iters iterations
+   * (at most gcr_restart) of the MG-preconditioned flexible GCR are run on
+   * D v = 0 from each prototype of the group, and the normalised iterates
+   * replace the group before the next one is taken.                       */
+  int refine_group;
+  int refine_iters;
 } mg_params_t;
 
 typedef struct {
@@ -177,6 +187,19 @@ int coarse_apply(mg_ctx_t *ctx, int level, const void *in, void *out,
  * (level out of range), MG_ENOTSUP (prec).                                  */
 int mg_apply_op(mg_ctx_t *ctx, int level, mg_prec_t prec, const void *in,
                 void *out, int nrhs, hipStream_t stream);
+
+/* One application of the multigrid preconditioner z = K(r) ("Formulating an
+ * algorithm"; the cycle of Eq. 3 with smoothing): MR pre-smoothing (pre
+ * steps), restriction, the next level's cycle (CGNR to coarse_tol on the
+ * coarsest level), prolongation added to the smoothed iterate, MR
+ * post-smoothing on the new residual (post steps), on every level below the
+ * coarsest.  prec as mg_apply_op.  in/out: DEVICE complex128 canonical fine
+ * spinors [nrhs][Lt][Lz][Ly][Lx][4][3], not aliased; 1 <= nrhs <= 16.
+ * cgnr_iters (host, may be NULL) receives the coarsest-level CGNR
+ * iterations of this call summed over the right-hand sides.  Ordered on
+ * `stream`; synchronous.  Errors: MG_EINVAL, MG_ENOTSUP (prec).            */
+int mg_vcycle(mg_ctx_t *ctx, mg_prec_t prec, const void *in, void *out,
+              int nrhs, int *cgnr_iters, hipStream_t stream);
 
 /* Coarse-stencil kernel choice.  For FP32 arithmetic (MG_F32, MG_F16) the
  * coarse operator D_c ("Formulating an algorithm") can be applied either by

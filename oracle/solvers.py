@@ -122,6 +122,8 @@ class MGParams:
     gcr_restart: int = 8
     max_iter: int = 10000
     antiperiodic_t: bool = True
+    refine_group: int = 0      # setup stage two: group size (0 = off)
+    refine_iters: int = 5
 
 
 @dataclass
@@ -198,6 +200,8 @@ def mg_setup(U, m, params: MGParams, starts, coarse_starts=None):
     L = tuple(reversed(U.shape[1:5]))
     geom = tr.BlockGeometry(L, params.blocks[0])
     V = relax_nullspace(h.op(0), starts, params.setup_rounds, params.setup_mr_steps, params.omega)
+    if params.refine_group > 0 and params.refine_iters > 0:
+        V = refine_nullspace(U, m, params, V, params.refine_group, params.refine_iters)
     Pb, Rc = tr.block_qr(np.moveaxis(geom.blockify(tr.fine_to_generic(V)), 0, -1))
     X, Y = co.galerkin_fine(U, m, Pb, geom, params.antiperiodic_t)
     levels.append(Level(geom, Pb, Rc, X, Y, V))
@@ -210,6 +214,60 @@ def mg_setup(U, m, params: MGParams, starts, coarse_starts=None):
         levels.append(Level(geom2, Pb2, Rc2, X2, Y2, V2))
     h.stats = dict(fine_D=0, coarse_apply=0, cgnr_iters=[])
     return h
+
+
+def refine_nullspace(U, m, params: MGParams, V, group: int, iters: int):
+    """Setup stage two ("Numerical Results"): the prototypes are refined in
+    groups of `group`: a group is taken out of V, a truncated two-level MG is
+    built from the remaining prototypes (block QR and Galerkin operator as in
+    stage one), the truncated MG method is iterated `iters` times on D v = 0
+    from every prototype of the group, and the normalised result goes back
+    into V.  Reading: "the MG method" is the paper's MG-preconditioned
+    flexible GCR, so the iterations are GCR steps (no restart within them)
+    on the homogeneous system started at the prototype."""
+    V = np.array(V, dtype=np.complex128, copy=True)
+    nv = V.shape[0]
+    if group <= 0 or iters <= 0 or group >= nv:
+        return V
+    L = tuple(reversed(U.shape[1:5]))
+    geom = tr.BlockGeometry(L, params.blocks[0])
+    for g0 in range(0, nv, group):
+        grp = list(range(g0, min(g0 + group, nv)))
+        keep = [k for k in range(nv) if k not in grp]
+        Pb, Rc = tr.block_qr(np.moveaxis(geom.blockify(tr.fine_to_generic(V[keep])), 0, -1))
+        X, Y = co.galerkin_fine(U, m, Pb, geom, params.antiperiodic_t)
+        pt = MGParams(**{**params.__dict__, "blocks": [params.blocks[0]], "nv": [len(keep)]})
+        h = Hierarchy(U, m, pt, [Level(geom, Pb, Rc, X, Y, V[keep])])
+        A = h.op(0)
+        for k in grp:
+            x, _, _, _ = gcr_homogeneous(A, lambda r: h.vcycle(r, 0), V[k], iters)
+            V[k] = x / np.sqrt(_nrm2(x))
+    return V
+
+
+def gcr_homogeneous(A, K, v, iters: int):
+    """`iters` steps of flexible GCR preconditioned by K on A x = 0 from x = v
+    (no restart): z_j = K(r), w_j = A z_j made orthonormal to the earlier w
+    (the same combination applied to z_j), x += <w_j, r> z_j,
+    r -= <w_j, r> w_j.  Returns (x, r, Z, W)."""
+    x = v.copy()
+    r = -A(x)
+    Z, Wv = [], []
+    for _ in range(iters):
+        z = K(r)
+        w = A(z)
+        for zi, wi in zip(Z, Wv):
+            beta = _dot(wi, w)
+            w = w - beta * wi
+            z = z - beta * zi
+        nw = np.sqrt(_nrm2(w))
+        w, z = w / nw, z / nw
+        Z.append(z)
+        Wv.append(w)
+        alpha = _dot(w, r)
+        x = x + alpha * z
+        r = r - alpha * w
+    return x, r, Z, Wv
 
 
 def fgcr(A, K, b, tol: float, restart: int = 8, max_iter: int = 10000, x0=None):

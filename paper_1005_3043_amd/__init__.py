@@ -22,7 +22,7 @@ MAX_LEVELS = 3
 MAX_RHS = 16
 
 EXPORTED = ["wilson_apply", "mg_setup", "mg_set_precond_prec", "mg_set_mass", "mg_set_timing", "mg_restrict",
-            "mg_prolong", "coarse_apply", "mg_apply_op", "mg_set_coarse_variant", "mg_coarse_variant", "mg_solve", "mg_time_dslash", "mg_time_coarse",
+            "mg_prolong", "coarse_apply", "mg_apply_op", "mg_vcycle", "mg_set_coarse_variant", "mg_coarse_variant", "mg_solve", "mg_time_dslash", "mg_time_coarse",
             "mg_destroy", "mg_last_error", "mg_export_maps", "mg_export_P",
             "mg_export_coarse_op", "mg_export_nullvecs", "mg_level_info",
             "ptc_create", "ptc_set_links", "ptc_set_targets", "ptc_forward", "ptc_loss_grad", "ptc_adam",
@@ -54,7 +54,8 @@ class Params(ctypes.Structure):
                 ("precond_prec", ctypes.c_int),
                 ("max_rhs", ctypes.c_int),
                 ("use_graph", ctypes.c_int),
-                ("init_vectors", ctypes.c_void_p * (MAX_LEVELS - 1))]
+                ("init_vectors", ctypes.c_void_p * (MAX_LEVELS - 1)),
+                ("refine_group", ctypes.c_int), ("refine_iters", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -103,6 +104,7 @@ def lib():
             "mg_prolong": [vp, ci, vp, vp, ci, vp],
             "coarse_apply": [vp, ci, vp, vp, ci, ci, vp],
             "mg_apply_op": [vp, ci, ci, vp, vp, ci, vp],
+            "mg_vcycle": [vp, ci, vp, vp, ci, ctypes.POINTER(ci), vp],
             "mg_set_coarse_variant": [vp, ci],
             "mg_coarse_variant": [vp, ci, ci, ci, ctypes.POINTER(ci), ctypes.POINTER(cd)],
             "mg_solve": [vp, vp, vp, ci, cd, ctypes.POINTER(Info), vp],
@@ -175,7 +177,7 @@ class MG:
     def __init__(self, U: torch.Tensor, mass: float, blocks, nv, init_vectors, *,
                  t_antiperiodic=True, setup_rounds=5, setup_mr_steps=4, omega=0.9, pre=4,
                  post=4, coarse_tol=1e-3, coarse_maxiter=1000, gcr_restart=8, max_iter=10000,
-                 precond_prec="f64", max_rhs=1, use_graph=True):
+                 precond_prec="f64", max_rhs=1, use_graph=True, refine_group=0, refine_iters=5):
         Lt, Lz, Ly, Lx = U.shape[1:5]
         self.L = (Lx, Ly, Lz, Lt)
         self.nv = list(nv)
@@ -190,6 +192,7 @@ class MG:
         p.pre, p.post, p.coarse_tol, p.coarse_maxiter = pre, post, coarse_tol, coarse_maxiter
         p.gcr_restart, p.max_iter = gcr_restart, max_iter
         p.precond_prec, p.max_rhs, p.use_graph = PREC[precond_prec], max_rhs, int(bool(use_graph))
+        p.refine_group, p.refine_iters = int(refine_group), int(refine_iters)
         self._keep = list(init_vectors)
         for i, v in enumerate(init_vectors):
             p.init_vectors[i] = _dev(v, f"init_vectors[{i}]").value
@@ -262,6 +265,17 @@ class MG:
         out = torch.empty_like(v)
         _check(lib().mg_apply_op(self.ctx, level, PREC[prec], _dev(v, "in"), _dev(out, "out"), nrhs, _stream()))
         return out
+
+    def vcycle(self, r, prec="f64"):
+        """One preconditioner application z = K(r) on canonical fine spinors
+        (complex128, [nrhs] + lattice shape or one spinor); returns (z, summed
+        coarsest-level CGNR iterations)."""
+        nrhs = self._nvec(0, r)
+        out = torch.empty_like(r)
+        it = ctypes.c_int(0)
+        _check(lib().mg_vcycle(self.ctx, PREC[prec], _dev(r, "in"), _dev(out, "out"), nrhs, ctypes.byref(it),
+                               _stream()))
+        return out, it.value
 
     def set_coarse_variant(self, variant):
         """Force the coarse-stencil kernel (0 per-RHS, 1/2/4 matrix-core GEMM

@@ -54,6 +54,10 @@ int check_params(const mg_lattice_t *lat, const mg_params_t *p) {
     return bad(MG_EINVAL, "bad omega / coarse tolerance / coarse iteration cap");
   if (p->gcr_restart < 1 || p->gcr_restart > 64 || p->max_iter < 1) return bad(MG_EINVAL, "bad GCR parameters");
   if (p->max_rhs < 1 || p->max_rhs > MG_MAX_RHS) return bad(MG_EINVAL, "max_rhs out of range");
+  if (p->refine_group < 0 || p->refine_group > MG_MAX_RHS || (p->refine_group > 0 && p->refine_group >= p->nv[0]))
+    return bad(MG_EINVAL, "refine_group must be 0 (off) or in [1, min(16, nv[0] - 1)]");
+  if (p->refine_group > 0 && (p->refine_iters < 0 || p->refine_iters > p->gcr_restart))
+    return bad(MG_EINVAL, "refine_iters must be in [0, gcr_restart]");
   if (p->precond_prec != MG_F64 && p->precond_prec != MG_F32 && p->precond_prec != MG_F16)
     return bad(MG_ENOTSUP, "precond_prec must be MG_F64, MG_F32 or MG_F16");
   return MG_OK;
@@ -329,6 +333,41 @@ extern "C" int mg_solve(mg_ctx_t *ctx, const void *b, void *x, int nrhs, double 
     }
   }
   return rc;
+}
+
+extern "C" int mg_vcycle(mg_ctx_t *ctx, mg_prec_t prec, const void *in, void *out, int nrhs, int *cgnr_iters,
+                         hipStream_t st) {
+  set_error("");
+  if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
+  if (!in || !out || in == out) return bad(MG_EINVAL, "mg_vcycle: bad buffers");
+  if (nrhs < 1 || nrhs > MG_MAX_RHS) return bad(MG_EINVAL, "mg_vcycle: nrhs out of range");
+  if (prec != MG_F64 && prec != MG_F32 && prec != MG_F16)
+    return bad(MG_ENOTSUP, "mg_vcycle: prec must be MG_F64, MG_F32 or MG_F16");
+  mg_ctx *c = ctx;
+  MG_TRY(ensure_prec(c, prec, st));
+  if (prec == MG_F64) MG_TRY(ensure_work<double>(c, nrhs));
+  else MG_TRY(ensure_work<float>(c, nrhs));
+  MG_TRY(ensure_scalars(c, part_need(c, nrhs)));
+  const Level &L0 = c->lev[0];
+  DevBuf<double2> a, b;
+  MG_TRY(a.alloc(L0.vsize() * nrhs));
+  MG_TRY(b.alloc(L0.vsize() * nrhs));
+  c->n_cgnr = 0;
+  // the cycle runs on the context's own stream (graph capture needs a
+  // non-default stream), ordered after and before the caller's stream
+  hipStream_t s2 = c->sti;
+  HIPK(hipEventRecord(c->ev_in, st));
+  HIPK(hipStreamWaitEvent(s2, c->ev_in, 0));
+  HIPK(pack_field<double>(L0.g, (const double2 *)in, a, 12, nrhs, s2));
+  const int rc = precondition_at(c, prec, a, b, nrhs, s2);
+  if (rc < 0) {
+    (void)hipStreamSynchronize(s2);
+    return rc;
+  }
+  HIPK(unpack_field<double>(L0.g, b, (double2 *)out, 12, nrhs, s2));
+  HIPK(hipStreamSynchronize(s2));
+  if (cgnr_iters) *cgnr_iters = (int)c->n_cgnr;
+  return MG_OK;
 }
 
 namespace {

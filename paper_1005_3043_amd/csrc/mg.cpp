@@ -575,18 +575,23 @@ template <typename P> int vcycle(mg_ctx *c, int l, const vec_t<P> *rin, vec_t<P>
   return MG_OK;
 }
 
-// z = K(r) in the context's preconditioner precision (FP64 in and out).
-int precondition(mg_ctx *c, const double2 *r, double2 *z, int nrhs, hipStream_t st) {
+// z = K(r) in the precision prec (FP64 in and out).
+int precondition_at(mg_ctx *c, mg_prec_t prec, const double2 *r, double2 *z, int nrhs, hipStream_t st) {
   c->n_vcyc += nrhs;
-  if (c->prec == MG_F64) return vcycle<PF64>(c, 0, r, z, nrhs, st);
+  if (prec == MG_F64) return vcycle<PF64>(c, 0, r, z, nrhs, st);
   Work<float> &w = c->w32;
   const size_t n = c->lev[0].vsize() * nrhs;
   float2 *rin = w.rin[0], *x = w.x[0];
   HIPK((convert<float, double>(rin, r, n, st)));
-  if (c->prec == MG_F16) MG_TRY(vcycle<PF16>(c, 0, rin, x, nrhs, st));
+  if (prec == MG_F16) MG_TRY(vcycle<PF16>(c, 0, rin, x, nrhs, st));
   else MG_TRY(vcycle<PF32>(c, 0, rin, x, nrhs, st));
   HIPK((convert<double, float>(z, x, n, st)));
   return MG_OK;
+}
+
+// z = K(r) in the context's preconditioner precision.
+int precondition(mg_ctx *c, const double2 *r, double2 *z, int nrhs, hipStream_t st) {
+  return precondition_at(c, c->prec, r, z, nrhs, st);
 }
 
 // ------------------------------------------------------------ FGCR
@@ -709,6 +714,115 @@ int relax(mg_ctx *c, int l, double2 *V, int nv, hipStream_t st) {
   return MG_OK;
 }
 
+// Drops the solver work buffers so that the next ensure_work allocates them
+// afresh (zeroed) for the current level sizes.
+template <typename R> void release_work(Work<R> &w) {
+  for (int l = 0; l < MG_MAX_LEVELS; ++l) {
+    w.x[l].release();
+    w.r[l].release();
+    w.q[l].release();
+    w.rin[l].release();
+  }
+  w.ce.release();
+  w.cr.release();
+  w.cz.release();
+  w.cp.release();
+  w.cw.release();
+  w.cp2.release();
+  w.cr2.release();
+  w.nrhs = 0;
+}
+
+// Setup stage two ("Numerical Results") on the level-0 prototypes in NV:
+// groups of refine_group vectors are taken out in turn; the remaining
+// prototypes define a truncated two-level method (block orthonormalisation,
+// Galerkin operator, the usual V-cycle with the coarsest-level CGNR); from
+// each prototype v of the group, refine_iters steps of the flexible GCR
+// preconditioned by that V-cycle are run on D v = 0 (residual -D v, no
+// restart), and the normalised iterates replace the group.  Level sizes are
+// shrunk while a group is out and restored afterwards; work buffers, captured
+// graphs and tuned coarse variants made at the shrunk sizes are dropped.
+int refine(mg_ctx *c, hipStream_t st_in) {
+  const int G0 = c->p.refine_group, iters = c->p.refine_iters;
+  Level &L0 = c->lev[0], &L1 = c->lev[1];
+  const int nv = L0.nv;
+  if (G0 <= 0 || iters <= 0 || G0 >= nv) return MG_OK;
+  // runs on the context's own stream (the coarsest-level CGNR captures
+  // graphs, which the default stream does not allow), after st_in's work
+  hipStream_t st = c->sti;
+  HIPK(hipEventRecord(c->ev_in, st_in));
+  HIPK(hipStreamWaitEvent(st, c->ev_in, 0));
+  const int nlev = c->nlev, n1 = L1.n;
+  const size_t n = L0.vsize();
+  DevBuf<double2> X, R, Z, W;
+  MG_TRY(X.alloc(n * G0));
+  MG_TRY(R.alloc(n * G0));
+  MG_TRY(Z.alloc(n * G0 * iters));
+  MG_TRY(W.alloc(n * G0 * iters));
+  MG_TRY(L1.L64.alloc((size_t)L1.g.V * 9 * n1 * n1));
+  double *rr = c->dsc;
+  double2 *sc = c->csc;
+  int *flag = c->done;
+  int rc = MG_OK;
+  for (int g0 = 0; g0 < nv && rc == MG_OK; g0 += G0) {
+    const int G = std::min(G0, nv - g0), nk = nv - G;
+    const size_t nn = n * G;
+    // the kept prototypes, in order, as the truncated method's P
+    if (g0 > 0) HIPK(hipMemcpyAsync(L0.P64, L0.NV, n * g0 * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    if (g0 + G < nv)
+      HIPK(hipMemcpyAsync(L0.P64 + n * g0, L0.NV + n * (g0 + G), n * (nv - g0 - G) * sizeof(double2),
+                          hipMemcpyDeviceToDevice, st));
+    c->nlev = 2;
+    L0.nv = nk;
+    L1.n = 2 * nk;
+    release_work(c->w64);
+    clear_graphs(c);
+    std::memset(c->cvar, 0xff, sizeof(c->cvar));
+    HIPK(hipMemsetAsync(flag, 0, sizeof(int), st));
+    HIPK(ortho_fine(L0.g, nk, L0.P64, flag, st));
+    HIPK(hipMemcpyAsync(c->h_done, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPK(hipStreamSynchronize(st));
+    if (c->h_done[0]) {
+      set_error("mg_setup: rank-deficient aggregate in the refinement's block orthonormalisation");
+      rc = MG_ERANK;
+      break;
+    }
+    HIPK(galerkin_fine(L0.g, L1.g, c->mass, L0.U64, nk, L0.P64, L1.L64, st));
+    if ((rc = ensure_work<double>(c, G)) != MG_OK) break;
+    // x = v, r = -D v
+    double2 *x = X, *r = R;
+    HIPK(hipMemcpyAsync(x, L0.NV + n * g0, nn * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    if ((rc = apply_A<PF64>(c, 0, x, W, G, DS_PLAIN, nullptr, st)) != MG_OK) break;
+    HIPK(zero<double>(r, nn, st));
+    HIPK(sub_inplace<double>(r, W, n, G, st));
+    for (int j = 0; j < iters && rc == MG_OK; ++j) {
+      double2 *Zj = Z + (size_t)j * nn, *Wj = W + (size_t)j * nn;
+      if ((rc = vcycle<PF64>(c, 0, r, Zj, G, st)) != MG_OK) break;
+      if ((rc = apply_A<PF64>(c, 0, Zj, Wj, G, DS_PLAIN, nullptr, st)) != MG_OK) break;
+      for (int i = 0; i < j; ++i) {
+        HIPK(dot<double>(W + (size_t)i * nn, Wj, n, G, c->part, sc, st));
+        HIPK(gcr_sub2(Wj, W + (size_t)i * nn, Zj, Z + (size_t)i * nn, n, G, sc, nullptr, st));
+      }
+      HIPK(norm2<double>(Wj, n, G, c->part, rr + MG_MAX_RHS, st));
+      HIPK(gcr_scale2(Wj, Zj, n, G, rr + MG_MAX_RHS, nullptr, st));
+      HIPK(dot<double>(Wj, r, n, G, c->part, sc, st));
+      HIPK(gcr_update(x, Zj, r, Wj, n, G, sc, nullptr, c->part, rr, st));
+    }
+    if (rc != MG_OK) break;
+    HIPK(norm2<double>(x, n, G, c->part, rr, st));
+    HIPK(scale_rsqrt<double>(x, n, G, rr, st));
+    HIPK(hipMemcpyAsync(L0.NV + n * g0, x, nn * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    HIPK(hipStreamSynchronize(st));
+  }
+  c->nlev = nlev;
+  L0.nv = nv;
+  L1.n = n1;
+  release_work(c->w64);
+  clear_graphs(c);
+  std::memset(c->cvar, 0xff, sizeof(c->cvar));
+  return rc;
+}
+
 int setup(mg_ctx *c, const void *U, hipStream_t st) {
   const mg_params_t &p = c->p;
   const int anti = c->lat.t_antiperiodic ? 1 : 0;
@@ -761,6 +875,7 @@ int setup(mg_ctx *c, const void *U, hipStream_t st) {
     if (l == 0) HIPK(pack_field<double>(Lv.g, (const double2 *)p.init_vectors[0], Lv.NV, 12, Lv.nv, st));
     else HIPK(pack_aos<double>(Lv.g, (const double2 *)p.init_vectors[l], Lv.NV, Lv.n, Lv.nv, st));
     MG_TRY(relax(c, l, Lv.NV, Lv.nv, st));
+    if (l == 0) MG_TRY(refine(c, st));
     HIPK(hipMemcpyAsync(Lv.P64, Lv.NV, nvs * sizeof(double2), hipMemcpyDeviceToDevice, st));
     HIPK(hipMemsetAsync(flag, 0, sizeof(int), st));
     if (l == 0) HIPK(ortho_fine(Lv.g, Lv.nv, Lv.P64, flag, st));

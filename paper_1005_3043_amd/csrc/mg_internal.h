@@ -24,6 +24,7 @@ int transfer_prolong(mg_ctx *c, int l, const vec_t<P> *coarse, vec_t<P> *fine, i
 template <typename P> int vcycle(mg_ctx *c, int l, const vec_t<P> *rin, vec_t<P> *x, int nrhs, hipStream_t st);
 int fgcr(mg_ctx *c, const double2 *b, double2 *x, int nrhs, double tol, int *iters, double *relres,
          hipStream_t st);
+int precondition_at(mg_ctx *c, mg_prec_t prec, const double2 *r, double2 *z, int nrhs, hipStream_t st);
 int setup(mg_ctx *c, const void *U, hipStream_t st);
 int check_lattice(const mg_lattice_t *lat);
 template <typename P> const typename P::S *links_of_level(Level &L);

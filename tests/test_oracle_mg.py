@@ -272,3 +272,105 @@ def test_three_level_hierarchy_galerkin():
     x, it, conv, _ = so.mg_solve(h, b, 1e-10)
     assert conv
     assert np.linalg.norm(b - wi.apply_D(U, x, m)) <= 1.0001e-10 * np.linalg.norm(b)
+
+
+# ---------------------------------------------------------------- setup stage two
+def test_gcr_homogeneous_minimal_residual():
+    """GCR steps on A x = 0 from v: the recurred residual is -A x, the w_j are
+    orthonormal and orthogonal to the final residual, x - v lies in span(Z),
+    and ||A x|| is the least-squares minimum over v + span(Z) (library lstsq),
+    for a flexible (arbitrary linear) preconditioner."""
+    rng = np.random.default_rng(5)
+    n = 40
+    A = np.eye(n) * 3 + rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    K = np.linalg.inv(A) + 0.05 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    v = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x, r, Z, Wv = so.gcr_homogeneous(lambda u: A @ u, lambda u: K @ u, v, 5)
+    assert np.abs(r + A @ x).max() < 1e-12 * np.abs(A @ v).max()
+    Wm, Zm = np.stack(Wv, 1), np.stack(Z, 1)
+    assert np.abs(Wm.conj().T @ Wm - np.eye(5)).max() < 1e-12
+    assert np.abs(Wm.conj().T @ r).max() < 1e-12 * np.linalg.norm(A @ v)
+    c, *_ = np.linalg.lstsq(A @ Zm, -(A @ v), rcond=None)
+    assert np.abs(x - (v + Zm @ c)).max() < 1e-10 * np.linalg.norm(v)
+    assert abs(np.linalg.norm(A @ x) - np.linalg.norm(A @ (v + Zm @ c))) < 1e-12 * np.linalg.norm(A @ v)
+    assert np.linalg.norm(A @ x) < np.linalg.norm(A @ v)
+
+
+def _refine_case():
+    L, b, nv, m = (4, 4, 4, 4), (2, 2, 2, 2), 5, -0.3
+    U = W.gauge_field(L, 0.3, 4)
+    p = so.MGParams(blocks=[b], nv=[nv], setup_rounds=2, coarse_tol=1e-12, coarse_maxiter=5000)
+    h = so.mg_setup(U, m, p, W.setup_starts(L, nv, 4))
+    return U, m, p, h.levels[0].nullvecs
+
+
+def test_refine_gauge_covariant_and_scale_invariant():
+    """Refining g V on U^g gives g (refined V) (the truncated hierarchy, the
+    V-cycle and GCR are gauge covariant), and rescaling the prototypes by
+    complex factors only rephases the refined ones (block QR fixes the span,
+    GCR is linear in its start, the result is normalised).  Group 2 of 5
+    prototypes leaves a ragged last group of one."""
+    U, m, p, V = _refine_case()
+    Vr = so.refine_nullspace(U, m, p, V, 2, 3)
+    g = W.gauge_transform(U.shape[1:5][::-1], 9)
+    Vg = so.refine_nullspace(wi.gauge_transform_links(U, g), m, p, wi.gauge_transform_spinor(g, V), 2, 3)
+    assert np.abs(Vg - wi.gauge_transform_spinor(g, Vr)).max() < 1e-9
+    ph = np.exp(1j * np.arange(1, 6)) * np.arange(1, 6)
+    Vs = so.refine_nullspace(U, m, p, V * ph[:, None, None, None, None, None, None], 2, 3)
+    ph_n = (ph / np.abs(ph))[:, None, None, None, None, None, None]
+    assert np.abs(Vs - Vr * ph_n).max() < 1e-9
+
+
+def test_refine_lowers_residual_and_keeps_norm():
+    """Every refined prototype has unit norm, and the group's GCR makes
+    ||D v|| / ||v|| no larger than the relaxed prototype's; zero iterations
+    leave V unchanged."""
+    U, m, p, V = _refine_case()
+    assert np.array_equal(so.refine_nullspace(U, m, p, V, 2, 0), V)
+    Vr = so.refine_nullspace(U, m, p, V, 2, 3)
+    A = lambda u: wi.apply_D(U, u, m)  # noqa: E731
+    for k in range(V.shape[0]):
+        assert abs(np.linalg.norm(Vr[k]) - 1) < 1e-12
+        assert np.linalg.norm(A(Vr[k])) <= np.linalg.norm(A(V[k])) / np.linalg.norm(V[k]) * (1 + 1e-12)
+
+
+def test_refine_one_step_is_projection_on_kept_span():
+    """With no smoothing and an exact coarse solve the truncated method is
+    K = P_k (P_k^dag D P_k)^{-1} P_k^dag, P_k spanning the kept prototypes
+    restricted to each (aggregate, chirality) (K does not depend on the basis,
+    so P_k is built from the raw prototypes, by coordinates).  One GCR step
+    from v is x = v + a K(-D v) with a minimising ||D x|| (closed form), then
+    x / ||x||.  Groups of one: the second prototype is refined with the first
+    one already replaced."""
+    U, m, p, V = _refine_case()
+    L, (bx, by, bz, bt), nv = (4, 4, 4, 4), (2, 2, 2, 2), V.shape[0]
+    p0 = so.MGParams(blocks=[(bx, by, bz, bt)], nv=[nv], pre=0, post=0, coarse_tol=1e-13,
+                     coarse_maxiter=20000)
+    Vr = so.refine_nullspace(U, m, p0, V, 1, 1)
+    D = wi.D_dense(U, m)
+
+    agg = np.array([(x // bx) + 2 * ((y // by) + 2 * ((z // bz) + 2 * (t // bt)))
+                    for t in range(L[3]) for z in range(L[2]) for y in range(L[1]) for x in range(L[0])])
+    comp_chi = np.arange(12) // 6
+
+    def refined(Vcur, k):
+        cols = []
+        for j in range(nv):
+            if j == k:
+                continue
+            f = Vcur[j].reshape(-1, 12)
+            for a in range(16):
+                for h in range(2):
+                    mask = (agg[:, None] == a) & (comp_chi[None, :] == h)
+                    cols.append(np.where(mask, f, 0).ravel())
+        Pk = np.stack(cols, 1)
+        v = Vcur[k].ravel()
+        z = -Pk @ np.linalg.solve(Pk.conj().T @ D @ Pk, Pk.conj().T @ (D @ v))
+        Dz, Dv = D @ z, D @ v
+        x = v - np.vdot(Dz, Dv) / np.vdot(Dz, Dz) * z
+        return (x / np.linalg.norm(x)).reshape(V[k].shape)
+    e0 = refined(V, 0)
+    assert np.abs(Vr[0] - e0).max() < 1e-8
+    V1 = V.copy()
+    V1[0] = Vr[0]
+    assert np.abs(Vr[1] - refined(V1, 1)).max() < 1e-8
