@@ -91,8 +91,9 @@ typedef struct {
    * is built from the other prototypes (block orthonormalisation and
    * Galerkin operator as in stage one, FP64), refine_iters iterations
    * (at most gcr_restart) of the MG-preconditioned flexible GCR are run on
-   * D v = 0 from each prototype of the group, and the normalised iterates
-   * replace the group before the next one is taken.                       */
+   * D v = 0 from each prototype of the group (GCR in FP64, its V-cycles in
+   * precond_prec), and the normalised iterates replace the group before
+   * the next one is taken.                                                */
   int refine_group;
   int refine_iters;
 } mg_params_t;

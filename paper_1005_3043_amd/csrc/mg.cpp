@@ -733,13 +733,24 @@ template <typename R> void release_work(Work<R> &w) {
   w.nrhs = 0;
 }
 
+// Drops the low-precision copies of the level-0 prolongator and the level-1
+// operator; the next ensure_prec rebuilds them from the FP64 data.
+void drop_op_copies(mg_ctx *c) {
+  c->lev[0].P32.release();
+  c->lev[0].P16.release();
+  c->lev[1].L32.release();
+  c->lev[1].L16.release();
+}
+
 // Setup stage two ("Numerical Results") on the level-0 prototypes in NV:
 // groups of refine_group vectors are taken out in turn; the remaining
 // prototypes define a truncated two-level method (block orthonormalisation,
 // Galerkin operator, the usual V-cycle with the coarsest-level CGNR); from
 // each prototype v of the group, refine_iters steps of the flexible GCR
 // preconditioned by that V-cycle are run on D v = 0 (residual -D v, no
-// restart), and the normalised iterates replace the group.  Level sizes are
+// restart), and the normalised iterates replace the group.  The V-cycles run
+// in the context's preconditioner precision (copies of the truncated P and
+// D_c made per group), the GCR steps in FP64.  Level sizes are
 // shrunk while a group is out and restored afterwards; work buffers, captured
 // graphs and tuned coarse variants made at the shrunk sizes are dropped.
 int refine(mg_ctx *c, hipStream_t st_in) {
@@ -752,7 +763,8 @@ int refine(mg_ctx *c, hipStream_t st_in) {
   hipStream_t st = c->sti;
   HIPK(hipEventRecord(c->ev_in, st_in));
   HIPK(hipStreamWaitEvent(st, c->ev_in, 0));
-  const int nlev = c->nlev, n1 = L1.n;
+  const int nlev = c->nlev, n1 = L1.n, nv1 = L1.nv;
+  const mg_prec_t rp = c->prec;
   const size_t n = L0.vsize();
   DevBuf<double2> X, R, Z, W;
   MG_TRY(X.alloc(n * G0));
@@ -775,7 +787,10 @@ int refine(mg_ctx *c, hipStream_t st_in) {
     c->nlev = 2;
     L0.nv = nk;
     L1.n = 2 * nk;
+    L1.nv = 0;
     release_work(c->w64);
+    release_work(c->w32);
+    drop_op_copies(c);
     clear_graphs(c);
     std::memset(c->cvar, 0xff, sizeof(c->cvar));
     HIPK(hipMemsetAsync(flag, 0, sizeof(int), st));
@@ -789,6 +804,10 @@ int refine(mg_ctx *c, hipStream_t st_in) {
     }
     HIPK(galerkin_fine(L0.g, L1.g, c->mass, L0.U64, nk, L0.P64, L1.L64, st));
     if ((rc = ensure_work<double>(c, G)) != MG_OK) break;
+    if (rp != MG_F64) {
+      if ((rc = ensure_prec(c, rp, st)) != MG_OK) break;
+      if ((rc = ensure_work<float>(c, G)) != MG_OK) break;
+    }
     // x = v, r = -D v
     double2 *x = X, *r = R;
     HIPK(hipMemcpyAsync(x, L0.NV + n * g0, nn * sizeof(double2), hipMemcpyDeviceToDevice, st));
@@ -797,7 +816,7 @@ int refine(mg_ctx *c, hipStream_t st_in) {
     HIPK(sub_inplace<double>(r, W, n, G, st));
     for (int j = 0; j < iters && rc == MG_OK; ++j) {
       double2 *Zj = Z + (size_t)j * nn, *Wj = W + (size_t)j * nn;
-      if ((rc = vcycle<PF64>(c, 0, r, Zj, G, st)) != MG_OK) break;
+      if ((rc = precondition_at(c, rp, r, Zj, G, st)) != MG_OK) break;
       if ((rc = apply_A<PF64>(c, 0, Zj, Wj, G, DS_PLAIN, nullptr, st)) != MG_OK) break;
       for (int i = 0; i < j; ++i) {
         HIPK(dot<double>(W + (size_t)i * nn, Wj, n, G, c->part, sc, st));
@@ -817,7 +836,10 @@ int refine(mg_ctx *c, hipStream_t st_in) {
   c->nlev = nlev;
   L0.nv = nv;
   L1.n = n1;
+  L1.nv = nv1;
   release_work(c->w64);
+  release_work(c->w32);
+  drop_op_copies(c);
   clear_graphs(c);
   std::memset(c->cvar, 0xff, sizeof(c->cvar));
   return rc;

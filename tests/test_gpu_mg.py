@@ -320,6 +320,19 @@ def test_set_mass(cuda):
         assert rc == 0 and res <= 1e-10 * 1.001
 
 
+_REFINED = {}
+
+
+def _oracle_refined(name, group):
+    """The oracle's refined hierarchy (CGNR to 1e-3), cached per case."""
+    if (name, group) not in _REFINED:
+        L, blocks, nv, eps, m, seed = CASES[name]
+        U = W.gauge_field(L, eps, seed)
+        _REFINED[name, group] = so.mg_setup(U, m, so.MGParams(blocks=blocks, nv=nv, refine_group=group,
+                                                              refine_iters=5), W.setup_starts(L, nv[0], seed))
+    return _REFINED[name, group]
+
+
 @pytest.mark.parametrize("name,group", [("8^4 b4^4 nv8", 3), ("6x4x2x8 b3x2x1x4 nv5", 2),
                                         ("4^4 b2^4 nv4", 1)])
 def test_setup_refinement(cuda, name, group):
@@ -349,7 +362,7 @@ def test_setup_refinement(cuda, name, group):
     e2 = max(_rel(X, h.levels[0].X), _rel(Y, h.levels[0].Y))
     ctx.close()
     ctx = mgwd.MG(Ud, m, blocks, nv, [sd], refine_group=group, refine_iters=5)
-    h = so.mg_setup(U, m, so.MGParams(blocks=blocks, nv=nv, refine_group=group, refine_iters=5), starts)
+    h = _oracle_refined(name, group)
     Vg, Vo = ctx.export_nullvecs(0), h.levels[0].nullvecs
     q = [abs(np.linalg.norm(wi.apply_D(U, Vg[k], m)) / np.linalg.norm(Vg[k])
              / (np.linalg.norm(wi.apply_D(U, Vo[k], m)) / np.linalg.norm(Vo[k])) - 1) for k in range(nv[0])]
@@ -368,6 +381,37 @@ def test_setup_refinement(cuda, name, group):
     assert max(q) < 1e-2
     assert rc == 0 and res <= 1e-10 * 1.001
     assert abs(info["iters"][0] - it_ref) <= 1
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_setup_refinement_lowprec(cuda, prec):
+    """Refinement with the truncated V-cycles in FP32 or with FP16-stored
+    operators (GCR steps in FP64): each refined vector's ||D v|| / ||v||
+    within 5 % of the oracle's FP64 refinement, and the solve with that
+    preconditioner within 2 outer iterations of the oracle's refined FP64
+    count, at 1e-10 by the oracle's operator."""
+    import paper_1005_3043_amd as mgwd
+    name, group = "8^4 b4^4 nv8", 3
+    L, blocks, nv, eps, m, seed = CASES[name]
+    U = W.gauge_field(L, eps, seed)
+    starts = W.setup_starts(L, nv[0], seed)
+    print(f"{name}: refinement group {group}, {prec} V-cycles", flush=True)
+    ctx = mgwd.MG(torch.from_numpy(U).cuda(), m, blocks, nv, [torch.from_numpy(starts).cuda()],
+                  refine_group=group, refine_iters=5, precond_prec=prec)
+    h = _oracle_refined(name, group)
+    Vg, Vo = ctx.export_nullvecs(0), h.levels[0].nullvecs
+    q = [abs(np.linalg.norm(wi.apply_D(U, Vg[k], m)) / np.linalg.norm(Vg[k])
+             / (np.linalg.norm(wi.apply_D(U, Vo[k], m)) / np.linalg.norm(Vo[k])) - 1) for k in range(nv[0])]
+    b = W.gaussian_spinor(L, 0)
+    x, info, rc = ctx.solve(torch.from_numpy(b).cuda(), 1e-10)
+    ctx.close()
+    res = np.linalg.norm(b - wi.apply_D(U, x.cpu().numpy(), m)) / np.linalg.norm(b)
+    _, it_ref, _, _ = so.mg_solve(h, b, 1e-10)
+    print(f"{name}: {prec} refinement: max ||Dv||/||v|| rel diff {max(q):.1e}, iterations {info['iters'][0]} "
+          f"(oracle FP64 {it_ref}), true rel resid {res:.2e}")
+    assert max(q) < 5e-2
+    assert rc == 0 and res <= 1e-10 * 1.001
+    assert abs(info["iters"][0] - it_ref) <= 2
 
 
 def test_setup_errors(cuda):
