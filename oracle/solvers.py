@@ -11,6 +11,12 @@ Paper sources:
     times (4 pre, 4 post).
   * Coarsest grid: CG on the normal equations to relative accuracy 1e-3
     ("Numerical Results").  D_c^dag is the plain adjoint of the stencil.
+  * The paper's own cycle ("Numerical Results"): V(0,4) with GMRES(4)
+    post-relaxation under-relaxed by omega, and a W-cycle in which every
+    correction of the fine grid takes two cycles of the intermediate grid.
+    Readings: the GMRES smoother is x = omega * GMRES(k)(A, r) from x = 0
+    (one cycle, no restart); the second intermediate cycle is applied to the
+    intermediate residual left by the first and its result added.
   * Outer solver: flexible GCR with restart length 8, because the
     preconditioner is non-stationary ("Formulating an algorithm").
   * Setup stage 1: relaxation applied to random vectors on A x = 0 gives
@@ -54,6 +60,46 @@ def mr(A, b, steps: int, omega: float = 0.9):
         x = x + a * r
         r = r - a * q
     return x, r
+
+
+def gmres(A, b, k: int):
+    """One GMRES(k) cycle from y = 0: the y in the Krylov space
+    span{b, Ab, ..., A^(k-1) b} that minimises ||b - A y||, through Arnoldi
+    with modified Gram-Schmidt and the (k+1) x k Hessenberg least-squares
+    problem (library lstsq).  A zero subdiagonal entry means the space is
+    invariant and ends it early; b = 0 gives y = 0."""
+    y = np.zeros_like(b)
+    beta = np.sqrt(_nrm2(b))
+    if beta == 0.0 or k <= 0:
+        return y
+    V = [b / beta]
+    H = np.zeros((k + 1, k), dtype=np.complex128)
+    kk = k
+    for j in range(k):
+        w = A(V[j])
+        for i in range(j + 1):
+            H[i, j] = _dot(V[i], w)
+            w = w - H[i, j] * V[i]
+        H[j + 1, j] = np.sqrt(_nrm2(w))
+        if H[j + 1, j] == 0.0:
+            kk = j + 1
+            break
+        V.append(w / H[j + 1, j])
+    g = np.zeros(kk + 1, dtype=np.complex128)
+    g[0] = beta
+    c, *_ = np.linalg.lstsq(H[:kk + 1, :kk], g, rcond=None)
+    for j in range(kk):
+        y = y + c[j] * V[j]
+    return y
+
+
+def gmres_smooth(A, b, steps: int, omega: float = 0.9):
+    """GMRES smoother with under-relaxation ("Formulating an algorithm"):
+    x = omega * GMRES(steps)(A, b) from x = 0.  Returns (x, b - A x)."""
+    if steps <= 0:
+        return np.zeros_like(b), b.copy()
+    x = omega * gmres(A, b, steps)
+    return x, b - A(x)
 
 
 def mr_batch(A, b, steps: int, omega: float = 0.9):
@@ -124,6 +170,8 @@ class MGParams:
     antiperiodic_t: bool = True
     refine_group: int = 0      # setup stage two: group size (0 = off)
     refine_iters: int = 5
+    smoother: str = "mr"       # "mr": pre/post MR steps; "gmres": GMRES(pre), GMRES(post)
+    cycles: int = 1            # cycles of level l+1 per correction of level l (2 = W-cycle)
 
 
 @dataclass
@@ -185,11 +233,18 @@ class Hierarchy:
             self.stats["cgnr_iters"].append(it)
             return e
         A = self.op(lvl)
-        x, rho = mr(A, r, p.pre, p.omega)
-        ec = self.vcycle(self.restrict(lvl, rho), lvl + 1)
+        smooth = gmres_smooth if p.smoother == "gmres" else mr
+        x, rho = smooth(A, r, p.pre, p.omega)
+        rc = self.restrict(lvl, rho)
+        ec = self.vcycle(rc, lvl + 1)
+        if lvl + 1 < nlev - 1:
+            # W-cycle: further cycles of the next level on its updated residual
+            Ac = self.op(lvl + 1)
+            for _ in range(1, p.cycles):
+                ec = ec + self.vcycle(rc - Ac(ec), lvl + 1)
         x = x + self.prolong(lvl, ec)
         rho = r - A(x)
-        x2, _ = mr(A, rho, p.post, p.omega)
+        x2, _ = smooth(A, rho, p.post, p.omega)
         return x + x2
 
 

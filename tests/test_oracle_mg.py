@@ -374,3 +374,52 @@ def test_refine_one_step_is_projection_on_kept_span():
     V1 = V.copy()
     V1[0] = Vr[0]
     assert np.abs(Vr[1] - refined(V1, 1)).max() < 1e-8
+
+
+# ---------------------------------------------------------------- GMRES smoother, W-cycle
+def test_gmres_is_krylov_minimiser():
+    """GMRES(k) from 0 equals the brute-force least-squares minimiser of
+    ||b - A y|| over span{b, Ab, ..., A^(k-1) b} (raw Krylov basis, library
+    lstsq); k = dimension gives A^{-1} b (dense solve); b = 0 gives 0; the
+    smoother returns omega y and the true residual."""
+    rng = np.random.default_rng(8)
+    n = 50
+    A = np.eye(n) * 2 + 0.3 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    Af = lambda u: A @ u  # noqa: E731
+    for k in (1, 2, 4):
+        K = np.stack([np.linalg.matrix_power(A, j) @ b for j in range(k)], 1)
+        c, *_ = np.linalg.lstsq(A @ K, b, rcond=None)
+        y = so.gmres(Af, b, k)
+        assert np.linalg.norm(y - K @ c) < 1e-10 * np.linalg.norm(K @ c)
+    A6 = A[:6, :6]
+    y6 = so.gmres(lambda u: A6 @ u, b[:6], 6)
+    assert np.linalg.norm(y6 - np.linalg.solve(A6, b[:6])) < 1e-11 * np.linalg.norm(y6)
+    assert not so.gmres(Af, np.zeros(n, complex), 4).any()
+    x, r = so.gmres_smooth(Af, b, 4, 0.9)
+    assert np.abs(x - 0.9 * so.gmres(Af, b, 4)).max() < 1e-14 and np.abs(r - (b - A @ x)).max() < 1e-13
+
+
+def test_w_cycle_identity_and_effect():
+    """Three levels with no smoothing and an exact coarsest solve: the
+    intermediate correction K1 = P1 A2^{-1} P1^dag satisfies K1 A1 K1 = K1,
+    so the W-cycle (second intermediate cycle on the updated residual)
+    equals the V-cycle; with GMRES(4) post-smoothing it differs, and the
+    fine-level cycle stays a good preconditioner (one FGCR solve to 1e-10)."""
+    L, m = (4, 4, 4, 8), -0.2
+    U = W.gauge_field(L, 0.3, 0)
+    blocks, nv = [(2, 2, 2, 2), (1, 1, 1, 2)], [4, 3]
+    st = W.setup_starts(L, 4, 0)
+    cst = W.coarse_setup_starts((2, 2, 2, 4), 8, 3, 0)
+    base = dict(blocks=blocks, nv=nv, setup_rounds=1, coarse_tol=1e-13, coarse_maxiter=20000)
+    hV = so.mg_setup(U, m, so.MGParams(**base, pre=0, post=0), st, cst)
+    hW = so.mg_setup(U, m, so.MGParams(**base, pre=0, post=0, cycles=2), st, cst)
+    r = W.gaussian_spinor(L, 3)
+    zV, zW = hV.vcycle(r, 0), hW.vcycle(r, 0)
+    assert np.linalg.norm(zW - zV) < 1e-9 * np.linalg.norm(zV)
+    g1 = so.mg_setup(U, m, so.MGParams(**base, pre=0, post=4, smoother="gmres"), st, cst)
+    g2 = so.mg_setup(U, m, so.MGParams(**base, pre=0, post=4, smoother="gmres", cycles=2), st, cst)
+    assert np.linalg.norm(g2.vcycle(r, 0) - g1.vcycle(r, 0)) > 1e-6 * np.linalg.norm(zV)
+    b = W.gaussian_spinor(L, 4)
+    x, it, conv, _ = so.mg_solve(g2, b, 1e-10)
+    assert conv and np.linalg.norm(b - wi.apply_D(U, x, m)) <= 1e-10 * np.linalg.norm(b) * 1.0001
