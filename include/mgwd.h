@@ -96,7 +96,21 @@ typedef struct {
    * the next one is taken.                                                */
   int refine_group;
   int refine_iters;
+  /* Relaxation and cycle ("Formulating an algorithm", "Numerical Results").
+   * smoother MG_SMOOTH_MR: pre and post steps of MR (GMRES(1)) with
+   * under-relaxation omega per step.  MG_SMOOTH_GMRES: one GMRES(pre)
+   * cycle before and one GMRES(post) cycle after the coarse correction
+   * (pre, post <= 8; 0 = none), each from zero and scaled by omega; the
+   * paper's V(0,4) is pre = 0, post = 4.  cycles: cycles of level l+1 per
+   * correction of level l whenever l+1 is not the coarsest level (1 or 0:
+   * V-cycle; 2: the paper's W-cycle, the second cycle applied to the
+   * residual the first leaves and added; at most 4).                      */
+  int smoother;
+  int cycles;
 } mg_params_t;
+
+#define MG_SMOOTH_MR 0
+#define MG_SMOOTH_GMRES 1
 
 typedef struct {
   int iters[MG_MAX_RHS];        /* outer FGCR iterations per RHS             */

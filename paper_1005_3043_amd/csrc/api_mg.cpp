@@ -58,6 +58,11 @@ int check_params(const mg_lattice_t *lat, const mg_params_t *p) {
     return bad(MG_EINVAL, "refine_group must be 0 (off) or in [1, min(16, nv[0] - 1)]");
   if (p->refine_group > 0 && (p->refine_iters < 0 || p->refine_iters > p->gcr_restart))
     return bad(MG_EINVAL, "refine_iters must be in [0, gcr_restart]");
+  if (p->smoother != MG_SMOOTH_MR && p->smoother != MG_SMOOTH_GMRES)
+    return bad(MG_EINVAL, "smoother must be MG_SMOOTH_MR or MG_SMOOTH_GMRES");
+  if (p->smoother == MG_SMOOTH_GMRES && (p->pre > GM_KMAX || p->post > GM_KMAX))
+    return bad(MG_EINVAL, "GMRES relaxation: pre and post must be at most 8");
+  if (p->cycles < 0 || p->cycles > 4) return bad(MG_EINVAL, "cycles must be in [0, 4]");
   if (p->precond_prec != MG_F64 && p->precond_prec != MG_F32 && p->precond_prec != MG_F16)
     return bad(MG_ENOTSUP, "precond_prec must be MG_F64, MG_F32 or MG_F16");
   return MG_OK;

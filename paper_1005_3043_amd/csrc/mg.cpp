@@ -115,6 +115,20 @@ template <typename R> int ensure_work(mg_ctx *c, int nrhs) {
   MG_TRY(w.cp2.alloc(n));
   MG_TRY(w.cr2.alloc(n));
   MG_TRY(ensure_scalars(c, part_need(c, nrhs)));
+  if (c->p.smoother == MG_SMOOTH_GMRES) {
+    const int K = std::max(c->p.pre, c->p.post);
+    for (int l = 0; l < c->nlev - 1; ++l) MG_TRY(w.gv[l].alloc((size_t)(K + 1) * c->lev[l].vsize() * nrhs));
+    MG_TRY(c->gmH.alloc((size_t)MG_MAX_RHS * (GM_KMAX + 1) * GM_KMAX));
+    MG_TRY(c->gmy.alloc((size_t)MG_MAX_RHS * GM_KMAX));
+    MG_TRY(c->gmb.alloc(2 * MG_MAX_RHS));
+    MG_TRY(c->gmp.alloc((size_t)RED_BLOCKS * MG_MAX_RHS * 2 * (GM_KMAX + 1)));
+  }
+  if (c->p.cycles > 1) {
+    for (int l = 1; l < c->nlev - 1; ++l) {
+      MG_TRY(w.w2r[l].alloc(c->lev[l].vsize() * nrhs));
+      MG_TRY(w.w2x[l].alloc(c->lev[l].vsize() * nrhs));
+    }
+  }
   w.nrhs = nrhs;
   return MG_OK;
 }
@@ -312,6 +326,31 @@ int mr(mg_ctx *c, int l, vec_t<P> *x, vec_t<P> *r, vec_t<P> *q, int steps, bool 
     HIPK(mr_update<R>(x, r, q, n, nrhs, c->part, np_mr(c, l), c->p.omega, c->csc, (!accumulate && k == 0) ? 1 : 0,
                       st));
   }
+  return MG_OK;
+}
+
+// GMRES relaxation of A_l x = b: x (+)= omega y, y the GMRES(k) iterate
+// from zero (one cycle), b unchanged.
+template <typename P>
+int gmres_smooth(mg_ctx *c, int l, vec_t<P> *x, const vec_t<P> *b, int k, bool accumulate, int nrhs,
+                 hipStream_t st) {
+  using R = typename P::R;
+  Work<R> &w = work<R>(c);
+  const size_t n = c->lev[l].vsize(), vs = n * nrhs;
+  if (k == 0) {
+    if (!accumulate) HIPK(zero<R>(x, vs, st));
+    return MG_OK;
+  }
+  vec_t<P> *V = w.gv[l];
+  double *nrm2 = c->gmb + MG_MAX_RHS, *beta = c->gmb;
+  HIPK(norm2<R>(b, n, nrhs, c->gmp, nrm2, st));
+  HIPK(gm_start<R>(V, b, n, nrhs, nrm2, beta, st));
+  for (int j = 0; j < k; ++j) {
+    MG_TRY(apply_A<P>(c, l, V + (size_t)j * vs, V + (size_t)(j + 1) * vs, nrhs, DS_PLAIN, nullptr, st));
+    HIPK(gm_arnoldi_col<R>(V, vs, j, n, nrhs, c->gmH, c->gmp, st));
+  }
+  HIPK(gm_lsq(c->gmH, beta, k, nrhs, c->gmy, st));
+  HIPK(gm_combine<R>(x, V, vs, k, n, nrhs, c->gmy, c->p.omega, accumulate ? 1 : 0, st));
   return MG_OK;
 }
 
@@ -565,13 +604,32 @@ template <typename P> int vcycle(mg_ctx *c, int l, const vec_t<P> *rin, vec_t<P>
   Level &L = c->lev[l];
   const size_t n = L.vsize();
   vec_t<P> *r = w.r[l], *q = w.q[l];
-  HIPK(copy<R>(r, rin, n * nrhs, st));
-  MG_TRY(mr<P>(c, l, x, r, q, c->p.pre, false, nrhs, st));
-  MG_TRY(transfer_restrict<P>(c, l, r, w.rin[l + 1], nrhs, st));
-  MG_TRY(vcycle<P>(c, l + 1, w.rin[l + 1], w.x[l + 1], nrhs, st));
-  MG_TRY(transfer_prolong<P>(c, l, w.x[l + 1], x, nrhs, 1, st));
+  const bool gm = c->p.smoother == MG_SMOOTH_GMRES;
+  if (!gm) {
+    HIPK(copy<R>(r, rin, n * nrhs, st));
+    MG_TRY(mr<P>(c, l, x, r, q, c->p.pre, false, nrhs, st));
+  } else if (c->p.pre > 0) {
+    MG_TRY(gmres_smooth<P>(c, l, x, rin, c->p.pre, false, nrhs, st));
+    MG_TRY(apply_A<P>(c, l, x, r, nrhs, DS_RESID, rin, st));
+  } else {
+    HIPK(zero<R>(x, n * nrhs, st));
+    HIPK(copy<R>(r, rin, n * nrhs, st));
+  }
+  const int m = l + 1;
+  MG_TRY(transfer_restrict<P>(c, l, r, w.rin[m], nrhs, st));
+  MG_TRY(vcycle<P>(c, m, w.rin[m], w.x[m], nrhs, st));
+  if (m < c->nlev - 1) {
+    // W-cycle: further cycles of level m on the residual the previous left
+    for (int cyc = 1; cyc < c->p.cycles; ++cyc) {
+      MG_TRY(apply_A<P>(c, m, w.x[m], w.w2r[m], nrhs, DS_RESID, w.rin[m], st));
+      MG_TRY(vcycle<P>(c, m, w.w2r[m], w.w2x[m], nrhs, st));
+      HIPK(add_inplace<R>(w.x[m], w.w2x[m], c->lev[m].vsize(), nrhs, st));
+    }
+  }
+  MG_TRY(transfer_prolong<P>(c, l, w.x[m], x, nrhs, 1, st));
   MG_TRY(apply_A<P>(c, l, x, r, nrhs, DS_RESID, rin, st));
-  MG_TRY(mr<P>(c, l, x, r, q, c->p.post, true, nrhs, st));
+  if (gm) MG_TRY(gmres_smooth<P>(c, l, x, r, c->p.post, true, nrhs, st));
+  else MG_TRY(mr<P>(c, l, x, r, q, c->p.post, true, nrhs, st));
   return MG_OK;
 }
 
@@ -722,6 +780,9 @@ template <typename R> void release_work(Work<R> &w) {
     w.r[l].release();
     w.q[l].release();
     w.rin[l].release();
+    w.gv[l].release();
+    w.w2r[l].release();
+    w.w2x[l].release();
   }
   w.ce.release();
   w.cr.release();

@@ -44,6 +44,24 @@ template <typename R> hipError_t scale_rsqrt(c_t<R> *v, size_t n, int nrhs, cons
 // out = b - out
 template <typename R> hipError_t resid_from(c_t<R> *out, const c_t<R> *b, size_t n, int nrhs, hipStream_t st);
 
+// ---- gmres.hip (GMRES(k) relaxation, k <= GM_KMAX)
+constexpr int GM_KMAX = 8;
+// v0 = b / ||b|| from nrm2 = ||b||^2; beta = ||b||
+template <typename R>
+hipError_t gm_start(c_t<R> *v0, const c_t<R> *b, size_t n, int nrhs, const double *nrm2, double *beta,
+                    hipStream_t st);
+// with V[j+1] = A v_j on entry: column j of H and v_{j+1} (basis stride vs)
+template <typename R>
+hipError_t gm_arnoldi_col(c_t<R> *V, size_t vs, int j, size_t n, int nrhs, double2 *H, double *part,
+                          hipStream_t st);
+hipError_t gm_lsq(const double2 *H, const double *beta, int k, int nrhs, double2 *y, hipStream_t st);
+// x = (accumulate ? x : 0) + omega sum_{j<k} y_j v_j
+template <typename R>
+hipError_t gm_combine(c_t<R> *x, const c_t<R> *V, size_t vs, int k, size_t n, int nrhs, const double2 *y,
+                      double omega, int accumulate, hipStream_t st);
+// v += x
+template <typename R> hipError_t add_inplace(c_t<R> *v, const c_t<R> *x, size_t n, int nrhs, hipStream_t st);
+
 // ---- pack.hip (site-major coarse vectors)
 template <typename T>
 hipError_t pack_aos(const Geom &g, const double2 *canon, c_t<T> *internal, int ncomp, int nvec, hipStream_t st);
@@ -114,6 +132,8 @@ template <typename R> struct Work {
   DevBuf<c_t<R>> x[MG_MAX_LEVELS], r[MG_MAX_LEVELS], q[MG_MAX_LEVELS], rin[MG_MAX_LEVELS];
   // coarsest CGNR
   DevBuf<c_t<R>> ce, cr, cz, cp, cw, cp2, cr2;  // cp2, cr2: second p, r of the fused CGNR
+  // GMRES relaxation basis per level; W-cycle residual and correction per level
+  DevBuf<c_t<R>> gv[MG_MAX_LEVELS], w2r[MG_MAX_LEVELS], w2x[MG_MAX_LEVELS];
   int nrhs = 0;
 };
 
@@ -214,6 +234,10 @@ struct mg_ctx {
   mg::Work<float> w32;
   // outer solver (FP64, fine level)
   mg::DevBuf<double2> gx, gr, gb, gZ, gW, gtmp;
+  // GMRES relaxation scalars: Hessenberg matrices, least-squares
+  // coefficients, ||b|| and column partials
+  mg::DevBuf<double2> gmH, gmy;
+  mg::DevBuf<double> gmb, gmp;
   mg::DevBuf<int> skip;
   int gcr_rhs = 0;
   // statistics

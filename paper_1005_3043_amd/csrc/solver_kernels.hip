@@ -168,6 +168,12 @@ __global__ __launch_bounds__(256) void k_sub(c_t<R> *v, const c_t<R> *x, size_t 
   GSTRIDE(i, n) v[i] = csub(v[i], x[i]);
 }
 template <typename R>
+__global__ __launch_bounds__(256) void k_add(c_t<R> *v, const c_t<R> *x, size_t n) {
+  const size_t off = (size_t)blockIdx.y * n;
+  v += off; x += off;
+  GSTRIDE(i, n) v[i] = cadd(v[i], x[i]);
+}
+template <typename R>
 __global__ __launch_bounds__(256) void k_scale_rsqrt(c_t<R> *v, size_t n, const double *nrm2) {
   v += (size_t)blockIdx.y * n;
   const double nn = nrm2[blockIdx.y];
@@ -286,6 +292,10 @@ template <typename R> hipError_t sub_inplace(c_t<R> *v, const c_t<R> *x, size_t 
   hipLaunchKernelGGL(k_sub<R>, dim3(sgrid(n), nrhs), dim3(256), 0, st, v, x, n);
   return hipGetLastError();
 }
+template <typename R> hipError_t add_inplace(c_t<R> *v, const c_t<R> *x, size_t n, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_add<R>, dim3(sgrid(n), nrhs), dim3(256), 0, st, v, x, n);
+  return hipGetLastError();
+}
 template <typename R> hipError_t scale_rsqrt(c_t<R> *v, size_t n, int nrhs, const double *nrm2, hipStream_t st) {
   hipLaunchKernelGGL(k_scale_rsqrt<R>, dim3(sgrid(n), nrhs), dim3(256), 0, st, v, n, nrm2);
   return hipGetLastError();
@@ -357,6 +367,7 @@ hipError_t gcr_update(double2 *x, const double2 *z, double2 *r, const double2 *w
   template int norm2_partials<R>(const c_t<R> *, size_t, int, double *, hipStream_t);                               \
   template hipError_t dot<R>(const c_t<R> *, const c_t<R> *, size_t, int, double *, double2 *, hipStream_t);        \
   template hipError_t sub_inplace<R>(c_t<R> *, const c_t<R> *, size_t, int, hipStream_t);                           \
+  template hipError_t add_inplace<R>(c_t<R> *, const c_t<R> *, size_t, int, hipStream_t);                           \
   template hipError_t scale_rsqrt<R>(c_t<R> *, size_t, int, const double *, hipStream_t);                           \
   template hipError_t resid_from<R>(c_t<R> *, const c_t<R> *, size_t, int, hipStream_t);                           \
   template int cg2_update<R>(c_t<R> *, const c_t<R> *, c_t<R> *, const c_t<R> *, size_t, int, const double *,        \

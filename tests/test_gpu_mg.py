@@ -296,6 +296,66 @@ def test_three_level(cuda):
     assert abs(info["iters"][0] - it_ref) <= 1
 
 
+_CYCLE_CASES = {
+    "3-level 8^4": ((8, 8, 8, 8), [(2, 2, 2, 2), (2, 2, 2, 2)], [6, 4], 0.3, -0.3, 3),
+    "2-level 8^4": CASES["8^4 b4^4 nv8"],
+}
+_CYCLE_ORACLE = {}
+
+
+@pytest.mark.parametrize("case,smoother,pre,post,cycles", [
+    ("3-level 8^4", "gmres", 0, 4, 2),   # the paper's V(0,4) GMRES(4) W-cycle
+    ("3-level 8^4", "gmres", 0, 4, 1),
+    ("3-level 8^4", "mr", 4, 4, 2),
+    ("2-level 8^4", "gmres", 0, 4, 1),
+    ("2-level 8^4", "gmres", 2, 3, 1),   # GMRES pre-smoothing too
+])
+def test_cycle_variants(cuda, case, smoother, pre, post, cycles):
+    """GMRES(k) relaxation (one cycle from zero, scaled by omega) and the
+    W-cycle (a second intermediate cycle on the residual the first leaves):
+    one preconditioner application against the oracle's element by element
+    for 1 and 3 right-hand sides, equal coarsest CGNR iteration counts, and
+    the solve to 1e-10 within one outer iteration of the oracle's."""
+    import dataclasses
+
+    import paper_1005_3043_amd as mgwd
+    L, blocks, nv, eps, m, seed = _CYCLE_CASES[case]
+    U = W.gauge_field(L, eps, seed)
+    starts = W.setup_starts(L, nv[0], seed)
+    inits = [torch.from_numpy(starts).cuda()]
+    cst = None
+    if len(blocks) > 1:
+        Lc = tuple(L[mu] // blocks[0][mu] for mu in range(4))
+        cst = W.coarse_setup_starts(Lc, 2 * nv[0], nv[1], seed)
+        inits.append(torch.from_numpy(cst).cuda())
+    if case not in _CYCLE_ORACLE:
+        _CYCLE_ORACLE[case] = so.mg_setup(U, m, so.MGParams(blocks=blocks, nv=nv), starts, cst)
+    h = _CYCLE_ORACLE[case]
+    h.p = dataclasses.replace(h.p, smoother=smoother, pre=pre, post=post, cycles=cycles)
+    print(f"{case}: {smoother} pre {pre} post {post}, {cycles} cycle(s)", flush=True)
+    ctx = mgwd.MG(torch.from_numpy(U).cuda(), m, blocks, nv, inits, max_rhs=4, smoother=smoother, pre=pre,
+                  post=post, cycles=cycles)
+    errs = []
+    for nrhs in (1, 3):
+        r = W.gaussian_spinor(L, 13, batch=(nrhs,))
+        z, it = ctx.vcycle(torch.from_numpy(r).cuda())
+        h.stats["cgnr_iters"] = []
+        zr = np.stack([h.vcycle(r[i], 0) for i in range(nrhs)])
+        errs.append((_rel(z.cpu().numpy(), zr), it, sum(h.stats["cgnr_iters"])))
+    b = W.gaussian_spinor(L, 1)
+    x, info, rc = ctx.solve(torch.from_numpy(b).cuda(), 1e-10)
+    ctx.close()
+    res = np.linalg.norm(b - wi.apply_D(U, x.cpu().numpy(), m)) / np.linalg.norm(b)
+    _, it_ref, conv, _ = so.mg_solve(h, b, 1e-10)
+    h.p = dataclasses.replace(h.p, smoother="mr", pre=4, post=4, cycles=1)
+    print(f"{case}: cycle rel err / CGNR iterations (oracle) {errs}; solve {info['iters'][0]} iterations "
+          f"(oracle {it_ref}), true rel resid {res:.2e}")
+    for e, it, it_o in errs:
+        assert e < 1e-10 and it == it_o
+    assert rc == 0 and res <= 1e-10 * 1.001
+    assert abs(info["iters"][0] - it_ref) <= 1
+
+
 def test_set_mass(cuda):
     """A setup reused at a heavier mass: the GPU's shifted Galerkin operator
     equals the oracle's Galerkin construction at the new mass with the same
