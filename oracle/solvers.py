@@ -264,6 +264,8 @@ def mg_setup(U, m, params: MGParams, starts, coarse_starts=None):
         geom2 = tr.BlockGeometry(levels[-1].geom.Lc, params.blocks[lv])
         V2 = relax_nullspace(h.op(lv), coarse_starts, params.setup_rounds,
                              params.setup_mr_steps, params.omega)
+        if params.refine_group > 0 and params.refine_iters > 0:
+            V2 = refine_nullspace(U, m, params, V2, params.refine_group, params.refine_iters, levels)
         Pb2, Rc2 = tr.block_qr(np.moveaxis(geom2.blockify(V2), 0, -1))
         X2, Y2 = co.galerkin_coarse(levels[-1].X, levels[-1].Y, Pb2, geom2)
         levels.append(Level(geom2, Pb2, Rc2, X2, Y2, V2))
@@ -271,31 +273,43 @@ def mg_setup(U, m, params: MGParams, starts, coarse_starts=None):
     return h
 
 
-def refine_nullspace(U, m, params: MGParams, V, group: int, iters: int):
-    """Setup stage two ("Numerical Results"): the prototypes are refined in
-    groups of `group`: a group is taken out of V, a truncated two-level MG is
-    built from the remaining prototypes (block QR and Galerkin operator as in
-    stage one), the truncated MG method is iterated `iters` times on D v = 0
-    from every prototype of the group, and the normalised result goes back
-    into V.  Reading: "the MG method" is the paper's MG-preconditioned
-    flexible GCR, so the iterations are GCR steps (no restart within them)
-    on the homogeneous system started at the prototype."""
+def refine_nullspace(U, m, params: MGParams, V, group: int, iters: int, levels=()):
+    """Setup stage two ("Numerical Results"): the prototypes of level
+    l = len(levels) (the levels below already built) are refined in groups of
+    `group`: a group is taken out of V, a truncated two-level method from
+    level l is built from the remaining prototypes (block QR and Galerkin
+    operator as in stage one; the cycle of level l over a CGNR solve on the
+    truncated next level), the truncated MG method is iterated `iters` times
+    on A_l v = 0 from every prototype of the group, and the normalised result
+    goes back into V before the next group is taken.  Reading: "the MG method"
+    is the solver of the adaptive process, the MG-preconditioned flexible GCR
+    applied to the homogeneous system ("Adaptive Multigrid"), so the
+    iterations are GCR steps (no restart within them) started at the
+    prototype."""
     V = np.array(V, dtype=np.complex128, copy=True)
     nv = V.shape[0]
     if group <= 0 or iters <= 0 or group >= nv:
         return V
-    L = tuple(reversed(U.shape[1:5]))
-    geom = tr.BlockGeometry(L, params.blocks[0])
+    lvl = len(levels)
+    if lvl == 0:
+        geom = tr.BlockGeometry(tuple(reversed(U.shape[1:5])), params.blocks[0])
+    else:
+        geom = tr.BlockGeometry(levels[-1].geom.Lc, params.blocks[lvl])
     for g0 in range(0, nv, group):
         grp = list(range(g0, min(g0 + group, nv)))
         keep = [k for k in range(nv) if k not in grp]
-        Pb, Rc = tr.block_qr(np.moveaxis(geom.blockify(tr.fine_to_generic(V[keep])), 0, -1))
-        X, Y = co.galerkin_fine(U, m, Pb, geom, params.antiperiodic_t)
-        pt = MGParams(**{**params.__dict__, "blocks": [params.blocks[0]], "nv": [len(keep)]})
-        h = Hierarchy(U, m, pt, [Level(geom, Pb, Rc, X, Y, V[keep])])
-        A = h.op(0)
+        B = tr.fine_to_generic(V[keep]) if lvl == 0 else V[keep]
+        Pb, Rc = tr.block_qr(np.moveaxis(geom.blockify(B), 0, -1))
+        if lvl == 0:
+            X, Y = co.galerkin_fine(U, m, Pb, geom, params.antiperiodic_t)
+        else:
+            X, Y = co.galerkin_coarse(levels[-1].X, levels[-1].Y, Pb, geom)
+        pt = MGParams(**{**params.__dict__, "blocks": list(params.blocks[:lvl + 1]),
+                         "nv": list(params.nv[:lvl]) + [len(keep)]})
+        h = Hierarchy(U, m, pt, list(levels) + [Level(geom, Pb, Rc, X, Y, V[keep])])
+        A = h.op(lvl)
         for k in grp:
-            x, _, _, _ = gcr_homogeneous(A, lambda r: h.vcycle(r, 0), V[k], iters)
+            x, _, _, _ = gcr_homogeneous(A, lambda r: h.vcycle(r, lvl), V[k], iters)
             V[k] = x / np.sqrt(_nrm2(x))
     return V
 

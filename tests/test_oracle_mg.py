@@ -423,3 +423,37 @@ def test_w_cycle_identity_and_effect():
     b = W.gaussian_spinor(L, 4)
     x, it, conv, _ = so.mg_solve(g2, b, 1e-10)
     assert conv and np.linalg.norm(b - wi.apply_D(U, x, m)) <= 1e-10 * np.linalg.norm(b) * 1.0001
+
+
+def test_refine_level1_one_step_is_projection_on_kept_span():
+    """The same dense construction one level down (three-level hierarchy):
+    the level-1 prototypes are refined with the truncated method from level
+    1 (no smoothing, exact CGNR on the truncated level 2), against
+    v + a K(-A_1 v) with A_1 the dense level-1 operator and K built from the
+    raw kept level-1 prototypes restricted to each (aggregate, chirality)."""
+    L, m = (4, 4, 4, 8), -0.2
+    U = W.gauge_field(L, 0.3, 2)
+    blocks, nv = [(2, 2, 2, 2), (1, 1, 1, 2)], [4, 3]
+    Lc = (2, 2, 2, 4)
+    base = dict(blocks=blocks, nv=nv, setup_rounds=2, coarse_tol=1e-13, coarse_maxiter=20000)
+    h = so.mg_setup(U, m, so.MGParams(**base), W.setup_starts(L, 4, 2), W.coarse_setup_starts(Lc, 8, 3, 2))
+    V1 = h.levels[1].nullvecs
+    p0 = so.MGParams(**base, pre=0, post=0)
+    Vr = so.refine_nullspace(U, m, p0, V1, 1, 1, h.levels[:1])
+    A1 = co.coarse_dense(h.levels[0].X, h.levels[0].Y)
+    agg = np.array([x + 2 * (y + 2 * (z + 2 * (t // 2)))
+                    for t in range(Lc[3]) for z in range(Lc[2]) for y in range(Lc[1]) for x in range(Lc[0])])
+    comp_chi = np.arange(8) // 4
+    cols = []
+    for j in (1, 2):
+        f = V1[j].reshape(-1, 8)
+        for a in range(16):
+            for hh in range(2):
+                mask = (agg[:, None] == a) & (comp_chi[None, :] == hh)
+                cols.append(np.where(mask, f, 0).ravel())
+    Pk = np.stack(cols, 1)
+    v = V1[0].ravel()
+    z = -Pk @ np.linalg.solve(Pk.conj().T @ A1 @ Pk, Pk.conj().T @ (A1 @ v))
+    Az, Av = A1 @ z, A1 @ v
+    x = v - np.vdot(Az, Av) / np.vdot(Az, Az) * z
+    assert np.abs(Vr[0].ravel() - x / np.linalg.norm(x)).max() < 1e-8
