@@ -85,13 +85,15 @@ typedef struct {
    *   init_vectors[0]: [nv[0]][Lt][Lz][Ly][Lx][4][3]
    *   init_vectors[1]: [nv[1]][Lct][Lcz][Lcy][Lcx][2*nv[0]] (3 levels)    */
   const void *init_vectors[MG_MAX_LEVELS - 1];
-  /* Setup stage two ("Numerical Results"), level 0 only: the relaxed
-   * prototypes are refined in groups of refine_group (0 = off; at most 16
-   * and below nv[0]).  Each group is taken out, a truncated two-level method
-   * is built from the other prototypes (block orthonormalisation and
-   * Galerkin operator as in stage one, FP64), refine_iters iterations
+  /* Setup stage two ("Numerical Results"), on every level l below the
+   * coarsest, after its relaxation: the prototypes are refined in groups of
+   * refine_group (0 = off; at most 16 and below nv[0]; a level with at most
+   * refine_group prototypes is left as relaxed).  Each group is taken out, a
+   * truncated two-level method from level l is built from the other
+   * prototypes (block orthonormalisation and Galerkin operator as in stage
+   * one, FP64), refine_iters iterations
    * (at most gcr_restart) of the MG-preconditioned flexible GCR are run on
-   * D v = 0 from each prototype of the group (GCR in FP64, its V-cycles in
+   * A_l v = 0 from each prototype of the group (GCR in FP64, its cycles in
    * precond_prec), and the normalised iterates replace the group before
    * the next one is taken.                                                */
   int refine_group;

@@ -796,43 +796,57 @@ template <typename R> void release_work(Work<R> &w) {
 
 // Drops the low-precision copies of the level-0 prolongator and the level-1
 // operator; the next ensure_prec rebuilds them from the FP64 data.
-void drop_op_copies(mg_ctx *c) {
-  c->lev[0].P32.release();
-  c->lev[0].P16.release();
-  c->lev[1].L32.release();
-  c->lev[1].L16.release();
+void drop_op_copies(mg_ctx *c, int l) {
+  c->lev[l].P32.release();
+  c->lev[l].P16.release();
+  c->lev[l + 1].L32.release();
+  c->lev[l + 1].L16.release();
 }
 
-// Setup stage two ("Numerical Results") on the level-0 prototypes in NV:
+// z = K_l(r): one cycle from level l in precision prec (FP64 in and out).
+int cycle_from(mg_ctx *c, int l, mg_prec_t prec, const double2 *r, double2 *z, int nrhs, hipStream_t st) {
+  if (prec == MG_F64) return vcycle<PF64>(c, l, r, z, nrhs, st);
+  Work<float> &w = c->w32;
+  const size_t n = c->lev[l].vsize() * nrhs;
+  float2 *rin = w.rin[l], *x = w.x[l];
+  HIPK((convert<float, double>(rin, r, n, st)));
+  if (prec == MG_F16) MG_TRY(vcycle<PF16>(c, l, rin, x, nrhs, st));
+  else MG_TRY(vcycle<PF32>(c, l, rin, x, nrhs, st));
+  HIPK((convert<double, float>(z, x, n, st)));
+  return MG_OK;
+}
+
+// Setup stage two ("Numerical Results") on the level-l prototypes in NV:
 // groups of refine_group vectors are taken out in turn; the remaining
-// prototypes define a truncated two-level method (block orthonormalisation,
-// Galerkin operator, the usual V-cycle with the coarsest-level CGNR); from
-// each prototype v of the group, refine_iters steps of the flexible GCR
-// preconditioned by that V-cycle are run on D v = 0 (residual -D v, no
-// restart), and the normalised iterates replace the group.  The V-cycles run
-// in the context's preconditioner precision (copies of the truncated P and
-// D_c made per group), the GCR steps in FP64.  Level sizes are
-// shrunk while a group is out and restored afterwards; work buffers, captured
-// graphs and tuned coarse variants made at the shrunk sizes are dropped.
-int refine(mg_ctx *c, hipStream_t st_in) {
+// prototypes define a truncated two-level method from level l (block
+// orthonormalisation, Galerkin operator, the cycle of level l over the
+// CGNR solve on the truncated level l+1); from each prototype v of the
+// group, refine_iters steps of the flexible GCR preconditioned by that cycle
+// are run on A_l v = 0 (residual -A_l v, no restart), and the normalised
+// iterates replace the group.  The cycles run in the context's
+// preconditioner precision (copies of the truncated P and operator made per
+// group), the GCR steps in FP64.  Level sizes are shrunk while a group is
+// out and restored afterwards; work buffers, captured graphs and tuned
+// coarse variants made at the shrunk sizes are dropped.
+int refine(mg_ctx *c, int l, hipStream_t st_in) {
   const int G0 = c->p.refine_group, iters = c->p.refine_iters;
-  Level &L0 = c->lev[0], &L1 = c->lev[1];
-  const int nv = L0.nv;
+  Level &Lv = c->lev[l], &Lc = c->lev[l + 1];
+  const int nv = Lv.nv;
   if (G0 <= 0 || iters <= 0 || G0 >= nv) return MG_OK;
   // runs on the context's own stream (the coarsest-level CGNR captures
   // graphs, which the default stream does not allow), after st_in's work
   hipStream_t st = c->sti;
   HIPK(hipEventRecord(c->ev_in, st_in));
   HIPK(hipStreamWaitEvent(st, c->ev_in, 0));
-  const int nlev = c->nlev, n1 = L1.n, nv1 = L1.nv;
+  const int nlev = c->nlev, nc = Lc.n, nvc = Lc.nv;
   const mg_prec_t rp = c->prec;
-  const size_t n = L0.vsize();
+  const size_t n = Lv.vsize();
   DevBuf<double2> X, R, Z, W;
   MG_TRY(X.alloc(n * G0));
   MG_TRY(R.alloc(n * G0));
   MG_TRY(Z.alloc(n * G0 * iters));
   MG_TRY(W.alloc(n * G0 * iters));
-  MG_TRY(L1.L64.alloc((size_t)L1.g.V * 9 * n1 * n1));
+  MG_TRY(Lc.L64.alloc((size_t)Lc.g.V * 9 * nc * nc));
   double *rr = c->dsc;
   double2 *sc = c->csc;
   int *flag = c->done;
@@ -841,21 +855,22 @@ int refine(mg_ctx *c, hipStream_t st_in) {
     const int G = std::min(G0, nv - g0), nk = nv - G;
     const size_t nn = n * G;
     // the kept prototypes, in order, as the truncated method's P
-    if (g0 > 0) HIPK(hipMemcpyAsync(L0.P64, L0.NV, n * g0 * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    if (g0 > 0) HIPK(hipMemcpyAsync(Lv.P64, Lv.NV, n * g0 * sizeof(double2), hipMemcpyDeviceToDevice, st));
     if (g0 + G < nv)
-      HIPK(hipMemcpyAsync(L0.P64 + n * g0, L0.NV + n * (g0 + G), n * (nv - g0 - G) * sizeof(double2),
+      HIPK(hipMemcpyAsync(Lv.P64 + n * g0, Lv.NV + n * (g0 + G), n * (nv - g0 - G) * sizeof(double2),
                           hipMemcpyDeviceToDevice, st));
-    c->nlev = 2;
-    L0.nv = nk;
-    L1.n = 2 * nk;
-    L1.nv = 0;
+    c->nlev = l + 2;
+    Lv.nv = nk;
+    Lc.n = 2 * nk;
+    Lc.nv = 0;
     release_work(c->w64);
     release_work(c->w32);
-    drop_op_copies(c);
+    drop_op_copies(c, l);
     clear_graphs(c);
     std::memset(c->cvar, 0xff, sizeof(c->cvar));
     HIPK(hipMemsetAsync(flag, 0, sizeof(int), st));
-    HIPK(ortho_fine(L0.g, nk, L0.P64, flag, st));
+    if (l == 0) HIPK(ortho_fine(Lv.g, nk, Lv.P64, flag, st));
+    else HIPK(ortho_coarse(Lv.g, Lv.n, nk, Lv.P64, flag, st));
     HIPK(hipMemcpyAsync(c->h_done, flag, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPK(hipStreamSynchronize(st));
     if (c->h_done[0]) {
@@ -863,22 +878,23 @@ int refine(mg_ctx *c, hipStream_t st_in) {
       rc = MG_ERANK;
       break;
     }
-    HIPK(galerkin_fine(L0.g, L1.g, c->mass, L0.U64, nk, L0.P64, L1.L64, st));
+    if (l == 0) HIPK(galerkin_fine(Lv.g, Lc.g, c->mass, Lv.U64, nk, Lv.P64, Lc.L64, st));
+    else HIPK(galerkin_coarse(Lv.g, Lc.g, Lv.n, Lv.L64, nk, Lv.P64, Lc.L64, st));
     if ((rc = ensure_work<double>(c, G)) != MG_OK) break;
     if (rp != MG_F64) {
       if ((rc = ensure_prec(c, rp, st)) != MG_OK) break;
       if ((rc = ensure_work<float>(c, G)) != MG_OK) break;
     }
-    // x = v, r = -D v
+    // x = v, r = -A v
     double2 *x = X, *r = R;
-    HIPK(hipMemcpyAsync(x, L0.NV + n * g0, nn * sizeof(double2), hipMemcpyDeviceToDevice, st));
-    if ((rc = apply_A<PF64>(c, 0, x, W, G, DS_PLAIN, nullptr, st)) != MG_OK) break;
+    HIPK(hipMemcpyAsync(x, Lv.NV + n * g0, nn * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    if ((rc = apply_A<PF64>(c, l, x, W, G, DS_PLAIN, nullptr, st)) != MG_OK) break;
     HIPK(zero<double>(r, nn, st));
     HIPK(sub_inplace<double>(r, W, n, G, st));
     for (int j = 0; j < iters && rc == MG_OK; ++j) {
       double2 *Zj = Z + (size_t)j * nn, *Wj = W + (size_t)j * nn;
-      if ((rc = precondition_at(c, rp, r, Zj, G, st)) != MG_OK) break;
-      if ((rc = apply_A<PF64>(c, 0, Zj, Wj, G, DS_PLAIN, nullptr, st)) != MG_OK) break;
+      if ((rc = cycle_from(c, l, rp, r, Zj, G, st)) != MG_OK) break;
+      if ((rc = apply_A<PF64>(c, l, Zj, Wj, G, DS_PLAIN, nullptr, st)) != MG_OK) break;
       for (int i = 0; i < j; ++i) {
         HIPK(dot<double>(W + (size_t)i * nn, Wj, n, G, c->part, sc, st));
         HIPK(gcr_sub2(Wj, W + (size_t)i * nn, Zj, Z + (size_t)i * nn, n, G, sc, nullptr, st));
@@ -891,16 +907,16 @@ int refine(mg_ctx *c, hipStream_t st_in) {
     if (rc != MG_OK) break;
     HIPK(norm2<double>(x, n, G, c->part, rr, st));
     HIPK(scale_rsqrt<double>(x, n, G, rr, st));
-    HIPK(hipMemcpyAsync(L0.NV + n * g0, x, nn * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    HIPK(hipMemcpyAsync(Lv.NV + n * g0, x, nn * sizeof(double2), hipMemcpyDeviceToDevice, st));
     HIPK(hipStreamSynchronize(st));
   }
   c->nlev = nlev;
-  L0.nv = nv;
-  L1.n = n1;
-  L1.nv = nv1;
+  Lv.nv = nv;
+  Lc.n = nc;
+  Lc.nv = nvc;
   release_work(c->w64);
   release_work(c->w32);
-  drop_op_copies(c);
+  drop_op_copies(c, l);
   clear_graphs(c);
   std::memset(c->cvar, 0xff, sizeof(c->cvar));
   return rc;
@@ -958,7 +974,7 @@ int setup(mg_ctx *c, const void *U, hipStream_t st) {
     if (l == 0) HIPK(pack_field<double>(Lv.g, (const double2 *)p.init_vectors[0], Lv.NV, 12, Lv.nv, st));
     else HIPK(pack_aos<double>(Lv.g, (const double2 *)p.init_vectors[l], Lv.NV, Lv.n, Lv.nv, st));
     MG_TRY(relax(c, l, Lv.NV, Lv.nv, st));
-    if (l == 0) MG_TRY(refine(c, st));
+    MG_TRY(refine(c, l, st));
     HIPK(hipMemcpyAsync(Lv.P64, Lv.NV, nvs * sizeof(double2), hipMemcpyDeviceToDevice, st));
     HIPK(hipMemsetAsync(flag, 0, sizeof(int), st));
     if (l == 0) HIPK(ortho_fine(Lv.g, Lv.nv, Lv.P64, flag, st));

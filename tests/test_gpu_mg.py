@@ -443,6 +443,45 @@ def test_setup_refinement(cuda, name, group):
     assert abs(info["iters"][0] - it_ref) <= 1
 
 
+def test_setup_refinement_three_level(cuda):
+    """Refinement on both levels of a three-level hierarchy (the level-1
+    prototypes with the truncated method from level 1), CGNR to 1e-12:
+    refined level-0 and level-1 null vectors and the level-2 operator against
+    the oracle's element by element (to 1e-9: a CGNR stopped at 1e-12 on the
+    ill-conditioned truncated level-2 operator leaves solution differences
+    of 1e-12 times its condition number); the solve at the default tolerance
+    within one outer iteration of the oracle's."""
+    import paper_1005_3043_amd as mgwd
+    L, blocks, nv, eps, m, seed = _CYCLE_CASES["3-level 8^4"]
+    U = W.gauge_field(L, eps, seed)
+    starts = W.setup_starts(L, nv[0], seed)
+    Lc = tuple(L[mu] // blocks[0][mu] for mu in range(4))
+    cst = W.coarse_setup_starts(Lc, 2 * nv[0], nv[1], seed)
+    inits = [torch.from_numpy(starts).cuda(), torch.from_numpy(cst).cuda()]
+    Ud = torch.from_numpy(U).cuda()
+    print("3-level 8^4: refinement group 2 on both levels", flush=True)
+    tight = dict(coarse_tol=1e-12, coarse_maxiter=5000)
+    ctx = mgwd.MG(Ud, m, blocks, nv, inits, refine_group=2, refine_iters=3, **tight)
+    h = so.mg_setup(U, m, so.MGParams(blocks=blocks, nv=nv, refine_group=2, refine_iters=3, **tight), starts, cst)
+    e0 = _rel(ctx.export_nullvecs(0), h.levels[0].nullvecs)
+    e1 = _rel(ctx.export_nullvecs(1), h.levels[1].nullvecs)
+    X2, Y2 = ctx.export_coarse_op(2)
+    e2 = max(_rel(X2, h.levels[1].X), _rel(Y2, h.levels[1].Y))
+    ctx.close()
+    ctx = mgwd.MG(Ud, m, blocks, nv, inits, refine_group=2, refine_iters=3)
+    hd = so.mg_setup(U, m, so.MGParams(blocks=blocks, nv=nv, refine_group=2, refine_iters=3), starts, cst)
+    b = W.gaussian_spinor(L, 1)
+    x, info, rc = ctx.solve(torch.from_numpy(b).cuda(), 1e-10)
+    ctx.close()
+    res = np.linalg.norm(b - wi.apply_D(U, x.cpu().numpy(), m)) / np.linalg.norm(b)
+    _, it_ref, _, _ = so.mg_solve(hd, b, 1e-10)
+    print(f"3-level 8^4 refined: level-0 / level-1 null vectors rel err {e0:.1e} / {e1:.1e}, level-2 operator "
+          f"{e2:.1e}; solve {info['iters'][0]} iterations (oracle {it_ref}), true rel resid {res:.2e}")
+    assert e0 < 1e-9 and e1 < 1e-9 and e2 < 1e-9
+    assert rc == 0 and res <= 1e-10 * 1.001
+    assert abs(info["iters"][0] - it_ref) <= 1
+
+
 @pytest.mark.parametrize("prec", ["f32", "f16"])
 def test_setup_refinement_lowprec(cuda, prec):
     """Refinement with the truncated V-cycles in FP32 or with FP16-stored
