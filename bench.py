@@ -199,6 +199,7 @@ def multi_rhs_report(mgwd, torch, W):
     ctx.solve(b[:12], 1e-10)  # warm-up: graphs, autotuning
     x, info, rc = ctx.solve(b, 1e-10)
     var, us = ctx.coarse_variant(1, "f16", 12)
+    tr_r, tr_p, tr_us = ctx.transfer_variant("f16", 12)
     ctx.set_precond_prec("f64")
     t64, it64 = 0.0, []
     for i in range(12):
@@ -223,7 +224,10 @@ def multi_rhs_report(mgwd, torch, W):
             "setup_s": round(setup_s, 3), "batched_f16_solve_s": round(info["t_solve_s"], 3),
             "batched_iters": info["iters"][:12], "plain_f64_12_solves_s": round(t64, 3), "plain_f64_iters": it64,
             "speedup": round(t64 / info["t_solve_s"], 2), "coarse_variant_12rhs": var,
-            "coarse_12rhs_us": round(us, 1), "converged": rc == 0}
+            "coarse_12rhs_us": round(us, 1),
+            "transfer_12rhs": {"restrict_variant": tr_r, "prolong_variant": tr_p,
+                               "us": {f"{d}_{'mfma' if v else 'vector'}": round(t, 1) for (d, v), t in tr_us.items()}},
+            "converged": rc == 0}
 
 
 def three_level_report(mgwd, torch, W):

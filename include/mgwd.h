@@ -218,6 +218,33 @@ int mg_apply_op(mg_ctx_t *ctx, int level, mg_prec_t prec, const void *in,
 int mg_vcycle(mg_ctx_t *ctx, mg_prec_t prec, const void *in, void *out,
               int nrhs, int *cgnr_iters, hipStream_t stream);
 
+/* Restriction (direction 0: out = P^dag in, level -> level+1) or
+ * prolongation (direction 1: out = P in, level+1 -> level, overwritten)
+ * with the stored P of precision prec (Eq. 4, Eq. 8): MG_F64, MG_F32, or
+ * MG_F16 (binary16-stored P, FP32 arithmetic), the copies the
+ * preconditioner uses.  in/out: canonical DEVICE complex128 arrays of the
+ * two levels (layouts as mg_restrict), not aliased.  Builds the
+ * low-precision copies on first use.  Async.  Errors: MG_EINVAL, MG_ESHAPE
+ * (level), MG_ENOTSUP (prec).                                              */
+int mg_transfer(mg_ctx_t *ctx, int level, mg_prec_t prec, int direction,
+                const void *in, void *out, int nrhs, hipStream_t stream);
+
+/* Fine-level transfer kernel choice for FP32 arithmetic (MG_F32, MG_F16)
+ * and 2..16 right-hand sides: vector kernels serving four right-hand sides
+ * per workgroup (variant 0) or one complex GEMM per aggregate for all of
+ * them on the FP32 matrix cores (variant 1; needs an aggregate volume
+ * divisible by 4).  By default each direction is timed once per (lattice,
+ * aggregate, Nv, precision, nrhs) on first use and the faster kept for the
+ * process; mg_set_transfer_variant forces one (-1 restores tuning; variant
+ * 1 falls back to 0 where it cannot run).  mg_transfer_variant reports the
+ * choice for restriction and prolongation (-1: not tuned yet) and, when us
+ * is not NULL, the tuning times in microseconds per application in us[4]
+ * (restriction variant 0, 1, prolongation variant 0, 1; 0 if not timed).   */
+int mg_set_transfer_variant(mg_ctx_t *ctx, int variant);
+int mg_transfer_variant(mg_ctx_t *ctx, mg_prec_t prec, int nrhs,
+                        int *restrict_variant, int *prolong_variant,
+                        double *us);
+
 /* Coarse-stencil kernel choice.  For FP32 arithmetic (MG_F32, MG_F16) the
  * coarse operator D_c ("Formulating an algorithm") can be applied either by
  * one workgroup per (site, right-hand side) (variant 0) or, for a batch of

@@ -22,7 +22,7 @@ MAX_LEVELS = 3
 MAX_RHS = 16
 
 EXPORTED = ["wilson_apply", "mg_setup", "mg_set_precond_prec", "mg_set_mass", "mg_set_timing", "mg_restrict",
-            "mg_prolong", "coarse_apply", "mg_apply_op", "mg_vcycle", "mg_set_coarse_variant", "mg_coarse_variant", "mg_solve", "mg_time_dslash", "mg_time_coarse",
+            "mg_prolong", "coarse_apply", "mg_apply_op", "mg_vcycle", "mg_transfer", "mg_set_transfer_variant", "mg_transfer_variant", "mg_set_coarse_variant", "mg_coarse_variant", "mg_solve", "mg_time_dslash", "mg_time_coarse",
             "mg_destroy", "mg_last_error", "mg_export_maps", "mg_export_P",
             "mg_export_coarse_op", "mg_export_nullvecs", "mg_level_info",
             "ptc_create", "ptc_set_links", "ptc_set_targets", "ptc_forward", "ptc_loss_grad", "ptc_adam",
@@ -106,6 +106,9 @@ def lib():
             "coarse_apply": [vp, ci, vp, vp, ci, ci, vp],
             "mg_apply_op": [vp, ci, ci, vp, vp, ci, vp],
             "mg_vcycle": [vp, ci, vp, vp, ci, ctypes.POINTER(ci), vp],
+            "mg_transfer": [vp, ci, ci, ci, vp, vp, ci, vp],
+            "mg_set_transfer_variant": [vp, ci],
+            "mg_transfer_variant": [vp, ci, ci, ctypes.POINTER(ci), ctypes.POINTER(ci), ctypes.POINTER(cd)],
             "mg_set_coarse_variant": [vp, ci],
             "mg_coarse_variant": [vp, ci, ci, ci, ctypes.POINTER(ci), ctypes.POINTER(cd)],
             "mg_solve": [vp, vp, vp, ci, cd, ctypes.POINTER(Info), vp],
@@ -279,6 +282,34 @@ class MG:
         _check(lib().mg_vcycle(self.ctx, PREC[prec], _dev(r, "in"), _dev(out, "out"), nrhs, ctypes.byref(it),
                                _stream()))
         return out, it.value
+
+    def transfer(self, level, v, direction, prec="f64", nrhs=None):
+        """Restriction (direction 0, level -> level+1) or prolongation
+        (direction 1, level+1 -> level) with the stored P of precision
+        `prec`; canonical complex128 in and out."""
+        lin, lout = (level, level + 1) if direction == 0 else (level + 1, level)
+        if nrhs is None:
+            nrhs = self._nvec(lin, v)
+        Lo, no = self.level_info(lout)
+        shape = (nrhs, Lo[3], Lo[2], Lo[1], Lo[0]) + ((4, 3) if lout == 0 else (no,))
+        out = torch.empty(shape, dtype=torch.complex128, device=v.device)
+        _check(lib().mg_transfer(self.ctx, level, PREC[prec], direction, _dev(v, "in"), _dev(out, "out"), nrhs,
+                                 _stream()))
+        return out
+
+    def set_transfer_variant(self, variant):
+        """Force the fine-level transfer kernels (0 vector, 1 matrix-core GEMM)
+        or restore tuning (-1)."""
+        _check(lib().mg_set_transfer_variant(self.ctx, int(variant)))
+
+    def transfer_variant(self, prec, nrhs):
+        """(restriction, prolongation) kernel choices for `prec` and nrhs and
+        the tuning times {(direction, variant): us}."""
+        r, p = ctypes.c_int(0), ctypes.c_int(0)
+        us = (ctypes.c_double * 4)()
+        _check(lib().mg_transfer_variant(self.ctx, PREC[prec], int(nrhs), ctypes.byref(r), ctypes.byref(p), us))
+        return r.value, p.value, {("restrict", 0): us[0], ("restrict", 1): us[1], ("prolong", 0): us[2],
+                                  ("prolong", 1): us[3]}
 
     def set_coarse_variant(self, variant):
         """Force the coarse-stencil kernel (0 per-RHS, 1/2/4 matrix-core GEMM

@@ -117,6 +117,7 @@ extern "C" int mg_setup(const mg_lattice_t *lat, const void *U, double mass, con
   c->prec = params->precond_prec;
   c->use_graph = params->use_graph ? 1 : 0;
   std::memset(c->cvar, 0xff, sizeof(c->cvar));  // -1: not tuned
+  std::memset(c->tvar, 0xff, sizeof(c->tvar));
   const double t0 = now_s();
   int rc = hip_rc(hipStreamCreateWithFlags(&c->sti, hipStreamNonBlocking), "hipStreamCreateWithFlags");
   if (rc == MG_OK) rc = hip_rc(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming), "hipEventCreate");
@@ -190,6 +191,30 @@ extern "C" int mg_coarse_variant(mg_ctx_t *ctx, int level, mg_prec_t prec, int n
   return MG_OK;
 }
 
+extern "C" int mg_set_transfer_variant(mg_ctx_t *ctx, int variant) {
+  if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
+  if (variant != -1 && variant != 0 && variant != 1)
+    return bad(MG_EINVAL, "mg_set_transfer_variant: variant must be -1, 0 or 1");
+  ctx->tvar_force = variant;
+  return MG_OK;
+}
+
+extern "C" int mg_transfer_variant(mg_ctx_t *ctx, mg_prec_t prec, int nrhs, int *restrict_variant,
+                                   int *prolong_variant, double *us) {
+  if (!ctx || !restrict_variant || !prolong_variant) return bad(MG_EINVAL, "mg_transfer_variant: NULL argument");
+  if (nrhs < 1 || nrhs > MG_MAX_RHS) return bad(MG_EINVAL, "mg_transfer_variant: nrhs out of range");
+  if (prec != MG_F64 && prec != MG_F32 && prec != MG_F16) return bad(MG_ENOTSUP, "mg_transfer_variant: prec");
+  const int pi = prec == MG_F64 ? 0 : prec == MG_F32 ? 1 : 2;
+  *restrict_variant = pi == 0 ? 0 : ctx->tvar[0][pi][nrhs];
+  *prolong_variant = pi == 0 ? 0 : ctx->tvar[1][pi][nrhs];
+  if (us) {
+    for (int d = 0; d < 2; ++d)
+      for (int v = 0; v < 2; ++v)
+        us[2 * d + v] = (pi == 0 || ctx->tvar[d][pi][nrhs] < 0) ? 0.0 : (double)ctx->tvar_us[d][pi][nrhs][v];
+  }
+  return MG_OK;
+}
+
 extern "C" int mg_restrict(mg_ctx_t *ctx, int level, const void *fine, void *coarse, int nrhs, hipStream_t st) {
   set_error("");
   if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
@@ -252,6 +277,53 @@ template <typename P> int apply_op_t(mg_ctx *c, int level, const double2 *a, dou
   }
 }
 }  // namespace
+
+namespace {
+template <typename P>
+int transfer_t(mg_ctx *c, int level, int dir, const double2 *a, double2 *b, int nrhs, hipStream_t st) {
+  using R = typename P::R;
+  if constexpr (sizeof(R) == 8) {
+    if (dir == 0) return transfer_restrict<P>(c, level, a, b, nrhs, st);
+    return transfer_prolong<P>(c, level, a, b, nrhs, 0, st);
+  } else {
+    const size_t nf = c->lev[level].vsize() * nrhs, nc = c->lev[level + 1].vsize() * nrhs;
+    const size_t nin = dir == 0 ? nf : nc, nout = dir == 0 ? nc : nf;
+    AsyncBuf<float2> x(st), y(st);
+    HIPK(x.alloc(nin));
+    HIPK(y.alloc(nout));
+    HIPK((convert<float, double>(x.p, a, nin, st)));
+    if (dir == 0) MG_TRY(transfer_restrict<P>(c, level, x.p, y.p, nrhs, st));
+    else MG_TRY(transfer_prolong<P>(c, level, x.p, y.p, nrhs, 0, st));
+    HIPK((convert<double, float>(b, y.p, nout, st)));
+    return MG_OK;
+  }
+}
+}  // namespace
+
+extern "C" int mg_transfer(mg_ctx_t *ctx, int level, mg_prec_t prec, int direction, const void *in, void *out,
+                           int nrhs, hipStream_t st) {
+  set_error("");
+  if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
+  MG_TRY(check_ctx_level(ctx, level, 0, ctx->nlev - 2));
+  if (!in || !out || in == out || nrhs < 1) return bad(MG_EINVAL, "mg_transfer: bad buffers or nrhs");
+  if (direction != 0 && direction != 1) return bad(MG_EINVAL, "mg_transfer: direction must be 0 or 1");
+  if (prec != MG_F64 && prec != MG_F32 && prec != MG_F16)
+    return bad(MG_ENOTSUP, "mg_transfer: prec must be MG_F64, MG_F32 or MG_F16");
+  MG_TRY(ensure_prec(ctx, prec, st));
+  MG_TRY(ensure_scalars(ctx, part_need(ctx, 1)));
+  const int lin = direction == 0 ? level : level + 1, lout = direction == 0 ? level + 1 : level;
+  AsyncBuf<double2> a(st), b(st);
+  HIPK(a.alloc(ctx->lev[lin].vsize() * nrhs));
+  HIPK(b.alloc(ctx->lev[lout].vsize() * nrhs));
+  HIPK(pack_level(ctx, lin, in, a.p, nrhs, st));
+  int rc;
+  if (prec == MG_F64) rc = transfer_t<PF64>(ctx, level, direction, a.p, b.p, nrhs, st);
+  else if (prec == MG_F32) rc = transfer_t<PF32>(ctx, level, direction, a.p, b.p, nrhs, st);
+  else rc = transfer_t<PF16>(ctx, level, direction, a.p, b.p, nrhs, st);
+  MG_TRY(rc);
+  HIPK(unpack_level(ctx, lout, b.p, out, nrhs, st));
+  return MG_OK;
+}
 
 extern "C" int mg_apply_op(mg_ctx_t *ctx, int level, mg_prec_t prec, const void *in, void *out, int nrhs,
                            hipStream_t st) {

@@ -135,6 +135,15 @@ hipError_t restrict_fine(const Geom &g, const Geom &gc, int nv, const S *P, cons
 template <typename R, typename S>
 hipError_t prolong_fine(const Geom &g, const Geom &gc, int nv, const S *P, const c_t<R> *coarse, c_t<R> *fine,
                         int nrhs, int accumulate, hipStream_t st);
+// Many right-hand sides on the FP32 matrix cores (transfer_mma.hip):
+// one workgroup per aggregate for all nrhs <= 16; requires |B| % 4 == 0.
+bool transfer_mma_ok(const Geom &g, int nv, int nrhs);
+template <typename S>
+hipError_t restrict_fine_mma(const Geom &g, const Geom &gc, int nv, const S *P, const float2 *fine, float2 *coarse,
+                             int nrhs, hipStream_t st);
+template <typename S>
+hipError_t prolong_fine_mma(const Geom &g, const Geom &gc, int nv, const S *P, const float2 *coarse, float2 *fine,
+                            int nrhs, int accumulate, hipStream_t st);
 // Coarse level l -> l+1: P = nv vectors in coarse AoS layout [nv][V][n];
 // requires block volume * n <= 2048.
 template <typename R, typename S>

@@ -222,6 +222,7 @@ template <typename P> int coarse_variant(mg_ctx *c, int l, int nrhs, hipStream_t
     Level &L = c->lev[l];
     if (c->cvar_force >= 0)
       return (c->cvar_force == 0 || coarse_mma_ok(L.n, nrhs, c->cvar_force)) ? c->cvar_force : 0;
+    if (nrhs > MG_MAX_RHS) return 0;  // the matrix-core variants take at most 16
     int &v = c->cvar[l][P::id][nrhs];
     if (v >= 0) return v;
     const TuneKey key{L.n, P::id, nrhs, L.g.V};
@@ -277,6 +278,92 @@ template <typename P> int coarse_variant(mg_ctx *c, int l, int nrhs, hipStream_t
     c->cvar_us[l][P::id][nrhs] = best_t;
     std::lock_guard<std::mutex> lk(tune_mu);
     tune_cache.push_back(TuneVal{key, best, best_t});
+    return v;
+  }
+}
+
+namespace {
+struct TKey {
+  uint32_t V, vb;
+  int nv, prec, nrhs, dir;
+  bool operator==(const TKey &o) const {
+    return V == o.V && vb == o.vb && nv == o.nv && prec == o.prec && nrhs == o.nrhs && dir == o.dir;
+  }
+};
+struct TVal {
+  TKey k;
+  int variant;
+  float us[2];
+};
+std::vector<TVal> ttune_cache;
+}  // namespace
+
+// Fine-level transfer kernel for (direction dir: 0 restriction, 1
+// prolongation; nrhs): the vector kernels (0) or the matrix-core GEMM (1),
+// timed once per shape on first use and kept for the process.
+template <typename P> int transfer_variant(mg_ctx *c, int dir, int nrhs, hipStream_t st) {
+  using R = typename P::R;
+  if constexpr (sizeof(R) == 8) {
+    return 0;
+  } else {
+    Level &L = c->lev[0], &Lc = c->lev[1];
+    if (nrhs < 2 || nrhs > MG_MAX_RHS || !transfer_mma_ok(L.g, L.nv, nrhs)) return 0;
+    if (c->tvar_force >= 0) return c->tvar_force > 0 ? 1 : 0;
+    int &v = c->tvar[dir][P::id][nrhs];
+    if (v >= 0) return v;
+    const TKey key{L.g.V, L.g.vb, L.nv, P::id, nrhs, dir};
+    {
+      std::lock_guard<std::mutex> lk(tune_mu);
+      for (const TVal &t : ttune_cache)
+        if (t.k == key) {
+          v = t.variant;
+          c->tvar_us[dir][P::id][nrhs][0] = t.us[0];
+          c->tvar_us[dir][P::id][nrhs][1] = t.us[1];
+          return v;
+        }
+    }
+    DevBuf<float2> a, b;
+    MG_TRY(a.alloc(L.vsize() * nrhs));
+    MG_TRY(b.alloc(Lc.vsize() * nrhs));
+    HIPK(fill_const<float>(a, L.vsize() * nrhs, 1.0f, st));
+    HIPK(fill_const<float>(b, Lc.vsize() * nrhs, 1.0f, st));
+    hipEvent_t e0, e1;
+    HIPK(hipEventCreate(&e0));
+    HIPK(hipEventCreate(&e1));
+    int best = 0, rc = MG_OK;
+    float best_t = 1e30f, t_us[2] = {0.f, 0.f};
+    for (int cv = 0; cv < 2 && rc == MG_OK; ++cv) {
+      const int reps = 6;
+      for (int i = 0; i < 2 + reps && rc == MG_OK; ++i) {
+        if (i == 2) rc = hip_rc(hipEventRecord(e0, st), "hipEventRecord");
+        hipError_t e;
+        if (dir == 0)
+          e = cv ? restrict_fine_mma(L.g, Lc.g, L.nv, P_of<P>(L), a.p, b.p, nrhs, st)
+                 : restrict_fine<R>(L.g, Lc.g, L.nv, P_of<P>(L), a.p, b.p, nrhs, st);
+        else
+          e = cv ? prolong_fine_mma(L.g, Lc.g, L.nv, P_of<P>(L), b.p, a.p, nrhs, 1, st)
+                 : prolong_fine<R>(L.g, Lc.g, L.nv, P_of<P>(L), b.p, a.p, nrhs, 1, st);
+        if (rc == MG_OK) rc = hip_rc(e, "transfer tune");
+      }
+      if (rc == MG_OK) rc = hip_rc(hipEventRecord(e1, st), "hipEventRecord");
+      if (rc == MG_OK) rc = hip_rc(hipEventSynchronize(e1), "hipEventSynchronize");
+      float ms = 0.f;
+      if (rc == MG_OK) rc = hip_rc(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+      const float us = ms * 1e3f / reps;
+      t_us[cv] = us;
+      if (rc == MG_OK && us < best_t) {
+        best_t = us;
+        best = cv;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    MG_TRY(rc);
+    v = best;
+    c->tvar_us[dir][P::id][nrhs][0] = t_us[0];
+    c->tvar_us[dir][P::id][nrhs][1] = t_us[1];
+    std::lock_guard<std::mutex> lk(tune_mu);
+    ttune_cache.push_back(TVal{key, best, {t_us[0], t_us[1]}});
     return v;
   }
 }
@@ -359,7 +446,17 @@ int transfer_restrict(mg_ctx *c, int l, const vec_t<P> *fine, vec_t<P> *coarse, 
   using R = typename P::R;
   using S = typename P::S;
   Level &L = c->lev[l], &Lc = c->lev[l + 1];
-  if (l == 0) HIPK((restrict_fine<R, S>(L.g, Lc.g, L.nv, P_of<P>(L), fine, coarse, nrhs, st)));
+  if (l == 0) {
+    const int tv = transfer_variant<P>(c, 0, nrhs, st);
+    if (tv < 0) return tv;
+    if constexpr (sizeof(R) == 4) {
+      if (tv == 1) {
+        HIPK(restrict_fine_mma(L.g, Lc.g, L.nv, P_of<P>(L), fine, coarse, nrhs, st));
+        return MG_OK;
+      }
+    }
+    HIPK((restrict_fine<R, S>(L.g, Lc.g, L.nv, P_of<P>(L), fine, coarse, nrhs, st)));
+  }
   else HIPK((restrict_coarse<R, S>(L.g, Lc.g, L.n, L.nv, P_of<P>(L), fine, coarse, nrhs, st)));
   return MG_OK;
 }
@@ -370,7 +467,17 @@ int transfer_prolong(mg_ctx *c, int l, const vec_t<P> *coarse, vec_t<P> *fine, i
   using R = typename P::R;
   using S = typename P::S;
   Level &L = c->lev[l], &Lc = c->lev[l + 1];
-  if (l == 0) HIPK((prolong_fine<R, S>(L.g, Lc.g, L.nv, P_of<P>(L), coarse, fine, nrhs, accumulate, st)));
+  if (l == 0) {
+    const int tv = transfer_variant<P>(c, 1, nrhs, st);
+    if (tv < 0) return tv;
+    if constexpr (sizeof(R) == 4) {
+      if (tv == 1) {
+        HIPK(prolong_fine_mma(L.g, Lc.g, L.nv, P_of<P>(L), coarse, fine, nrhs, accumulate, st));
+        return MG_OK;
+      }
+    }
+    HIPK((prolong_fine<R, S>(L.g, Lc.g, L.nv, P_of<P>(L), coarse, fine, nrhs, accumulate, st)));
+  }
   else HIPK((prolong_coarse<R, S>(L.g, Lc.g, L.n, L.nv, P_of<P>(L), coarse, fine, nrhs, accumulate, st)));
   return MG_OK;
 }
@@ -868,6 +975,7 @@ int refine(mg_ctx *c, int l, hipStream_t st_in) {
     drop_op_copies(c, l);
     clear_graphs(c);
     std::memset(c->cvar, 0xff, sizeof(c->cvar));
+    std::memset(c->tvar, 0xff, sizeof(c->tvar));
     HIPK(hipMemsetAsync(flag, 0, sizeof(int), st));
     if (l == 0) HIPK(ortho_fine(Lv.g, nk, Lv.P64, flag, st));
     else HIPK(ortho_coarse(Lv.g, Lv.n, nk, Lv.P64, flag, st));
@@ -919,6 +1027,7 @@ int refine(mg_ctx *c, int l, hipStream_t st_in) {
   drop_op_copies(c, l);
   clear_graphs(c);
   std::memset(c->cvar, 0xff, sizeof(c->cvar));
+  std::memset(c->tvar, 0xff, sizeof(c->tvar));
   return rc;
 }
 

@@ -221,6 +221,11 @@ struct mg_ctx {
   int cvar[MG_MAX_LEVELS][3][MG_MAX_RHS + 1];
   float cvar_us[MG_MAX_LEVELS][3][MG_MAX_RHS + 1];
   int cvar_force = -1;  // >= 0: use this variant wherever it can run
+  // fine-level transfer kernel per (direction, precision, nrhs): 0 = vector
+  // kernels, 1 = matrix-core GEMM; -1 = not tuned yet
+  int tvar[2][3][MG_MAX_RHS + 1];
+  float tvar_us[2][3][MG_MAX_RHS + 1][2];  // tuning times of both variants
+  int tvar_force = -1;
   hipStream_t sti = nullptr;                  // library-owned stream of mg_solve
   hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_chunk[2] = {nullptr, nullptr};
   int use_graph = 1;

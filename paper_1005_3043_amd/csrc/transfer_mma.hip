@@ -1,0 +1,203 @@
+// Fine-level restriction r_c = P^dag r and prolongation e (+)= P e_c for many
+// right-hand sides as complex GEMMs on the FP32 matrix cores (Eq. 4, Eq. 8;
+// 16x16x4 MFMA, four real products per complex one).  One workgroup per
+// aggregate B serves every right-hand side, so each entry of P is read once
+// per application instead of once per group of right-hand sides.  Per
+// chirality h the restriction is C = P_h^dag F (M = Nv, N = nrhs,
+// K = 6 |B|) and the prolongation F (+)= P_h E (M = 6 |B|, N = nrhs, K = Nv).
+// The 6 |B| index runs over (component c' of the spin half, site t of the
+// aggregate) with t fastest: four consecutive indices are four consecutive
+// sites of one component plane of the tile-interleaved layout (|B| % 4 == 0
+// is required).  MFMA lane layouts (16x16x4, FP32): A lane l = (row l % 16,
+// k l / 16); B lane l = (k l / 16, column l % 16); C lane l = (rows
+// 4 (l / 16) + 0..3, column l % 16).
+#include "kernels.h"
+
+namespace mg {
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+constexpr int TM_NR = 16;    // right-hand sides per tile (N of the MFMA)
+constexpr int TM_U = 8;      // k-steps per load batch of the restriction
+constexpr int TM_WAVES = 8;  // wavefronts per workgroup
+
+// Site-blocked coarse index of aggregate B (aggregates are numbered
+// lexicographically over the coarse lattice).
+__device__ __forceinline__ uint32_t agg_site(const Geom &gc, uint32_t B) {
+  const int x[4] = {(int)(B % gc.L[0]), (int)((B / gc.L[0]) % gc.L[1]), (int)((B / (gc.L[0] * gc.L[1])) % gc.L[2]),
+                    (int)(B / (gc.L[0] * gc.L[1] * gc.L[2]))};
+  return encode(gc, x);
+}
+
+// Restriction.  Wavefront w = (ks, h, mt): rows 16 mt .. 16 mt + 15 of the
+// chirality-h output over the k-steps ks, ks + KS, ...; the KS partial
+// tiles are summed in LDS in a fixed order.
+template <typename S>
+__global__ __launch_bounds__(64 * TM_WAVES) void k_restrict_fine_mma(Geom g, Geom gc, int nv, int nrhs,
+                                                                     const S *__restrict__ P,
+                                                                     const float2 *__restrict__ fine,
+                                                                     float2 *__restrict__ coarse) {
+  __shared__ float red[TM_WAVES - 1][64][8];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int MT = (nv + 15) >> 4, NH = 2 * MT, KS = TM_WAVES / NH;
+  const int hm = wv % NH, ks = wv / NH, h = hm / MT, mt = hm % MT;
+  const uint32_t B = blockIdx.x;
+  const size_t V = g.Vpad;
+  const int vb = (int)g.vb, KQ = (6 * vb) >> 2;
+  const int arow = mt * 16 + (lane & 15), kq = lane >> 4, col = lane & 15;
+  const bool arow_ok = arow < nv, col_ok = col < nrhs;
+  const S *Pa = P + (size_t)(arow_ok ? arow : 0) * 12 * V;
+  const float2 *Fb = fine + (size_t)(col_ok ? col : 0) * 12 * V;
+  const uint32_t s0 = B * (uint32_t)vb;
+  const int nq = ks < KQ ? (KQ - ks + KS - 1) / KS : 0;
+  floatx4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+  for (int q0 = 0; q0 < nq; q0 += TM_U) {
+    float2 av[TM_U], bv[TM_U];
+#pragma unroll
+    for (int u = 0; u < TM_U; ++u) {
+      const int K = 4 * (ks + min(q0 + u, nq - 1) * KS) + kq;
+      const int cp = K / vb, t = K - cp * vb;
+      const size_t o = fidx(s0 + (uint32_t)t, 6 * h + cp, 12);
+      av[u] = cvt<float2>(Pa[o]);
+      bv[u] = Fb[o];
+    }
+#pragma unroll
+    for (int u = 0; u < TM_U; ++u) {
+      if (q0 + u < nq) {
+        const float2 a = arow_ok ? av[u] : make_float2(0.f, 0.f);
+        const float2 b = col_ok ? bv[u] : make_float2(0.f, 0.f);
+        // conj(P) F: re += a.x b.x + a.y b.y, im += a.x b.y - a.y b.x
+        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, cre, 0, 0, 0);
+        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, cim, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.x, cim, 0, 0, 0);
+      }
+    }
+  }
+  if (ks > 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      red[wv - NH][lane][v] = cre[v];
+      red[wv - NH][lane][4 + v] = cim[v];
+    }
+  }
+  __syncthreads();
+  if (ks == 0) {
+    for (int q = 1; q < KS; ++q) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        cre[v] += red[q * NH + hm - NH][lane][v];
+        cim[v] += red[q * NH + hm - NH][lane][4 + v];
+      }
+    }
+    const uint32_t ic = agg_site(gc, B);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int k = mt * 16 + 4 * kq + v;
+      if (k < nv && col_ok)
+        coarse[((size_t)col * gc.V + ic) * (2 * nv) + h * nv + k] = make_float2(cre[v], cim[v]);
+    }
+  }
+}
+
+// Prolongation.  The aggregate's coarse values are staged in LDS; wavefront
+// w takes the output row tiles w, w + 8, ... of both chiralities.
+template <typename S>
+__global__ __launch_bounds__(64 * TM_WAVES) void k_prolong_fine_mma(Geom g, Geom gc, int nv, int nrhs,
+                                                                    const S *__restrict__ P,
+                                                                    const float2 *__restrict__ coarse,
+                                                                    float2 *__restrict__ fine, int accumulate) {
+  __shared__ float2 eb[COARSE_NMAX][TM_NR];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const uint32_t B = blockIdx.x;
+  const size_t V = g.Vpad;
+  const int vb = (int)g.vb, Mh = 6 * vb, MTh = (Mh + 15) >> 4;
+  const uint32_t ic = agg_site(gc, B), s0 = B * (uint32_t)vb;
+  for (int idx = tid; idx < 2 * nv * TM_NR; idx += blockDim.x) {
+    const int j = idx % TM_NR, hk = idx / TM_NR;
+    eb[hk][j] = j < nrhs ? coarse[((size_t)j * gc.V + ic) * (2 * nv) + hk] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const int kq = lane >> 4, col = lane & 15;
+  const bool col_ok = col < nrhs;
+  const int nks = (nv + 3) >> 2;
+  float2 *Fc = fine + (size_t)(col_ok ? col : 0) * 12 * V;
+  for (int tile = wv; tile < 2 * MTh; tile += TM_WAVES) {
+    const int h = tile / MTh, mt = tile - h * MTh;
+    const int row = mt * 16 + (lane & 15);
+    const bool row_ok = row < Mh;
+    const int rc = row_ok ? row : Mh - 1;
+    const int cpa = rc / vb, ta = rc - cpa * vb;
+    const size_t oa = fidx(s0 + (uint32_t)ta, 6 * h + cpa, 12);
+    float2 av[COARSE_NMAX / 8];
+#pragma unroll
+    for (int u = 0; u < COARSE_NMAX / 8; ++u) {
+      const int k = min(4 * u + kq, nv - 1);
+      av[u] = u < nks ? cvt<float2>(P[(size_t)k * 12 * V + oa]) : make_float2(0.f, 0.f);
+    }
+    floatx4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int u = 0; u < COARSE_NMAX / 8; ++u) {
+      if (u < nks) {
+        const int k = 4 * u + kq;
+        const bool k_ok = k < nv;
+        const float2 a = (row_ok && k_ok) ? av[u] : make_float2(0.f, 0.f);
+        const float2 b = k_ok ? eb[h * nv + k][col] : make_float2(0.f, 0.f);
+        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, cre, 0, 0, 0);
+        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.y, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, cim, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, cim, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = mt * 16 + 4 * kq + v;
+      if (r < Mh && col_ok) {
+        const int cp = r / vb, t = r - cp * vb;
+        const size_t o = fidx(s0 + (uint32_t)t, 6 * h + cp, 12);
+        float2 val = make_float2(cre[v], cim[v]);
+        if (accumulate) {
+          const float2 f = Fc[o];
+          val = make_float2(val.x + f.x, val.y + f.y);
+        }
+        Fc[o] = val;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+bool transfer_mma_ok(const Geom &g, int nv, int nrhs) {
+  return nrhs >= 1 && nrhs <= TM_NR && nv >= 1 && 2 * nv <= COARSE_NMAX && g.vb % 4 == 0 && nv <= 32;
+}
+
+template <typename S>
+hipError_t restrict_fine_mma(const Geom &g, const Geom &gc, int nv, const S *P, const float2 *fine, float2 *coarse,
+                             int nrhs, hipStream_t st) {
+  if (!transfer_mma_ok(g, nv, nrhs)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_restrict_fine_mma<S>), dim3(g.Vc), dim3(64 * TM_WAVES), 0, st, g, gc, nv, nrhs, P, fine,
+                     coarse);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t prolong_fine_mma(const Geom &g, const Geom &gc, int nv, const S *P, const float2 *coarse, float2 *fine,
+                            int nrhs, int accumulate, hipStream_t st) {
+  if (!transfer_mma_ok(g, nv, nrhs)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_prolong_fine_mma<S>), dim3(g.Vc), dim3(64 * TM_WAVES), 0, st, g, gc, nv, nrhs, P, coarse,
+                     fine, accumulate);
+  return hipGetLastError();
+}
+
+template hipError_t restrict_fine_mma<float2>(const Geom &, const Geom &, int, const float2 *, const float2 *,
+                                              float2 *, int, hipStream_t);
+template hipError_t restrict_fine_mma<chalf>(const Geom &, const Geom &, int, const chalf *, const float2 *, float2 *,
+                                             int, hipStream_t);
+template hipError_t prolong_fine_mma<float2>(const Geom &, const Geom &, int, const float2 *, const float2 *,
+                                             float2 *, int, int, hipStream_t);
+template hipError_t prolong_fine_mma<chalf>(const Geom &, const Geom &, int, const chalf *, const float2 *, float2 *,
+                                            int, int, hipStream_t);
+
+}  // namespace mg

@@ -216,6 +216,38 @@ def test_operator_precision(built, prec):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f16"])
+@pytest.mark.parametrize("nrhs", [5, 12])
+def test_transfer_variants(built, prec, nrhs):
+    """Fine-level restriction and prolongation with the stored-precision P,
+    by the vector kernels (four right-hand sides per workgroup) and by the
+    matrix-core GEMM (one workgroup per aggregate for all of them), against
+    the oracle's FP64 transfers (storage rounding only) and against each
+    other (FP32 summation order only)."""
+    name, U, m, ctx, h = built
+    L = h.levels[0].geom.L
+    r = W.gaussian_spinor(L, 21, batch=(nrhs,))
+    ref_r = np.stack([h.restrict(0, r[i]) for i in range(nrhs)])
+    rng = np.random.default_rng(22)
+    ec = rng.standard_normal(ref_r.shape) + 1j * rng.standard_normal(ref_r.shape)
+    ref_p = np.stack([h.prolong(0, ec[i]) for i in range(nrhs)])
+    out = {}
+    try:
+        for var in (0, 1):
+            ctx.set_transfer_variant(var)
+            out[var] = (ctx.transfer(0, torch.from_numpy(r).cuda(), 0, prec).cpu().numpy(),
+                        ctx.transfer(0, torch.from_numpy(ec).cuda(), 1, prec).cpu().numpy())
+    finally:
+        ctx.set_transfer_variant(-1)
+    e = {var: (_rel(out[var][0], ref_r), _rel(out[var][1], ref_p)) for var in (0, 1)}
+    d = (_rel(out[1][0], out[0][0]), _rel(out[1][1], out[0][1]))
+    print(f"{name}: {prec} {nrhs} vectors: restrict / prolong rel err vector {e[0][0]:.1e} / {e[0][1]:.1e}, "
+          f"matrix core {e[1][0]:.1e} / {e[1][1]:.1e}; between them {d[0]:.1e} / {d[1]:.1e}")
+    for var in (0, 1):
+        assert e[var][0] < PREC_BOUND[prec] and e[var][1] < PREC_BOUND[prec]
+    assert d[0] < 1e-5 and d[1] < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
 def test_coarse_variants(built, prec):
     """Every coarse-stencil kernel variant (per-RHS FMA, matrix-core GEMM with
     K split 1/2/4) applies the stored-precision D_c to a batch of right-hand
