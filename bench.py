@@ -179,6 +179,25 @@ def kernel_probe(mgwd, torch, W):
         ms = lctx.time_dslash(prec, 1, 20)
         print(json.dumps({"probe": f"dslash_{prec}_32^3x64", "launches": 22, "avg_ms": ms}), flush=True)
     lctx.close()
+    # 24^3x48 with 12 right-hand sides: the matrix-core coarse stencil (tuned
+    # K split) and the matrix-core restriction / prolongation, FP16-stored
+    cfg2 = W.CONFIGS["C2"]
+    L2 = cfg2["L"]
+    U2 = torch.from_numpy(W.gauge_field(L2, cfg2["eps"], cfg2["seed"])).cuda()
+    st2 = torch.from_numpy(W.setup_starts(L2, cfg2["nv"][0], cfg2["seed"])).cuda()
+    ctx2 = mgwd.MG(U2, W.mass_for("C2"), cfg2["blocks"], cfg2["nv"], [st2], max_rhs=12, precond_prec="f16")
+    ms = ctx2.time_coarse(1, "f16", 12, 20)
+    var, us = ctx2.coarse_variant(1, "f16", 12)
+    print(json.dumps({"probe": "coarse_f16_12rhs_24^3x48", "launches": 22, "avg_ms": ms, "variant": var}), flush=True)
+    r12 = torch.from_numpy(W.point_sources(L2)).cuda()
+    ec12 = ctx2.transfer(0, r12, 0, "f16")
+    ctx2.set_transfer_variant(1)
+    for _ in range(10):
+        ctx2.transfer(0, r12, 0, "f16")
+        ctx2.transfer(0, ec12, 1, "f16")
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "transfer_mma_f16_12rhs_24^3x48", "launches": 10}), flush=True)
+    ctx2.close()
 
 
 def multi_rhs_report(mgwd, torch, W):

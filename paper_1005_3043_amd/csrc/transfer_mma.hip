@@ -19,7 +19,7 @@ namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int TM_NR = 16;    // right-hand sides per tile (N of the MFMA)
-constexpr int TM_U = 8;      // k-steps per load batch of the restriction
+constexpr int TM_U = 4;      // k-blocks (16 indices each) per load batch of the restriction
 constexpr int TM_WAVES = 8;  // wavefronts per workgroup
 
 // Site-blocked coarse index of aggregate B (aggregates are numbered
@@ -30,9 +30,27 @@ __device__ __forceinline__ uint32_t agg_site(const Geom &gc, uint32_t B) {
   return encode(gc, x);
 }
 
+// Four consecutive stored entries (16-byte aligned) as FP32 complex.
+__device__ __forceinline__ void load4(const chalf *p, float2 (&o)[4]) {
+  const chalf4 v = *reinterpret_cast<const chalf4 *>(p);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) o[q] = cvt<float2>(v.v[q]);
+}
+__device__ __forceinline__ void load4(const float2 *p, float2 (&o)[4]) {
+  const float4 a = reinterpret_cast<const float4 *>(p)[0], b = reinterpret_cast<const float4 *>(p)[1];
+  o[0] = make_float2(a.x, a.y);
+  o[1] = make_float2(a.z, a.w);
+  o[2] = make_float2(b.x, b.y);
+  o[3] = make_float2(b.z, b.w);
+}
+
 // Restriction.  Wavefront w = (ks, h, mt): rows 16 mt .. 16 mt + 15 of the
-// chirality-h output over the k-steps ks, ks + KS, ...; the KS partial
-// tiles are summed in LDS in a fixed order.
+// chirality-h output over the k-blocks ks, ks + KS, ... of 16 indices; the
+// KS partial tiles are summed in LDS in a fixed order.  In a k-block, lane
+// (i, kk) loads the four consecutive sites 4 kk .. 4 kk + 3 of its row of P
+// and of its column of the fine vectors in one access each, and the four
+// MFMAs u = 0..3 of the block take index 4 kk + u in k-slot kk (the sum over
+// K does not depend on the order of its terms).
 template <typename S>
 __global__ __launch_bounds__(64 * TM_WAVES) void k_restrict_fine_mma(Geom g, Geom gc, int nv, int nrhs,
                                                                      const S *__restrict__ P,
@@ -44,34 +62,41 @@ __global__ __launch_bounds__(64 * TM_WAVES) void k_restrict_fine_mma(Geom g, Geo
   const int hm = wv % NH, ks = wv / NH, h = hm / MT, mt = hm % MT;
   const uint32_t B = blockIdx.x;
   const size_t V = g.Vpad;
-  const int vb = (int)g.vb, KQ = (6 * vb) >> 2;
+  const int vb = (int)g.vb, Kh = 6 * vb, KB = (Kh + 15) >> 4;
   const int arow = mt * 16 + (lane & 15), kq = lane >> 4, col = lane & 15;
   const bool arow_ok = arow < nv, col_ok = col < nrhs;
   const S *Pa = P + (size_t)(arow_ok ? arow : 0) * 12 * V;
   const float2 *Fb = fine + (size_t)(col_ok ? col : 0) * 12 * V;
   const uint32_t s0 = B * (uint32_t)vb;
-  const int nq = ks < KQ ? (KQ - ks + KS - 1) / KS : 0;
+  const int nb = ks < KB ? (KB - ks + KS - 1) / KS : 0;  // k-blocks of this wavefront
   floatx4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
-  for (int q0 = 0; q0 < nq; q0 += TM_U) {
-    float2 av[TM_U], bv[TM_U];
+  for (int b0 = 0; b0 < nb; b0 += TM_U) {
+    float2 av[TM_U][4], bv[TM_U][4];
+    bool kin[TM_U];
 #pragma unroll
     for (int u = 0; u < TM_U; ++u) {
-      const int K = 4 * (ks + min(q0 + u, nq - 1) * KS) + kq;
-      const int cp = K / vb, t = K - cp * vb;
+      const int K0 = 16 * (ks + min(b0 + u, nb - 1) * KS) + 4 * kq;
+      kin[u] = K0 < Kh;
+      const int Kc = kin[u] ? K0 : 0;
+      const int cp = Kc / vb, t = Kc - cp * vb;
       const size_t o = fidx(s0 + (uint32_t)t, 6 * h + cp, 12);
-      av[u] = cvt<float2>(Pa[o]);
-      bv[u] = Fb[o];
+      load4(Pa + o, av[u]);
+      load4(Fb + o, bv[u]);
     }
 #pragma unroll
     for (int u = 0; u < TM_U; ++u) {
-      if (q0 + u < nq) {
-        const float2 a = arow_ok ? av[u] : make_float2(0.f, 0.f);
-        const float2 b = col_ok ? bv[u] : make_float2(0.f, 0.f);
-        // conj(P) F: re += a.x b.x + a.y b.y, im += a.x b.y - a.y b.x
-        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, cre, 0, 0, 0);
-        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, cre, 0, 0, 0);
-        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, cim, 0, 0, 0);
-        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.x, cim, 0, 0, 0);
+      if (b0 + u < nb) {
+        const bool aon = arow_ok && kin[u], bon = col_ok && kin[u];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float2 a = aon ? av[u][q] : make_float2(0.f, 0.f);
+          const float2 b = bon ? bv[u][q] : make_float2(0.f, 0.f);
+          // conj(P) F: re += a.x b.x + a.y b.y, im += a.x b.y - a.y b.x
+          cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, cre, 0, 0, 0);
+          cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, cre, 0, 0, 0);
+          cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, cim, 0, 0, 0);
+          cim = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.x, cim, 0, 0, 0);
+        }
       }
     }
   }
