@@ -214,9 +214,12 @@ def multi_rhs_report(mgwd, torch, W):
     ctx = mgwd.MG(U, mass, blocks, nv, [st], max_rhs=12)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)  # noqa: E731
+    log(f"24^3x48: setup {setup_s:.3f} s")
     ctx.set_precond_prec("f16")
     ctx.solve(b[:12], 1e-10)  # warm-up: graphs, autotuning
     x, info, rc = ctx.solve(b, 1e-10)
+    log(f"24^3x48: batched FP16 solve {info['t_solve_s']:.3f} s, iterations {info['iters'][:12]}")
     var, us = ctx.coarse_variant(1, "f16", 12)
     tr_r, tr_p, tr_us = ctx.transfer_variant("f16", 12)
     ctx.set_precond_prec("f64")
@@ -225,6 +228,7 @@ def multi_rhs_report(mgwd, torch, W):
         _, i1, _ = ctx.solve(b[i:i + 1].contiguous(), 1e-10)
         t64 += i1["t_solve_s"]
         it64.append(i1["iters"][0])
+        log(f"24^3x48: plain FP64 solve of source {i}: {i1['t_solve_s']:.3f} s, {i1['iters'][0]} iterations")
     ctx.close()
     # setup stage two (groups of 8 prototypes, 5 truncated-MG GCR steps,
     # FP16-stored V-cycles), then the same batched solve
@@ -233,7 +237,9 @@ def multi_rhs_report(mgwd, torch, W):
     ctx = mgwd.MG(U, mass, blocks, nv, [st], max_rhs=12, precond_prec="f16", refine_group=8, refine_iters=5)
     torch.cuda.synchronize()
     setup_r = time.perf_counter() - t0
+    log(f"24^3x48: setup with stage two {setup_r:.3f} s")
     _, info_r, rc_r = ctx.solve(b, 1e-10)
+    log(f"24^3x48: batched FP16 solve after stage two {info_r['t_solve_s']:.3f} s")
     ctx.close()
     refined = {"refine_group": 8, "refine_iters": 5, "setup_s": round(setup_r, 3),
                "batched_f16_solve_s": round(info_r["t_solve_s"], 3), "batched_iters": info_r["iters"][:12],

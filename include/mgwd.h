@@ -250,7 +250,9 @@ int mg_transfer_variant(mg_ctx_t *ctx, mg_prec_t prec, int nrhs,
  * one workgroup per (site, right-hand side) (variant 0) or, for a batch of
  * right-hand sides, as one complex GEMM per coarse site on the FP32 matrix
  * cores with the K range split over 1, 2 or 4 wavefront groups (variants
- * 1, 2, 4).  By default the library times the candidates once per
+ * 1, 2, 4), reading either the stencil itself or a row-major copy of it
+ * made on first use (variants 9, 10, 12; four columns per access; needs
+ * n = 2 Nv divisible by 4).  By default the library times the candidates once per
  * (operator size, coarse volume, nrhs, precision) on first use and keeps the
  * fastest for the process.  mg_set_coarse_variant forces a variant
  * (-1 restores tuning; a variant that cannot run a shape falls back to 0).

@@ -156,6 +156,8 @@ extern "C" int mg_set_mass(mg_ctx_t *ctx, double mass) {
     HIPK(shift_diag(L.L64, L.g.V, L.n, delta, nullptr));
     L.L32.release();  // low-precision copies are rebuilt from the shifted FP64 stencil
     L.L16.release();
+    L.L32t.release();
+    L.L16t.release();
   }
   clear_graphs(ctx);
   HIPK(hipStreamSynchronize(nullptr));
@@ -173,8 +175,9 @@ extern "C" int mg_set_timing(mg_ctx_t *ctx, int on) {
 
 extern "C" int mg_set_coarse_variant(mg_ctx_t *ctx, int variant) {
   if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
-  if (variant != -1 && variant != 0 && variant != 1 && variant != 2 && variant != 4)
-    return bad(MG_EINVAL, "mg_set_coarse_variant: variant must be -1, 0, 1, 2 or 4");
+  if (variant != -1 && variant != 0 && variant != 1 && variant != 2 && variant != 4 && variant != 9 &&
+      variant != 10 && variant != 12)
+    return bad(MG_EINVAL, "mg_set_coarse_variant: variant must be -1, 0, 1, 2, 4, 9, 10 or 12");
   ctx->cvar_force = variant;
   clear_graphs(ctx);
   return MG_OK;
@@ -481,6 +484,7 @@ int time_coarse_t(mg_ctx *c, int level, int nrhs, int reps, hipEvent_t e0, hipEv
   CoarseArgs ca;
   ca.variant = coarse_variant<P>(c, level, nrhs, st);
   if (ca.variant < 0) return ca.variant;
+  if (ca.variant >= 8) ca.lt = cop_t_of_level<P>(c, L, st);
   for (int i = 0; i < 2; ++i) HIPK((coarse_apply_k<R, S>(L.g, L.n, Lop, a, b, nrhs, 0, ca, st)));
   HIPK(hipEventRecord(e0, st));
   for (int i = 0; i < reps; ++i) HIPK((coarse_apply_k<R, S>(L.g, L.n, Lop, a, b, nrhs, 0, ca, st)));

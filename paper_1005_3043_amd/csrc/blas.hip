@@ -77,6 +77,23 @@ template <typename S> hipError_t store_convert(S *y, const double2 *x, size_t n,
   hipLaunchKernelGGL(k_store_convert<S>, dim3(stream_grid(n)), dim3(256), 0, st, y, x, n);
   return hipGetLastError();
 }
+// Lt[s][i][p] = L[s][p][i]: row i of a site's 9n-column block row made contiguous.
+template <typename S>
+__global__ __launch_bounds__(256) void k_transpose_convert(S *Lt, const double2 *L, uint32_t V, int n) {
+  const size_t per = (size_t)9 * n * n, tot = per * V, K = (size_t)9 * n;
+  for (size_t o = blockIdx.x * (size_t)blockDim.x + threadIdx.x; o < tot; o += (size_t)gridDim.x * blockDim.x) {
+    const size_t s = o / per, r = o - s * per, i = r / K, p = r - i * K;
+    Lt[o] = cvt<S>(L[s * per + p * n + i]);
+  }
+}
+template <typename S> hipError_t transpose_convert(S *Lt, const double2 *L, uint32_t V, int n, hipStream_t st) {
+  const size_t tot = (size_t)9 * n * n * V;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transpose_convert<S>, dim3(stream_grid(tot)), dim3(256), 0, st, Lt, L, V, n);
+  return hipGetLastError();
+}
+template hipError_t transpose_convert<float2>(float2 *, const double2 *, uint32_t, int, hipStream_t);
+template hipError_t transpose_convert<chalf>(chalf *, const double2 *, uint32_t, int, hipStream_t);
 template hipError_t store_convert<float2>(float2 *, const double2 *, size_t, hipStream_t);
 template hipError_t store_convert<chalf>(chalf *, const double2 *, size_t, hipStream_t);
 

@@ -301,6 +301,20 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 template <typename S> __device__ __forceinline__ float2 op_f32(const S &v) { return cvt<float2>(v); }
 
+// Four consecutive operator entries (16-byte aligned) as FP32 complex.
+__device__ __forceinline__ void load4_op(const chalf *p, float2 (&o)[4]) {
+  const chalf4 v = *reinterpret_cast<const chalf4 *>(p);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) o[q] = cvt<float2>(v.v[q]);
+}
+__device__ __forceinline__ void load4_op(const float2 *p, float2 (&o)[4]) {
+  const float4 a = reinterpret_cast<const float4 *>(p)[0], b = reinterpret_cast<const float4 *>(p)[1];
+  o[0] = make_float2(a.x, a.y);
+  o[1] = make_float2(a.z, a.w);
+  o[2] = make_float2(b.x, b.y);
+  o[3] = make_float2(b.z, b.w);
+}
+
 constexpr int MMA_NR = 16;  // right-hand sides per GEMM tile (N of the MFMA)
 constexpr int MMA_U = 8;    // operator k-steps per load batch
 
@@ -339,7 +353,7 @@ __device__ __forceinline__ void block_allsum_multi(const double *__restrict__ p,
 // (slot, column) pairs per step).  MFMA lane layouts (16x16x4, FP32):
 // A lane l = (row l % 16, k l / 16); B lane l = (k l / 16, column l % 16);
 // C lane l = (rows 4 (l / 16) + 0..3, column l % 16).
-template <typename S, int KS>
+template <typename S, int KS, bool RM>
 __global__ __launch_bounds__(1024) void k_coarse_mma(Geom g, int n, const S *__restrict__ L,
                                                      const float2 *__restrict__ in, float2 *__restrict__ out,
                                                      int nrhs, int dagger, double *__restrict__ part, int pw,
@@ -381,18 +395,37 @@ __global__ __launch_bounds__(1024) void k_coarse_mma(Geom g, int n, const S *__r
   // out-of-range values zeroed afterwards) and double-buffered MMA_U k-steps
   // ahead, so every wavefront keeps MMA_U loads in flight; the first batch is
   // issued before the input staging.
-  const S *La = L + (size_t)s * K * n + (arow_ok ? arow : 0);
+  // Column-major operator (RM false): lane (row, kq) reads entry (row, k)
+  // of each k-step, rows contiguous.  Row-major copy (RM true): lane (row,
+  // kq) reads the four consecutive columns 16 b + 4 kq .. + 3 of its row in
+  // one access for the four k-steps of block b (k-slot kq of step u takes
+  // column 16 b + 4 kq + u; the sum over K does not depend on term order).
+  const S *La = RM ? L + (size_t)s * K * n + (size_t)(arow_ok ? arow : 0) * K
+                   : L + (size_t)s * K * n + (arow_ok ? arow : 0);
   const int KQ = (K + 3) >> 2;
-  const int nq = (KQ - ks + KS - 1) / KS;  // k-steps of this wavefront
+  const int nq = RM ? 0 : (KQ - ks + KS - 1) / KS;  // k-steps of this wavefront
+  const int KB = (K + 15) >> 4;
+  const int nbk = RM ? (ks < KB ? (KB - ks + KS - 1) / KS : 0) : 0;  // k-blocks of this wavefront
   float2 abuf[2][MMA_U];
   auto load_batch = [&](float2 (&dst)[MMA_U], int q0) {
+    if constexpr (RM) {
 #pragma unroll
-    for (int u = 0; u < MMA_U; ++u) {
-      const int kk = min(4 * (ks + (q0 + u) * KS) + kq, K - 1);
-      dst[u] = op_f32(La[(size_t)kk * n]);
+      for (int u = 0; u < MMA_U / 4; ++u) {
+        const int k0 = min(16 * (ks + min(q0 + u, nbk - 1) * KS) + 4 * kq, K - 4);
+        float2 o[4];
+        load4_op(La + k0, o);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[4 * u + q] = o[q];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < MMA_U; ++u) {
+        const int kk = min(4 * (ks + (q0 + u) * KS) + kq, K - 1);
+        dst[u] = op_f32(La[(size_t)kk * n]);
+      }
     }
   };
-  load_batch(abuf[0], 0);
+  if (RM ? nbk > 0 : true) load_batch(abuf[0], 0);
   __shared__ uint32_t nbs[9];
   if (tid < 9) nbs[tid] = slot_site(g, s, tid);
   __syncthreads();
@@ -407,6 +440,34 @@ __global__ __launch_bounds__(1024) void k_coarse_mma(Geom g, int n, const S *__r
   }
   __syncthreads();
   floatx4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+  if constexpr (RM) {
+    constexpr int BB = MMA_U / 4;  // k-blocks per load batch
+    for (int b0 = 0; b0 < nbk; b0 += 2 * BB) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int bb = b0 + h * BB;
+        if (bb >= nbk) break;
+        if (bb + BB < nbk) load_batch(abuf[h ^ 1], bb + BB);
+#pragma unroll
+        for (int u = 0; u < BB; ++u) {
+          const bool bok = bb + u < nbk;
+          const int kbase = 16 * (ks + (bb + u) * KS) + 4 * kq;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int kk = kbase + q;
+            const bool kok = bok && kk < K;
+            const float2 a = (kok && arow_ok) ? abuf[h][4 * u + q] : make_float2(0.f, 0.f);
+            const float2 bv = bl[min(kk, K - 1) * nrhs + colc];
+            const float2 b = (kok && col_ok) ? bv : make_float2(0.f, 0.f);
+            cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, cre, 0, 0, 0);
+            cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, cim, 0, 0, 0);
+            cre = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.y, cre, 0, 0, 0);
+            cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, cim, 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
   for (int q0 = 0; q0 < nq; q0 += 2 * MMA_U) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -505,8 +566,10 @@ static size_t mma_lds_bytes(int n, int nrhs, int ks) {
   return b > r ? b : r;
 }
 
-bool coarse_mma_ok(int n, int nrhs, int ks) {
+bool coarse_mma_ok(int n, int nrhs, int variant) {
+  const int ks = variant & 7;
   if (n > COARSE_NMAX || nrhs < 1 || nrhs > MMA_NR) return false;
+  if (variant != ks && (variant != (ks | 8) || n % 4 != 0)) return false;  // row-major copy: 16-byte rows
   if (ks != 1 && ks != 2 && ks != 4) return false;
   if (((n + 15) / 16) * ks * 64 > 1024) return false;
   return mma_lds_bytes(n, nrhs, ks) <= 56 * 1024;  // + 8 KB static LDS
@@ -536,19 +599,27 @@ hipError_t coarse_apply_k(const Geom &g, int n, const S *L, const c_t<R> *in, c_
   if constexpr (sizeof(R) == 4) {
     if (a.variant > 0) {
       if (a.fuse && a.fuse->kind) return hipErrorInvalidValue;  // fusion is per-RHS kernel only
-      const int ks = a.variant;
-      if (!coarse_mma_ok(n, nrhs, ks)) return hipErrorInvalidValue;
+      const int ks = a.variant & 7;
+      const bool rm = (a.variant & 8) != 0;
+      if (!coarse_mma_ok(n, nrhs, a.variant)) return hipErrorInvalidValue;
+      if (rm && a.lt == nullptr) return hipErrorInvalidValue;
+      const S *Lk = rm ? static_cast<const S *>(a.lt) : L;
       const dim3 block(64 * ((n + 15) / 16) * ks);
       const size_t lds = mma_lds_bytes(n, nrhs, ks);
-      if (ks == 1)
-        hipLaunchKernelGGL((k_coarse_mma<S, 1>), dim3(g.V), block, lds, st, g, n, L, in, out, nrhs, dagger, a.part,
-                           a.pw, a.done, c);
-      else if (ks == 2)
-        hipLaunchKernelGGL((k_coarse_mma<S, 2>), dim3(g.V), block, lds, st, g, n, L, in, out, nrhs, dagger, a.part,
-                           a.pw, a.done, c);
-      else
-        hipLaunchKernelGGL((k_coarse_mma<S, 4>), dim3(g.V), block, lds, st, g, n, L, in, out, nrhs, dagger, a.part,
-                           a.pw, a.done, c);
+#define MG_MMA_LAUNCH(KSV, RMV)                                                                                 \
+  hipLaunchKernelGGL((k_coarse_mma<S, KSV, RMV>), dim3(g.V), block, lds, st, g, n, Lk, in, out, nrhs, dagger, \
+                     a.part, a.pw, a.done, c)
+      if (ks == 1) {
+        if (rm) MG_MMA_LAUNCH(1, true);
+        else MG_MMA_LAUNCH(1, false);
+      } else if (ks == 2) {
+        if (rm) MG_MMA_LAUNCH(2, true);
+        else MG_MMA_LAUNCH(2, false);
+      } else {
+        if (rm) MG_MMA_LAUNCH(4, true);
+        else MG_MMA_LAUNCH(4, false);
+      }
+#undef MG_MMA_LAUNCH
       return hipGetLastError();
     }
   } else {

@@ -106,7 +106,8 @@ struct CgFuse {
 //  variant: 0 = one workgroup per (site, right-hand side), FP vector FMA;
 //    KS = 1, 2, 4 = one workgroup per site for all right-hand sides, a
 //    complex GEMM on FP32 matrix cores with the K dimension split over KS
-//    wavefront groups (FP32 arithmetic only).
+//    wavefront groups (FP32 arithmetic only); 8 + KS = the same GEMM reading
+//    the row-major operator copy `lt` four columns per access (n % 4 == 0).
 struct CoarseArgs {
   double *part = nullptr;
   int pw = 1;
@@ -114,7 +115,11 @@ struct CoarseArgs {
   const CgCheck *chk = nullptr;
   const CgFuse *fuse = nullptr;  // per-RHS kernel (variant 0) only
   int variant = 0;
+  const void *lt = nullptr;  // row-major operator copy (variants 8 + KS)
 };
+// Row-major copy of a coarse operator (Lt[site][row][9n] from the
+// column-major FP64 stencil), for the matrix-core variants 8 + KS.
+template <typename S> hipError_t transpose_convert(S *Lt, const double2 *L, uint32_t V, int n, hipStream_t st);
 // out = D_c in (dagger: sigma3 D_c sigma3) for nrhs right-hand sides
 // (site-major vectors [nrhs][V][n]).
 template <typename R, typename S>

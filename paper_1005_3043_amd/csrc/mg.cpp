@@ -151,12 +151,34 @@ template <> const chalf *P_of<PF16>(Level &L) { return L.P16.p; }
 
 template <typename P> const typename P::S *links_of_level(Level &L) { return links_of<P>(L); }
 template <typename P> const typename P::S *cop_of_level(Level &L) { return cop_of<P>(L); }
+
+// Row-major copy of level l's operator for the matrix-core variants 8 + KS,
+// made from the FP64 stencil on first use (nullptr in FP64 or on failure).
+template <typename P> const void *cop_t_of(mg_ctx *, Level &, hipStream_t) { return nullptr; }
+template <typename S> static const void *make_cop_t(DevBuf<S> &Lt, Level &L, hipStream_t st) {
+  if (!Lt.p) {
+    if (Lt.alloc(L.L64.n) != MG_OK) return nullptr;
+    if (transpose_convert<S>(Lt.p, L.L64.p, L.g.V, L.n, st) != hipSuccess) {
+      Lt.release();
+      return nullptr;
+    }
+  }
+  return Lt.p;
+}
+template <> const void *cop_t_of<PF32>(mg_ctx *, Level &L, hipStream_t st) { return make_cop_t(L.L32t, L, st); }
+template <> const void *cop_t_of<PF16>(mg_ctx *, Level &L, hipStream_t st) { return make_cop_t(L.L16t, L, st); }
 template const double2 *links_of_level<PF64>(Level &);
 template const float2 *links_of_level<PF32>(Level &);
 template const chalf *links_of_level<PF16>(Level &);
 template const double2 *cop_of_level<PF64>(Level &);
 template const float2 *cop_of_level<PF32>(Level &);
 template const chalf *cop_of_level<PF16>(Level &);
+template <typename P> const void *cop_t_of_level(mg_ctx *c, Level &L, hipStream_t st) {
+  return cop_t_of<P>(c, L, st);
+}
+template const void *cop_t_of_level<PF64>(mg_ctx *, Level &, hipStream_t);
+template const void *cop_t_of_level<PF32>(mg_ctx *, Level &, hipStream_t);
+template const void *cop_t_of_level<PF16>(mg_ctx *, Level &, hipStream_t);
 
 int np_mr(mg_ctx *c, int l) { return l == 0 ? dslash_blocks(c->lev[0].g) : (int)np_coarse(c->lev[l]); }
 
@@ -246,15 +268,16 @@ template <typename P> int coarse_variant(mg_ctx *c, int l, int nrhs, hipStream_t
     HIPK(hipEventCreate(&e1));
     int best = 0;
     float best_t = 1e30f;
-    const int cands[4] = {0, 1, 2, 4};
+    const int cands[7] = {0, 1, 2, 4, 9, 10, 12};
     int rc = MG_OK;
-    for (int ci = 0; ci < 4 && rc == MG_OK; ++ci) {
+    for (int ci = 0; ci < 7 && rc == MG_OK; ++ci) {
       const int cv = cands[ci];
       if (cv > 0 && !coarse_mma_ok(L.n, nrhs, cv)) continue;
       CoarseArgs ca;
       ca.part = c->part;
       ca.pw = 1;
       ca.variant = cv;
+      if (cv >= 8 && (ca.lt = cop_t_of<P>(c, L, st)) == nullptr) continue;
       const int reps = 8;
       for (int i = 0; i < 2 + reps && rc == MG_OK; ++i) {
         if (i == 2) rc = hip_rc(hipEventRecord(e0, st), "hipEventRecord");
@@ -388,6 +411,7 @@ int apply_A(mg_ctx *c, int l, const vec_t<P> *in, vec_t<P> *out, int nrhs, Dslas
       ca.pw = 3;
     }
     ca.variant = var;
+    if (var >= 8) ca.lt = cop_t_of<P>(c, L, st);
     {
       TimerScope ts(c, c->tm[tclass<P>(true)], st, (double)L.g.V * nrhs);
       HIPK((coarse_apply_k<R, S>(L.g, L.n, cop_of<P>(L), in, out, nrhs, 0, ca, st)));
@@ -576,6 +600,7 @@ int cgnr_chunk(mg_ctx *c, int l, vec_t<P> *e, int nrhs, int var, bool fused, hip
     ca.part = q.pw;
     ca.done = c->done;
     ca.variant = var;
+    if (var >= 8) ca.lt = cop_t_of<P>(c, L, st);
     {
       TimerScope ts(c, tm, st, sites, k == 0);
       HIPK((coarse_apply_k<R, S>(L.g, L.n, Lop, p, ww, nrhs, 0, ca, st)));
@@ -660,6 +685,7 @@ template <typename P> int cgnr(mg_ctx *c, int l, const vec_t<P> *b, vec_t<P> *e,
     ca.part = q.pz[0];
     ca.done = c->done;
     ca.variant = var;
+    if (var >= 8) ca.lt = cop_t_of<P>(c, L, st);
     TimerScope ts(c, tm, st, (double)L.g.V * nrhs);
     HIPK((coarse_apply_k<R, S>(L.g, L.n, cop_of<P>(L), w.cr, w.cz, nrhs, 1, ca, st)));
   }
@@ -908,6 +934,8 @@ void drop_op_copies(mg_ctx *c, int l) {
   c->lev[l].P16.release();
   c->lev[l + 1].L32.release();
   c->lev[l + 1].L16.release();
+  c->lev[l + 1].L32t.release();
+  c->lev[l + 1].L16t.release();
 }
 
 // z = K_l(r): one cycle from level l in precision prec (FP64 in and out).

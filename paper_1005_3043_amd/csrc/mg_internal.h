@@ -29,5 +29,6 @@ int setup(mg_ctx *c, const void *U, hipStream_t st);
 int check_lattice(const mg_lattice_t *lat);
 template <typename P> const typename P::S *links_of_level(Level &L);
 template <typename P> const typename P::S *cop_of_level(Level &L);
+template <typename P> const void *cop_t_of_level(mg_ctx *c, Level &L, hipStream_t st);
 
 }  // namespace mg

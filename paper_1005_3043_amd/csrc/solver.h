@@ -89,7 +89,11 @@ template <typename T> struct DevBuf {
     release();
     if (count == 0) return MG_OK;
     hipError_t e = hipMalloc((void **)&p, count * sizeof(T));
-    if (e == hipSuccess) e = hipMemset(p, 0, count * sizeof(T));  // padding entries stay zero
+    // Zero-filled (padding entries stay zero), and the fill has completed
+    // on return: the buffer is next used on streams that do not order
+    // themselves after the default stream.
+    if (e == hipSuccess) e = hipMemsetAsync(p, 0, count * sizeof(T), nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
       if (p) (void)hipFree(p);
       p = nullptr;
@@ -120,6 +124,7 @@ struct Level {
   DevBuf<float2> U32;    // fine links in FP32, nl entries per direction
   DevBuf<chalf> U16;     // fine links in FP16, nl entries per direction
   DevBuf<double2> L64;  DevBuf<float2> L32;  DevBuf<chalf> L16;  // coarse stencil [V][9][n][n]
+  DevBuf<float2> L32t;  DevBuf<chalf> L16t;  // row-major copies [V][n][9n] (matrix-core variants 8 + KS)
   DevBuf<double2> P64;  DevBuf<float2> P32;  DevBuf<chalf> P16;  // prolongator to next level
   DevBuf<double2> NV;                         // relaxed candidates before QR
   // complex entries per vector

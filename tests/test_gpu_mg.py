@@ -250,7 +250,8 @@ def test_transfer_variants(built, prec, nrhs):
 @pytest.mark.parametrize("prec", ["f32", "f16"])
 def test_coarse_variants(built, prec):
     """Every coarse-stencil kernel variant (per-RHS FMA, matrix-core GEMM with
-    K split 1/2/4) applies the stored-precision D_c to a batch of right-hand
+    K split 1/2/4, on the column-major operator or on its row-major copy,
+    9/10/12) applies the stored-precision D_c to a batch of right-hand
     sides with the storage rounding error only, and the variants agree with
     each other to FP32 rounding (they differ in summation order)."""
     name, U, m, ctx, h = built
@@ -261,7 +262,7 @@ def test_coarse_variants(built, prec):
     ref = np.stack([co.coarse_apply(lv.X, lv.Y, vc[i]) for i in range(nr)])
     outs = {}
     try:
-        for var in (0, 1, 2, 4):
+        for var in (0, 1, 2, 4, 9, 10, 12):
             ctx.set_coarse_variant(var)
             outs[var] = ctx.apply_op(1, torch.from_numpy(vc).cuda(), prec).cpu().numpy()
     finally:
@@ -282,7 +283,7 @@ def test_solve_multi_rhs_variants(built):
     b = W.gaussian_spinor(L, 9, batch=(4,))
     ctx.set_precond_prec("f32")
     try:
-        for var in (2, -1):
+        for var in (2, 10, -1):
             ctx.set_coarse_variant(var)
             x, info, rc = ctx.solve(torch.from_numpy(b).cuda(), 1e-10)
             xn = x.cpu().numpy()
@@ -291,7 +292,7 @@ def test_solve_multi_rhs_variants(built):
             assert rc == 0 and max(res) <= 1e-10 * 1.001
         v, us = ctx.coarse_variant(1, "f32", 4)
         print(f"{name}: autotuned coarse variant for 4 RHS: {v} ({us:.1f} us)")
-        assert v in (0, 1, 2, 4) and us > 0
+        assert v in (0, 1, 2, 4, 9, 10, 12) and us > 0
     finally:
         ctx.set_coarse_variant(-1)
         ctx.set_precond_prec("f64")
