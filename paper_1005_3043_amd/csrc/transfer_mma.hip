@@ -19,7 +19,7 @@ namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int TM_NR = 16;    // right-hand sides per tile (N of the MFMA)
-constexpr int TM_U = 4;      // k-blocks (16 indices each) per load batch of the restriction
+constexpr int TM_U = 2;      // k-blocks (16 indices each) per load batch of the restriction
 constexpr int TM_WAVES = 8;  // wavefronts per workgroup
 
 // Site-blocked coarse index of aggregate B (aggregates are numbered
@@ -44,34 +44,39 @@ __device__ __forceinline__ void load4(const float2 *p, float2 (&o)[4]) {
   o[3] = make_float2(b.z, b.w);
 }
 
-// Restriction.  Wavefront w = (ks, h, mt): rows 16 mt .. 16 mt + 15 of the
-// chirality-h output over the k-blocks ks, ks + KS, ... of 16 indices; the
-// KS partial tiles are summed in LDS in a fixed order.  In a k-block, lane
-// (i, kk) loads the four consecutive sites 4 kk .. 4 kk + 3 of its row of P
-// and of its column of the fine vectors in one access each, and the four
-// MFMAs u = 0..3 of the block take index 4 kk + u in k-slot kk (the sum over
-// K does not depend on the order of its terms).
+// Restriction.  Wavefront w = (ks, h): both row tiles (Nv <= 32) of the
+// chirality-h output over the k-blocks ks, ks + KS, ... of 16 indices, so
+// each fine-vector entry is loaded once per wavefront; the KS partial tiles
+// are summed in LDS in a fixed order.  In a k-block, lane (i, kk) loads the
+// four consecutive sites 4 kk .. 4 kk + 3 of its row of P (per tile) and of
+// its column of the fine vectors in one access each, and the four MFMAs
+// u = 0..3 of the block take index 4 kk + u in k-slot kk (the sum over K
+// does not depend on the order of its terms).
 template <typename S>
 __global__ __launch_bounds__(64 * TM_WAVES) void k_restrict_fine_mma(Geom g, Geom gc, int nv, int nrhs,
                                                                      const S *__restrict__ P,
                                                                      const float2 *__restrict__ fine,
                                                                      float2 *__restrict__ coarse) {
-  __shared__ float red[TM_WAVES - 1][64][8];
+  constexpr int KS = TM_WAVES / 2;
+  __shared__ float red[TM_WAVES - 2][64][16];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int MT = (nv + 15) >> 4, NH = 2 * MT, KS = TM_WAVES / NH;
-  const int hm = wv % NH, ks = wv / NH, h = hm / MT, mt = hm % MT;
+  const int MT = (nv + 15) >> 4;
+  const int h = wv & 1, ks = wv >> 1;
   const uint32_t B = blockIdx.x;
   const size_t V = g.Vpad;
   const int vb = (int)g.vb, Kh = 6 * vb, KB = (Kh + 15) >> 4;
-  const int arow = mt * 16 + (lane & 15), kq = lane >> 4, col = lane & 15;
-  const bool arow_ok = arow < nv, col_ok = col < nrhs;
-  const S *Pa = P + (size_t)(arow_ok ? arow : 0) * 12 * V;
+  const int kq = lane >> 4, col = lane & 15;
+  const int ar0 = lane & 15, ar1 = 16 + (lane & 15);
+  const bool a0_ok = ar0 < nv, a1_ok = MT > 1 && ar1 < nv, col_ok = col < nrhs;
+  const S *Pa0 = P + (size_t)(a0_ok ? ar0 : 0) * 12 * V;
+  const S *Pa1 = P + (size_t)(a1_ok ? ar1 : 0) * 12 * V;
   const float2 *Fb = fine + (size_t)(col_ok ? col : 0) * 12 * V;
   const uint32_t s0 = B * (uint32_t)vb;
   const int nb = ks < KB ? (KB - ks + KS - 1) / KS : 0;  // k-blocks of this wavefront
-  floatx4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+  floatx4 cre0 = {0.f, 0.f, 0.f, 0.f}, cim0 = {0.f, 0.f, 0.f, 0.f};
+  floatx4 cre1 = {0.f, 0.f, 0.f, 0.f}, cim1 = {0.f, 0.f, 0.f, 0.f};
   for (int b0 = 0; b0 < nb; b0 += TM_U) {
-    float2 av[TM_U][4], bv[TM_U][4];
+    float2 av0[TM_U][4], av1[TM_U][4], bv[TM_U][4];
     bool kin[TM_U];
 #pragma unroll
     for (int u = 0; u < TM_U; ++u) {
@@ -80,22 +85,30 @@ __global__ __launch_bounds__(64 * TM_WAVES) void k_restrict_fine_mma(Geom g, Geo
       const int Kc = kin[u] ? K0 : 0;
       const int cp = Kc / vb, t = Kc - cp * vb;
       const size_t o = fidx(s0 + (uint32_t)t, 6 * h + cp, 12);
-      load4(Pa + o, av[u]);
+      load4(Pa0 + o, av0[u]);
+      if (MT > 1) load4(Pa1 + o, av1[u]);
       load4(Fb + o, bv[u]);
     }
 #pragma unroll
     for (int u = 0; u < TM_U; ++u) {
       if (b0 + u < nb) {
-        const bool aon = arow_ok && kin[u], bon = col_ok && kin[u];
+        const bool bon = col_ok && kin[u];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const float2 a = aon ? av[u][q] : make_float2(0.f, 0.f);
           const float2 b = bon ? bv[u][q] : make_float2(0.f, 0.f);
           // conj(P) F: re += a.x b.x + a.y b.y, im += a.x b.y - a.y b.x
-          cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, cre, 0, 0, 0);
-          cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, cre, 0, 0, 0);
-          cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, cim, 0, 0, 0);
-          cim = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.x, cim, 0, 0, 0);
+          const float2 a = (a0_ok && kin[u]) ? av0[u][q] : make_float2(0.f, 0.f);
+          cre0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, cre0, 0, 0, 0);
+          cre0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, cre0, 0, 0, 0);
+          cim0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, cim0, 0, 0, 0);
+          cim0 = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.x, cim0, 0, 0, 0);
+          if (MT > 1) {
+            const float2 a1 = (a1_ok && kin[u]) ? av1[u][q] : make_float2(0.f, 0.f);
+            cre1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.x, b.x, cre1, 0, 0, 0);
+            cre1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.y, b.y, cre1, 0, 0, 0);
+            cim1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.x, b.y, cim1, 0, 0, 0);
+            cim1 = __builtin_amdgcn_mfma_f32_16x16x4f32(-a1.y, b.x, cim1, 0, 0, 0);
+          }
         }
       }
     }
@@ -103,8 +116,10 @@ __global__ __launch_bounds__(64 * TM_WAVES) void k_restrict_fine_mma(Geom g, Geo
   if (ks > 0) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      red[wv - NH][lane][v] = cre[v];
-      red[wv - NH][lane][4 + v] = cim[v];
+      red[wv - 2][lane][v] = cre0[v];
+      red[wv - 2][lane][4 + v] = cim0[v];
+      red[wv - 2][lane][8 + v] = cre1[v];
+      red[wv - 2][lane][12 + v] = cim1[v];
     }
   }
   __syncthreads();
@@ -112,16 +127,19 @@ __global__ __launch_bounds__(64 * TM_WAVES) void k_restrict_fine_mma(Geom g, Geo
     for (int q = 1; q < KS; ++q) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        cre[v] += red[q * NH + hm - NH][lane][v];
-        cim[v] += red[q * NH + hm - NH][lane][4 + v];
+        cre0[v] += red[2 * q + h - 2][lane][v];
+        cim0[v] += red[2 * q + h - 2][lane][4 + v];
+        cre1[v] += red[2 * q + h - 2][lane][8 + v];
+        cim1[v] += red[2 * q + h - 2][lane][12 + v];
       }
     }
     const uint32_t ic = agg_site(gc, B);
+    float2 *out = coarse + ((size_t)col * gc.V + ic) * (2 * nv) + h * nv;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int k = mt * 16 + 4 * kq + v;
-      if (k < nv && col_ok)
-        coarse[((size_t)col * gc.V + ic) * (2 * nv) + h * nv + k] = make_float2(cre[v], cim[v]);
+      const int k0 = 4 * kq + v, k1 = 16 + 4 * kq + v;
+      if (col_ok && k0 < nv) out[k0] = make_float2(cre0[v], cim0[v]);
+      if (col_ok && MT > 1 && k1 < nv) out[k1] = make_float2(cre1[v], cim1[v]);
     }
   }
 }
