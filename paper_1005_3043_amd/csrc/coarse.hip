@@ -21,7 +21,7 @@
 // site in one workgroup: out[:, 0:nrhs] = A [B_0 .. B_8], a complex GEMM with
 // M = n rows, N = nrhs (padded to 16) and K = 9n, where A is the site's
 // operator (loaded once for every right-hand side) and B the nine staged
-// input blocks.  Each complex product is four real 16x16x4 FP32 MFMAs.
+// input blocks.  Each complex product is three real 16x16x4 FP32 MFMAs.
 #include "solver.h"
 
 namespace mg {
@@ -439,7 +439,10 @@ __global__ __launch_bounds__(1024) void k_coarse_mma(Geom g, int n, const S *__r
     }
   }
   __syncthreads();
-  floatx4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f};
+  // Complex products with three real MFMAs each (Gauss): cre = sum a.x b.x,
+  // c2 = sum a.y b.y, cim = sum (a.x + a.y)(b.x + b.y); then re = cre - c2
+  // and im = cim - cre - c2.
+  floatx4 cre = {0.f, 0.f, 0.f, 0.f}, cim = {0.f, 0.f, 0.f, 0.f}, c2 = {0.f, 0.f, 0.f, 0.f};
   if constexpr (RM) {
     constexpr int BB = MMA_U / 4;  // k-blocks per load batch
     for (int b0 = 0; b0 < nbk; b0 += 2 * BB) {
@@ -460,9 +463,8 @@ __global__ __launch_bounds__(1024) void k_coarse_mma(Geom g, int n, const S *__r
             const float2 bv = bl[min(kk, K - 1) * nrhs + colc];
             const float2 b = (kok && col_ok) ? bv : make_float2(0.f, 0.f);
             cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, cre, 0, 0, 0);
-            cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, cim, 0, 0, 0);
-            cre = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.y, cre, 0, 0, 0);
-            cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, cim, 0, 0, 0);
+            c2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, c2, 0, 0, 0);
+            cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, b.x + b.y, cim, 0, 0, 0);
           }
         }
       }
@@ -482,12 +484,13 @@ __global__ __launch_bounds__(1024) void k_coarse_mma(Geom g, int n, const S *__r
         const float2 bv = bl[min(kk, K - 1) * nrhs + colc];
         const float2 b = (kok && col_ok) ? bv : make_float2(0.f, 0.f);
         cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, cre, 0, 0, 0);
-        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, cim, 0, 0, 0);
-        cre = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.y, cre, 0, 0, 0);
-        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, cim, 0, 0, 0);
+        c2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, c2, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, b.x + b.y, cim, 0, 0, 0);
       }
     }
   }
+  cim = cim - cre - c2;
+  cre = cre - c2;
   // centre inputs of this lane's output rows (for the <out, in> partial)
   float2 ctr[4];
 #pragma unroll
