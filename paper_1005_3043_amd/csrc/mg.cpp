@@ -48,7 +48,7 @@ size_t np_coarse(const Level &L) { return (size_t)L.g.V * coarse_split(L.n, L.g.
 
 // Partial-sum slots needed by a batch of nrhs vectors on every level.
 size_t part_need(mg_ctx *c, int nrhs) {
-  size_t m = (size_t)RED_BLOCKS * 2;
+  size_t m = (size_t)RED_BLOCKS * 2 * GCR_CHUNK;
   m = std::max(m, (size_t)dslash_blocks(c->lev[0].g) * 3);
   for (int l = 1; l < c->nlev; ++l) m = std::max(m, np_coarse(c->lev[l]) * 3);
   return m * (size_t)nrhs;
@@ -828,12 +828,12 @@ int fgcr(mg_ctx *c, const double2 *b, double2 *x, int nrhs, double tol, int *ite
                                       nullptr, st)));
       }
       c->n_fine += nrhs;
-      for (int i = 0; i < j; ++i) {
-        const double2 *Wi = W + (size_t)i * nn, *Zi = Z + (size_t)i * nn;
-        HIPK(dot<double>(Wi, Wj, n, nrhs, c->part, sc, st));
-        HIPK(gcr_sub2(Wj, Wi, Zj, Zi, n, nrhs, sc, skip, st));
-      }
-      HIPK(norm2<double>(Wj, n, nrhs, c->part, rr + MG_MAX_RHS, st));
+      // classical Gram-Schmidt against the earlier directions, up to eight
+      // per pass (same result as the modified form up to rounding)
+      if (j == 0) HIPK(norm2<double>(Wj, n, nrhs, c->part, rr + MG_MAX_RHS, st));
+      for (int i0 = 0; i0 < j; i0 += GCR_CHUNK)
+        HIPK(gcr_cgs(W + (size_t)i0 * nn, Z + (size_t)i0 * nn, nn, std::min(GCR_CHUNK, j - i0), Wj, Zj, n, nrhs,
+                     sc + 512, skip, c->part, rr + MG_MAX_RHS, st));
       HIPK(gcr_scale2(Wj, Zj, n, nrhs, rr + MG_MAX_RHS, skip, st));
       HIPK(dot<double>(Wj, r, n, nrhs, c->part, sc, st));
       HIPK(gcr_update(x, Zj, r, Wj, n, nrhs, sc, skip, c->part, rr, st));

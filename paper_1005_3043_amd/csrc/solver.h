@@ -9,6 +9,7 @@ namespace mg {
 
 constexpr int RED_BLOCKS = 1024;  // fixed grid of generic reductions
 constexpr int CG_NS = 8;          // CGNR scalars per right-hand side
+constexpr int GCR_CHUNK = 8;      // FGCR directions orthogonalised against per pass
 
 // ---- solver_kernels.hip
 template <typename R>
@@ -24,6 +25,11 @@ hipError_t gcr_sub2(double2 *y, const double2 *x, double2 *v, const double2 *u, 
                     const double2 *sc, const int *skip, hipStream_t st);
 hipError_t gcr_scale2(double2 *y, double2 *v, size_t n, int nrhs, const double *nrm2, const int *skip,
                       hipStream_t st);
+// w_j -= sum_i <w_i, w_j> w_i and z_j -= (same) z_i over the ni <= 8 earlier
+// directions W + i vs, Z + i vs (classical Gram-Schmidt, coefficients in
+// sc[rhs * 8 + i]); nrm2[rhs] = ||w_j||^2 afterwards.
+hipError_t gcr_cgs(const double2 *W, const double2 *Z, size_t vs, int ni, double2 *wj, double2 *zj, size_t n,
+                   int nrhs, double2 *sc, const int *skip, double *part, double *nrm2, hipStream_t st);
 hipError_t gcr_update(double2 *x, const double2 *z, double2 *r, const double2 *w, size_t n, int nrhs,
                       const double2 *sc, const int *skip, double *part, double *rr, hipStream_t st);
 // Fused CGNR steps (no finisher kernels): scalars are re-derived from the

@@ -133,6 +133,78 @@ __global__ __launch_bounds__(256) void k_scale2(double2 *y, double2 *v, size_t n
   }
 }
 
+// FGCR orthogonalisation of w_j against up to GCR_CHUNK earlier directions
+// w_i0 .. w_{i0+ni-1} by classical Gram-Schmidt: all inner products <w_i,
+// w_j> in one pass (GCR_CHUNK x 2 partials per block), then one pass
+// w_j -= sum c_i w_i, z_j -= sum c_i z_i with the partial ||w_j||^2.
+__global__ __launch_bounds__(256) void k_gcr_mdot(const double2 *__restrict__ W, size_t vs, int ni,
+                                                  const double2 *__restrict__ wj, size_t n, const int *skip,
+                                                  double *part) {
+  __shared__ double lds[4 * 2 * GCR_CHUNK];
+  const size_t off = (size_t)blockIdx.y * n;
+  double t[2 * GCR_CHUNK];
+#pragma unroll
+  for (int q = 0; q < 2 * GCR_CHUNK; ++q) t[q] = 0.0;
+  if (!(skip && skip[blockIdx.y])) {
+    GSTRIDE(idx, n) {
+      const double2 w = wj[off + idx];
+#pragma unroll
+      for (int i = 0; i < GCR_CHUNK; ++i) {
+        if (i < ni) {
+          const double2 v = W[(size_t)i * vs + off + idx];
+          t[2 * i] += v.x * w.x + v.y * w.y;
+          t[2 * i + 1] += v.x * w.y - v.y * w.x;
+        }
+      }
+    }
+  }
+  block_sum<2 * GCR_CHUNK>(t, lds);
+  if (threadIdx.x == 0) {
+    double *p = part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 2 * GCR_CHUNK;
+#pragma unroll
+    for (int q = 0; q < 2 * GCR_CHUNK; ++q) p[q] = t[q];
+  }
+}
+__global__ void k_gcr_mdot_fin(const double *part, int np, int ni, double2 *sc) {
+  double t[2 * GCR_CHUNK];
+  finish_sum<2 * GCR_CHUNK>(part, np, t);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < GCR_CHUNK; ++i)
+      if (i < ni) sc[(size_t)blockIdx.y * GCR_CHUNK + i] = make_double2(t[2 * i], t[2 * i + 1]);
+  }
+}
+__global__ __launch_bounds__(256) void k_gcr_orth(const double2 *__restrict__ W, const double2 *__restrict__ Z,
+                                                  size_t vs, int ni, double2 *wj, double2 *zj, size_t n,
+                                                  const double2 *sc, const int *skip, double *part) {
+  __shared__ double lds[4];
+  const size_t off = (size_t)blockIdx.y * n;
+  double t[1] = {0.0};
+  if (!(skip && skip[blockIdx.y])) {
+    double2 c[GCR_CHUNK];
+#pragma unroll
+    for (int i = 0; i < GCR_CHUNK; ++i) {
+      const double2 v = i < ni ? sc[(size_t)blockIdx.y * GCR_CHUNK + i] : make_double2(0.0, 0.0);
+      c[i] = make_double2(-v.x, -v.y);
+    }
+    GSTRIDE(idx, n) {
+      double2 w = wj[off + idx], z = zj[off + idx];
+#pragma unroll
+      for (int i = 0; i < GCR_CHUNK; ++i) {
+        if (i < ni) {
+          w = cfma(c[i], W[(size_t)i * vs + off + idx], w);
+          z = cfma(c[i], Z[(size_t)i * vs + off + idx], z);
+        }
+      }
+      wj[off + idx] = w;
+      zj[off + idx] = z;
+      t[0] += w.x * w.x + w.y * w.y;
+    }
+  }
+  block_sum<1>(t, lds);
+  if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = t[0];
+}
+
 // x += a z; r -= a w (a = sc[rhs]); partial ||r||^2
 __global__ __launch_bounds__(256) void k_gcr_update(double2 *x, const double2 *z, double2 *r, const double2 *w,
                                                     size_t n, const double2 *sc, const int *skip, double *part) {
@@ -349,6 +421,17 @@ hipError_t gcr_sub2(double2 *y, const double2 *x, double2 *v, const double2 *u, 
 hipError_t gcr_scale2(double2 *y, double2 *v, size_t n, int nrhs, const double *nrm2, const int *skip,
                       hipStream_t st) {
   hipLaunchKernelGGL(k_scale2, dim3(sgrid(n), nrhs), dim3(256), 0, st, y, v, n, nrm2, skip);
+  return hipGetLastError();
+}
+
+hipError_t gcr_cgs(const double2 *W, const double2 *Z, size_t vs, int ni, double2 *wj, double2 *zj, size_t n,
+                   int nrhs, double2 *sc, const int *skip, double *part, double *nrm2, hipStream_t st) {
+  if (ni < 1 || ni > GCR_CHUNK) return hipErrorInvalidValue;
+  const int g = sgrid(n);
+  hipLaunchKernelGGL(k_gcr_mdot, dim3(g, nrhs), dim3(256), 0, st, W, vs, ni, wj, n, skip, part);
+  hipLaunchKernelGGL(k_gcr_mdot_fin, dim3(1, nrhs), dim3(256), 0, st, part, g, ni, sc);
+  hipLaunchKernelGGL(k_gcr_orth, dim3(g, nrhs), dim3(256), 0, st, W, Z, vs, ni, wj, zj, n, sc, skip, part);
+  hipLaunchKernelGGL(k_fin_sum<1>, dim3(1, nrhs), dim3(256), 0, st, part, g, nrm2);
   return hipGetLastError();
 }
 
