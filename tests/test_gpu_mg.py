@@ -216,7 +216,7 @@ def test_operator_precision(built, prec):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f16"])
-@pytest.mark.parametrize("nrhs", [5, 12])
+@pytest.mark.parametrize("nrhs", [5, 12, 16])
 def test_transfer_variants(built, prec, nrhs):
     """Fine-level restriction and prolongation with the stored-precision P,
     by the vector kernels (four right-hand sides per workgroup) and by the
@@ -544,6 +544,33 @@ def test_setup_refinement_lowprec(cuda, prec):
     assert max(q) < 5e-2
     assert rc == 0 and res <= 1e-10 * 1.001
     assert abs(info["iters"][0] - it_ref) <= 2
+
+
+@pytest.mark.parametrize("prec", ["f64", "f16"])
+def test_edge_zero_rhs_and_full_batch(cuda, prec):
+    """Degenerate and maximal inputs: a batch of the largest size (16
+    right-hand sides) holding a zero right-hand side solves to x = 0 for it
+    in zero iterations and to 1e-10 for the others; one preconditioner
+    application of a zero vector is exactly zero (MR and CGNR guard their
+    zero denominators)."""
+    import paper_1005_3043_amd as mgwd
+    L, blocks, nv, eps, m, seed = CASES["4^4 b2^4 nv4"]
+    U = W.gauge_field(L, eps, seed)
+    starts = W.setup_starts(L, nv[0], seed)
+    ctx = mgwd.MG(torch.from_numpy(U).cuda(), m, blocks, nv, [torch.from_numpy(starts).cuda()], max_rhs=16,
+                  precond_prec=prec)
+    b = W.gaussian_spinor(L, 30, batch=(16,))
+    b[3] = 0.0
+    x, info, rc = ctx.solve(torch.from_numpy(b).cuda(), 1e-10)
+    xn = x.cpu().numpy()
+    res = [np.linalg.norm(b[i] - wi.apply_D(U, xn[i], m)) / np.linalg.norm(b[i]) for i in range(16) if i != 3]
+    z, it = ctx.vcycle(torch.zeros((2,) + b.shape[1:], dtype=torch.complex128, device="cuda"), prec)
+    ctx.close()
+    print(f"4^4 {prec}: 16 RHS with a zero one: iterations {info['iters'][:16]}, max resid {max(res):.2e}, "
+          f"zero cycle max |z| {float(z.abs().max()):.1e} ({it} CGNR iterations)")
+    assert rc == 0 and max(res) <= 1e-10 * 1.001
+    assert info["iters"][3] == 0 and not np.any(xn[3])
+    assert float(z.abs().max()) == 0.0 and it == 0
 
 
 def test_setup_errors(cuda):
