@@ -120,10 +120,27 @@ __device__ __forceinline__ double block_allsum_partials(const double *__restrict
 }
 
 
+// Workgroup i of a per-RHS launch -> (logical workgroup ws of its right-hand
+// side, rhs).  Workgroups go round-robin to the 8 XCDs; when the per-RHS
+// count is a multiple of 8, XCD x takes the contiguous workgroup range
+// [x nbx / 8, (x + 1) nbx / 8) (neighbouring sites share L2) and runs the
+// right-hand sides of one workgroup back to back, so that a site's operator
+// blocks come from HBM once and from that XCD's L2 for the other RHS.
+__device__ __forceinline__ void block_rhs_of(uint32_t i, uint32_t nbx, uint32_t nrhs, uint32_t &ws, int &rhs) {
+  if ((nbx & 7u) == 0u) {
+    const uint32_t t = i >> 3;
+    ws = (i & 7u) * (nbx >> 3) + t / nrhs;
+    rhs = (int)(t % nrhs);
+  } else {
+    ws = i / nrhs;
+    rhs = (int)(i % nrhs);
+  }
+}
+
 template <typename R, typename S, int RW>
 __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restrict__ L,
                                                  const c_t<R> *__restrict__ in, c_t<R> *__restrict__ out,
-                                                 int dagger, double *__restrict__ partials, int pw,
+                                                 int nrhs, int dagger, double *__restrict__ partials, int pw,
                                                  const int *__restrict__ done, CgCheck chk, CgFuse fz) {
   using C = c_t<R>;
   using VT = typename OpVec<S, RW>::V;
@@ -131,10 +148,12 @@ __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restri
   __shared__ C red[512 * RW];
   __shared__ C red2[CO_PARTS * COARSE_NMAX];
   __shared__ double wred[8 * 4];
-  const int rhs = blockIdx.y;
+  const uint32_t nbx = gridDim.x / (uint32_t)nrhs;  // workgroups per right-hand side
+  uint32_t ws;
+  int rhs;
+  block_rhs_of(blockIdx.x, nbx, (uint32_t)nrhs, ws, rhs);
   if (done != nullptr && done[rhs]) return;
-  const uint32_t ws = xcd_remap(blockIdx.x, gridDim.x);
-  const int RS = (int)(gridDim.x / g.V);
+  const int RS = (int)(nbx / g.V);
   const uint32_t s = ws / RS;
   const int nr = n / RS, r0 = (int)(ws - s * RS) * nr;
   const size_t rhs_off = (size_t)rhs * g.V * n;
@@ -178,7 +197,7 @@ __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restri
       bool conv;
       if (chk.fused) conv = (iter > 0 && !(rr > cg[4] * cg[3])) || iter >= chk.maxit;
       else conv = !(rr > cg[4] * cg[3]) || iter + 1 >= chk.maxit;
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (ws == 0 && threadIdx.x == 0) {
         chk.it_out[rhs] = (chk.fused && conv) ? iter : iter + 1;
         if (conv) chk.done[rhs] = 1;
       }
@@ -187,7 +206,7 @@ __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restri
     if (coef_on) {
       if (!(sums[2] > 0.0)) {
         if (fz.kind == 2) {
-          if (blockIdx.x == 0 && tid == 0) fz.done_w[rhs] = 1;
+          if (ws == 0 && tid == 0) fz.done_w[rhs] = 1;
           return;
         }
       } else {
@@ -282,7 +301,7 @@ __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restri
     block_sum<4>(v4, wred);
     if (tid == 0) {
       if (partials != nullptr) {
-        double *p = partials + ((size_t)rhs * gridDim.x + blockIdx.x) * pw;
+        double *p = partials + ((size_t)rhs * nbx + ws) * pw;
         if (pw == 1) {
           p[0] = v4[2];
         } else {
@@ -291,7 +310,7 @@ __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restri
           p[2] = v4[2];
         }
       }
-      if (fz.kind == 2) fz.part_own[(size_t)rhs * gridDim.x + blockIdx.x] = v4[3];
+      if (fz.kind == 2) fz.part_own[(size_t)rhs * nbx + ws] = v4[3];
     }
   }
 }
@@ -628,24 +647,24 @@ hipError_t coarse_apply_k(const Geom &g, int n, const S *L, const c_t<R> *in, c_
   } else {
     if (a.variant > 0) return hipErrorInvalidValue;
   }
-  dim3 grid(g.V * coarse_split(n, g.V), nrhs);
+  const dim3 grid(g.V * coarse_split(n, g.V) * nrhs);
   dim3 block(coarse_threads(n, g.V));
   CgFuse f{};
   if (a.fuse) f = *a.fuse;
   if constexpr (sizeof(S) == 16) {
-    hipLaunchKernelGGL((k_coarse<R, S, 1>), grid, block, 0, st, g, n, L, in, out, dagger, a.part, a.pw, a.done,
+    hipLaunchKernelGGL((k_coarse<R, S, 1>), grid, block, 0, st, g, n, L, in, out, nrhs, dagger, a.part, a.pw, a.done,
                        c, f);
   } else if constexpr (sizeof(S) == 8) {
-    hipLaunchKernelGGL((k_coarse<R, S, 2>), grid, block, 0, st, g, n, L, in, out, dagger, a.part, a.pw, a.done,
+    hipLaunchKernelGGL((k_coarse<R, S, 2>), grid, block, 0, st, g, n, L, in, out, nrhs, dagger, a.part, a.pw, a.done,
                        c, f);
   } else {
     // half storage: four rows per 16-byte load when the rows of a workgroup
     // come in multiples of four, else two rows per 8-byte load
     if ((n / coarse_split(n, g.V)) % 4 == 0)
-      hipLaunchKernelGGL((k_coarse<R, S, 4>), grid, block, 0, st, g, n, L, in, out, dagger, a.part, a.pw, a.done,
+      hipLaunchKernelGGL((k_coarse<R, S, 4>), grid, block, 0, st, g, n, L, in, out, nrhs, dagger, a.part, a.pw, a.done,
                          c, f);
     else
-      hipLaunchKernelGGL((k_coarse<R, S, 2>), grid, block, 0, st, g, n, L, in, out, dagger, a.part, a.pw, a.done,
+      hipLaunchKernelGGL((k_coarse<R, S, 2>), grid, block, 0, st, g, n, L, in, out, nrhs, dagger, a.part, a.pw, a.done,
                          c, f);
   }
   return hipGetLastError();

@@ -10,15 +10,35 @@
 //   X(x_c)[:, j]   = P^dag [ diag W + sum of intra-aggregate hops of W ] on x_c
 //   Y_d(x_c)[:, j] = P^dag [ hops of W in slot d that leave the aggregate ]
 // with P^dag the block-local restriction.  One workgroup per (coarse site,
-// column j); threads over the sites (fine) or elements (coarse) of the
-// aggregate; the 2Nv row inner products of each of the 9 slots are wavefront
-// shuffle reductions plus a fixed-order sum over waves.  FP64.
+// column j), the columns of one site consecutive on one XCD; threads over the
+// sites (fine) or elements (coarse) of the aggregate; the 2Nv row inner
+// products of each of the 9 slots are wavefront shuffle reductions plus a
+// fixed-order sum over waves.  FP64.
 // Output layout L[site][slot][j][i] (column-major blocks), slot 0 = X,
 // slot 1 + (2 mu + dir) = Y (dir 0: couples to x_c + mu).
 #include "kernels.h"
 #include "wilson_site.h"
 
 namespace mg {
+
+// Workgroup i -> (aggregate B, coarse column j).  Workgroups go round-robin
+// to the 8 XCDs; this order hands every XCD whole aggregates and runs the
+// 2Nv columns of one aggregate back to back there, so the aggregate's null
+// vectors (fine) or operator blocks (coarse) come from HBM once and from that
+// XCD's L2 for the other columns.  Aggregates beyond the last multiple of 8
+// follow in plain aggregate-major order.
+__device__ __forceinline__ void agg_col_of(uint32_t i, uint32_t nagg, uint32_t ncol, uint32_t &B, int &j) {
+  const uint32_t nagg8 = nagg & ~7u;
+  if (i < nagg8 * ncol) {
+    const uint32_t t = i >> 3;
+    B = (t / ncol) * 8u + (i & 7u);
+    j = (int)(t % ncol);
+  } else {
+    const uint32_t r = i - nagg8 * ncol;
+    B = nagg8 + r / ncol;
+    j = (int)(r % ncol);
+  }
+}
 
 __device__ __forceinline__ uint32_t coarse_site_of(const Geom &gc, uint32_t B, const Geom &g) {
   const int x[4] = {(int)(B % g.C[0]), (int)((B / g.C[0]) % g.C[1]), (int)((B / (g.C[0] * g.C[1])) % g.C[2]),
@@ -66,15 +86,30 @@ __device__ __forceinline__ void fine_hop(double2 (&f)[12], const Geom &g, uint32
 // projections onto the nv null vectors then load P_ki once per pass for all
 // slots of the pass (pass 0: slot 0 and directions x, y; pass 1: directions
 // z, t) instead of once per slot.
+//
+// Sum over the sites: for every ki each wavefront stages the KV per-site
+// terms of its 64 sites (re, im of both spin halves of each slot) in its own
+// LDS region, site-major, and 8 lanes per term add the 64 sites in a fixed
+// interleaved order and combine with 3 shuffle steps (8 LDS reads and 3
+// shuffles per term instead of a 6-step wavefront shuffle reduction).  The
+// exchange stays inside one wavefront, whose LDS operations complete in
+// issue order, so it needs no workgroup barrier; the per-wave results meet in
+// a fixed-order sum over the waves after the ki loop.
+constexpr int GF_KV = 20;  // terms per site and ki, pass 0 (5 slots x 4)
+constexpr int GF_LD = 72;  // row stride of a wave's term rows (64 sites + 8)
+
 template <int PASS>
 __device__ __forceinline__ void galerkin_pass(const Geom &g, uint32_t s, const Coords &k, bool act, int chi,
                                               double diag, const double2 *__restrict__ U,
                                               const double2 *__restrict__ Pj, const double2 *__restrict__ P,
-                                              int nv, int jcol, int n, uint32_t ic, double2 (*part)[2 * COARSE_NMAX],
-                                              double2 *__restrict__ Lc) {
+                                              int nv, int jcol, int n, uint32_t ic, double *red,
+                                              double2 (*part)[COARSE_NMAX], double2 *__restrict__ Lc) {
   constexpr int NS = PASS == 0 ? 3 : 2;  // vectors of this pass: [slot0,] mu, mu + 1
   constexpr int MU0 = PASS == 0 ? 0 : 2;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = (blockDim.x + 63) >> 6;
+  constexpr int NSLOT = PASS == 0 ? 5 : 4;
+  constexpr int KV = 4 * NSLOT;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = (int)(blockDim.x >> 6);
+  double *rw = red + w * GF_KV * GF_LD;
   const size_t V = g.Vpad;
   double2 f[NS][12];
   bool up[NS];
@@ -109,8 +144,6 @@ __device__ __forceinline__ void galerkin_pass(const Geom &g, uint32_t s, const C
       }
     }
   }
-  // slots of this pass: slot 0 (pass 0), then (up, down) per direction
-  constexpr int NSLOT = PASS == 0 ? 5 : 4;
   for (int ki = 0; ki < nv; ++ki) {
     const double2 *Pi = P + (size_t)ki * 12 * V;
     double2 pi[12];
@@ -127,9 +160,10 @@ __device__ __forceinline__ void galerkin_pass(const Geom &g, uint32_t s, const C
       dv[q][0] = d0;
       dv[q][1] = d1;
     }
+    // this site's term of each slot: term 4 sl + (0, 1, 2, 3) = (re, im) of
+    // the upper-half row ki, then of the lower-half row nv + ki
 #pragma unroll
     for (int sl = 0; sl < NSLOT; ++sl) {
-      // value of slot sl for this lane
       double2 v0, v1;
       if (PASS == 0 && sl == 0) {
         v0 = dv[0][0];
@@ -141,12 +175,30 @@ __device__ __forceinline__ void galerkin_pass(const Geom &g, uint32_t s, const C
         v0 = mine ? dv[qi][0] : make_double2(0, 0);
         v1 = mine ? dv[qi][1] : make_double2(0, 0);
       }
-      const double a0 = wave_sum(v0.x), b0 = wave_sum(v0.y), a1 = wave_sum(v1.x), b1 = wave_sum(v1.y);
-      if (lane == 0) {
-        part[w * NSLOT + sl][ki] = make_double2(a0, b0);
-        part[w * NSLOT + sl][nv + ki] = make_double2(a1, b1);
+      rw[(4 * sl + 0) * GF_LD + lane] = v0.x;
+      rw[(4 * sl + 1) * GF_LD + lane] = v0.y;
+      rw[(4 * sl + 2) * GF_LD + lane] = v1.x;
+      rw[(4 * sl + 3) * GF_LD + lane] = v1.y;
+    }
+    __builtin_amdgcn_wave_barrier();
+    // 8 consecutive lanes per term (a group never straddles an iteration);
+    // lane p adds sites p, p + 8, ..., p + 56 of this wave
+    for (int o = lane; o < KV * 8; o += 64) {
+      const int term = o >> 3, p = o & 7;
+      const double *row = rw + term * GF_LD;
+      double a = 0.0;
+#pragma unroll
+      for (int j = 0; j < 64; j += 8) a += row[j + p];
+      a += __shfl_xor(a, 4, 64);
+      a += __shfl_xor(a, 2, 64);
+      a += __shfl_xor(a, 1, 64);
+      if (p == 0) {
+        const int sl = term >> 2, e = term & 3;
+        double *r = reinterpret_cast<double *>(&part[w * NSLOT + sl][(e < 2 ? 0 : nv) + ki]);
+        r[e & 1] = a;
       }
     }
+    __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
   for (int o = tid; o < NSLOT * n; o += blockDim.x) {
@@ -162,12 +214,16 @@ __device__ __forceinline__ void galerkin_pass(const Geom &g, uint32_t s, const C
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_galerkin_fine(Geom g, Geom gc, double diag, const double2 *__restrict__ U,
-                                                       int nv, const double2 *__restrict__ P,
-                                                       double2 *__restrict__ Lc) {
-  __shared__ double2 part[4 * 5][2 * COARSE_NMAX];
-  const uint32_t B = blockIdx.x;
-  const int jcol = blockIdx.y, chi = jcol / nv, kj = jcol % nv;
+// At most 256 VGPRs so that two workgroups share a CU (a handful of spills).
+__global__ __launch_bounds__(256, 2) void k_galerkin_fine(Geom g, Geom gc, double diag,
+                                                          const double2 *__restrict__ U, int nv,
+                                                          const double2 *__restrict__ P, double2 *__restrict__ Lc) {
+  __shared__ double red[4 * GF_KV * GF_LD];
+  __shared__ double2 part[4 * 5][COARSE_NMAX];
+  uint32_t B;
+  int jcol;
+  agg_col_of(blockIdx.x, g.Vc, 2 * nv, B, jcol);
+  const int chi = jcol / nv, kj = jcol % nv;
   const int n = 2 * nv;
   const int tid = threadIdx.x;
   const bool act = (uint32_t)tid < g.vb;
@@ -175,8 +231,8 @@ __global__ __launch_bounds__(256) void k_galerkin_fine(Geom g, Geom gc, double d
   const Coords k = decode(g, s);
   const double2 *Pj = P + (size_t)kj * 12 * g.Vpad;
   const uint32_t ic = coarse_site_of(gc, B, g);
-  galerkin_pass<0>(g, s, k, act, chi, diag, U, Pj, P, nv, jcol, n, ic, part, Lc);
-  galerkin_pass<1>(g, s, k, act, chi, diag, U, Pj, P, nv, jcol, n, ic, part, Lc);
+  galerkin_pass<0>(g, s, k, act, chi, diag, U, Pj, P, nv, jcol, n, ic, red, part, Lc);
+  galerkin_pass<1>(g, s, k, act, chi, diag, U, Pj, P, nv, jcol, n, ic, red, part, Lc);
 }
 
 // Any aggregate shape (also one site wide in some direction, where a site
@@ -186,8 +242,10 @@ __global__ __launch_bounds__(256) void k_galerkin_fine_generic(Geom g, Geom gc, 
                                                        double2 *__restrict__ Lc) {
   __shared__ double2 part[4][2 * COARSE_NMAX];
   const size_t V = g.Vpad;
-  const uint32_t B = blockIdx.x;
-  const int jcol = blockIdx.y, chi = jcol / nv, kj = jcol % nv;
+  uint32_t B;
+  int jcol;
+  agg_col_of(blockIdx.x, g.Vc, 2 * nv, B, jcol);
+  const int chi = jcol / nv, kj = jcol % nv;
   const int n = 2 * nv;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = (blockDim.x + 63) >> 6;
   const bool act = (uint32_t)tid < g.vb;
@@ -248,32 +306,37 @@ hipError_t galerkin_fine(const Geom &g, const Geom &gc, double mass, const doubl
   const int th = (int)((g.vb + 63) / 64 * 64);
   const bool wide = g.b[0] > 1 && g.b[1] > 1 && g.b[2] > 1 && g.b[3] > 1;
   if (wide)
-    hipLaunchKernelGGL(k_galerkin_fine, dim3(g.Vc, 2 * nv), dim3(th), 0, st, g, gc, 4.0 + mass, U, nv, P, Lc);
+    hipLaunchKernelGGL(k_galerkin_fine, dim3(g.Vc * 2 * nv), dim3(th), 0, st, g, gc, 4.0 + mass, U, nv, P, Lc);
   else
-    hipLaunchKernelGGL(k_galerkin_fine_generic, dim3(g.Vc, 2 * nv), dim3(th), 0, st, g, gc, 4.0 + mass, U, nv, P,
+    hipLaunchKernelGGL(k_galerkin_fine_generic, dim3(g.Vc * 2 * nv), dim3(th), 0, st, g, gc, 4.0 + mass, U, nv, P,
                        Lc);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ coarse
-constexpr int GC_EMAX = 8;
-
-__global__ __launch_bounds__(256) void k_galerkin_coarse(Geom g, Geom gc, int n, const double2 *__restrict__ L1,
+// EM elements per thread (256 threads): 4 when the aggregate has at most
+// 1024 elements (fewer registers, two workgroups per CU), else 8.
+template <int EM>
+__global__ __launch_bounds__(256, EM == 4 ? 2 : 1) void k_galerkin_coarse(Geom g, Geom gc, int n, const double2 *__restrict__ L1,
                                                          int nv, const double2 *__restrict__ P,
                                                          double2 *__restrict__ Lc) {
-  __shared__ double2 part[4][2 * COARSE_NMAX];
+  constexpr int KB = 4;  // null vectors per wave-local reduction round
+  __shared__ double red[4 * 4 * KB * GF_LD];
+  __shared__ double2 part[4][COARSE_NMAX];
   const size_t V = g.V;
-  const uint32_t B = blockIdx.x;
-  const int jcol = blockIdx.y, chi = jcol / nv, kj = jcol % nv;
+  uint32_t B;
+  int jcol;
+  agg_col_of(blockIdx.x, g.Vc, 2 * nv, B, jcol);
+  const int chi = jcol / nv, kj = jcol % nv;
   const int nc = 2 * nv, half = n >> 1;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = (blockDim.x + 63) >> 6;
   const int ne = (int)g.vb * n;
   const double2 *Pj = P + (size_t)kj * V * n;
   const uint32_t ic = coarse_site_of(gc, B, g);
   for (int slot = 0; slot < 9; ++slot) {
-    double2 f[GC_EMAX];
+    double2 f[EM];
 #pragma unroll
-    for (int q = 0; q < GC_EMAX; ++q) {
+    for (int q = 0; q < EM; ++q) {
       f[q] = make_double2(0, 0);
       const int e = tid + q * (int)blockDim.x;
       if (e >= ne) continue;
@@ -302,22 +365,45 @@ __global__ __launch_bounds__(256) void k_galerkin_coarse(Geom g, Geom gc, int n,
         f[q] = a;
       }
     }
-    for (int ki = 0; ki < nv; ++ki) {
-      const double2 *Pi = P + (size_t)ki * V * n + (size_t)B * g.vb * n;
-      double2 d0 = make_double2(0, 0), d1 = make_double2(0, 0);
+    // projections onto KB null vectors at a time; the sum over this wave's
+    // elements is the wave-local LDS reduction of the fine kernel (4 KB
+    // terms: re, im of the upper- and lower-half rows of each null vector)
+    double *rw = red + w * 4 * KB * GF_LD;
+    for (int k0 = 0; k0 < nv; k0 += KB) {
 #pragma unroll
-      for (int q = 0; q < GC_EMAX; ++q) {
-        const int e = tid + q * (int)blockDim.x;
-        if (e < ne) {
-          if ((e % n) < half) d0 = cfmac(Pi[e], f[q], d0);
-          else d1 = cfmac(Pi[e], f[q], d1);
+      for (int u = 0; u < KB; ++u) {
+        const int ki = k0 + u;
+        double2 d0 = make_double2(0, 0), d1 = make_double2(0, 0);
+        if (ki < nv) {
+          const double2 *Pi = P + (size_t)ki * V * n + (size_t)B * g.vb * n;
+#pragma unroll
+          for (int q = 0; q < EM; ++q) {
+            const int e = tid + q * (int)blockDim.x;
+            if (e < ne) {
+              if ((e % n) < half) d0 = cfmac(Pi[e], f[q], d0);
+              else d1 = cfmac(Pi[e], f[q], d1);
+            }
+          }
         }
+        rw[(4 * u + 0) * GF_LD + lane] = d0.x;
+        rw[(4 * u + 1) * GF_LD + lane] = d0.y;
+        rw[(4 * u + 2) * GF_LD + lane] = d1.x;
+        rw[(4 * u + 3) * GF_LD + lane] = d1.y;
       }
-      const double a0 = wave_sum(d0.x), b0 = wave_sum(d0.y), a1 = wave_sum(d1.x), b1 = wave_sum(d1.y);
-      if (lane == 0) {
-        part[w][ki] = make_double2(a0, b0);
-        part[w][nv + ki] = make_double2(a1, b1);
+      __builtin_amdgcn_wave_barrier();
+      for (int o = lane; o < 4 * KB * 8; o += 64) {
+        const int term = o >> 3, p = o & 7;
+        const double *row = rw + term * GF_LD;
+        double a = 0.0;
+#pragma unroll
+        for (int j = 0; j < 64; j += 8) a += row[j + p];
+        a += __shfl_xor(a, 4, 64);
+        a += __shfl_xor(a, 2, 64);
+        a += __shfl_xor(a, 1, 64);
+        const int ki = k0 + (term >> 2), e = term & 3;
+        if (p == 0 && ki < nv) reinterpret_cast<double *>(&part[w][(e < 2 ? 0 : nv) + ki])[e & 1] = a;
       }
+      __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
     if (tid < nc) {
@@ -334,7 +420,10 @@ __global__ __launch_bounds__(256) void k_galerkin_coarse(Geom g, Geom gc, int n,
 
 hipError_t galerkin_coarse(const Geom &g, const Geom &gc, int n, const double2 *L1, int nv, const double2 *P,
                            double2 *Lc, hipStream_t st) {
-  hipLaunchKernelGGL(k_galerkin_coarse, dim3(g.Vc, 2 * nv), dim3(256), 0, st, g, gc, n, L1, nv, P, Lc);
+  if (g.vb * n <= 4 * 256)
+    hipLaunchKernelGGL(k_galerkin_coarse<4>, dim3(g.Vc * 2 * nv), dim3(256), 0, st, g, gc, n, L1, nv, P, Lc);
+  else
+    hipLaunchKernelGGL(k_galerkin_coarse<8>, dim3(g.Vc * 2 * nv), dim3(256), 0, st, g, gc, n, L1, nv, P, Lc);
   return hipGetLastError();
 }
 

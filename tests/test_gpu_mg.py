@@ -329,6 +329,20 @@ def test_three_level(cuda):
     assert abs(info["iters"][0] - it_ref) <= 1
 
 
+def test_three_level_wide_coarse_aggregate(cuda):
+    """Level-1 aggregates of 4x2x2x2 sites with n = 34 components (1088
+    elements per aggregate): the coarse Galerkin build takes its eight
+    elements-per-thread form here (the other tests take the four-element
+    one)."""
+    three = ((16, 8, 8, 8), [(2, 2, 2, 2), (4, 2, 2, 2)], [17, 4], 0.3, -0.3, 4)
+    U, m, ctx, h = _build(None, three=three)
+    X2, Y2 = ctx.export_coarse_op(2)
+    l2 = h.levels[1]
+    e = max(_rel(X2, l2.X), _rel(Y2, l2.Y))
+    print(f"3-level, 4x2x2x2 coarse aggregates: D_c2 rel err {e:.2e}")
+    assert e < 1e-9
+
+
 _CYCLE_CASES = {
     "3-level 8^4": ((8, 8, 8, 8), [(2, 2, 2, 2), (2, 2, 2, 2)], [6, 4], 0.3, -0.3, 3),
     "2-level 8^4": CASES["8^4 b4^4 nv8"],
