@@ -141,6 +141,26 @@ def large_dslash(mgwd, torch):
                      "bytes_per_site": dslash_bytes(prec, True)}
     ctx.close()
     torch.cuda.empty_cache()
+    # What plain streaming reaches on this GPU: a device-to-device copy (a
+    # PyTorch kernel, timed on its own stream) of as many bytes as the FP64
+    # stencil reads and writes per launch.
+    nbytes = int(dslash_bytes("f64", compressed=True)) * V
+    src = torch.ones(nbytes // 16, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    copy_gbps = 2 * src.numel() * 8 / (e0.elapsed_time(e1) / 20 * 1e-3) / 1e9
+    out["copy_GBps"] = round(copy_gbps, 1)
+    for prec in ("f64", "f32", "f16"):
+        out[prec]["frac_copy"] = round(out[prec]["GBps"] / copy_gbps, 3)
+    del src, dst
+    torch.cuda.empty_cache()
     return out
 
 

@@ -28,7 +28,6 @@ namespace mg {
 
 constexpr int CO_CHUNK = 8;   // operator loads in flight per thread
 constexpr int CO_PARTS = 8;   // first-stage partial sums per row of the group reduction
-constexpr int CO_PF = 2;      // input elements per thread loaded ahead of the scalar sums
 
 // 16-byte (or 8-byte) load of RW consecutive operator entries in storage S.
 template <typename S, int RW> struct OpVec;
@@ -168,45 +167,19 @@ __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restri
   const int nu = n / RW;    // row units per column
   const VT *Ls = reinterpret_cast<const VT *>(L + (size_t)s * 9 * n * n + r0) + ip;
   // Issue the first chunk of operator loads before staging the input vectors
-  // so that the two memory phases overlap.
+  // so that the two memory phases overlap.  Every load is issued
+  // unconditionally (a lane without an entry of its own reads entry 0 and
+  // never uses it): a load under a lane mask gets a basic block of its own,
+  // where the compiler waits for it before the next one is issued.
   VT lv[CO_CHUNK];
   const bool on = grp < G;
 #pragma unroll
   for (int q = 0; q < CO_CHUNK; ++q) {
     const int p = grp + q * G;
-    lv[q] = (on && p < nP) ? Ls[(size_t)p * nu] : VT{};
+    lv[q] = Ls[(size_t)((on && p < nP) ? p : 0) * nu];
   }
-  // Then this thread's input elements (at most CO_PF of them: the thread
-  // counts of coarse_threads give 9 n <= 2 blockDim.x for every n <= 64):
-  // their loads are in flight while the scalars below are summed, so the
-  // two memory round trips of the launch overlap.
-  const C *fa = reinterpret_cast<const C *>(fz.a) + rhs_off;
-  const C *fb = reinterpret_cast<const C *>(fz.b) + rhs_off;
-  C *fe = reinterpret_cast<C *>(fz.e) + rhs_off;
-  const C *fp = reinterpret_cast<const C *>(fz.p) + rhs_off;
-  C xa[CO_PF], xb[CO_PF], xe[CO_PF], xp[CO_PF];
-  size_t xo[CO_PF];
-#pragma unroll
-  for (int u = 0; u < CO_PF; ++u) {
-    const int idx = tid + u * (int)blockDim.x;
-    xa[u] = xb[u] = xe[u] = xp[u] = mk<C>(0, 0);
-    xo[u] = 0;
-    if (idx < nP) {
-      const int slot = idx / n, j = idx - slot * n;
-      const size_t o = (size_t)slot_site(g, s, slot) * n + j;
-      xo[u] = o;
-      if (fz.kind == 0) {
-        xa[u] = in[o];
-      } else {
-        xa[u] = fa[o];
-        xb[u] = fb[o];
-        if (slot == 0 && fz.kind == 2) {
-          xe[u] = fe[o];
-          xp[u] = fp[o];
-        }
-      }
-    }
-  }
+  __shared__ uint32_t nbs[9];
+  if (tid < 9) nbs[tid] = slot_site(g, s, tid);
   // Scalars of this launch, summed from per-workgroup partials in one pass
   // (one round trip): the CGNR convergence test on the residual of the
   // update just made, and the fused update's coefficient.
@@ -246,36 +219,34 @@ __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restri
   }
   __syncthreads();
   double own_sq = 0.0;
-  const R sc = fz.kind == 1 ? coef : -coef;
-  // element idx of this thread from its prefetched values (pass < CO_PF) or
-  // loaded here (never reached at the thread counts launched)
-  auto stage = [&](int idx, int pass) {
-    const int slot = idx / n, j = idx - slot * n;
-    const size_t o = pass < CO_PF ? xo[pass] : (size_t)slot_site(g, s, slot) * n + j;
-    C v;
-    if (fz.kind == 0) {
-      v = pass < CO_PF ? xa[pass] : in[o];
-    } else {
-      const C va = pass < CO_PF ? xa[pass] : fa[o], vb = pass < CO_PF ? xb[pass] : fb[o];
-      v = cfma(mk<C>(sc, 0), vb, va);
+  if (fz.kind == 0) {
+    for (int idx = tid; idx < nP; idx += blockDim.x) {
+      const int slot = idx / n, j = idx - slot * n;
+      C v = in[(size_t)nbs[slot] * n + j];
+      if (dagger && j >= (n >> 1)) v = mk<C>(-v.x, -v.y);
+      vin[idx] = v;
+    }
+  } else {
+    const C *fa = reinterpret_cast<const C *>(fz.a) + rhs_off;
+    const C *fb = reinterpret_cast<const C *>(fz.b) + rhs_off;
+    const R sc = fz.kind == 1 ? coef : -coef;
+    for (int idx = tid; idx < nP; idx += blockDim.x) {
+      const int slot = idx / n, j = idx - slot * n;
+      const size_t o = (size_t)nbs[slot] * n + j;
+      C v = cfma(mk<C>(sc, 0), fb[o], fa[o]);
       if (slot == 0) {
         reinterpret_cast<C *>(fz.own)[rhs_off + o] = v;
         if (fz.kind == 2) {
-          const C ve = pass < CO_PF ? xe[pass] : fe[o], vp = pass < CO_PF ? xp[pass] : fp[o];
-          fe[o] = cfma(mk<C>(coef, 0), vp, ve);
+          C *e = reinterpret_cast<C *>(fz.e) + rhs_off;
+          const C *pp = reinterpret_cast<const C *>(fz.p) + rhs_off;
+          e[o] = cfma(mk<C>(coef, 0), pp[o], e[o]);
           own_sq += (double)v.x * v.x + (double)v.y * v.y;
         }
       }
+      if (dagger && j >= (n >> 1)) v = mk<C>(-v.x, -v.y);
+      vin[idx] = v;
     }
-    if (dagger && j >= (n >> 1)) v = mk<C>(-v.x, -v.y);
-    vin[idx] = v;
-  };
-#pragma unroll
-  for (int u = 0; u < CO_PF; ++u) {
-    const int idx = tid + u * (int)blockDim.x;
-    if (idx < nP) stage(idx, u);
   }
-  for (int idx = tid + CO_PF * (int)blockDim.x; idx < nP; idx += blockDim.x) stage(idx, CO_PF);
   __syncthreads();
   C acc[RW];
 #pragma unroll
@@ -285,7 +256,7 @@ __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restri
 #pragma unroll
       for (int q = 0; q < CO_CHUNK; ++q) {
         const int p = base + q * G;
-        lv[q] = p < nP ? Ls[(size_t)p * nu] : VT{};
+        lv[q] = Ls[(size_t)(p < nP ? p : 0) * nu];
       }
     }
 #pragma unroll
