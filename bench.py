@@ -414,15 +414,18 @@ def main():
     # average launch time therefore comes from the sample, and its bytes per
     # launch count only the effective applications among all dispatches
     # (dispatches queued after a right-hand side converged return at once).
+    # Stencil applications made inside whole-solve CGNR launches count as
+    # applications, not dispatches, and are left out of the per-launch class.
     agg = {}
     for inf in infos:
+        in_whole = sum(d["sites"] for k, d in inf["kernels"].items() if k.startswith("cgnr")) / Vc
         for k, d in inf["kernels"].items():
             e = agg.setdefault(k, {"ms": 0.0, "launches": 0, "sites": 0.0, "eff": 0.0})
             e["ms"] += d["ms"]
             e["launches"] += d["launches"]
             e["sites"] += d["sites"]
             if k.startswith("coarse") and d["launches"]:
-                e["eff"] += inf["n_coarse_apply"] / max(inf["n_coarse_dispatch"], 1) * d["launches"]
+                e["eff"] += (inf["n_coarse_apply"] - in_whole) / max(inf["n_coarse_dispatch"], 1) * d["launches"]
 
     def achieved(k):
         e = agg[k]
@@ -434,6 +437,15 @@ def main():
             # the workload links are SU(3), so the stencil reads them as two rows
             bpl = dslash_bytes(prec, True) * e["sites"] / e["launches"]
             fpl = dslash_flops(True) * e["sites"] / e["launches"]
+        elif k.startswith("cgnr"):
+            # one launch = one whole coarsest CGNR: the operator read once
+            # (then held in registers), and per iteration and site the FP32
+            # vectors of both phases (reads z, p_old, r_old, w, p, e; writes
+            # p, w, r, z, e: 11 n complex) plus five partial sums
+            apps = e["sites"] / Vc / e["launches"]  # stencil applications per launch
+            wv, wl = WIDTH[prec]
+            bpl = (2 * 9 * n_c * n_c * wl + (apps / 2) * (11 * n_c * 2 * wv + 5 * 8)) * Vc
+            fpl = coarse_flops(n_c) * Vc * apps
         else:
             frac = e["eff"] / e["launches"]
             bpl = coarse_bytes(n_c, prec) * Vc * frac

@@ -121,7 +121,9 @@ typedef struct {
   int n_coarse_apply;           /* coarse stencil applications, all levels   */
   int n_coarse_dispatch;        /* coarse stencil applications dispatched,
                                    including those that returned at once
-                                   because their RHS had converged        */
+                                   because their RHS had converged (those
+                                   inside a whole-solve CGNR launch are
+                                   applications, not dispatches)          */
   int n_cgnr_iters;             /* coarsest CGNR iterations, summed          */
   int n_vcycles;                /* preconditioner applications               */
   double t_setup_s, t_solve_s;  /* wall time of the last setup / solve       */
@@ -130,10 +132,13 @@ typedef struct {
    * kernel class 2 p + k: p = 0 FP64, 1 FP32, 2 FP16-stored operators with
    * FP32 arithmetic; k = 0 fine stencil, 1 coarse stencil (all coarse
    * levels).  Launch counts include dispatches that returned early because
-   * their right-hand side had converged.                                   */
-  double kernel_ms[6];
-  int kernel_launches[6];
-  double kernel_sites[6];
+   * their right-hand side had converged.  Classes 6 and 7: the whole-solve
+   * coarsest CGNR launches (mg_set_cgnr_persistent) with the FP32 and the
+   * FP16-stored operator, one launch per coarsest solve, sites = coarse
+   * sites x stencil applications inside the launches.                     */
+  double kernel_ms[8];
+  int kernel_launches[8];
+  double kernel_sites[8];
 } mg_info_t;
 
 /* Fine Wilson operator out = D(U) in (Eq. 2) on nrhs canonical spinors.
@@ -262,6 +267,18 @@ int mg_transfer_variant(mg_ctx_t *ctx, mg_prec_t prec, int nrhs,
 int mg_set_coarse_variant(mg_ctx_t *ctx, int variant);
 int mg_coarse_variant(mg_ctx_t *ctx, int level, mg_prec_t prec, int nrhs,
                       int *variant, double *us);
+
+/* Coarsest-level CGNR of a single right-hand side (paper, "Numerical
+ * Results": CG on the normal equations to 10^-3 on the coarsest grid) in
+ * the FP32 and FP16-storage preconditioners: on (default), all iterations
+ * run in one cooperative launch that keeps each coarse site's operator rows
+ * in registers and joins its two stencil phases per iteration with grid
+ * barriers; off, they run as chunks of captured per-iteration launches.
+ * Both forms do the same arithmetic in the same order (same iterates, same
+ * iteration counts).  Where the device cannot hold the whole coarse grid at
+ * once (or the operator rows do not fit), the chunks run regardless.
+ * MG_EINVAL on a NULL context.                                             */
+int mg_set_cgnr_persistent(mg_ctx_t *ctx, int on);
 
 /* Solve D x = b for nrhs canonical spinors (DEVICE complex128) with
  * flexible GCR(gcr_restart) preconditioned by one MG V-cycle (MR pre/post

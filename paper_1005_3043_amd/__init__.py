@@ -22,7 +22,7 @@ MAX_LEVELS = 3
 MAX_RHS = 16
 
 EXPORTED = ["wilson_apply", "mg_setup", "mg_set_precond_prec", "mg_set_mass", "mg_set_timing", "mg_restrict",
-            "mg_prolong", "coarse_apply", "mg_apply_op", "mg_vcycle", "mg_transfer", "mg_set_transfer_variant", "mg_transfer_variant", "mg_set_coarse_variant", "mg_coarse_variant", "mg_solve", "mg_time_dslash", "mg_time_coarse",
+            "mg_prolong", "coarse_apply", "mg_apply_op", "mg_vcycle", "mg_transfer", "mg_set_transfer_variant", "mg_transfer_variant", "mg_set_coarse_variant", "mg_coarse_variant", "mg_set_cgnr_persistent", "mg_solve", "mg_time_dslash", "mg_time_coarse",
             "mg_destroy", "mg_last_error", "mg_export_maps", "mg_export_P",
             "mg_export_coarse_op", "mg_export_nullvecs", "mg_level_info",
             "ptc_create", "ptc_set_links", "ptc_set_targets", "ptc_forward", "ptc_loss_grad", "ptc_adam",
@@ -68,11 +68,12 @@ class Info(ctypes.Structure):
                 ("n_cgnr_iters", ctypes.c_int),
                 ("n_vcycles", ctypes.c_int),
                 ("t_setup_s", ctypes.c_double), ("t_solve_s", ctypes.c_double),
-                ("kernel_ms", ctypes.c_double * 6),
-                ("kernel_launches", ctypes.c_int * 6),
-                ("kernel_sites", ctypes.c_double * 6)]
+                ("kernel_ms", ctypes.c_double * 8),
+                ("kernel_launches", ctypes.c_int * 8),
+                ("kernel_sites", ctypes.c_double * 8)]
 
-    KERNELS = ("dslash_f64", "coarse_f64", "dslash_f32", "coarse_f32", "dslash_f16", "coarse_f16")
+    KERNELS = ("dslash_f64", "coarse_f64", "dslash_f32", "coarse_f32", "dslash_f16", "coarse_f16", "cgnr_f32",
+               "cgnr_f16")
 
     def as_dict(self, nrhs=1):
         return dict(iters=list(self.iters[:nrhs]), rel_resid=list(self.rel_resid[:nrhs]),
@@ -110,6 +111,7 @@ def lib():
             "mg_set_transfer_variant": [vp, ci],
             "mg_transfer_variant": [vp, ci, ci, ctypes.POINTER(ci), ctypes.POINTER(ci), ctypes.POINTER(cd)],
             "mg_set_coarse_variant": [vp, ci],
+            "mg_set_cgnr_persistent": [vp, ci],
             "mg_coarse_variant": [vp, ci, ci, ci, ctypes.POINTER(ci), ctypes.POINTER(cd)],
             "mg_solve": [vp, vp, vp, ci, cd, ctypes.POINTER(Info), vp],
             "mg_time_dslash": [vp, ci, ci, ci, ctypes.POINTER(cd), vp],
@@ -315,6 +317,11 @@ class MG:
         """Force the coarse-stencil kernel (0 per-RHS, 1/2/4 matrix-core GEMM
         with that K split) or restore autotuning (-1)."""
         _check(lib().mg_set_coarse_variant(self.ctx, int(variant)))
+
+    def set_cgnr_persistent(self, on):
+        """Single-RHS coarsest CGNR as one cooperative launch (True, default)
+        or as chunks of per-iteration launches (False); same arithmetic."""
+        _check(lib().mg_set_cgnr_persistent(self.ctx, 1 if on else 0))
 
     def coarse_variant(self, level=1, prec="f32", nrhs=1):
         v, us = ctypes.c_int(), ctypes.c_double()

@@ -173,6 +173,12 @@ extern "C" int mg_set_timing(mg_ctx_t *ctx, int on) {
   return MG_OK;
 }
 
+extern "C" int mg_set_cgnr_persistent(mg_ctx_t *ctx, int on) {
+  if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
+  ctx->cg_persist = on ? 1 : 0;
+  return MG_OK;
+}
+
 extern "C" int mg_set_coarse_variant(mg_ctx_t *ctx, int variant) {
   if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
   if (variant != -1 && variant != 0 && variant != 1 && variant != 2 && variant != 4 && variant != 9 &&
@@ -405,7 +411,7 @@ extern "C" int mg_solve(mg_ctx_t *ctx, const void *b, void *x, int nrhs, double 
     info->t_setup_s = c->t_setup;
     info->t_solve_s = t1 - t0;
     if (c->timing) {
-      for (int k = 0; k < 6; ++k) {
+      for (int k = 0; k < 8; ++k) {
         info->kernel_ms[k] = c->tm[k].ms;
         info->kernel_launches[k] = (int)c->tm[k].launches;
         info->kernel_sites[k] = c->tm[k].sites;

@@ -318,6 +318,286 @@ __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restri
   }
 }
 
+// ------------------------------------------------------------ persistent CGNR
+// The whole coarsest-level CGNR of one right-hand side in one cooperative
+// launch: the fused two-phase iteration of k_coarse (phase 1: p = z + beta
+// p_old staged, w = A p; phase 2: r = r_old - alpha w staged, e += alpha p,
+// z = A^dag r) with a grid-wide barrier after each phase instead of a kernel
+// boundary.  Each workgroup (one coarse site) loads its operator rows once
+// into registers and keeps them for every iteration; a kernel boundary would
+// drop the L2 and fetch the operator again.  Every workgroup computes the
+// same scalars from the same partials in the same order, so all of them take
+// the same exit.  A barrier wait is bounded: a workgroup that gives up sets
+// *fail and leaves, so the grid always drains.
+constexpr int CGP_PMAX = 16;          // most operator entries per thread kept in registers
+constexpr unsigned CGP_SPIN = 1u << 20;  // barrier polls before giving up
+
+// Data exchanged between workgroups inside the launch (vectors and partial
+// sums) is read and written as agent-scope relaxed atomics: the loads skip
+// the XCD's non-coherent L2 and the stores write through it, so a barrier
+// needs only each thread's stores acknowledged before its arrival, and no
+// L2 write-back or invalidation (which cost about 80 us per barrier here).
+__device__ __forceinline__ float2 cld(const float2 *p) {
+  const unsigned long long v = __hip_atomic_load(reinterpret_cast<unsigned long long *>(const_cast<float2 *>(p)),
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  float2 r;
+  __builtin_memcpy(&r, &v, sizeof(r));
+  return r;
+}
+__device__ __forceinline__ void cst(float2 *p, float2 v) {
+  unsigned long long u;
+  __builtin_memcpy(&u, &v, sizeof(u));
+  __hip_atomic_store(reinterpret_cast<unsigned long long *>(p), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double cldd(const double *p) {
+  const unsigned long long v = __hip_atomic_load(reinterpret_cast<unsigned long long *>(const_cast<double *>(p)),
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  double r;
+  __builtin_memcpy(&r, &v, sizeof(r));
+  return r;
+}
+__device__ __forceinline__ void cstd(double *p, double v) {
+  unsigned long long u;
+  __builtin_memcpy(&u, &v, sizeof(u));
+  __hip_atomic_store(reinterpret_cast<unsigned long long *>(p), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// block_allsum3 over partials written inside the launch (same order).
+__device__ __forceinline__ void cgp_allsum3(const double *__restrict__ a, int na, const double *__restrict__ b,
+                                            const double *__restrict__ c, int nb, double (&out)[3], double *lds) {
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < na; i += blockDim.x) v[0] += cldd(a + i);
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    v[1] += cldd(b + i);
+    v[2] += cldd(c + i);
+  }
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) v[q] = wave_sum(v[q]);
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) lds[w * 3 + q] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    double t = 0.0;
+    for (int k = 0; k < nw; ++k) t += lds[k * 3 + q];
+    out[q] = t;
+  }
+  __syncthreads();
+}
+
+// Arrivals are spread over CGP_NC counters on separate 256-byte lines
+// (workgroup i counts on i mod CGP_NC), so that no single address takes
+// every workgroup's atomic; the first wavefront polls all of them at once.
+constexpr int CGP_NC = CGP_BAR_WORDS / 64;
+__device__ __forceinline__ bool cgp_barrier(unsigned *bar, unsigned target, int *fail, int *lds_ok) {
+  __builtin_amdgcn_s_waitcnt(0);  // this thread's stores acknowledged
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    if (lane == 0)
+      __hip_atomic_fetch_add(bar + (blockIdx.x % CGP_NC) * 64, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    unsigned spins = 0;
+    for (;;) {
+      unsigned v = lane < CGP_NC ? __hip_atomic_load(bar + lane * 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+      v = wave_sum(v);
+      if (v >= target) break;
+      if (++spins > CGP_SPIN) {
+        ok = 0;
+        if (lane == 0) __hip_atomic_store(fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (lane == 0) *lds_ok = ok;
+  }
+  __syncthreads();
+  return *lds_ok != 0;
+}
+
+template <typename S, int RW, int PM>
+__global__ __launch_bounds__(512, 4) void k_cgnr_persistent(Geom g, int n, const S *__restrict__ L, CgPersist a) {
+  using C = float2;
+  using VT = typename OpVec<S, RW>::V;
+  __shared__ C vin[9 * COARSE_NMAX];
+  __shared__ C red[512 * RW];
+  __shared__ C red2[CO_PARTS * COARSE_NMAX];
+  __shared__ double wred[8 * 4];
+  __shared__ uint32_t nbs[9];
+  __shared__ int bar_ok;
+  const uint32_t s = blockIdx.x, nblk = gridDim.x;
+  const int tid = threadIdx.x;
+  const int npr = n / RW, G = (int)blockDim.x / npr;
+  const int ip = tid % npr, grp = tid / npr;
+  const int nP = 9 * n, half = n >> 1;
+  const bool on = grp < G;
+  const VT *Ls = reinterpret_cast<const VT *>(L + (size_t)s * 9 * n * n) + ip;
+  VT lv[PM];
+#pragma unroll
+  for (int q = 0; q < PM; ++q) {
+    const int p = grp + q * G;
+    lv[q] = Ls[(size_t)((on && p < nP) ? p : 0) * n / RW];
+  }
+  if (tid < 9) nbs[tid] = slot_site(g, s, tid);
+  __syncthreads();
+  const double tol2b2 = a.cg[4] * a.cg[3];
+  unsigned round = 0;
+  int k = 0, final_it = 0;
+  // rows of this workgroup times the staged vector, summed over the groups in
+  // the fixed two-stage order of k_coarse; returns the row sum (tid < n)
+  auto apply = [&]() -> C {
+    C acc[RW];
+#pragma unroll
+    for (int t = 0; t < RW; ++t) acc[t] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int q = 0; q < PM; ++q) {
+      const int p = grp + q * G;
+      if (on && p < nP) {
+        const C x = vin[p];
+        C o[RW];
+        OpVec<S, RW>::get(lv[q], o);
+#pragma unroll
+        for (int t = 0; t < RW; ++t) acc[t] = cfma(o[t], x, acc[t]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < RW; ++t) red[tid * RW + t] = acc[t];
+    __syncthreads();
+    if (tid < n * CO_PARTS) {
+      const int i = tid % n, part = tid / n;
+      const int ipr = i / RW, sub = i % RW;
+      C sum = make_float2(0.f, 0.f);
+      for (int q = part; q < G; q += CO_PARTS) sum = cadd(sum, red[(q * npr + ipr) * RW + sub]);
+      red2[part * COARSE_NMAX + i] = sum;
+    }
+    __syncthreads();
+    C sum = make_float2(0.f, 0.f);
+    if (tid < n) {
+      sum = red2[tid];
+#pragma unroll
+      for (int q = 1; q < CO_PARTS; ++q) sum = cadd(sum, red2[q * COARSE_NMAX + tid]);
+    }
+    return sum;
+  };
+  for (;;) {
+    // ---- phase 1: convergence test of the last update, p = z + beta p_old, w = A p
+    float2 *pn = a.p[k & 1];
+    const float2 *po = a.p[(k + 1) & 1];
+    double sums[3];
+    cgp_allsum3(a.pr, k > 0 ? (int)nblk : 0, a.pz[k & 1], a.pz[(k + 1) & 1], k > 0 ? (int)nblk : 0, sums, wred);
+    if ((k > 0 && !(sums[0] > tol2b2)) || k >= a.maxit) {
+      final_it = k;
+      break;
+    }
+    const float beta = (k > 0 && sums[2] > 0.0) ? (float)(sums[1] / sums[2]) : 0.f;
+    for (int idx = tid; idx < nP; idx += blockDim.x) {
+      const int slot = idx / n, j = idx - slot * n;
+      const size_t o = (size_t)nbs[slot] * n + j;
+      const C v = cfma(make_float2(beta, 0.f), cld(po + o), cld(a.z + o));
+      if (slot == 0) cst(pn + o, v);
+      vin[idx] = v;
+    }
+    __syncthreads();
+    {
+      const C wv = apply();
+      double t2 = 0.0;
+      if (tid < n) {
+        cst(a.w + (size_t)s * n + tid, wv);
+        t2 = (double)wv.x * wv.x + (double)wv.y * wv.y;
+      }
+      double v4[4] = {0.0, 0.0, t2, 0.0};
+      block_sum<4>(v4, wred);
+      if (tid == 0) cstd(a.pw + s, v4[2]);
+    }
+    if (!cgp_barrier(a.bar, ++round * nblk, a.fail, &bar_ok)) {
+      final_it = k;
+      break;
+    }
+    // ---- phase 2: r = r_old - alpha w, e += alpha p, z = A^dag r
+    const float2 *ro = a.r[k & 1];
+    float2 *rn = a.r[(k + 1) & 1];
+    cgp_allsum3(nullptr, 0, a.pz[k & 1], a.pw, (int)nblk, sums, wred);
+    if (!(sums[2] > 0.0)) {
+      final_it = k + 1;
+      break;
+    }
+    const float alpha = (float)(sums[1] / sums[2]);
+    double own_sq = 0.0;
+    for (int idx = tid; idx < nP; idx += blockDim.x) {
+      const int slot = idx / n, j = idx - slot * n;
+      const size_t o = (size_t)nbs[slot] * n + j;
+      C v = cfma(make_float2(-alpha, 0.f), cld(a.w + o), cld(ro + o));
+      if (slot == 0) {
+        cst(rn + o, v);
+        a.e[o] = cfma(make_float2(alpha, 0.f), cld(pn + o), a.e[o]);
+        own_sq += (double)v.x * v.x + (double)v.y * v.y;
+      }
+      if (j >= half) v = make_float2(-v.x, -v.y);
+      vin[idx] = v;
+    }
+    __syncthreads();
+    {
+      C zv = apply();
+      double t2 = 0.0;
+      if (tid < n) {
+        if (tid >= half) zv = make_float2(-zv.x, -zv.y);
+        cst(a.z + (size_t)s * n + tid, zv);
+        t2 = (double)zv.x * zv.x + (double)zv.y * zv.y;
+      }
+      double v4[4] = {0.0, 0.0, t2, own_sq};
+      block_sum<4>(v4, wred);
+      if (tid == 0) {
+        cstd(a.pz[(k + 1) & 1] + s, v4[2]);
+        cstd(a.pr + s, v4[3]);
+      }
+    }
+    ++k;
+    if (!cgp_barrier(a.bar, ++round * nblk, a.fail, &bar_ok)) {
+      final_it = k;
+      break;
+    }
+  }
+  if (s == 0 && tid == 0) {
+    a.it[0] = final_it;
+    a.it[1] = final_it;
+    a.done[0] = 1;
+  }
+}
+
+template <typename S>
+hipError_t cgnr_persistent(const Geom &g, int n, const S *L, const CgPersist &a, hipStream_t st) {
+  const int rs = coarse_split(n, g.V);
+  if (rs != 1 || n > COARSE_NMAX) return hipErrorInvalidValue;
+  const int th = coarse_threads(n, g.V);
+  const bool rw4 = sizeof(S) == 4 && n % 4 == 0;
+  const int RW = sizeof(S) == 4 ? (rw4 ? 4 : 2) : 2;
+  const int G = th / (n / RW);
+  if ((9 * n + G - 1) / G > CGP_PMAX || th > 512 || 9 * n > 2 * th) return hipErrorInvalidValue;
+  CgPersist args = a;
+  Geom gg = g;
+  const S *LL = L;
+  int nn = n;
+  void *kargs[] = {&gg, &nn, &LL, &args};
+  // entries per thread decide the register array: 8 where they fit
+  const bool p8 = (9 * n + G - 1) / G <= 8;
+  const void *fn;
+  if constexpr (sizeof(S) == 4) {
+    if (rw4 && !p8) return hipErrorInvalidValue;  // 16 four-row entries would spill
+    if (rw4) fn = reinterpret_cast<const void *>(&k_cgnr_persistent<S, 4, 8>);
+    else fn = p8 ? reinterpret_cast<const void *>(&k_cgnr_persistent<S, 2, 8>)
+                 : reinterpret_cast<const void *>(&k_cgnr_persistent<S, 2, 16>);
+  } else {
+    fn = p8 ? reinterpret_cast<const void *>(&k_cgnr_persistent<S, 2, 8>)
+            : reinterpret_cast<const void *>(&k_cgnr_persistent<S, 2, 16>);
+  }
+  return hipLaunchCooperativeKernel(fn, dim3(g.V), dim3(th), kargs, 0, st);
+}
+template hipError_t cgnr_persistent<chalf>(const Geom &, int, const chalf *, const CgPersist &, hipStream_t);
+template hipError_t cgnr_persistent<float2>(const Geom &, int, const float2 *, const CgPersist &, hipStream_t);
+
 // ------------------------------------------------------------ matrix cores
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 

@@ -97,6 +97,29 @@ struct CgFuse {
   int *done_w = nullptr;
   const int *it0 = nullptr;
 };
+// Whole coarsest-level CGNR of one right-hand side in one cooperative
+// launch (FP32 arithmetic): the state the chunked fused iteration starts from
+// (e = 0, r[0] = b, p[1] = 0, z = A^dag b with its partials in pz[0], cg from
+// cg2_init), the same two phases per iteration with a grid barrier between
+// them, and on exit it[0] = it[1] = iterations, done[0] = 1.  bar (zero on
+// entry, CGP_BAR_WORDS words) counts barrier arrivals; *fail is set when a
+// barrier wait gave up.
+// Returns an error without launching when the shape does not suit the
+// kernel, and the cooperative launch's error when the grid cannot be
+// co-resident; the caller then takes the chunked path.
+constexpr int CGP_BAR_WORDS = 64 * 64;  // barrier counters: 64, one per 256-byte line
+struct CgPersist {
+  float2 *e = nullptr, *z = nullptr, *w = nullptr;
+  float2 *p[2] = {nullptr, nullptr}, *r[2] = {nullptr, nullptr};
+  double *pz[2] = {nullptr, nullptr}, *pw = nullptr, *pr = nullptr;
+  const double *cg = nullptr;
+  int *it = nullptr, *done = nullptr;
+  int maxit = 0;
+  unsigned *bar = nullptr;
+  int *fail = nullptr;
+};
+template <typename S>
+hipError_t cgnr_persistent(const Geom &g, int n, const S *L, const CgPersist &a, hipStream_t st);
 // Reduction outputs and options of the coarse stencil.
 //  part/pw: when part != nullptr each workgroup writes pw doubles at
 //    part[(rhs * nwg + wg) * pw] (nwg = workgroups per right-hand side = V):

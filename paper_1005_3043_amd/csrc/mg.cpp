@@ -662,6 +662,85 @@ ChunkGraph *chunk_graph(mg_ctx *c, int l, vec_t<P> *e, int nrhs, int var, bool f
   return g;
 }
 
+// The iterations of the fused CGNR of one right-hand side as one cooperative
+// launch (FP32 arithmetic, same arithmetic and iteration count as the chunked
+// path), from the state the chunks start from.  ran = false, and nothing is
+// launched, when the shape or the device cannot take it; the caller then
+// runs the chunks.
+template <typename P> int cgnr_whole(mg_ctx *c, int l, vec_t<P> *e, hipStream_t st, bool &ran) {
+  ran = false;
+  using R = typename P::R;
+  if constexpr (sizeof(R) == 8) {
+    return MG_OK;
+  } else {
+    using S = typename P::S;
+    const int pc = P::id;
+    if (c->cgp_off[l][pc]) return MG_OK;
+    Level &L = c->lev[l];
+    Work<R> &w = work<R>(c);
+    const CgPtrs q = cg_ptrs(c, l, 1);
+    if (c->cgp_bar.n == 0) {
+      MG_TRY(c->cgp_bar.alloc(CGP_BAR_WORDS));
+      MG_TRY(c->cgp_fail.alloc(1));
+    }
+    HIPK(hipMemsetAsync(c->cgp_bar, 0, sizeof(unsigned) * CGP_BAR_WORDS, st));
+    HIPK(hipMemsetAsync(c->cgp_fail, 0, sizeof(int), st));
+    CgPersist a;
+    a.e = e;
+    a.z = w.cz;
+    a.w = w.cw;
+    a.p[0] = w.cp;
+    a.p[1] = w.cp2;
+    a.r[0] = w.cr;
+    a.r[1] = w.cr2;
+    a.pz[0] = q.pz[0];
+    a.pz[1] = q.pz[1];
+    a.pw = q.pw;
+    a.pr = q.pr;
+    a.cg = c->cg;
+    a.it = c->it;
+    a.done = c->done;
+    a.maxit = c->p.coarse_maxiter;
+    a.bar = c->cgp_bar;
+    a.fail = c->cgp_fail;
+    EventTimer &tw = c->tm[P::id == 2 ? 7 : 6];  // whole-solve CGNR classes
+    const size_t npairs = tw.pair_launches.size();
+    hipError_t err;
+    {
+      TimerScope ts(c, tw, st, (double)L.g.V * 2, true, 1);
+      err = cgnr_persistent<S>(L.g, L.n, cop_of<P>(L), a, st);
+    }
+    if (err != hipSuccess) {
+      // not launched: this shape or device takes the chunked path from now on
+      (void)hipGetLastError();
+      c->cgp_off[l][pc] = 1;
+      if (tw.pair_launches.size() > npairs) {  // drop the unused event pair
+        tw.pair_launches.pop_back();
+        tw.pair_sites.pop_back();
+        tw.used -= 2;
+      }
+      return MG_OK;
+    }
+    ran = true;
+    HIPK(hipMemcpyAsync(c->h_it, c->it, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
+    HIPK(hipMemcpyAsync(c->h_done, c->cgp_fail, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPK(hipStreamSynchronize(st));
+    if (c->h_done[0]) {
+      set_error("coarsest CGNR: a grid-barrier wait gave up");
+      return MG_EHIP;
+    }
+    const long it = std::max(c->h_it[0], c->h_it[1]);
+    c->n_cgnr += it;
+    // the initial application before the launch, then those inside it
+    // (applications, not dispatches)
+    c->n_coarse += 1 + 2L * it;
+    c->n_coarse_disp += 1;
+    if (tw.pair_launches.size() > npairs)  // the launch made 2 it stencil applications
+      tw.pair_sites.back() = (double)L.g.V * (double)(2L * it);
+    return MG_OK;
+  }
+}
+
 template <typename P> int cgnr(mg_ctx *c, int l, const vec_t<P> *b, vec_t<P> *e, int nrhs, hipStream_t st) {
   using R = typename P::R;
   using S = typename P::S;
@@ -690,6 +769,11 @@ template <typename P> int cgnr(mg_ctx *c, int l, const vec_t<P> *b, vec_t<P> *e,
     HIPK((coarse_apply_k<R, S>(L.g, L.n, cop_of<P>(L), w.cr, w.cz, nrhs, 1, ca, st)));
   }
   if (!fused) HIPK(copy<R>(w.cp, w.cz, n * nrhs, st));
+  if (fused && nrhs == 1 && c->cg_persist) {
+    bool ran = false;
+    MG_TRY(cgnr_whole<P>(c, l, e, st, ran));
+    if (ran) return MG_OK;
+  }
   // With timing on, chunks alternate between two captured graphs so that the
   // event pairs of one are read while the other runs.
   ChunkGraph *gph[2] = {nullptr, nullptr};

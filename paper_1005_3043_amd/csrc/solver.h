@@ -243,6 +243,12 @@ struct mg_ctx {
   mg::ChunkGraph *graphs[16] = {};            // captured CGNR chunks
   mg::DevBuf<double2> csc;
   mg::DevBuf<int> done, it;
+  // whole-solve cooperative CGNR (one RHS): barrier counter, give-up flag,
+  // on/off, and per (level, precision class) whether the launch was refused
+  mg::DevBuf<unsigned> cgp_bar;
+  mg::DevBuf<int> cgp_fail;
+  int cg_persist = 1;
+  int cgp_off[MG_MAX_LEVELS][3] = {};
   int *h_done = nullptr;   // pinned host mirrors
   double *h_rr = nullptr;
   int *h_it = nullptr;
@@ -258,6 +264,6 @@ struct mg_ctx {
   int gcr_rhs = 0;
   // statistics
   long n_fine = 0, n_coarse = 0, n_coarse_disp = 0, n_cgnr = 0, n_vcyc = 0;
-  mg::EventTimer tm[6];  // (fine, coarse) x (FP64, FP32, FP16 storage)
+  mg::EventTimer tm[8];  // (fine, coarse) x (FP64, FP32, FP16 storage), whole-solve CGNR (FP32, FP16)
   double t_setup = 0.0;
 };

@@ -329,6 +329,38 @@ def test_three_level(cuda):
     assert abs(info["iters"][0] - it_ref) <= 1
 
 
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_cgnr_persistent_matches_chunks(cuda, prec):
+    """The single-RHS coarsest CGNR as one cooperative launch does the
+    chunked launches' arithmetic in the same order: the same V-cycle output
+    bit for bit, and the same solve (iterates, outer and CGNR iteration
+    counts), on a two- and a three-level hierarchy."""
+    import paper_1005_3043_amd as mgwd
+    for case in ("8^4 b4^4 nv8", "3-level 8^4"):
+        L, blocks, nv, eps, m, seed = CASES[case] if case in CASES else _CYCLE_CASES[case]
+        U = W.gauge_field(L, eps, seed)
+        inits = [torch.from_numpy(W.setup_starts(L, nv[0], seed)).cuda()]
+        if len(blocks) > 1:
+            Lc = tuple(L[mu] // blocks[0][mu] for mu in range(4))
+            inits.append(torch.from_numpy(W.coarse_setup_starts(Lc, 2 * nv[0], nv[1], seed)).cuda())
+        ctx = mgwd.MG(torch.from_numpy(U).cuda(), m, blocks, nv, inits, precond_prec=prec)
+        b = torch.from_numpy(W.gaussian_spinor(L, 0)).cuda()
+        out = {}
+        for on in (True, False):
+            ctx.set_cgnr_persistent(on)
+            z, cg_it = ctx.vcycle(b, prec)
+            x, info, rc = ctx.solve(b, 1e-10)
+            out[on] = (z.clone(), cg_it, x.clone(), info["iters"][0], info["n_cgnr_iters"], rc)
+        ctx.close()
+        zp, cgp, xp, itp, ncp, rcp = out[True]
+        zc, cgc, xc, itc, ncc, rcc = out[False]
+        print(f"{case} {prec}: CGNR iterations per V-cycle {cgp} / {cgc}, outer {itp} / {itc}, "
+              f"total CGNR {ncp} / {ncc}")
+        assert rcp == rcc == 0
+        assert cgp == cgc and itp == itc and ncp == ncc
+        assert torch.equal(zp, zc) and torch.equal(xp, xc)
+
+
 def test_three_level_wide_coarse_aggregate(cuda):
     """Level-1 aggregates of 4x2x2x2 sites with n = 34 components (1088
     elements per aggregate): the coarse Galerkin build takes its eight
