@@ -276,8 +276,12 @@ int mg_coarse_variant(mg_ctx_t *ctx, int level, mg_prec_t prec, int nrhs,
  * barriers; off, they run as chunks of captured per-iteration launches.
  * Both forms do the same arithmetic in the same order (same iterates, same
  * iteration counts).  Where the device cannot hold the whole coarse grid at
- * once (or the operator rows do not fit), the chunks run regardless.
- * MG_EINVAL on a NULL context.                                             */
+ * once (or the operator rows do not fit), the chunks run regardless.  A
+ * barrier wait gives up after 2^20 polls (on >= 2: after `on` polls, to
+ * exercise this path); the launch then leaves, and that coarsest solve is
+ * done again from its right-hand side by the chunks, which that (level,
+ * precision) keeps using until this function is called again.
+ * MG_EINVAL on a NULL context or on < 0.                                   */
 int mg_set_cgnr_persistent(mg_ctx_t *ctx, int on);
 
 /* Solve D x = b for nrhs canonical spinors (DEVICE complex128) with

@@ -318,10 +318,11 @@ class MG:
         with that K split) or restore autotuning (-1)."""
         _check(lib().mg_set_coarse_variant(self.ctx, int(variant)))
 
-    def set_cgnr_persistent(self, on):
+    def set_cgnr_persistent(self, on, polls=None):
         """Single-RHS coarsest CGNR as one cooperative launch (True, default)
-        or as chunks of per-iteration launches (False); same arithmetic."""
-        _check(lib().mg_set_cgnr_persistent(self.ctx, 1 if on else 0))
+        or as chunks of per-iteration launches (False); same arithmetic.
+        polls (>= 2): barrier polls before a wait gives up (default 2^20)."""
+        _check(lib().mg_set_cgnr_persistent(self.ctx, (int(polls) if polls else 1) if on else 0))
 
     def coarse_variant(self, level=1, prec="f32", nrhs=1):
         v, us = ctypes.c_int(), ctypes.c_double()

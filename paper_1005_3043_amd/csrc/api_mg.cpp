@@ -175,7 +175,11 @@ extern "C" int mg_set_timing(mg_ctx_t *ctx, int on) {
 
 extern "C" int mg_set_cgnr_persistent(mg_ctx_t *ctx, int on) {
   if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
+  if (on < 0) return bad(MG_EINVAL, "mg_set_cgnr_persistent: on must be >= 0");
   ctx->cg_persist = on ? 1 : 0;
+  ctx->cgp_spin = on >= 2 ? (unsigned)on : 1u << 20;
+  for (auto &lv : ctx->cgp_off)
+    for (int &o : lv) o = 0;
   return MG_OK;
 }
 

@@ -330,7 +330,6 @@ __global__ __launch_bounds__(512) void k_coarse(Geom g, int n, const S *__restri
 // the same exit.  A barrier wait is bounded: a workgroup that gives up sets
 // *fail and leaves, so the grid always drains.
 constexpr int CGP_PMAX = 16;          // most operator entries per thread kept in registers
-constexpr unsigned CGP_SPIN = 1u << 20;  // barrier polls before giving up
 
 // Data exchanged between workgroups inside the launch (vectors and partial
 // sums) is read and written as agent-scope relaxed atomics: the loads skip
@@ -392,7 +391,8 @@ __device__ __forceinline__ void cgp_allsum3(const double *__restrict__ a, int na
 // (workgroup i counts on i mod CGP_NC), so that no single address takes
 // every workgroup's atomic; the first wavefront polls all of them at once.
 constexpr int CGP_NC = CGP_BAR_WORDS / 64;
-__device__ __forceinline__ bool cgp_barrier(unsigned *bar, unsigned target, int *fail, int *lds_ok) {
+__device__ __forceinline__ bool cgp_barrier(unsigned *bar, unsigned target, int *fail, unsigned spin_max,
+                                            int *lds_ok) {
   __builtin_amdgcn_s_waitcnt(0);  // this thread's stores acknowledged
   __syncthreads();
   if (threadIdx.x < 64) {
@@ -405,7 +405,7 @@ __device__ __forceinline__ bool cgp_barrier(unsigned *bar, unsigned target, int 
       unsigned v = lane < CGP_NC ? __hip_atomic_load(bar + lane * 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
       v = wave_sum(v);
       if (v >= target) break;
-      if (++spins > CGP_SPIN) {
+      if (++spins > spin_max) {
         ok = 0;
         if (lane == 0) __hip_atomic_store(fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
@@ -512,7 +512,7 @@ __global__ __launch_bounds__(512, 4) void k_cgnr_persistent(Geom g, int n, const
       block_sum<4>(v4, wred);
       if (tid == 0) cstd(a.pw + s, v4[2]);
     }
-    if (!cgp_barrier(a.bar, ++round * nblk, a.fail, &bar_ok)) {
+    if (!cgp_barrier(a.bar, ++round * nblk, a.fail, a.spin, &bar_ok)) {
       final_it = k;
       break;
     }
@@ -555,7 +555,7 @@ __global__ __launch_bounds__(512, 4) void k_cgnr_persistent(Geom g, int n, const
       }
     }
     ++k;
-    if (!cgp_barrier(a.bar, ++round * nblk, a.fail, &bar_ok)) {
+    if (!cgp_barrier(a.bar, ++round * nblk, a.fail, a.spin, &bar_ok)) {
       final_it = k;
       break;
     }

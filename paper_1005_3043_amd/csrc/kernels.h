@@ -117,6 +117,7 @@ struct CgPersist {
   int maxit = 0;
   unsigned *bar = nullptr;
   int *fail = nullptr;
+  unsigned spin = 1u << 20;  // barrier polls before a wait gives up
 };
 template <typename S>
 hipError_t cgnr_persistent(const Geom &g, int n, const S *L, const CgPersist &a, hipStream_t st);

@@ -667,8 +667,10 @@ ChunkGraph *chunk_graph(mg_ctx *c, int l, vec_t<P> *e, int nrhs, int var, bool f
 // path), from the state the chunks start from.  ran = false, and nothing is
 // launched, when the shape or the device cannot take it; the caller then
 // runs the chunks.
-template <typename P> int cgnr_whole(mg_ctx *c, int l, vec_t<P> *e, hipStream_t st, bool &ran) {
+template <typename P>
+int cgnr_whole(mg_ctx *c, int l, vec_t<P> *e, hipStream_t st, bool &ran, bool &retry) {
   ran = false;
+  retry = false;
   using R = typename P::R;
   if constexpr (sizeof(R) == 8) {
     return MG_OK;
@@ -703,6 +705,7 @@ template <typename P> int cgnr_whole(mg_ctx *c, int l, vec_t<P> *e, hipStream_t 
     a.maxit = c->p.coarse_maxiter;
     a.bar = c->cgp_bar;
     a.fail = c->cgp_fail;
+    a.spin = c->cgp_spin;
     EventTimer &tw = c->tm[P::id == 2 ? 7 : 6];  // whole-solve CGNR classes
     const size_t npairs = tw.pair_launches.size();
     hipError_t err;
@@ -726,8 +729,13 @@ template <typename P> int cgnr_whole(mg_ctx *c, int l, vec_t<P> *e, hipStream_t 
     HIPK(hipMemcpyAsync(c->h_done, c->cgp_fail, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPK(hipStreamSynchronize(st));
     if (c->h_done[0]) {
-      set_error("coarsest CGNR: a grid-barrier wait gave up");
-      return MG_EHIP;
+      // a barrier wait gave up (the grid was not all resident at once, e.g.
+      // beside other work on the device): this (level, precision) takes the
+      // chunks from now on, and the caller solves again from b with them
+      c->cgp_off[l][pc] = 1;
+      ran = false;
+      retry = true;
+      return MG_OK;
     }
     const long it = std::max(c->h_it[0], c->h_it[1]);
     c->n_cgnr += it;
@@ -770,9 +778,10 @@ template <typename P> int cgnr(mg_ctx *c, int l, const vec_t<P> *b, vec_t<P> *e,
   }
   if (!fused) HIPK(copy<R>(w.cp, w.cz, n * nrhs, st));
   if (fused && nrhs == 1 && c->cg_persist) {
-    bool ran = false;
-    MG_TRY(cgnr_whole<P>(c, l, e, st, ran));
+    bool ran = false, retry = false;
+    MG_TRY(cgnr_whole<P>(c, l, e, st, ran, retry));
     if (ran) return MG_OK;
+    if (retry) return cgnr<P>(c, l, b, e, nrhs, st);
   }
   // With timing on, chunks alternate between two captured graphs so that the
   // event pairs of one are read while the other runs.

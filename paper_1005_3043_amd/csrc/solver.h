@@ -248,6 +248,7 @@ struct mg_ctx {
   mg::DevBuf<unsigned> cgp_bar;
   mg::DevBuf<int> cgp_fail;
   int cg_persist = 1;
+  unsigned cgp_spin = 1u << 20;  // barrier polls before a wait gives up
   int cgp_off[MG_MAX_LEVELS][3] = {};
   int *h_done = nullptr;   // pinned host mirrors
   double *h_rr = nullptr;

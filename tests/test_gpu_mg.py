@@ -361,6 +361,32 @@ def test_cgnr_persistent_matches_chunks(cuda, prec):
         assert torch.equal(zp, zc) and torch.equal(xp, xc)
 
 
+def test_cgnr_persistent_gives_up_cleanly(cuda):
+    """With a barrier wait limited to two polls the whole-solve launch gives
+    up (every wait is bounded, so the grid drains); the coarsest solve is
+    then done again by the chunks and the result is the chunked one."""
+    import paper_1005_3043_amd as mgwd
+    L, blocks, nv = (16, 16, 16, 16), [(4, 4, 4, 4)], [8]
+    U = torch.from_numpy(W.gauge_field(L, 0.3, 5)).cuda()
+    st = torch.from_numpy(W.setup_starts(L, nv[0], 5)).cuda()
+    ctx = mgwd.MG(U, -0.3, blocks, nv, [st], precond_prec="f16")
+    ctx.set_coarse_variant(0)  # the fused per-RHS CGNR, which the whole-solve launch replaces
+    b = torch.from_numpy(W.gaussian_spinor(L, 1)).cuda()
+    ctx.set_timing(True)
+    ctx.set_cgnr_persistent(True, polls=2)
+    x1, i1, rc1 = ctx.solve(b, 1e-10)
+    ctx.set_cgnr_persistent(False)
+    x2, i2, rc2 = ctx.solve(b, 1e-10)
+    ctx.close()
+    whole = i1["kernels"]["cgnr_f16"]["launches"]
+    print(f"two-poll limit: {whole} whole-solve launches for {i1['n_vcycles']} V-cycles "
+          f"(fewer: a wait gave up and the chunks took over), outer {i1['iters'][0]} / {i2['iters'][0]}")
+    assert rc1 == rc2 == 0
+    assert whole >= 1  # the whole-solve launch was tried
+    assert i1["iters"] == i2["iters"] and i1["n_cgnr_iters"] == i2["n_cgnr_iters"]
+    assert torch.equal(x1, x2)
+
+
 def test_three_level_wide_coarse_aggregate(cuda):
     """Level-1 aggregates of 4x2x2x2 sites with n = 34 components (1088
     elements per aggregate): the coarse Galerkin build takes its eight
