@@ -361,25 +361,26 @@ __device__ __forceinline__ void cstd(double *p, double v) {
   __hip_atomic_store(reinterpret_cast<unsigned long long *>(p), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// block_allsum3 over partials written inside the launch (same order).
-__device__ __forceinline__ void cgp_allsum3(const double *__restrict__ a, int na, const double *__restrict__ b,
-                                            const double *__restrict__ c, int nb, double (&out)[3], double *lds) {
-  double v[3] = {0.0, 0.0, 0.0};
-  for (int i = threadIdx.x; i < na; i += blockDim.x) v[0] += cldd(a + i);
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-    v[1] += cldd(b + i);
-    v[2] += cldd(c + i);
+// Sums over partials written inside the launch, in block_allsum3's order
+// (so each equals the chunked path's sum of the same array): out[0] over a,
+// out[1] over b (when b != nullptr), n entries each.
+__device__ __forceinline__ void cgp_allsum2(const double *__restrict__ a, const double *__restrict__ b, int n,
+                                            double (&out)[2], double *lds) {
+  double v[2] = {0.0, 0.0};
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    v[0] += cldd(a + i);
+    if (b != nullptr) v[1] += cldd(b + i);
   }
   const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
 #pragma unroll
-  for (int q = 0; q < 3; ++q) v[q] = wave_sum(v[q]);
+  for (int q = 0; q < 2; ++q) v[q] = wave_sum(v[q]);
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-    for (int q = 0; q < 3; ++q) lds[w * 3 + q] = v[q];
+    for (int q = 0; q < 2; ++q) lds[w * 3 + q] = v[q];
   }
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
+  for (int q = 0; q < 2; ++q) {
     double t = 0.0;
     for (int k = 0; k < nw; ++k) t += lds[k * 3 + q];
     out[q] = t;
@@ -445,6 +446,7 @@ __global__ __launch_bounds__(512, 4) void k_cgnr_persistent(Geom g, int n, const
   __syncthreads();
   const double tol2b2 = a.cg[4] * a.cg[3];
   unsigned round = 0;
+  double gam = 0.0;  // gamma_k = ||z_k||^2 of the current iteration
   int k = 0, final_it = 0;
   // rows of this workgroup times the staged vector, summed over the groups in
   // the fixed two-stage order of k_coarse; returns the row sum (tid < n)
@@ -486,13 +488,17 @@ __global__ __launch_bounds__(512, 4) void k_cgnr_persistent(Geom g, int n, const
     // ---- phase 1: convergence test of the last update, p = z + beta p_old, w = A p
     float2 *pn = a.p[k & 1];
     const float2 *po = a.p[(k + 1) & 1];
-    double sums[3];
-    cgp_allsum3(a.pr, k > 0 ? (int)nblk : 0, a.pz[k & 1], a.pz[(k + 1) & 1], k > 0 ? (int)nblk : 0, sums, wred);
+    // ||r||^2 of the last update and gamma_k = ||z_k||^2; gamma_{k-1} is
+    // the sum of the same array the previous phase 1 made (the chunked path
+    // sums it again, to the same value)
+    double sums[2] = {0.0, 0.0};
+    if (k > 0) cgp_allsum2(a.pr, a.pz[k & 1], (int)nblk, sums, wred);
     if ((k > 0 && !(sums[0] > tol2b2)) || k >= a.maxit) {
       final_it = k;
       break;
     }
-    const float beta = (k > 0 && sums[2] > 0.0) ? (float)(sums[1] / sums[2]) : 0.f;
+    const float beta = (k > 0 && gam > 0.0) ? (float)(sums[1] / gam) : 0.f;
+    if (k > 0) gam = sums[1];
     for (int idx = tid; idx < nP; idx += blockDim.x) {
       const int slot = idx / n, j = idx - slot * n;
       const size_t o = (size_t)nbs[slot] * n + j;
@@ -519,12 +525,14 @@ __global__ __launch_bounds__(512, 4) void k_cgnr_persistent(Geom g, int n, const
     // ---- phase 2: r = r_old - alpha w, e += alpha p, z = A^dag r
     const float2 *ro = a.r[k & 1];
     float2 *rn = a.r[(k + 1) & 1];
-    cgp_allsum3(nullptr, 0, a.pz[k & 1], a.pw, (int)nblk, sums, wred);
-    if (!(sums[2] > 0.0)) {
+    // ||w||^2 (and gamma_0 at the first iteration)
+    cgp_allsum2(a.pw, k == 0 ? a.pz[0] : nullptr, (int)nblk, sums, wred);
+    if (k == 0) gam = sums[1];
+    if (!(sums[0] > 0.0)) {
       final_it = k + 1;
       break;
     }
-    const float alpha = (float)(sums[1] / sums[2]);
+    const float alpha = (float)(gam / sums[0]);
     double own_sq = 0.0;
     for (int idx = tid; idx < nP; idx += blockDim.x) {
       const int slot = idx / n, j = idx - slot * n;
