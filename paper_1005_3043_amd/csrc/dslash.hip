@@ -108,7 +108,12 @@ __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash(Geom g, const
       for (int i = 0; i < 12; ++i) res[i] = csub(bb[fidx(s, i, 12)], res[i]);
     }
 #pragma unroll
-    for (int i = 0; i < 12; ++i) out[fidx(s, i, 12)] = res[i];
+    for (int i = 0; i < 12; ++i) {
+      // the output is not read again by this launch: a non-temporal store
+      // leaves L2 to the neighbour spinors and links that are
+      __builtin_nontemporal_store(res[i].x, &out[fidx(s, i, 12)].x);
+      __builtin_nontemporal_store(res[i].y, &out[fidx(s, i, 12)].y);
+    }
     if constexpr (MODE == DS_MR) {
 #pragma unroll
       for (int i = 0; i < 12; ++i) {
