@@ -457,3 +457,108 @@ def test_refine_level1_one_step_is_projection_on_kept_span():
     Az, Av = A1 @ z, A1 @ v
     x = v - np.vdot(Az, Av) / np.vdot(Az, Az) * z
     assert np.abs(Vr[0].ravel() - x / np.linalg.norm(x)).max() < 1e-8
+
+
+# ---------------------------------------------------------------- setup stage one (a5)
+def _dense_case(L=(4, 4, 4, 4), m=-0.2, eps=0.3, seed=5):
+    U = W.gauge_field(L, eps, seed)
+    return U, m, wi.D_dense(U, m)
+
+
+def test_relax_one_round_one_step_is_damped_minimiser():
+    """One round of one MR step moves each start v along -D v by omega times
+    the scalar that minimises ||D (v - c D v)|| (library least squares on the
+    dense operator), then normalises: the relaxation solves D e = -D v, it
+    does not move v towards the large modes."""
+    L = (4, 4, 4, 4)
+    U, m, D = _dense_case(L)
+    starts = W.setup_starts(L, 2, 3)
+    A = lambda u: wi.apply_D(U, u, m)  # noqa: E731
+    for omega in (1.0, 0.9):
+        Vr = so.relax_nullspace(A, starts, 1, 1, omega)
+        for k in range(2):
+            v = starts[k].ravel()
+            Dv = D @ v
+            c, *_ = np.linalg.lstsq((D @ Dv)[:, None], Dv, rcond=None)
+            x = v - omega * c[0] * Dv
+            ref = x / np.linalg.norm(x)
+            assert np.abs(Vr[k].ravel() - ref).max() < 1e-12
+            assert abs(np.linalg.norm(Vr[k]) - 1.0) < 1e-13
+
+
+def test_relax_rounds_compose_and_lower_the_rayleigh_ratio():
+    """Rounds compose (two rounds = one round applied to the result of one
+    round), every relaxed vector has unit norm, and five rounds of four MR
+    steps lower ||D v|| / ||v|| of every start well below the start's value
+    (relaxation leaves the near-null space)."""
+    L = (4, 4, 4, 4)
+    U, m, D = _dense_case(L)
+    starts = W.setup_starts(L, 3, 4)
+    A = lambda u: wi.apply_D(U, u, m)  # noqa: E731
+    two = so.relax_nullspace(A, starts, 2, 3, 0.9)
+    once_twice = so.relax_nullspace(A, so.relax_nullspace(A, starts, 1, 3, 0.9), 1, 3, 0.9)
+    assert np.abs(two - once_twice).max() < 1e-13
+    V5 = so.relax_nullspace(A, starts, 5, 4, 0.9)
+    svals = np.linalg.svd(D, compute_uv=False)
+    for k in range(3):
+        before = np.linalg.norm(D @ starts[k].ravel()) / np.linalg.norm(starts[k])
+        after = np.linalg.norm(D @ V5[k].ravel())
+        assert abs(np.linalg.norm(V5[k]) - 1.0) < 1e-13
+        assert svals[-1] * (1 - 1e-12) <= after < 0.5 * before
+
+
+# ---------------------------------------------------------------- smoothed cycle (a12)
+def _exact_coarse_projector(h, L, b):
+    """K = P (P^dag D P)^{-1} P^dag with P spanning the raw null vectors
+    restricted to each (aggregate, chirality) by coordinates (K does not
+    depend on the basis of that span)."""
+    V = h.levels[0].nullvecs
+    nv = V.shape[0]
+    Cx, Cy, Cz = L[0] // b[0], L[1] // b[1], L[2] // b[2]
+    agg = np.array([(x // b[0]) + Cx * ((y // b[1]) + Cy * ((z // b[2]) + Cz * (t // b[3])))
+                    for t in range(L[3]) for z in range(L[2]) for y in range(L[1]) for x in range(L[0])])
+    nagg = agg.max() + 1
+    comp_chi = np.arange(12) // 6
+    cols = []
+    for j in range(nv):
+        f = V[j].reshape(-1, 12)
+        for a in range(nagg):
+            for hh in range(2):
+                mask = (agg[:, None] == a) & (comp_chi[None, :] == hh)
+                cols.append(np.where(mask, f, 0).ravel())
+    P = np.stack(cols, 1)
+    return P
+
+
+@pytest.mark.parametrize("pre,post", [(0, 1), (1, 0), (1, 1)])
+def test_vcycle_smoothing_around_exact_coarse_correction(pre, post):
+    """Two levels with an exact coarse solve (CGNR to 1e-13): the cycle is
+    x1 = omega c1 r (pre-step, c1 = argmin ||r - c D r||), rho1 = r - D x1,
+    x2 = x1 + K rho1 with K the exact coarse correction of the null-vector
+    span, rho2 = r - D x2, z = x2 + omega c2 rho2 (post-step, c2 =
+    argmin ||rho2 - c D rho2||): each minimiser by library least squares on
+    the dense operator.  The post-step never raises the residual."""
+    L, b, nv, m = (4, 4, 4, 4), (2, 2, 2, 2), 4, -0.2
+    U = W.gauge_field(L, 0.3, 6)
+    p = so.MGParams(blocks=[b], nv=[nv], setup_rounds=2, pre=pre, post=post, coarse_tol=1e-13,
+                    coarse_maxiter=20000)
+    h = so.mg_setup(U, m, p, W.setup_starts(L, nv, 6))
+    D = wi.D_dense(U, m)
+    P = _exact_coarse_projector(h, L, b)
+    K = lambda v: P @ np.linalg.solve(P.conj().T @ D @ P, P.conj().T @ v)  # noqa: E731
+    r = W.gaussian_spinor(L, 7)
+    rv = r.ravel()
+
+    def mr_step(res):
+        c, *_ = np.linalg.lstsq((D @ res)[:, None], res, rcond=None)
+        return 0.9 * c[0] * res
+
+    x = mr_step(rv) if pre else np.zeros_like(rv)
+    x = x + K(rv - D @ x)
+    xc = x.copy()
+    if post:
+        x = x + mr_step(rv - D @ x)
+    z = h.vcycle(r, 0).ravel()
+    assert np.linalg.norm(z - x) < 1e-9 * np.linalg.norm(x)
+    if post:
+        assert np.linalg.norm(rv - D @ z) <= np.linalg.norm(rv - D @ xc) * (1 + 1e-12)

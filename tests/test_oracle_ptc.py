@@ -118,3 +118,29 @@ def test_adam_first_step():
     step = (p - q) / 1e-3
     ref = np.sign(g.real) + 1j * np.sign(g.imag)
     assert np.allclose(step, ref, rtol=1e-4)
+
+
+@pytest.mark.parametrize("t", [2, 3])
+def test_adam_bias_correction_later_steps(t):
+    """Bias correction at steps after the first.  With the same gradient g at
+    every step, m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so the corrected
+    step is lr g / (|g| + eps) per real component at every t.  With alternating gradients g, -g, g the
+    second moment is still (1 - b2^t) g^2 per component while
+    m_2 = -(1 - b1)^2 g and m_3 = (1 - b1)(1 - b1 (1 - b1)) g, so the steps
+    are -(1 - b1) / (1 + b1) = -0.0526315789... times that at t = 2 and
+    0.091 / 0.271 = 0.3357933579... times it at t = 3 (b1 = 0.9)."""
+    p0 = np.array([1.0 + 2.0j, -1.0 + 0.5j, 0.25 - 3.0j])
+    g = np.array([0.3 - 2.0j, -5.0 + 1e-3j, 7.0 + 0.02j])
+    eps = 1e-8
+    sg = g.real / (np.abs(g.real) + eps) + 1j * g.imag / (np.abs(g.imag) + eps)
+    lr = 1e-3
+    for alternate, expect in ((False, {2: 1.0, 3: 1.0}), (True, {2: -0.05263157894736842, 3: 0.33579335793357934})):
+        opt = ptc.Adam(lr=lr, eps=eps)
+        p = p0
+        for k in range(1, t + 1):
+            gk = -g if (alternate and k % 2 == 0) else g
+            (q,) = opt.step([p], [gk])
+            if k == t:
+                step = (p - q) / lr
+            p = q
+        assert np.allclose(step, expect[t] * sg, rtol=1e-9, atol=0)

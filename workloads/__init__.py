@@ -125,14 +125,6 @@ def point_sources(L) -> np.ndarray:
     return b
 
 
-def noise_spinor(L, seed: int, step: int = 0) -> np.ndarray:
-    """Gaussian noise input of the null-vector proposal network."""
-    Lx, Ly, Lz, Lt = L
-    g = np.random.default_rng([int(seed), STREAM_NOISE, int(step)])
-    shp = (Lt, Lz, Ly, Lx, 4, 3)
-    return g.standard_normal(shp) + 1j * g.standard_normal(shp)
-
-
 # ---------------------------------------------------------------------------
 # Workload table.  Masses are stored in masses.json (written by the oracle's
 # Arnoldi mass-tuning script); "target" is the requested min Re lambda(D).
