@@ -139,6 +139,9 @@ typedef struct {
   double kernel_ms[8];
   int kernel_launches[8];
   double kernel_sites[8];
+  int n_cgnr_fallbacks;         /* whole-solve CGNR launches whose barrier
+                                   wait gave up, so that the coarsest solve
+                                   was done again by the chunks            */
 } mg_info_t;
 
 /* Fine Wilson operator out = D(U) in (Eq. 2) on nrhs canonical spinors.
@@ -283,6 +286,21 @@ int mg_coarse_variant(mg_ctx_t *ctx, int level, mg_prec_t prec, int nrhs,
  * precision) keeps using until this function is called again.
  * MG_EINVAL on a NULL context or on < 0.                                   */
 int mg_set_cgnr_persistent(mg_ctx_t *ctx, int on);
+
+/* The coarsest-level solve of the cycle ("Numerical Results": CG on the
+ * normal equations D_c^dag D_c e = D_c^dag b to ||b - D_c e|| <=
+ * coarse_tol ||b||, at most coarse_maxiter iterations, D_c^dag = sigma_3 D_c
+ * sigma_3) with the stored coarsest operator of precision prec (MG_F64,
+ * MG_F32, MG_F16 as mg_apply_op), exactly as the V-cycle runs it: one
+ * whole-solve launch for one right-hand side in FP32 arithmetic (see
+ * mg_set_cgnr_persistent), chunks of captured iterations otherwise.
+ * b, x: DEVICE complex128 canonical vectors of the coarsest level
+ * [nrhs][Lct][Lcz][Lcy][Lcx][n], not aliased; 1 <= nrhs <= 16.  iters (HOST,
+ * may be NULL) receives the CGNR iterations of each right-hand side (nrhs
+ * ints).  Ordered on `stream`; synchronous.  Errors: MG_EINVAL (NULL or
+ * aliased buffers, nrhs), MG_ENOTSUP (prec).                              */
+int mg_coarse_solve(mg_ctx_t *ctx, mg_prec_t prec, const void *b, void *x, int nrhs, int *iters,
+                    hipStream_t stream);
 
 /* Solve D x = b for nrhs canonical spinors (DEVICE complex128) with
  * flexible GCR(gcr_restart) preconditioned by one MG V-cycle (MR pre/post

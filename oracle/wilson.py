@@ -115,6 +115,36 @@ def apply_D(U, psi, m: float, antiperiodic_t: bool = True):
     return out
 
 
+def apply_D_sites(U, psi, m: float, sites, antiperiodic_t: bool = True):
+    """(D psi)(x) of Eq. (2) evaluated only at the listed sites, one term at a
+    time: sites is an integer array [n, 4] of (x, y, z, t); psi may carry
+    leading batch axes.  Returns [..., n, 4, 3].  For checking large lattices
+    on a sample of sites."""
+    L = dims_of(U.shape[1:5])
+    X = np.asarray(sites, dtype=np.int64)
+    out = (4.0 + m) * psi[..., X[:, 3], X[:, 2], X[:, 1], X[:, 0], :, :]
+    for mu in range(4):
+        e = np.zeros(4, dtype=np.int64)
+        e[mu] = 1
+        Xf = (X + e) % np.array(L)
+        Xb = (X - e) % np.array(L)
+        etaf = np.ones(len(X))
+        etab = np.ones(len(X))
+        if mu == 3 and antiperiodic_t:
+            etaf[X[:, 3] == L[3] - 1] = -1.0
+            etab[X[:, 3] == 0] = -1.0
+        Uf = U[mu, X[:, 3], X[:, 2], X[:, 1], X[:, 0]]        # U_mu(x)
+        Ub = U[mu, Xb[:, 3], Xb[:, 2], Xb[:, 1], Xb[:, 0]]    # U_mu(x - mu)
+        pf = psi[..., Xf[:, 3], Xf[:, 2], Xf[:, 1], Xf[:, 0], :, :]
+        pb = psi[..., Xb[:, 3], Xb[:, 2], Xb[:, 1], Xb[:, 0], :, :]
+        tf = np.einsum("nab,...nsb->...nsa", Uf, pf)
+        tb = np.einsum("nba,...nsb->...nsa", np.conj(Ub), pb)
+        tf = np.einsum("st,...ntc->...nsc", PROJ_MINUS[mu], tf)
+        tb = np.einsum("st,...ntc->...nsc", PROJ_PLUS[mu], tb)
+        out = out - 0.5 * (etaf[:, None, None] * tf + etab[:, None, None] * tb)
+    return out
+
+
 def apply_gamma5(psi):
     return _spin(GAMMA5, psi)
 

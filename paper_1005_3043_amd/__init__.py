@@ -22,7 +22,7 @@ MAX_LEVELS = 3
 MAX_RHS = 16
 
 EXPORTED = ["wilson_apply", "mg_setup", "mg_set_precond_prec", "mg_set_mass", "mg_set_timing", "mg_restrict",
-            "mg_prolong", "coarse_apply", "mg_apply_op", "mg_vcycle", "mg_transfer", "mg_set_transfer_variant", "mg_transfer_variant", "mg_set_coarse_variant", "mg_coarse_variant", "mg_set_cgnr_persistent", "mg_solve", "mg_time_dslash", "mg_time_coarse",
+            "mg_prolong", "coarse_apply", "mg_apply_op", "mg_vcycle", "mg_transfer", "mg_set_transfer_variant", "mg_transfer_variant", "mg_set_coarse_variant", "mg_coarse_variant", "mg_set_cgnr_persistent", "mg_coarse_solve", "mg_solve", "mg_time_dslash", "mg_time_coarse",
             "mg_destroy", "mg_last_error", "mg_export_maps", "mg_export_P",
             "mg_export_coarse_op", "mg_export_nullvecs", "mg_level_info",
             "ptc_create", "ptc_set_links", "ptc_set_targets", "ptc_forward", "ptc_loss_grad", "ptc_adam",
@@ -70,7 +70,8 @@ class Info(ctypes.Structure):
                 ("t_setup_s", ctypes.c_double), ("t_solve_s", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double * 8),
                 ("kernel_launches", ctypes.c_int * 8),
-                ("kernel_sites", ctypes.c_double * 8)]
+                ("kernel_sites", ctypes.c_double * 8),
+                ("n_cgnr_fallbacks", ctypes.c_int)]
 
     KERNELS = ("dslash_f64", "coarse_f64", "dslash_f32", "coarse_f32", "dslash_f16", "coarse_f16", "cgnr_f32",
                "cgnr_f16")
@@ -80,6 +81,7 @@ class Info(ctypes.Structure):
                     n_fine_dslash=self.n_fine_dslash, n_coarse_apply=self.n_coarse_apply,
                     n_coarse_dispatch=self.n_coarse_dispatch,
                     n_cgnr_iters=self.n_cgnr_iters, n_vcycles=self.n_vcycles,
+                    n_cgnr_fallbacks=self.n_cgnr_fallbacks,
                     t_setup_s=self.t_setup_s, t_solve_s=self.t_solve_s,
                     kernels={k: dict(ms=self.kernel_ms[i], launches=self.kernel_launches[i],
                                      sites=self.kernel_sites[i]) for i, k in enumerate(self.KERNELS)})
@@ -113,6 +115,7 @@ def lib():
             "mg_set_coarse_variant": [vp, ci],
             "mg_set_cgnr_persistent": [vp, ci],
             "mg_coarse_variant": [vp, ci, ci, ci, ctypes.POINTER(ci), ctypes.POINTER(cd)],
+            "mg_coarse_solve": [vp, ci, vp, vp, ci, ctypes.POINTER(ci), vp],
             "mg_solve": [vp, vp, vp, ci, cd, ctypes.POINTER(Info), vp],
             "mg_time_dslash": [vp, ci, ci, ci, ctypes.POINTER(cd), vp],
             "mg_time_coarse": [vp, ci, ci, ci, ci, ctypes.POINTER(cd), vp],
@@ -328,6 +331,17 @@ class MG:
         v, us = ctypes.c_int(), ctypes.c_double()
         _check(lib().mg_coarse_variant(self.ctx, level, PREC[prec], nrhs, ctypes.byref(v), ctypes.byref(us)))
         return v.value, us.value
+
+    def coarse_solve(self, b, prec="f64", nrhs=None):
+        """The cycle's coarsest-level CGNR on canonical coarsest-level vectors
+        (complex128); returns (x, CGNR iterations per right-hand side)."""
+        lc = len(self.nv)
+        if nrhs is None:
+            nrhs = self._nvec(lc, b)
+        x = torch.empty_like(b)
+        it = (ctypes.c_int * nrhs)()
+        _check(lib().mg_coarse_solve(self.ctx, PREC[prec], _dev(b, "b"), _dev(x, "x"), nrhs, it, _stream()))
+        return x, list(it)
 
     def solve(self, b, tol=1e-10, nrhs=None, x=None):
         if nrhs is None:

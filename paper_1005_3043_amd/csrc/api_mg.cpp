@@ -369,18 +369,12 @@ extern "C" int mg_solve(mg_ctx_t *ctx, const void *b, void *x, int nrhs, double 
   if (nrhs < 1 || nrhs > ctx->p.max_rhs) return bad(MG_EINVAL, "mg_solve: nrhs out of range (max_rhs)");
   if (!(tol > 0.0)) return bad(MG_EINVAL, "mg_solve: tol must be positive");
   mg_ctx *c = ctx;
-  const size_t n = c->lev[0].vsize() * nrhs;
-  MG_TRY(c->gx.alloc(n));
-  MG_TRY(c->gr.alloc(n));
-  MG_TRY(c->gb.alloc(n));
-  MG_TRY(c->gZ.alloc(n * c->p.gcr_restart));
-  MG_TRY(c->gW.alloc(n * c->p.gcr_restart));
-  MG_TRY(c->skip.alloc(MG_MAX_RHS));
+  MG_TRY(ensure_fgcr(c, nrhs));
   MG_TRY(ensure_prec(c, c->prec, st));
   if (c->prec == MG_F64) MG_TRY(ensure_work<double>(c, nrhs));
   else MG_TRY(ensure_work<float>(c, nrhs));
   MG_TRY(ensure_scalars(c, part_need(c, nrhs)));
-  c->n_fine = c->n_coarse = c->n_coarse_disp = c->n_cgnr = c->n_vcyc = 0;
+  c->n_fine = c->n_coarse = c->n_coarse_disp = c->n_cgnr = c->n_vcyc = c->n_cg_fallback = 0;
   for (auto &t : c->tm) t.reset();
   HIPK(hipStreamSynchronize(st));
   const double t0 = now_s();
@@ -412,6 +406,7 @@ extern "C" int mg_solve(mg_ctx_t *ctx, const void *b, void *x, int nrhs, double 
     info->n_cgnr_iters = (int)c->n_cgnr;
     info->n_coarse_dispatch = (int)c->n_coarse_disp;
     info->n_vcycles = (int)c->n_vcyc;
+    info->n_cgnr_fallbacks = (int)c->n_cg_fallback;
     info->t_setup_s = c->t_setup;
     info->t_solve_s = t1 - t0;
     if (c->timing) {
@@ -457,6 +452,67 @@ extern "C" int mg_vcycle(mg_ctx_t *ctx, mg_prec_t prec, const void *in, void *ou
   HIPK(unpack_field<double>(L0.g, b, (double2 *)out, 12, nrhs, s2));
   HIPK(hipStreamSynchronize(s2));
   if (cgnr_iters) *cgnr_iters = (int)c->n_cgnr;
+  return MG_OK;
+}
+
+namespace {
+template <typename P>
+int coarse_solve_t(mg_ctx *c, const double2 *b, double2 *x, int nrhs, int *iters, hipStream_t st) {
+  using R = typename P::R;
+  const int l = c->nlev - 1;
+  const size_t n = c->lev[l].vsize() * nrhs;
+  const vec_t<P> *bb;
+  vec_t<P> *xx;
+  if constexpr (sizeof(R) == 8) {
+    bb = b;
+    xx = x;
+  } else {
+    Work<float> &w = c->w32;
+    HIPK((convert<float, double>(w.rin[l], b, n, st)));
+    bb = w.rin[l];
+    xx = w.x[l];
+  }
+  MG_TRY(cgnr<P>(c, l, bb, xx, nrhs, st));
+  // per right-hand side counts as the solve left them (both parity slots of
+  // the chunks; the whole-solve launch writes both)
+  for (int i = 0; i < nrhs && iters; ++i)
+    iters[i] = std::max(c->h_it[i], c->h_it[(nrhs == 1 ? 1 : nrhs + i)]);
+  if constexpr (sizeof(R) != 8) HIPK((convert<double, float>(x, xx, n, st)));
+  return MG_OK;
+}
+}  // namespace
+
+extern "C" int mg_coarse_solve(mg_ctx_t *ctx, mg_prec_t prec, const void *b, void *x, int nrhs, int *iters,
+                               hipStream_t st) {
+  set_error("");
+  if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
+  if (!b || !x || b == x) return bad(MG_EINVAL, "mg_coarse_solve: bad buffers");
+  if (nrhs < 1 || nrhs > MG_MAX_RHS) return bad(MG_EINVAL, "mg_coarse_solve: nrhs out of range");
+  if (prec != MG_F64 && prec != MG_F32 && prec != MG_F16)
+    return bad(MG_ENOTSUP, "mg_coarse_solve: prec must be MG_F64, MG_F32 or MG_F16");
+  mg_ctx *c = ctx;
+  MG_TRY(ensure_prec(c, prec, st));
+  if (prec == MG_F64) MG_TRY(ensure_work<double>(c, nrhs));
+  else MG_TRY(ensure_work<float>(c, nrhs));
+  MG_TRY(ensure_scalars(c, part_need(c, nrhs)));
+  const int l = c->nlev - 1;
+  DevBuf<double2> a, e;
+  MG_TRY(a.alloc(c->lev[l].vsize() * nrhs));
+  MG_TRY(e.alloc(c->lev[l].vsize() * nrhs));
+  hipStream_t s2 = c->sti;
+  HIPK(hipEventRecord(c->ev_in, st));
+  HIPK(hipStreamWaitEvent(s2, c->ev_in, 0));
+  HIPK(pack_level(c, l, b, a, nrhs, s2));
+  int rc;
+  if (prec == MG_F64) rc = coarse_solve_t<PF64>(c, a, e, nrhs, iters, s2);
+  else if (prec == MG_F32) rc = coarse_solve_t<PF32>(c, a, e, nrhs, iters, s2);
+  else rc = coarse_solve_t<PF16>(c, a, e, nrhs, iters, s2);
+  if (rc < 0) {
+    (void)hipStreamSynchronize(s2);
+    return rc;
+  }
+  HIPK(unpack_level(c, l, e, x, nrhs, s2));
+  HIPK(hipStreamSynchronize(s2));
   return MG_OK;
 }
 

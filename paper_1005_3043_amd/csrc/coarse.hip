@@ -448,6 +448,9 @@ __global__ __launch_bounds__(512, 4) void k_cgnr_persistent(Geom g, int n, const
   unsigned round = 0;
   double gam = 0.0;  // gamma_k = ||z_k||^2 of the current iteration
   int k = 0, final_it = 0;
+  // a zero right-hand side was marked done before the launch (as the chunks
+  // see it): no iteration, e stays zero
+  const bool nothing = a.done[0] != 0;
   // rows of this workgroup times the staged vector, summed over the groups in
   // the fixed two-stage order of k_coarse; returns the row sum (tid < n)
   auto apply = [&]() -> C {
@@ -484,7 +487,7 @@ __global__ __launch_bounds__(512, 4) void k_cgnr_persistent(Geom g, int n, const
     }
     return sum;
   };
-  for (;;) {
+  for (; !nothing;) {
     // ---- phase 1: convergence test of the last update, p = z + beta p_old, w = A p
     float2 *pn = a.p[k & 1];
     const float2 *po = a.p[(k + 1) & 1];

@@ -29,23 +29,38 @@ template <typename C> __host__ __device__ __forceinline__ void reconstruct_row2(
   u[8] = mk<C>(c.x, -c.y);
 }
 
+#ifndef MG_LINK_NT
+#define MG_LINK_NT 0
+#endif
+template <typename S> __device__ __forceinline__ S ld_link(const S *p) {
+#if MG_LINK_NT
+  S v;
+  v.x = __builtin_nontemporal_load(&p->x);
+  v.y = __builtin_nontemporal_load(&p->y);
+  return v;
+#else
+  return *p;
+#endif
+}
+
 template <int NL, typename C, typename S>
-__host__ __device__ __forceinline__ void load_link_t(C (&u)[9], const S *__restrict__ U, int mu, uint32_t s) {
+__device__ __forceinline__ void load_link_t(C (&u)[9], const S *__restrict__ U, int mu, uint32_t s) {
 #pragma unroll
-  for (int e = 0; e < NL; ++e) u[e] = cvt<C>(U[fidx(s, mu * NL + e, 4 * NL)]);
+  for (int e = 0; e < NL; ++e) u[e] = cvt<C>(ld_link(&U[fidx(s, mu * NL + e, 4 * NL)]));
   if constexpr (NL == 6) reconstruct_row2(u);
 }
 
-template <typename C>
-__host__ __device__ __forceinline__ void load_spinor_t(C (&psi)[12], const C *__restrict__ in, uint32_t s) {
+template <typename C, typename TI>
+__host__ __device__ __forceinline__ void load_spinor_t(C (&psi)[12], const TI *__restrict__ in, uint32_t s) {
 #pragma unroll
-  for (int c = 0; c < 12; ++c) psi[c] = in[fidx(s, c, 12)];
+  for (int c = 0; c < 12; ++c) psi[c] = cvt<C>(in[fidx(s, c, 12)]);
 }
 
-// Full stencil at one site: res = D psi at s, ctr = psi(s).
-template <int NL, typename C, typename S>
-__host__ __device__ __forceinline__ void dslash_site(C (&res)[12], C (&ctr)[12], const Geom &g, uint32_t s,
-                                                     const S *__restrict__ U, const C *__restrict__ in,
+// Full stencil at one site: res = D psi at s, ctr = psi(s).  The input
+// spinors may be stored in a narrower type TI than the arithmetic type C.
+template <int NL, typename C, typename S, typename TI>
+__device__ __forceinline__ void dslash_site(C (&res)[12], C (&ctr)[12], const Geom &g, uint32_t s,
+                                                     const S *__restrict__ U, const TI *__restrict__ in,
                                                      decltype(C::x) diag) {
   using R = decltype(C::x);
   const Coords k = decode(g, s);
@@ -76,6 +91,85 @@ __host__ __device__ __forceinline__ void dslash_site(C (&res)[12], C (&ctr)[12],
   }
 }
 
+// The stencil at one site for K right-hand sides (input stride vs between
+// them): each direction's two links are loaded once and applied to all K.
+// Only the first kv are distinct; the spare slots repeat the last of them.
+template <int K, int NL, typename C, typename S, typename TI>
+__device__ __forceinline__ void dslash_site_k(C (&res)[K][12], C (&ctr)[K][12], const Geom &g, uint32_t s,
+                                              const S *__restrict__ U, const TI *__restrict__ in, size_t vs, int kv,
+                                              decltype(C::x) diag) {
+  using R = decltype(C::x);
+  const Coords kk = decode(g, s);
+  C acc[K][12];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int i = 0; i < 12; ++i) acc[k][i] = mk<C>(0, 0);
+#pragma unroll 1
+  for (int mu = 0; mu < 4; ++mu) {
+    const uint32_t sf = nbr_fwd(g, s, kk, mu), sb = nbr_bwd(g, s, kk, mu);
+    R ef = 1, eb = 1;
+    if (mu == 3 && g.antiperiodic) {
+      if (kk.o[3] == g.b[3] - 1 && kk.c[3] == g.C[3] - 1) ef = -1;
+      if (kk.o[3] == 0 && kk.c[3] == 0) eb = -1;
+    }
+    C u[9];
+    load_link_t<NL>(u, U, mu, s);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      C p[12];
+      load_spinor_t(p, in + (size_t)(k < kv ? k : kv - 1) * vs, sf);
+      hop_dispatch<true>(mu, acc[k], p, u, ef);
+    }
+    load_link_t<NL>(u, U, mu, sb);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      C p[12];
+      load_spinor_t(p, in + (size_t)(k < kv ? k : kv - 1) * vs, sb);
+      hop_dispatch<false>(mu, acc[k], p, u, eb);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    load_spinor_t(ctr[k], in + (size_t)(k < kv ? k : kv - 1) * vs, s);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      res[k][i].x = fma(diag, ctr[k][i].x, (R)-0.5 * acc[k][i].x);
+      res[k][i].y = fma(diag, ctr[k][i].y, (R)-0.5 * acc[k][i].y);
+    }
+  }
+}
+
+#ifndef MG_DSLASH_ORDER
+#define MG_DSLASH_ORDER 0
+#endif
+// Block of `per` consecutive sites that workgroup bid of nblk visits.  The
+// hardware deals workgroups to the eight XCDs round-robin; xcd_remap gives
+// each XCD a contiguous range.  Order 1 (aggregates of whole blocks, a
+// coarse z extent divisible by 8): XCD k takes the aggregates of the z
+// layers k C_z/8 .. (k+1) C_z/8 - 1 and walks them x fastest, then y, then
+// t, so that the XCDs move through t in step.
+__device__ __forceinline__ uint32_t visit_block(uint32_t bid, uint32_t nblk, const Geom &g, uint32_t per) {
+  const uint32_t q = xcd_remap(bid, nblk);
+#if MG_DSLASH_ORDER == 1
+  const uint32_t sub = g.vb / per;
+  if ((nblk & 7u) == 0 && g.C[2] % 8 == 0 && sub * per == g.vb && nblk == g.Vc * sub) {
+    const uint32_t per_xcd = nblk >> 3, xcd = q / per_xcd, r0 = q - xcd * per_xcd;
+    const uint32_t j = r0 % sub;
+    uint32_t r = r0 / sub;
+    const uint32_t cx = r % (uint32_t)g.C[0];
+    r /= (uint32_t)g.C[0];
+    const uint32_t cy = r % (uint32_t)g.C[1];
+    r /= (uint32_t)g.C[1];
+    const uint32_t ct = r % (uint32_t)g.C[3];
+    const uint32_t cz = xcd * ((uint32_t)g.C[2] >> 3) + r / (uint32_t)g.C[3];
+    const uint32_t B = cx + (uint32_t)g.C[0] * (cy + (uint32_t)g.C[1] * (cz + (uint32_t)g.C[2] * ct));
+    return B * sub + j;
+  }
+#endif
+  return q;
+}
+
 // Minimum waves per SIMD requested from the register allocator (0 = none).
 #ifndef MG_DSLASH_WAVES_F64
 #define MG_DSLASH_WAVES_F64 0
@@ -87,21 +181,21 @@ template <typename R> constexpr int dslash_waves() {
   return sizeof(R) == 8 ? MG_DSLASH_WAVES_F64 : MG_DSLASH_WAVES_F32;
 }
 
-template <typename R, int MODE, int NL, typename S>
+template <typename R, int MODE, int NL, typename S, typename TI = c_t<R>>
 __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash(Geom g, const S *__restrict__ U,
-                                                const c_t<R> *__restrict__ in, c_t<R> *__restrict__ out,
+                                                const TI *__restrict__ in, c_t<R> *__restrict__ out,
                                                 const c_t<R> *__restrict__ b, R diag,
                                                 double *__restrict__ partials) {
   using C = c_t<R>;
   const size_t off = (size_t)blockIdx.y * 12 * g.Vpad;
   in += off;
   out += off;
-  const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t tile = visit_block(blockIdx.x, gridDim.x, g, blockDim.x);
   const uint32_t s = tile * blockDim.x + threadIdx.x;
   double red[3] = {0.0, 0.0, 0.0};
   if (s < g.V) {
     C res[12], ctr[12];
-    dslash_site<NL>(res, ctr, g, s, U, in, diag);
+    dslash_site<NL, C>(res, ctr, g, s, U, in, diag);
     if constexpr (MODE == DS_RESID) {
       const C *bb = b + off;
 #pragma unroll
@@ -136,11 +230,185 @@ __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash(Geom g, const
   }
 }
 
+// Several right-hand sides: a workgroup covers one 64-site tile for up to
+// four right-hand sides, one wavefront each.  The wavefronts read the same
+// links at the same time, so the links of a tile come from memory once per
+// group of four right-hand sides instead of once per right-hand side; the
+// spinor loads are those of the single-RHS kernel.  A wavefront is one
+// (tile, right-hand side) pair, so the MR partial sums are wavefront sums (no
+// workgroup barrier), one slot per tile and right-hand side.
+constexpr int MRHS_GROUP = 4;
+
+template <typename R, int MODE, int NL, typename S, typename TI = c_t<R>>
+__global__ __launch_bounds__(64 * MRHS_GROUP, dslash_waves<R>()) void k_dslash_mrhs(Geom g, const S *__restrict__ U,
+                                                                const TI *__restrict__ in,
+                                                                c_t<R> *__restrict__ out,
+                                                                const c_t<R> *__restrict__ b, R diag,
+                                                                double *__restrict__ partials, int nrhs) {
+  using C = c_t<R>;
+  const int rhs = blockIdx.y * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (rhs >= nrhs) return;  // a whole wavefront; no workgroup barrier follows
+  const size_t off = (size_t)rhs * 12 * g.Vpad;
+  in += off;
+  out += off;
+  const uint32_t tile = visit_block(blockIdx.x, gridDim.x, g, TILE);
+  const uint32_t s = tile * TILE + (threadIdx.x & 63);
+  double red[3] = {0.0, 0.0, 0.0};
+  if (s < g.V) {
+    C res[12], ctr[12];
+    dslash_site<NL, C>(res, ctr, g, s, U, in, diag);
+    if constexpr (MODE == DS_RESID) {
+      const C *bb = b + off;
+#pragma unroll
+      for (int i = 0; i < 12; ++i) res[i] = csub(bb[fidx(s, i, 12)], res[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      __builtin_nontemporal_store(res[i].x, &out[fidx(s, i, 12)].x);
+      __builtin_nontemporal_store(res[i].y, &out[fidx(s, i, 12)].y);
+    }
+    if constexpr (MODE == DS_MR) {
+#pragma unroll
+      for (int i = 0; i < 12; ++i) {
+        red[0] += (double)res[i].x * ctr[i].x + (double)res[i].y * ctr[i].y;
+        red[1] += (double)res[i].x * ctr[i].y - (double)res[i].y * ctr[i].x;
+        red[2] += (double)res[i].x * res[i].x + (double)res[i].y * res[i].y;
+      }
+    }
+  }
+  if constexpr (MODE == DS_MR) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) red[i] = wave_sum(red[i]);
+    if ((threadIdx.x & 63) == 0) {
+      double *p = partials + ((size_t)rhs * gridDim.x + blockIdx.x) * 3;
+      p[0] = red[0];
+      p[1] = red[1];
+      p[2] = red[2];
+    }
+  }
+}
+
+#ifndef MG_MRHS_K
+#define MG_MRHS_K 0
+#endif
+// K right-hand sides per thread (256-site workgroups): the links of a site
+// are loaded once for all K; workgroups of one group of K right-hand sides
+// cover the lattice, grid.y = groups.  A ragged last group repeats its last
+// right-hand side in the spare slots and stores only the valid ones.
+template <typename R, int MODE, int NL, typename S, int K, typename TI = c_t<R>>
+__global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash_rb(Geom g, const S *__restrict__ U, const TI *__restrict__ in,
+                                                   c_t<R> *__restrict__ out, const c_t<R> *__restrict__ b, R diag,
+                                                   double *__restrict__ partials, int nrhs) {
+  using C = c_t<R>;
+  const int r0 = blockIdx.y * K;
+  const int kv = nrhs - r0 < K ? nrhs - r0 : K;
+  const size_t vs = (size_t)12 * g.Vpad;
+  const uint32_t blk = visit_block(blockIdx.x, gridDim.x, g, blockDim.x);
+  const uint32_t s = blk * blockDim.x + threadIdx.x;
+  double red[K][3];
+#pragma unroll
+  for (int k = 0; k < K; ++k) red[k][0] = red[k][1] = red[k][2] = 0.0;
+  if (s < g.V) {
+    C res[K][12], ctr[K][12];
+    dslash_site_k<K, NL, C>(res, ctr, g, s, U, in + (size_t)r0 * vs, vs, kv, diag);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (k >= kv) break;
+      const size_t off = (size_t)(r0 + k) * vs;
+      if constexpr (MODE == DS_RESID) {
+#pragma unroll
+        for (int i = 0; i < 12; ++i) res[k][i] = csub(b[off + fidx(s, i, 12)], res[k][i]);
+      }
+#pragma unroll
+      for (int i = 0; i < 12; ++i) {
+        __builtin_nontemporal_store(res[k][i].x, &out[off + fidx(s, i, 12)].x);
+        __builtin_nontemporal_store(res[k][i].y, &out[off + fidx(s, i, 12)].y);
+      }
+      if constexpr (MODE == DS_MR) {
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+          red[k][0] += (double)res[k][i].x * ctr[k][i].x + (double)res[k][i].y * ctr[k][i].y;
+          red[k][1] += (double)res[k][i].x * ctr[k][i].y - (double)res[k][i].y * ctr[k][i].x;
+          red[k][2] += (double)res[k][i].x * res[k][i].x + (double)res[k][i].y * res[k][i].y;
+        }
+      }
+    }
+  }
+  if constexpr (MODE == DS_MR) {
+    __shared__ double lds[4 * 3 * K];
+    double v[3 * K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) v[3 * k + q] = red[k][q];
+    block_sum<3 * K>(v, lds);
+    if (threadIdx.x == 0) {
+      for (int k = 0; k < kv; ++k) {
+        double *p = partials + ((size_t)(r0 + k) * gridDim.x + blockIdx.x) * 3;
+        p[0] = v[3 * k];
+        p[1] = v[3 * k + 1];
+        p[2] = v[3 * k + 2];
+      }
+    }
+  }
+}
+
+constexpr int mrhs_k(int prec_bytes) { return MG_MRHS_K == 4 && prec_bytes == 8 ? 2 : MG_MRHS_K; }
+
 int dslash_blocks(const Geom &g) { return div_up(g.V, 256); }
+int dslash_partials(const Geom &g, int nrhs) {
+  return (nrhs > 1 && MG_MRHS_K == 0) ? (int)(g.Vpad / TILE) : dslash_blocks(g);
+}
+
+template <typename R, int NL, typename S, int K>
+static hipError_t launch_rb(const Geom &g, const S *U, const c_t<R> *in, c_t<R> *out, const c_t<R> *b, double diag,
+                            int nrhs, DslashMode mode, double *partials, hipStream_t st) {
+  dim3 grid(dslash_blocks(g), (nrhs + K - 1) / K);
+  switch (mode) {
+    case DS_PLAIN:
+      hipLaunchKernelGGL((k_dslash_rb<R, DS_PLAIN, NL, S, K>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag,
+                         partials, nrhs);
+      break;
+    case DS_RESID:
+      hipLaunchKernelGGL((k_dslash_rb<R, DS_RESID, NL, S, K>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag,
+                         partials, nrhs);
+      break;
+    case DS_MR:
+      hipLaunchKernelGGL((k_dslash_rb<R, DS_MR, NL, S, K>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag,
+                         partials, nrhs);
+      break;
+  }
+  return hipGetLastError();
+}
 
 template <typename R, int NL, typename S>
 static hipError_t launch(const Geom &g, const S *U, const c_t<R> *in, c_t<R> *out, const c_t<R> *b, double diag,
                          int nrhs, DslashMode mode, double *partials, hipStream_t st) {
+  if constexpr (MG_MRHS_K > 0) {
+    if (nrhs > 1) {
+      constexpr int K = mrhs_k(sizeof(R));
+      return launch_rb<R, NL, S, K>(g, U, in, out, b, diag, nrhs, mode, partials, st);
+    }
+  }
+  if (nrhs > 1) {
+    const int grp = nrhs < MRHS_GROUP ? nrhs : MRHS_GROUP;
+    dim3 grid(g.Vpad / TILE, (nrhs + grp - 1) / grp), block(64 * grp);
+    switch (mode) {
+      case DS_PLAIN:
+        hipLaunchKernelGGL((k_dslash_mrhs<R, DS_PLAIN, NL, S>), grid, block, 0, st, g, U, in, out, b, (R)diag,
+                           partials, nrhs);
+        break;
+      case DS_RESID:
+        hipLaunchKernelGGL((k_dslash_mrhs<R, DS_RESID, NL, S>), grid, block, 0, st, g, U, in, out, b, (R)diag,
+                           partials, nrhs);
+        break;
+      case DS_MR:
+        hipLaunchKernelGGL((k_dslash_mrhs<R, DS_MR, NL, S>), grid, block, 0, st, g, U, in, out, b, (R)diag,
+                           partials, nrhs);
+        break;
+    }
+    return hipGetLastError();
+  }
   dim3 grid(dslash_blocks(g), nrhs);
   switch (mode) {
     case DS_PLAIN:
@@ -163,6 +431,29 @@ hipError_t dslash(const Geom &g, const S *U, int nl, const c_t<R> *in, c_t<R> *o
                   int nrhs, DslashMode mode, double *partials, hipStream_t st) {
   if (nl == 6) return launch<R, 6, S>(g, U, in, out, b, diag, nrhs, mode, partials, st);
   return launch<R, 9, S>(g, U, in, out, b, diag, nrhs, mode, partials, st);
+}
+
+// Plain stencil in FP64 arithmetic on FP32-stored input spinors (the
+// flexible GCR applies D to the preconditioner's FP32 output this way).
+template <int NL>
+static hipError_t launch_in32(const Geom &g, const double2 *U, const float2 *in, double2 *out, double diag,
+                              int nrhs, hipStream_t st) {
+  if (nrhs > 1) {
+    const int grp = nrhs < MRHS_GROUP ? nrhs : MRHS_GROUP;
+    dim3 grid(g.Vpad / TILE, (nrhs + grp - 1) / grp), block(64 * grp);
+    hipLaunchKernelGGL((k_dslash_mrhs<double, DS_PLAIN, NL, double2, float2>), grid, block, 0, st, g, U, in, out,
+                       nullptr, diag, nullptr, nrhs);
+  } else {
+    hipLaunchKernelGGL((k_dslash<double, DS_PLAIN, NL, double2, float2>), dim3(dslash_blocks(g), 1), dim3(256), 0,
+                       st, g, U, in, out, nullptr, diag, nullptr);
+  }
+  return hipGetLastError();
+}
+
+hipError_t dslash_in32(const Geom &g, const double2 *U, int nl, const float2 *in, double2 *out, double diag,
+                       int nrhs, hipStream_t st) {
+  if (nl == 6) return launch_in32<6>(g, U, in, out, diag, nrhs, st);
+  return launch_in32<9>(g, U, in, out, diag, nrhs, st);
 }
 
 // ---------------------------------------------------------------- links

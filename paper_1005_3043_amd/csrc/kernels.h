@@ -22,17 +22,23 @@ template <typename T> hipError_t pack_gauge(const Geom &g, const double2 *canon,
 enum DslashMode { DS_PLAIN = 0, DS_RESID = 1, DS_MR = 2 };
 // out = diag*in - 1/2 hop(in)              (DS_PLAIN)
 // out = b - (diag*in - 1/2 hop(in))        (DS_RESID)
-// out = D in; partials[blk] += (<out,in>, ||out||^2)  (DS_MR, 3 doubles / block)
+// out = D in; partials[slot] = (<out,in>, ||out||^2)  (DS_MR, 3 doubles per slot,
+//   dslash_partials(g, nrhs) slots per right-hand side)
 // R = arithmetic precision of vectors and accumulation, S = link storage
 // (double2, float2 or chalf).
 template <typename R, typename S>
 hipError_t dslash(const Geom &g, const S *U, int nl, const c_t<R> *in, c_t<R> *out, const c_t<R> *b, double diag,
                   int nrhs, DslashMode mode, double *partials, hipStream_t st);
+// out = D in (DS_PLAIN) in FP64 arithmetic on FP32-stored input spinors
+hipError_t dslash_in32(const Geom &g, const double2 *U, int nl, const float2 *in, double2 *out, double diag,
+                       int nrhs, hipStream_t st);
 // Uc = first two rows of every link of U (full FP64 links) in storage type S;
 // blockmax[blk] = max |row2 - conj(row0 x row1)| (dslash_blocks(g) entries).
 template <typename S>
 hipError_t compress_links(const Geom &g, const double2 *U, S *Uc, double *blockmax, hipStream_t st);
-int dslash_blocks(const Geom &g);  // number of partial slots per RHS of DS_MR
+int dslash_blocks(const Geom &g);  // 256-site workgroups of the single-RHS stencil
+// number of DS_MR partial slots per right-hand side for a launch of nrhs
+int dslash_partials(const Geom &g, int nrhs);
 
 // ---- blas.hip
 template <typename R> hipError_t zero(c_t<R> *x, size_t n, hipStream_t st);

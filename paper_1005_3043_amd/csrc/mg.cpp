@@ -48,8 +48,8 @@ size_t np_coarse(const Level &L) { return (size_t)L.g.V * coarse_split(L.n, L.g.
 
 // Partial-sum slots needed by a batch of nrhs vectors on every level.
 size_t part_need(mg_ctx *c, int nrhs) {
-  size_t m = (size_t)RED_BLOCKS * 2 * GCR_CHUNK;
-  m = std::max(m, (size_t)dslash_blocks(c->lev[0].g) * 3);
+  size_t m = (size_t)RED_BLOCKS * (4 * GCR_CHUNK + 3);  // FGCR inner-product pass
+  m = std::max(m, (size_t)dslash_partials(c->lev[0].g, nrhs) * 3);
   for (int l = 1; l < c->nlev; ++l) m = std::max(m, np_coarse(c->lev[l]) * 3);
   return m * (size_t)nrhs;
 }
@@ -180,7 +180,9 @@ template const void *cop_t_of_level<PF64>(mg_ctx *, Level &, hipStream_t);
 template const void *cop_t_of_level<PF32>(mg_ctx *, Level &, hipStream_t);
 template const void *cop_t_of_level<PF16>(mg_ctx *, Level &, hipStream_t);
 
-int np_mr(mg_ctx *c, int l) { return l == 0 ? dslash_blocks(c->lev[0].g) : (int)np_coarse(c->lev[l]); }
+int np_mr(mg_ctx *c, int l, int nrhs) {
+  return l == 0 ? dslash_partials(c->lev[0].g, nrhs) : (int)np_coarse(c->lev[l]);
+}
 
 // kernel-class index of the timers: 2 * precision id + (coarse ? 1 : 0)
 template <typename P> constexpr int tclass(bool coarse) { return 2 * P::id + (coarse ? 1 : 0); }
@@ -434,7 +436,7 @@ int mr(mg_ctx *c, int l, vec_t<P> *x, vec_t<P> *r, vec_t<P> *q, int steps, bool 
   if (steps == 0 && !accumulate) HIPK(zero<R>(x, n * nrhs, st));
   for (int k = 0; k < steps; ++k) {
     MG_TRY(apply_A<P>(c, l, r, q, nrhs, DS_MR, nullptr, st));
-    HIPK(mr_update<R>(x, r, q, n, nrhs, c->part, np_mr(c, l), c->p.omega, c->csc, (!accumulate && k == 0) ? 1 : 0,
+    HIPK(mr_update<R>(x, r, q, n, nrhs, c->part, np_mr(c, l, nrhs), c->p.omega, c->csc, (!accumulate && k == 0) ? 1 : 0,
                       st));
   }
   return MG_OK;
@@ -733,6 +735,7 @@ int cgnr_whole(mg_ctx *c, int l, vec_t<P> *e, hipStream_t st, bool &ran, bool &r
       // beside other work on the device): this (level, precision) takes the
       // chunks from now on, and the caller solves again from b with them
       c->cgp_off[l][pc] = 1;
+      c->n_cg_fallback += 1;
       ran = false;
       retry = true;
       return MG_OK;
@@ -879,15 +882,27 @@ int precondition(mg_ctx *c, const double2 *r, double2 *z, int nrhs, hipStream_t 
 }
 
 // ------------------------------------------------------------ FGCR
-int fgcr(mg_ctx *c, const double2 *b, double2 *x, int nrhs, double tol, int *iters, double *relres,
-         hipStream_t st) {
+// Flexible GCR(m) in FP64 preconditioned by one V-cycle per step, with the
+// solution update deferred to the end of each restart cycle (gcr.hip): the
+// preconditioner writes z_j straight into Z in its own precision (FP64 for
+// the FP64 preconditioner, FP32 otherwise), D z_j is taken in FP64, w_j is
+// orthogonalised against the earlier directions by classical Gram-Schmidt
+// (all inner products in one pass, one update pass), the residual moves
+// along it, and x = x + Z c once per cycle.  Converged right-hand sides are
+// frozen (skip flags); the host reads ||r||^2 once per step for the
+// decision.  At the end of every cycle the true residual b - D x replaces
+// the recursive one.
+template <typename TZ>
+static int fgcr_t(mg_ctx *c, const double2 *b, double2 *x, int nrhs, double tol, int *iters, double *relres,
+                  TZ *Z, hipStream_t st) {
   Level &L0 = c->lev[0];
   const size_t n = L0.vsize();
   const size_t nn = n * nrhs;
-  const int restart = c->p.gcr_restart;
-  double2 *r = c->gr, *Z = c->gZ, *W = c->gW;
+  const int m = c->p.gcr_restart;
+  constexpr bool f32z = sizeof(TZ) == 8;
+  double2 *r = c->gr, *W = c->gW;
+  float2 *r32 = f32z ? c->gr32.p : nullptr;
   double *rr = c->dsc;
-  double2 *sc = c->csc;
   int *skip = c->skip;
   HIPK(zero<double>(x, nn, st));
   HIPK(copy<double>(r, b, nn, st));
@@ -912,24 +927,32 @@ int fgcr(mg_ctx *c, const double2 *b, double2 *x, int nrhs, double tol, int *ite
   bool all_conv = true;
   for (int i = 0; i < nrhs; ++i) all_conv = all_conv && hskip[i];
   while (!all_conv) {
-    for (int j = 0; j < restart; ++j) {
-      double2 *Zj = Z + (size_t)j * nn, *Wj = W + (size_t)j * nn;
-      MG_TRY(precondition(c, r, Zj, nrhs, st));
+    HIPK(hipMemsetAsync(c->gcnt, 0, sizeof(int) * MG_MAX_RHS, st));
+    if constexpr (f32z) HIPK((convert<float, double>(r32, r, nn, st)));
+    int used = 0;
+    for (int j = 0; j < m; ++j) {
+      TZ *Zj = Z + (size_t)j * nn;
+      double2 *Wj = W + (size_t)j * nn;
+      // z_j = K(r_j), written in the preconditioner's precision
+      c->n_vcyc += nrhs;
+      if constexpr (f32z) {
+        if (c->prec == MG_F16) MG_TRY(vcycle<PF16>(c, 0, r32, Zj, nrhs, st));
+        else MG_TRY(vcycle<PF32>(c, 0, r32, Zj, nrhs, st));
+      } else {
+        MG_TRY(vcycle<PF64>(c, 0, r, Zj, nrhs, st));
+      }
       {
         TimerScope ts(c, c->tm[0], st, (double)L0.g.V * nrhs);
-        HIPK((dslash<double, double2>(L0.g, L0.links64(), L0.nl, Zj, Wj, nullptr, 4.0 + c->mass, nrhs, DS_PLAIN,
-                                      nullptr, st)));
+        if constexpr (f32z)
+          HIPK(dslash_in32(L0.g, L0.links64(), L0.nl, Zj, Wj, 4.0 + c->mass, nrhs, st));
+        else
+          HIPK((dslash<double, double2>(L0.g, L0.links64(), L0.nl, Zj, Wj, nullptr, 4.0 + c->mass, nrhs,
+                                        DS_PLAIN, nullptr, st)));
       }
       c->n_fine += nrhs;
-      // classical Gram-Schmidt against the earlier directions, up to eight
-      // per pass (same result as the modified form up to rounding)
-      if (j == 0) HIPK(norm2<double>(Wj, n, nrhs, c->part, rr + MG_MAX_RHS, st));
-      for (int i0 = 0; i0 < j; i0 += GCR_CHUNK)
-        HIPK(gcr_cgs(W + (size_t)i0 * nn, Z + (size_t)i0 * nn, nn, std::min(GCR_CHUNK, j - i0), Wj, Zj, n, nrhs,
-                     sc + 512, skip, c->part, rr + MG_MAX_RHS, st));
-      HIPK(gcr_scale2(Wj, Zj, n, nrhs, rr + MG_MAX_RHS, skip, st));
-      HIPK(dot<double>(Wj, r, n, nrhs, c->part, sc, st));
-      HIPK(gcr_update(x, Zj, r, Wj, n, nrhs, sc, skip, c->part, rr, st));
+      HIPK(gcr2_step(W, nn, j, m, r, n, nrhs, c->gsc, c->gnu, c->gcnt, skip, c->part, st));
+      HIPK(gcr2_residual(r, W, nn, j, m, n, nrhs, c->gsc, skip, c->part, rr, r32, st));
+      used = j + 1;
       HIPK(hipMemcpyAsync(c->h_rr, rr, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
       HIPK(hipStreamSynchronize(st));
       ++total;
@@ -951,6 +974,8 @@ int fgcr(mg_ctx *c, const double2 *b, double2 *x, int nrhs, double tol, int *ite
       if (changed && !all) HIPK(hipMemcpyAsync(skip, hskip, sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
       if (all || total >= c->p.max_iter) break;
     }
+    // x += Z T^{-1} a over the steps of this cycle
+    HIPK(gcr2_solution<TZ>(x, Z, nn, used, m, n, nrhs, c->gsc, c->gnu, c->gcnt, st));
     // true residual r = b - D x
     {
       TimerScope ts(c, c->tm[0], st, (double)L0.g.V * nrhs);
@@ -975,6 +1000,33 @@ int fgcr(mg_ctx *c, const double2 *b, double2 *x, int nrhs, double tol, int *ite
     if (!all_conv && total >= c->p.max_iter) return MG_NOT_CONVERGED;
   }
   return MG_OK;
+}
+
+// Allocates the solver's outer buffers for nrhs right-hand sides.
+int ensure_fgcr(mg_ctx *c, int nrhs) {
+  const size_t n = c->lev[0].vsize() * nrhs;
+  const int m = c->p.gcr_restart;
+  MG_TRY(c->gx.alloc(n));
+  MG_TRY(c->gr.alloc(n));
+  MG_TRY(c->gb.alloc(n));
+  MG_TRY(c->gW.alloc(n * m));
+  if (c->prec == MG_F64) {
+    MG_TRY(c->gZ.alloc(n * m));
+  } else {
+    MG_TRY(c->gZf.alloc(n * m));
+    MG_TRY(c->gr32.alloc(n));
+  }
+  MG_TRY(c->gsc.alloc(MG_MAX_RHS * gcr_scalars_per_rhs(m)));
+  MG_TRY(c->gnu.alloc((size_t)MG_MAX_RHS * m));
+  MG_TRY(c->gcnt.alloc(MG_MAX_RHS));
+  MG_TRY(c->skip.alloc(MG_MAX_RHS));
+  return MG_OK;
+}
+
+int fgcr(mg_ctx *c, const double2 *b, double2 *x, int nrhs, double tol, int *iters, double *relres,
+         hipStream_t st) {
+  if (c->prec == MG_F64) return fgcr_t<double2>(c, b, x, nrhs, tol, iters, relres, c->gZ.p, st);
+  return fgcr_t<float2>(c, b, x, nrhs, tol, iters, relres, c->gZf.p, st);
 }
 
 // ------------------------------------------------------------ setup
@@ -1171,7 +1223,7 @@ int setup(mg_ctx *c, const void *U, hipStream_t st) {
   size_t pn = part_need(c, 1);
   for (int l = 0; l < c->nlev - 1; ++l) {
     const Level &Lv = c->lev[l];
-    const size_t per = (l == 0) ? (size_t)dslash_blocks(Lv.g) * 3 : np_coarse(Lv) * 3;
+    const size_t per = (l == 0) ? (size_t)dslash_partials(Lv.g, Lv.nv) * 3 : np_coarse(Lv) * 3;
     pn = std::max(pn, std::max(per, (size_t)RED_BLOCKS * 2) * Lv.nv);
   }
   MG_TRY(ensure_scalars(c, pn));
@@ -1229,7 +1281,8 @@ int setup(mg_ctx *c, const void *U, hipStream_t st) {
                           hipStream_t);                                                                          \
   template int transfer_restrict<P>(mg_ctx *, int, const vec_t<P> *, vec_t<P> *, int, hipStream_t);             \
   template int transfer_prolong<P>(mg_ctx *, int, const vec_t<P> *, vec_t<P> *, int, int, hipStream_t);       \
-  template int coarse_variant<P>(mg_ctx *, int, int, hipStream_t);
+  template int coarse_variant<P>(mg_ctx *, int, int, hipStream_t);                                              \
+  template int cgnr<P>(mg_ctx *, int, const vec_t<P> *, vec_t<P> *, int, hipStream_t);
 INST(PF64)
 INST(PF32)
 INST(PF16)

@@ -21,7 +21,9 @@ int transfer_restrict(mg_ctx *c, int l, const vec_t<P> *fine, vec_t<P> *coarse, 
 template <typename P>
 int transfer_prolong(mg_ctx *c, int l, const vec_t<P> *coarse, vec_t<P> *fine, int nrhs, int accumulate,
                      hipStream_t st);
+template <typename P> int cgnr(mg_ctx *c, int l, const vec_t<P> *b, vec_t<P> *e, int nrhs, hipStream_t st);
 template <typename P> int vcycle(mg_ctx *c, int l, const vec_t<P> *rin, vec_t<P> *x, int nrhs, hipStream_t st);
+int ensure_fgcr(mg_ctx *c, int nrhs);
 int fgcr(mg_ctx *c, const double2 *b, double2 *x, int nrhs, double tol, int *iters, double *relres,
          hipStream_t st);
 int precondition_at(mg_ctx *c, mg_prec_t prec, const double2 *r, double2 *z, int nrhs, hipStream_t st);

@@ -10,6 +10,9 @@ namespace mg {
 constexpr int RED_BLOCKS = 1024;  // fixed grid of generic reductions
 constexpr int CG_NS = 8;          // CGNR scalars per right-hand side
 constexpr int GCR_CHUNK = 8;      // FGCR directions orthogonalised against per pass
+// double2 scalars per right-hand side of the deferred-update FGCR (gcr.hip)
+// with restart length m: g_ij (m x m), a, e, c (m each), f
+__host__ __device__ constexpr size_t gcr_scalars_per_rhs(int m) { return (size_t)m * m + 3 * (size_t)m + 1; }
 
 // ---- solver_kernels.hip
 template <typename R>
@@ -32,6 +35,22 @@ hipError_t gcr_cgs(const double2 *W, const double2 *Z, size_t vs, int ni, double
                    int nrhs, double2 *sc, const int *skip, double *part, double *nrm2, hipStream_t st);
 hipError_t gcr_update(double2 *x, const double2 *z, double2 *r, const double2 *w, size_t n, int nrhs,
                       const double2 *sc, const int *skip, double *part, double *rr, hipStream_t st);
+// ---- gcr.hip: flexible GCR with the solution update deferred to the end of
+// each restart cycle.  Wh holds w_0 .. w_{m-1} (stride vs); w_j = D z_j on
+// entry to gcr2_step, which orthogonalises it against w^_0 .. w^_{j-1} in
+// place and derives a_j from the residual r_in; gcr2_residual moves r along
+// w^_j (rr[rhs] = ||r||^2; r32, if not null, receives r in FP32);
+// gcr2_solution adds the cycle's update Z T^{-1} a to x, over the cnt[rhs]
+// steps each right-hand side took (kmax = steps of the cycle).  gs: double2
+// [MG_MAX_RHS][gcr_scalars_per_rhs(m)], nu: double [MG_MAX_RHS][m].
+hipError_t gcr2_step(double2 *Wh, size_t vs, int j, int m, const double2 *r_in, size_t n, int nrhs,
+                     double2 *gs, double *nu, int *cnt, const int *skip, double *part, hipStream_t st);
+hipError_t gcr2_residual(double2 *r, const double2 *Wh, size_t vs, int j, int m, size_t n, int nrhs,
+                         const double2 *gs, const int *skip, double *part, double *rr, float2 *r32,
+                         hipStream_t st);
+template <typename TZ>
+hipError_t gcr2_solution(double2 *x, const TZ *Z, size_t vs, int kmax, int m, size_t n, int nrhs, double2 *gs,
+                         double *nu, const int *cnt, hipStream_t st);
 // Fused CGNR steps (no finisher kernels): scalars are re-derived from the
 // per-block partials by every consuming workgroup in a fixed order.
 hipError_t cg2_init(const double *part_b, int npb, int nrhs, double *cg, int *done, int *it, double tol,
@@ -257,6 +276,10 @@ struct mg_ctx {
   mg::Work<float> w32;
   // outer solver (FP64, fine level)
   mg::DevBuf<double2> gx, gr, gb, gZ, gW, gtmp;
+  mg::DevBuf<float2> gZf, gr32;  // FP32 preconditioned vectors and preconditioner input (FP32/FP16 precond)
+  mg::DevBuf<double2> gsc;       // deferred-update FGCR scalars
+  mg::DevBuf<double> gnu;
+  mg::DevBuf<int> gcnt;
   // GMRES relaxation scalars: Hessenberg matrices, least-squares
   // coefficients, ||b|| and column partials
   mg::DevBuf<double2> gmH, gmy;
@@ -264,7 +287,7 @@ struct mg_ctx {
   mg::DevBuf<int> skip;
   int gcr_rhs = 0;
   // statistics
-  long n_fine = 0, n_coarse = 0, n_coarse_disp = 0, n_cgnr = 0, n_vcyc = 0;
+  long n_fine = 0, n_coarse = 0, n_coarse_disp = 0, n_cgnr = 0, n_vcyc = 0, n_cg_fallback = 0;
   mg::EventTimer tm[8];  // (fine, coarse) x (FP64, FP32, FP16 storage), whole-solve CGNR (FP32, FP16)
   double t_setup = 0.0;
 };

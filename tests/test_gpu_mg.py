@@ -383,6 +383,9 @@ def test_cgnr_persistent_gives_up_cleanly(cuda):
           f"(fewer: a wait gave up and the chunks took over), outer {i1['iters'][0]} / {i2['iters'][0]}")
     assert rc1 == rc2 == 0
     assert whole >= 1  # the whole-solve launch was tried
+    assert i1["n_cgnr_fallbacks"] >= 1  # a wait gave up and the chunks redid that solve
+    assert whole < i1["n_vcycles"]      # and took over for the rest of the solve
+    assert i2["n_cgnr_fallbacks"] == 0
     assert i1["iters"] == i2["iters"] and i1["n_cgnr_iters"] == i2["n_cgnr_iters"]
     assert torch.equal(x1, x2)
 

@@ -118,3 +118,19 @@ def test_c_matvec_matches_numpy():
         a = wi.apply_D(U, psi, -0.3, anti)
         b = cref.apply_D(U, psi, -0.3, anti)
         assert np.abs(a - b).max() < 1e-13 * np.abs(a).max()
+
+
+def test_sampled_sites_match_full_operator():
+    """The per-site evaluation of Eq. (2) agrees with the full operator at
+    every site of a small lattice (both time boundary conditions, a batch of
+    two spinors)."""
+    L = (4, 6, 2, 8)
+    U = W.gauge_field(L, 0.3, 3)
+    psi = W.gaussian_spinor(L, 4, batch=(2,))
+    sites = np.array([(x, y, z, t) for t in range(L[3]) for z in range(L[2]) for y in range(L[1])
+                      for x in range(L[0])])
+    for anti in (True, False):
+        full = wi.apply_D(U, psi, -0.3, anti)
+        part = wi.apply_D_sites(U, psi, -0.3, sites, anti)
+        ref = full.reshape(2, -1, 4, 3)
+        assert np.abs(part - ref).max() < 1e-14
