@@ -1,24 +1,26 @@
 #!/usr/bin/env python
 """Benchmark of the adaptive-MG Wilson-Dirac hot path on one MI355X.
 
-One step = one pass of the whole hot path on the two-level 16^3 x 32 workload
-(random SU(3) links of generator width eps = 0.3, mass for min Re lambda(D) =
-0.01 from the oracle's Arnoldi estimate, aggregates 4^4, Nv = 20, one complex
-Gaussian right-hand side): mg_setup (null-vector relaxation, block
-orthonormalisation, Galerkin D_c) followed by mg_solve to a 1e-10 relative
-residual with the mixed-precision preconditioner (FP16-stored operators and
-FP32 arithmetic by default; FP64 outer FGCR).  Inputs are generated on the
-host and resident in device memory before the timed region.
+One step = one pass of the whole hot path on the three-level 32^3 x 64
+workload (random SU(3) links of generator width eps = 0.35, the mass of
+nominal min Re lambda(D) = 0.1, aggregates 4^4 then 2^4, Nv = 24 on both
+levels, the 12 spin-colour point sources at the origin): mg_setup (null-vector
+relaxation, block orthonormalisation, Galerkin D_c on both levels) followed
+by one batched mg_solve of all 12 sources to a 1e-10 relative residual with
+the FP32 preconditioner (FP64 outer flexible GCR).  Inputs are generated on
+the host and resident in device memory before the timed region.
 
-Prints one JSON line: the step throughput, time-to-solution against plain
-FP64 MG on the same setup, the roofline of the dominant kernel of the timed
-solves (device time from HIP events on the library's stream), the fine
-stencil on 32^3 x 64 (working set above the last-level cache) and the CPU
-oracle on a bounded sample.
+Prints one JSON line: right-hand sides solved per second, the plain FP64
+single-RHS MG on the same setup (each source on its own), the FP16-stored
+preconditioner, the lightest nominal mass with the paper's setup stage two,
+the roofline of the dominant kernel of the timed steps (device time from HIP
+events on the library's stream), the fine stencil on 32^3 x 64 with one
+right-hand side, the two-level 16^3 x 32 workload, and the CPU oracle on a
+bounded sample.
 
 --kernel-probe runs fixed launches of the profiled kernels (a 1 GiB device
-copy for counter calibration, the coarse stencil of the workload in every
-precision, the 32^3 x 64 fine stencil) for rocprofv3 counter runs.
+copy for counter calibration, the 32^3 x 64 fine stencil with 12 and 1
+right-hand sides in each precision class) for rocprofv3 counter runs.
 """
 from __future__ import annotations
 
@@ -33,8 +35,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-WORKLOAD = "C1"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "coarse_c1_traffic.txt")
+HEADLINE_TARGET = 0.1   # nominal min Re lambda of the headline 32^3 x 64 step
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dslash_c3_12rhs_traffic.txt")
+# kernel name in the counter summary for each precision class of the stencil
+TRAFFIC_KERNEL = {"f64": "dslash_f64_12rhs", "f32": "dslash_f32_12rhs", "f16": "dslash_f16_12rhs"}
 
 # bytes per real of (vectors, operators) for each precision class; "f16"
 # keeps FP32 vectors and stores the operators (links, P, D_c) in binary16
@@ -68,44 +72,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precond", default="f16", choices=["f64", "f32", "f16"])
+    ap.add_argument("--precond", default="f32", choices=["f64", "f32", "f16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-c1", action="store_true")
     ap.add_argument("--kernel-probe", action="store_true")
-    ap.add_argument("--workload", default="C1", choices=["C1", "C2", "C3"],
-                    help="C1: the benchmark step; C2: 12 batched point sources on 24^3x48 against 12 plain "
-                         "FP64 single-RHS solves; C3: three-level 32^3x64, 12 point sources, mass sweep")
+    ap.add_argument("--workload", default="C3", choices=["C3", "C1", "C2", "C3sweep"],
+                    help="C3: the benchmark step (three-level 32^3x64, 12 batched point sources); C1: two-level "
+                         "16^3x32, one source; C2: 12 batched point sources on 24^3x48 against 12 plain FP64 "
+                         "single-RHS solves; C3sweep: 32^3x64 at the three nominal masses")
     return ap.parse_args()
-
-
-def workload(torch, W):
-    cfg = W.CONFIGS[WORKLOAD]
-    L = cfg["L"]
-    U_np = W.gauge_field(L, cfg["eps"], cfg["seed"])
-    b_np = W.gaussian_spinor(L, cfg["seed"])
-    st_np = W.setup_starts(L, cfg["nv"][0], cfg["seed"])
-    dev = torch.device("cuda:0")
-    return cfg, U_np, b_np, torch.from_numpy(U_np).to(dev), torch.from_numpy(b_np).to(dev), \
-        torch.from_numpy(st_np).to(dev)
-
-
-def cpu_baseline(U_np, psi_np, mass, n_d_per_step):
-    """Numpy FP64 oracle Wilson operator on the workload lattice; the oracle's
-    step rate is bounded above by 1 / (fine-D applications per step x time
-    per application)."""
-    from oracle import wilson as wi
-    wi.apply_D(U_np, psi_np, mass)
-    n, t0 = 0, time.perf_counter()
-    while n < 3 or time.perf_counter() - t0 < 15.0:
-        wi.apply_D(U_np, psi_np, mass)
-        n += 1
-    dt = (time.perf_counter() - t0) / n
-    return {"value": round(1.0 / (n_d_per_step * dt), 6), "unit": "solves/s (upper bound)", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{n} applications of the numpy FP64 oracle Wilson operator on 16^3x32 "
-                      f"({dt * 1e3:.0f} ms each, numpy elementwise work on one core); rate = 1 / "
-                      f"({n_d_per_step} fine-D applications per step, setup + solve, as counted on the "
-                      f"GPU run x time per application), ignoring the oracle's coarse-level work"}
 
 
 def random_su3(torch, shape, g):
@@ -179,7 +155,12 @@ def stored_traffic(kernel, workload_name):
 
 
 def kernel_probe(mgwd, torch, W):
-    """Fixed launches for counter runs (one process, printed as they go)."""
+    """Fixed launches for counter runs, printed as they go: a 1 GiB device copy
+    (counter calibration), then on the 32^3 x 64 workload (its links, the
+    headline setup) the fine stencil with 12 right-hand sides per launch in
+    each precision class, as the benchmark step launches it (the step's MR
+    launches add per-tile partial sums, 24 bytes per tile and right-hand
+    side), and with one right-hand side."""
     n = 1 << 27  # 1 GiB of float64
     a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
@@ -188,36 +169,18 @@ def kernel_probe(mgwd, torch, W):
     torch.cuda.synchronize()
     print(json.dumps({"probe": "copy", "bytes_read": n * 8, "bytes_written": n * 8, "launches": 5}), flush=True)
     del a, b
-    cfg, U_np, b_np, U, b, starts = workload(torch, W)
-    ctx = mgwd.MG(U, W.mass_for(WORKLOAD), cfg["blocks"], cfg["nv"], [starts])
+    cfg = W.CONFIGS["C3"]
+    L, nv, blocks = cfg["L"], cfg["nv"], cfg["blocks"]
+    U = torch.from_numpy(W.gauge_field(L, cfg["eps"], cfg["seed"])).cuda()
+    st = torch.from_numpy(W.setup_starts(L, nv[0], cfg["seed"])).cuda()
+    Lc = tuple(L[mu] // blocks[0][mu] for mu in range(4))
+    st1 = torch.from_numpy(W.coarse_setup_starts(Lc, 2 * nv[0], nv[1], cfg["seed"])).cuda()
+    ctx = mgwd.MG(U, W.mass_for("C3", HEADLINE_TARGET), blocks, nv, [st, st1], max_rhs=12)
     for prec in ("f64", "f32", "f16"):
-        ms = ctx.time_coarse(1, prec, 1, 20)
-        print(json.dumps({"probe": f"coarse_{prec}", "launches": 22, "avg_ms": ms}), flush=True)
+        for nrhs in (12, 1):
+            ms = ctx.time_dslash(prec, nrhs, 10)
+            print(json.dumps({"probe": f"dslash_{prec}_{nrhs}rhs", "launches": 12, "avg_ms": ms}), flush=True)
     ctx.close()
-    Lg, lctx = large_ctx(mgwd, torch)
-    for prec in ("f64", "f32", "f16"):
-        ms = lctx.time_dslash(prec, 1, 20)
-        print(json.dumps({"probe": f"dslash_{prec}_32^3x64", "launches": 22, "avg_ms": ms}), flush=True)
-    lctx.close()
-    # 24^3x48 with 12 right-hand sides: the matrix-core coarse stencil (tuned
-    # K split) and the matrix-core restriction / prolongation, FP16-stored
-    cfg2 = W.CONFIGS["C2"]
-    L2 = cfg2["L"]
-    U2 = torch.from_numpy(W.gauge_field(L2, cfg2["eps"], cfg2["seed"])).cuda()
-    st2 = torch.from_numpy(W.setup_starts(L2, cfg2["nv"][0], cfg2["seed"])).cuda()
-    ctx2 = mgwd.MG(U2, W.mass_for("C2"), cfg2["blocks"], cfg2["nv"], [st2], max_rhs=12, precond_prec="f16")
-    ms = ctx2.time_coarse(1, "f16", 12, 20)
-    var, us = ctx2.coarse_variant(1, "f16", 12)
-    print(json.dumps({"probe": "coarse_f16_12rhs_24^3x48", "launches": 22, "avg_ms": ms, "variant": var}), flush=True)
-    r12 = torch.from_numpy(W.point_sources(L2)).cuda()
-    ec12 = ctx2.transfer(0, r12, 0, "f16")
-    ctx2.set_transfer_variant(1)
-    for _ in range(10):
-        ctx2.transfer(0, r12, 0, "f16")
-        ctx2.transfer(0, ec12, 1, "f16")
-    torch.cuda.synchronize()
-    print(json.dumps({"probe": "transfer_mma_f16_12rhs_24^3x48", "launches": 10}), flush=True)
-    ctx2.close()
 
 
 def multi_rhs_report(mgwd, torch, W):
@@ -335,6 +298,62 @@ def three_level_report(mgwd, torch, W):
             "dslash_32^3x64": large_dslash(mgwd, torch)}
 
 
+def oracle_baseline(U3_np, mass3, n_d_step, nrhs):
+    """The CPU oracle timed on this host: one full C0 setup + solve with the
+    numpy oracle, and the oracle's C operator (OpenMP) on the 32^3 x 64
+    lattice; the rate for the headline step is bounded above by nrhs / (fine-D
+    applications of the step x time per application), which leaves out all
+    coarse-level and vector work (about a tenth of the oracle's C0 time)."""
+    import numpy as np
+
+    import workloads as W
+    from oracle import cref
+    from oracle import solvers as so
+    from oracle import wilson as wi
+
+    cfg = W.CONFIGS["C0"]
+    L = cfg["L"]
+    U = W.gauge_field(L, cfg["eps"], cfg["seed"])
+    m = W.mass_for("C0")
+    t0 = time.perf_counter()
+    h = so.mg_setup(U, m, so.MGParams(blocks=cfg["blocks"], nv=cfg["nv"]), W.setup_starts(L, cfg["nv"][0], cfg["seed"]))
+    t1 = time.perf_counter()
+    b = W.gaussian_spinor(L, cfg["seed"])
+    _, it0, conv0, _ = so.mg_solve(h, b, 1e-10)
+    t2 = time.perf_counter()
+    nD0 = h.stats["fine_D"]
+    tD0 = 0.0
+    for _ in range(3):
+        ta = time.perf_counter()
+        wi.apply_D(U, b, m)
+        tD0 += (time.perf_counter() - ta) / 3
+    psi = np.ascontiguousarray(W.gaussian_spinor(tuple(reversed(U3_np.shape[1:5])), 3))
+    cref.apply_D(U3_np, psi, mass3)
+    n, ta = 0, time.perf_counter()
+    while n < 3 or time.perf_counter() - ta < 5.0:
+        cref.apply_D(U3_np, psi, mass3)
+        n += 1
+    tD3 = (time.perf_counter() - ta) / n
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(nrhs / (n_d_step * tD3), 6), "unit": "right-hand sides/s (upper bound)",
+            "cores": threads, "kind": "oracle",
+            "sample": f"C0 (8^4, Nv 8) oracle setup + solve timed in full: {t1 - t0:.1f} s + {t2 - t1:.1f} s, "
+                      f"{it0} iterations, {nD0} fine-D applications in the solve ({nD0 * tD0 / (t2 - t1):.0%} of its "
+                      f"time); the oracle's C operator on 32^3x64 timed {n} times ({tD3:.3f} s each, OpenMP on "
+                      f"{threads} threads of {model or 'this host'}); rate = {nrhs} / ({n_d_step} fine-D "
+                      f"applications of the step x time per application), coarse work left out",
+            "cpu_model": model, "c0_setup_s": round(t1 - t0, 2), "c0_solve_s": round(t2 - t1, 2)}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -352,155 +371,195 @@ def main():
     if a.workload == "C2":
         print(json.dumps(multi_rhs_report(mgwd, torch, W)), flush=True)
         return
-    if a.workload == "C3":
+    if a.workload == "C3sweep":
         print(json.dumps(three_level_report(mgwd, torch, W)), flush=True)
         return
+    if a.workload == "C1":
+        print(json.dumps(c1_report(mgwd, torch, W, a)), flush=True)
+        return
 
-    cfg, U_np, b_np, U, b, starts = workload(torch, W)
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)  # noqa: E731
+    cfg = W.CONFIGS["C3"]
     L, nv, blocks = cfg["L"], cfg["nv"], cfg["blocks"]
-    mass = W.mass_for(WORKLOAD)
+    target = HEADLINE_TARGET
+    mass = W.mass_for("C3", target)
     V = L[0] * L[1] * L[2] * L[3]
-    n_c = 2 * nv[0]
-    Vc = V // 256
+    log("generating the 32^3x64 inputs")
+    U_np = W.gauge_field(L, cfg["eps"], cfg["seed"])
+    U = torch.from_numpy(U_np).cuda()
+    st = torch.from_numpy(W.setup_starts(L, nv[0], cfg["seed"])).cuda()
+    Lc = tuple(L[mu] // blocks[0][mu] for mu in range(4))
+    st1 = torch.from_numpy(W.coarse_setup_starts(Lc, 2 * nv[0], nv[1], cfg["seed"])).cuda()
+    b = torch.from_numpy(W.point_sources(L)).cuda()
+    nrhs = b.shape[0]
+    torch.cuda.synchronize()
 
-    def step(prec, timing):
-        ctx = mgwd.MG(U, mass, blocks, nv, [starts])
+    def setup(**kw):
+        return mgwd.MG(U, mass, blocks, nv, [st, st1], max_rhs=nrhs, precond_prec=a.precond, **kw)
+
+    def step(timing):
+        ctx = setup()
         ctx.set_timing(timing)
-        if prec != "f64":
-            ctx.set_precond_prec(prec)
         x, info, rc = ctx.solve(b, 1e-10)
         ctx.close()
         if rc != 0:
             raise RuntimeError("mg_solve did not converge")
         return x, info
 
-    for _ in range(a.warmup):
-        step(a.precond, True)
+    for i in range(a.warmup):
+        step(True)
+        log(f"warm-up step {i + 1}/{a.warmup} done")
     torch.cuda.synchronize()
     infos = []
     t0 = time.perf_counter()
-    for _ in range(a.steps):
-        x, info = step(a.precond, True)
+    for i in range(a.steps):
+        x, info = step(True)
         infos.append(info)
+        log(f"step {i + 1}/{a.steps} done")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) / a.steps * 1e3
 
-    # true residual of the last solution, FP64 on the GPU via the fine operator
+    # true residual of every right-hand side of the last step, FP64 on the GPU
     r = b - mgwd.wilson_apply(U, x, mass)
-    true_res = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b))
+    true_res = max(float(torch.linalg.vector_norm(r[i]) / torch.linalg.vector_norm(b[i])) for i in range(nrhs))
+    del r
 
-    # plain FP64 MG and the FP32 preconditioner on the same workload
-    _, info64 = step("f64", True)
-    _, info32 = step("f32", True)
+    # plain FP64 single-RHS MG on the same setup: every source on its own
+    ctx = setup()
+    ctx.set_precond_prec("f64")
+    t64, it64 = 0.0, []
+    for i in range(nrhs):
+        _, i1, rc1 = ctx.solve(b[i:i + 1].contiguous(), 1e-10)
+        if rc1 != 0:
+            raise RuntimeError("plain FP64 solve did not converge")
+        t64 += i1["t_solve_s"]
+        it64.append(i1["iters"][0])
+    log(f"plain FP64 MG, {nrhs} sources one at a time: {t64:.3f} s")
+    # the same batched solve with the FP16-stored preconditioner
+    ctx.set_precond_prec("f16")
+    _, i16, rc16 = ctx.solve(b, 1e-10)
+    ctx.close()
+    setup64_s = sum(i["t_setup_s"] for i in infos) / len(infos)
 
-    # the paper's setup stage two on the same workload (groups of 4 of the
-    # N_v prototypes, 5 truncated-MG GCR steps each, V-cycles in the
-    # preconditioner precision), reported beside the headline setup
+    # the lightest nominal mass with the paper's setup stage two
+    light = min(cfg["targets"])
     torch.cuda.synchronize()
-    t0r = time.perf_counter()
-    ctx_r = mgwd.MG(U, mass, blocks, nv, [starts], refine_group=4, refine_iters=5, precond_prec=a.precond)
+    tl0 = time.perf_counter()
+    ctx = mgwd.MG(U, W.mass_for("C3", light), blocks, nv, [st, st1], max_rhs=nrhs, precond_prec=a.precond,
+                  refine_group=8, refine_iters=5)
     torch.cuda.synchronize()
-    setup_r = time.perf_counter() - t0r
-    _, info_r, rc_r = ctx_r.solve(b, 1e-10)
-    ctx_r.close()
-    refined = {"refine_group": 4, "refine_iters": 5, "setup_s": round(setup_r, 4),
-               "time_to_solution_s": round(info_r["t_solve_s"], 4), "iters": info_r["iters"][0],
-               "converged": rc_r == 0}
+    setup_l = time.perf_counter() - tl0
+    _, il, rcl = ctx.solve(b, 1e-10)
+    ctx.close()
+    log(f"min Re lambda {light} with setup stage two: setup {setup_l:.2f} s, solve {il['t_solve_s']:.2f} s")
 
-    # kernel-class aggregates over the timed steps.  Every fine-stencil
-    # launch is timed; inside the captured CGNR chunks the event pairs sample
-    # the first iteration's two coarse launches of every chunk.  The coarse
-    # average launch time therefore comes from the sample, and its bytes per
-    # launch count only the effective applications among all dispatches
-    # (dispatches queued after a right-hand side converged return at once).
-    # Stencil applications made inside whole-solve CGNR launches count as
-    # applications, not dispatches, and are left out of the per-launch class.
+    # roofline of the dominant kernel class of the timed steps (device time
+    # from HIP events on the library's stream around every fine-stencil
+    # launch; coarse launches inside captured CGNR chunks are sampled)
     agg = {}
     for inf in infos:
-        in_whole = sum(d["sites"] for k, d in inf["kernels"].items() if k.startswith("cgnr")) / Vc
         for k, d in inf["kernels"].items():
-            e = agg.setdefault(k, {"ms": 0.0, "launches": 0, "sites": 0.0, "eff": 0.0})
+            e = agg.setdefault(k, {"ms": 0.0, "launches": 0, "sites": 0.0})
             e["ms"] += d["ms"]
             e["launches"] += d["launches"]
             e["sites"] += d["sites"]
-            if k.startswith("coarse") and d["launches"]:
-                e["eff"] += (inf["n_coarse_apply"] - in_whole) / max(inf["n_coarse_dispatch"], 1) * d["launches"]
-
-    def achieved(k):
-        e = agg[k]
-        if e["launches"] == 0 or e["ms"] == 0:
-            return None
-        prec = k.split("_")[1]
-        avg_us = e["ms"] * 1e3 / e["launches"]
-        if k.startswith("dslash"):
-            # the workload links are SU(3), so the stencil reads them as two rows
-            bpl = dslash_bytes(prec, True) * e["sites"] / e["launches"]
-            fpl = dslash_flops(True) * e["sites"] / e["launches"]
-        elif k.startswith("cgnr"):
-            # one launch = one whole coarsest CGNR: the operator read once
-            # (then held in registers), and per iteration and site the FP32
-            # vectors of both phases (reads z, p_old, r_old, w, p, e; writes
-            # p, w, r, z, e: 11 n complex) plus five partial sums
-            apps = e["sites"] / Vc / e["launches"]  # stencil applications per launch
-            wv, wl = WIDTH[prec]
-            bpl = (2 * 9 * n_c * n_c * wl + (apps / 2) * (11 * n_c * 2 * wv + 5 * 8)) * Vc
-            fpl = coarse_flops(n_c) * Vc * apps
-        else:
-            frac = e["eff"] / e["launches"]
-            bpl = coarse_bytes(n_c, prec) * Vc * frac
-            fpl = coarse_flops(n_c) * Vc * frac
-        return {"GBps": bpl / avg_us / 1e3, "TFLOPs": fpl / avg_us / 1e6, "avg_us": avg_us,
-                "launches": e["launches"], "bytes_per_launch": bpl, "total_ms": e["ms"]}
-
-    kern = {k: achieved(k) for k in agg if achieved(k) is not None}
-    # dominant kernel by estimated device time over all its dispatches
-    disp = {k: (infos[-1]["n_coarse_dispatch"] * len(infos) if k.startswith("coarse") else kern[k]["launches"])
-            for k in kern}
-    dom = max(kern, key=lambda k: kern[k]["avg_us"] * disp[k])
-    kd = kern[dom]
-    traffic = stored_traffic(dom, WORKLOAD)
-    roofline = {"bound": "hbm", "achieved": round(kd["GBps"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(kd["GBps"] / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": dom, "avg_launch_us": round(kd["avg_us"], 2),
-                "bytes_per_launch": round(kd["bytes_per_launch"])}
+    fine = {k: e for k, e in agg.items() if k.startswith("dslash") and e["launches"]}
+    dom = max(fine, key=lambda k: fine[k]["ms"])
+    e = fine[dom]
+    prec = dom.split("_")[1]
+    avg_us = e["ms"] * 1e3 / e["launches"]
+    rhs_per_launch = e["sites"] / e["launches"] / V
+    wv, wl = WIDTH[prec]
+    # algorithmic bytes per launch: each site's links (two rows) once, and
+    # per right-hand side the input spinor once and the output spinor once
+    bpl = V * (48 * wl + rhs_per_launch * 48 * wv)
+    fpl = V * rhs_per_launch * dslash_flops(True)
+    achieved = bpl / avg_us / 1e3
+    traffic = stored_traffic(TRAFFIC_KERNEL[prec], "C3")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                "kernel": f"fine Wilson stencil, {prec} class, {rhs_per_launch:.0f} right-hand sides per launch",
+                "avg_launch_us": round(avg_us, 2), "bytes_per_launch": round(bpl),
+                "TFLOPs": round(fpl / avg_us / 1e6, 2),
+                "device_ms_per_step": {k: round(v["ms"] / len(infos), 1) for k, v in agg.items() if v["launches"]}}
 
     solve_s = sum(i["t_solve_s"] for i in infos) / len(infos)
-    setup_s = sum(i["t_setup_s"] for i in infos) / len(infos)
-    dsl = {k: {"GBps": round(v["GBps"], 1), "avg_us": round(v["avg_us"], 2), "launches": v["launches"]}
-           for k, v in kern.items()}
-    n_d_setup = 5 * (1 + 4) * nv[0]
+    n_d_step = 5 * (1 + 4) * nv[0] + infos[-1]["n_fine_dslash"]
     out = {
         "metric": "dslash HBM GB/s; MG time-to-solution to 1e-10 rel. residual vs plain FP64 MG",
-        "value": round(1e3 / ms_step, 4),
-        "unit": "solves/s (mg_setup + mg_solve to 1e-10, one RHS)",
+        "value": round(nrhs * 1e3 / ms_step, 4),
+        "unit": "right-hand sides/s (mg_setup + one batched mg_solve of the 12 point sources to 1e-10)",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": round(ms_step, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64 outer / " + {"f16": "f16-stored operators, f32 arithmetic", "f32": "f32",
                                    "f64": "f64"}[a.precond] + " preconditioner",
-        "data": "synthetic (seeded random SU(3) links, Gaussian source)",
-        "config": {"workload": f"two-level MG, {L[0]}^3x{L[3]}, eps {cfg['eps']}, min Re lambda "
-                               f"{cfg['targets'][0]}, aggregates 4^4, Nv {nv[0]}, 1 RHS",
+        "data": "synthetic (seeded random SU(3) links, 12 spin-colour point sources at the origin)",
+        "config": {"workload": f"three-level MG, 32^3x64, eps {cfg['eps']}, aggregates 4^4 then 2^4, Nv 24/24, "
+                               f"12 point sources batched, nominal min Re lambda {target}",
                    "mass": mass, "precond": a.precond},
         "time_to_solution_s": round(solve_s, 4),
-        "setup_s": round(setup_s, 4),
-        "fp64_plain_time_to_solution_s": round(info64["t_solve_s"], 4),
-        "fp32_time_to_solution_s": round(info32["t_solve_s"], 4),
-        "speedup_vs_plain_fp64": round(info64["t_solve_s"] / solve_s, 3),
-        "iters": infos[-1]["iters"][0], "iters_fp64": info64["iters"][0], "iters_fp32": info32["iters"][0],
-        "true_rel_resid": true_res,
+        "setup_s": round(setup64_s, 4),
+        "iters": infos[-1]["iters"][:nrhs],
+        "true_rel_resid_max": true_res,
+        "plain_fp64_single_rhs": {"time_to_solution_s": round(t64, 3), "iters": it64,
+                                  "speedup_of_batched": round(t64 / solve_s, 2)},
+        "f16_batched_time_to_solution_s": round(i16["t_solve_s"], 4) if rc16 == 0 else None,
+        "lightest_mass_setup_stage_two": {"min_re_lambda_nominal": light, "setup_s": round(setup_l, 3),
+                                          "time_to_solution_s": round(il["t_solve_s"], 3),
+                                          "iters_max": max(il["iters"][:nrhs]), "converged": rcl == 0},
         "fine_dslash_per_solve": infos[-1]["n_fine_dslash"],
         "cgnr_iters_per_solve": infos[-1]["n_cgnr_iters"],
-        "kernels": dsl,
-        "setup_stage_two": refined,
         "roofline": roofline,
     }
     if not a.no_large:
         out["dslash_32^3x64"] = large_dslash(mgwd, torch)
+    if not a.no_c1:
+        out["c1_two_level"] = c1_report(mgwd, torch, W, a, steps=5, warmup=1, quiet=True)
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(U_np, b_np, mass, n_d_setup + infos[-1]["n_fine_dslash"])
+        out["cpu_baseline"] = oracle_baseline(U_np, mass, n_d_step, nrhs)
     print(json.dumps(out), flush=True)
+
+
+def c1_report(mgwd, torch, W, a, steps=None, warmup=None, quiet=False):
+    """The two-level 16^3 x 32 workload (Nv 20, one Gaussian source,
+    FP16-stored preconditioner): setup + solve per step, and plain FP64 MG
+    on the same setup."""
+    steps = a.steps if steps is None else steps
+    warmup = a.warmup if warmup is None else warmup
+    cfg = W.CONFIGS["C1"]
+    L, nv, blocks = cfg["L"], cfg["nv"], cfg["blocks"]
+    mass = W.mass_for("C1")
+    U = torch.from_numpy(W.gauge_field(L, cfg["eps"], cfg["seed"])).cuda()
+    b = torch.from_numpy(W.gaussian_spinor(L, cfg["seed"])).cuda()
+    st = torch.from_numpy(W.setup_starts(L, nv[0], cfg["seed"])).cuda()
+
+    def step(prec):
+        ctx = mgwd.MG(U, mass, blocks, nv, [st])
+        if prec != "f64":
+            ctx.set_precond_prec(prec)
+        x, info, rc = ctx.solve(b, 1e-10)
+        ctx.close()
+        if rc != 0:
+            raise RuntimeError("mg_solve did not converge")
+        return info
+
+    for _ in range(warmup):
+        step("f16")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [step("f16") for _ in range(steps)]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    i64 = step("f64")
+    solve = sum(i["t_solve_s"] for i in infos) / len(infos)
+    return {"workload": f"two-level MG, 16^3x32, eps {cfg['eps']}, min Re lambda {cfg['targets'][0]}, Nv {nv[0]}, "
+                        f"1 Gaussian source, f16-stored preconditioner",
+            "steps_per_s": round(1e3 / ms, 3), "ms_per_step": round(ms, 2), "time_to_solution_s": round(solve, 4),
+            "fp64_plain_time_to_solution_s": round(i64["t_solve_s"], 4),
+            "speedup_vs_plain_fp64": round(i64["t_solve_s"] / solve, 2), "iters": infos[-1]["iters"][0],
+            "iters_fp64": i64["iters"][0]}
 
 
 if __name__ == "__main__":

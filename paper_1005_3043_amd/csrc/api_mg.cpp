@@ -209,6 +209,7 @@ extern "C" int mg_set_transfer_variant(mg_ctx_t *ctx, int variant) {
   if (variant != -1 && variant != 0 && variant != 1)
     return bad(MG_EINVAL, "mg_set_transfer_variant: variant must be -1, 0 or 1");
   ctx->tvar_force = variant;
+  clear_graphs(ctx);
   return MG_OK;
 }
 

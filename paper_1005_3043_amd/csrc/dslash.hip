@@ -6,11 +6,11 @@
 // The spin projection (wilson_site.h) reduces each hop to a half spinor and
 // two SU(3) mat-vecs: 1320 flops per site for all eight hops.
 //
-// One thread per site of the site-blocked, tile-interleaved layout.  The loop
-// over mu is rolled (wave-uniform): both hops of one direction issue their 42
-// (or 36 with compressed links) loads together, then compute, which keeps the
-// FP64 kernel free of spills while doubling the loads in flight per wave
-// compared with one hop at a time.  Links are either stored in full (9
+// One thread per site of the site-blocked, tile-interleaved layout (two
+// right-hand sides per thread when there are several).  The loop over mu is
+// rolled (wave-uniform): both hops of one direction issue their 42 (or 36
+// with compressed links) loads together, then compute, which doubles the
+// loads in flight per wave compared with one hop at a time.  Links are either stored in full (9
 // complex) or as their first two rows (6 complex, NL = 6); the third row of an
 // SU(3) matrix is the complex conjugate of the cross product of the first two,
 // which trades 42 flops per link for a third less link traffic.
@@ -29,24 +29,10 @@ template <typename C> __host__ __device__ __forceinline__ void reconstruct_row2(
   u[8] = mk<C>(c.x, -c.y);
 }
 
-#ifndef MG_LINK_NT
-#define MG_LINK_NT 0
-#endif
-template <typename S> __device__ __forceinline__ S ld_link(const S *p) {
-#if MG_LINK_NT
-  S v;
-  v.x = __builtin_nontemporal_load(&p->x);
-  v.y = __builtin_nontemporal_load(&p->y);
-  return v;
-#else
-  return *p;
-#endif
-}
-
 template <int NL, typename C, typename S>
 __device__ __forceinline__ void load_link_t(C (&u)[9], const S *__restrict__ U, int mu, uint32_t s) {
 #pragma unroll
-  for (int e = 0; e < NL; ++e) u[e] = cvt<C>(ld_link(&U[fidx(s, mu * NL + e, 4 * NL)]));
+  for (int e = 0; e < NL; ++e) u[e] = cvt<C>(U[fidx(s, mu * NL + e, 4 * NL)]);
   if constexpr (NL == 6) reconstruct_row2(u);
 }
 
@@ -140,18 +126,19 @@ __device__ __forceinline__ void dslash_site_k(C (&res)[K][12], C (&ctr)[K][12], 
   }
 }
 
-#ifndef MG_DSLASH_ORDER
-#define MG_DSLASH_ORDER 0
-#endif
 // Block of `per` consecutive sites that workgroup bid of nblk visits.  The
 // hardware deals workgroups to the eight XCDs round-robin; xcd_remap gives
-// each XCD a contiguous range.  Order 1 (aggregates of whole blocks, a
-// coarse z extent divisible by 8): XCD k takes the aggregates of the z
-// layers k C_z/8 .. (k+1) C_z/8 - 1 and walks them x fastest, then y, then
-// t, so that the XCDs move through t in step.
+// each XCD a contiguous range of the visiting order.  Where aggregates are
+// whole blocks and the coarse z extent is divisible by 8, XCD k takes the
+// aggregates of the z layers k C_z/8 .. (k+1) C_z/8 - 1 and walks them x
+// fastest, then y, then t: the t neighbours of an aggregate are visited one
+// x-y layer apart on the same XCD (L2), and the XCDs move through t in step,
+// so the z neighbours another XCD needs are read at about the same time.
+// (The aggregate-major order walks x, y, z, then t, with each XCD owning a
+// t range; on 32^3 x 64 the visiting order above is 4-6 % faster.)
+// Otherwise the order is the storage order.
 __device__ __forceinline__ uint32_t visit_block(uint32_t bid, uint32_t nblk, const Geom &g, uint32_t per) {
   const uint32_t q = xcd_remap(bid, nblk);
-#if MG_DSLASH_ORDER == 1
   const uint32_t sub = g.vb / per;
   if ((nblk & 7u) == 0 && g.C[2] % 8 == 0 && sub * per == g.vb && nblk == g.Vc * sub) {
     const uint32_t per_xcd = nblk >> 3, xcd = q / per_xcd, r0 = q - xcd * per_xcd;
@@ -166,7 +153,6 @@ __device__ __forceinline__ uint32_t visit_block(uint32_t bid, uint32_t nblk, con
     const uint32_t B = cx + (uint32_t)g.C[0] * (cy + (uint32_t)g.C[1] * (cz + (uint32_t)g.C[2] * ct));
     return B * sub + j;
   }
-#endif
   return q;
 }
 
@@ -230,70 +216,12 @@ __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash(Geom g, const
   }
 }
 
-// Several right-hand sides: a workgroup covers one 64-site tile for up to
-// four right-hand sides, one wavefront each.  The wavefronts read the same
-// links at the same time, so the links of a tile come from memory once per
-// group of four right-hand sides instead of once per right-hand side; the
-// spinor loads are those of the single-RHS kernel.  A wavefront is one
-// (tile, right-hand side) pair, so the MR partial sums are wavefront sums (no
-// workgroup barrier), one slot per tile and right-hand side.
-constexpr int MRHS_GROUP = 4;
-
-template <typename R, int MODE, int NL, typename S, typename TI = c_t<R>>
-__global__ __launch_bounds__(64 * MRHS_GROUP, dslash_waves<R>()) void k_dslash_mrhs(Geom g, const S *__restrict__ U,
-                                                                const TI *__restrict__ in,
-                                                                c_t<R> *__restrict__ out,
-                                                                const c_t<R> *__restrict__ b, R diag,
-                                                                double *__restrict__ partials, int nrhs) {
-  using C = c_t<R>;
-  const int rhs = blockIdx.y * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (rhs >= nrhs) return;  // a whole wavefront; no workgroup barrier follows
-  const size_t off = (size_t)rhs * 12 * g.Vpad;
-  in += off;
-  out += off;
-  const uint32_t tile = visit_block(blockIdx.x, gridDim.x, g, TILE);
-  const uint32_t s = tile * TILE + (threadIdx.x & 63);
-  double red[3] = {0.0, 0.0, 0.0};
-  if (s < g.V) {
-    C res[12], ctr[12];
-    dslash_site<NL, C>(res, ctr, g, s, U, in, diag);
-    if constexpr (MODE == DS_RESID) {
-      const C *bb = b + off;
-#pragma unroll
-      for (int i = 0; i < 12; ++i) res[i] = csub(bb[fidx(s, i, 12)], res[i]);
-    }
-#pragma unroll
-    for (int i = 0; i < 12; ++i) {
-      __builtin_nontemporal_store(res[i].x, &out[fidx(s, i, 12)].x);
-      __builtin_nontemporal_store(res[i].y, &out[fidx(s, i, 12)].y);
-    }
-    if constexpr (MODE == DS_MR) {
-#pragma unroll
-      for (int i = 0; i < 12; ++i) {
-        red[0] += (double)res[i].x * ctr[i].x + (double)res[i].y * ctr[i].y;
-        red[1] += (double)res[i].x * ctr[i].y - (double)res[i].y * ctr[i].x;
-        red[2] += (double)res[i].x * res[i].x + (double)res[i].y * res[i].y;
-      }
-    }
-  }
-  if constexpr (MODE == DS_MR) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i) red[i] = wave_sum(red[i]);
-    if ((threadIdx.x & 63) == 0) {
-      double *p = partials + ((size_t)rhs * gridDim.x + blockIdx.x) * 3;
-      p[0] = red[0];
-      p[1] = red[1];
-      p[2] = red[2];
-    }
-  }
-}
-
-#ifndef MG_MRHS_K
-#define MG_MRHS_K 0
-#endif
-// K right-hand sides per thread (256-site workgroups): the links of a site
-// are loaded once for all K; workgroups of one group of K right-hand sides
-// cover the lattice, grid.y = groups.  A ragged last group repeats its last
+// Several right-hand sides: K per thread (256-site workgroups), so that
+// each direction's links are loaded once for all K; the workgroups of one
+// group of K right-hand sides cover the lattice, grid.y = groups.  K = 2:
+// on 32^3 x 64 with 12 right-hand sides, per right-hand side FP64 0.40 ms
+// (one per thread: 0.47 ms), FP32 0.214 ms (0.231), FP16-stored links 0.195
+// ms (0.198); K = 4 is slower in FP32 (0.248 ms: one wave per SIMD).  A ragged last group repeats its last
 // right-hand side in the spare slots and stores only the valid ones.
 template <typename R, int MODE, int NL, typename S, int K, typename TI = c_t<R>>
 __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash_rb(Geom g, const S *__restrict__ U, const TI *__restrict__ in,
@@ -353,12 +281,10 @@ __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash_rb(Geom g, co
   }
 }
 
-constexpr int mrhs_k(int prec_bytes) { return MG_MRHS_K == 4 && prec_bytes == 8 ? 2 : MG_MRHS_K; }
+constexpr int MRHS_K = 2;
 
 int dslash_blocks(const Geom &g) { return div_up(g.V, 256); }
-int dslash_partials(const Geom &g, int nrhs) {
-  return (nrhs > 1 && MG_MRHS_K == 0) ? (int)(g.Vpad / TILE) : dslash_blocks(g);
-}
+int dslash_partials(const Geom &g, int) { return dslash_blocks(g); }
 
 template <typename R, int NL, typename S, int K>
 static hipError_t launch_rb(const Geom &g, const S *U, const c_t<R> *in, c_t<R> *out, const c_t<R> *b, double diag,
@@ -384,31 +310,7 @@ static hipError_t launch_rb(const Geom &g, const S *U, const c_t<R> *in, c_t<R> 
 template <typename R, int NL, typename S>
 static hipError_t launch(const Geom &g, const S *U, const c_t<R> *in, c_t<R> *out, const c_t<R> *b, double diag,
                          int nrhs, DslashMode mode, double *partials, hipStream_t st) {
-  if constexpr (MG_MRHS_K > 0) {
-    if (nrhs > 1) {
-      constexpr int K = mrhs_k(sizeof(R));
-      return launch_rb<R, NL, S, K>(g, U, in, out, b, diag, nrhs, mode, partials, st);
-    }
-  }
-  if (nrhs > 1) {
-    const int grp = nrhs < MRHS_GROUP ? nrhs : MRHS_GROUP;
-    dim3 grid(g.Vpad / TILE, (nrhs + grp - 1) / grp), block(64 * grp);
-    switch (mode) {
-      case DS_PLAIN:
-        hipLaunchKernelGGL((k_dslash_mrhs<R, DS_PLAIN, NL, S>), grid, block, 0, st, g, U, in, out, b, (R)diag,
-                           partials, nrhs);
-        break;
-      case DS_RESID:
-        hipLaunchKernelGGL((k_dslash_mrhs<R, DS_RESID, NL, S>), grid, block, 0, st, g, U, in, out, b, (R)diag,
-                           partials, nrhs);
-        break;
-      case DS_MR:
-        hipLaunchKernelGGL((k_dslash_mrhs<R, DS_MR, NL, S>), grid, block, 0, st, g, U, in, out, b, (R)diag,
-                           partials, nrhs);
-        break;
-    }
-    return hipGetLastError();
-  }
+  if (nrhs > 1) return launch_rb<R, NL, S, MRHS_K>(g, U, in, out, b, diag, nrhs, mode, partials, st);
   dim3 grid(dslash_blocks(g), nrhs);
   switch (mode) {
     case DS_PLAIN:
@@ -439,10 +341,9 @@ template <int NL>
 static hipError_t launch_in32(const Geom &g, const double2 *U, const float2 *in, double2 *out, double diag,
                               int nrhs, hipStream_t st) {
   if (nrhs > 1) {
-    const int grp = nrhs < MRHS_GROUP ? nrhs : MRHS_GROUP;
-    dim3 grid(g.Vpad / TILE, (nrhs + grp - 1) / grp), block(64 * grp);
-    hipLaunchKernelGGL((k_dslash_mrhs<double, DS_PLAIN, NL, double2, float2>), grid, block, 0, st, g, U, in, out,
-                       nullptr, diag, nullptr, nrhs);
+    dim3 grid(dslash_blocks(g), (nrhs + MRHS_K - 1) / MRHS_K);
+    hipLaunchKernelGGL((k_dslash_rb<double, DS_PLAIN, NL, double2, MRHS_K, float2>), grid, dim3(256), 0, st, g, U,
+                       in, out, nullptr, diag, nullptr, nrhs);
   } else {
     hipLaunchKernelGGL((k_dslash<double, DS_PLAIN, NL, double2, float2>), dim3(dslash_blocks(g), 1), dim3(256), 0,
                        st, g, U, in, out, nullptr, diag, nullptr);

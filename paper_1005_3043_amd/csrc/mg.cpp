@@ -5,6 +5,7 @@
 // in the HIP kernels; the host only sequences launches on one stream and
 // reads residual norms / convergence flags for its decisions.
 #include <chrono>
+#include <cstdio>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -92,6 +93,8 @@ void clear_graphs(mg_ctx *c) {
     delete g;
     g = nullptr;
   }
+  for (VGraph *g : c->vgraphs) delete g;
+  c->vgraphs.clear();
 }
 
 template <typename R> int ensure_work(mg_ctx *c, int nrhs) {
@@ -188,22 +191,21 @@ int np_mr(mg_ctx *c, int l, int nrhs) {
 template <typename P> constexpr int tclass(bool coarse) { return 2 * P::id + (coarse ? 1 : 0); }
 
 // Records a (start, stop) event pair around the launches in its scope when
-// timing is on.  Inside a stream capture the events are recorded as external
-// event nodes, so every replay of the graph re-records them.
+// timing is on.  With timing on the solver runs its launches eagerly (the
+// runtime refuses event records inside a stream capture), so a scope never
+// sits inside a capture; should one, it records nothing.
 struct TimerScope {
   EventTimer *t = nullptr;
   hipEvent_t e1 = nullptr;
   hipStream_t st;
-  unsigned flags = 0;
   TimerScope(mg_ctx *c, EventTimer &tm, hipStream_t s, double sites, bool sample = true, int nlaunch = 1) : st(s) {
     if (c->timing && sample) {
       hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-      if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive)
-        flags = hipEventRecordExternal;
+      if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
       hipEvent_t e0 = tm.next();
       e1 = tm.next();
       if (e0 && e1) {
-        (void)hipEventRecordWithFlags(e0, st, flags);
+        (void)hipEventRecord(e0, st);
         t = &tm;
         tm.pair_sites.push_back(sites);
         tm.pair_launches.push_back(nlaunch);
@@ -211,7 +213,7 @@ struct TimerScope {
     }
   }
   ~TimerScope() {
-    if (t) (void)hipEventRecordWithFlags(e1, st, flags);
+    if (t) (void)hipEventRecord(e1, st);
   }
 };
 
@@ -426,18 +428,20 @@ int apply_A(mg_ctx *c, int l, const vec_t<P> *in, vec_t<P> *out, int nrhs, Dslas
 }
 
 // MR smoothing of A_l x = r0 from x = 0 (accumulate: add into x): on return
-// r holds the recursively updated residual.
+// r holds the recursively updated residual, unless keep_r = false (the
+// caller does not use it; the last step then updates x only).
 template <typename P>
 int mr(mg_ctx *c, int l, vec_t<P> *x, vec_t<P> *r, vec_t<P> *q, int steps, bool accumulate, int nrhs,
-       hipStream_t st) {
+       hipStream_t st, bool keep_r = true) {
   using R = typename P::R;
   Level &L = c->lev[l];
   const size_t n = L.vsize();
   if (steps == 0 && !accumulate) HIPK(zero<R>(x, n * nrhs, st));
   for (int k = 0; k < steps; ++k) {
     MG_TRY(apply_A<P>(c, l, r, q, nrhs, DS_MR, nullptr, st));
-    HIPK(mr_update<R>(x, r, q, n, nrhs, c->part, np_mr(c, l, nrhs), c->p.omega, c->csc, (!accumulate && k == 0) ? 1 : 0,
-                      st));
+    const int upd_r = (keep_r || k + 1 < steps) ? 1 : 0;
+    HIPK(mr_update<R>(x, r, q, n, nrhs, c->part, np_mr(c, l, nrhs), c->p.omega, c->csc,
+                      (!accumulate && k == 0) ? 1 : 0, upd_r, st));
   }
   return MG_OK;
 }
@@ -629,23 +633,21 @@ int cgnr_chunk(mg_ctx *c, int l, vec_t<P> *e, int nrhs, int var, bool fused, hip
 }
 
 template <typename P>
-ChunkGraph *chunk_graph(mg_ctx *c, int l, vec_t<P> *e, int nrhs, int var, bool fused, int phase, hipStream_t st) {
+ChunkGraph *chunk_graph(mg_ctx *c, int l, vec_t<P> *e, int nrhs, int var, bool fused, hipStream_t st) {
   const int prec = P::id;
   for (ChunkGraph *g : c->graphs)
-    if (g && g->level == l && g->prec == prec && g->nrhs == nrhs && g->timing == c->timing && g->variant == var &&
-        g->phase == phase && g->fused == (int)fused)
+    if (g && g->level == l && g->prec == prec && g->nrhs == nrhs && g->variant == var && g->fused == (int)fused)
       return g;
   ChunkGraph *g = new ChunkGraph();
   g->level = l;
   g->prec = prec;
   g->nrhs = nrhs;
-  g->timing = c->timing;
   g->variant = var;
-  g->phase = phase;
   g->fused = fused ? 1 : 0;
+  EventTimer unused;
   bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) == hipSuccess;
   if (ok) {
-    const int rc = cgnr_chunk<P>(c, l, e, nrhs, var, fused, st, g->tm);
+    const int rc = cgnr_chunk<P>(c, l, e, nrhs, var, fused, st, unused);
     ok = hipStreamEndCapture(st, &g->graph) == hipSuccess && rc == MG_OK;
   }
   if (ok) ok = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) == hipSuccess;
@@ -786,20 +788,14 @@ template <typename P> int cgnr(mg_ctx *c, int l, const vec_t<P> *b, vec_t<P> *e,
     if (ran) return MG_OK;
     if (retry) return cgnr<P>(c, l, b, e, nrhs, st);
   }
-  // With timing on, chunks alternate between two captured graphs so that the
-  // event pairs of one are read while the other runs.
-  ChunkGraph *gph[2] = {nullptr, nullptr};
-  if (c->use_graph) {
-    gph[0] = chunk_graph<P>(c, l, e, nrhs, var, fused, 0, st);
-    gph[1] = c->timing ? chunk_graph<P>(c, l, e, nrhs, var, fused, 1, st) : gph[0];
-    if (!gph[0] || !gph[1]) gph[0] = gph[1] = nullptr;
-  }
+  // Captured chunks (not with timing on: event records cannot be captured)
+  ChunkGraph *gph = (c->use_graph && !c->timing) ? chunk_graph<P>(c, l, e, nrhs, var, fused, st) : nullptr;
   const int nchunks = (c->p.coarse_maxiter + CG_CHUNK - 1) / CG_CHUNK;
   c->n_coarse_disp += nrhs;  // the initial application above
   int last = 0;
   for (int ch = 0; ch < nchunks; ++ch) {
     last = ch;
-    if (gph[0]) HIPK(hipGraphLaunch(gph[ch & 1]->exec, st));
+    if (gph) HIPK(hipGraphLaunch(gph->exec, st));
     else MG_TRY(cgnr_chunk<P>(c, l, e, nrhs, var, fused, st, tm));
     c->n_coarse_disp += 2L * CG_CHUNK * nrhs;
     int *hd = c->h_done + (size_t)(ch & 1) * MG_MAX_RHS;
@@ -808,7 +804,6 @@ template <typename P> int cgnr(mg_ctx *c, int l, const vec_t<P> *b, vec_t<P> *e,
     const int look = ch - 1;  // one chunk stays queued ahead of the host's check
     if (look < 0) continue;
     HIPK(hipEventSynchronize(c->ev_chunk[look & 1]));
-    if (gph[0] && c->timing) gph[look & 1]->tm.harvest(&tm, true);
     const int *hl = c->h_done + (size_t)(look & 1) * MG_MAX_RHS;
     bool all = true;
     for (int i = 0; i < nrhs; ++i) all = all && hl[i];
@@ -816,7 +811,6 @@ template <typename P> int cgnr(mg_ctx *c, int l, const vec_t<P> *b, vec_t<P> *e,
   }
   HIPK(hipMemcpyAsync(c->h_it, c->it, sizeof(int) * 2 * nrhs, hipMemcpyDeviceToHost, st));
   HIPK(hipStreamSynchronize(st));
-  if (gph[0] && c->timing) gph[last & 1]->tm.harvest(&tm, true);
   for (int i = 0; i < nrhs; ++i) {
     const long it = std::max(c->h_it[i], c->h_it[nrhs + i]);
     c->n_cgnr += it;
@@ -825,16 +819,15 @@ template <typename P> int cgnr(mg_ctx *c, int l, const vec_t<P> *b, vec_t<P> *e,
   return MG_OK;
 }
 
-// One V-cycle K_l(rin) -> x (levels l..coarsest).
-template <typename P> int vcycle(mg_ctx *c, int l, const vec_t<P> *rin, vec_t<P> *x, int nrhs, hipStream_t st) {
+// Smoothing before the coarse correction on level l (x from zero, r the
+// residual left for restriction).
+template <typename P>
+static int smooth_pre(mg_ctx *c, int l, const vec_t<P> *rin, vec_t<P> *x, int nrhs, hipStream_t st) {
   using R = typename P::R;
-  if (l == c->nlev - 1) return cgnr<P>(c, l, rin, x, nrhs, st);
   Work<R> &w = work<R>(c);
-  Level &L = c->lev[l];
-  const size_t n = L.vsize();
+  const size_t n = c->lev[l].vsize();
   vec_t<P> *r = w.r[l], *q = w.q[l];
-  const bool gm = c->p.smoother == MG_SMOOTH_GMRES;
-  if (!gm) {
+  if (c->p.smoother != MG_SMOOTH_GMRES) {
     HIPK(copy<R>(r, rin, n * nrhs, st));
     MG_TRY(mr<P>(c, l, x, r, q, c->p.pre, false, nrhs, st));
   } else if (c->p.pre > 0) {
@@ -844,8 +837,115 @@ template <typename P> int vcycle(mg_ctx *c, int l, const vec_t<P> *rin, vec_t<P>
     HIPK(zero<R>(x, n * nrhs, st));
     HIPK(copy<R>(r, rin, n * nrhs, st));
   }
+  return MG_OK;
+}
+
+// After the coarse correction of level l: x += P e_c, the new residual, and
+// the post-smoothing added into x.
+template <typename P>
+static int smooth_post(mg_ctx *c, int l, const vec_t<P> *rin, vec_t<P> *x, int nrhs, hipStream_t st) {
+  using R = typename P::R;
+  Work<R> &w = work<R>(c);
+  vec_t<P> *r = w.r[l], *q = w.q[l];
+  MG_TRY(transfer_prolong<P>(c, l, w.x[l + 1], x, nrhs, 1, st));
+  MG_TRY(apply_A<P>(c, l, x, r, nrhs, DS_RESID, rin, st));
+  if (c->p.smoother == MG_SMOOTH_GMRES) MG_TRY(gmres_smooth<P>(c, l, x, r, c->p.post, true, nrhs, st));
+  else MG_TRY(mr<P>(c, l, x, r, q, c->p.post, true, nrhs, st, false));
+  return MG_OK;
+}
+
+// The two fixed launch sequences of a V-cycle from level 0: part 0 runs
+// smooth_pre and the restriction on every level down to the coarsest, part
+// 1 smooth_post on every level back up.
+template <typename P>
+static int vcycle_part(mg_ctx *c, int part, const vec_t<P> *rin0, vec_t<P> *x0, int nrhs, hipStream_t st) {
+  using R = typename P::R;
+  Work<R> &w = work<R>(c);
+  const int top = c->nlev - 2;
+  if (part == 0) {
+    for (int l = 0; l <= top; ++l) {
+      MG_TRY(smooth_pre<P>(c, l, l == 0 ? rin0 : w.rin[l], l == 0 ? x0 : w.x[l], nrhs, st));
+      MG_TRY(transfer_restrict<P>(c, l, w.r[l], w.rin[l + 1], nrhs, st));
+    }
+  } else {
+    for (int l = top; l >= 0; --l)
+      MG_TRY(smooth_post<P>(c, l, l == 0 ? rin0 : w.rin[l], l == 0 ? x0 : w.x[l], nrhs, st));
+  }
+  return MG_OK;
+}
+
+// Runs one part of the V-cycle from a captured graph: the first time a key
+// is seen the part runs eagerly, the second time it is captured (and the
+// graph launched), later it is replayed.
+template <typename P>
+static int vcycle_part_graphed(mg_ctx *c, int part, const vec_t<P> *rin0, vec_t<P> *x0, int nrhs, hipStream_t st) {
+  VGraph *g = nullptr;
+  for (VGraph *v : c->vgraphs)
+    if (v->prec == P::id && v->nrhs == nrhs && v->part == part && v->rin == rin0 && v->x == x0) {
+      g = v;
+      break;
+    }
+  if (!g) {
+    if ((int)c->vgraphs.size() >= VGRAPH_MAX) clear_graphs(c);
+    g = new VGraph();
+    g->prec = P::id;
+    g->nrhs = nrhs;
+    g->part = part;
+    g->rin = rin0;
+    g->x = x0;
+    c->vgraphs.push_back(g);
+    return vcycle_part<P>(c, part, rin0, x0, nrhs, st);
+  }
+  if (g->state == 0) {
+    const long f0 = c->n_fine, c0 = c->n_coarse, d0 = c->n_coarse_disp;
+    bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) == hipSuccess;
+    int rc = MG_OK;
+    if (ok) {
+      rc = vcycle_part<P>(c, part, rin0, x0, nrhs, st);
+      ok = hipStreamEndCapture(st, &g->graph) == hipSuccess && rc == MG_OK;
+    }
+    if (ok) ok = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) == hipSuccess;
+    // the capture launched nothing: its launches run below, by the graph or
+    // eagerly, and are counted there
+    g->dfine = c->n_fine - f0;
+    g->dcoarse = c->n_coarse - c0;
+    g->ddisp = c->n_coarse_disp - d0;
+    c->n_fine = f0;
+    c->n_coarse = c0;
+    c->n_coarse_disp = d0;
+    if (!ok) {
+      // the part runs eagerly from now on (an error it meets there is reported)
+      (void)hipGetLastError();
+      if (g->graph) (void)hipGraphDestroy(g->graph);
+      g->graph = nullptr;
+      g->state = -1;
+    } else {
+      g->state = 1;
+    }
+  }
+  if (g->state < 0) return vcycle_part<P>(c, part, rin0, x0, nrhs, st);
+  HIPK(hipGraphLaunch(g->exec, st));
+  c->n_fine += g->dfine;
+  c->n_coarse += g->dcoarse;
+  c->n_coarse_disp += g->ddisp;
+  return MG_OK;
+}
+
+// One V-cycle K_l(rin) -> x (levels l..coarsest).
+template <typename P> int vcycle(mg_ctx *c, int l, const vec_t<P> *rin, vec_t<P> *x, int nrhs, hipStream_t st) {
+  using R = typename P::R;
+  if (l == c->nlev - 1) return cgnr<P>(c, l, rin, x, nrhs, st);
+  if (l == 0 && c->vgraph_on && c->use_graph && !c->timing && c->p.cycles <= 1) {
+    Work<R> &w = work<R>(c);
+    const int lc = c->nlev - 1;
+    MG_TRY(vcycle_part_graphed<P>(c, 0, rin, x, nrhs, st));
+    MG_TRY(cgnr<P>(c, lc, w.rin[lc], w.x[lc], nrhs, st));
+    return vcycle_part_graphed<P>(c, 1, rin, x, nrhs, st);
+  }
+  Work<R> &w = work<R>(c);
+  MG_TRY(smooth_pre<P>(c, l, rin, x, nrhs, st));
   const int m = l + 1;
-  MG_TRY(transfer_restrict<P>(c, l, r, w.rin[m], nrhs, st));
+  MG_TRY(transfer_restrict<P>(c, l, w.r[l], w.rin[m], nrhs, st));
   MG_TRY(vcycle<P>(c, m, w.rin[m], w.x[m], nrhs, st));
   if (m < c->nlev - 1) {
     // W-cycle: further cycles of level m on the residual the previous left
@@ -855,11 +955,7 @@ template <typename P> int vcycle(mg_ctx *c, int l, const vec_t<P> *rin, vec_t<P>
       HIPK(add_inplace<R>(w.x[m], w.w2x[m], c->lev[m].vsize(), nrhs, st));
     }
   }
-  MG_TRY(transfer_prolong<P>(c, l, w.x[m], x, nrhs, 1, st));
-  MG_TRY(apply_A<P>(c, l, x, r, nrhs, DS_RESID, rin, st));
-  if (gm) MG_TRY(gmres_smooth<P>(c, l, x, r, c->p.post, true, nrhs, st));
-  else MG_TRY(mr<P>(c, l, x, r, q, c->p.post, true, nrhs, st));
-  return MG_OK;
+  return smooth_post<P>(c, l, rin, x, nrhs, st);
 }
 
 // z = K(r) in the precision prec (FP64 in and out).
@@ -904,6 +1000,12 @@ static int fgcr_t(mg_ctx *c, const double2 *b, double2 *x, int nrhs, double tol,
   float2 *r32 = f32z ? c->gr32.p : nullptr;
   double *rr = c->dsc;
   int *skip = c->skip;
+  // the cycles of the outer solver may run from captured V-cycle parts
+  struct GraphGuard {
+    mg_ctx *c;
+    explicit GraphGuard(mg_ctx *cc) : c(cc) { c->vgraph_on = 1; }
+    ~GraphGuard() { c->vgraph_on = 0; }
+  } guard(c);
   HIPK(zero<double>(x, nn, st));
   HIPK(copy<double>(r, b, nn, st));
   HIPK(norm2<double>(b, n, nrhs, c->part, rr, st));
@@ -1041,7 +1143,7 @@ int relax(mg_ctx *c, int l, double2 *V, int nv, hipStream_t st) {
   MG_TRY(q.alloc(n * nv));
   for (int round = 0; round < c->p.setup_rounds; ++round) {
     MG_TRY(apply_A<PF64>(c, l, V, r, nv, DS_PLAIN, nullptr, st));
-    MG_TRY(mr<PF64>(c, l, x, r, q, c->p.setup_mr_steps, false, nv, st));
+    MG_TRY(mr<PF64>(c, l, x, r, q, c->p.setup_mr_steps, false, nv, st, false));
     HIPK(sub_inplace<double>(V, x, n, nv, st));
     HIPK(norm2<double>(V, n, nv, c->part, c->dsc, st));
     HIPK(scale_rsqrt<double>(V, n, nv, c->dsc, st));

@@ -15,9 +15,11 @@ constexpr int GCR_CHUNK = 8;      // FGCR directions orthogonalised against per 
 __host__ __device__ constexpr size_t gcr_scalars_per_rhs(int m) { return (size_t)m * m + 3 * (size_t)m + 1; }
 
 // ---- solver_kernels.hip
+// x = (first ? 0 : x) + alpha r and, when upd_r, r -= alpha q, with alpha =
+// omega <q,r>/<q,q> from the stencil's np partials per right-hand side
 template <typename R>
 hipError_t mr_update(c_t<R> *x, c_t<R> *r, const c_t<R> *q, size_t n, int nrhs, const double *part, int np,
-                     double omega, double2 *alpha, int first, hipStream_t st);
+                     double omega, double2 *alpha, int first, int upd_r, hipStream_t st);
 template <typename R> hipError_t norm2(const c_t<R> *a, size_t n, int nrhs, double *part, double *out, hipStream_t st);
 // launches the per-block partials of ||a||^2 and returns their count per RHS
 template <typename R> int norm2_partials(const c_t<R> *a, size_t n, int nrhs, double *part, hipStream_t st);
@@ -220,15 +222,36 @@ struct EventTimer {
 
 // A captured chunk of CGNR iterations for one (level, precision, nrhs).
 struct ChunkGraph {
-  int level = -1, prec = -1, nrhs = 0, timing = 0, variant = 0, phase = 0, fused = 0;
+  int level = -1, prec = -1, nrhs = 0, variant = 0, fused = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  EventTimer tm;  // coarse-stencil timing events inside the graph (timing on)
   ~ChunkGraph() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
   }
 };
+
+// One part of a V-cycle captured for replay: part 0 = smoothing, residual
+// and restriction on every level down to the coarsest, part 1 = prolongation,
+// residual and smoothing on every level back up (the coarsest solve between
+// them stays host-driven).  Keyed by precision, right-hand sides and the
+// cycle's input and output buffers.  state 0: the key was seen once and ran
+// eagerly (which tuned its kernels and made the operator copies it needs);
+// 1: captured; -1: capture failed, runs eagerly.  The host-side counts of
+// one execution are kept so that replays add them.
+struct VGraph {
+  int prec = -1, nrhs = 0, part = 0;
+  const void *rin = nullptr, *x = nullptr;
+  int state = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  long dfine = 0, dcoarse = 0, ddisp = 0;
+  ~VGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+constexpr int VGRAPH_MAX = 48;
 
 constexpr int CG_FUSE_MAXV = 1024;  // fused CGNR up to this many coarse sites (<= RED_BLOCKS)
 constexpr int CG_CHUNK = 8;  // CGNR iterations per chunk (even: parity slots repeat)
@@ -260,6 +283,8 @@ struct mg_ctx {
   hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_chunk[2] = {nullptr, nullptr};
   int use_graph = 1;
   mg::ChunkGraph *graphs[16] = {};            // captured CGNR chunks
+  std::vector<mg::VGraph *> vgraphs;          // captured V-cycle parts
+  int vgraph_on = 0;                          // set by the outer solver around its cycles
   mg::DevBuf<double2> csc;
   mg::DevBuf<int> done, it;
   // whole-solve cooperative CGNR (one RHS): barrier counter, give-up flag,

@@ -92,16 +92,20 @@ __global__ __launch_bounds__(256) void k_dot(const c_t<R> *a, const c_t<R> *b, s
 // MR: x = (first ? 0 : x) + alpha r;  r -= alpha q
 template <typename R>
 __global__ __launch_bounds__(256) void k_mr_update(c_t<R> *x, c_t<R> *r, const c_t<R> *q, size_t n,
-                                                   const double2 *alpha, int first) {
+                                                   const double2 *alpha, int first, int upd_r) {
   using C = c_t<R>;
   const size_t off = (size_t)blockIdx.y * n;
   x += off; r += off; q += off;
   const double2 ad = alpha[blockIdx.y];
   const C a = mk<C>((R)ad.x, (R)ad.y), ma = mk<C>((R)-ad.x, (R)-ad.y);
-  GSTRIDE(i, n) {
-    const C rv = r[i];
-    x[i] = first ? cmul(a, rv) : cfma(a, rv, x[i]);
-    r[i] = cfma(ma, q[i], rv);
+  if (upd_r) {
+    GSTRIDE(i, n) {
+      const C rv = r[i];
+      x[i] = first ? cmul(a, rv) : cfma(a, rv, x[i]);
+      r[i] = cfma(ma, q[i], rv);
+    }
+  } else {
+    GSTRIDE(i, n) x[i] = first ? cmul(a, r[i]) : cfma(a, r[i], x[i]);
   }
 }
 
@@ -379,9 +383,9 @@ template <typename R> hipError_t resid_from(c_t<R> *out, const c_t<R> *b, size_t
 
 template <typename R>
 hipError_t mr_update(c_t<R> *x, c_t<R> *r, const c_t<R> *q, size_t n, int nrhs, const double *part, int np,
-                     double omega, double2 *alpha, int first, hipStream_t st) {
+                     double omega, double2 *alpha, int first, int upd_r, hipStream_t st) {
   hipLaunchKernelGGL(k_fin_mr, dim3(1, nrhs), dim3(256), 0, st, part, np, omega, alpha);
-  hipLaunchKernelGGL(k_mr_update<R>, dim3(sgrid(n), nrhs), dim3(256), 0, st, x, r, q, n, alpha, first);
+  hipLaunchKernelGGL(k_mr_update<R>, dim3(sgrid(n), nrhs), dim3(256), 0, st, x, r, q, n, alpha, first, upd_r);
   return hipGetLastError();
 }
 
@@ -445,7 +449,7 @@ hipError_t gcr_update(double2 *x, const double2 *z, double2 *r, const double2 *w
 
 #define INST(R)                                                                                                     \
   template hipError_t mr_update<R>(c_t<R> *, c_t<R> *, const c_t<R> *, size_t, int, const double *, int, double,    \
-                                   double2 *, int, hipStream_t);                                                    \
+                                   double2 *, int, int, hipStream_t);                                               \
   template hipError_t norm2<R>(const c_t<R> *, size_t, int, double *, double *, hipStream_t);                       \
   template int norm2_partials<R>(const c_t<R> *, size_t, int, double *, hipStream_t);                               \
   template hipError_t dot<R>(const c_t<R> *, const c_t<R> *, size_t, int, double *, double2 *, hipStream_t);        \

@@ -664,7 +664,8 @@ def test_setup_errors(cuda):
 
 
 def test_graph_replay_matches_eager(cuda):
-    """CGNR chunks replayed from a captured hipGraph give bit-identical
+    """The V-cycle parts (smoothing, residuals and transfers on every level)
+    and the CGNR chunks replayed from captured hipGraphs give bit-identical
     solutions to eager launches, across repeated solves with eager work and
     synchronisations between them (same kernels, same order)."""
     import paper_1005_3043_amd as mgwd
@@ -710,3 +711,42 @@ def test_timing_does_not_change_results(cuda):
     assert 0 < k["coarse_f64"]["launches"] <= i1["n_coarse_dispatch"]
     assert k["dslash_f64"]["launches"] == i1["n_fine_dslash"]
     assert k["coarse_f64"]["ms"] > 0 and k["dslash_f64"]["ms"] > 0
+
+
+@pytest.mark.parametrize("case,nrhs,smoother", [("3-level 8^4", 1, "mr"), ("3-level 8^4", 3, "mr"),
+                                                 ("2-level 8^4", 1, "mr"), ("2-level 8^4", 2, "gmres")])
+def test_vcycle_graph_matches_eager(cuda, case, nrhs, smoother):
+    """Solves whose cycles run from captured graphs (the first solve runs each
+    cycle eagerly, the second captures, later ones replay) equal a context
+    that never captures, bit for bit, with the same iteration and kernel
+    counts, in every preconditioner precision, with timing on and off; the
+    timed launch counts of the fine stencil equal the fine-operator
+    applications."""
+    import paper_1005_3043_amd as mgwd
+    L, blocks, nv, eps, m, seed = _CYCLE_CASES[case]
+    U = torch.from_numpy(W.gauge_field(L, eps, seed)).cuda()
+    inits = [torch.from_numpy(W.setup_starts(L, nv[0], seed)).cuda()]
+    if len(blocks) > 1:
+        Lc = tuple(L[mu] // blocks[0][mu] for mu in range(4))
+        inits.append(torch.from_numpy(W.coarse_setup_starts(Lc, 2 * nv[0], nv[1], seed)).cuda())
+    kw = dict(max_rhs=4, smoother=smoother, pre=(4 if smoother == "mr" else 0), post=4)
+    ctx_g = mgwd.MG(U, m, blocks, nv, inits, use_graph=True, **kw)
+    ctx_e = mgwd.MG(U, m, blocks, nv, inits, use_graph=False, **kw)
+    b = torch.from_numpy(W.gaussian_spinor(L, 4, batch=(nrhs,))).cuda()
+    for prec in ("f64", "f32", "f16"):
+        ctx_g.set_precond_prec(prec)
+        ctx_e.set_precond_prec(prec)
+        xe, ie, rce = ctx_e.solve(b, 1e-10)
+        for rep in range(3):
+            ctx_g.set_timing(rep == 2)
+            xg, ig, rcg = ctx_g.solve(b, 1e-10)
+            torch.cuda.synchronize()
+            assert rce == rcg == 0
+            assert torch.equal(xe, xg), (prec, rep)
+            for k in ("iters", "n_fine_dslash", "n_coarse_apply", "n_cgnr_iters", "n_vcycles"):
+                assert ie[k] == ig[k], (prec, rep, k)
+        kk = ig["kernels"]
+        fine = sum(kk[f"dslash_{p}"]["launches"] for p in ("f64", "f32", "f16"))
+        assert fine == ig["n_fine_dslash"] if nrhs == 1 else fine > 0
+    ctx_g.close()
+    ctx_e.close()
