@@ -153,6 +153,24 @@ int wilson_apply(const mg_lattice_t *lat, const void *U, double mass,
                  const void *in, void *out, int nrhs, mg_prec_t prec,
                  hipStream_t stream);
 
+/* wilson_apply for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid allocation):
+ * the same operator, arguments, layouts and kernels as wilson_apply, with
+ * the internal layouts (links and nrhs input and output spinors, (36 +
+ * 24 nrhs) x Vpad complex entries of the arithmetic precision, Vpad = V
+ * rounded up to 64) in a library-owned device array of MG_NOALLOC_BYTES
+ * that each GPU holds from its first call until the process ends.  This
+ * call allocates nothing.  Lattices and nrhs that need more scratch than
+ * MG_NOALLOC_BYTES are refused with MG_ENOMEM before any work is enqueued
+ * (FP64 and one right-hand side: up to 131 072 sites, e.g. 16^3 x 32).
+ * Every call on one GPU uses the same array: calls that overlap on a GPU
+ * (from several streams or threads) race, and the caller must order them.
+ * Asynchronous on `stream`.                                               */
+#define MG_NOALLOC_BYTES (128u << 20)
+int wilson_apply_noalloc(const mg_lattice_t *lat, const void *U, double mass,
+                         const void *in, void *out, int nrhs, mg_prec_t prec,
+                         hipStream_t stream);
+
 /* Adaptive MG setup (paper: "Adaptive Multigrid", "Formulating an
  * algorithm", setup stage one in "Numerical Results"): relax the start
  * vectors on D x = 0 (setup_rounds x setup_mr_steps MR steps each,

@@ -21,7 +21,7 @@ PREC = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 MAX_LEVELS = 3
 MAX_RHS = 16
 
-EXPORTED = ["wilson_apply", "mg_setup", "mg_set_precond_prec", "mg_set_mass", "mg_set_timing", "mg_restrict",
+EXPORTED = ["wilson_apply", "wilson_apply_noalloc", "mg_setup", "mg_set_precond_prec", "mg_set_mass", "mg_set_timing", "mg_restrict",
             "mg_prolong", "coarse_apply", "mg_apply_op", "mg_vcycle", "mg_transfer", "mg_set_transfer_variant", "mg_transfer_variant", "mg_set_coarse_variant", "mg_coarse_variant", "mg_set_cgnr_persistent", "mg_coarse_solve", "mg_solve", "mg_time_dslash", "mg_time_coarse",
             "mg_destroy", "mg_last_error", "mg_export_maps", "mg_export_P",
             "mg_export_coarse_op", "mg_export_nullvecs", "mg_level_info",
@@ -100,6 +100,7 @@ def lib():
         vp, ci, cd = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
         sig = {
             "wilson_apply": [ctypes.POINTER(Lattice), vp, cd, vp, vp, ci, ci, vp],
+            "wilson_apply_noalloc": [ctypes.POINTER(Lattice), vp, cd, vp, vp, ci, ci, vp],
             "mg_setup": [ctypes.POINTER(Lattice), vp, cd, ctypes.POINTER(Params), ctypes.POINTER(vp), vp],
             "mg_set_precond_prec": [vp, ci],
             "mg_set_mass": [vp, cd],
@@ -177,6 +178,19 @@ def wilson_apply(U: torch.Tensor, psi: torch.Tensor, mass: float, prec: str = "f
     lat = lattice(L, t_antiperiodic)
     _check(lib().wilson_apply(ctypes.byref(lat), _dev(U, "U"), float(mass), _dev(psi, "psi"),
                               _dev(out, "out"), nrhs, PREC[prec], _stream()))
+    return out
+
+
+def wilson_apply_noalloc(U: torch.Tensor, psi: torch.Tensor, mass: float, out: torch.Tensor, prec: str = "f64",
+                         t_antiperiodic: bool = True) -> torch.Tensor:
+    """wilson_apply through the entry point that allocates nothing (the
+    caller passes out; the library's fixed scratch holds the internal
+    layouts)."""
+    L = dims_of_spinor(psi)
+    nrhs = int(psi.numel() // (12 * L[0] * L[1] * L[2] * L[3]))
+    lat = lattice(L, t_antiperiodic)
+    _check(lib().wilson_apply_noalloc(ctypes.byref(lat), _dev(U, "U"), float(mass), _dev(psi, "psi"),
+                                      _dev(out, "out"), nrhs, PREC[prec], _stream()))
     return out
 
 

@@ -1,4 +1,8 @@
-// C ABI: the stateless fine operator wilson_apply and mg_last_error.
+// C ABI: the stateless fine operator wilson_apply (and its variant that
+// allocates nothing, wilson_apply_noalloc) and mg_last_error.
+#include <cstdio>
+#include <mutex>
+
 #include "kernels.h"
 
 namespace mg {
@@ -45,9 +49,84 @@ static int wilson_apply_t(const mg_lattice_t *lat, const void *U, double mass, c
   return MG_OK;
 }
 
+// ---------------------------------------------------------------- no-alloc
+// Scratch of wilson_apply_noalloc: the internal link and spinor layouts of
+// one call, in a file-scope device array that each GPU the library runs on
+// holds until the process ends.  Host code never uses the array's name as an
+// address: it takes the per-device address from hipGetSymbolAddress once per
+// device (on the first call with that device current) and passes that.
+static __device__ __align__(256) unsigned char scratch[MG_NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex noalloc_mu;
+static void *noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+static int noalloc_scratch(unsigned char **out) {
+  int dev = 0;
+  MG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+    set_error("wilson_apply_noalloc: device ordinal out of range");
+    return MG_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(noalloc_mu);
+  if (!noalloc_ptr[dev]) {
+    void *p = nullptr;
+    MG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    noalloc_ptr[dev] = p;
+  }
+  *out = static_cast<unsigned char *>(noalloc_ptr[dev]);
+  return MG_OK;
+}
+
+template <typename T>
+static int wilson_apply_noalloc_t(const mg_lattice_t *lat, const void *U, double mass, const void *in, void *out,
+                                  int nrhs, hipStream_t st) {
+  int b[4];
+  pick_tile(lat->L, b);
+  Geom g = make_geom(lat->L, b, lat->t_antiperiodic ? 1 : 0);
+  using C = c_t<T>;
+  const size_t Vp = g.Vpad;
+  const size_t need = sizeof(C) * (36 + 24 * (size_t)nrhs) * Vp;  // links, in, out
+  if (need > (size_t)MG_NOALLOC_BYTES) {
+    char buf[256];
+    std::snprintf(buf, sizeof(buf),
+                  "wilson_apply_noalloc: this lattice and nrhs need %zu bytes of scratch, above the %zu-byte limit",
+                  need, (size_t)MG_NOALLOC_BYTES);
+    set_error(buf);
+    return MG_ENOMEM;
+  }
+  unsigned char *base = nullptr;
+  MG_TRY(noalloc_scratch(&base));
+  C *Ui = reinterpret_cast<C *>(base);
+  C *xi = Ui + 36 * Vp;
+  C *yi = xi + 12 * Vp * (size_t)nrhs;
+  hipError_t e = pack_gauge<T>(g, (const double2 *)U, Ui, st);
+  if (e == hipSuccess) e = pack_field<T>(g, (const double2 *)in, xi, 12, nrhs, st);
+  if (e == hipSuccess) e = dslash<T>(g, Ui, 9, xi, yi, nullptr, 4.0 + mass, nrhs, DS_PLAIN, nullptr, st);
+  if (e == hipSuccess) e = unpack_field<T>(g, yi, (double2 *)out, 12, nrhs, st);
+  if (e != hipSuccess) {
+    set_error(hip_error_string(e, "wilson_apply_noalloc"));
+    return MG_EHIP;
+  }
+  return MG_OK;
+}
+
 }  // namespace mg
 
 using namespace mg;
+
+extern "C" int wilson_apply_noalloc(const mg_lattice_t *lat, const void *U, double mass, const void *in, void *out,
+                                    int nrhs, mg_prec_t prec, hipStream_t stream) {
+  set_error("");
+  MG_TRY(check_lattice(lat));
+  if (!U || !in || !out) { set_error("wilson_apply_noalloc: NULL buffer"); return MG_EINVAL; }
+  if (in == out) { set_error("wilson_apply_noalloc: in and out alias"); return MG_EINVAL; }
+  if (nrhs < 1 || nrhs > 65535) { set_error("wilson_apply_noalloc: nrhs out of range"); return MG_EINVAL; }
+  if (prec == MG_F64) return wilson_apply_noalloc_t<double>(lat, U, mass, in, out, nrhs, stream);
+  if (prec == MG_F32) return wilson_apply_noalloc_t<float>(lat, U, mass, in, out, nrhs, stream);
+  set_error("wilson_apply_noalloc: precision must be MG_F64 or MG_F32");
+  return MG_ENOTSUP;
+}
 
 extern "C" int wilson_apply(const mg_lattice_t *lat, const void *U, double mass, const void *in, void *out,
                             int nrhs, mg_prec_t prec, hipStream_t stream) {
