@@ -135,26 +135,30 @@ __device__ __forceinline__ void dslash_site_k(C (&res)[K][12], C (&ctr)[K][12], 
 // x-y layer apart on the same XCD (L2), and the XCDs move through t in step,
 // so the z neighbours another XCD needs are read at about the same time.
 // (The aggregate-major order walks x, y, z, then t, with each XCD owning a
-// t range; on 32^3 x 64 the visiting order above is 4-6 % faster.)
+// t range; on 32^3 x 64 the visiting order above is 3-6 % faster, and
+// walking 4x4-aggregate x-y quadrants in t or in z instead is 5-13 % slower.)
 // Otherwise the order is the storage order.
-__device__ __forceinline__ uint32_t visit_block(uint32_t bid, uint32_t nblk, const Geom &g, uint32_t per) {
-  const uint32_t q = xcd_remap(bid, nblk);
+__device__ __forceinline__ uint32_t visit_pos(uint32_t q, uint32_t nblk, const Geom &g, uint32_t per) {
   const uint32_t sub = g.vb / per;
-  if ((nblk & 7u) == 0 && g.C[2] % 8 == 0 && sub * per == g.vb && nblk == g.Vc * sub) {
+  const uint32_t C0 = (uint32_t)g.C[0], C1 = (uint32_t)g.C[1], C2 = (uint32_t)g.C[2], C3 = (uint32_t)g.C[3];
+  if ((nblk & 7u) == 0 && C2 % 8 == 0 && sub * per == g.vb && nblk == g.Vc * sub) {
     const uint32_t per_xcd = nblk >> 3, xcd = q / per_xcd, r0 = q - xcd * per_xcd;
     const uint32_t j = r0 % sub;
     uint32_t r = r0 / sub;
-    const uint32_t cx = r % (uint32_t)g.C[0];
-    r /= (uint32_t)g.C[0];
-    const uint32_t cy = r % (uint32_t)g.C[1];
-    r /= (uint32_t)g.C[1];
-    const uint32_t ct = r % (uint32_t)g.C[3];
-    const uint32_t cz = xcd * ((uint32_t)g.C[2] >> 3) + r / (uint32_t)g.C[3];
-    const uint32_t B = cx + (uint32_t)g.C[0] * (cy + (uint32_t)g.C[1] * (cz + (uint32_t)g.C[2] * ct));
-    return B * sub + j;
+    const uint32_t cx = r % C0;
+    r /= C0;
+    const uint32_t cy = r % C1;
+    r /= C1;
+    const uint32_t ct = r % C3;
+    const uint32_t cz = xcd * (C2 >> 3) + r / C3;
+    return (cx + C0 * (cy + C1 * (cz + C2 * ct))) * sub + j;
   }
   return q;
 }
+__device__ __forceinline__ uint32_t visit_block(uint32_t bid, uint32_t nblk, const Geom &g, uint32_t per) {
+  return visit_pos(xcd_remap(bid, nblk), nblk, g, per);
+}
+
 
 // Minimum waves per SIMD requested from the register allocator (0 = none).
 #ifndef MG_DSLASH_WAVES_F64
@@ -221,7 +225,9 @@ __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash(Geom g, const
 // group of K right-hand sides cover the lattice, grid.y = groups.  K = 2:
 // on 32^3 x 64 with 12 right-hand sides, per right-hand side FP64 0.40 ms
 // (one per thread: 0.47 ms), FP32 0.214 ms (0.231), FP16-stored links 0.195
-// ms (0.198); K = 4 is slower in FP32 (0.248 ms: one wave per SIMD).  A ragged last group repeats its last
+// ms (0.198); K = 4 is slower in FP32 (0.248 ms: one wave per SIMD), and so
+// is running the groups of one block back to back on an XCD (links from L2,
+// but the spinor neighbours further apart: FP32 0.228 ms, more traffic).  A ragged last group repeats its last
 // right-hand side in the spare slots and stores only the valid ones.
 template <typename R, int MODE, int NL, typename S, int K, typename TI = c_t<R>>
 __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash_rb(Geom g, const S *__restrict__ U, const TI *__restrict__ in,
@@ -229,9 +235,10 @@ __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash_rb(Geom g, co
                                                    double *__restrict__ partials, int nrhs) {
   using C = c_t<R>;
   const int r0 = blockIdx.y * K;
+  const uint32_t blk = visit_block(blockIdx.x, gridDim.x, g, blockDim.x);
+  const uint32_t slot = blockIdx.x, nslot = gridDim.x;
   const int kv = nrhs - r0 < K ? nrhs - r0 : K;
   const size_t vs = (size_t)12 * g.Vpad;
-  const uint32_t blk = visit_block(blockIdx.x, gridDim.x, g, blockDim.x);
   const uint32_t s = blk * blockDim.x + threadIdx.x;
   double red[K][3];
 #pragma unroll
@@ -272,7 +279,7 @@ __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash_rb(Geom g, co
     block_sum<3 * K>(v, lds);
     if (threadIdx.x == 0) {
       for (int k = 0; k < kv; ++k) {
-        double *p = partials + ((size_t)(r0 + k) * gridDim.x + blockIdx.x) * 3;
+        double *p = partials + ((size_t)(r0 + k) * nslot + slot) * 3;
         p[0] = v[3 * k];
         p[1] = v[3 * k + 1];
         p[2] = v[3 * k + 2];
