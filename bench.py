@@ -40,9 +40,12 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dslash_c3_12rhs_traffic.txt")
 # kernel name in the counter summary for each precision class of the stencil
 TRAFFIC_KERNEL = {"f64": "dslash_f64_12rhs", "f32": "dslash_f32_12rhs", "f16": "dslash_f16_12rhs"}
 
-# bytes per real of (vectors, operators) for each precision class; "f16"
-# keeps FP32 vectors and stores the operators (links, P, D_c) in binary16
-WIDTH = {"f64": (8.0, 8.0), "f32": (4.0, 4.0), "f16": (4.0, 2.0)}
+# bytes per real of (fine-level spinors, operators) for each precision class;
+# "f16" stores the operators (links, P, D_c) in binary16 and the fine spinors
+# of the cycle in binary16 with one FP32 scale per site (52 bytes per site
+# for 24 reals); coarse vectors stay FP32 in that class
+WIDTH = {"f64": (8.0, 8.0), "f32": (4.0, 4.0), "f16": (52.0 / 24.0, 2.0)}
+COARSE_VEC = {"f64": 8.0, "f32": 4.0, "f16": 4.0}
 
 
 def dslash_bytes(prec, compressed=False):
@@ -54,8 +57,8 @@ def dslash_bytes(prec, compressed=False):
 
 def coarse_bytes(n, prec):
     """Per coarse site: 9 n^2 operator entries + vector in and out."""
-    wv, wl = WIDTH[prec]
-    return 2 * (9 * n * n * wl + 2 * n * wv)
+    wl = WIDTH[prec][1]
+    return 2 * (9 * n * n * wl + 2 * n * COARSE_VEC[prec])
 
 
 def dslash_flops(compressed=False):
@@ -493,7 +496,7 @@ def main():
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": round(ms_step, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64 outer / " + {"f16": "f16-stored operators, f32 arithmetic", "f32": "f32",
+        "dtype": "f64 outer / " + {"f16": "f16-stored operators and fine spinors, f32 arithmetic", "f32": "f32",
                                    "f64": "f64"}[a.precond] + " preconditioner",
         "data": "synthetic (seeded random SU(3) links, 12 spin-colour point sources at the origin)",
         "config": {"workload": f"three-level MG, 32^3x64, eps {cfg['eps']}, aggregates 4^4 then 2^4, Nv 24/24, "

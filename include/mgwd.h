@@ -77,7 +77,11 @@ typedef struct {
   int gcr_restart;                   /* flexible GCR restart length (8)      */
   int max_iter;                      /* outer iteration cap                  */
   mg_prec_t precond_prec;            /* MG_F64, MG_F32 or MG_F16 (FP16-stored
-                                        links, P and D_c; FP32 arithmetic)   */
+                                        links, P and D_c; inside the cycle
+                                        the fine level's input, smoother
+                                        residual and stencil output stored
+                                        as binary16 with per-site scales;
+                                        FP32 arithmetic)                     */
   int max_rhs;                       /* largest nrhs passed to mg_solve      */
   int use_graph;                     /* 1: replay the coarsest-level CGNR
                                         iterations from captured hipGraphs  */
@@ -146,9 +150,13 @@ typedef struct {
 
 /* Fine Wilson operator out = D(U) in (Eq. 2) on nrhs canonical spinors.
  * U, in, out: DEVICE complex128 canonical layouts (in and out may not
- * alias).  prec selects the arithmetic of the stencil (MG_F64 or MG_F32;
- * inputs and outputs stay complex128).  Stateless: converts to the
- * library's internal site-blocked SoA layout and back on every call.     */
+ * alias).  prec selects the arithmetic of the stencil: MG_F64, MG_F32, or
+ * MG_F16 (links and spinors stored in binary16, the spinors of each site
+ * divided by the largest |Re|, |Im| of its 12 components, which is kept in
+ * FP32; FP32 arithmetic; the input is rounded to FP32, then to binary16, so
+ * every stored entry carries a relative rounding of up to 2^-11).  Inputs
+ * and outputs stay complex128.  Stateless: converts to the library's
+ * internal site-blocked SoA layout and back on every call.               */
 int wilson_apply(const mg_lattice_t *lat, const void *U, double mass,
                  const void *in, void *out, int nrhs, mg_prec_t prec,
                  hipStream_t stream);
@@ -236,7 +244,9 @@ int mg_apply_op(mg_ctx_t *ctx, int level, mg_prec_t prec, const void *in,
  * steps), restriction, the next level's cycle (CGNR to coarse_tol on the
  * coarsest level), prolongation added to the smoothed iterate, MR
  * post-smoothing on the new residual (post steps), on every level below the
- * coarsest.  prec as mg_apply_op.  in/out: DEVICE complex128 canonical fine
+ * coarsest.  prec as mg_apply_op; with MG_F16 the cycle keeps the fine
+ * level's input, smoother residual and stencil output in binary16 with
+ * per-site scales (its correction x in FP32).  in/out: DEVICE complex128 canonical fine
  * spinors [nrhs][Lt][Lz][Ly][Lx][4][3], not aliased; 1 <= nrhs <= 16.
  * cgnr_iters (host, may be NULL) receives the coarsest-level CGNR
  * iterations of this call summed over the right-hand sides.  Ordered on

@@ -49,6 +49,43 @@ static int wilson_apply_t(const mg_lattice_t *lat, const void *U, double mass, c
   return MG_OK;
 }
 
+// FP16 class: links and spinors stored in binary16 (spinors with a per-site
+// scale), FP32 arithmetic; the complex128 input is rounded to FP32 and then
+// to binary16, and the output widened back.
+static int wilson_apply_f16(const mg_lattice_t *lat, const void *U, double mass, const void *in, void *out,
+                            int nrhs, hipStream_t st) {
+  int b[4];
+  pick_tile(lat->L, b);
+  Geom g = make_geom(lat->L, b, lat->t_antiperiodic ? 1 : 0);
+  const size_t Vp = g.Vpad;
+  double2 *U64 = nullptr, *f64 = nullptr;
+  chalf *Uh = nullptr;
+  h16 *xh = nullptr, *yh = nullptr;
+  hipError_t e = hipMallocAsync((void **)&U64, sizeof(double2) * 36 * Vp, st);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&f64, sizeof(double2) * 12 * Vp * nrhs, st);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&Uh, sizeof(chalf) * 36 * Vp, st);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&xh, sizeof(h16) * 13 * Vp * nrhs, st);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&yh, sizeof(h16) * 13 * Vp * nrhs, st);
+  if (e == hipSuccess) e = pack_gauge<double>(g, (const double2 *)U, U64, st);
+  if (e == hipSuccess) e = store_convert<chalf>(Uh, U64, 36 * Vp, st);
+  if (e == hipSuccess) e = pack_field<double>(g, (const double2 *)in, f64, 12, nrhs, st);
+  if (e == hipSuccess) e = to_h16<double2>(xh, f64, (uint32_t)Vp, nrhs, st);
+  if (e == hipSuccess)
+    e = dslash<float, chalf, h16, h16>(g, Uh, 9, xh, yh, nullptr, 4.0 + mass, nrhs, DS_PLAIN, nullptr, st);
+  if (e == hipSuccess) e = from_h16<double2>(f64, yh, (uint32_t)Vp, nrhs, st);
+  if (e == hipSuccess) e = unpack_field<double>(g, f64, (double2 *)out, 12, nrhs, st);
+  if (yh) (void)hipFreeAsync(yh, st);
+  if (xh) (void)hipFreeAsync(xh, st);
+  if (Uh) (void)hipFreeAsync(Uh, st);
+  if (f64) (void)hipFreeAsync(f64, st);
+  if (U64) (void)hipFreeAsync(U64, st);
+  if (e != hipSuccess) {
+    set_error(hip_error_string(e, "wilson_apply"));
+    return MG_EHIP;
+  }
+  return MG_OK;
+}
+
 // ---------------------------------------------------------------- no-alloc
 // Scratch of wilson_apply_noalloc: the internal link and spinor layouts of
 // one call, in a file-scope device array that each GPU the library runs on
@@ -137,7 +174,8 @@ extern "C" int wilson_apply(const mg_lattice_t *lat, const void *U, double mass,
   if (nrhs < 1 || nrhs > 65535) { set_error("wilson_apply: nrhs out of range"); return MG_EINVAL; }
   if (prec == MG_F64) return wilson_apply_t<double>(lat, U, mass, in, out, nrhs, stream);
   if (prec == MG_F32) return wilson_apply_t<float>(lat, U, mass, in, out, nrhs, stream);
-  set_error("wilson_apply: precision must be MG_F64 or MG_F32");
+  if (prec == MG_F16) return wilson_apply_f16(lat, U, mass, in, out, nrhs, stream);
+  set_error("wilson_apply: precision must be MG_F64, MG_F32 or MG_F16");
   return MG_ENOTSUP;
 }
 

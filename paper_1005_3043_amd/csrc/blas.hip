@@ -97,6 +97,57 @@ template hipError_t transpose_convert<chalf>(chalf *, const double2 *, uint32_t,
 template hipError_t store_convert<float2>(float2 *, const double2 *, size_t, hipStream_t);
 template hipError_t store_convert<chalf>(chalf *, const double2 *, size_t, hipStream_t);
 
+// ---------------------------------------------------------------- binary16 spinor fields
+// One site per thread: the site's scale needs all 12 of its components.
+// Every site of the Vpad padded sites is written (padding sites are zero in
+// the source, so they get scale 0 and zero entries).
+template <typename Cs> __global__ __launch_bounds__(256) void k_to_h16(h16 *y, const Cs *x, uint32_t Vpad) {
+  y += (size_t)blockIdx.y * 13 * Vpad;
+  x += (size_t)blockIdx.y * 12 * Vpad;
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < Vpad; s += gridDim.x * blockDim.x) {
+    float2 v[12];
+    load_site(v, x, s);
+    store_site(y, s, v);
+  }
+}
+template <typename Cd> __global__ __launch_bounds__(256) void k_from_h16(Cd *y, const h16 *x, uint32_t Vpad) {
+  y += (size_t)blockIdx.y * 12 * Vpad;
+  x += (size_t)blockIdx.y * 13 * Vpad;
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < Vpad; s += gridDim.x * blockDim.x) {
+    float2 v[12];
+    load_site(v, x, s);
+    Cd w[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) w[c] = cvt<Cd>(v[c]);
+    store_site(y, s, w);
+  }
+}
+__global__ __launch_bounds__(256) void k_copy_words(uint32_t *y, const uint32_t *x, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = x[i];
+}
+
+template <typename Cs> hipError_t to_h16(h16 *y, const Cs *x, uint32_t Vpad, int nrhs, hipStream_t st) {
+  if (Vpad == 0 || nrhs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_to_h16<Cs>, dim3(stream_grid(Vpad), nrhs), dim3(256), 0, st, y, x, Vpad);
+  return hipGetLastError();
+}
+template <typename Cd> hipError_t from_h16(Cd *y, const h16 *x, uint32_t Vpad, int nrhs, hipStream_t st) {
+  if (Vpad == 0 || nrhs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_from_h16<Cd>, dim3(stream_grid(Vpad), nrhs), dim3(256), 0, st, y, x, Vpad);
+  return hipGetLastError();
+}
+hipError_t copy_h16(h16 *y, const h16 *x, uint32_t Vpad, int nrhs, hipStream_t st) {
+  const size_t n = (size_t)13 * Vpad * nrhs;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_words, dim3(stream_grid(n)), dim3(256), 0, st, (uint32_t *)y, (const uint32_t *)x, n);
+  return hipGetLastError();
+}
+template hipError_t to_h16<double2>(h16 *, const double2 *, uint32_t, int, hipStream_t);
+template hipError_t to_h16<float2>(h16 *, const float2 *, uint32_t, int, hipStream_t);
+template hipError_t from_h16<double2>(double2 *, const h16 *, uint32_t, int, hipStream_t);
+template hipError_t from_h16<float2>(float2 *, const h16 *, uint32_t, int, hipStream_t);
+
 template hipError_t zero<double>(double2 *, size_t, hipStream_t);
 template hipError_t zero<float>(float2 *, size_t, hipStream_t);
 template hipError_t copy<double>(double2 *, const double2 *, size_t, hipStream_t);

@@ -81,6 +81,15 @@ template <typename C, typename S> __host__ __device__ __forceinline__ C cvt(S v)
   c.y = static_cast<decltype(C::x)>(v.y);
   return c;
 }
+// Fine-level spinor entry of the FP16 preconditioner.  A site's 12 complex
+// components are stored in binary16 after division by the site's scale m =
+// max |Re|, |Im| over them (so every stored magnitude is at most 1 and the
+// relative rounding is that of binary16, 2^-11, whatever the site's size),
+// and m itself sits in a 13th slot of the site as an FP32 number.  A field
+// of V sites takes 13 slots of 4 bytes per site (52 bytes against 96 in
+// FP32), in the tile-interleaved layout with ncomp = 13.
+struct __align__(4) h16 { _Float16 x, y; };
+
 // multiply by i^k (k = 0: 1, 1: i, 2: -1, 3: -i)
 template <int k, typename C> __host__ __device__ __forceinline__ C mul_ipow(C a) {
   if constexpr (k == 0) return a;
@@ -135,6 +144,64 @@ struct Coords { int o[4]; int c[4]; uint32_t B, l; };
 constexpr int TILE = 64;
 __host__ __device__ __forceinline__ size_t fidx(uint32_t s, int c, int ncomp) {
   return ((size_t)(s >> 6) * ncomp + c) * TILE + (s & (TILE - 1));
+}
+
+// Slots per site of a fine-level spinor field stored as T.
+template <typename T> struct SiteSlots { static constexpr int n = 12; };
+template <> struct SiteSlots<h16> { static constexpr int n = 13; };
+template <typename T> constexpr int site_slots() { return SiteSlots<T>::n; }
+
+// The 12 components of site s of one spinor field, as complex type C.
+template <typename C, typename T>
+__host__ __device__ __forceinline__ void load_site(C (&v)[12], const T *__restrict__ f, uint32_t s) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) v[c] = cvt<C>(f[fidx(s, c, 12)]);
+}
+template <typename C>
+__host__ __device__ __forceinline__ void load_site(C (&v)[12], const h16 *__restrict__ f, uint32_t s) {
+  const float m = __builtin_bit_cast(float, f[fidx(s, 12, 13)]);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const h16 e = f[fidx(s, c, 13)];
+    v[c] = mk<C>((float)e.x * m, (float)e.y * m);
+  }
+}
+
+// Stores the 12 components of site s (NT: non-temporal stores, for output
+// that the launch does not read again).  For binary16 storage the site's
+// scale is computed here and v is replaced by the values as stored (decoded),
+// so that sums formed from v afterwards agree with what was written.
+template <bool NT = false, typename C, typename T>
+__device__ __forceinline__ void store_site(T *__restrict__ f, uint32_t s, C (&v)[12]) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const T e = cvt<T>(v[c]);
+    if constexpr (NT) {
+      __builtin_nontemporal_store(e.x, &f[fidx(s, c, 12)].x);
+      __builtin_nontemporal_store(e.y, &f[fidx(s, c, 12)].y);
+    } else {
+      f[fidx(s, c, 12)] = e;
+    }
+  }
+}
+template <bool NT = false, typename C>
+__device__ __forceinline__ void store_site(h16 *__restrict__ f, uint32_t s, C (&v)[12]) {
+  float m = 0.f;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf((float)v[c].x), fabsf((float)v[c].y)));
+  const float inv = m > 0.f ? 1.0f / m : 0.f;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    h16 e;
+    e.x = (_Float16)((float)v[c].x * inv);
+    e.y = (_Float16)((float)v[c].y * inv);
+    v[c] = mk<C>((float)e.x * m, (float)e.y * m);
+    if constexpr (NT) __builtin_nontemporal_store(__builtin_bit_cast(float, e), (float *)&f[fidx(s, c, 13)]);
+    else f[fidx(s, c, 13)] = e;
+  }
+  const h16 ms = __builtin_bit_cast(h16, m);
+  if constexpr (NT) __builtin_nontemporal_store(m, (float *)&f[fidx(s, 12, 13)]);
+  else f[fidx(s, 12, 13)] = ms;
 }
 
 __host__ __device__ __forceinline__ Coords decode(const Geom &g, uint32_t s) {

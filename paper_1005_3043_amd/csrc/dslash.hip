@@ -36,12 +36,6 @@ __device__ __forceinline__ void load_link_t(C (&u)[9], const S *__restrict__ U, 
   if constexpr (NL == 6) reconstruct_row2(u);
 }
 
-template <typename C, typename TI>
-__host__ __device__ __forceinline__ void load_spinor_t(C (&psi)[12], const TI *__restrict__ in, uint32_t s) {
-#pragma unroll
-  for (int c = 0; c < 12; ++c) psi[c] = cvt<C>(in[fidx(s, c, 12)]);
-}
-
 // Full stencil at one site: res = D psi at s, ctr = psi(s).  The input
 // spinors may be stored in a narrower type TI than the arithmetic type C.
 template <int NL, typename C, typename S, typename TI>
@@ -62,14 +56,14 @@ __device__ __forceinline__ void dslash_site(C (&res)[12], C (&ctr)[12], const Ge
       if (k.o[3] == g.b[3] - 1 && k.c[3] == g.C[3] - 1) ef = -1;
       if (k.o[3] == 0 && k.c[3] == 0) eb = -1;
     }
-    load_spinor_t(pf, in, sf);
-    load_spinor_t(pb, in, sb);
+    load_site(pf, in, sf);
+    load_site(pb, in, sb);
     load_link_t<NL>(uf, U, mu, s);
     load_link_t<NL>(ub, U, mu, sb);
     hop_dispatch<true>(mu, acc, pf, uf, ef);
     hop_dispatch<false>(mu, acc, pb, ub, eb);
   }
-  load_spinor_t(ctr, in, s);
+  load_site(ctr, in, s);
 #pragma unroll
   for (int i = 0; i < 12; ++i) {
     res[i].x = fma(diag, ctr[i].x, (R)-0.5 * acc[i].x);
@@ -104,20 +98,20 @@ __device__ __forceinline__ void dslash_site_k(C (&res)[K][12], C (&ctr)[K][12], 
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       C p[12];
-      load_spinor_t(p, in + (size_t)(k < kv ? k : kv - 1) * vs, sf);
+      load_site(p, in + (size_t)(k < kv ? k : kv - 1) * vs, sf);
       hop_dispatch<true>(mu, acc[k], p, u, ef);
     }
     load_link_t<NL>(u, U, mu, sb);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       C p[12];
-      load_spinor_t(p, in + (size_t)(k < kv ? k : kv - 1) * vs, sb);
+      load_site(p, in + (size_t)(k < kv ? k : kv - 1) * vs, sb);
       hop_dispatch<false>(mu, acc[k], p, u, eb);
     }
   }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    load_spinor_t(ctr[k], in + (size_t)(k < kv ? k : kv - 1) * vs, s);
+    load_site(ctr[k], in + (size_t)(k < kv ? k : kv - 1) * vs, s);
 #pragma unroll
     for (int i = 0; i < 12; ++i) {
       res[k][i].x = fma(diag, ctr[k][i].x, (R)-0.5 * acc[k][i].x);
@@ -171,14 +165,17 @@ template <typename R> constexpr int dslash_waves() {
   return sizeof(R) == 8 ? MG_DSLASH_WAVES_F64 : MG_DSLASH_WAVES_F32;
 }
 
-template <typename R, int MODE, int NL, typename S, typename TI = c_t<R>>
+// One site per thread, one right-hand side per grid row.  Input spinors
+// are stored as TI, the output (and b of the residual mode) as TO: complex
+// FP64 / FP32, or binary16 with a per-site scale (h16).
+template <typename R, int MODE, int NL, typename S, typename TI, typename TO>
 __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash(Geom g, const S *__restrict__ U,
-                                                const TI *__restrict__ in, c_t<R> *__restrict__ out,
-                                                const c_t<R> *__restrict__ b, R diag,
+                                                const TI *__restrict__ in, TO *__restrict__ out,
+                                                const TO *__restrict__ b, R diag,
                                                 double *__restrict__ partials) {
   using C = c_t<R>;
-  const size_t off = (size_t)blockIdx.y * 12 * g.Vpad;
-  in += off;
+  in += (size_t)blockIdx.y * site_slots<TI>() * g.Vpad;
+  const size_t off = (size_t)blockIdx.y * site_slots<TO>() * g.Vpad;
   out += off;
   const uint32_t tile = visit_block(blockIdx.x, gridDim.x, g, blockDim.x);
   const uint32_t s = tile * blockDim.x + threadIdx.x;
@@ -187,21 +184,18 @@ __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash(Geom g, const
     C res[12], ctr[12];
     dslash_site<NL, C>(res, ctr, g, s, U, in, diag);
     if constexpr (MODE == DS_RESID) {
-      const C *bb = b + off;
+      C bb[12];
+      load_site(bb, b + off, s);
 #pragma unroll
-      for (int i = 0; i < 12; ++i) res[i] = csub(bb[fidx(s, i, 12)], res[i]);
+      for (int i = 0; i < 12; ++i) res[i] = csub(bb[i], res[i]);
     }
-#pragma unroll
-    for (int i = 0; i < 12; ++i) {
-      // the output is not read again by this launch: a non-temporal store
-      // leaves L2 to the neighbour spinors and links that are
-      __builtin_nontemporal_store(res[i].x, &out[fidx(s, i, 12)].x);
-      __builtin_nontemporal_store(res[i].y, &out[fidx(s, i, 12)].y);
-    }
+    // the output is not read again by this launch: non-temporal stores leave
+    // L2 to the neighbour spinors and links that are
+    store_site<true>(out, s, res);
     if constexpr (MODE == DS_MR) {
 #pragma unroll
       for (int i = 0; i < 12; ++i) {
-        // <q, r> = sum conj(q) r with q = D r, r = centre
+        // <q, r> = sum conj(q) r with q = D r (as stored), r = centre
         red[0] += (double)res[i].x * ctr[i].x + (double)res[i].y * ctr[i].y;
         red[1] += (double)res[i].x * ctr[i].y - (double)res[i].y * ctr[i].x;
         red[2] += (double)res[i].x * res[i].x + (double)res[i].y * res[i].y;
@@ -229,36 +223,34 @@ __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash(Geom g, const
 // is running the groups of one block back to back on an XCD (links from L2,
 // but the spinor neighbours further apart: FP32 0.228 ms, more traffic).  A ragged last group repeats its last
 // right-hand side in the spare slots and stores only the valid ones.
-template <typename R, int MODE, int NL, typename S, int K, typename TI = c_t<R>>
+template <typename R, int MODE, int NL, typename S, int K, typename TI, typename TO>
 __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash_rb(Geom g, const S *__restrict__ U, const TI *__restrict__ in,
-                                                   c_t<R> *__restrict__ out, const c_t<R> *__restrict__ b, R diag,
+                                                   TO *__restrict__ out, const TO *__restrict__ b, R diag,
                                                    double *__restrict__ partials, int nrhs) {
   using C = c_t<R>;
   const int r0 = blockIdx.y * K;
   const uint32_t blk = visit_block(blockIdx.x, gridDim.x, g, blockDim.x);
   const uint32_t slot = blockIdx.x, nslot = gridDim.x;
   const int kv = nrhs - r0 < K ? nrhs - r0 : K;
-  const size_t vs = (size_t)12 * g.Vpad;
+  const size_t vsi = (size_t)site_slots<TI>() * g.Vpad, vso = (size_t)site_slots<TO>() * g.Vpad;
   const uint32_t s = blk * blockDim.x + threadIdx.x;
   double red[K][3];
 #pragma unroll
   for (int k = 0; k < K; ++k) red[k][0] = red[k][1] = red[k][2] = 0.0;
   if (s < g.V) {
     C res[K][12], ctr[K][12];
-    dslash_site_k<K, NL, C>(res, ctr, g, s, U, in + (size_t)r0 * vs, vs, kv, diag);
+    dslash_site_k<K, NL, C>(res, ctr, g, s, U, in + (size_t)r0 * vsi, vsi, kv, diag);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       if (k >= kv) break;
-      const size_t off = (size_t)(r0 + k) * vs;
+      const size_t off = (size_t)(r0 + k) * vso;
       if constexpr (MODE == DS_RESID) {
+        C bb[12];
+        load_site(bb, b + off, s);
 #pragma unroll
-        for (int i = 0; i < 12; ++i) res[k][i] = csub(b[off + fidx(s, i, 12)], res[k][i]);
+        for (int i = 0; i < 12; ++i) res[k][i] = csub(bb[i], res[k][i]);
       }
-#pragma unroll
-      for (int i = 0; i < 12; ++i) {
-        __builtin_nontemporal_store(res[k][i].x, &out[off + fidx(s, i, 12)].x);
-        __builtin_nontemporal_store(res[k][i].y, &out[off + fidx(s, i, 12)].y);
-      }
+      store_site<true>(out + off, s, res[k]);
       if constexpr (MODE == DS_MR) {
 #pragma unroll
         for (int i = 0; i < 12; ++i) {
@@ -293,75 +285,58 @@ constexpr int MRHS_K = 2;
 int dslash_blocks(const Geom &g) { return div_up(g.V, 256); }
 int dslash_partials(const Geom &g, int) { return dslash_blocks(g); }
 
-template <typename R, int NL, typename S, int K>
-static hipError_t launch_rb(const Geom &g, const S *U, const c_t<R> *in, c_t<R> *out, const c_t<R> *b, double diag,
-                            int nrhs, DslashMode mode, double *partials, hipStream_t st) {
-  dim3 grid(dslash_blocks(g), (nrhs + K - 1) / K);
-  switch (mode) {
-    case DS_PLAIN:
-      hipLaunchKernelGGL((k_dslash_rb<R, DS_PLAIN, NL, S, K>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag,
-                         partials, nrhs);
-      break;
-    case DS_RESID:
-      hipLaunchKernelGGL((k_dslash_rb<R, DS_RESID, NL, S, K>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag,
-                         partials, nrhs);
-      break;
-    case DS_MR:
-      hipLaunchKernelGGL((k_dslash_rb<R, DS_MR, NL, S, K>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag,
-                         partials, nrhs);
-      break;
+template <typename R, int NL, typename S, typename TI, typename TO>
+static hipError_t launch(const Geom &g, const S *U, const TI *in, TO *out, const TO *b, double diag, int nrhs,
+                         DslashMode mode, double *partials, hipStream_t st) {
+  if (nrhs > 1) {
+    constexpr int K = MRHS_K;
+    dim3 grid(dslash_blocks(g), (nrhs + K - 1) / K);
+    switch (mode) {
+      case DS_PLAIN:
+        hipLaunchKernelGGL((k_dslash_rb<R, DS_PLAIN, NL, S, K, TI, TO>), grid, dim3(256), 0, st, g, U, in, out, b,
+                           (R)diag, partials, nrhs);
+        break;
+      case DS_RESID:
+        hipLaunchKernelGGL((k_dslash_rb<R, DS_RESID, NL, S, K, TI, TO>), grid, dim3(256), 0, st, g, U, in, out, b,
+                           (R)diag, partials, nrhs);
+        break;
+      case DS_MR:
+        hipLaunchKernelGGL((k_dslash_rb<R, DS_MR, NL, S, K, TI, TO>), grid, dim3(256), 0, st, g, U, in, out, b,
+                           (R)diag, partials, nrhs);
+        break;
+    }
+    return hipGetLastError();
   }
-  return hipGetLastError();
-}
-
-template <typename R, int NL, typename S>
-static hipError_t launch(const Geom &g, const S *U, const c_t<R> *in, c_t<R> *out, const c_t<R> *b, double diag,
-                         int nrhs, DslashMode mode, double *partials, hipStream_t st) {
-  if (nrhs > 1) return launch_rb<R, NL, S, MRHS_K>(g, U, in, out, b, diag, nrhs, mode, partials, st);
   dim3 grid(dslash_blocks(g), nrhs);
   switch (mode) {
     case DS_PLAIN:
-      hipLaunchKernelGGL((k_dslash<R, DS_PLAIN, NL, S>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag,
+      hipLaunchKernelGGL((k_dslash<R, DS_PLAIN, NL, S, TI, TO>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag,
                          partials);
       break;
     case DS_RESID:
-      hipLaunchKernelGGL((k_dslash<R, DS_RESID, NL, S>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag,
+      hipLaunchKernelGGL((k_dslash<R, DS_RESID, NL, S, TI, TO>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag,
                          partials);
       break;
     case DS_MR:
-      hipLaunchKernelGGL((k_dslash<R, DS_MR, NL, S>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag, partials);
+      hipLaunchKernelGGL((k_dslash<R, DS_MR, NL, S, TI, TO>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag,
+                         partials);
       break;
   }
   return hipGetLastError();
 }
 
-template <typename R, typename S>
-hipError_t dslash(const Geom &g, const S *U, int nl, const c_t<R> *in, c_t<R> *out, const c_t<R> *b, double diag,
-                  int nrhs, DslashMode mode, double *partials, hipStream_t st) {
+template <typename R, typename S, typename TI, typename TO>
+hipError_t dslash(const Geom &g, const S *U, int nl, const TI *in, TO *out, const typename same_t<TO>::type *b,
+                  double diag, int nrhs, DslashMode mode, double *partials, hipStream_t st) {
   if (nl == 6) return launch<R, 6, S>(g, U, in, out, b, diag, nrhs, mode, partials, st);
   return launch<R, 9, S>(g, U, in, out, b, diag, nrhs, mode, partials, st);
 }
 
 // Plain stencil in FP64 arithmetic on FP32-stored input spinors (the
 // flexible GCR applies D to the preconditioner's FP32 output this way).
-template <int NL>
-static hipError_t launch_in32(const Geom &g, const double2 *U, const float2 *in, double2 *out, double diag,
-                              int nrhs, hipStream_t st) {
-  if (nrhs > 1) {
-    dim3 grid(dslash_blocks(g), (nrhs + MRHS_K - 1) / MRHS_K);
-    hipLaunchKernelGGL((k_dslash_rb<double, DS_PLAIN, NL, double2, MRHS_K, float2>), grid, dim3(256), 0, st, g, U,
-                       in, out, nullptr, diag, nullptr, nrhs);
-  } else {
-    hipLaunchKernelGGL((k_dslash<double, DS_PLAIN, NL, double2, float2>), dim3(dslash_blocks(g), 1), dim3(256), 0,
-                       st, g, U, in, out, nullptr, diag, nullptr);
-  }
-  return hipGetLastError();
-}
-
 hipError_t dslash_in32(const Geom &g, const double2 *U, int nl, const float2 *in, double2 *out, double diag,
                        int nrhs, hipStream_t st) {
-  if (nl == 6) return launch_in32<6>(g, U, in, out, diag, nrhs, st);
-  return launch_in32<9>(g, U, in, out, diag, nrhs, st);
+  return dslash<double, double2, float2, double2>(g, U, nl, in, out, nullptr, diag, nrhs, DS_PLAIN, nullptr, st);
 }
 
 // ---------------------------------------------------------------- links
@@ -403,12 +378,16 @@ hipError_t compress_links(const Geom &g, const double2 *U, S *Uc, double *blockm
   return hipGetLastError();
 }
 
-template hipError_t dslash<double, double2>(const Geom &, const double2 *, int, const double2 *, double2 *,
-                                            const double2 *, double, int, DslashMode, double *, hipStream_t);
-template hipError_t dslash<float, float2>(const Geom &, const float2 *, int, const float2 *, float2 *,
-                                          const float2 *, double, int, DslashMode, double *, hipStream_t);
-template hipError_t dslash<float, chalf>(const Geom &, const chalf *, int, const float2 *, float2 *,
-                                         const float2 *, double, int, DslashMode, double *, hipStream_t);
+#define DSLASH_INST(R, S, TI, TO)                                                                      \
+  template hipError_t dslash<R, S, TI, TO>(const Geom &, const S *, int, const TI *, TO *,                        \
+                                           const typename same_t<TO>::type *, double, int, DslashMode, double *,   \
+                                           hipStream_t);
+DSLASH_INST(double, double2, double2, double2)
+DSLASH_INST(float, float2, float2, float2)
+DSLASH_INST(float, chalf, float2, float2)
+DSLASH_INST(float, chalf, h16, h16)
+DSLASH_INST(float, chalf, float2, h16)
+#undef DSLASH_INST
 template hipError_t compress_links<double2>(const Geom &, const double2 *, double2 *, double *, hipStream_t);
 template hipError_t compress_links<float2>(const Geom &, const double2 *, float2 *, double *, hipStream_t);
 template hipError_t compress_links<chalf>(const Geom &, const double2 *, chalf *, double *, hipStream_t);

@@ -201,6 +201,37 @@ __global__ __launch_bounds__(256) void k_gcr2_rupd(double2 *r, const double2 *__
   block_partials<1>(t, part);
 }
 
+// The same with the next preconditioner input in binary16 with a per-site
+// scale (r16, 13 slots per site): one site (12 entries) per thread, over the
+// Vpad sites of the fine level.
+__global__ __launch_bounds__(256) void k_gcr2_rupd_h(double2 *r, const double2 *__restrict__ wj, uint32_t Vpad,
+                                                     int j, int m, const double2 *gs, const int *skip, double *part,
+                                                     h16 *r16) {
+  const size_t off = (size_t)blockIdx.y * 12 * Vpad;
+  double t[1] = {0.0};
+  if (!(skip && skip[blockIdx.y])) {
+    const double2 a = gs[(size_t)blockIdx.y * gcr_scalars_per_rhs(m) + (size_t)m * m + j];
+    const double2 ma = make_double2(-a.x, -a.y);
+    h16 *o16 = r16 + (size_t)blockIdx.y * 13 * Vpad;
+    GSTRIDE(i, Vpad) {
+      const uint32_t s = (uint32_t)i;
+      double2 rv[12], w[12];
+      load_site(rv, r + off, s);
+      load_site(w, wj + off, s);
+      float2 f[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        rv[c] = cfma(ma, w[c], rv[c]);
+        t[0] += rv[c].x * rv[c].x + rv[c].y * rv[c].y;
+        f[c] = make_float2((float)rv[c].x, (float)rv[c].y);
+      }
+      store_site(r + off, s, rv);
+      store_site(o16, s, f);
+    }
+  }
+  block_partials<1>(t, part);
+}
+
 // c = T^{-1} a over the cnt steps of the cycle (one thread per right-hand side).
 __global__ void k_gcr2_backsub(double2 *gs, double *nu, const int *cnt, int m, int nrhs) {
   const int rhs = blockIdx.x * blockDim.x + threadIdx.x;
@@ -273,8 +304,16 @@ hipError_t gcr2_step(double2 *Wh, size_t vs, int j, int m, const double2 *r_in, 
 }
 
 hipError_t gcr2_residual(double2 *r, const double2 *Wh, size_t vs, int j, int m, size_t n, int nrhs,
-                         const double2 *gs, const int *skip, double *part, double *rr, float2 *r32,
+                         const double2 *gs, const int *skip, double *part, double *rr, float2 *r32, h16 *r16,
                          hipStream_t st) {
+  if (r16) {
+    const uint32_t Vpad = (uint32_t)(n / 12);
+    const int g = ggrid(Vpad);
+    hipLaunchKernelGGL(k_gcr2_rupd_h, dim3(g, nrhs), dim3(256), 0, st, r, Wh + (size_t)j * vs, Vpad, j, m, gs, skip,
+                       part, r16);
+    hipLaunchKernelGGL(k_gcr2_fin1, dim3(1, nrhs), dim3(256), 0, st, part, g, rr, skip);
+    return hipGetLastError();
+  }
   const int g = ggrid(n);
   hipLaunchKernelGGL(k_gcr2_rupd, dim3(g, nrhs), dim3(256), 0, st, r, Wh + (size_t)j * vs, n, j, m, gs, skip,
                      part, r32);

@@ -25,10 +25,15 @@ enum DslashMode { DS_PLAIN = 0, DS_RESID = 1, DS_MR = 2 };
 // out = D in; partials[slot] = (<out,in>, ||out||^2)  (DS_MR, 3 doubles per slot,
 //   dslash_partials(g, nrhs) slots per right-hand side)
 // R = arithmetic precision of vectors and accumulation, S = link storage
-// (double2, float2 or chalf).
-template <typename R, typename S>
-hipError_t dslash(const Geom &g, const S *U, int nl, const c_t<R> *in, c_t<R> *out, const c_t<R> *b, double diag,
-                  int nrhs, DslashMode mode, double *partials, hipStream_t st);
+// (double2, float2 or chalf), TI / TO = storage of the input / output (and
+// b) spinors: c_t<R>, or h16 (binary16 with a per-site scale, 13 slots per
+// site) with R = float.  Instantiated: (double, double2, double2, double2),
+// (float, float2, float2, float2), (float, chalf, float2, float2),
+// (float, chalf, h16, h16), (float, chalf, float2, h16).
+template <typename T> struct same_t { using type = T; };  // keeps b out of template argument deduction
+template <typename R, typename S, typename TI = c_t<R>, typename TO = c_t<R>>
+hipError_t dslash(const Geom &g, const S *U, int nl, const TI *in, TO *out, const typename same_t<TO>::type *b,
+                  double diag, int nrhs, DslashMode mode, double *partials, hipStream_t st);
 // out = D in (DS_PLAIN) in FP64 arithmetic on FP32-stored input spinors
 hipError_t dslash_in32(const Geom &g, const double2 *U, int nl, const float2 *in, double2 *out, double diag,
                        int nrhs, hipStream_t st);
@@ -51,6 +56,13 @@ template <typename R> hipError_t fill_const(c_t<R> *x, size_t n, R v, hipStream_
 template <typename S> hipError_t store_convert(S *y, const double2 *x, size_t n, hipStream_t st);
 // diagonal shift X += delta I of a coarse stencil's slot-0 blocks
 hipError_t shift_diag(double2 *L, uint32_t V, int n, double delta, hipStream_t st);
+// Fine-level spinor fields (Vpad sites, nrhs of them back to back) between
+// complex storage (12 entries per site, Cs / Cd = double2 or float2) and
+// binary16 with a per-site scale (h16, 13 slots per site); copy_h16 copies
+// h16 fields.
+template <typename Cs> hipError_t to_h16(h16 *y, const Cs *x, uint32_t Vpad, int nrhs, hipStream_t st);
+template <typename Cd> hipError_t from_h16(Cd *y, const h16 *x, uint32_t Vpad, int nrhs, hipStream_t st);
+hipError_t copy_h16(h16 *y, const h16 *x, uint32_t Vpad, int nrhs, hipStream_t st);
 
 }  // namespace mg
 
@@ -162,9 +174,10 @@ bool coarse_mma_ok(int n, int nrhs, int ks);
 // Fine level: P = nv null-vector fields in the fine layout [nv][12 * Vpad].
 // g = geometry of the finer level (tile = aggregate), gc = geometry of the
 // coarser level (its own site-blocked order).
-// S = storage type of P (double2, float2 or chalf); vectors in c_t<R>.
-template <typename R, typename S>
-hipError_t restrict_fine(const Geom &g, const Geom &gc, int nv, const S *P, const c_t<R> *fine, c_t<R> *coarse,
+// S = storage type of P (double2, float2 or chalf); vectors in c_t<R>; the
+// fine vectors of the restriction may also be h16 (R = float, S = chalf).
+template <typename R, typename S, typename TF = c_t<R>>
+hipError_t restrict_fine(const Geom &g, const Geom &gc, int nv, const S *P, const TF *fine, c_t<R> *coarse,
                          int nrhs, hipStream_t st);
 // fine (+)= P coarse  (accumulate != 0: add into fine)
 template <typename R, typename S>
@@ -173,8 +186,9 @@ hipError_t prolong_fine(const Geom &g, const Geom &gc, int nv, const S *P, const
 // Many right-hand sides on the FP32 matrix cores (transfer_mma.hip):
 // one workgroup per aggregate for all nrhs <= 16; requires |B| % 4 == 0.
 bool transfer_mma_ok(const Geom &g, int nv, int nrhs);
-template <typename S>
-hipError_t restrict_fine_mma(const Geom &g, const Geom &gc, int nv, const S *P, const float2 *fine, float2 *coarse,
+// TF = float2, or h16 with S = chalf
+template <typename S, typename TF>
+hipError_t restrict_fine_mma(const Geom &g, const Geom &gc, int nv, const S *P, const TF *fine, float2 *coarse,
                              int nrhs, hipStream_t st);
 template <typename S>
 hipError_t prolong_fine_mma(const Geom &g, const Geom &gc, int nv, const S *P, const float2 *coarse, float2 *fine,

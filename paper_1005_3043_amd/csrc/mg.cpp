@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "mg_internal.h"
@@ -106,6 +107,12 @@ template <typename R> int ensure_work(mg_ctx *c, int nrhs) {
     MG_TRY(w.r[l].alloc(n));
     MG_TRY(w.q[l].alloc(n));
     MG_TRY(w.rin[l].alloc(n));
+  }
+  if constexpr (sizeof(R) == 4) {
+    const size_t nh = (size_t)13 * c->lev[0].g.Vpad * nrhs;
+    MG_TRY(w.hr.alloc(nh));
+    MG_TRY(w.hq.alloc(nh));
+    MG_TRY(w.hrin.alloc(nh));
   }
   clear_graphs(c);
   const size_t n = c->lev[c->nlev - 1].vsize() * nrhs;
@@ -395,6 +402,19 @@ template <typename P> int transfer_variant(mg_ctx *c, int dir, int nrhs, hipStre
   }
 }
 
+// out = D in on the fine level with the input stored as TI and the output
+// (and b) as TO (DS_MR: MR partials into c->part; DS_RESID: out = b - D in).
+template <typename P, typename TI, typename TO>
+static int apply_fine(mg_ctx *c, const TI *in, TO *out, int nrhs, DslashMode mode, const TO *b, hipStream_t st) {
+  using R = typename P::R;
+  using S = typename P::S;
+  Level &L = c->lev[0];
+  TimerScope ts(c, c->tm[tclass<P>(false)], st, (double)L.g.V * nrhs);
+  HIPK((dslash<R, S, TI, TO>(L.g, links_of<P>(L), L.nl, in, out, b, 4.0 + c->mass, nrhs, mode, c->part, st)));
+  c->n_fine += nrhs;
+  return MG_OK;
+}
+
 // out = A_l in  (DS_MR: MR partials into c->part; DS_RESID: out = b - A_l in)
 template <typename P>
 int apply_A(mg_ctx *c, int l, const vec_t<P> *in, vec_t<P> *out, int nrhs, DslashMode mode, const vec_t<P> *b,
@@ -403,9 +423,7 @@ int apply_A(mg_ctx *c, int l, const vec_t<P> *in, vec_t<P> *out, int nrhs, Dslas
   using S = typename P::S;
   Level &L = c->lev[l];
   if (l == 0) {
-    TimerScope ts(c, c->tm[tclass<P>(false)], st, (double)L.g.V * nrhs);
-    HIPK((dslash<R, S>(L.g, links_of<P>(L), L.nl, in, out, b, 4.0 + c->mass, nrhs, mode, c->part, st)));
-    c->n_fine += nrhs;
+    MG_TRY((apply_fine<P, vec_t<P>, vec_t<P>>(c, in, out, nrhs, mode, b, st)));
   } else {
     const int var = coarse_variant<P>(c, l, nrhs, st);
     if (var < 0) return var;
@@ -429,19 +447,28 @@ int apply_A(mg_ctx *c, int l, const vec_t<P> *in, vec_t<P> *out, int nrhs, Dslas
 
 // MR smoothing of A_l x = r0 from x = 0 (accumulate: add into x): on return
 // r holds the recursively updated residual, unless keep_r = false (the
-// caller does not use it; the last step then updates x only).
-template <typename P>
-int mr(mg_ctx *c, int l, vec_t<P> *x, vec_t<P> *r, vec_t<P> *q, int steps, bool accumulate, int nrhs,
-       hipStream_t st, bool keep_r = true) {
+// caller does not use it; the last step then updates x only).  r0 is r on
+// entry, or the separate vector r_in when given (read by the first step,
+// which then writes r: no copy of the input).  TR = storage of r and q:
+// vec_t<P>, or h16 on the fine level of the FP16 class.
+template <typename P, typename TR = vec_t<P>>
+int mr(mg_ctx *c, int l, vec_t<P> *x, TR *r, TR *q, int steps, bool accumulate, int nrhs, hipStream_t st,
+       bool keep_r = true, const TR *r_in = nullptr) {
   using R = typename P::R;
   Level &L = c->lev[l];
   const size_t n = L.vsize();
   if (steps == 0 && !accumulate) HIPK(zero<R>(x, n * nrhs, st));
   for (int k = 0; k < steps; ++k) {
-    MG_TRY(apply_A<P>(c, l, r, q, nrhs, DS_MR, nullptr, st));
+    const TR *src = (k == 0 && r_in) ? r_in : r;
     const int upd_r = (keep_r || k + 1 < steps) ? 1 : 0;
-    HIPK(mr_update<R>(x, r, q, n, nrhs, c->part, np_mr(c, l, nrhs), c->p.omega, c->csc,
-                      (!accumulate && k == 0) ? 1 : 0, upd_r, st));
+    const int first = (!accumulate && k == 0) ? 1 : 0;
+    if constexpr (std::is_same<TR, h16>::value) {
+      MG_TRY((apply_fine<P, h16, h16>(c, src, q, nrhs, DS_MR, nullptr, st)));
+      HIPK(mr_update_h(x, r, src, q, L.g, nrhs, c->part, np_mr(c, l, nrhs), c->p.omega, c->csc, first, upd_r, st));
+    } else {
+      MG_TRY(apply_A<P>(c, l, src, q, nrhs, DS_MR, nullptr, st));
+      HIPK(mr_update<R>(x, r, src, q, n, nrhs, c->part, np_mr(c, l, nrhs), c->p.omega, c->csc, first, upd_r, st));
+    }
   }
   return MG_OK;
 }
@@ -471,8 +498,8 @@ int gmres_smooth(mg_ctx *c, int l, vec_t<P> *x, const vec_t<P> *b, int k, bool a
   return MG_OK;
 }
 
-template <typename P>
-int transfer_restrict(mg_ctx *c, int l, const vec_t<P> *fine, vec_t<P> *coarse, int nrhs, hipStream_t st) {
+template <typename P, typename TR>
+int transfer_restrict(mg_ctx *c, int l, const TR *fine, vec_t<P> *coarse, int nrhs, hipStream_t st) {
   using R = typename P::R;
   using S = typename P::S;
   Level &L = c->lev[l], &Lc = c->lev[l + 1];
@@ -481,13 +508,14 @@ int transfer_restrict(mg_ctx *c, int l, const vec_t<P> *fine, vec_t<P> *coarse, 
     if (tv < 0) return tv;
     if constexpr (sizeof(R) == 4) {
       if (tv == 1) {
-        HIPK(restrict_fine_mma(L.g, Lc.g, L.nv, P_of<P>(L), fine, coarse, nrhs, st));
+        HIPK((restrict_fine_mma<S, TR>(L.g, Lc.g, L.nv, P_of<P>(L), fine, coarse, nrhs, st)));
         return MG_OK;
       }
     }
-    HIPK((restrict_fine<R, S>(L.g, Lc.g, L.nv, P_of<P>(L), fine, coarse, nrhs, st)));
+    HIPK((restrict_fine<R, S, TR>(L.g, Lc.g, L.nv, P_of<P>(L), fine, coarse, nrhs, st)));
+  } else if constexpr (std::is_same<TR, vec_t<P>>::value) {
+    HIPK((restrict_coarse<R, S>(L.g, Lc.g, L.n, L.nv, P_of<P>(L), fine, coarse, nrhs, st)));
   }
-  else HIPK((restrict_coarse<R, S>(L.g, Lc.g, L.n, L.nv, P_of<P>(L), fine, coarse, nrhs, st)));
   return MG_OK;
 }
 
@@ -819,38 +847,90 @@ template <typename P> int cgnr(mg_ctx *c, int l, const vec_t<P> *b, vec_t<P> *e,
   return MG_OK;
 }
 
+// The smoother's residual and stencil-output buffers of level l, stored as
+// TR (binary16 ones exist on the fine level of the FP16 class only).
+template <typename P, typename TR> static void res_bufs(mg_ctx *c, int l, TR *&r, TR *&q) {
+  if constexpr (std::is_same<TR, h16>::value) {
+    r = c->w32.hr;
+    q = c->w32.hq;
+  } else {
+    Work<typename P::R> &w = work<typename P::R>(c);
+    r = w.r[l];
+    q = w.q[l];
+  }
+}
+
+// dst = src for residual-type vectors of level l.
+template <typename P, typename TR>
+static int copy_res(mg_ctx *c, int l, TR *dst, const TR *src, int nrhs, hipStream_t st) {
+  if constexpr (std::is_same<TR, h16>::value) HIPK(copy_h16(dst, src, c->lev[0].g.Vpad, nrhs, st));
+  else HIPK(copy<typename P::R>(dst, src, c->lev[l].vsize() * nrhs, st));
+  return MG_OK;
+}
+
+// v as a vec_t<P> vector (binary16 fine vectors are expanded into the FP32
+// work vector r of level 0, which the FP16 class does not use otherwise).
+template <typename P, typename TR>
+static const vec_t<P> *as_vec(mg_ctx *c, const TR *v, int nrhs, hipStream_t st, int &rc) {
+  rc = MG_OK;
+  if constexpr (std::is_same<TR, h16>::value) {
+    float2 *o = c->w32.r[0];
+    const hipError_t e = from_h16<float2>(o, v, c->lev[0].g.Vpad, nrhs, st);
+    if (e != hipSuccess) rc = hip_rc(e, "from_h16");
+    return o;
+  } else {
+    return v;
+  }
+}
+
+// r = b - A_l x with r and b stored as TR.
+template <typename P, typename TR>
+static int resid(mg_ctx *c, int l, const vec_t<P> *x, TR *r, const TR *b, int nrhs, hipStream_t st) {
+  if constexpr (std::is_same<TR, h16>::value) return apply_fine<P, vec_t<P>, h16>(c, x, r, nrhs, DS_RESID, b, st);
+  else return apply_A<P>(c, l, x, r, nrhs, DS_RESID, b, st);
+}
+
 // Smoothing before the coarse correction on level l (x from zero, r the
 // residual left for restriction).
-template <typename P>
-static int smooth_pre(mg_ctx *c, int l, const vec_t<P> *rin, vec_t<P> *x, int nrhs, hipStream_t st) {
+template <typename P, typename TR>
+static int smooth_pre(mg_ctx *c, int l, const TR *rin, vec_t<P> *x, int nrhs, hipStream_t st) {
   using R = typename P::R;
-  Work<R> &w = work<R>(c);
   const size_t n = c->lev[l].vsize();
-  vec_t<P> *r = w.r[l], *q = w.q[l];
-  if (c->p.smoother != MG_SMOOTH_GMRES) {
-    HIPK(copy<R>(r, rin, n * nrhs, st));
-    MG_TRY(mr<P>(c, l, x, r, q, c->p.pre, false, nrhs, st));
-  } else if (c->p.pre > 0) {
-    MG_TRY(gmres_smooth<P>(c, l, x, rin, c->p.pre, false, nrhs, st));
-    MG_TRY(apply_A<P>(c, l, x, r, nrhs, DS_RESID, rin, st));
+  TR *r, *q;
+  res_bufs<P, TR>(c, l, r, q);
+  if (c->p.smoother != MG_SMOOTH_GMRES && c->p.pre > 0) {
+    MG_TRY((mr<P, TR>(c, l, x, r, q, c->p.pre, false, nrhs, st, true, rin)));
+  } else if (c->p.smoother == MG_SMOOTH_GMRES && c->p.pre > 0) {
+    int rc;
+    const vec_t<P> *b = as_vec<P, TR>(c, rin, nrhs, st, rc);
+    MG_TRY(rc);
+    MG_TRY(gmres_smooth<P>(c, l, x, b, c->p.pre, false, nrhs, st));
+    MG_TRY((resid<P, TR>(c, l, x, r, rin, nrhs, st)));
   } else {
     HIPK(zero<R>(x, n * nrhs, st));
-    HIPK(copy<R>(r, rin, n * nrhs, st));
+    MG_TRY((copy_res<P, TR>(c, l, r, rin, nrhs, st)));
   }
   return MG_OK;
 }
 
 // After the coarse correction of level l: x += P e_c, the new residual, and
 // the post-smoothing added into x.
-template <typename P>
-static int smooth_post(mg_ctx *c, int l, const vec_t<P> *rin, vec_t<P> *x, int nrhs, hipStream_t st) {
+template <typename P, typename TR>
+static int smooth_post(mg_ctx *c, int l, const TR *rin, vec_t<P> *x, int nrhs, hipStream_t st) {
   using R = typename P::R;
   Work<R> &w = work<R>(c);
-  vec_t<P> *r = w.r[l], *q = w.q[l];
+  TR *r, *q;
+  res_bufs<P, TR>(c, l, r, q);
   MG_TRY(transfer_prolong<P>(c, l, w.x[l + 1], x, nrhs, 1, st));
-  MG_TRY(apply_A<P>(c, l, x, r, nrhs, DS_RESID, rin, st));
-  if (c->p.smoother == MG_SMOOTH_GMRES) MG_TRY(gmres_smooth<P>(c, l, x, r, c->p.post, true, nrhs, st));
-  else MG_TRY(mr<P>(c, l, x, r, q, c->p.post, true, nrhs, st, false));
+  MG_TRY((resid<P, TR>(c, l, x, r, rin, nrhs, st)));
+  if (c->p.smoother == MG_SMOOTH_GMRES) {
+    int rc;
+    const vec_t<P> *b = as_vec<P, TR>(c, r, nrhs, st, rc);
+    MG_TRY(rc);
+    MG_TRY(gmres_smooth<P>(c, l, x, b, c->p.post, true, nrhs, st));
+  } else {
+    MG_TRY((mr<P, TR>(c, l, x, r, q, c->p.post, true, nrhs, st, false)));
+  }
   return MG_OK;
 }
 
@@ -858,18 +938,23 @@ static int smooth_post(mg_ctx *c, int l, const vec_t<P> *rin, vec_t<P> *x, int n
 // smooth_pre and the restriction on every level down to the coarsest, part
 // 1 smooth_post on every level back up.
 template <typename P>
-static int vcycle_part(mg_ctx *c, int part, const vec_t<P> *rin0, vec_t<P> *x0, int nrhs, hipStream_t st) {
+static int vcycle_part(mg_ctx *c, int part, const fres_t<P> *rin0, vec_t<P> *x0, int nrhs, hipStream_t st) {
   using R = typename P::R;
+  using TR = fres_t<P>;
   Work<R> &w = work<R>(c);
   const int top = c->nlev - 2;
   if (part == 0) {
-    for (int l = 0; l <= top; ++l) {
-      MG_TRY(smooth_pre<P>(c, l, l == 0 ? rin0 : w.rin[l], l == 0 ? x0 : w.x[l], nrhs, st));
-      MG_TRY(transfer_restrict<P>(c, l, w.r[l], w.rin[l + 1], nrhs, st));
+    TR *r0, *q0;
+    res_bufs<P, TR>(c, 0, r0, q0);
+    MG_TRY((smooth_pre<P, TR>(c, 0, rin0, x0, nrhs, st)));
+    MG_TRY((transfer_restrict<P, TR>(c, 0, r0, w.rin[1], nrhs, st)));
+    for (int l = 1; l <= top; ++l) {
+      MG_TRY((smooth_pre<P, vec_t<P>>(c, l, w.rin[l], w.x[l], nrhs, st)));
+      MG_TRY((transfer_restrict<P, vec_t<P>>(c, l, w.r[l], w.rin[l + 1], nrhs, st)));
     }
   } else {
-    for (int l = top; l >= 0; --l)
-      MG_TRY(smooth_post<P>(c, l, l == 0 ? rin0 : w.rin[l], l == 0 ? x0 : w.x[l], nrhs, st));
+    for (int l = top; l >= 1; --l) MG_TRY((smooth_post<P, vec_t<P>>(c, l, w.rin[l], w.x[l], nrhs, st)));
+    MG_TRY((smooth_post<P, TR>(c, 0, rin0, x0, nrhs, st)));
   }
   return MG_OK;
 }
@@ -878,7 +963,8 @@ static int vcycle_part(mg_ctx *c, int part, const vec_t<P> *rin0, vec_t<P> *x0, 
 // is seen the part runs eagerly, the second time it is captured (and the
 // graph launched), later it is replayed.
 template <typename P>
-static int vcycle_part_graphed(mg_ctx *c, int part, const vec_t<P> *rin0, vec_t<P> *x0, int nrhs, hipStream_t st) {
+static int vcycle_part_graphed(mg_ctx *c, int part, const fres_t<P> *rin0, vec_t<P> *x0, int nrhs,
+                               hipStream_t st) {
   VGraph *g = nullptr;
   for (VGraph *v : c->vgraphs)
     if (v->prec == P::id && v->nrhs == nrhs && v->part == part && v->rin == rin0 && v->x == x0) {
@@ -931,31 +1017,55 @@ static int vcycle_part_graphed(mg_ctx *c, int part, const vec_t<P> *rin0, vec_t<
   return MG_OK;
 }
 
-// One V-cycle K_l(rin) -> x (levels l..coarsest).
-template <typename P> int vcycle(mg_ctx *c, int l, const vec_t<P> *rin, vec_t<P> *x, int nrhs, hipStream_t st) {
+// One V-cycle K_l(rin) -> x (levels l..coarsest), rin stored as TR (fres_t
+// on level 0, vec_t below).
+template <typename P, typename TR>
+static int vcycle_t(mg_ctx *c, int l, const TR *rin, vec_t<P> *x, int nrhs, hipStream_t st) {
   using R = typename P::R;
-  if (l == c->nlev - 1) return cgnr<P>(c, l, rin, x, nrhs, st);
-  if (l == 0 && c->vgraph_on && c->use_graph && !c->timing && c->p.cycles <= 1) {
-    Work<R> &w = work<R>(c);
-    const int lc = c->nlev - 1;
-    MG_TRY(vcycle_part_graphed<P>(c, 0, rin, x, nrhs, st));
-    MG_TRY(cgnr<P>(c, lc, w.rin[lc], w.x[lc], nrhs, st));
-    return vcycle_part_graphed<P>(c, 1, rin, x, nrhs, st);
+  if constexpr (std::is_same<TR, vec_t<P>>::value) {
+    if (l == c->nlev - 1) return cgnr<P>(c, l, rin, x, nrhs, st);
   }
   Work<R> &w = work<R>(c);
-  MG_TRY(smooth_pre<P>(c, l, rin, x, nrhs, st));
+  if constexpr (std::is_same<TR, fres_t<P>>::value) {
+    if (l == 0 && c->vgraph_on && c->use_graph && !c->timing && c->p.cycles <= 1) {
+      const int lc = c->nlev - 1;
+      MG_TRY(vcycle_part_graphed<P>(c, 0, rin, x, nrhs, st));
+      MG_TRY(cgnr<P>(c, lc, w.rin[lc], w.x[lc], nrhs, st));
+      return vcycle_part_graphed<P>(c, 1, rin, x, nrhs, st);
+    }
+  }
+  MG_TRY((smooth_pre<P, TR>(c, l, rin, x, nrhs, st)));
   const int m = l + 1;
-  MG_TRY(transfer_restrict<P>(c, l, w.r[l], w.rin[m], nrhs, st));
-  MG_TRY(vcycle<P>(c, m, w.rin[m], w.x[m], nrhs, st));
+  TR *r, *q;
+  res_bufs<P, TR>(c, l, r, q);
+  MG_TRY((transfer_restrict<P, TR>(c, l, r, w.rin[m], nrhs, st)));
+  MG_TRY((vcycle_t<P, vec_t<P>>(c, m, w.rin[m], w.x[m], nrhs, st)));
   if (m < c->nlev - 1) {
     // W-cycle: further cycles of level m on the residual the previous left
     for (int cyc = 1; cyc < c->p.cycles; ++cyc) {
       MG_TRY(apply_A<P>(c, m, w.x[m], w.w2r[m], nrhs, DS_RESID, w.rin[m], st));
-      MG_TRY(vcycle<P>(c, m, w.w2r[m], w.w2x[m], nrhs, st));
+      MG_TRY((vcycle_t<P, vec_t<P>>(c, m, w.w2r[m], w.w2x[m], nrhs, st)));
       HIPK(add_inplace<R>(w.x[m], w.w2x[m], c->lev[m].vsize(), nrhs, st));
     }
   }
-  return smooth_post<P>(c, l, rin, x, nrhs, st);
+  return smooth_post<P, TR>(c, l, rin, x, nrhs, st);
+}
+
+// One V-cycle from level 0 with the input in the class's fine storage.
+template <typename P> static int vcycle_fine(mg_ctx *c, const fres_t<P> *rin, vec_t<P> *x, int nrhs, hipStream_t st) {
+  return vcycle_t<P, fres_t<P>>(c, 0, rin, x, nrhs, st);
+}
+
+// One V-cycle K_l(rin) -> x (levels l..coarsest) with rin in the arithmetic
+// type (on level 0 of the FP16 class it is first stored in binary16).
+template <typename P> int vcycle(mg_ctx *c, int l, const vec_t<P> *rin, vec_t<P> *x, int nrhs, hipStream_t st) {
+  if constexpr (std::is_same<fres_t<P>, h16>::value) {
+    if (l == 0) {
+      HIPK(to_h16<float2>(c->w32.hrin, rin, c->lev[0].g.Vpad, nrhs, st));
+      return vcycle_fine<P>(c, c->w32.hrin, x, nrhs, st);
+    }
+  }
+  return vcycle_t<P, vec_t<P>>(c, l, rin, x, nrhs, st);
 }
 
 // z = K(r) in the precision prec (FP64 in and out).
@@ -965,9 +1075,13 @@ int precondition_at(mg_ctx *c, mg_prec_t prec, const double2 *r, double2 *z, int
   Work<float> &w = c->w32;
   const size_t n = c->lev[0].vsize() * nrhs;
   float2 *rin = w.rin[0], *x = w.x[0];
-  HIPK((convert<float, double>(rin, r, n, st)));
-  if (prec == MG_F16) MG_TRY(vcycle<PF16>(c, 0, rin, x, nrhs, st));
-  else MG_TRY(vcycle<PF32>(c, 0, rin, x, nrhs, st));
+  if (prec == MG_F16) {
+    HIPK(to_h16<double2>(w.hrin, r, c->lev[0].g.Vpad, nrhs, st));
+    MG_TRY(vcycle_fine<PF16>(c, w.hrin, x, nrhs, st));
+  } else {
+    HIPK((convert<float, double>(rin, r, n, st)));
+    MG_TRY(vcycle<PF32>(c, 0, rin, x, nrhs, st));
+  }
   HIPK((convert<double, float>(z, x, n, st)));
   return MG_OK;
 }
@@ -997,7 +1111,10 @@ static int fgcr_t(mg_ctx *c, const double2 *b, double2 *x, int nrhs, double tol,
   const int m = c->p.gcr_restart;
   constexpr bool f32z = sizeof(TZ) == 8;
   double2 *r = c->gr, *W = c->gW;
-  float2 *r32 = f32z ? c->gr32.p : nullptr;
+  // preconditioner input: FP32, or binary16 with per-site scales (FP16 class)
+  const bool h16in = f32z && c->prec == MG_F16;
+  float2 *r32 = f32z && !h16in ? c->gr32.p : nullptr;
+  h16 *r16 = h16in ? c->gr16.p : nullptr;
   double *rr = c->dsc;
   int *skip = c->skip;
   // the cycles of the outer solver may run from captured V-cycle parts
@@ -1030,7 +1147,8 @@ static int fgcr_t(mg_ctx *c, const double2 *b, double2 *x, int nrhs, double tol,
   for (int i = 0; i < nrhs; ++i) all_conv = all_conv && hskip[i];
   while (!all_conv) {
     HIPK(hipMemsetAsync(c->gcnt, 0, sizeof(int) * MG_MAX_RHS, st));
-    if constexpr (f32z) HIPK((convert<float, double>(r32, r, nn, st)));
+    if (r32) HIPK((convert<float, double>(r32, r, nn, st)));
+    if (r16) HIPK(to_h16<double2>(r16, r, L0.g.Vpad, nrhs, st));
     int used = 0;
     for (int j = 0; j < m; ++j) {
       TZ *Zj = Z + (size_t)j * nn;
@@ -1038,7 +1156,7 @@ static int fgcr_t(mg_ctx *c, const double2 *b, double2 *x, int nrhs, double tol,
       // z_j = K(r_j), written in the preconditioner's precision
       c->n_vcyc += nrhs;
       if constexpr (f32z) {
-        if (c->prec == MG_F16) MG_TRY(vcycle<PF16>(c, 0, r32, Zj, nrhs, st));
+        if (r16) MG_TRY(vcycle_fine<PF16>(c, r16, Zj, nrhs, st));
         else MG_TRY(vcycle<PF32>(c, 0, r32, Zj, nrhs, st));
       } else {
         MG_TRY(vcycle<PF64>(c, 0, r, Zj, nrhs, st));
@@ -1053,7 +1171,7 @@ static int fgcr_t(mg_ctx *c, const double2 *b, double2 *x, int nrhs, double tol,
       }
       c->n_fine += nrhs;
       HIPK(gcr2_step(W, nn, j, m, r, n, nrhs, c->gsc, c->gnu, c->gcnt, skip, c->part, st));
-      HIPK(gcr2_residual(r, W, nn, j, m, n, nrhs, c->gsc, skip, c->part, rr, r32, st));
+      HIPK(gcr2_residual(r, W, nn, j, m, n, nrhs, c->gsc, skip, c->part, rr, r32, r16, st));
       used = j + 1;
       HIPK(hipMemcpyAsync(c->h_rr, rr, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
       HIPK(hipStreamSynchronize(st));
@@ -1116,7 +1234,8 @@ int ensure_fgcr(mg_ctx *c, int nrhs) {
     MG_TRY(c->gZ.alloc(n * m));
   } else {
     MG_TRY(c->gZf.alloc(n * m));
-    MG_TRY(c->gr32.alloc(n));
+    if (c->prec == MG_F16) MG_TRY(c->gr16.alloc((size_t)13 * c->lev[0].g.Vpad * nrhs));
+    else MG_TRY(c->gr32.alloc(n));
   }
   MG_TRY(c->gsc.alloc(MG_MAX_RHS * gcr_scalars_per_rhs(m)));
   MG_TRY(c->gnu.alloc((size_t)MG_MAX_RHS * m));
@@ -1143,7 +1262,7 @@ int relax(mg_ctx *c, int l, double2 *V, int nv, hipStream_t st) {
   MG_TRY(q.alloc(n * nv));
   for (int round = 0; round < c->p.setup_rounds; ++round) {
     MG_TRY(apply_A<PF64>(c, l, V, r, nv, DS_PLAIN, nullptr, st));
-    MG_TRY(mr<PF64>(c, l, x, r, q, c->p.setup_mr_steps, false, nv, st, false));
+    MG_TRY(mr<PF64>(c, l, x.p, r.p, q.p, c->p.setup_mr_steps, false, nv, st, false));
     HIPK(sub_inplace<double>(V, x, n, nv, st));
     HIPK(norm2<double>(V, n, nv, c->part, c->dsc, st));
     HIPK(scale_rsqrt<double>(V, n, nv, c->dsc, st));
@@ -1164,6 +1283,9 @@ template <typename R> void release_work(Work<R> &w) {
     w.w2r[l].release();
     w.w2x[l].release();
   }
+  w.hr.release();
+  w.hq.release();
+  w.hrin.release();
   w.ce.release();
   w.cr.release();
   w.cz.release();
@@ -1191,9 +1313,14 @@ int cycle_from(mg_ctx *c, int l, mg_prec_t prec, const double2 *r, double2 *z, i
   Work<float> &w = c->w32;
   const size_t n = c->lev[l].vsize() * nrhs;
   float2 *rin = w.rin[l], *x = w.x[l];
-  HIPK((convert<float, double>(rin, r, n, st)));
-  if (prec == MG_F16) MG_TRY(vcycle<PF16>(c, l, rin, x, nrhs, st));
-  else MG_TRY(vcycle<PF32>(c, l, rin, x, nrhs, st));
+  if (prec == MG_F16 && l == 0) {
+    HIPK(to_h16<double2>(w.hrin, r, c->lev[0].g.Vpad, nrhs, st));
+    MG_TRY(vcycle_fine<PF16>(c, w.hrin, x, nrhs, st));
+  } else {
+    HIPK((convert<float, double>(rin, r, n, st)));
+    if (prec == MG_F16) MG_TRY(vcycle<PF16>(c, l, rin, x, nrhs, st));
+    else MG_TRY(vcycle<PF32>(c, l, rin, x, nrhs, st));
+  }
   HIPK((convert<double, float>(z, x, n, st)));
   return MG_OK;
 }

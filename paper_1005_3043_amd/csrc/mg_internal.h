@@ -16,8 +16,9 @@ template <typename R> int ensure_work(mg_ctx *c, int nrhs);
 template <typename P>
 int apply_A(mg_ctx *c, int l, const vec_t<P> *in, vec_t<P> *out, int nrhs, DslashMode mode, const vec_t<P> *b,
             hipStream_t st);
-template <typename P>
-int transfer_restrict(mg_ctx *c, int l, const vec_t<P> *fine, vec_t<P> *coarse, int nrhs, hipStream_t st);
+// fine stored as TR: vec_t<P>, or h16 on level 0 of the FP16 class
+template <typename P, typename TR = vec_t<P>>
+int transfer_restrict(mg_ctx *c, int l, const TR *fine, vec_t<P> *coarse, int nrhs, hipStream_t st);
 template <typename P>
 int transfer_prolong(mg_ctx *c, int l, const vec_t<P> *coarse, vec_t<P> *fine, int nrhs, int accumulate,
                      hipStream_t st);

@@ -15,11 +15,18 @@ constexpr int GCR_CHUNK = 8;      // FGCR directions orthogonalised against per 
 __host__ __device__ constexpr size_t gcr_scalars_per_rhs(int m) { return (size_t)m * m + 3 * (size_t)m + 1; }
 
 // ---- solver_kernels.hip
-// x = (first ? 0 : x) + alpha r and, when upd_r, r -= alpha q, with alpha =
-// omega <q,r>/<q,q> from the stencil's np partials per right-hand side
+// x = (first ? 0 : x) + alpha r_in and, when upd_r, r_out = r_in - alpha q
+// (r_out may be r_in), with alpha = omega <q,r>/<q,q> from the stencil's np
+// partials per right-hand side
 template <typename R>
-hipError_t mr_update(c_t<R> *x, c_t<R> *r, const c_t<R> *q, size_t n, int nrhs, const double *part, int np,
-                     double omega, double2 *alpha, int first, int upd_r, hipStream_t st);
+hipError_t mr_update(c_t<R> *x, c_t<R> *r_out, const c_t<R> *r_in, const c_t<R> *q, size_t n, int nrhs,
+                     const double *part, int np, double omega, double2 *alpha, int first, int upd_r,
+                     hipStream_t st);
+// the same on the fine level g with r and q in binary16 with a per-site
+// scale (13 slots per site) and x in FP32
+hipError_t mr_update_h(float2 *x, h16 *r_out, const h16 *r_in, const h16 *q, const Geom &g, int nrhs,
+                       const double *part, int np, double omega, double2 *alpha, int first, int upd_r,
+                       hipStream_t st);
 template <typename R> hipError_t norm2(const c_t<R> *a, size_t n, int nrhs, double *part, double *out, hipStream_t st);
 // launches the per-block partials of ||a||^2 and returns their count per RHS
 template <typename R> int norm2_partials(const c_t<R> *a, size_t n, int nrhs, double *part, hipStream_t st);
@@ -41,14 +48,15 @@ hipError_t gcr_update(double2 *x, const double2 *z, double2 *r, const double2 *w
 // each restart cycle.  Wh holds w_0 .. w_{m-1} (stride vs); w_j = D z_j on
 // entry to gcr2_step, which orthogonalises it against w^_0 .. w^_{j-1} in
 // place and derives a_j from the residual r_in; gcr2_residual moves r along
-// w^_j (rr[rhs] = ||r||^2; r32, if not null, receives r in FP32);
+// w^_j (rr[rhs] = ||r||^2; r32 or r16, if not null, receives r in FP32 or in
+// binary16 with per-site scales, n = 12 Vpad);
 // gcr2_solution adds the cycle's update Z T^{-1} a to x, over the cnt[rhs]
 // steps each right-hand side took (kmax = steps of the cycle).  gs: double2
 // [MG_MAX_RHS][gcr_scalars_per_rhs(m)], nu: double [MG_MAX_RHS][m].
 hipError_t gcr2_step(double2 *Wh, size_t vs, int j, int m, const double2 *r_in, size_t n, int nrhs,
                      double2 *gs, double *nu, int *cnt, const int *skip, double *part, hipStream_t st);
 hipError_t gcr2_residual(double2 *r, const double2 *Wh, size_t vs, int j, int m, size_t n, int nrhs,
-                         const double2 *gs, const int *skip, double *part, double *rr, float2 *r32,
+                         const double2 *gs, const int *skip, double *part, double *rr, float2 *r32, h16 *r16,
                          hipStream_t st);
 template <typename TZ>
 hipError_t gcr2_solution(double2 *x, const TZ *Z, size_t vs, int kmax, int m, size_t n, int nrhs, double2 *gs,
@@ -139,6 +147,13 @@ struct PF64 { using R = double; using S = double2; static constexpr int id = 0; 
 struct PF32 { using R = float; using S = float2; static constexpr int id = 1; };
 struct PF16 { using R = float; using S = chalf; static constexpr int id = 2; };
 template <typename P> using vec_t = c_t<typename P::R>;
+// Storage of the fine level's residual-type vectors inside a V-cycle (the
+// cycle's input, the smoother's residual and the stencil's output q): the
+// arithmetic type, except binary16 with a per-site scale in the FP16 class.
+// The fine-level correction x is always vec_t.
+template <typename P> struct FineRes { using T = vec_t<P>; };
+template <> struct FineRes<PF16> { using T = h16; };
+template <typename P> using fres_t = typename FineRes<P>::T;
 
 struct Level {
   Geom g;            // this level's lattice; tile = aggregate shape to the next level
@@ -166,6 +181,9 @@ template <typename R> struct Work {
   DevBuf<c_t<R>> ce, cr, cz, cp, cw, cp2, cr2;  // cp2, cr2: second p, r of the fused CGNR
   // GMRES relaxation basis per level; W-cycle residual and correction per level
   DevBuf<c_t<R>> gv[MG_MAX_LEVELS], w2r[MG_MAX_LEVELS], w2x[MG_MAX_LEVELS];
+  // fine-level r, q and cycle input of the FP16 class (binary16, 13 slots
+  // per site; allocated in the FP32 work set only)
+  DevBuf<h16> hr, hq, hrin;
   int nrhs = 0;
 };
 
@@ -302,6 +320,7 @@ struct mg_ctx {
   // outer solver (FP64, fine level)
   mg::DevBuf<double2> gx, gr, gb, gZ, gW, gtmp;
   mg::DevBuf<float2> gZf, gr32;  // FP32 preconditioned vectors and preconditioner input (FP32/FP16 precond)
+  mg::DevBuf<mg::h16> gr16;      // preconditioner input of the FP16 class
   mg::DevBuf<double2> gsc;       // deferred-update FGCR scalars
   mg::DevBuf<double> gnu;
   mg::DevBuf<int> gcnt;

@@ -91,21 +91,55 @@ __global__ __launch_bounds__(256) void k_dot(const c_t<R> *a, const c_t<R> *b, s
 // --------------------------------------------------------------- updates
 // MR: x = (first ? 0 : x) + alpha r;  r -= alpha q
 template <typename R>
-__global__ __launch_bounds__(256) void k_mr_update(c_t<R> *x, c_t<R> *r, const c_t<R> *q, size_t n,
-                                                   const double2 *alpha, int first, int upd_r) {
+__global__ __launch_bounds__(256) void k_mr_update(c_t<R> *x, c_t<R> *r_out, const c_t<R> *r_in, const c_t<R> *q,
+                                                   size_t n, const double2 *alpha, int first, int upd_r) {
   using C = c_t<R>;
   const size_t off = (size_t)blockIdx.y * n;
-  x += off; r += off; q += off;
+  x += off; r_out += off; r_in += off; q += off;
   const double2 ad = alpha[blockIdx.y];
   const C a = mk<C>((R)ad.x, (R)ad.y), ma = mk<C>((R)-ad.x, (R)-ad.y);
   if (upd_r) {
     GSTRIDE(i, n) {
-      const C rv = r[i];
+      const C rv = r_in[i];
       x[i] = first ? cmul(a, rv) : cfma(a, rv, x[i]);
-      r[i] = cfma(ma, q[i], rv);
+      r_out[i] = cfma(ma, q[i], rv);
     }
   } else {
-    GSTRIDE(i, n) x[i] = first ? cmul(a, r[i]) : cfma(a, r[i], x[i]);
+    GSTRIDE(i, n) x[i] = first ? cmul(a, r_in[i]) : cfma(a, r_in[i], x[i]);
+  }
+}
+
+// The same on the fine level with the residual and q stored in binary16 with
+// a per-site scale (x in FP32): one site per thread, so that the new
+// residual's scale is formed from all 12 of its components.
+__global__ __launch_bounds__(256) void k_mr_update_h(float2 *x, h16 *r_out, const h16 *r_in, const h16 *q,
+                                                     uint32_t V, uint32_t Vpad, const double2 *alpha, int first,
+                                                     int upd_r) {
+  x += (size_t)blockIdx.y * 12 * Vpad;
+  const size_t off = (size_t)blockIdx.y * 13 * Vpad;
+  r_out += off; r_in += off; q += off;
+  const double2 ad = alpha[blockIdx.y];
+  const float2 a = make_float2((float)ad.x, (float)ad.y), ma = make_float2((float)-ad.x, (float)-ad.y);
+  GSTRIDE(i, V) {
+    const uint32_t s = (uint32_t)i;
+    float2 rv[12], xv[12];
+    load_site(rv, r_in, s);
+    if (first) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) xv[c] = cmul(a, rv[c]);
+    } else {
+      load_site(xv, x, s);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) xv[c] = cfma(a, rv[c], xv[c]);
+    }
+    store_site(x, s, xv);
+    if (upd_r) {
+      float2 qv[12];
+      load_site(qv, q, s);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) rv[c] = cfma(ma, qv[c], rv[c]);
+      store_site(r_out, s, rv);
+    }
   }
 }
 
@@ -382,10 +416,21 @@ template <typename R> hipError_t resid_from(c_t<R> *out, const c_t<R> *b, size_t
 }
 
 template <typename R>
-hipError_t mr_update(c_t<R> *x, c_t<R> *r, const c_t<R> *q, size_t n, int nrhs, const double *part, int np,
-                     double omega, double2 *alpha, int first, int upd_r, hipStream_t st) {
+hipError_t mr_update(c_t<R> *x, c_t<R> *r_out, const c_t<R> *r_in, const c_t<R> *q, size_t n, int nrhs,
+                     const double *part, int np, double omega, double2 *alpha, int first, int upd_r,
+                     hipStream_t st) {
   hipLaunchKernelGGL(k_fin_mr, dim3(1, nrhs), dim3(256), 0, st, part, np, omega, alpha);
-  hipLaunchKernelGGL(k_mr_update<R>, dim3(sgrid(n), nrhs), dim3(256), 0, st, x, r, q, n, alpha, first, upd_r);
+  hipLaunchKernelGGL(k_mr_update<R>, dim3(sgrid(n), nrhs), dim3(256), 0, st, x, r_out, r_in, q, n, alpha, first,
+                     upd_r);
+  return hipGetLastError();
+}
+
+hipError_t mr_update_h(float2 *x, h16 *r_out, const h16 *r_in, const h16 *q, const Geom &g, int nrhs,
+                       const double *part, int np, double omega, double2 *alpha, int first, int upd_r,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_fin_mr, dim3(1, nrhs), dim3(256), 0, st, part, np, omega, alpha);
+  hipLaunchKernelGGL(k_mr_update_h, dim3(sgrid(g.V), nrhs), dim3(256), 0, st, x, r_out, r_in, q, g.V, g.Vpad, alpha,
+                     first, upd_r);
   return hipGetLastError();
 }
 
@@ -448,8 +493,8 @@ hipError_t gcr_update(double2 *x, const double2 *z, double2 *r, const double2 *w
 }
 
 #define INST(R)                                                                                                     \
-  template hipError_t mr_update<R>(c_t<R> *, c_t<R> *, const c_t<R> *, size_t, int, const double *, int, double,    \
-                                   double2 *, int, int, hipStream_t);                                               \
+  template hipError_t mr_update<R>(c_t<R> *, c_t<R> *, const c_t<R> *, const c_t<R> *, size_t, int, const double *, \
+                                   int, double, double2 *, int, int, hipStream_t);                                  \
   template hipError_t norm2<R>(const c_t<R> *, size_t, int, double *, double *, hipStream_t);                       \
   template int norm2_partials<R>(const c_t<R> *, size_t, int, double *, hipStream_t);                               \
   template hipError_t dot<R>(const c_t<R> *, const c_t<R> *, size_t, int, double *, double2 *, hipStream_t);        \

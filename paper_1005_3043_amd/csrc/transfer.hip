@@ -22,14 +22,16 @@ __device__ __forceinline__ uint32_t coarse_index(const Geom &g, const Geom &gc, 
 }
 
 // ------------------------------------------------------------------ fine
-template <typename R, typename S>
+// The fine vectors are stored as TF: c_t<R>, or binary16 with a per-site
+// scale (h16, R = float).
+template <typename R, typename S, typename TF>
 __global__ __launch_bounds__(256) void k_restrict_fine(Geom g, Geom gc, int nv, const S *__restrict__ P,
-                                                       const c_t<R> *__restrict__ fine, c_t<R> *__restrict__ coarse) {
+                                                       const TF *__restrict__ fine, c_t<R> *__restrict__ coarse) {
   using C = c_t<R>;
   __shared__ double2 part[4][2 * COARSE_NMAX];
   const size_t V = g.Vpad;
   const uint32_t B = blockIdx.x;
-  fine += (size_t)blockIdx.y * 12 * V;
+  fine += (size_t)blockIdx.y * site_slots<TF>() * V;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (int k = lane; k < 2 * nv; k += 64) part[w][k] = make_double2(0.0, 0.0);
   __syncthreads();
@@ -38,8 +40,11 @@ __global__ __launch_bounds__(256) void k_restrict_fine(Geom g, Geom gc, int nv, 
     const bool act = t < g.vb;
     const uint32_t s = B * g.vb + (act ? t : 0);
     C r[12];
+    load_site(r, fine, s);
+    if (!act) {
 #pragma unroll
-    for (int c = 0; c < 12; ++c) r[c] = act ? fine[fidx(s, c, 12)] : mk<C>(0, 0);
+      for (int c = 0; c < 12; ++c) r[c] = mk<C>(0, 0);
+    }
     for (int kk = 0; kk < nv; ++kk) {
       const S *Pk = P + (size_t)kk * 12 * V;
       C d0 = mk<C>(0, 0), d1 = mk<C>(0, 0);
@@ -109,9 +114,9 @@ __global__ __launch_bounds__(256) void k_prolong_fine(Geom g, Geom gc, int nv, c
 // entry loaded from memory serves TR_RG vectors instead of one.
 constexpr int TR_RG = 4;
 
-template <typename R, typename S>
+template <typename R, typename S, typename TF>
 __global__ __launch_bounds__(256) void k_restrict_fine_mrhs(Geom g, Geom gc, int nv, int nrhs,
-                                                            const S *__restrict__ P, const c_t<R> *__restrict__ fine,
+                                                            const S *__restrict__ P, const TF *__restrict__ fine,
                                                             c_t<R> *__restrict__ coarse) {
   using C = c_t<R>;
   __shared__ double2 part[4][TR_RG][2 * COARSE_NMAX];
@@ -131,9 +136,11 @@ __global__ __launch_bounds__(256) void k_restrict_fine_mrhs(Geom g, Geom gc, int
 #pragma unroll
     for (int q = 0; q < TR_RG; ++q) {
       const bool on = act && r0 + q < nrhs;
-      const C *fr = fine + (size_t)(on ? r0 + q : 0) * 12 * V;
+      load_site(f[q], fine + (size_t)(on ? r0 + q : 0) * site_slots<TF>() * V, s);
+      if (!on) {
 #pragma unroll
-      for (int c = 0; c < 12; ++c) f[q][c] = on ? fr[fidx(s, c, 12)] : mk<C>(0, 0);
+        for (int c = 0; c < 12; ++c) f[q][c] = mk<C>(0, 0);
+      }
     }
     for (int kk = 0; kk < nv; ++kk) {
       const S *Pk = P + (size_t)kk * 12 * V;
@@ -219,15 +226,15 @@ __global__ __launch_bounds__(256) void k_prolong_fine_mrhs(Geom g, Geom gc, int 
   }
 }
 
-template <typename R, typename S>
-hipError_t restrict_fine(const Geom &g, const Geom &gc, int nv, const S *P, const c_t<R> *fine, c_t<R> *coarse,
+template <typename R, typename S, typename TF>
+hipError_t restrict_fine(const Geom &g, const Geom &gc, int nv, const S *P, const TF *fine, c_t<R> *coarse,
                          int nrhs, hipStream_t st) {
   const int th = g.vb >= 256 ? 256 : (int)((g.vb + 63) / 64 * 64);
   if (nrhs > 1)
-    hipLaunchKernelGGL((k_restrict_fine_mrhs<R, S>), dim3(g.Vc, (nrhs + TR_RG - 1) / TR_RG), dim3(th), 0, st, g, gc,
-                       nv, nrhs, P, fine, coarse);
+    hipLaunchKernelGGL((k_restrict_fine_mrhs<R, S, TF>), dim3(g.Vc, (nrhs + TR_RG - 1) / TR_RG), dim3(th), 0, st, g,
+                       gc, nv, nrhs, P, fine, coarse);
   else
-    hipLaunchKernelGGL((k_restrict_fine<R, S>), dim3(g.Vc, nrhs), dim3(th), 0, st, g, gc, nv, P, fine, coarse);
+    hipLaunchKernelGGL((k_restrict_fine<R, S, TF>), dim3(g.Vc, nrhs), dim3(th), 0, st, g, gc, nv, P, fine, coarse);
   return hipGetLastError();
 }
 
@@ -336,8 +343,8 @@ hipError_t prolong_coarse(const Geom &g, const Geom &gc, int n, int nv, const S 
 }
 
 #define INST(R, S)                                                                                                \
-  template hipError_t restrict_fine<R, S>(const Geom &, const Geom &, int, const S *, const c_t<R> *, c_t<R> *, int,  \
-                                          hipStream_t);                                                             \
+  template hipError_t restrict_fine<R, S, c_t<R>>(const Geom &, const Geom &, int, const S *, const c_t<R> *,       \
+                                                  c_t<R> *, int, hipStream_t);                                      \
   template hipError_t prolong_fine<R, S>(const Geom &, const Geom &, int, const S *, const c_t<R> *, c_t<R> *, int,   \
                                          int, hipStream_t);                                                         \
   template hipError_t restrict_coarse<R, S>(const Geom &, const Geom &, int, int, const S *, const c_t<R> *,          \
@@ -348,5 +355,7 @@ INST(double, double2)
 INST(float, float2)
 INST(float, chalf)
 #undef INST
+template hipError_t restrict_fine<float, chalf, h16>(const Geom &, const Geom &, int, const chalf *, const h16 *,
+                                                     float2 *, int, hipStream_t);
 
 }  // namespace mg

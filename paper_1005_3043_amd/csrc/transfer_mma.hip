@@ -44,6 +44,20 @@ __device__ __forceinline__ void load4(const float2 *p, float2 (&o)[4]) {
   o[3] = make_float2(b.z, b.w);
 }
 
+// Component comp of the four consecutive sites s .. s + 3 (s % 4 == 0) of a
+// fine vector stored as FP32 complex or as binary16 with per-site scales.
+__device__ __forceinline__ void load4_site(const float2 *f, uint32_t s, int comp, float2 (&o)[4]) {
+  load4(f + fidx(s, comp, 12), o);
+}
+__device__ __forceinline__ void load4_site(const h16 *f, uint32_t s, int comp, float2 (&o)[4]) {
+  const chalf4 v = *reinterpret_cast<const chalf4 *>(f + fidx(s, comp, 13));
+  const float4 m = *reinterpret_cast<const float4 *>(f + fidx(s, 12, 13));
+  o[0] = make_float2((float)v.v[0].x * m.x, (float)v.v[0].y * m.x);
+  o[1] = make_float2((float)v.v[1].x * m.y, (float)v.v[1].y * m.y);
+  o[2] = make_float2((float)v.v[2].x * m.z, (float)v.v[2].y * m.z);
+  o[3] = make_float2((float)v.v[3].x * m.w, (float)v.v[3].y * m.w);
+}
+
 // Restriction.  Wavefront w = (ks, h): both row tiles (Nv <= 32) of the
 // chirality-h output over the k-blocks ks, ks + KS, ... of 16 indices, so
 // each fine-vector entry is loaded once per wavefront; the KS partial tiles
@@ -52,10 +66,10 @@ __device__ __forceinline__ void load4(const float2 *p, float2 (&o)[4]) {
 // its column of the fine vectors in one access each, and the four MFMAs
 // u = 0..3 of the block take index 4 kk + u in k-slot kk (the sum over K
 // does not depend on the order of its terms).
-template <typename S>
+template <typename S, typename TF>
 __global__ __launch_bounds__(64 * TM_WAVES) void k_restrict_fine_mma(Geom g, Geom gc, int nv, int nrhs,
                                                                      const S *__restrict__ P,
-                                                                     const float2 *__restrict__ fine,
+                                                                     const TF *__restrict__ fine,
                                                                      float2 *__restrict__ coarse) {
   constexpr int KS = TM_WAVES / 2;
   __shared__ float red[TM_WAVES - 2][64][16];
@@ -70,7 +84,7 @@ __global__ __launch_bounds__(64 * TM_WAVES) void k_restrict_fine_mma(Geom g, Geo
   const bool a0_ok = ar0 < nv, a1_ok = MT > 1 && ar1 < nv, col_ok = col < nrhs;
   const S *Pa0 = P + (size_t)(a0_ok ? ar0 : 0) * 12 * V;
   const S *Pa1 = P + (size_t)(a1_ok ? ar1 : 0) * 12 * V;
-  const float2 *Fb = fine + (size_t)(col_ok ? col : 0) * 12 * V;
+  const TF *Fb = fine + (size_t)(col_ok ? col : 0) * site_slots<TF>() * V;
   const uint32_t s0 = B * (uint32_t)vb;
   const int nb = ks < KB ? (KB - ks + KS - 1) / KS : 0;  // k-blocks of this wavefront
   floatx4 cre0 = {0.f, 0.f, 0.f, 0.f}, cim0 = {0.f, 0.f, 0.f, 0.f};
@@ -87,7 +101,7 @@ __global__ __launch_bounds__(64 * TM_WAVES) void k_restrict_fine_mma(Geom g, Geo
       const size_t o = fidx(s0 + (uint32_t)t, 6 * h + cp, 12);
       load4(Pa0 + o, av0[u]);
       if (MT > 1) load4(Pa1 + o, av1[u]);
-      load4(Fb + o, bv[u]);
+      load4_site(Fb, s0 + (uint32_t)t, 6 * h + cp, bv[u]);
     }
 #pragma unroll
     for (int u = 0; u < TM_U; ++u) {
@@ -216,11 +230,11 @@ bool transfer_mma_ok(const Geom &g, int nv, int nrhs) {
   return nrhs >= 1 && nrhs <= TM_NR && nv >= 1 && 2 * nv <= COARSE_NMAX && g.vb % 4 == 0 && nv <= 32;
 }
 
-template <typename S>
-hipError_t restrict_fine_mma(const Geom &g, const Geom &gc, int nv, const S *P, const float2 *fine, float2 *coarse,
+template <typename S, typename TF>
+hipError_t restrict_fine_mma(const Geom &g, const Geom &gc, int nv, const S *P, const TF *fine, float2 *coarse,
                              int nrhs, hipStream_t st) {
   if (!transfer_mma_ok(g, nv, nrhs)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_restrict_fine_mma<S>), dim3(g.Vc), dim3(64 * TM_WAVES), 0, st, g, gc, nv, nrhs, P, fine,
+  hipLaunchKernelGGL((k_restrict_fine_mma<S, TF>), dim3(g.Vc), dim3(64 * TM_WAVES), 0, st, g, gc, nv, nrhs, P, fine,
                      coarse);
   return hipGetLastError();
 }
@@ -234,10 +248,12 @@ hipError_t prolong_fine_mma(const Geom &g, const Geom &gc, int nv, const S *P, c
   return hipGetLastError();
 }
 
-template hipError_t restrict_fine_mma<float2>(const Geom &, const Geom &, int, const float2 *, const float2 *,
-                                              float2 *, int, hipStream_t);
-template hipError_t restrict_fine_mma<chalf>(const Geom &, const Geom &, int, const chalf *, const float2 *, float2 *,
-                                             int, hipStream_t);
+template hipError_t restrict_fine_mma<float2, float2>(const Geom &, const Geom &, int, const float2 *,
+                                                      const float2 *, float2 *, int, hipStream_t);
+template hipError_t restrict_fine_mma<chalf, float2>(const Geom &, const Geom &, int, const chalf *, const float2 *,
+                                                     float2 *, int, hipStream_t);
+template hipError_t restrict_fine_mma<chalf, h16>(const Geom &, const Geom &, int, const chalf *, const h16 *,
+                                                  float2 *, int, hipStream_t);
 template hipError_t prolong_fine_mma<float2>(const Geom &, const Geom &, int, const float2 *, const float2 *,
                                              float2 *, int, int, hipStream_t);
 template hipError_t prolong_fine_mma<chalf>(const Geom &, const Geom &, int, const chalf *, const float2 *, float2 *,

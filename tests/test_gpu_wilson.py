@@ -54,6 +54,44 @@ def test_wilson_f32_error(cuda):
     assert err < 1e-6
 
 
+def _h16_round(psi):
+    """Spinors as the FP16 class stores them: each value rounded to FP32, the
+    site's 12 components divided by m = max |Re|, |Im| over them (FP32
+    arithmetic, 1/m rounded once), rounded to binary16 (nearest even) and
+    multiplied by m again in FP32.  Returns (decoded values, m per site)."""
+    x = psi.astype(np.complex64)
+    re, im = x.real, x.imag
+    m = np.maximum(np.abs(re).max(axis=(-2, -1)), np.abs(im).max(axis=(-2, -1))).astype(np.float32)
+    inv = np.where(m > 0, np.float32(1) / np.where(m > 0, m, np.float32(1)), np.float32(0)).astype(np.float32)
+    hr = (re * inv[..., None, None]).astype(np.float16).astype(np.float32) * m[..., None, None]
+    hi = (im * inv[..., None, None]).astype(np.float16).astype(np.float32) * m[..., None, None]
+    return hr.astype(np.float64) + 1j * hi.astype(np.float64), m.astype(np.float64)
+
+
+@pytest.mark.parametrize("L,nrhs", [((8, 8, 8, 8), 1), ((6, 4, 2, 10), 3)])
+def test_wilson_f16_storage(cuda, L, nrhs):
+    """FP16 class (binary16 links; binary16 spinors with a per-site scale;
+    FP32 arithmetic), one right-hand side and a ragged pair: against the
+    oracle applied in FP64 to the links rounded to binary16 and to the input
+    rounded as the library stores it.  What remains is the binary16 rounding
+    of the output, at most 2^-11 of each entry (2-norm bound), plus FP32
+    accumulation; entry by entry the output is within one binary16 unit of
+    its site's scale (2^-10 m) of the reference rounded the same way."""
+    U, psi, got = _run(L, 0.3, -0.25, "f16", nrhs=nrhs)
+    U16 = U.real.astype(np.float16).astype(np.float64) + 1j * U.imag.astype(np.float16).astype(np.float64)
+    xin, _ = _h16_round(psi)
+    ref = wi.apply_D(U16, xin, -0.25)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    ref_r, m = _h16_round(ref)
+    ulp = np.max(np.abs(got - ref_r) / np.maximum(m, 1e-300)[..., None, None])
+    e_plain = np.linalg.norm(got - wi.apply_D(U, psi, -0.25)) / np.linalg.norm(ref)
+    print(f"wilson f16 L={L} nrhs={nrhs}: rel err vs stored-input oracle {err:.2e} (vs unrounded {e_plain:.2e}); "
+          f"largest entry difference to the rounded reference {ulp * 1024:.2f} units of 2^-10 m")
+    assert 1e-6 < err < 2.0 ** -11 + 2e-6
+    assert ulp <= 2.0 ** -10 * 1.01
+    assert e_plain < 1e-3
+
+
 def test_wilson_full_size_sampled(cuda):
     """16^3 x 32 (the two-level benchmark lattice): full output against the C
     oracle matvec (itself pinned to the numpy oracle)."""
