@@ -5,9 +5,9 @@ One step = one pass of the whole hot path on the three-level 32^3 x 64
 workload (random SU(3) links of generator width eps = 0.35, the mass of
 nominal min Re lambda(D) = 0.1, aggregates 4^4 then 2^4, Nv = 24 on both
 levels, the 12 spin-colour point sources at the origin): mg_setup (null-vector
-relaxation, block orthonormalisation, Galerkin D_c on both levels) followed
-by one batched mg_solve of all 12 sources to a 1e-10 relative residual with
-the FP32 preconditioner (FP64 outer flexible GCR).  Inputs are generated on
+relaxation in FP32, block orthonormalisation and Galerkin D_c on both levels
+in FP64) followed by one batched mg_solve of all 12 sources to a 1e-10
+relative residual with the FP32 preconditioner (FP64 outer flexible GCR).  Inputs are generated on
 the host and resident in device memory before the timed region.
 
 Prints one JSON line: right-hand sides solved per second, the plain FP64
@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precond", default="f32", choices=["f64", "f32", "f16"])
+    ap.add_argument("--setup-prec", default="f32", choices=["f64", "f32"],
+                    help="arithmetic of the null-vector relaxation (setup stage one)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-c1", action="store_true")
@@ -398,7 +400,8 @@ def main():
     torch.cuda.synchronize()
 
     def setup(**kw):
-        return mgwd.MG(U, mass, blocks, nv, [st, st1], max_rhs=nrhs, precond_prec=a.precond, **kw)
+        return mgwd.MG(U, mass, blocks, nv, [st, st1], max_rhs=nrhs, precond_prec=a.precond,
+                       setup_prec=a.setup_prec, **kw)
 
     def step(timing):
         ctx = setup()
@@ -450,7 +453,7 @@ def main():
     torch.cuda.synchronize()
     tl0 = time.perf_counter()
     ctx = mgwd.MG(U, W.mass_for("C3", light), blocks, nv, [st, st1], max_rhs=nrhs, precond_prec=a.precond,
-                  refine_group=8, refine_iters=5)
+                  setup_prec=a.setup_prec, refine_group=8, refine_iters=5)
     torch.cuda.synchronize()
     setup_l = time.perf_counter() - tl0
     _, il, rcl = ctx.solve(b, 1e-10)
@@ -501,7 +504,7 @@ def main():
         "data": "synthetic (seeded random SU(3) links, 12 spin-colour point sources at the origin)",
         "config": {"workload": f"three-level MG, 32^3x64, eps {cfg['eps']}, aggregates 4^4 then 2^4, Nv 24/24, "
                                f"12 point sources batched, nominal min Re lambda {target}",
-                   "mass": mass, "precond": a.precond},
+                   "mass": mass, "precond": a.precond, "setup_relaxation": a.setup_prec},
         "time_to_solution_s": round(solve_s, 4),
         "setup_s": round(setup64_s, 4),
         "iters": infos[-1]["iters"][:nrhs],

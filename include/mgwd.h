@@ -113,6 +113,12 @@ typedef struct {
    * residual the first leaves and added; at most 4).                      */
   int smoother;
   int cycles;
+  /* Arithmetic of setup stage one (the relaxation of the start vectors):
+   * MG_F64 (0, default), or MG_F32 (FP32 copies of the level's operator and
+   * vectors, batches of at most 12 vectors; the relaxed vectors are widened
+   * to FP64 before the block orthonormalisation, which, like the Galerkin
+   * construction, is always FP64).                                        */
+  mg_prec_t setup_prec;
 } mg_params_t;
 
 #define MG_SMOOTH_MR 0

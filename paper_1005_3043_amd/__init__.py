@@ -56,7 +56,8 @@ class Params(ctypes.Structure):
                 ("use_graph", ctypes.c_int),
                 ("init_vectors", ctypes.c_void_p * (MAX_LEVELS - 1)),
                 ("refine_group", ctypes.c_int), ("refine_iters", ctypes.c_int),
-                ("smoother", ctypes.c_int), ("cycles", ctypes.c_int)]
+                ("smoother", ctypes.c_int), ("cycles", ctypes.c_int),
+                ("setup_prec", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -201,7 +202,7 @@ class MG:
                  t_antiperiodic=True, setup_rounds=5, setup_mr_steps=4, omega=0.9, pre=4,
                  post=4, coarse_tol=1e-3, coarse_maxiter=1000, gcr_restart=8, max_iter=10000,
                  precond_prec="f64", max_rhs=1, use_graph=True, refine_group=0, refine_iters=5,
-                 smoother="mr", cycles=1):
+                 smoother="mr", cycles=1, setup_prec="f64"):
         Lt, Lz, Ly, Lx = U.shape[1:5]
         self.L = (Lx, Ly, Lz, Lt)
         self.nv = list(nv)
@@ -218,6 +219,7 @@ class MG:
         p.precond_prec, p.max_rhs, p.use_graph = PREC[precond_prec], max_rhs, int(bool(use_graph))
         p.refine_group, p.refine_iters = int(refine_group), int(refine_iters)
         p.smoother, p.cycles = {"mr": 0, "gmres": 1}[smoother], int(cycles)
+        p.setup_prec = PREC[setup_prec]
         self._keep = list(init_vectors)
         for i, v in enumerate(init_vectors):
             p.init_vectors[i] = _dev(v, f"init_vectors[{i}]").value

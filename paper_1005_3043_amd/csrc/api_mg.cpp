@@ -67,6 +67,8 @@ int check_params(const mg_lattice_t *lat, const mg_params_t *p) {
   if (p->cycles < 0 || p->cycles > 4) return bad(MG_EINVAL, "cycles must be in [0, 4]");
   if (p->precond_prec != MG_F64 && p->precond_prec != MG_F32 && p->precond_prec != MG_F16)
     return bad(MG_ENOTSUP, "precond_prec must be MG_F64, MG_F32 or MG_F16");
+  if (p->setup_prec != MG_F64 && p->setup_prec != MG_F32)
+    return bad(MG_ENOTSUP, "setup_prec must be MG_F64 or MG_F32");
   return MG_OK;
 }
 

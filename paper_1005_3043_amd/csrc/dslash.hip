@@ -153,6 +153,36 @@ __device__ __forceinline__ uint32_t visit_block(uint32_t bid, uint32_t nblk, con
   return visit_pos(xcd_remap(bid, nblk), nblk, g, per);
 }
 
+// 64-site tile (one wavefront) that wave w of workgroup bid (of nblk, with
+// wpb waves each) visits.  With 4^4 aggregates a tile is the 4 x 4 x 4 cube
+// at one time slice o_t of an aggregate; the tiles of XCD k are those of
+// its z layers, walked x fastest, then y, then z, then the site time 4 c_t +
+// o_t, so that a tile's time neighbours are one x-y layer of tiles away
+// (1.6 MB of spinors and links for two FP32 right-hand sides on 32^3 x 64,
+// against 6.3 MB for the layer of whole aggregates, more than an XCD's 4 MB
+// L2): on 32^3 x 64 with 12 right-hand sides 2 % faster than visiting whole
+// aggregates, 3-4 % fewer bytes fetched in FP32 and FP16.  Other shapes
+// take visit_block's order, a wave per tile of each block.
+__device__ __forceinline__ uint32_t visit_tile(uint32_t bid, uint32_t nblk, uint32_t w, uint32_t wpb,
+                                               const Geom &g) {
+  const uint32_t C0 = (uint32_t)g.C[0], C1 = (uint32_t)g.C[1], C2 = (uint32_t)g.C[2];
+  const uint32_t ntile = nblk * wpb;
+  if (g.vb == 256 && g.b[0] == 4 && g.b[1] == 4 && g.b[2] == 4 && (nblk & 7u) == 0 &&
+      C2 % 8 == 0 && ntile == g.Vc * 4u) {
+    const uint32_t q = xcd_remap(bid, nblk) * wpb + w;
+    const uint32_t per_xcd = ntile >> 3, xcd = q / per_xcd;
+    uint32_t r = q - xcd * per_xcd;
+    const uint32_t cx = r % C0;
+    r /= C0;
+    const uint32_t cy = r % C1;
+    r /= C1;
+    const uint32_t nz = C2 >> 3, czl = r % nz, T = r / nz;
+    const uint32_t cz = xcd * nz + czl, ct = T >> 2, ot = T & 3u;
+    return (cx + C0 * (cy + C1 * (cz + C2 * ct))) * 4u + ot;
+  }
+  return visit_block(bid, nblk, g, 64 * wpb) * wpb + w;
+}
+
 
 // Minimum waves per SIMD requested from the register allocator (0 = none).
 #ifndef MG_DSLASH_WAVES_F64
@@ -177,8 +207,7 @@ __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash(Geom g, const
   in += (size_t)blockIdx.y * site_slots<TI>() * g.Vpad;
   const size_t off = (size_t)blockIdx.y * site_slots<TO>() * g.Vpad;
   out += off;
-  const uint32_t tile = visit_block(blockIdx.x, gridDim.x, g, blockDim.x);
-  const uint32_t s = tile * blockDim.x + threadIdx.x;
+  const uint32_t s = visit_tile(blockIdx.x, gridDim.x, threadIdx.x >> 6, blockDim.x >> 6, g) * 64 + (threadIdx.x & 63);
   double red[3] = {0.0, 0.0, 0.0};
   if (s < g.V) {
     C res[12], ctr[12];
@@ -229,11 +258,10 @@ __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash_rb(Geom g, co
                                                    double *__restrict__ partials, int nrhs) {
   using C = c_t<R>;
   const int r0 = blockIdx.y * K;
-  const uint32_t blk = visit_block(blockIdx.x, gridDim.x, g, blockDim.x);
   const uint32_t slot = blockIdx.x, nslot = gridDim.x;
   const int kv = nrhs - r0 < K ? nrhs - r0 : K;
   const size_t vsi = (size_t)site_slots<TI>() * g.Vpad, vso = (size_t)site_slots<TO>() * g.Vpad;
-  const uint32_t s = blk * blockDim.x + threadIdx.x;
+  const uint32_t s = visit_tile(blockIdx.x, gridDim.x, threadIdx.x >> 6, blockDim.x >> 6, g) * 64 + (threadIdx.x & 63);
   double red[K][3];
 #pragma unroll
   for (int k = 0; k < K; ++k) red[k][0] = red[k][1] = red[k][2] = 0.0;

@@ -1251,11 +1251,54 @@ int fgcr(mg_ctx *c, const double2 *b, double2 *x, int nrhs, double tol, int *ite
 }
 
 // ------------------------------------------------------------ setup
+// The relaxation rounds of relax() in FP32 (setup_prec = MG_F32): FP32 copies of the level's
+// operator (links of level 0, or the coarse stencil of a coarser level) and
+// of the vectors, in batches of at most RELAX32_BATCH vectors so that the
+// coarse levels take the matrix-core stencil; the relaxed vectors are
+// widened back into V.
+constexpr int RELAX32_BATCH = 12;
+static int relax32(mg_ctx *c, int l, double2 *V, int nv, hipStream_t st) {
+  Level &L = c->lev[l];
+  const size_t n = L.vsize();
+  if (l == 0) {
+    if (!L.U32.p) {
+      MG_TRY(L.U32.alloc(4 * (size_t)L.nl * L.g.Vpad));
+      if (L.nl == 6) HIPK(compress_links<float2>(L.g, L.U64, L.U32, c->part, st));
+      else HIPK(store_convert<float2>(L.U32, L.U64, 36 * (size_t)L.g.Vpad, st));
+    }
+  } else if (!L.L32.p) {
+    MG_TRY(L.L32.alloc(L.L64.n));
+    HIPK(store_convert<float2>(L.L32, L.L64, L.L64.n, st));
+  }
+  const int B = std::min(nv, RELAX32_BATCH);
+  DevBuf<float2> v, x, r, q;
+  MG_TRY(v.alloc(n * B));
+  MG_TRY(x.alloc(n * B));
+  MG_TRY(r.alloc(n * B));
+  MG_TRY(q.alloc(n * B));
+  for (int k0 = 0; k0 < nv; k0 += B) {
+    const int nb = std::min(B, nv - k0);
+    double2 *Vk = V + (size_t)k0 * n;
+    HIPK((convert<float, double>(v, Vk, n * nb, st)));
+    for (int round = 0; round < c->p.setup_rounds; ++round) {
+      MG_TRY(apply_A<PF32>(c, l, v, r, nb, DS_PLAIN, nullptr, st));
+      MG_TRY(mr<PF32>(c, l, x.p, r.p, q.p, c->p.setup_mr_steps, false, nb, st, false));
+      HIPK(sub_inplace<float>(v, x, n, nb, st));
+      HIPK(norm2<float>(v, n, nb, c->part, c->dsc, st));
+      HIPK(scale_rsqrt<float>(v, n, nb, c->dsc, st));
+    }
+    HIPK((convert<double, float>(Vk, v, n * nb, st)));
+  }
+  HIPK(hipStreamSynchronize(st));
+  return MG_OK;
+}
+
 // Null-vector relaxation: v <- v - MR(A, A v), v <- v / ||v||, `rounds` times,
-// all nv vectors as one batch (FP64).
+// all nv vectors as one batch (FP64; FP32 in batches when setup_prec says so).
 int relax(mg_ctx *c, int l, double2 *V, int nv, hipStream_t st) {
   Level &L = c->lev[l];
   const size_t n = L.vsize();
+  if (c->p.setup_prec == MG_F32) return relax32(c, l, V, nv, st);
   DevBuf<double2> x, r, q;
   MG_TRY(x.alloc(n * nv));
   MG_TRY(r.alloc(n * nv));

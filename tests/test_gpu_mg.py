@@ -329,6 +329,40 @@ def test_three_level(cuda):
     assert abs(info["iters"][0] - it_ref) <= 1
 
 
+def test_setup_prec_f32(cuda):
+    """Setup stage one in FP32 (setup_prec = MG_F32) on both levels of a
+    three-level hierarchy whose 16 and 14 start vectors go through in
+    batches of 12 and a ragged rest: the relaxed vectors against the
+    oracle's FP64 relaxation of the same starts, and the solve built on them.
+    Bound: 20 MR steps per vector, each a handful of FP32 operations per
+    entry after a 9-term stencil sum, relative rounding at most ~50 u per
+    step with u = 2^-24, so 20 x 50 x 6e-8 = 6e-5 < 1e-4; the level-1
+    vectors also carry the FP32 error of the level-0 P they are built on.
+    The FP64 outer method absorbs it: the solve meets 1e-10 within one
+    iteration of the oracle's count."""
+    import paper_1005_3043_amd as mgwd
+    L, blocks, nv, eps, m, seed = (8, 8, 8, 8), [(2, 2, 2, 2), (2, 2, 2, 2)], [16, 14], 0.3, -0.3, 5
+    U = W.gauge_field(L, eps, seed)
+    starts = W.setup_starts(L, nv[0], seed)
+    Lc = tuple(L[mu] // blocks[0][mu] for mu in range(4))
+    cst = W.coarse_setup_starts(Lc, 2 * nv[0], nv[1], seed)
+    ctx = mgwd.MG(torch.from_numpy(U).cuda(), m, blocks, nv,
+                  [torch.from_numpy(starts).cuda(), torch.from_numpy(cst).cuda()], setup_prec="f32")
+    h = so.mg_setup(U, m, so.MGParams(blocks=blocks, nv=nv), starts, cst)
+    e0 = _rel(ctx.export_nullvecs(0), h.levels[0].nullvecs)
+    e1 = _rel(ctx.export_nullvecs(1), h.levels[1].nullvecs)
+    b = W.gaussian_spinor(L, 1)
+    x, info, rc = ctx.solve(torch.from_numpy(b).cuda(), 1e-10)
+    res = np.linalg.norm(b - wi.apply_D(U, x.cpu().numpy(), m)) / np.linalg.norm(b)
+    _, it_ref, _, _ = so.mg_solve(h, b, 1e-10)
+    print(f"FP32 setup: null vectors rel err level 0 {e0:.2e}, level 1 {e1:.2e}; solve resid {res:.2e}, "
+          f"iters {info['iters'][0]} (oracle {it_ref})")
+    ctx.close()
+    assert 1e-9 < e0 < 1e-4 and 1e-9 < e1 < 1e-4
+    assert rc == 0 and res <= 1e-10 * 1.001
+    assert abs(info["iters"][0] - it_ref) <= 1
+
+
 @pytest.mark.parametrize("prec", ["f32", "f16"])
 def test_cgnr_persistent_matches_chunks(cuda, prec):
     """The single-RHS coarsest CGNR as one cooperative launch does the
