@@ -403,11 +403,20 @@ def main():
         return mgwd.MG(U, mass, blocks, nv, [st, st1], max_rhs=nrhs, precond_prec=a.precond,
                        setup_prec=a.setup_prec, **kw)
 
+    phase_ms = {"create": [], "solve": [], "close": []}
+
     def step(timing):
+        t0 = time.perf_counter()
         ctx = setup()
+        t1 = time.perf_counter()
         ctx.set_timing(timing)
         x, info, rc = ctx.solve(b, 1e-10)
+        t2 = time.perf_counter()
         ctx.close()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        for k, v in (("create", t1 - t0), ("solve", t2 - t1), ("close", t3 - t2)):
+            phase_ms[k].append(round(v * 1e3, 1))
         if rc != 0:
             raise RuntimeError("mg_solve did not converge")
         return x, info
@@ -505,6 +514,7 @@ def main():
         "config": {"workload": f"three-level MG, 32^3x64, eps {cfg['eps']}, aggregates 4^4 then 2^4, Nv 24/24, "
                                f"12 point sources batched, nominal min Re lambda {target}",
                    "mass": mass, "precond": a.precond, "setup_relaxation": a.setup_prec},
+        "host_ms_per_phase": phase_ms,
         "time_to_solution_s": round(solve_s, 4),
         "setup_s": round(setup64_s, 4),
         "iters": infos[-1]["iters"][:nrhs],

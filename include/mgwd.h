@@ -119,6 +119,20 @@ typedef struct {
    * to FP64 before the block orthonormalisation, which, like the Galerkin
    * construction, is always FP64).                                        */
   mg_prec_t setup_prec;
+  /* Learned start vectors (the network of the ptc_* calls below, an
+   * extension): learned_setup = 1 takes the level-0 start vectors from the
+   * network instead of from init_vectors[0] directly: init_vectors[0] then
+   * holds ONE noise field eta ([Lt][Lz][Ly][Lx][4][3], DEVICE complex128),
+   * the starts are Y = net(eta) with the DEVICE complex64 weights
+   * ptc_weights[0] = W1 [ptc_hidden][1][9][4][4] and ptc_weights[1] = W2
+   * [nv[0]][ptc_hidden][9][4][4] (n_out = nv[0]) on the links U, and the
+   * setup_rounds relaxation rounds start from Y (0 rounds: Y itself).
+   * The links and the aggregate shape are those of mg_setup (block[0]).
+   * learned_setup = 0 (default): plain start vectors.  Errors: MG_EINVAL
+   * (missing weights, ptc_hidden outside [1, 64]).                        */
+  int learned_setup;
+  int ptc_hidden;
+  const void *ptc_weights[2];
 } mg_params_t;
 
 #define MG_SMOOTH_MR 0
@@ -356,7 +370,17 @@ int mg_time_dslash(mg_ctx_t *ctx, mg_prec_t prec, int nrhs, int reps,
 int mg_time_coarse(mg_ctx_t *ctx, int level, mg_prec_t prec, int nrhs,
                    int reps, double *avg_ms, hipStream_t stream);
 
+/* Frees a context.  Its device buffers go back to the library's cache of
+ * device allocations (per device, at most 60 % of the device's memory,
+ * oldest blocks freed first), from which later contexts with the same
+ * buffer sizes take them instead of allocating again: allocating the
+ * buffers of a 32^3 x 64 context anew takes seconds.                      */
 int mg_destroy(mg_ctx_t *ctx);
+
+/* Frees every cached device allocation of the current device (see
+ * mg_destroy); *released (may be NULL) receives the number of bytes.
+ * Returns MG_OK, or MG_EHIP if no device is current.                      */
+int mg_release_cached_memory(size_t *released);
 
 /* Message describing the last error on the calling thread ("" if none).   */
 const char *mg_last_error(void);

@@ -23,7 +23,7 @@ MAX_RHS = 16
 
 EXPORTED = ["wilson_apply", "wilson_apply_noalloc", "mg_setup", "mg_set_precond_prec", "mg_set_mass", "mg_set_timing", "mg_restrict",
             "mg_prolong", "coarse_apply", "mg_apply_op", "mg_vcycle", "mg_transfer", "mg_set_transfer_variant", "mg_transfer_variant", "mg_set_coarse_variant", "mg_coarse_variant", "mg_set_cgnr_persistent", "mg_coarse_solve", "mg_solve", "mg_time_dslash", "mg_time_coarse",
-            "mg_destroy", "mg_last_error", "mg_export_maps", "mg_export_P",
+            "mg_destroy", "mg_release_cached_memory", "mg_last_error", "mg_export_maps", "mg_export_P",
             "mg_export_coarse_op", "mg_export_nullvecs", "mg_level_info",
             "ptc_create", "ptc_set_links", "ptc_set_targets", "ptc_forward", "ptc_loss_grad", "ptc_adam",
             "ptc_destroy"]
@@ -57,7 +57,9 @@ class Params(ctypes.Structure):
                 ("init_vectors", ctypes.c_void_p * (MAX_LEVELS - 1)),
                 ("refine_group", ctypes.c_int), ("refine_iters", ctypes.c_int),
                 ("smoother", ctypes.c_int), ("cycles", ctypes.c_int),
-                ("setup_prec", ctypes.c_int)]
+                ("setup_prec", ctypes.c_int),
+                ("learned_setup", ctypes.c_int), ("ptc_hidden", ctypes.c_int),
+                ("ptc_weights", ctypes.c_void_p * 2)]
 
 
 class Info(ctypes.Structure):
@@ -122,6 +124,7 @@ def lib():
             "mg_time_dslash": [vp, ci, ci, ci, ctypes.POINTER(cd), vp],
             "mg_time_coarse": [vp, ci, ci, ci, ci, ctypes.POINTER(cd), vp],
             "mg_destroy": [vp],
+            "mg_release_cached_memory": [ctypes.POINTER(ctypes.c_size_t)],
             "mg_last_error": [],
             "mg_export_maps": [vp, ci, vp, vp, vp, vp],
             "mg_export_P": [vp, ci, vp],
@@ -169,6 +172,14 @@ def dims_of_spinor(psi: torch.Tensor):
     return (Lx, Ly, Lz, Lt)
 
 
+def release_cached_memory() -> int:
+    """Frees the library's cache of device allocations on the current device
+    (buffers of destroyed contexts kept for reuse); returns the bytes freed."""
+    n = ctypes.c_size_t(0)
+    _check(lib().mg_release_cached_memory(ctypes.byref(n)))
+    return int(n.value)
+
+
 def wilson_apply(U: torch.Tensor, psi: torch.Tensor, mass: float, prec: str = "f64",
                  t_antiperiodic: bool = True, out: torch.Tensor | None = None) -> torch.Tensor:
     """out = D(U) psi (Eq. 2) for psi[..., t, z, y, x, 4, 3] (leading axes = RHS)."""
@@ -202,7 +213,10 @@ class MG:
                  t_antiperiodic=True, setup_rounds=5, setup_mr_steps=4, omega=0.9, pre=4,
                  post=4, coarse_tol=1e-3, coarse_maxiter=1000, gcr_restart=8, max_iter=10000,
                  precond_prec="f64", max_rhs=1, use_graph=True, refine_group=0, refine_iters=5,
-                 smoother="mr", cycles=1, setup_prec="f64"):
+                 smoother="mr", cycles=1, setup_prec="f64", learned=None):
+        """learned = (W1, W2, n_hidden): the level-0 start vectors are the
+        network's output for the noise field init_vectors[0] (one field),
+        computed inside mg_setup."""
         Lt, Lz, Ly, Lx = U.shape[1:5]
         self.L = (Lx, Ly, Lz, Lt)
         self.nv = list(nv)
@@ -221,6 +235,12 @@ class MG:
         p.smoother, p.cycles = {"mr": 0, "gmres": 1}[smoother], int(cycles)
         p.setup_prec = PREC[setup_prec]
         self._keep = list(init_vectors)
+        if learned is not None:
+            W1, W2, n_hidden = learned
+            p.learned_setup, p.ptc_hidden = 1, int(n_hidden)
+            p.ptc_weights[0] = _dev64(W1, "W1").value
+            p.ptc_weights[1] = _dev64(W2, "W2").value
+            self._keep += [W1, W2]
         for i, v in enumerate(init_vectors):
             p.init_vectors[i] = _dev(v, f"init_vectors[{i}]").value
         self.params = p

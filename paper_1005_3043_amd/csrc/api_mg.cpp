@@ -69,6 +69,11 @@ int check_params(const mg_lattice_t *lat, const mg_params_t *p) {
     return bad(MG_ENOTSUP, "precond_prec must be MG_F64, MG_F32 or MG_F16");
   if (p->setup_prec != MG_F64 && p->setup_prec != MG_F32)
     return bad(MG_ENOTSUP, "setup_prec must be MG_F64 or MG_F32");
+  if (p->learned_setup != 0 && p->learned_setup != 1) return bad(MG_EINVAL, "learned_setup must be 0 or 1");
+  if (p->learned_setup) {
+    if (!p->ptc_weights[0] || !p->ptc_weights[1]) return bad(MG_EINVAL, "learned_setup: ptc_weights missing");
+    if (p->ptc_hidden < 1 || p->ptc_hidden > 64) return bad(MG_EINVAL, "learned_setup: ptc_hidden must be in [1, 64]");
+  }
   return MG_OK;
 }
 
@@ -128,7 +133,26 @@ extern "C" int mg_setup(const mg_lattice_t *lat, const void *U, double mass, con
   if (rc == MG_OK) rc = hip_rc(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming), "hipEventCreate");
   for (int i = 0; i < 2 && rc == MG_OK; ++i)
     rc = hip_rc(hipEventCreateWithFlags(&c->ev_chunk[i], hipEventDisableTiming), "hipEventCreate");
+  // learned start vectors: the network's output replaces init_vectors[0]
+  // for the relaxation (kept in Y until the setup has used it)
+  AsyncBuf<double2> Y(stream);
+  if (rc == MG_OK && params->learned_setup) {
+    ptc_ctx_t *pc = nullptr;
+    rc = ptc_create(lat, params->block[0], params->ptc_hidden, params->nv[0], &pc);
+    if (rc == MG_OK) {
+      uint64_t V = 1;
+      for (int mu = 0; mu < 4; ++mu) V *= (uint64_t)lat->L[mu];
+      rc = hip_rc(Y.alloc((size_t)12 * V * params->nv[0]), "hipMallocAsync");
+      if (rc == MG_OK) rc = ptc_set_links(pc, U, stream);
+      if (rc == MG_OK)
+        rc = ptc_forward(pc, params->ptc_weights[0], params->ptc_weights[1], params->init_vectors[0], Y.p, stream);
+      const int rd = ptc_destroy(pc);
+      if (rc == MG_OK) rc = rd;
+    }
+    if (rc == MG_OK) c->p.init_vectors[0] = Y.p;
+  }
   if (rc == MG_OK) rc = setup(c, U, stream);
+  c->p.init_vectors[0] = params->init_vectors[0];
   if (rc == MG_OK) rc = ensure_prec(c, c->prec, stream);
   if (rc == MG_OK) rc = hip_rc(hipStreamSynchronize(stream), "mg_setup");
   if (rc != MG_OK) {

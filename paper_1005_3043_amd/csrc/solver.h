@@ -107,6 +107,12 @@ hipError_t export_maps_k(const Geom &g, const Geom &gc, int32_t *f2c, int32_t *f
                          hipStream_t st);
 
 // ---------------------------------------------------------------- buffers
+// Device allocations through the library's cache (pool.cpp): pool_alloc
+// reuses a cached block of the same rounded size or calls hipMalloc;
+// pool_free keeps the block for the next request (up to a per-device cap).
+hipError_t pool_alloc(void **out, size_t bytes);
+void pool_free(void *p, size_t bytes);
+
 template <typename T> struct DevBuf {
   T *p = nullptr;
   size_t n = 0;
@@ -115,7 +121,7 @@ template <typename T> struct DevBuf {
   DevBuf &operator=(const DevBuf &) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) pool_free(p, n * sizeof(T));
     p = nullptr;
     n = 0;
   }
@@ -123,14 +129,14 @@ template <typename T> struct DevBuf {
     if (p && n >= count) return MG_OK;
     release();
     if (count == 0) return MG_OK;
-    hipError_t e = hipMalloc((void **)&p, count * sizeof(T));
+    hipError_t e = pool_alloc((void **)&p, count * sizeof(T));
     // Zero-filled (padding entries stay zero), and the fill has completed
     // on return: the buffer is next used on streams that do not order
     // themselves after the default stream.
     if (e == hipSuccess) e = hipMemsetAsync(p, 0, count * sizeof(T), nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
-      if (p) (void)hipFree(p);
+      if (p) pool_free(p, count * sizeof(T));
       p = nullptr;
       set_error(hip_error_string(e, "hipMalloc"));
       return e == hipErrorOutOfMemory ? MG_ENOMEM : MG_EHIP;

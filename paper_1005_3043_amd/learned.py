@@ -71,21 +71,21 @@ def train(prop: Proposal, net: PTC, fields, noise, steps, lr=1e-3, log=None):
     return hist
 
 
-def learned_setup(U, mass, block, prop: Proposal, net: PTC, eta, rounds, **kw):
-    """mg_setup started from the network's proposal with `rounds` relaxation
-    rounds (0 = use the proposal as is)."""
-    net.set_links(U)
-    Y = net.forward(prop.W1, prop.W2, eta)
-    return MG(U, mass, [block], [prop.n_out], [Y], setup_rounds=rounds, **kw)
+def learned_setup(U, mass, block, prop: Proposal, eta, rounds, **kw):
+    """mg_setup started from the network's proposal for the noise field eta
+    (the forward pass runs inside mg_setup) with `rounds` relaxation rounds
+    (0 = use the proposal as is)."""
+    return MG(U, mass, [block], [prop.n_out], [eta], setup_rounds=rounds,
+              learned=(prop.W1, prop.W2, prop.n_hidden), **kw)
 
 
-def solve_with_fallback(U, mass, block, prop, net, eta, rounds, b, plain_starts, max_iters, tol=1e-10,
+def solve_with_fallback(U, mass, block, prop, eta, rounds, b, plain_starts, max_iters, tol=1e-10,
                         precond="f16"):
     """Learned setup judged by its outer iteration count: if the solve needs
     more than max_iters iterations (or fails), redo it with the plain
     relaxation setup.  Returns (x, info, used_fallback, setup_s)."""
     t0 = time.perf_counter()
-    ctx = learned_setup(U, mass, block, prop, net, eta, rounds)
+    ctx = learned_setup(U, mass, block, prop, eta, rounds)
     setup_s = time.perf_counter() - t0
     ctx.set_precond_prec(precond)
     x, info, rc = ctx.solve(b, tol)
@@ -105,9 +105,6 @@ def evaluate(prop, U, mass, block, eta, b, starts, rounds_list, precond="f16"):
     """Setup time and outer iterations: Gaussian starts with 0, 1, 2 and 5
     relaxation rounds (5 = the plain setup) and the learned proposal with each
     number of rounds in rounds_list."""
-    from . import PTC as _PTC
-    Lt, Lz, Ly, Lx = U.shape[1:5]
-    net = _PTC((Lx, Ly, Lz, Lt), block, prop.n_hidden, prop.n_out)
     out = {}
 
     def run(make):
@@ -125,8 +122,7 @@ def evaluate(prop, U, mass, block, eta, b, starts, rounds_list, precond="f16"):
     for r in (0, 1, 2, 5):
         out[f"plain_r{r}"] = run(lambda r=r: MG(U, mass, [block], [prop.n_out], [starts], setup_rounds=r))
     for r in rounds_list:
-        out[f"learned_r{r}"] = run(lambda r=r: learned_setup(U, mass, block, prop, net, eta, r))
-    net.close()
+        out[f"learned_r{r}"] = run(lambda r=r: learned_setup(U, mass, block, prop, eta, r))
     return out
 
 

@@ -83,10 +83,29 @@ def test_fallback_to_plain_setup(trained):
     net, init, prop, hist = trained
     U, st, b, eta = _held_out(2002)
     # a judge threshold below what the learned setup reaches forces the fallback
-    x, info, fell, _ = lr.solve_with_fallback(U, MASS, BLOCK, prop, net, eta, 0, b, st, max_iters=1)
+    x, info, fell, _ = lr.solve_with_fallback(U, MASS, BLOCK, prop, eta, 0, b, st, max_iters=1)
     assert fell and info["iters"][0] > 1
     res = np.linalg.norm(b.cpu().numpy() - wi.apply_D(U.cpu().numpy(), x.cpu().numpy(), MASS)) / \
         np.linalg.norm(b.cpu().numpy())
     assert res <= 1e-10 * 1.001
-    x2, info2, fell2, _ = lr.solve_with_fallback(U, MASS, BLOCK, prop, net, eta, 1, b, st, max_iters=10_000)
+    x2, info2, fell2, _ = lr.solve_with_fallback(U, MASS, BLOCK, prop, eta, 1, b, st, max_iters=10_000)
     assert not fell2
+
+
+def test_learned_setup_inside_mg_setup(trained):
+    """mg_setup with learned_setup = 1 runs the network on the noise field
+    itself: the same null vectors, bit for bit, as the network's output
+    computed with ptc_forward and passed to mg_setup as plain starts, for 0
+    and 2 relaxation rounds."""
+    import paper_1005_3043_amd as mgwd
+    net, init, prop, hist = trained
+    U, st, b, eta = _held_out(2003)
+    net.set_links(U)
+    Y = net.forward(prop.W1, prop.W2, eta)
+    for rounds in (0, 2):
+        a = mgwd.MG(U, MASS, [BLOCK], [NOUT], [eta], setup_rounds=rounds, learned=(prop.W1, prop.W2, NH))
+        p = mgwd.MG(U, MASS, [BLOCK], [NOUT], [Y], setup_rounds=rounds)
+        va, vp = a.export_nullvecs(0), p.export_nullvecs(0)
+        a.close()
+        p.close()
+        assert np.array_equal(va, vp), rounds

@@ -329,6 +329,31 @@ def test_three_level(cuda):
     assert abs(info["iters"][0] - it_ref) <= 1
 
 
+def test_allocation_cache_reuse(cuda):
+    """A context built after one of the same shape was destroyed takes its
+    buffers from the library's cache of device allocations: it solves bit for
+    bit as the first (every buffer is zero-filled again when handed out), the
+    cache holds the destroyed context's buffers, and releasing it frees them
+    all."""
+    import paper_1005_3043_amd as mgwd
+    L, blocks, nv, eps, m, seed = CASES["8^4 b4^4 nv8"]
+    U = torch.from_numpy(W.gauge_field(L, eps, seed)).cuda()
+    st = torch.from_numpy(W.setup_starts(L, nv[0], seed)).cuda()
+    b = torch.from_numpy(W.gaussian_spinor(L, 0, batch=(2,))).cuda()
+    mgwd.release_cached_memory()
+    xs = []
+    for rep in range(2):
+        ctx = mgwd.MG(U, m, blocks, nv, [st], precond_prec="f32", max_rhs=2)
+        x, info, rc = ctx.solve(b, 1e-10)
+        assert rc == 0
+        xs.append(x.clone())
+        ctx.close()
+    freed = mgwd.release_cached_memory()
+    print(f"allocation cache: {freed / 2**20:.1f} MiB cached after two contexts")
+    assert torch.equal(xs[0], xs[1])
+    assert freed > 0 and mgwd.release_cached_memory() == 0
+
+
 def test_setup_prec_f32(cuda):
     """Setup stage one in FP32 (setup_prec = MG_F32) on both levels of a
     three-level hierarchy whose 16 and 14 start vectors go through in
