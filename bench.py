@@ -180,7 +180,7 @@ def kernel_probe(mgwd, torch, W):
     st = torch.from_numpy(W.setup_starts(L, nv[0], cfg["seed"])).cuda()
     Lc = tuple(L[mu] // blocks[0][mu] for mu in range(4))
     st1 = torch.from_numpy(W.coarse_setup_starts(Lc, 2 * nv[0], nv[1], cfg["seed"])).cuda()
-    ctx = mgwd.MG(U, W.mass_for("C3", HEADLINE_TARGET), blocks, nv, [st, st1], max_rhs=12)
+    ctx = mgwd.MG(U, W.mass_for("C3", HEADLINE_TARGET), blocks, nv, [st, st1], max_rhs=12, setup_prec="f32")
     for prec in ("f64", "f32", "f16"):
         for nrhs in (12, 1):
             ms = ctx.time_dslash(prec, nrhs, 10)
