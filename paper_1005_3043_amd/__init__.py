@@ -9,6 +9,7 @@ fallback implementation.
 from __future__ import annotations
 
 import ctypes
+import sys
 import os
 
 import torch
@@ -257,6 +258,11 @@ class MG:
             self.ctx = None
 
     def __del__(self):
+        # At interpreter shutdown the HIP runtime (and a profiler's hooks) may
+        # already be torn down: a handle still open then is left to process
+        # exit, which frees device memory anyway.  close() is the teardown.
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -476,6 +482,11 @@ class PTC:
             self.ctx = None
 
     def __del__(self):
+        # At interpreter shutdown the HIP runtime (and a profiler's hooks) may
+        # already be torn down: a handle still open then is left to process
+        # exit, which frees device memory anyway.  close() is the teardown.
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -391,6 +391,19 @@ __device__ __forceinline__ void cgp_allsum2(const double *__restrict__ a, const 
 // Arrivals are spread over CGP_NC counters on separate 256-byte lines
 // (workgroup i counts on i mod CGP_NC), so that no single address takes
 // every workgroup's atomic; the first wavefront polls all of them at once.
+//
+// Why relaxed atomics order the exchange: every value another workgroup
+// reads was stored with an agent-scope atomic store (written through to the
+// agent's coherence point) and is read with an agent-scope atomic load
+// (which bypasses the XCD's L2 and reads at that point).  s_waitcnt(0)
+// holds each thread until its stores are acknowledged, i.e. performed at
+// agent scope; the workgroup barrier then puts all of them before the one
+// arrival increment.  A reader issues its data loads only after it has seen
+// the count reach the target (the loop exit and the workgroup barrier order
+// them after the poll).  So every data load is performed after every data
+// store it depends on, at the same coherence point.  A release / acquire pair
+// would give the same order with an L2 write-back and invalidate per barrier
+// (about 80 us each here); with no data ever held in L2 they are not needed.
 constexpr int CGP_NC = CGP_BAR_WORDS / 64;
 __device__ __forceinline__ bool cgp_barrier(unsigned *bar, unsigned target, int *fail, unsigned spin_max,
                                             int *lds_ok) {
