@@ -20,7 +20,9 @@ bounded sample.
 
 --kernel-probe runs fixed launches of the profiled kernels (a 1 GiB device
 copy for counter calibration, the 32^3 x 64 fine stencil with 12 and 1
-right-hand sides in each precision class) for rocprofv3 counter runs.
+right-hand sides in each precision class, and with 12 in the form of the MR
+step by the q recursion in the FP32 and FP16 classes) for rocprofv3 counter
+runs.
 """
 from __future__ import annotations
 
@@ -38,7 +40,9 @@ HBM_PEAK_GBPS = 8000.0
 HEADLINE_TARGET = 0.1   # nominal min Re lambda of the headline 32^3 x 64 step
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dslash_c3_12rhs_traffic.txt")
 # kernel name in the counter summary for each precision class of the stencil
-TRAFFIC_KERNEL = {"f64": "dslash_f64_12rhs", "f32": "dslash_f32_12rhs", "f16": "dslash_f16_12rhs"}
+TRAFFIC_KERNEL = {"dslash_f64": "dslash_f64_12rhs", "dslash_f32": "dslash_f32_12rhs",
+                  "dslash_f16": "dslash_f16_12rhs", "dslash_mrq_f32": "dslash_mrq_f32_12rhs",
+                  "dslash_mrq_f16": "dslash_mrq_f16_12rhs"}
 
 # bytes per real of (fine-level spinors, operators) for each precision class;
 # "f16" stores the operators (links, P, D_c) in binary16 and the fine spinors
@@ -185,6 +189,9 @@ def kernel_probe(mgwd, torch, W):
         for nrhs in (12, 1):
             ms = ctx.time_dslash(prec, nrhs, 10)
             print(json.dumps({"probe": f"dslash_{prec}_{nrhs}rhs", "launches": 12, "avg_ms": ms}), flush=True)
+    for prec in ("f32", "f16"):
+        ms = ctx.time_dslash_mrq(prec, 12, 10)
+        print(json.dumps({"probe": f"dslash_mrq_{prec}_12rhs", "launches": 12, "avg_ms": ms}), flush=True)
     ctx.close()
 
 
@@ -482,19 +489,24 @@ def main():
     fine = {k: e for k, e in agg.items() if k.startswith("dslash") and e["launches"]}
     dom = max(fine, key=lambda k: fine[k]["ms"])
     e = fine[dom]
-    prec = dom.split("_")[1]
+    prec = dom.split("_")[-1]
+    mrq = dom.startswith("dslash_mrq")
     avg_us = e["ms"] * 1e3 / e["launches"]
     rhs_per_launch = e["sites"] / e["launches"] / V
     wv, wl = WIDTH[prec]
     # algorithmic bytes per launch: each site's links (two rows) once, and
-    # per right-hand side the input spinor once and the output spinor once
-    bpl = V * (48 * wl + rhs_per_launch * 48 * wv)
-    fpl = V * rhs_per_launch * dslash_flops(True)
+    # per right-hand side the input spinor once and the output spinor once;
+    # the MR step by the q recursion also reads r_k and writes r_{k+1}
+    spinors = 4 if mrq else 2
+    bpl = V * (48 * wl + rhs_per_launch * 24 * spinors * wv)
+    fpl = V * rhs_per_launch * (dslash_flops(True) + (192 if mrq else 0))
     achieved = bpl / avg_us / 1e3
-    traffic = stored_traffic(TRAFFIC_KERNEL[prec], "C3")
+    traffic = stored_traffic(TRAFFIC_KERNEL[dom], "C3")
+    form = "MR step by the q recursion" if mrq else "plain / MR / residual form"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": f"fine Wilson stencil, {prec} class, {rhs_per_launch:.0f} right-hand sides per launch",
+                "kernel": f"fine Wilson stencil, {prec} class, {form}, {rhs_per_launch:.0f} right-hand sides "
+                          "per launch",
                 "avg_launch_us": round(avg_us, 2), "bytes_per_launch": round(bpl),
                 "TFLOPs": round(fpl / avg_us / 1e6, 2),
                 "device_ms_per_step": {k: round(v["ms"] / len(infos), 1) for k, v in agg.items() if v["launches"]}}

@@ -54,6 +54,7 @@ extern "C" {
 
 #define MG_MAX_LEVELS 3
 #define MG_MAX_RHS 16
+#define MG_KERNEL_CLASSES 10 /* kernel timing classes of mg_info_t */
 
 typedef struct {
   int L[4];            /* Lx, Ly, Lz, Lt                                    */
@@ -104,7 +105,13 @@ typedef struct {
   int refine_iters;
   /* Relaxation and cycle ("Formulating an algorithm", "Numerical Results").
    * smoother MG_SMOOTH_MR: pre and post steps of MR (GMRES(1)) with
-   * under-relaxation omega per step.  MG_SMOOTH_GMRES: one GMRES(pre)
+   * under-relaxation omega per step (on the fine level of the FP32 and
+   * FP16 classes, smoothings of 2 to 8 steps run by the q recursion: the
+   * same iterates in exact arithmetic, one fused update pass per
+   * smoothing; the device memory for it, max(pre, post) fine vectors per
+   * right-hand side, is taken at the first solve or cycle in that class;
+   * the FP32 setup relaxation takes it the same way with setup_mr_steps).
+   * MG_SMOOTH_GMRES: one GMRES(pre)
    * cycle before and one GMRES(post) cycle after the coarse correction
    * (pre, post <= 8; 0 = none), each from zero and scaled by omega; the
    * paper's V(0,4) is pre = 0, post = 4.  cycles: cycles of level l+1 per
@@ -159,10 +166,14 @@ typedef struct {
    * their right-hand side had converged.  Classes 6 and 7: the whole-solve
    * coarsest CGNR launches (mg_set_cgnr_persistent) with the FP32 and the
    * FP16-stored operator, one launch per coarsest solve, sites = coarse
-   * sites x stencil applications inside the launches.                     */
-  double kernel_ms[8];
-  int kernel_launches[8];
-  double kernel_sites[8];
+   * sites x stencil applications inside the launches.  Classes 8 and 9:
+   * the fine stencil launches of the MR steps taken by the q recursion
+   * (each also reads the previous residual and writes the next one) in
+   * the FP32 and FP16 classes; class 2 and 4 count the other fine-stencil
+   * launches of those classes.                                            */
+  double kernel_ms[MG_KERNEL_CLASSES];
+  int kernel_launches[MG_KERNEL_CLASSES];
+  double kernel_sites[MG_KERNEL_CLASSES];
   int n_cgnr_fallbacks;         /* whole-solve CGNR launches whose barrier
                                    wait gave up, so that the coarsest solve
                                    was done again by the chunks            */
@@ -365,6 +376,14 @@ int mg_solve(mg_ctx_t *ctx, const void *b, void *x, int nrhs, double tol,
  * HIP events on `stream`.  avg_ms (HOST) receives the mean per launch.    */
 int mg_time_dslash(mg_ctx_t *ctx, mg_prec_t prec, int nrhs, int reps,
                    double *avg_ms, hipStream_t stream);
+
+/* The same for the fine-stencil form of the MR step by the q recursion
+ * (q' = q - a D q and r' = r - a q written, with the MR partial sums of
+ * (q', r')) that the V-cycle of the FP32 and FP16 classes launches, with
+ * a = 0.1 for every right-hand side.  prec: MG_F32 or MG_F16 (MG_ENOTSUP
+ * otherwise).                                                             */
+int mg_time_dslash_mrq(mg_ctx_t *ctx, mg_prec_t prec, int nrhs, int reps,
+                       double *avg_ms, hipStream_t stream);
 
 /* Device time of `reps` coarse-stencil launches of level `level`.        */
 int mg_time_coarse(mg_ctx_t *ctx, int level, mg_prec_t prec, int nrhs,

@@ -23,7 +23,7 @@ MAX_LEVELS = 3
 MAX_RHS = 16
 
 EXPORTED = ["wilson_apply", "wilson_apply_noalloc", "mg_setup", "mg_set_precond_prec", "mg_set_mass", "mg_set_timing", "mg_restrict",
-            "mg_prolong", "coarse_apply", "mg_apply_op", "mg_vcycle", "mg_transfer", "mg_set_transfer_variant", "mg_transfer_variant", "mg_set_coarse_variant", "mg_coarse_variant", "mg_set_cgnr_persistent", "mg_coarse_solve", "mg_solve", "mg_time_dslash", "mg_time_coarse",
+            "mg_prolong", "coarse_apply", "mg_apply_op", "mg_vcycle", "mg_transfer", "mg_set_transfer_variant", "mg_transfer_variant", "mg_set_coarse_variant", "mg_coarse_variant", "mg_set_cgnr_persistent", "mg_coarse_solve", "mg_solve", "mg_time_dslash", "mg_time_dslash_mrq", "mg_time_coarse",
             "mg_destroy", "mg_release_cached_memory", "mg_last_error", "mg_export_maps", "mg_export_P",
             "mg_export_coarse_op", "mg_export_nullvecs", "mg_level_info",
             "ptc_create", "ptc_set_links", "ptc_set_targets", "ptc_forward", "ptc_loss_grad", "ptc_adam",
@@ -72,13 +72,13 @@ class Info(ctypes.Structure):
                 ("n_cgnr_iters", ctypes.c_int),
                 ("n_vcycles", ctypes.c_int),
                 ("t_setup_s", ctypes.c_double), ("t_solve_s", ctypes.c_double),
-                ("kernel_ms", ctypes.c_double * 8),
-                ("kernel_launches", ctypes.c_int * 8),
-                ("kernel_sites", ctypes.c_double * 8),
+                ("kernel_ms", ctypes.c_double * 10),
+                ("kernel_launches", ctypes.c_int * 10),
+                ("kernel_sites", ctypes.c_double * 10),
                 ("n_cgnr_fallbacks", ctypes.c_int)]
 
     KERNELS = ("dslash_f64", "coarse_f64", "dslash_f32", "coarse_f32", "dslash_f16", "coarse_f16", "cgnr_f32",
-               "cgnr_f16")
+               "cgnr_f16", "dslash_mrq_f32", "dslash_mrq_f16")
 
     def as_dict(self, nrhs=1):
         return dict(iters=list(self.iters[:nrhs]), rel_resid=list(self.rel_resid[:nrhs]),
@@ -123,6 +123,7 @@ def lib():
             "mg_coarse_solve": [vp, ci, vp, vp, ci, ctypes.POINTER(ci), vp],
             "mg_solve": [vp, vp, vp, ci, cd, ctypes.POINTER(Info), vp],
             "mg_time_dslash": [vp, ci, ci, ci, ctypes.POINTER(cd), vp],
+            "mg_time_dslash_mrq": [vp, ci, ci, ci, ctypes.POINTER(cd), vp],
             "mg_time_coarse": [vp, ci, ci, ci, ci, ctypes.POINTER(cd), vp],
             "mg_destroy": [vp],
             "mg_release_cached_memory": [ctypes.POINTER(ctypes.c_size_t)],
@@ -398,6 +399,13 @@ class MG:
     def time_dslash(self, prec="f64", nrhs=1, reps=20):
         ms = ctypes.c_double()
         _check(lib().mg_time_dslash(self.ctx, PREC[prec], nrhs, reps, ctypes.byref(ms), _stream()))
+        return ms.value
+
+    def time_dslash_mrq(self, prec="f32", nrhs=12, reps=20):
+        """Mean device time (ms) of the fine stencil in the form the MR steps
+        of the FP32 / FP16-class V-cycle launch (q recursion)."""
+        ms = ctypes.c_double()
+        _check(lib().mg_time_dslash_mrq(self.ctx, PREC[prec], nrhs, reps, ctypes.byref(ms), _stream()))
         return ms.value
 
     def time_coarse(self, level=1, prec="f64", nrhs=1, reps=20):

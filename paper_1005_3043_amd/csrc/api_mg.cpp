@@ -402,6 +402,7 @@ extern "C" int mg_solve(mg_ctx_t *ctx, const void *b, void *x, int nrhs, double 
   MG_TRY(ensure_prec(c, c->prec, st));
   if (c->prec == MG_F64) MG_TRY(ensure_work<double>(c, nrhs));
   else MG_TRY(ensure_work<float>(c, nrhs));
+  MG_TRY(ensure_mrq(c, c->prec, nrhs));
   MG_TRY(ensure_scalars(c, part_need(c, nrhs)));
   c->n_fine = c->n_coarse = c->n_coarse_disp = c->n_cgnr = c->n_vcyc = c->n_cg_fallback = 0;
   for (auto &t : c->tm) t.reset();
@@ -439,7 +440,7 @@ extern "C" int mg_solve(mg_ctx_t *ctx, const void *b, void *x, int nrhs, double 
     info->t_setup_s = c->t_setup;
     info->t_solve_s = t1 - t0;
     if (c->timing) {
-      for (int k = 0; k < 8; ++k) {
+      for (int k = 0; k < MG_KERNEL_CLASSES; ++k) {
         info->kernel_ms[k] = c->tm[k].ms;
         info->kernel_launches[k] = (int)c->tm[k].launches;
         info->kernel_sites[k] = c->tm[k].sites;
@@ -461,6 +462,7 @@ extern "C" int mg_vcycle(mg_ctx_t *ctx, mg_prec_t prec, const void *in, void *ou
   MG_TRY(ensure_prec(c, prec, st));
   if (prec == MG_F64) MG_TRY(ensure_work<double>(c, nrhs));
   else MG_TRY(ensure_work<float>(c, nrhs));
+  MG_TRY(ensure_mrq(c, prec, nrhs));
   MG_TRY(ensure_scalars(c, part_need(c, nrhs)));
   const Level &L0 = c->lev[0];
   DevBuf<double2> a, b;
@@ -582,6 +584,51 @@ template <typename P> int time_dslash_t(mg_ctx *c, int nrhs, int reps, hipEvent_
   HIPK(hipEventSynchronize(e1));
   return MG_OK;
 }
+// The DS_MRQ stencil on the level-0 vectors of the FP32 or FP16 class:
+// q' and r' alternate between two buffer pairs, a = 0.1 for every RHS.
+template <typename P, typename T>
+static int time_mrq_t(mg_ctx *c, int nrhs, int reps, hipEvent_t e0, hipEvent_t e1, hipStream_t st) {
+  using R = typename P::R;
+  using S = typename P::S;
+  Level &L = c->lev[0];
+  const size_t nv = L.vsize() * nrhs, nt = (size_t)site_slots<T>() * L.g.Vpad * nrhs;
+  DevBuf<float2> a;
+  DevBuf<T> q[2], r[2];
+  DevBuf<double> part;
+  DevBuf<double2> alpha;
+  MG_TRY(a.alloc(nv));
+  for (int i = 0; i < 2; ++i) {
+    MG_TRY(q[i].alloc(nt));
+    MG_TRY(r[i].alloc(nt));
+  }
+  MG_TRY(part.alloc((size_t)3 * dslash_partials(L.g, nrhs) * nrhs));
+  MG_TRY(alpha.alloc(nrhs));
+  HIPK((convert<float, double>(a, L.P64, std::min(nv, L.P64.n), st)));
+  if constexpr (std::is_same<T, h16>::value) {
+    HIPK(to_h16<float2>(q[0], a, L.g.Vpad, nrhs, st));
+    HIPK(to_h16<float2>(r[0], a, L.g.Vpad, nrhs, st));
+  } else {
+    HIPK(copy<float>(q[0], a, nv, st));
+    HIPK(copy<float>(r[0], a, nv, st));
+  }
+  HIPK(fill_const<double>(alpha, nrhs, 0.1, st));
+  const S *U = links_of_level<P>(L);
+  auto launch = [&](int i) {
+    MrqArgs<T> mq;
+    mq.rprev = r[i & 1];
+    mq.rout = r[(i + 1) & 1];
+    mq.alpha = alpha;
+    return dslash<R, S, T, T>(L.g, U, L.nl, q[i & 1].p, q[(i + 1) & 1].p, nullptr, 4.0 + c->mass, nrhs, DS_MRQ,
+                              part, st, mq);
+  };
+  for (int i = 0; i < 2; ++i) HIPK(launch(i));
+  HIPK(hipEventRecord(e0, st));
+  for (int i = 0; i < reps; ++i) HIPK(launch(i));
+  HIPK(hipEventRecord(e1, st));
+  HIPK(hipEventSynchronize(e1));
+  return MG_OK;
+}
+
 template <typename P>
 int time_coarse_t(mg_ctx *c, int level, int nrhs, int reps, hipEvent_t e0, hipEvent_t e1, hipStream_t st) {
   using R = typename P::R;
@@ -616,6 +663,26 @@ extern "C" int mg_time_dslash(mg_ctx_t *ctx, mg_prec_t prec, int nrhs, int reps,
   if (prec == MG_F64) rc = time_dslash_t<PF64>(ctx, nrhs, reps, e0, e1, st);
   else if (prec == MG_F32) rc = time_dslash_t<PF32>(ctx, nrhs, reps, e0, e1, st);
   else rc = time_dslash_t<PF16>(ctx, nrhs, reps, e0, e1, st);
+  float ms = 0.f;
+  if (rc == MG_OK) rc = hip_rc(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *avg_ms = ms / reps;
+  return rc;
+}
+
+extern "C" int mg_time_dslash_mrq(mg_ctx_t *ctx, mg_prec_t prec, int nrhs, int reps, double *avg_ms,
+                                  hipStream_t st) {
+  set_error("");
+  if (!ctx || !avg_ms || nrhs < 1 || reps < 1) return bad(MG_EINVAL, "mg_time_dslash_mrq: bad arguments");
+  if (prec != MG_F32 && prec != MG_F16) return bad(MG_ENOTSUP, "mg_time_dslash_mrq: prec must be MG_F32 or MG_F16");
+  MG_TRY(ensure_prec(ctx, prec, st));
+  hipEvent_t e0, e1;
+  HIPK(hipEventCreate(&e0));
+  HIPK(hipEventCreate(&e1));
+  int rc;
+  if (prec == MG_F32) rc = time_mrq_t<PF32, float2>(ctx, nrhs, reps, e0, e1, st);
+  else rc = time_mrq_t<PF16, h16>(ctx, nrhs, reps, e0, e1, st);
   float ms = 0.f;
   if (rc == MG_OK) rc = hip_rc(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
   (void)hipEventDestroy(e0);

@@ -14,6 +14,8 @@
 // complex) or as their first two rows (6 complex, NL = 6); the third row of an
 // SU(3) matrix is the complex conjugate of the cross product of the first two,
 // which trades 42 flops per link for a third less link traffic.
+#include <type_traits>
+
 #include "kernels.h"
 #include "wilson_site.h"
 
@@ -195,6 +197,28 @@ template <typename R> constexpr int dslash_waves() {
   return sizeof(R) == 8 ? MG_DSLASH_WAVES_F64 : MG_DSLASH_WAVES_F32;
 }
 
+// The MR step of the q recursion (DS_MRQ) at one site: res = D q_k and
+// ctr = q_k on entry; q_{k+1} = q_k - a D q_k is written to qout and left in
+// res, r_{k+1} = rprev - a q_k to rout and left in ctr (values as stored).
+template <typename C, typename TO>
+__device__ __forceinline__ void mrq_site(C (&res)[12], C (&ctr)[12], const TO *rprev, TO *qout, TO *rout,
+                                         uint32_t s, double2 ad) {
+  using R = decltype(C::x);
+  const C ma = mk<C>((R)-ad.x, (R)-ad.y);
+  C rp[12];
+  load_site(rp, rprev, s);
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    const C t = res[i];
+    res[i] = cfma(ma, t, ctr[i]);
+    rp[i] = cfma(ma, ctr[i], rp[i]);
+  }
+  store_site<true>(qout, s, res);
+  store_site<true>(rout, s, rp);
+#pragma unroll
+  for (int i = 0; i < 12; ++i) ctr[i] = rp[i];
+}
+
 // One site per thread, one right-hand side per grid row.  Input spinors
 // are stored as TI, the output (and b of the residual mode) as TO: complex
 // FP64 / FP32, or binary16 with a per-site scale (h16).
@@ -202,7 +226,7 @@ template <typename R, int MODE, int NL, typename S, typename TI, typename TO>
 __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash(Geom g, const S *__restrict__ U,
                                                 const TI *__restrict__ in, TO *__restrict__ out,
                                                 const TO *__restrict__ b, R diag,
-                                                double *__restrict__ partials) {
+                                                double *__restrict__ partials, MrqArgs<TO> mq) {
   using C = c_t<R>;
   in += (size_t)blockIdx.y * site_slots<TI>() * g.Vpad;
   const size_t off = (size_t)blockIdx.y * site_slots<TO>() * g.Vpad;
@@ -220,18 +244,20 @@ __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash(Geom g, const
     }
     // the output is not read again by this launch: non-temporal stores leave
     // L2 to the neighbour spinors and links that are
-    store_site<true>(out, s, res);
-    if constexpr (MODE == DS_MR) {
+    if constexpr (MODE == DS_MRQ) mrq_site(res, ctr, mq.rprev + off, out, mq.rout + off, s, mq.alpha[blockIdx.y]);
+    else store_site<true>(out, s, res);
+    if constexpr (MODE == DS_MR || MODE == DS_MRQ) {
 #pragma unroll
       for (int i = 0; i < 12; ++i) {
-        // <q, r> = sum conj(q) r with q = D r (as stored), r = centre
+        // <q, r> = sum conj(q) r with q = D r (as stored), r = centre (DS_MRQ:
+        // q_{k+1} and r_{k+1} as stored)
         red[0] += (double)res[i].x * ctr[i].x + (double)res[i].y * ctr[i].y;
         red[1] += (double)res[i].x * ctr[i].y - (double)res[i].y * ctr[i].x;
         red[2] += (double)res[i].x * res[i].x + (double)res[i].y * res[i].y;
       }
     }
   }
-  if constexpr (MODE == DS_MR) {
+  if constexpr (MODE == DS_MR || MODE == DS_MRQ) {
     __shared__ double lds[16 * 3];
     block_sum<3>(red, lds);
     if (threadIdx.x == 0) {
@@ -255,7 +281,7 @@ __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash(Geom g, const
 template <typename R, int MODE, int NL, typename S, int K, typename TI, typename TO>
 __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash_rb(Geom g, const S *__restrict__ U, const TI *__restrict__ in,
                                                    TO *__restrict__ out, const TO *__restrict__ b, R diag,
-                                                   double *__restrict__ partials, int nrhs) {
+                                                   double *__restrict__ partials, int nrhs, MrqArgs<TO> mq) {
   using C = c_t<R>;
   const int r0 = blockIdx.y * K;
   const uint32_t slot = blockIdx.x, nslot = gridDim.x;
@@ -278,8 +304,11 @@ __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash_rb(Geom g, co
 #pragma unroll
         for (int i = 0; i < 12; ++i) res[k][i] = csub(bb[i], res[k][i]);
       }
-      store_site<true>(out + off, s, res[k]);
-      if constexpr (MODE == DS_MR) {
+      if constexpr (MODE == DS_MRQ)
+        mrq_site(res[k], ctr[k], mq.rprev + off, out + off, mq.rout + off, s, mq.alpha[r0 + k]);
+      else
+        store_site<true>(out + off, s, res[k]);
+      if constexpr (MODE == DS_MR || MODE == DS_MRQ) {
 #pragma unroll
         for (int i = 0; i < 12; ++i) {
           red[k][0] += (double)res[k][i].x * ctr[k][i].x + (double)res[k][i].y * ctr[k][i].y;
@@ -289,7 +318,7 @@ __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash_rb(Geom g, co
       }
     }
   }
-  if constexpr (MODE == DS_MR) {
+  if constexpr (MODE == DS_MR || MODE == DS_MRQ) {
     __shared__ double lds[4 * 3 * K];
     double v[3 * K];
 #pragma unroll
@@ -315,22 +344,29 @@ int dslash_partials(const Geom &g, int) { return dslash_blocks(g); }
 
 template <typename R, int NL, typename S, typename TI, typename TO>
 static hipError_t launch(const Geom &g, const S *U, const TI *in, TO *out, const TO *b, double diag, int nrhs,
-                         DslashMode mode, double *partials, hipStream_t st) {
+                         DslashMode mode, double *partials, hipStream_t st, MrqArgs<TO> mq) {
   if (nrhs > 1) {
     constexpr int K = MRHS_K;
     dim3 grid(dslash_blocks(g), (nrhs + K - 1) / K);
     switch (mode) {
       case DS_PLAIN:
         hipLaunchKernelGGL((k_dslash_rb<R, DS_PLAIN, NL, S, K, TI, TO>), grid, dim3(256), 0, st, g, U, in, out, b,
-                           (R)diag, partials, nrhs);
+                           (R)diag, partials, nrhs, mq);
         break;
       case DS_RESID:
         hipLaunchKernelGGL((k_dslash_rb<R, DS_RESID, NL, S, K, TI, TO>), grid, dim3(256), 0, st, g, U, in, out, b,
-                           (R)diag, partials, nrhs);
+                           (R)diag, partials, nrhs, mq);
         break;
       case DS_MR:
         hipLaunchKernelGGL((k_dslash_rb<R, DS_MR, NL, S, K, TI, TO>), grid, dim3(256), 0, st, g, U, in, out, b,
-                           (R)diag, partials, nrhs);
+                           (R)diag, partials, nrhs, mq);
+        break;
+      case DS_MRQ:
+        if constexpr (std::is_same<TI, TO>::value && sizeof(R) == 4)
+          hipLaunchKernelGGL((k_dslash_rb<R, DS_MRQ, NL, S, K, TI, TO>), grid, dim3(256), 0, st, g, U, in, out, b,
+                             (R)diag, partials, nrhs, mq);
+        else
+          return hipErrorInvalidValue;
         break;
     }
     return hipGetLastError();
@@ -339,15 +375,22 @@ static hipError_t launch(const Geom &g, const S *U, const TI *in, TO *out, const
   switch (mode) {
     case DS_PLAIN:
       hipLaunchKernelGGL((k_dslash<R, DS_PLAIN, NL, S, TI, TO>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag,
-                         partials);
+                         partials, mq);
       break;
     case DS_RESID:
       hipLaunchKernelGGL((k_dslash<R, DS_RESID, NL, S, TI, TO>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag,
-                         partials);
+                         partials, mq);
       break;
     case DS_MR:
       hipLaunchKernelGGL((k_dslash<R, DS_MR, NL, S, TI, TO>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag,
-                         partials);
+                         partials, mq);
+      break;
+    case DS_MRQ:
+      if constexpr (std::is_same<TI, TO>::value && sizeof(R) == 4)
+        hipLaunchKernelGGL((k_dslash<R, DS_MRQ, NL, S, TI, TO>), grid, dim3(256), 0, st, g, U, in, out, b, (R)diag,
+                           partials, mq);
+      else
+        return hipErrorInvalidValue;
       break;
   }
   return hipGetLastError();
@@ -355,9 +398,10 @@ static hipError_t launch(const Geom &g, const S *U, const TI *in, TO *out, const
 
 template <typename R, typename S, typename TI, typename TO>
 hipError_t dslash(const Geom &g, const S *U, int nl, const TI *in, TO *out, const typename same_t<TO>::type *b,
-                  double diag, int nrhs, DslashMode mode, double *partials, hipStream_t st) {
-  if (nl == 6) return launch<R, 6, S>(g, U, in, out, b, diag, nrhs, mode, partials, st);
-  return launch<R, 9, S>(g, U, in, out, b, diag, nrhs, mode, partials, st);
+                  double diag, int nrhs, DslashMode mode, double *partials, hipStream_t st,
+                  MrqArgs<typename same_t<TO>::type> mq) {
+  if (nl == 6) return launch<R, 6, S>(g, U, in, out, b, diag, nrhs, mode, partials, st, mq);
+  return launch<R, 9, S>(g, U, in, out, b, diag, nrhs, mode, partials, st, mq);
 }
 
 // Plain stencil in FP64 arithmetic on FP32-stored input spinors (the
@@ -409,7 +453,7 @@ hipError_t compress_links(const Geom &g, const double2 *U, S *Uc, double *blockm
 #define DSLASH_INST(R, S, TI, TO)                                                                      \
   template hipError_t dslash<R, S, TI, TO>(const Geom &, const S *, int, const TI *, TO *,                        \
                                            const typename same_t<TO>::type *, double, int, DslashMode, double *,   \
-                                           hipStream_t);
+                                           hipStream_t, MrqArgs<typename same_t<TO>::type>);
 DSLASH_INST(double, double2, double2, double2)
 DSLASH_INST(float, float2, float2, float2)
 DSLASH_INST(float, chalf, float2, float2)

@@ -19,11 +19,20 @@ template <typename T> hipError_t pack_gauge(const Geom &g, const double2 *canon,
 
 // ---- dslash.hip: fine Wilson operator on internal spinors (12 components).
 // nl = 9: full links [36 components]; nl = 6: first two rows [24 components].
-enum DslashMode { DS_PLAIN = 0, DS_RESID = 1, DS_MR = 2 };
+enum DslashMode { DS_PLAIN = 0, DS_RESID = 1, DS_MR = 2, DS_MRQ = 3 };
 // out = diag*in - 1/2 hop(in)              (DS_PLAIN)
 // out = b - (diag*in - 1/2 hop(in))        (DS_RESID)
 // out = D in; partials[slot] = (<out,in>, ||out||^2)  (DS_MR, 3 doubles per slot,
 //   dslash_partials(g, nrhs) slots per right-hand side)
+// MR step by the q recursion (DS_MRQ, in = q_k, which is D r_k, TI = TO):
+//   out = q_{k+1} = q_k - a D q_k, rout = r_{k+1} = rprev - a q_k with
+//   a = alpha[rhs] (complex), partials as DS_MR of (q_{k+1}, r_{k+1});
+//   R = float and TI = TO only (hipErrorInvalidValue otherwise).
+template <typename TO> struct MrqArgs {
+  const TO *rprev = nullptr;
+  TO *rout = nullptr;
+  const double2 *alpha = nullptr;
+};
 // R = arithmetic precision of vectors and accumulation, S = link storage
 // (double2, float2 or chalf), TI / TO = storage of the input / output (and
 // b) spinors: c_t<R>, or h16 (binary16 with a per-site scale, 13 slots per
@@ -33,7 +42,8 @@ enum DslashMode { DS_PLAIN = 0, DS_RESID = 1, DS_MR = 2 };
 template <typename T> struct same_t { using type = T; };  // keeps b out of template argument deduction
 template <typename R, typename S, typename TI = c_t<R>, typename TO = c_t<R>>
 hipError_t dslash(const Geom &g, const S *U, int nl, const TI *in, TO *out, const typename same_t<TO>::type *b,
-                  double diag, int nrhs, DslashMode mode, double *partials, hipStream_t st);
+                  double diag, int nrhs, DslashMode mode, double *partials, hipStream_t st,
+                  MrqArgs<typename same_t<TO>::type> mq = {});
 // out = D in (DS_PLAIN) in FP64 arithmetic on FP32-stored input spinors
 hipError_t dslash_in32(const Geom &g, const double2 *U, int nl, const float2 *in, double2 *out, double diag,
                        int nrhs, hipStream_t st);

@@ -145,6 +145,37 @@ template <typename R> int ensure_work(mg_ctx *c, int nrhs) {
 template int ensure_work<double>(mg_ctx *, int);
 template int ensure_work<float>(mg_ctx *, int);
 
+// MR steps of the fine-level smoother taken by the q recursion (0: the
+// smoother does not take it)
+static int mrq_steps(const mg_ctx *c) {
+  if (c->p.smoother != MG_SMOOTH_MR) return 0;
+  const int n = std::max(c->p.pre, c->p.post);
+  return (n >= 2 && n <= MRQ_MAX) ? n : 0;
+}
+
+int ensure_mrq(mg_ctx *c, mg_prec_t prec, int nrhs, int steps) {
+  if (prec != MG_F32 && prec != MG_F16) return MG_OK;
+  if (steps < 0) steps = mrq_steps(c);
+  if (steps < 2 || steps > MRQ_MAX) return MG_OK;
+  Work<float> &w = c->w32;
+  const int i = prec == MG_F16 ? 1 : 0;
+  if (w.mrq_nrhs[i] >= nrhs && w.mrq_steps[i] >= steps) return MG_OK;
+  nrhs = std::max(nrhs, w.mrq_nrhs[i]);
+  steps = std::max(steps, w.mrq_steps[i]);
+  const size_t Vpad = c->lev[0].g.Vpad;
+  if (i == 0) {
+    MG_TRY(w.q2.alloc(12 * Vpad * nrhs));
+    for (int k = 0; k + 1 < steps; ++k) MG_TRY(w.rk[k].alloc(12 * Vpad * nrhs));
+  } else {
+    MG_TRY(w.hq2.alloc(13 * Vpad * nrhs));
+    for (int k = 0; k + 1 < steps; ++k) MG_TRY(w.hrk[k].alloc(13 * Vpad * nrhs));
+  }
+  w.mrq_nrhs[i] = nrhs;
+  w.mrq_steps[i] = steps;
+  clear_graphs(c);  // captured cycles took the other MR path
+  return MG_OK;
+}
+
 // ------------------------------------------------------------ operators
 template <typename P> const typename P::S *links_of(Level &L);
 template <> const double2 *links_of<PF64>(Level &L) { return L.links64(); }
@@ -405,12 +436,14 @@ template <typename P> int transfer_variant(mg_ctx *c, int dir, int nrhs, hipStre
 // out = D in on the fine level with the input stored as TI and the output
 // (and b) as TO (DS_MR: MR partials into c->part; DS_RESID: out = b - D in).
 template <typename P, typename TI, typename TO>
-static int apply_fine(mg_ctx *c, const TI *in, TO *out, int nrhs, DslashMode mode, const TO *b, hipStream_t st) {
+static int apply_fine(mg_ctx *c, const TI *in, TO *out, int nrhs, DslashMode mode, const TO *b, hipStream_t st,
+                      MrqArgs<TO> mq = {}) {
   using R = typename P::R;
   using S = typename P::S;
   Level &L = c->lev[0];
-  TimerScope ts(c, c->tm[tclass<P>(false)], st, (double)L.g.V * nrhs);
-  HIPK((dslash<R, S, TI, TO>(L.g, links_of<P>(L), L.nl, in, out, b, 4.0 + c->mass, nrhs, mode, c->part, st)));
+  const int tc = mode == DS_MRQ ? (P::id == 2 ? 9 : 8) : tclass<P>(false);
+  TimerScope ts(c, c->tm[tc], st, (double)L.g.V * nrhs);
+  HIPK((dslash<R, S, TI, TO>(L.g, links_of<P>(L), L.nl, in, out, b, 4.0 + c->mass, nrhs, mode, c->part, st, mq)));
   c->n_fine += nrhs;
   return MG_OK;
 }
@@ -451,12 +484,59 @@ int apply_A(mg_ctx *c, int l, const vec_t<P> *in, vec_t<P> *out, int nrhs, Dslas
 // entry, or the separate vector r_in when given (read by the first step,
 // which then writes r: no copy of the input).  TR = storage of r and q:
 // vec_t<P>, or h16 on the fine level of the FP16 class.
+//
+// On the fine level of the FP32 and FP16 classes the steps take the q
+// recursion when its buffers are there: with q_0 = A r_0, step k forms
+// q_k = q_{k-1} - a_{k-1} A q_{k-1} and r_k = r_{k-1} - a_{k-1} q_{k-1} in
+// the stencil's epilogue (q_k = A r_k in exact arithmetic), with a_k from
+// the partials of (q_k, r_k); x = sum a_k r_k and the last residual update
+// follow in one pass.  The same iterates as the update after each stencil,
+// without the separate pass over x, r and q per step.
+template <typename P, typename TR>
+static int mr_q(mg_ctx *c, vec_t<P> *x, TR *r, TR *q, int steps, bool accumulate, int nrhs, hipStream_t st,
+                bool keep_r, const TR *r_in) {
+  Work<float> &w = c->w32;
+  const int np = np_mr(c, 0, nrhs);
+  MrqList<TR> rs;
+  TR *qb[2];
+  TR *rk[MRQ_MAX - 1];
+  if constexpr (std::is_same<TR, h16>::value) {
+    qb[1] = w.hq2.p;
+    for (int k = 0; k + 1 < steps; ++k) rk[k] = w.hrk[k].p;
+  } else {
+    qb[1] = w.q2.p;
+    for (int k = 0; k + 1 < steps; ++k) rk[k] = w.rk[k].p;
+  }
+  qb[0] = q;
+  rs.r[0] = r_in ? r_in : r;
+  MG_TRY((apply_fine<P, TR, TR>(c, rs.r[0], qb[0], nrhs, DS_MR, nullptr, st)));
+  HIPK(fin_mr(c->part, np, nrhs, c->p.omega, c->csc, st));
+  for (int k = 1; k < steps; ++k) {
+    MrqArgs<TR> mq;
+    mq.rprev = rs.r[k - 1];
+    mq.rout = rk[k - 1];
+    mq.alpha = c->csc + (size_t)(k - 1) * MG_MAX_RHS;
+    MG_TRY((apply_fine<P, TR, TR>(c, qb[(k - 1) & 1], qb[k & 1], nrhs, DS_MRQ, nullptr, st, mq)));
+    HIPK(fin_mr(c->part, np, nrhs, c->p.omega, c->csc + (size_t)k * MG_MAX_RHS, st));
+    rs.r[k] = rk[k - 1];
+  }
+  HIPK(mrq_combine<TR>(x, r, rs, qb[(steps - 1) & 1], c->lev[0].g, steps, nrhs, c->csc, accumulate ? 0 : 1,
+                       keep_r ? 1 : 0, st));
+  return MG_OK;
+}
+
 template <typename P, typename TR = vec_t<P>>
 int mr(mg_ctx *c, int l, vec_t<P> *x, TR *r, TR *q, int steps, bool accumulate, int nrhs, hipStream_t st,
        bool keep_r = true, const TR *r_in = nullptr) {
   using R = typename P::R;
   Level &L = c->lev[l];
   const size_t n = L.vsize();
+  if constexpr (sizeof(R) == 4) {
+    const int i = std::is_same<TR, h16>::value ? 1 : 0;
+    const Work<float> &w = c->w32;
+    if (l == 0 && steps >= 2 && steps <= w.mrq_steps[i] && nrhs <= w.mrq_nrhs[i])
+      return mr_q<P, TR>(c, x, r, q, steps, accumulate, nrhs, st, keep_r, r_in);
+  }
   if (steps == 0 && !accumulate) HIPK(zero<R>(x, n * nrhs, st));
   for (int k = 0; k < steps; ++k) {
     const TR *src = (k == 0 && r_in) ? r_in : r;
@@ -1271,6 +1351,7 @@ static int relax32(mg_ctx *c, int l, double2 *V, int nv, hipStream_t st) {
     HIPK(store_convert<float2>(L.L32, L.L64, L.L64.n, st));
   }
   const int B = std::min(nv, RELAX32_BATCH);
+  if (l == 0) MG_TRY(ensure_mrq(c, MG_F32, B, c->p.setup_mr_steps));
   DevBuf<float2> v, x, r, q;
   MG_TRY(v.alloc(n * B));
   MG_TRY(x.alloc(n * B));
@@ -1329,6 +1410,13 @@ template <typename R> void release_work(Work<R> &w) {
   w.hr.release();
   w.hq.release();
   w.hrin.release();
+  w.q2.release();
+  w.hq2.release();
+  for (int k = 0; k + 1 < MRQ_MAX; ++k) {
+    w.rk[k].release();
+    w.hrk[k].release();
+  }
+  w.mrq_nrhs[0] = w.mrq_nrhs[1] = 0;
   w.ce.release();
   w.cr.release();
   w.cz.release();
@@ -1437,6 +1525,7 @@ int refine(mg_ctx *c, int l, hipStream_t st_in) {
     if (rp != MG_F64) {
       if ((rc = ensure_prec(c, rp, st)) != MG_OK) break;
       if ((rc = ensure_work<float>(c, G)) != MG_OK) break;
+      if ((rc = ensure_mrq(c, rp, G)) != MG_OK) break;
     }
     // x = v, r = -A v
     double2 *x = X, *r = R;

@@ -13,6 +13,10 @@ size_t np_coarse(const Level &L);
 size_t part_need(mg_ctx *c, int nrhs);
 int ensure_prec(mg_ctx *c, mg_prec_t prec, hipStream_t st);
 template <typename R> int ensure_work(mg_ctx *c, int nrhs);
+// buffers of the fine-level MR by the q recursion for precision class prec
+// (MG_F32 or MG_F16; no-op otherwise) and MR runs of `steps` steps (default:
+// those of the cycle's smoother; no-op when it is not MR)
+int ensure_mrq(mg_ctx *c, mg_prec_t prec, int nrhs, int steps = -1);
 template <typename P>
 int apply_A(mg_ctx *c, int l, const vec_t<P> *in, vec_t<P> *out, int nrhs, DslashMode mode, const vec_t<P> *b,
             hipStream_t st);

@@ -27,6 +27,20 @@ hipError_t mr_update(c_t<R> *x, c_t<R> *r_out, const c_t<R> *r_in, const c_t<R> 
 hipError_t mr_update_h(float2 *x, h16 *r_out, const h16 *r_in, const h16 *q, const Geom &g, int nrhs,
                        const double *part, int np, double omega, double2 *alpha, int first, int upd_r,
                        hipStream_t st);
+// alpha[rhs] = omega <q,r>/<q,q> from the np MR partials per right-hand side
+hipError_t fin_mr(const double *part, int np, int nrhs, double omega, double2 *alpha, hipStream_t st);
+// MR by the q recursion on the fine level g (FP32 x; TR = float2 or h16
+// residuals): after steps n of the stencil in DS_MR then DS_MRQ mode, which
+// produced r_0 .. r_{n-1} (list r) and q_{n-1} (q) with a_k at
+// alpha[k * MG_MAX_RHS + rhs],  x = (first ? 0 : x) + sum_k a_k r_k  and,
+// when upd_r, r_out = r_{n-1} - a_{n-1} q_{n-1} (r_out may be r_0).
+constexpr int MRQ_MAX = 8;
+template <typename TR> struct MrqList {
+  const TR *r[MRQ_MAX];
+};
+template <typename TR>
+hipError_t mrq_combine(float2 *x, TR *r_out, const MrqList<TR> &rs, const TR *q, const Geom &g, int steps, int nrhs,
+                       const double2 *alpha, int first, int upd_r, hipStream_t st);
 template <typename R> hipError_t norm2(const c_t<R> *a, size_t n, int nrhs, double *part, double *out, hipStream_t st);
 // launches the per-block partials of ||a||^2 and returns their count per RHS
 template <typename R> int norm2_partials(const c_t<R> *a, size_t n, int nrhs, double *part, hipStream_t st);
@@ -191,6 +205,12 @@ template <typename R> struct Work {
   // per site; allocated in the FP32 work set only)
   DevBuf<h16> hr, hq, hrin;
   int nrhs = 0;
+  // fine-level MR by the q recursion (FP32 work set): second q and the
+  // residuals r_1 .. r_{n-1}, FP32 ([0]) and binary16 ([1]) storage, for
+  // mrq_nrhs[i] right-hand sides and mrq_steps[i] steps
+  DevBuf<float2> q2, rk[MRQ_MAX - 1];
+  DevBuf<h16> hq2, hrk[MRQ_MAX - 1];
+  int mrq_nrhs[2] = {0, 0}, mrq_steps[2] = {0, 0};
 };
 
 // Device-side timing of one kernel class: (start, stop) event pairs recorded
@@ -338,6 +358,8 @@ struct mg_ctx {
   int gcr_rhs = 0;
   // statistics
   long n_fine = 0, n_coarse = 0, n_coarse_disp = 0, n_cgnr = 0, n_vcyc = 0, n_cg_fallback = 0;
-  mg::EventTimer tm[8];  // (fine, coarse) x (FP64, FP32, FP16 storage), whole-solve CGNR (FP32, FP16)
+  // (fine, coarse) x (FP64, FP32, FP16 storage), whole-solve CGNR (FP32, FP16),
+  // fine stencil of the MR q recursion (FP32, FP16)
+  mg::EventTimer tm[MG_KERNEL_CLASSES];
   double t_setup = 0.0;
 };

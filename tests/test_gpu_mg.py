@@ -163,7 +163,12 @@ def test_vcycle(built, nrhs):
     print(f"{name}: {nrhs} vectors: V-cycle rel err {e:.2e}, CGNR iterations {it} (oracle {it_ref}); "
           f"FP32 cycle {lo['f32']:.1e}, FP16-stored {lo['f16']:.1e}")
     assert e < 1e-10 and it == it_ref
-    assert lo["f32"] < 1e-2 and lo["f16"] < 5e-2
+    # FP32: u = 6e-8 per operation through ~10 stencil applications and the
+    # coarse CGNR; 1e-4 leaves two orders over what these lattices give and
+    # stays below the 1e-3 coarse tolerance that a different CGNR iteration
+    # count would show.  FP16 class: every operator entry and fine spinor
+    # rounded to binary16 (2^-11 = 4.9e-4 relative), so a few units of that.
+    assert lo["f32"] < 1e-4 and lo["f16"] < 2e-3
 
 
 @pytest.mark.parametrize("prec", ["f32", "f16"])
@@ -523,6 +528,62 @@ def test_cycle_variants(cuda, case, smoother, pre, post, cycles):
     assert abs(info["iters"][0] - it_ref) <= 1
 
 
+@pytest.mark.parametrize("pre,post", [(2, 3), (4, 1), (3, 0)])
+def test_vcycle_mr_q_recursion(cuda, pre, post):
+    """The fine-level MR of the FP32 and FP16-class cycles takes the q
+    recursion (q_k = q_{k-1} - a A q_{k-1}, r_k = r_{k-1} - a q_{k-1}, x and
+    the last residual formed after the steps) whenever a smoothing has two
+    or more steps.  Against the oracle's MR (update after every stencil) in
+    the same cycle, with step counts that differ before and after the
+    coarse correction, one that falls back to the update form (1 step) and
+    none: 1 and 3 right-hand sides, bounds as for the standard cycle.  The
+    solve's kernel timing shows the q-recursion launches, and the solve
+    meets 1e-10 within one outer iteration of the oracle's count."""
+    import dataclasses
+
+    import paper_1005_3043_amd as mgwd
+    L, blocks, nv, eps, m, seed = _CYCLE_CASES["2-level 8^4"]
+    U = W.gauge_field(L, eps, seed)
+    starts = W.setup_starts(L, nv[0], seed)
+    key = "2-level 8^4"
+    if key not in _CYCLE_ORACLE:
+        _CYCLE_ORACLE[key] = so.mg_setup(U, m, so.MGParams(blocks=blocks, nv=nv), starts)
+    h = _CYCLE_ORACLE[key]
+    h.p = dataclasses.replace(h.p, smoother="mr", pre=pre, post=post, cycles=1)
+    ctx = mgwd.MG(torch.from_numpy(U).cuda(), m, blocks, nv, [torch.from_numpy(starts).cuda()], max_rhs=3,
+                  pre=pre, post=post)
+    try:
+        errs = {}
+        for nrhs in (1, 3):
+            r = W.gaussian_spinor(L, 21, batch=(nrhs,))
+            zr = np.stack([h.vcycle(r[i], 0) for i in range(nrhs)])
+            for prec in ("f32", "f16"):
+                z, _ = ctx.vcycle(torch.from_numpy(r).cuda(), prec)
+                errs[(prec, nrhs)] = _rel(z.cpu().numpy(), zr)
+        b = W.gaussian_spinor(L, 1)
+        ctx.set_precond_prec("f32")
+        ctx.set_timing(True)
+        x, info, rc = ctx.solve(torch.from_numpy(b).cuda(), 1e-10)
+        ctx.set_timing(False)
+        _, it_ref, _, _ = so.mg_solve(h, b, 1e-10)
+    finally:
+        h.p = dataclasses.replace(h.p, smoother="mr", pre=4, post=4, cycles=1)
+        ctx.close()
+    res = np.linalg.norm(b - wi.apply_D(U, x.cpu().numpy(), m)) / np.linalg.norm(b)
+    nq = info["kernels"]["dslash_mrq_f32"]["launches"]
+    print(f"MR {pre}/{post}: cycle rel errs {errs}; q-recursion launches {nq}; solve {info['iters'][0]} "
+          f"iterations (oracle {it_ref}), true rel resid {res:.2e}")
+    for (prec, _), e in errs.items():
+        assert e < (1e-4 if prec == "f32" else 2e-3)
+    steps_q = sum(k for k in (pre, post) if k >= 2)
+    if steps_q:
+        assert nq > 0
+    else:
+        assert nq == 0
+    assert rc == 0 and res <= 1e-10 * 1.001
+    assert abs(info["iters"][0] - it_ref) <= 1
+
+
 def test_set_mass(cuda):
     """A setup reused at a heavier mass: the GPU's shifted Galerkin operator
     equals the oracle's Galerkin construction at the new mass with the same
@@ -805,7 +866,7 @@ def test_vcycle_graph_matches_eager(cuda, case, nrhs, smoother):
             for k in ("iters", "n_fine_dslash", "n_coarse_apply", "n_cgnr_iters", "n_vcycles"):
                 assert ie[k] == ig[k], (prec, rep, k)
         kk = ig["kernels"]
-        fine = sum(kk[f"dslash_{p}"]["launches"] for p in ("f64", "f32", "f16"))
+        fine = sum(v["launches"] for k, v in kk.items() if k.startswith("dslash"))
         assert fine == ig["n_fine_dslash"] if nrhs == 1 else fine > 0
     ctx_g.close()
     ctx_e.close()
