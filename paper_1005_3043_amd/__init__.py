@@ -258,11 +258,13 @@ class MG:
             lib().mg_destroy(self.ctx)
             self.ctx = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # At interpreter shutdown the HIP runtime (and a profiler's hooks) may
         # already be torn down: a handle still open then is left to process
         # exit, which frees device memory anyway.  close() is the teardown.
-        if sys.is_finalizing():
+        # (The check is bound at definition: module globals such as sys may
+        # already be cleared when this runs.)
+        if _finalizing():
             return
         try:
             self.close()
@@ -489,11 +491,13 @@ class PTC:
             lib().ptc_destroy(self.ctx)
             self.ctx = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # At interpreter shutdown the HIP runtime (and a profiler's hooks) may
         # already be torn down: a handle still open then is left to process
         # exit, which frees device memory anyway.  close() is the teardown.
-        if sys.is_finalizing():
+        # (The check is bound at definition: module globals such as sys may
+        # already be cleared when this runs.)
+        if _finalizing():
             return
         try:
             self.close()
