@@ -271,7 +271,8 @@ __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash(Geom g, const
 
 // Several right-hand sides: K per thread (256-site workgroups), so that
 // each direction's links are loaded once for all K; the workgroups of one
-// group of K right-hand sides cover the lattice, grid.y = groups.  K = 2:
+// group of K right-hand sides cover the lattice, grid.y = groups (K from
+// mrhs_k below).  K = 2:
 // on 32^3 x 64 with 12 right-hand sides, per right-hand side FP64 0.40 ms
 // (one per thread: 0.47 ms), FP32 0.214 ms (0.231), FP16-stored links 0.195
 // ms (0.198); K = 4 is slower in FP32 (0.248 ms: one wave per SIMD), and so
@@ -337,7 +338,15 @@ __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash_rb(Geom g, co
   }
 }
 
-constexpr int MRHS_K = 2;
+// Right-hand sides per thread of the multi-RHS stencil: each link is loaded
+// once per group.  Three for binary16 spinors (about 240 registers, two
+// waves per SIMD as with two; the links are read four times per 12-RHS
+// launch instead of six: 1.82 -> 1.72 ms plain, 2.55 -> 2.43 ms in the MR
+// q-recursion form on 32^3 x 64), two otherwise (FP32 spinors: 2.51 against
+// 2.58 ms with three, 3.40 against 3.38 ms; FP64 spills with three).
+template <typename R, typename TI> constexpr int mrhs_k() {
+  return (sizeof(R) == 4 && std::is_same<TI, h16>::value) ? 3 : 2;
+}
 
 int dslash_blocks(const Geom &g) { return div_up(g.V, 256); }
 int dslash_partials(const Geom &g, int) { return dslash_blocks(g); }
@@ -346,7 +355,7 @@ template <typename R, int NL, typename S, typename TI, typename TO>
 static hipError_t launch(const Geom &g, const S *U, const TI *in, TO *out, const TO *b, double diag, int nrhs,
                          DslashMode mode, double *partials, hipStream_t st, MrqArgs<TO> mq) {
   if (nrhs > 1) {
-    constexpr int K = MRHS_K;
+    constexpr int K = mrhs_k<R, TI>();
     dim3 grid(dslash_blocks(g), (nrhs + K - 1) / K);
     switch (mode) {
       case DS_PLAIN:
