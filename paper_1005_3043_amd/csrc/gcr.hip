@@ -35,9 +35,10 @@ static inline int ggrid(size_t n) {
 
 namespace {
 
-// Per-RHS scalar block inside gs (double2) / nu2 (double) / cnt (int).
+// Per-RHS scalar block inside gs (double2) / nu2 (double) / cnt (int);
+// flag->x != 0: the fused step's a_j waits for the measured ||w^_j||^2.
 struct GS {
-  double2 *gam, *a, *e, *f, *c;
+  double2 *gam, *a, *e, *f, *c, *flag;
   double *nu2;
 };
 __device__ __forceinline__ GS gs_of(double2 *gs, double *nu, int m, int rhs) {
@@ -48,8 +49,12 @@ __device__ __forceinline__ GS gs_of(double2 *gs, double *nu, int m, int rhs) {
   s.e = s.a + m;
   s.c = s.e + m;
   s.f = s.c + m;
+  s.flag = s.f + 1;
   s.nu2 = nu + (size_t)rhs * m;
   return s;
+}
+__device__ __forceinline__ bool gs_flag(const double2 *gs, int m, int rhs) {
+  return gs[(size_t)rhs * gcr_scalars_per_rhs(m) + (size_t)m * m + 3 * (size_t)m + 1].x != 0.0;
 }
 
 template <int W>
@@ -185,7 +190,8 @@ __global__ void k_gcr2_orth_fin(const double *part, int np, int j, int m, double
 // next preconditioner input).
 __global__ __launch_bounds__(256) void k_gcr2_rupd(double2 *r, const double2 *__restrict__ wj, size_t n, int j,
                                                    int m, const double2 *gs, const int *skip, double *part,
-                                                   float2 *r32) {
+                                                   float2 *r32, int flagged_only) {
+  if (flagged_only && !gs_flag(gs, m, blockIdx.y)) return;
   const size_t off = (size_t)blockIdx.y * n;
   double t[1] = {0.0};
   if (!(skip && skip[blockIdx.y])) {
@@ -206,7 +212,8 @@ __global__ __launch_bounds__(256) void k_gcr2_rupd(double2 *r, const double2 *__
 // Vpad sites of the fine level.
 __global__ __launch_bounds__(256) void k_gcr2_rupd_h(double2 *r, const double2 *__restrict__ wj, uint32_t Vpad,
                                                      int j, int m, const double2 *gs, const int *skip, double *part,
-                                                     h16 *r16) {
+                                                     h16 *r16, int flagged_only) {
+  if (flagged_only && !gs_flag(gs, m, blockIdx.y)) return;
   const size_t off = (size_t)blockIdx.y * 12 * Vpad;
   double t[1] = {0.0};
   if (!(skip && skip[blockIdx.y])) {
@@ -230,6 +237,159 @@ __global__ __launch_bounds__(256) void k_gcr2_rupd_h(double2 *r, const double2 *
     }
   }
   block_partials<1>(t, part);
+}
+
+// ---- fused step (1 <= j <= GCR_CHUNK, one chunk of earlier directions)
+// After k_gcr2_dots over all j earlier directions: g_ij, e_i, f as
+// k_gcr2_dots_fin, and a_j from the Pythagorean ||w^_j||^2 unless it has
+// cancelled (then flag).
+constexpr double GCR_CANCEL = 1e-4;
+__global__ void k_gcr2_dots_fin_fused(const double *part, int np, int j, int m, double2 *gs, double *nu, int *cnt,
+                                      const int *skip) {
+  if (skip && skip[blockIdx.y]) return;
+  double t[DW];
+  fin<DW>(part, np, t);
+  if (threadIdx.x != 0) return;
+  GS s = gs_of(gs, nu, m, blockIdx.y);
+  const double ww = t[4 * GCR_CHUNK + 2];
+  double proj = 0.0;
+  double2 g = make_double2(t[4 * GCR_CHUNK], t[4 * GCR_CHUNK + 1]);
+  s.f[0] = g;
+  for (int i = 0; i < j; ++i) {
+    const double nn = s.nu2[i];
+    const double inv = nn > 0.0 ? 1.0 / nn : 0.0;
+    const double2 gi = make_double2(t[4 * i] * inv, t[4 * i + 1] * inv), ei = make_double2(t[4 * i + 2], t[4 * i + 3]);
+    s.gam[(size_t)i * m + j] = gi;
+    s.e[i] = ei;
+    proj += (t[4 * i] * t[4 * i] + t[4 * i + 1] * t[4 * i + 1]) * inv;
+    // conj(g_ij) e_i
+    g.x -= gi.x * ei.x + gi.y * ei.y;
+    g.y -= gi.x * ei.y - gi.y * ei.x;
+  }
+  const double nw2 = ww - proj;
+  if (nw2 > GCR_CANCEL * ww) {
+    s.nu2[j] = nw2;
+    s.a[j] = make_double2(g.x / nw2, g.y / nw2);
+    s.flag[0] = make_double2(0.0, 0.0);
+  } else {
+    s.a[j] = make_double2(0.0, 0.0);
+    s.flag[0] = make_double2(1.0, 0.0);
+  }
+  cnt[blockIdx.y] = j + 1;
+}
+
+// w^_j = w_j - sum_i g_ij w^_i (in place) and, unless flagged, r -= a_j w^_j
+// (r32 = r in FP32 when given); partials ||w^_j||^2, ||r||^2.
+__global__ __launch_bounds__(256) void k_gcr2_orth_rupd(const double2 *__restrict__ Wh, size_t vs, int ni,
+                                                        double2 *wj, double2 *r, size_t n, int j, int m,
+                                                        const double2 *gs, const int *skip, double *part,
+                                                        float2 *r32) {
+  const size_t off = (size_t)blockIdx.y * n;
+  double t[2] = {0.0, 0.0};
+  if (!(skip && skip[blockIdx.y])) {
+    const double2 *b = gs + (size_t)blockIdx.y * gcr_scalars_per_rhs(m);
+    const bool fl = gs_flag(gs, m, blockIdx.y);
+    const double2 a = b[(size_t)m * m + j];
+    const double2 ma = make_double2(-a.x, -a.y);
+    double2 c[GCR_CHUNK];
+#pragma unroll
+    for (int i = 0; i < GCR_CHUNK; ++i) {
+      const double2 v = i < ni ? b[(size_t)i * m + j] : make_double2(0.0, 0.0);
+      c[i] = make_double2(-v.x, -v.y);
+    }
+    GSTRIDE(idx, n) {
+      double2 w = wj[off + idx];
+#pragma unroll
+      for (int i = 0; i < GCR_CHUNK; ++i)
+        if (i < ni) w = cfma(c[i], Wh[(size_t)i * vs + off + idx], w);
+      wj[off + idx] = w;
+      t[0] += w.x * w.x + w.y * w.y;
+      if (!fl) {
+        const double2 rv = cfma(ma, w, r[off + idx]);
+        r[off + idx] = rv;
+        if (r32) r32[off + idx] = make_float2((float)rv.x, (float)rv.y);
+        t[1] += rv.x * rv.x + rv.y * rv.y;
+      }
+    }
+  }
+  block_partials<2>(t, part);
+}
+
+// The same with the next preconditioner input in binary16 with a per-site
+// scale (r16): one site per thread over the Vpad sites of the fine level.
+__global__ __launch_bounds__(256) void k_gcr2_orth_rupd_h(const double2 *__restrict__ Wh, size_t vs, int ni,
+                                                          double2 *wj, double2 *r, uint32_t Vpad, int j, int m,
+                                                          const double2 *gs, const int *skip, double *part,
+                                                          h16 *r16) {
+  const size_t off = (size_t)blockIdx.y * 12 * Vpad;
+  double t[2] = {0.0, 0.0};
+  if (!(skip && skip[blockIdx.y])) {
+    const double2 *b = gs + (size_t)blockIdx.y * gcr_scalars_per_rhs(m);
+    const bool fl = gs_flag(gs, m, blockIdx.y);
+    const double2 a = b[(size_t)m * m + j];
+    const double2 ma = make_double2(-a.x, -a.y);
+    double2 c[GCR_CHUNK];
+#pragma unroll
+    for (int i = 0; i < GCR_CHUNK; ++i) {
+      const double2 v = i < ni ? b[(size_t)i * m + j] : make_double2(0.0, 0.0);
+      c[i] = make_double2(-v.x, -v.y);
+    }
+    h16 *o16 = r16 + (size_t)blockIdx.y * 13 * Vpad;
+    GSTRIDE(i, Vpad) {
+      const uint32_t s = (uint32_t)i;
+      double2 w[12];
+      load_site(w, wj + off, s);
+#pragma unroll
+      for (int q = 0; q < GCR_CHUNK; ++q) {
+        if (q < ni) {
+          double2 h[12];
+          load_site(h, Wh + (size_t)q * vs + off, s);
+#pragma unroll
+          for (int e = 0; e < 12; ++e) w[e] = cfma(c[q], h[e], w[e]);
+        }
+      }
+      store_site(wj + off, s, w);
+#pragma unroll
+      for (int e = 0; e < 12; ++e) t[0] += w[e].x * w[e].x + w[e].y * w[e].y;
+      if (!fl) {
+        double2 rv[12];
+        float2 f[12];
+        load_site(rv, r + off, s);
+#pragma unroll
+        for (int e = 0; e < 12; ++e) {
+          rv[e] = cfma(ma, w[e], rv[e]);
+          t[1] += rv[e].x * rv[e].x + rv[e].y * rv[e].y;
+          f[e] = make_float2((float)rv[e].x, (float)rv[e].y);
+        }
+        store_site(r + off, s, rv);
+        store_site(o16, s, f);
+      }
+    }
+  }
+  block_partials<2>(t, part);
+}
+
+// nu2[j] = measured ||w^_j||^2; unflagged: rr = ||r||^2; flagged: a_j from
+// the measured ||w^_j||^2 (the residual follows in a second pass).
+__global__ void k_gcr2_orth_rupd_fin(const double *part, int np, int j, int m, double2 *gs, double *nu, double *rr,
+                                     const int *skip) {
+  if (skip && skip[blockIdx.y]) return;
+  double t[2];
+  fin<2>(part, np, t);
+  if (threadIdx.x != 0) return;
+  GS s = gs_of(gs, nu, m, blockIdx.y);
+  s.nu2[j] = t[0];
+  if (s.flag[0].x == 0.0) {
+    rr[blockIdx.y] = t[1];
+    return;
+  }
+  double2 g = s.f[0];
+  for (int i = 0; i < j; ++i) {
+    const double2 gi = s.gam[(size_t)i * m + j], ei = s.e[i];
+    g.x -= gi.x * ei.x + gi.y * ei.y;
+    g.y -= gi.x * ei.y - gi.y * ei.x;
+  }
+  s.a[j] = t[0] > 0.0 ? make_double2(g.x / t[0], g.y / t[0]) : make_double2(0.0, 0.0);
 }
 
 // c = T^{-1} a over the cnt steps of the cycle (one thread per right-hand side).
@@ -270,8 +430,9 @@ __global__ __launch_bounds__(256) void k_gcr2_xupd(double2 *x, const TZ *__restr
   }
 }
 
-__global__ void k_gcr2_fin1(const double *part, int np, double *out, const int *skip) {
+__global__ void k_gcr2_fin1(const double *part, int np, double *out, const int *skip, const double2 *gs, int m) {
   if (skip && skip[blockIdx.y]) return;
+  if (gs && !gs_flag(gs, m, blockIdx.y)) return;
   double t[1];
   fin<1>(part, np, t);
   if (threadIdx.x == 0) out[blockIdx.y] = t[0];
@@ -310,14 +471,46 @@ hipError_t gcr2_residual(double2 *r, const double2 *Wh, size_t vs, int j, int m,
     const uint32_t Vpad = (uint32_t)(n / 12);
     const int g = ggrid(Vpad);
     hipLaunchKernelGGL(k_gcr2_rupd_h, dim3(g, nrhs), dim3(256), 0, st, r, Wh + (size_t)j * vs, Vpad, j, m, gs, skip,
-                       part, r16);
-    hipLaunchKernelGGL(k_gcr2_fin1, dim3(1, nrhs), dim3(256), 0, st, part, g, rr, skip);
+                       part, r16, 0);
+    hipLaunchKernelGGL(k_gcr2_fin1, dim3(1, nrhs), dim3(256), 0, st, part, g, rr, skip, nullptr, m);
     return hipGetLastError();
   }
   const int g = ggrid(n);
   hipLaunchKernelGGL(k_gcr2_rupd, dim3(g, nrhs), dim3(256), 0, st, r, Wh + (size_t)j * vs, n, j, m, gs, skip,
-                     part, r32);
-  hipLaunchKernelGGL(k_gcr2_fin1, dim3(1, nrhs), dim3(256), 0, st, part, g, rr, skip);
+                     part, r32, 0);
+  hipLaunchKernelGGL(k_gcr2_fin1, dim3(1, nrhs), dim3(256), 0, st, part, g, rr, skip, nullptr, m);
+  return hipGetLastError();
+}
+
+hipError_t gcr2_step_residual(double2 *Wh, size_t vs, int j, int m, double2 *r, size_t n, int nrhs, double2 *gs,
+                              double *nu, int *cnt, const int *skip, double *part, double *rr, float2 *r32,
+                              h16 *r16, hipStream_t st) {
+  if (j < 1 || j > GCR_CHUNK) {
+    hipError_t e = gcr2_step(Wh, vs, j, m, r, n, nrhs, gs, nu, cnt, skip, part, st);
+    if (e != hipSuccess) return e;
+    return gcr2_residual(r, Wh, vs, j, m, n, nrhs, gs, skip, part, rr, r32, r16, st);
+  }
+  const int g = ggrid(n);
+  double2 *wj = Wh + (size_t)j * vs;
+  hipLaunchKernelGGL(k_gcr2_dots, dim3(g, nrhs), dim3(256), 0, st, Wh, vs, j, wj, r, n, 1, skip, part);
+  hipLaunchKernelGGL(k_gcr2_dots_fin_fused, dim3(1, nrhs), dim3(256), 0, st, part, g, j, m, gs, nu, cnt, skip);
+  if (r16) {
+    const uint32_t Vpad = (uint32_t)(n / 12);
+    const int gh = ggrid(Vpad);
+    hipLaunchKernelGGL(k_gcr2_orth_rupd_h, dim3(gh, nrhs), dim3(256), 0, st, Wh, vs, j, wj, r, Vpad, j, m,
+                       (const double2 *)gs, skip, part, r16);
+    hipLaunchKernelGGL(k_gcr2_orth_rupd_fin, dim3(1, nrhs), dim3(256), 0, st, part, gh, j, m, gs, nu, rr, skip);
+    hipLaunchKernelGGL(k_gcr2_rupd_h, dim3(gh, nrhs), dim3(256), 0, st, r, wj, Vpad, j, m, (const double2 *)gs, skip,
+                       part, r16, 1);
+    hipLaunchKernelGGL(k_gcr2_fin1, dim3(1, nrhs), dim3(256), 0, st, part, gh, rr, skip, (const double2 *)gs, m);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_gcr2_orth_rupd, dim3(g, nrhs), dim3(256), 0, st, Wh, vs, j, wj, r, n, j, m,
+                     (const double2 *)gs, skip, part, r32);
+  hipLaunchKernelGGL(k_gcr2_orth_rupd_fin, dim3(1, nrhs), dim3(256), 0, st, part, g, j, m, gs, nu, rr, skip);
+  hipLaunchKernelGGL(k_gcr2_rupd, dim3(g, nrhs), dim3(256), 0, st, r, wj, n, j, m, (const double2 *)gs, skip, part,
+                     r32, 1);
+  hipLaunchKernelGGL(k_gcr2_fin1, dim3(1, nrhs), dim3(256), 0, st, part, g, rr, skip, (const double2 *)gs, m);
   return hipGetLastError();
 }
 

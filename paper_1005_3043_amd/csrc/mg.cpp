@@ -494,7 +494,7 @@ int apply_A(mg_ctx *c, int l, const vec_t<P> *in, vec_t<P> *out, int nrhs, Dslas
 // without the separate pass over x, r and q per step.
 template <typename P, typename TR>
 static int mr_q(mg_ctx *c, vec_t<P> *x, TR *r, TR *q, int steps, bool accumulate, int nrhs, hipStream_t st,
-                bool keep_r, const TR *r_in) {
+                bool keep_r, const TR *r_in, float xs = 1.f) {
   Work<float> &w = c->w32;
   const int np = np_mr(c, 0, nrhs);
   MrqList<TR> rs;
@@ -521,8 +521,16 @@ static int mr_q(mg_ctx *c, vec_t<P> *x, TR *r, TR *q, int steps, bool accumulate
     rs.r[k] = rk[k - 1];
   }
   HIPK(mrq_combine<TR>(x, r, rs, qb[(steps - 1) & 1], c->lev[0].g, steps, nrhs, c->csc, accumulate ? 0 : 1,
-                       keep_r ? 1 : 0, st));
+                       keep_r ? 1 : 0, xs, st));
   return MG_OK;
+}
+
+// Whether the fine-level MR of `steps` steps on nrhs vectors takes the q
+// recursion (TR: storage of r and q).
+template <typename TR> static bool mrq_ready(const mg_ctx *c, int l, int steps, int nrhs) {
+  const int i = std::is_same<TR, h16>::value ? 1 : 0;
+  const Work<float> &w = c->w32;
+  return l == 0 && steps >= 2 && steps <= w.mrq_steps[i] && nrhs <= w.mrq_nrhs[i];
 }
 
 template <typename P, typename TR = vec_t<P>>
@@ -532,10 +540,7 @@ int mr(mg_ctx *c, int l, vec_t<P> *x, TR *r, TR *q, int steps, bool accumulate, 
   Level &L = c->lev[l];
   const size_t n = L.vsize();
   if constexpr (sizeof(R) == 4) {
-    const int i = std::is_same<TR, h16>::value ? 1 : 0;
-    const Work<float> &w = c->w32;
-    if (l == 0 && steps >= 2 && steps <= w.mrq_steps[i] && nrhs <= w.mrq_nrhs[i])
-      return mr_q<P, TR>(c, x, r, q, steps, accumulate, nrhs, st, keep_r, r_in);
+    if (mrq_ready<TR>(c, l, steps, nrhs)) return mr_q<P, TR>(c, x, r, q, steps, accumulate, nrhs, st, keep_r, r_in);
   }
   if (steps == 0 && !accumulate) HIPK(zero<R>(x, n * nrhs, st));
   for (int k = 0; k < steps; ++k) {
@@ -1250,8 +1255,7 @@ static int fgcr_t(mg_ctx *c, const double2 *b, double2 *x, int nrhs, double tol,
                                         DS_PLAIN, nullptr, st)));
       }
       c->n_fine += nrhs;
-      HIPK(gcr2_step(W, nn, j, m, r, n, nrhs, c->gsc, c->gnu, c->gcnt, skip, c->part, st));
-      HIPK(gcr2_residual(r, W, nn, j, m, n, nrhs, c->gsc, skip, c->part, rr, r32, r16, st));
+      HIPK(gcr2_step_residual(W, nn, j, m, r, n, nrhs, c->gsc, c->gnu, c->gcnt, skip, c->part, rr, r32, r16, st));
       used = j + 1;
       HIPK(hipMemcpyAsync(c->h_rr, rr, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
       HIPK(hipStreamSynchronize(st));
@@ -1357,10 +1361,28 @@ static int relax32(mg_ctx *c, int l, double2 *V, int nv, hipStream_t st) {
   MG_TRY(x.alloc(n * B));
   MG_TRY(r.alloc(n * B));
   MG_TRY(q.alloc(n * B));
+  const int steps = c->p.setup_mr_steps;
   for (int k0 = 0; k0 < nv; k0 += B) {
     const int nb = std::min(B, nv - k0);
     double2 *Vk = V + (size_t)k0 * n;
     HIPK((convert<float, double>(v, Vk, n * nb, st)));
+    if (mrq_ready<float2>(c, l, steps, nb) && c->p.setup_rounds > 0) {
+      // The combine pass of the q recursion subtracts the MR solution from v
+      // in place, and the normalisation, which only scales the direction the
+      // rounds produce (MR from zero is scale-covariant), is done once after
+      // the last round.  The residual A v is recomputed every round: the
+      // recursive one the MR steps leave (A v - A x) loses its relative
+      // accuracy as the rounds shrink it (measured: 2.5e-4 instead of 7e-7
+      // from the FP64 relaxation after five rounds).
+      for (int round = 0; round < c->p.setup_rounds; ++round) {
+        MG_TRY(apply_A<PF32>(c, l, v, r, nb, DS_PLAIN, nullptr, st));
+        MG_TRY((mr_q<PF32, float2>(c, v, r.p, q.p, steps, true, nb, st, false, nullptr, -1.f)));
+      }
+      HIPK(norm2<float>(v, n, nb, c->part, c->dsc, st));
+      HIPK(scale_rsqrt<float>(v, n, nb, c->dsc, st));
+      HIPK((convert<double, float>(Vk, v, n * nb, st)));
+      continue;
+    }
     for (int round = 0; round < c->p.setup_rounds; ++round) {
       MG_TRY(apply_A<PF32>(c, l, v, r, nb, DS_PLAIN, nullptr, st));
       MG_TRY(mr<PF32>(c, l, x.p, r.p, q.p, c->p.setup_mr_steps, false, nb, st, false));

@@ -11,8 +11,9 @@ constexpr int RED_BLOCKS = 1024;  // fixed grid of generic reductions
 constexpr int CG_NS = 8;          // CGNR scalars per right-hand side
 constexpr int GCR_CHUNK = 8;      // FGCR directions orthogonalised against per pass
 // double2 scalars per right-hand side of the deferred-update FGCR (gcr.hip)
-// with restart length m: g_ij (m x m), a, e, c (m each), f
-__host__ __device__ constexpr size_t gcr_scalars_per_rhs(int m) { return (size_t)m * m + 3 * (size_t)m + 1; }
+// with restart length m: g_ij (m x m), a, e, c (m each), f, and a flag (the
+// fused step's fallback, see gcr2_step_residual)
+__host__ __device__ constexpr size_t gcr_scalars_per_rhs(int m) { return (size_t)m * m + 3 * (size_t)m + 2; }
 
 // ---- solver_kernels.hip
 // x = (first ? 0 : x) + alpha r_in and, when upd_r, r_out = r_in - alpha q
@@ -32,15 +33,16 @@ hipError_t fin_mr(const double *part, int np, int nrhs, double omega, double2 *a
 // MR by the q recursion on the fine level g (FP32 x; TR = float2 or h16
 // residuals): after steps n of the stencil in DS_MR then DS_MRQ mode, which
 // produced r_0 .. r_{n-1} (list r) and q_{n-1} (q) with a_k at
-// alpha[k * MG_MAX_RHS + rhs],  x = (first ? 0 : x) + sum_k a_k r_k  and,
-// when upd_r, r_out = r_{n-1} - a_{n-1} q_{n-1} (r_out may be r_0).
+// alpha[k * MG_MAX_RHS + rhs],  x = (first ? 0 : x) + xs sum_k a_k r_k  and,
+// when upd_r, r_out = r_{n-1} - a_{n-1} q_{n-1} (r_out may be r_0); xs = 1,
+// or -1 to subtract the MR solution from x.
 constexpr int MRQ_MAX = 8;
 template <typename TR> struct MrqList {
   const TR *r[MRQ_MAX];
 };
 template <typename TR>
 hipError_t mrq_combine(float2 *x, TR *r_out, const MrqList<TR> &rs, const TR *q, const Geom &g, int steps, int nrhs,
-                       const double2 *alpha, int first, int upd_r, hipStream_t st);
+                       const double2 *alpha, int first, int upd_r, float xs, hipStream_t st);
 template <typename R> hipError_t norm2(const c_t<R> *a, size_t n, int nrhs, double *part, double *out, hipStream_t st);
 // launches the per-block partials of ||a||^2 and returns their count per RHS
 template <typename R> int norm2_partials(const c_t<R> *a, size_t n, int nrhs, double *part, hipStream_t st);
@@ -72,6 +74,16 @@ hipError_t gcr2_step(double2 *Wh, size_t vs, int j, int m, const double2 *r_in, 
 hipError_t gcr2_residual(double2 *r, const double2 *Wh, size_t vs, int j, int m, size_t n, int nrhs,
                          const double2 *gs, const int *skip, double *part, double *rr, float2 *r32, h16 *r16,
                          hipStream_t st);
+// gcr2_step followed by gcr2_residual, with the orthogonalisation of w_j and
+// the residual update in one pass over the vectors for 1 <= j <= GCR_CHUNK:
+// a_j is taken before the pass from ||w^_j||^2 = ||w_j||^2 - sum_i
+// |<w^_i, w_j>|^2 / ||w^_i||^2 (exact for the classical Gram-Schmidt step),
+// unless that difference has cancelled to below 1e-4 ||w_j||^2; then the
+// pass only orthogonalises and a second one updates r with a_j from the
+// measured ||w^_j||^2 (per right-hand side).
+hipError_t gcr2_step_residual(double2 *Wh, size_t vs, int j, int m, double2 *r, size_t n, int nrhs, double2 *gs,
+                              double *nu, int *cnt, const int *skip, double *part, double *rr, float2 *r32,
+                              h16 *r16, hipStream_t st);
 template <typename TZ>
 hipError_t gcr2_solution(double2 *x, const TZ *Z, size_t vs, int kmax, int m, size_t n, int nrhs, double2 *gs,
                          double *nu, const int *cnt, hipStream_t st);

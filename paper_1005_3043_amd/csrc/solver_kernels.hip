@@ -143,14 +143,14 @@ __global__ __launch_bounds__(256) void k_mr_update_h(float2 *x, h16 *r_out, cons
   }
 }
 
-// MR by the q recursion: x = (first ? 0 : x) + sum_k a_k r_k, and r_out =
+// MR by the q recursion: x = (first ? 0 : x) + xs sum_k a_k r_k, and r_out =
 // r_{n-1} - a_{n-1} q when upd_r.  One site per thread (the binary16 scale of
 // r_out needs the whole site); the step loop is unrolled to MRQ_MAX so that
 // the list of residuals stays in kernel arguments.
 template <typename TR>
 __global__ __launch_bounds__(256) void k_mrq_combine(float2 *x, TR *r_out, MrqList<TR> rs, const TR *q, uint32_t V,
                                                      uint32_t Vpad, int steps, const double2 *alpha, int first,
-                                                     int upd_r) {
+                                                     int upd_r, float xs) {
   x += (size_t)blockIdx.y * 12 * Vpad;
   const size_t off = (size_t)blockIdx.y * site_slots<TR>() * Vpad;
   GSTRIDE(i, V) {
@@ -168,9 +168,10 @@ __global__ __launch_bounds__(256) void k_mrq_combine(float2 *x, TR *r_out, MrqLi
       if (k < steps) {
         const double2 ad = alpha[(size_t)k * MG_MAX_RHS + blockIdx.y];
         a = make_float2((float)ad.x, (float)ad.y);
+        const float2 ax = make_float2(xs * a.x, xs * a.y);
         load_site(rv, rs.r[k] + off, s);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) xv[c] = cfma(a, rv[c], xv[c]);
+        for (int c = 0; c < 12; ++c) xv[c] = cfma(ax, rv[c], xv[c]);
       }
     }
     store_site(x, s, xv);
@@ -483,16 +484,16 @@ hipError_t fin_mr(const double *part, int np, int nrhs, double omega, double2 *a
 
 template <typename TR>
 hipError_t mrq_combine(float2 *x, TR *r_out, const MrqList<TR> &rs, const TR *q, const Geom &g, int steps, int nrhs,
-                       const double2 *alpha, int first, int upd_r, hipStream_t st) {
+                       const double2 *alpha, int first, int upd_r, float xs, hipStream_t st) {
   if (steps < 1 || steps > MRQ_MAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_mrq_combine<TR>, dim3(sgrid(g.V), nrhs), dim3(256), 0, st, x, r_out, rs, q, g.V, g.Vpad,
-                     steps, alpha, first, upd_r);
+                     steps, alpha, first, upd_r, xs);
   return hipGetLastError();
 }
 template hipError_t mrq_combine<float2>(float2 *, float2 *, const MrqList<float2> &, const float2 *, const Geom &,
-                                        int, int, const double2 *, int, int, hipStream_t);
+                                        int, int, const double2 *, int, int, float, hipStream_t);
 template hipError_t mrq_combine<h16>(float2 *, h16 *, const MrqList<h16> &, const h16 *, const Geom &, int, int,
-                                     const double2 *, int, int, hipStream_t);
+                                     const double2 *, int, int, float, hipStream_t);
 
 template <typename R>
 hipError_t norm2(const c_t<R> *a, size_t n, int nrhs, double *part, double *out, hipStream_t st) {
