@@ -346,6 +346,18 @@ int mg_coarse_variant(mg_ctx_t *ctx, int level, mg_prec_t prec, int nrhs,
  * MG_EINVAL on a NULL context or on < 0.                                   */
 int mg_set_cgnr_persistent(mg_ctx_t *ctx, int on);
 
+/* Outer flexible GCR ("Formulating an algorithm"): mode 1 (default) forms
+ * the step length a_j = <w^_j, r> / ||w^_j||^2 before the orthogonalisation
+ * of w_j, with ||w^_j||^2 = ||w_j||^2 - sum_i |<w^_i, w_j>|^2 / ||w^_i||^2
+ * (exact for the classical Gram-Schmidt step), and updates the residual in
+ * the same pass over the vectors; where that difference has cancelled below
+ * 1e-4 ||w_j||^2 the pass only orthogonalises and a second pass updates the
+ * residual with a_j from the measured ||w^_j||^2.  Mode 0: orthogonalisation
+ * and residual update as two passes always; mode 2: the fused pass with
+ * every step taking the second pass (exercises that path).  The iterates
+ * agree to rounding.  MG_EINVAL on a NULL context or a mode outside 0..2. */
+int mg_set_gcr_fusion(mg_ctx_t *ctx, int mode);
+
 /* The coarsest-level solve of the cycle ("Numerical Results": CG on the
  * normal equations D_c^dag D_c e = D_c^dag b to ||b - D_c e|| <=
  * coarse_tol ||b||, at most coarse_maxiter iterations, D_c^dag = sigma_3 D_c

@@ -23,7 +23,7 @@ MAX_LEVELS = 3
 MAX_RHS = 16
 
 EXPORTED = ["wilson_apply", "wilson_apply_noalloc", "mg_setup", "mg_set_precond_prec", "mg_set_mass", "mg_set_timing", "mg_restrict",
-            "mg_prolong", "coarse_apply", "mg_apply_op", "mg_vcycle", "mg_transfer", "mg_set_transfer_variant", "mg_transfer_variant", "mg_set_coarse_variant", "mg_coarse_variant", "mg_set_cgnr_persistent", "mg_coarse_solve", "mg_solve", "mg_time_dslash", "mg_time_dslash_mrq", "mg_time_coarse",
+            "mg_prolong", "coarse_apply", "mg_apply_op", "mg_vcycle", "mg_transfer", "mg_set_transfer_variant", "mg_transfer_variant", "mg_set_coarse_variant", "mg_coarse_variant", "mg_set_cgnr_persistent", "mg_set_gcr_fusion", "mg_coarse_solve", "mg_solve", "mg_time_dslash", "mg_time_dslash_mrq", "mg_time_coarse",
             "mg_destroy", "mg_release_cached_memory", "mg_last_error", "mg_export_maps", "mg_export_P",
             "mg_export_coarse_op", "mg_export_nullvecs", "mg_level_info",
             "ptc_create", "ptc_set_links", "ptc_set_targets", "ptc_forward", "ptc_loss_grad", "ptc_adam",
@@ -119,6 +119,7 @@ def lib():
             "mg_transfer_variant": [vp, ci, ci, ctypes.POINTER(ci), ctypes.POINTER(ci), ctypes.POINTER(cd)],
             "mg_set_coarse_variant": [vp, ci],
             "mg_set_cgnr_persistent": [vp, ci],
+            "mg_set_gcr_fusion": [vp, ci],
             "mg_coarse_variant": [vp, ci, ci, ci, ctypes.POINTER(ci), ctypes.POINTER(cd)],
             "mg_coarse_solve": [vp, ci, vp, vp, ci, ctypes.POINTER(ci), vp],
             "mg_solve": [vp, vp, vp, ci, cd, ctypes.POINTER(Info), vp],
@@ -365,6 +366,12 @@ class MG:
         """Force the coarse-stencil kernel (0 per-RHS, 1/2/4 matrix-core GEMM
         with that K split) or restore autotuning (-1)."""
         _check(lib().mg_set_coarse_variant(self.ctx, int(variant)))
+
+    def set_gcr_fusion(self, mode: int):
+        """Outer FGCR step: 1 (default) orthogonalisation and residual update
+        in one pass, 0 two passes, 2 the fused pass with every step taking
+        the second pass (the fallback where the norm estimate cancels)."""
+        _check(lib().mg_set_gcr_fusion(self.ctx, int(mode)))
 
     def set_cgnr_persistent(self, on, polls=None):
         """Single-RHS coarsest CGNR as one cooperative launch (True, default)

@@ -211,6 +211,13 @@ extern "C" int mg_set_cgnr_persistent(mg_ctx_t *ctx, int on) {
   return MG_OK;
 }
 
+extern "C" int mg_set_gcr_fusion(mg_ctx_t *ctx, int mode) {
+  if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
+  if (mode < 0 || mode > 2) return bad(MG_EINVAL, "mg_set_gcr_fusion: mode must be 0, 1 or 2");
+  ctx->gcr_fuse = mode;
+  return MG_OK;
+}
+
 extern "C" int mg_set_coarse_variant(mg_ctx_t *ctx, int variant) {
   if (!ctx) return bad(MG_EINVAL, "ctx is NULL");
   if (variant != -1 && variant != 0 && variant != 1 && variant != 2 && variant != 4 && variant != 9 &&

@@ -245,7 +245,7 @@ __global__ __launch_bounds__(256) void k_gcr2_rupd_h(double2 *r, const double2 *
 // cancelled (then flag).
 constexpr double GCR_CANCEL = 1e-4;
 __global__ void k_gcr2_dots_fin_fused(const double *part, int np, int j, int m, double2 *gs, double *nu, int *cnt,
-                                      const int *skip) {
+                                      const int *skip, double cancel) {
   if (skip && skip[blockIdx.y]) return;
   double t[DW];
   fin<DW>(part, np, t);
@@ -267,7 +267,7 @@ __global__ void k_gcr2_dots_fin_fused(const double *part, int np, int j, int m, 
     g.y -= gi.x * ei.y - gi.y * ei.x;
   }
   const double nw2 = ww - proj;
-  if (nw2 > GCR_CANCEL * ww) {
+  if (nw2 > cancel * ww) {
     s.nu2[j] = nw2;
     s.a[j] = make_double2(g.x / nw2, g.y / nw2);
     s.flag[0] = make_double2(0.0, 0.0);
@@ -484,8 +484,8 @@ hipError_t gcr2_residual(double2 *r, const double2 *Wh, size_t vs, int j, int m,
 
 hipError_t gcr2_step_residual(double2 *Wh, size_t vs, int j, int m, double2 *r, size_t n, int nrhs, double2 *gs,
                               double *nu, int *cnt, const int *skip, double *part, double *rr, float2 *r32,
-                              h16 *r16, hipStream_t st) {
-  if (j < 1 || j > GCR_CHUNK) {
+                              h16 *r16, int mode, hipStream_t st) {
+  if (mode == 0 || j < 1 || j > GCR_CHUNK) {
     hipError_t e = gcr2_step(Wh, vs, j, m, r, n, nrhs, gs, nu, cnt, skip, part, st);
     if (e != hipSuccess) return e;
     return gcr2_residual(r, Wh, vs, j, m, n, nrhs, gs, skip, part, rr, r32, r16, st);
@@ -493,7 +493,10 @@ hipError_t gcr2_step_residual(double2 *Wh, size_t vs, int j, int m, double2 *r, 
   const int g = ggrid(n);
   double2 *wj = Wh + (size_t)j * vs;
   hipLaunchKernelGGL(k_gcr2_dots, dim3(g, nrhs), dim3(256), 0, st, Wh, vs, j, wj, r, n, 1, skip, part);
-  hipLaunchKernelGGL(k_gcr2_dots_fin_fused, dim3(1, nrhs), dim3(256), 0, st, part, g, j, m, gs, nu, cnt, skip);
+  // mode 2: a threshold no difference passes (every step takes the second pass)
+  const double cancel = mode == 2 ? 2.0 : GCR_CANCEL;
+  hipLaunchKernelGGL(k_gcr2_dots_fin_fused, dim3(1, nrhs), dim3(256), 0, st, part, g, j, m, gs, nu, cnt, skip,
+                     cancel);
   if (r16) {
     const uint32_t Vpad = (uint32_t)(n / 12);
     const int gh = ggrid(Vpad);

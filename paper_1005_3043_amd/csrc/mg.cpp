@@ -1255,7 +1255,8 @@ static int fgcr_t(mg_ctx *c, const double2 *b, double2 *x, int nrhs, double tol,
                                         DS_PLAIN, nullptr, st)));
       }
       c->n_fine += nrhs;
-      HIPK(gcr2_step_residual(W, nn, j, m, r, n, nrhs, c->gsc, c->gnu, c->gcnt, skip, c->part, rr, r32, r16, st));
+      HIPK(gcr2_step_residual(W, nn, j, m, r, n, nrhs, c->gsc, c->gnu, c->gcnt, skip, c->part, rr, r32, r16,
+                              c->gcr_fuse, st));
       used = j + 1;
       HIPK(hipMemcpyAsync(c->h_rr, rr, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
       HIPK(hipStreamSynchronize(st));

@@ -81,9 +81,11 @@ hipError_t gcr2_residual(double2 *r, const double2 *Wh, size_t vs, int j, int m,
 // unless that difference has cancelled to below 1e-4 ||w_j||^2; then the
 // pass only orthogonalises and a second one updates r with a_j from the
 // measured ||w^_j||^2 (per right-hand side).
+// mode: 1 fused as described, 0 two passes always, 2 the fused pass with
+// every right-hand side taking the second pass.
 hipError_t gcr2_step_residual(double2 *Wh, size_t vs, int j, int m, double2 *r, size_t n, int nrhs, double2 *gs,
                               double *nu, int *cnt, const int *skip, double *part, double *rr, float2 *r32,
-                              h16 *r16, hipStream_t st);
+                              h16 *r16, int mode, hipStream_t st);
 template <typename TZ>
 hipError_t gcr2_solution(double2 *x, const TZ *Z, size_t vs, int kmax, int m, size_t n, int nrhs, double2 *gs,
                          double *nu, const int *cnt, hipStream_t st);
@@ -348,6 +350,7 @@ struct mg_ctx {
   mg::DevBuf<unsigned> cgp_bar;
   mg::DevBuf<int> cgp_fail;
   int cg_persist = 1;
+  int gcr_fuse = 1;  // mg_set_gcr_fusion
   unsigned cgp_spin = 1u << 20;  // barrier polls before a wait gives up
   int cgp_off[MG_MAX_LEVELS][3] = {};
   int *h_done = nullptr;   // pinned host mirrors

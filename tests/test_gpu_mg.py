@@ -584,6 +584,45 @@ def test_vcycle_mr_q_recursion(cuda, pre, post):
     assert abs(info["iters"][0] - it_ref) <= 1
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_gcr_fusion_modes(cuda, prec):
+    """The outer FGCR with the orthogonalisation and residual update fused
+    (step length from the Pythagorean norm), as two passes, and with every
+    step forced through the fused pass's fallback (second residual pass):
+    one and three right-hand sides, the oracle's iteration count within one
+    (FP16 class: within three, as for its other solve tests) and the same
+    true residual bound; the three solutions agree to 1e-6 (each has a
+    relative residual below 1e-10, so they differ by at most 2e-10 times
+    the condition number of D, which is below 10^3 here)."""
+    import paper_1005_3043_amd as mgwd
+    L, blocks, nv, eps, m, seed = CASES["8^4 b4^4 nv8"]
+    U = W.gauge_field(L, eps, seed)
+    starts = W.setup_starts(L, nv[0], seed)
+    h = so.mg_setup(U, m, so.MGParams(blocks=blocks, nv=nv), starts)
+    ctx = mgwd.MG(torch.from_numpy(U).cuda(), m, blocks, nv, [torch.from_numpy(starts).cuda()], max_rhs=3,
+                  precond_prec=prec)
+    try:
+        for nrhs in (1, 3):
+            b = W.gaussian_spinor(L, 5, batch=(nrhs,))
+            its_ref = [so.mg_solve(h, b[i], 1e-10)[1] for i in range(nrhs)]
+            xs = {}
+            for mode in (1, 0, 2):
+                ctx.set_gcr_fusion(mode)
+                x, info, rc = ctx.solve(torch.from_numpy(b).cuda(), 1e-10)
+                x = x.cpu().numpy()
+                res = [np.linalg.norm(b[i] - wi.apply_D(U, x[i], m)) / np.linalg.norm(b[i]) for i in range(nrhs)]
+                print(f"{prec} {nrhs} RHS mode {mode}: iterations {info['iters'][:nrhs]} (oracle {its_ref}), "
+                      f"max true rel resid {max(res):.2e}")
+                assert rc == 0 and max(res) <= 1e-10 * 1.001
+                for i in range(nrhs):
+                    assert -1 <= info["iters"][i] - its_ref[i] <= (3 if prec == "f16" else 1)
+                xs[mode] = x
+            for mode in (0, 2):
+                assert _rel(xs[mode], xs[1]) < 1e-6
+    finally:
+        ctx.close()
+
+
 def test_set_mass(cuda):
     """A setup reused at a heavier mass: the GPU's shifted Galerkin operator
     equals the oracle's Galerkin construction at the new mass with the same
