@@ -207,19 +207,22 @@ __global__ __launch_bounds__(64 * TM_WAVES) void k_prolong_fine_mma(Geom g, Geom
         cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, cim, 0, 0, 0);
       }
     }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = mt * 16 + 4 * kq + v;
-      if (r < Mh && col_ok) {
-        const int cp = r / vb, t = r - cp * vb;
-        const size_t o = fidx(s0 + (uint32_t)t, 6 * h + cp, 12);
-        float2 val = make_float2(cre[v], cim[v]);
-        if (accumulate) {
-          const float2 f = Fc[o];
-          val = make_float2(val.x + f.x, val.y + f.y);
-        }
-        Fc[o] = val;
+    // The lane's four rows 4 kq .. 4 kq + 3 of the tile are four consecutive
+    // sites of one component (|B| % 4 == 0, tiles start at multiples of 16):
+    // 32 contiguous bytes, read and written as two 16-byte accesses, so that
+    // the four lanes of a column cover 128 contiguous bytes per access.
+    const int r = mt * 16 + 4 * kq;
+    if (r < Mh && col_ok) {
+      const int cp = r / vb, t = r - cp * vb;
+      float4 *o4 = reinterpret_cast<float4 *>(Fc + fidx(s0 + (uint32_t)t, 6 * h + cp, 12));
+      float4 lo = make_float4(cre[0], cim[0], cre[1], cim[1]), hi = make_float4(cre[2], cim[2], cre[3], cim[3]);
+      if (accumulate) {
+        const float4 a = o4[0], b = o4[1];
+        lo = make_float4(lo.x + a.x, lo.y + a.y, lo.z + a.z, lo.w + a.w);
+        hi = make_float4(hi.x + b.x, hi.y + b.y, hi.z + b.z, hi.w + b.w);
       }
+      o4[0] = lo;
+      o4[1] = hi;
     }
   }
 }
