@@ -153,7 +153,10 @@ template <typename T> struct DevBuf {
     p = nullptr;
     n = 0;
   }
-  int alloc(size_t count) {
+  // zero = false only for buffers whose every entry is written before it is
+  // read (e.g. fine-level vectors of a lattice without padding sites, fully
+  // overwritten by a kernel that covers every site).
+  int alloc(size_t count, bool zero = true) {
     if (p && n >= count) return MG_OK;
     release();
     if (count == 0) return MG_OK;
@@ -161,7 +164,7 @@ template <typename T> struct DevBuf {
     // Zero-filled (padding entries stay zero), and the fill has completed
     // on return: the buffer is next used on streams that do not order
     // themselves after the default stream.
-    if (e == hipSuccess) e = hipMemsetAsync(p, 0, count * sizeof(T), nullptr);
+    if (e == hipSuccess && zero) e = hipMemsetAsync(p, 0, count * sizeof(T), nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
       if (p) pool_free(p, count * sizeof(T));
