@@ -342,10 +342,14 @@ __global__ __launch_bounds__(256, dslash_waves<R>()) void k_dslash_rb(Geom g, co
 // once per group.  Three for binary16 spinors (about 240 registers, two
 // waves per SIMD as with two; the links are read four times per 12-RHS
 // launch instead of six: 1.82 -> 1.72 ms plain, 2.55 -> 2.43 ms in the MR
-// q-recursion form on 32^3 x 64), two otherwise (FP32 spinors: 2.51 against
-// 2.58 ms with three, 3.40 against 3.38 ms; FP64 spills with three).
+// q-recursion form on 32^3 x 64) and for the outer method's FP64 operator on
+// FP32-stored vectors (256 registers, no spill, one wave per SIMD: 7 % less
+// time per step in that class), two otherwise (FP32 spinors: 2.51 against
+// 2.58 ms with three, 3.40 against 3.38 ms; FP64 spinors spill with three).
 template <typename R, typename TI> constexpr int mrhs_k() {
-  return (sizeof(R) == 4 && std::is_same<TI, h16>::value) ? 3 : 2;
+  return ((sizeof(R) == 4 && std::is_same<TI, h16>::value) || (sizeof(R) == 8 && std::is_same<TI, float2>::value))
+             ? 3
+             : 2;
 }
 
 int dslash_blocks(const Geom &g) { return div_up(g.V, 256); }

@@ -197,12 +197,23 @@ hipError_t prolong_fine(const Geom &g, const Geom &gc, int nv, const S *P, const
 // one workgroup per aggregate for all nrhs <= 16; requires |B| % 4 == 0.
 bool transfer_mma_ok(const Geom &g, int nv, int nrhs);
 // TF = float2, or h16 with S = chalf
+// The residuals r_0 .. r_{n-1} of an MR run by the q recursion (n <= MRQ_MAX).
+constexpr int MRQ_MAX = 8;
+template <typename TR> struct MrqList {
+  const TR *r[MRQ_MAX];
+};
+// With q given, the restriction takes r = fine - a q per right-hand side
+// (a = alpha[rhs]): the last residual of such a run formed on the fly.
 template <typename S, typename TF>
 hipError_t restrict_fine_mma(const Geom &g, const Geom &gc, int nv, const S *P, const TF *fine, float2 *coarse,
-                             int nrhs, hipStream_t st);
-template <typename S>
+                             int nrhs, hipStream_t st, const TF *q = nullptr, const double2 *alpha = nullptr);
+// With rs given (steps > 0), fine = P coarse + sum_k a_k r_k (a_k of
+// right-hand side i at alpha[k MG_MAX_RHS + i]): the run's solution added to
+// the prolongated correction without a pass of its own; accumulate ignored.
+template <typename S, typename TR = float2>
 hipError_t prolong_fine_mma(const Geom &g, const Geom &gc, int nv, const S *P, const float2 *coarse, float2 *fine,
-                            int nrhs, int accumulate, hipStream_t st);
+                            int nrhs, int accumulate, hipStream_t st, const MrqList<TR> *rs = nullptr,
+                            int steps = 0, const double2 *alpha = nullptr);
 // Coarse level l -> l+1: P = nv vectors in coarse AoS layout [nv][V][n];
 // requires block volume * n <= 2048.
 template <typename R, typename S>

@@ -495,35 +495,49 @@ int apply_A(mg_ctx *c, int l, const vec_t<P> *in, vec_t<P> *out, int nrhs, Dslas
 // the partials of (q_k, r_k); x = sum a_k r_k and the last residual update
 // follow in one pass.  The same iterates as the update after each stencil,
 // without the separate pass over x, r and q per step.
+// The step lengths a_k of the fine-level runs sit at csc + MRQ_ABASE +
+// k MG_MAX_RHS, apart from the coarse levels' (csc[0 .. nrhs)), so that a
+// pre-smoothing whose combine is deferred to the transfers keeps them over
+// the coarse-grid correction.
+constexpr size_t MRQ_ABASE = 96 * MG_MAX_RHS;
+
+// The residual list r_0 .. r_{steps-1} of a fine-level run from r0, and its
+// last q (q_{steps-1}), in the q-recursion buffers (TR: their storage).
+template <typename TR> static MrqList<TR> mrq_list(mg_ctx *c, const TR *r0, int steps) {
+  MrqList<TR> rs{};
+  rs.r[0] = r0;
+  for (int k = 1; k < steps; ++k) {
+    if constexpr (std::is_same<TR, h16>::value) rs.r[k] = c->w32.hrk[k - 1].p;
+    else rs.r[k] = c->w32.rk[k - 1].p;
+  }
+  return rs;
+}
+template <typename TR> static TR *mrq_q(mg_ctx *c, TR *q, int k) {
+  if ((k & 1) == 0) return q;
+  if constexpr (std::is_same<TR, h16>::value) return c->w32.hq2.p;
+  else return c->w32.q2.p;
+}
+
+// defer: stop after the steps (no combine pass): x and the last residual
+// are formed later from the list by the transfers (smooth_pre).
 template <typename P, typename TR>
 static int mr_q(mg_ctx *c, vec_t<P> *x, TR *r, TR *q, int steps, bool accumulate, int nrhs, hipStream_t st,
-                bool keep_r, const TR *r_in, float xs = 1.f) {
-  Work<float> &w = c->w32;
+                bool keep_r, const TR *r_in, float xs = 1.f, bool defer = false) {
   const int np = np_mr(c, 0, nrhs);
-  MrqList<TR> rs;
-  TR *qb[2];
-  TR *rk[MRQ_MAX - 1];
-  if constexpr (std::is_same<TR, h16>::value) {
-    qb[1] = w.hq2.p;
-    for (int k = 0; k + 1 < steps; ++k) rk[k] = w.hrk[k].p;
-  } else {
-    qb[1] = w.q2.p;
-    for (int k = 0; k + 1 < steps; ++k) rk[k] = w.rk[k].p;
-  }
-  qb[0] = q;
-  rs.r[0] = r_in ? r_in : r;
-  MG_TRY((apply_fine<P, TR, TR>(c, rs.r[0], qb[0], nrhs, DS_MR, nullptr, st)));
-  HIPK(fin_mr(c->part, np, nrhs, c->p.omega, c->csc, st));
+  const MrqList<TR> rs = mrq_list<TR>(c, r_in ? r_in : r, steps);
+  double2 *al = c->csc + MRQ_ABASE;
+  MG_TRY((apply_fine<P, TR, TR>(c, rs.r[0], q, nrhs, DS_MR, nullptr, st)));
+  HIPK(fin_mr(c->part, np, nrhs, c->p.omega, al, st));
   for (int k = 1; k < steps; ++k) {
     MrqArgs<TR> mq;
     mq.rprev = rs.r[k - 1];
-    mq.rout = rk[k - 1];
-    mq.alpha = c->csc + (size_t)(k - 1) * MG_MAX_RHS;
-    MG_TRY((apply_fine<P, TR, TR>(c, qb[(k - 1) & 1], qb[k & 1], nrhs, DS_MRQ, nullptr, st, mq)));
-    HIPK(fin_mr(c->part, np, nrhs, c->p.omega, c->csc + (size_t)k * MG_MAX_RHS, st));
-    rs.r[k] = rk[k - 1];
+    mq.rout = const_cast<TR *>(rs.r[k]);
+    mq.alpha = al + (size_t)(k - 1) * MG_MAX_RHS;
+    MG_TRY((apply_fine<P, TR, TR>(c, mrq_q<TR>(c, q, k - 1), mrq_q<TR>(c, q, k), nrhs, DS_MRQ, nullptr, st, mq)));
+    HIPK(fin_mr(c->part, np, nrhs, c->p.omega, al + (size_t)k * MG_MAX_RHS, st));
   }
-  HIPK(mrq_combine<TR>(x, r, rs, qb[(steps - 1) & 1], c->lev[0].g, steps, nrhs, c->csc, accumulate ? 0 : 1,
+  if (defer) return MG_OK;
+  HIPK(mrq_combine<TR>(x, r, rs, mrq_q<TR>(c, q, steps - 1), c->lev[0].g, steps, nrhs, al, accumulate ? 0 : 1,
                        keep_r ? 1 : 0, xs, st));
   return MG_OK;
 }
@@ -978,6 +992,50 @@ static int resid(mg_ctx *c, int l, const vec_t<P> *x, TR *r, const TR *b, int nr
   else return apply_A<P>(c, l, x, r, nrhs, DS_RESID, b, st);
 }
 
+// Whether the pre-smoothing of level l leaves its combine pass to the
+// transfers: on the fine level of the FP32 and FP16 classes with MR of two
+// or more steps by the q recursion and the matrix-core restriction and
+// prolongation chosen for nrhs.  The restriction then forms the last
+// residual r_{n-1} - a_{n-1} q_{n-1} as it loads it, and the prolongation
+// adds sum a_k r_k to P e_c as it stores x; x and the residual are not
+// written in between (one pass over 4 + 2 vectors fewer, three more reads
+// inside the transfers).  A pure function of the configuration and the
+// tuned variants, so the two halves of a captured cycle agree.
+template <typename P, typename TR> static int pre_fused(mg_ctx *c, int l, int nrhs, hipStream_t st, bool &on) {
+  on = false;
+  if constexpr (sizeof(typename P::R) == 4) {
+    if (l != 0 || c->p.smoother == MG_SMOOTH_GMRES || !mrq_ready<TR>(c, 0, c->p.pre, nrhs)) return MG_OK;
+    const int tr = transfer_variant<P>(c, 0, nrhs, st);
+    if (tr < 0) return tr;
+    const int tp = transfer_variant<P>(c, 1, nrhs, st);
+    if (tp < 0) return tp;
+    on = tr == 1 && tp == 1;
+  }
+  return MG_OK;
+}
+
+// The restriction of the residual smooth_pre left on level l (its deferred
+// form when pre_fused).
+template <typename P, typename TR>
+static int restrict_pre(mg_ctx *c, int l, const TR *r, vec_t<P> *coarse, int nrhs, hipStream_t st) {
+  if constexpr (sizeof(typename P::R) == 4) {
+    bool fused;
+    MG_TRY((pre_fused<P, TR>(c, l, nrhs, st, fused)));
+    if (fused) {
+      const int n = c->p.pre;
+      Level &L = c->lev[0], &Lc = c->lev[1];
+      TR *r0, *q0;
+      res_bufs<P, TR>(c, 0, r0, q0);
+      const MrqList<TR> rs = mrq_list<TR>(c, r0, n);
+      HIPK((restrict_fine_mma<typename P::S, TR>(L.g, Lc.g, L.nv, P_of<P>(L), rs.r[n - 1], coarse, nrhs, st,
+                                                 mrq_q<TR>(c, q0, n - 1),
+                                                 c->csc + MRQ_ABASE + (size_t)(n - 1) * MG_MAX_RHS)));
+      return MG_OK;
+    }
+  }
+  return transfer_restrict<P, TR>(c, l, r, coarse, nrhs, st);
+}
+
 // Smoothing before the coarse correction on level l (x from zero, r the
 // residual left for restriction).
 template <typename P, typename TR>
@@ -987,6 +1045,11 @@ static int smooth_pre(mg_ctx *c, int l, const TR *rin, vec_t<P> *x, int nrhs, hi
   TR *r, *q;
   res_bufs<P, TR>(c, l, r, q);
   if (c->p.smoother != MG_SMOOTH_GMRES && c->p.pre > 0) {
+    if constexpr (sizeof(R) == 4) {
+      bool fused;
+      MG_TRY((pre_fused<P, TR>(c, l, nrhs, st, fused)));
+      if (fused) return mr_q<P, TR>(c, x, r, q, c->p.pre, false, nrhs, st, true, rin, 1.f, true);
+    }
     MG_TRY((mr<P, TR>(c, l, x, r, q, c->p.pre, false, nrhs, st, true, rin)));
   } else if (c->p.smoother == MG_SMOOTH_GMRES && c->p.pre > 0) {
     int rc;
@@ -1009,7 +1072,19 @@ static int smooth_post(mg_ctx *c, int l, const TR *rin, vec_t<P> *x, int nrhs, h
   Work<R> &w = work<R>(c);
   TR *r, *q;
   res_bufs<P, TR>(c, l, r, q);
-  MG_TRY(transfer_prolong<P>(c, l, w.x[l + 1], x, nrhs, 1, st));
+  bool fused = false;
+  if constexpr (sizeof(R) == 4) MG_TRY((pre_fused<P, TR>(c, l, nrhs, st, fused)));
+  if (fused) {
+    if constexpr (sizeof(R) == 4) {
+      // x = P e_c + sum a_k r_k of the deferred pre-smoothing
+      Level &L = c->lev[0], &Lc = c->lev[1];
+      const MrqList<TR> rs = mrq_list<TR>(c, rin, c->p.pre);
+      HIPK((prolong_fine_mma<typename P::S, TR>(L.g, Lc.g, L.nv, P_of<P>(L), w.x[1], x, nrhs, 0, st, &rs,
+                                                c->p.pre, c->csc + MRQ_ABASE)));
+    }
+  } else {
+    MG_TRY(transfer_prolong<P>(c, l, w.x[l + 1], x, nrhs, 1, st));
+  }
   MG_TRY((resid<P, TR>(c, l, x, r, rin, nrhs, st)));
   if (c->p.smoother == MG_SMOOTH_GMRES) {
     int rc;
@@ -1035,7 +1110,7 @@ static int vcycle_part(mg_ctx *c, int part, const fres_t<P> *rin0, vec_t<P> *x0,
     TR *r0, *q0;
     res_bufs<P, TR>(c, 0, r0, q0);
     MG_TRY((smooth_pre<P, TR>(c, 0, rin0, x0, nrhs, st)));
-    MG_TRY((transfer_restrict<P, TR>(c, 0, r0, w.rin[1], nrhs, st)));
+    MG_TRY((restrict_pre<P, TR>(c, 0, r0, w.rin[1], nrhs, st)));
     for (int l = 1; l <= top; ++l) {
       MG_TRY((smooth_pre<P, vec_t<P>>(c, l, w.rin[l], w.x[l], nrhs, st)));
       MG_TRY((transfer_restrict<P, vec_t<P>>(c, l, w.r[l], w.rin[l + 1], nrhs, st)));
@@ -1126,7 +1201,7 @@ static int vcycle_t(mg_ctx *c, int l, const TR *rin, vec_t<P> *x, int nrhs, hipS
   const int m = l + 1;
   TR *r, *q;
   res_bufs<P, TR>(c, l, r, q);
-  MG_TRY((transfer_restrict<P, TR>(c, l, r, w.rin[m], nrhs, st)));
+  MG_TRY((restrict_pre<P, TR>(c, l, r, w.rin[m], nrhs, st)));
   MG_TRY((vcycle_t<P, vec_t<P>>(c, m, w.rin[m], w.x[m], nrhs, st)));
   if (m < c->nlev - 1) {
     // W-cycle: further cycles of level m on the residual the previous left

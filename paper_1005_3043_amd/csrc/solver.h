@@ -36,10 +36,6 @@ hipError_t fin_mr(const double *part, int np, int nrhs, double omega, double2 *a
 // alpha[k * MG_MAX_RHS + rhs],  x = (first ? 0 : x) + xs sum_k a_k r_k  and,
 // when upd_r, r_out = r_{n-1} - a_{n-1} q_{n-1} (r_out may be r_0); xs = 1,
 // or -1 to subtract the MR solution from x.
-constexpr int MRQ_MAX = 8;
-template <typename TR> struct MrqList {
-  const TR *r[MRQ_MAX];
-};
 template <typename TR>
 hipError_t mrq_combine(float2 *x, TR *r_out, const MrqList<TR> &rs, const TR *q, const Geom &g, int steps, int nrhs,
                        const double2 *alpha, int first, int upd_r, float xs, hipStream_t st);

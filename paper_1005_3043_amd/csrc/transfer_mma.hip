@@ -70,7 +70,9 @@ template <typename S, typename TF>
 __global__ __launch_bounds__(64 * TM_WAVES) void k_restrict_fine_mma(Geom g, Geom gc, int nv, int nrhs,
                                                                      const S *__restrict__ P,
                                                                      const TF *__restrict__ fine,
-                                                                     float2 *__restrict__ coarse) {
+                                                                     float2 *__restrict__ coarse,
+                                                                     const TF *__restrict__ qv,
+                                                                     const double2 *__restrict__ alpha) {
   constexpr int KS = TM_WAVES / 2;
   __shared__ float red[TM_WAVES - 2][64][16];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -85,6 +87,12 @@ __global__ __launch_bounds__(64 * TM_WAVES) void k_restrict_fine_mma(Geom g, Geo
   const S *Pa0 = P + (size_t)(a0_ok ? ar0 : 0) * 12 * V;
   const S *Pa1 = P + (size_t)(a1_ok ? ar1 : 0) * 12 * V;
   const TF *Fb = fine + (size_t)(col_ok ? col : 0) * site_slots<TF>() * V;
+  const TF *Qb = qv ? qv + (size_t)(col_ok ? col : 0) * site_slots<TF>() * V : nullptr;
+  float2 ma = make_float2(0.f, 0.f);
+  if (Qb) {
+    const double2 ad = alpha[col_ok ? col : 0];
+    ma = make_float2((float)-ad.x, (float)-ad.y);
+  }
   const uint32_t s0 = B * (uint32_t)vb;
   const int nb = ks < KB ? (KB - ks + KS - 1) / KS : 0;  // k-blocks of this wavefront
   floatx4 cre0 = {0.f, 0.f, 0.f, 0.f}, cim0 = {0.f, 0.f, 0.f, 0.f};
@@ -102,6 +110,12 @@ __global__ __launch_bounds__(64 * TM_WAVES) void k_restrict_fine_mma(Geom g, Geo
       load4(Pa0 + o, av0[u]);
       if (MT > 1) load4(Pa1 + o, av1[u]);
       load4_site(Fb, s0 + (uint32_t)t, 6 * h + cp, bv[u]);
+      if (Qb) {
+        float2 qq[4];
+        load4_site(Qb, s0 + (uint32_t)t, 6 * h + cp, qq);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bv[u][e] = cfma(ma, qq[e], bv[u][e]);
+      }
     }
 #pragma unroll
     for (int u = 0; u < TM_U; ++u) {
@@ -160,11 +174,13 @@ __global__ __launch_bounds__(64 * TM_WAVES) void k_restrict_fine_mma(Geom g, Geo
 
 // Prolongation.  The aggregate's coarse values are staged in LDS; wavefront
 // w takes the output row tiles w, w + 8, ... of both chiralities.
-template <typename S>
+template <typename S, typename TR>
 __global__ __launch_bounds__(64 * TM_WAVES) void k_prolong_fine_mma(Geom g, Geom gc, int nv, int nrhs,
                                                                     const S *__restrict__ P,
                                                                     const float2 *__restrict__ coarse,
-                                                                    float2 *__restrict__ fine, int accumulate) {
+                                                                    float2 *__restrict__ fine, int accumulate,
+                                                                    MrqList<TR> rs, int steps,
+                                                                    const double2 *__restrict__ alpha) {
   __shared__ float2 eb[COARSE_NMAX][TM_NR];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const uint32_t B = blockIdx.x;
@@ -216,7 +232,25 @@ __global__ __launch_bounds__(64 * TM_WAVES) void k_prolong_fine_mma(Geom g, Geom
       const int cp = r / vb, t = r - cp * vb;
       float4 *o4 = reinterpret_cast<float4 *>(Fc + fidx(s0 + (uint32_t)t, 6 * h + cp, 12));
       float4 lo = make_float4(cre[0], cim[0], cre[1], cim[1]), hi = make_float4(cre[2], cim[2], cre[3], cim[3]);
-      if (accumulate) {
+      if (steps > 0) {
+        // + sum_k a_k r_k of this right-hand side at the four sites
+        float2 acc[4] = {make_float2(lo.x, lo.y), make_float2(lo.z, lo.w), make_float2(hi.x, hi.y),
+                         make_float2(hi.z, hi.w)};
+        const size_t ro = (size_t)col * site_slots<TR>() * V;
+#pragma unroll
+        for (int k = 0; k < MRQ_MAX; ++k) {
+          if (k < steps) {
+            const double2 ad = alpha[(size_t)k * MG_MAX_RHS + col];
+            const float2 a = make_float2((float)ad.x, (float)ad.y);
+            float2 rv[4];
+            load4_site(rs.r[k] + ro, s0 + (uint32_t)t, 6 * h + cp, rv);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[e] = cfma(a, rv[e], acc[e]);
+          }
+        }
+        lo = make_float4(acc[0].x, acc[0].y, acc[1].x, acc[1].y);
+        hi = make_float4(acc[2].x, acc[2].y, acc[3].x, acc[3].y);
+      } else if (accumulate) {
         const float4 a = o4[0], b = o4[1];
         lo = make_float4(lo.x + a.x, lo.y + a.y, lo.z + a.z, lo.w + a.w);
         hi = make_float4(hi.x + b.x, hi.y + b.y, hi.z + b.z, hi.w + b.w);
@@ -235,31 +269,46 @@ bool transfer_mma_ok(const Geom &g, int nv, int nrhs) {
 
 template <typename S, typename TF>
 hipError_t restrict_fine_mma(const Geom &g, const Geom &gc, int nv, const S *P, const TF *fine, float2 *coarse,
-                             int nrhs, hipStream_t st) {
+                             int nrhs, hipStream_t st, const TF *q, const double2 *alpha) {
   if (!transfer_mma_ok(g, nv, nrhs)) return hipErrorInvalidValue;
+  if (q && !alpha) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_restrict_fine_mma<S, TF>), dim3(g.Vc), dim3(64 * TM_WAVES), 0, st, g, gc, nv, nrhs, P, fine,
-                     coarse);
+                     coarse, q, alpha);
   return hipGetLastError();
 }
 
-template <typename S>
+template <typename S, typename TR>
 hipError_t prolong_fine_mma(const Geom &g, const Geom &gc, int nv, const S *P, const float2 *coarse, float2 *fine,
-                            int nrhs, int accumulate, hipStream_t st) {
+                            int nrhs, int accumulate, hipStream_t st, const MrqList<TR> *rs, int steps,
+                            const double2 *alpha) {
   if (!transfer_mma_ok(g, nv, nrhs)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_prolong_fine_mma<S>), dim3(g.Vc), dim3(64 * TM_WAVES), 0, st, g, gc, nv, nrhs, P, coarse,
-                     fine, accumulate);
+  MrqList<TR> l{};
+  if (rs) {
+    if (steps < 1 || steps > MRQ_MAX || !alpha) return hipErrorInvalidValue;
+    l = *rs;
+  } else {
+    steps = 0;
+  }
+  hipLaunchKernelGGL((k_prolong_fine_mma<S, TR>), dim3(g.Vc), dim3(64 * TM_WAVES), 0, st, g, gc, nv, nrhs, P, coarse,
+                     fine, accumulate, l, steps, alpha);
   return hipGetLastError();
 }
 
 template hipError_t restrict_fine_mma<float2, float2>(const Geom &, const Geom &, int, const float2 *,
-                                                      const float2 *, float2 *, int, hipStream_t);
+                                                      const float2 *, float2 *, int, hipStream_t, const float2 *,
+                                                      const double2 *);
 template hipError_t restrict_fine_mma<chalf, float2>(const Geom &, const Geom &, int, const chalf *, const float2 *,
-                                                     float2 *, int, hipStream_t);
+                                                     float2 *, int, hipStream_t, const float2 *, const double2 *);
 template hipError_t restrict_fine_mma<chalf, h16>(const Geom &, const Geom &, int, const chalf *, const h16 *,
-                                                  float2 *, int, hipStream_t);
-template hipError_t prolong_fine_mma<float2>(const Geom &, const Geom &, int, const float2 *, const float2 *,
-                                             float2 *, int, int, hipStream_t);
-template hipError_t prolong_fine_mma<chalf>(const Geom &, const Geom &, int, const chalf *, const float2 *, float2 *,
-                                            int, int, hipStream_t);
+                                                  float2 *, int, hipStream_t, const h16 *, const double2 *);
+template hipError_t prolong_fine_mma<float2, float2>(const Geom &, const Geom &, int, const float2 *, const float2 *,
+                                                     float2 *, int, int, hipStream_t, const MrqList<float2> *, int,
+                                                     const double2 *);
+template hipError_t prolong_fine_mma<chalf, float2>(const Geom &, const Geom &, int, const chalf *, const float2 *,
+                                                    float2 *, int, int, hipStream_t, const MrqList<float2> *, int,
+                                                    const double2 *);
+template hipError_t prolong_fine_mma<chalf, h16>(const Geom &, const Geom &, int, const chalf *, const float2 *,
+                                                 float2 *, int, int, hipStream_t, const MrqList<h16> *, int,
+                                                 const double2 *);
 
 }  // namespace mg

@@ -584,6 +584,60 @@ def test_vcycle_mr_q_recursion(cuda, pre, post):
     assert abs(info["iters"][0] - it_ref) <= 1
 
 
+@pytest.mark.parametrize("case", ["2-level 8^4", "3-level 8^4"])
+def test_vcycle_deferred_presmoothing(cuda, case):
+    """With the matrix-core transfers the fine pre-smoothing (MR by the q
+    recursion) leaves its combine pass to them: the restriction forms the
+    last residual r_{n-1} - a q_{n-1} as it loads it, the prolongation adds
+    sum a_k r_k to P e_c.  Forced matrix-core transfers (deferred) and vector
+    transfers (combine pass) against the oracle's cycle for 2 and 3
+    right-hand sides in the FP32 and FP16 classes (bounds as for the
+    standard cycle), the two forms within FP32 rounding of each other
+    (FP16 class: within its binary16 rounding, since the deferred form skips
+    the binary16 rounding of the last residual), and a solve with the
+    deferred form at the oracle's iteration count."""
+    L, blocks, nv, eps, m, seed = _CYCLE_CASES[case]
+    U = W.gauge_field(L, eps, seed)
+    starts = W.setup_starts(L, nv[0], seed)
+    inits = [torch.from_numpy(starts).cuda()]
+    cst = None
+    if len(blocks) > 1:
+        Lc = tuple(L[mu] // blocks[0][mu] for mu in range(4))
+        cst = W.coarse_setup_starts(Lc, 2 * nv[0], nv[1], seed)
+        inits.append(torch.from_numpy(cst).cuda())
+    if case not in _CYCLE_ORACLE:
+        _CYCLE_ORACLE[case] = so.mg_setup(U, m, so.MGParams(blocks=blocks, nv=nv), starts, cst)
+    h = _CYCLE_ORACLE[case]
+    import paper_1005_3043_amd as mgwd
+    ctx = mgwd.MG(torch.from_numpy(U).cuda(), m, blocks, nv, inits, max_rhs=4)
+    try:
+        for nrhs in (2, 3):
+            r = W.gaussian_spinor(L, 17, batch=(nrhs,))
+            h.stats["cgnr_iters"] = []
+            zr = np.stack([h.vcycle(r[i], 0) for i in range(nrhs)])
+            for prec, bound, between in (("f32", 1e-4, 1e-5), ("f16", 2e-3, 2e-3)):
+                z = {}
+                for var in (1, 0):
+                    ctx.set_transfer_variant(var)
+                    zz, _ = ctx.vcycle(torch.from_numpy(r).cuda(), prec)
+                    z[var] = zz.cpu().numpy()
+                e1, e0, e10 = _rel(z[1], zr), _rel(z[0], zr), _rel(z[1], z[0])
+                print(f"{case} {nrhs} RHS {prec}: deferred {e1:.2e}, combine pass {e0:.2e} from the oracle; "
+                      f"between {e10:.2e}")
+                assert e1 < bound and e0 < bound and e10 < between
+        ctx.set_transfer_variant(1)
+        ctx.set_precond_prec("f32")
+        b = W.gaussian_spinor(L, 1, batch=(2,))
+        x, info, rc = ctx.solve(torch.from_numpy(b).cuda(), 1e-10)
+        x = x.cpu().numpy()
+        for i in range(2):
+            res = np.linalg.norm(b[i] - wi.apply_D(U, x[i], m)) / np.linalg.norm(b[i])
+            _, it_ref, _, _ = so.mg_solve(h, b[i], 1e-10)
+            assert rc == 0 and res <= 1e-10 * 1.001 and abs(info["iters"][i] - it_ref) <= 1
+    finally:
+        ctx.close()
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
 def test_gcr_fusion_modes(cuda, prec):
     """The outer FGCR with the orthogonalisation and residual update fused
