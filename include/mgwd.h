@@ -140,6 +140,14 @@ typedef struct {
   int learned_setup;
   int ptc_hidden;
   const void *ptc_weights[2];
+  /* Storage of the prolongator the FP32 preconditioner's transfers read
+   * (restriction and prolongation on every level): MG_F16 takes the
+   * binary16 copy of P (FP32 arithmetic, FP32 vectors), halving the bytes
+   * of P that every cycle streams; any other value (MG_F64 = 0, the
+   * default, or MG_F32): each preconditioner class reads P in its own
+   * storage (FP32 in the FP32 class, binary16 in the FP16 class, FP64 in
+   * the FP64 class).  Errors: MG_ENOTSUP for values outside MG_F64..MG_F16. */
+  mg_prec_t transfer_prec;
 } mg_params_t;
 
 #define MG_SMOOTH_MR 0

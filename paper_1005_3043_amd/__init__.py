@@ -60,7 +60,8 @@ class Params(ctypes.Structure):
                 ("smoother", ctypes.c_int), ("cycles", ctypes.c_int),
                 ("setup_prec", ctypes.c_int),
                 ("learned_setup", ctypes.c_int), ("ptc_hidden", ctypes.c_int),
-                ("ptc_weights", ctypes.c_void_p * 2)]
+                ("ptc_weights", ctypes.c_void_p * 2),
+                ("transfer_prec", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -216,7 +217,7 @@ class MG:
                  t_antiperiodic=True, setup_rounds=5, setup_mr_steps=4, omega=0.9, pre=4,
                  post=4, coarse_tol=1e-3, coarse_maxiter=1000, gcr_restart=8, max_iter=10000,
                  precond_prec="f64", max_rhs=1, use_graph=True, refine_group=0, refine_iters=5,
-                 smoother="mr", cycles=1, setup_prec="f64", learned=None):
+                 smoother="mr", cycles=1, setup_prec="f64", learned=None, transfer_prec="f64"):
         """learned = (W1, W2, n_hidden): the level-0 start vectors are the
         network's output for the noise field init_vectors[0] (one field),
         computed inside mg_setup."""
@@ -237,6 +238,7 @@ class MG:
         p.refine_group, p.refine_iters = int(refine_group), int(refine_iters)
         p.smoother, p.cycles = {"mr": 0, "gmres": 1}[smoother], int(cycles)
         p.setup_prec = PREC[setup_prec]
+        p.transfer_prec = transfer_prec if isinstance(transfer_prec, int) else PREC[transfer_prec]
         self._keep = list(init_vectors)
         if learned is not None:
             W1, W2, n_hidden = learned

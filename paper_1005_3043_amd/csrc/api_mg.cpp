@@ -69,6 +69,8 @@ int check_params(const mg_lattice_t *lat, const mg_params_t *p) {
     return bad(MG_ENOTSUP, "precond_prec must be MG_F64, MG_F32 or MG_F16");
   if (p->setup_prec != MG_F64 && p->setup_prec != MG_F32)
     return bad(MG_ENOTSUP, "setup_prec must be MG_F64 or MG_F32");
+  if (p->transfer_prec != MG_F64 && p->transfer_prec != MG_F32 && p->transfer_prec != MG_F16)
+    return bad(MG_ENOTSUP, "transfer_prec must be MG_F64, MG_F32 or MG_F16");
   if (p->learned_setup != 0 && p->learned_setup != 1) return bad(MG_EINVAL, "learned_setup must be 0 or 1");
   if (p->learned_setup) {
     if (!p->ptc_weights[0] || !p->ptc_weights[1]) return bad(MG_EINVAL, "learned_setup: ptc_weights missing");

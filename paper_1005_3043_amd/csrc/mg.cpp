@@ -83,7 +83,20 @@ static int make_copies(mg_ctx *c, DevBuf<S> &U, DevBuf<S> Level::*Pm, DevBuf<S> 
 
 int ensure_prec(mg_ctx *c, mg_prec_t prec, hipStream_t st) {
   if (prec == MG_F64) return MG_OK;
-  if (prec == MG_F32) return make_copies<float2>(c, c->lev[0].U32, &Level::P32, &Level::L32, st);
+  if (prec == MG_F32) {
+    MG_TRY(make_copies<float2>(c, c->lev[0].U32, &Level::P32, &Level::L32, st));
+    if (c->p.transfer_prec == MG_F16) {
+      // the binary16 prolongators the FP32 class's transfers read
+      for (int l = 0; l < c->nlev; ++l) {
+        Level &L = c->lev[l];
+        if (L.nv > 0 && !L.P16.p) {
+          MG_TRY(L.P16.alloc(L.P64.n));
+          HIPK(store_convert<chalf>(L.P16, L.P64, L.P64.n, st));
+        }
+      }
+    }
+    return MG_OK;
+  }
   if (prec == MG_F16) return make_copies<chalf>(c, c->lev[0].U16, &Level::P16, &Level::L16, st);
   set_error("preconditioner precision must be MG_F64, MG_F32 or MG_F16");
   return MG_ENOTSUP;
@@ -192,6 +205,21 @@ template <typename P> const typename P::S *P_of(Level &L);
 template <> const double2 *P_of<PF64>(Level &L) { return L.P64.p; }
 template <> const float2 *P_of<PF32>(Level &L) { return L.P32.p; }
 template <> const chalf *P_of<PF16>(Level &L) { return L.P16.p; }
+
+// Calls f with the prolongator the transfers of class P read on level L:
+// P's own storage, or the binary16 copy in the FP32 class when transfer_prec
+// is MG_F16.  f returns the same type for every storage.
+template <typename P, typename F> static auto with_transfer_P(const mg_ctx *c, Level &L, F &&f) {
+  if constexpr (std::is_same<P, PF32>::value) {
+    if (c->p.transfer_prec == MG_F16) return f(P_of<PF16>(L));
+  }
+  return f(P_of<P>(L));
+}
+// identifies the transfers' P storage in the process-wide tuning cache
+template <typename P> static int transfer_store_id(const mg_ctx *c) {
+  return (std::is_same<P, PF32>::value && c->p.transfer_prec == MG_F16) ? 3 : P::id;
+}
+template <typename T> using stor_t = std::remove_cv_t<std::remove_pointer_t<T>>;
 
 template <typename P> const typename P::S *links_of_level(Level &L) { return links_of<P>(L); }
 template <typename P> const typename P::S *cop_of_level(Level &L) { return cop_of<P>(L); }
@@ -379,7 +407,7 @@ template <typename P> int transfer_variant(mg_ctx *c, int dir, int nrhs, hipStre
     if (c->tvar_force >= 0) return c->tvar_force > 0 ? 1 : 0;
     int &v = c->tvar[dir][P::id][nrhs];
     if (v >= 0) return v;
-    const TKey key{L.g.V, L.g.vb, L.nv, P::id, nrhs, dir};
+    const TKey key{L.g.V, L.g.vb, L.nv, transfer_store_id<P>(c), nrhs, dir};
     {
       std::lock_guard<std::mutex> lk(tune_mu);
       for (const TVal &t : ttune_cache)
@@ -405,12 +433,14 @@ template <typename P> int transfer_variant(mg_ctx *c, int dir, int nrhs, hipStre
       for (int i = 0; i < 2 + reps && rc == MG_OK; ++i) {
         if (i == 2) rc = hip_rc(hipEventRecord(e0, st), "hipEventRecord");
         hipError_t e;
-        if (dir == 0)
-          e = cv ? restrict_fine_mma(L.g, Lc.g, L.nv, P_of<P>(L), a.p, b.p, nrhs, st)
-                 : restrict_fine<R>(L.g, Lc.g, L.nv, P_of<P>(L), a.p, b.p, nrhs, st);
-        else
-          e = cv ? prolong_fine_mma(L.g, Lc.g, L.nv, P_of<P>(L), b.p, a.p, nrhs, 1, st)
-                 : prolong_fine<R>(L.g, Lc.g, L.nv, P_of<P>(L), b.p, a.p, nrhs, 1, st);
+        e = with_transfer_P<P>(c, L, [&](auto Pp) -> hipError_t {
+          using SS = stor_t<decltype(Pp)>;
+          if (dir == 0)
+            return cv ? restrict_fine_mma<SS, float2>(L.g, Lc.g, L.nv, Pp, a.p, b.p, nrhs, st)
+                      : restrict_fine<R, SS, float2>(L.g, Lc.g, L.nv, Pp, a.p, b.p, nrhs, st);
+          return cv ? prolong_fine_mma<SS>(L.g, Lc.g, L.nv, Pp, b.p, a.p, nrhs, 1, st)
+                    : prolong_fine<R, SS>(L.g, Lc.g, L.nv, Pp, b.p, a.p, nrhs, 1, st);
+        });
         if (rc == MG_OK) rc = hip_rc(e, "transfer tune");
       }
       if (rc == MG_OK) rc = hip_rc(hipEventRecord(e1, st), "hipEventRecord");
@@ -603,20 +633,21 @@ int gmres_smooth(mg_ctx *c, int l, vec_t<P> *x, const vec_t<P> *b, int k, bool a
 template <typename P, typename TR>
 int transfer_restrict(mg_ctx *c, int l, const TR *fine, vec_t<P> *coarse, int nrhs, hipStream_t st) {
   using R = typename P::R;
-  using S = typename P::S;
   Level &L = c->lev[l], &Lc = c->lev[l + 1];
   if (l == 0) {
     const int tv = transfer_variant<P>(c, 0, nrhs, st);
     if (tv < 0) return tv;
-    if constexpr (sizeof(R) == 4) {
-      if (tv == 1) {
-        HIPK((restrict_fine_mma<S, TR>(L.g, Lc.g, L.nv, P_of<P>(L), fine, coarse, nrhs, st)));
-        return MG_OK;
+    HIPK(with_transfer_P<P>(c, L, [&](auto Pp) -> hipError_t {
+      using SS = stor_t<decltype(Pp)>;
+      if constexpr (sizeof(R) == 4) {
+        if (tv == 1) return restrict_fine_mma<SS, TR>(L.g, Lc.g, L.nv, Pp, fine, coarse, nrhs, st);
       }
-    }
-    HIPK((restrict_fine<R, S, TR>(L.g, Lc.g, L.nv, P_of<P>(L), fine, coarse, nrhs, st)));
+      return restrict_fine<R, SS, TR>(L.g, Lc.g, L.nv, Pp, fine, coarse, nrhs, st);
+    }));
   } else if constexpr (std::is_same<TR, vec_t<P>>::value) {
-    HIPK((restrict_coarse<R, S>(L.g, Lc.g, L.n, L.nv, P_of<P>(L), fine, coarse, nrhs, st)));
+    HIPK(with_transfer_P<P>(c, L, [&](auto Pp) -> hipError_t {
+      return restrict_coarse<R, stor_t<decltype(Pp)>>(L.g, Lc.g, L.n, L.nv, Pp, fine, coarse, nrhs, st);
+    }));
   }
   return MG_OK;
 }
@@ -625,20 +656,22 @@ template <typename P>
 int transfer_prolong(mg_ctx *c, int l, const vec_t<P> *coarse, vec_t<P> *fine, int nrhs, int accumulate,
                      hipStream_t st) {
   using R = typename P::R;
-  using S = typename P::S;
   Level &L = c->lev[l], &Lc = c->lev[l + 1];
   if (l == 0) {
     const int tv = transfer_variant<P>(c, 1, nrhs, st);
     if (tv < 0) return tv;
-    if constexpr (sizeof(R) == 4) {
-      if (tv == 1) {
-        HIPK(prolong_fine_mma(L.g, Lc.g, L.nv, P_of<P>(L), coarse, fine, nrhs, accumulate, st));
-        return MG_OK;
+    HIPK(with_transfer_P<P>(c, L, [&](auto Pp) -> hipError_t {
+      using SS = stor_t<decltype(Pp)>;
+      if constexpr (sizeof(R) == 4) {
+        if (tv == 1) return prolong_fine_mma<SS>(L.g, Lc.g, L.nv, Pp, coarse, fine, nrhs, accumulate, st);
       }
-    }
-    HIPK((prolong_fine<R, S>(L.g, Lc.g, L.nv, P_of<P>(L), coarse, fine, nrhs, accumulate, st)));
+      return prolong_fine<R, SS>(L.g, Lc.g, L.nv, Pp, coarse, fine, nrhs, accumulate, st);
+    }));
+  } else {
+    HIPK(with_transfer_P<P>(c, L, [&](auto Pp) -> hipError_t {
+      return prolong_coarse<R, stor_t<decltype(Pp)>>(L.g, Lc.g, L.n, L.nv, Pp, coarse, fine, nrhs, accumulate, st);
+    }));
   }
-  else HIPK((prolong_coarse<R, S>(L.g, Lc.g, L.n, L.nv, P_of<P>(L), coarse, fine, nrhs, accumulate, st)));
   return MG_OK;
 }
 
@@ -1027,9 +1060,11 @@ static int restrict_pre(mg_ctx *c, int l, const TR *r, vec_t<P> *coarse, int nrh
       TR *r0, *q0;
       res_bufs<P, TR>(c, 0, r0, q0);
       const MrqList<TR> rs = mrq_list<TR>(c, r0, n);
-      HIPK((restrict_fine_mma<typename P::S, TR>(L.g, Lc.g, L.nv, P_of<P>(L), rs.r[n - 1], coarse, nrhs, st,
-                                                 mrq_q<TR>(c, q0, n - 1),
-                                                 c->csc + MRQ_ABASE + (size_t)(n - 1) * MG_MAX_RHS)));
+      HIPK(with_transfer_P<P>(c, L, [&](auto Pp) -> hipError_t {
+        return restrict_fine_mma<stor_t<decltype(Pp)>, TR>(L.g, Lc.g, L.nv, Pp, rs.r[n - 1], coarse, nrhs, st,
+                                                           mrq_q<TR>(c, q0, n - 1),
+                                                           c->csc + MRQ_ABASE + (size_t)(n - 1) * MG_MAX_RHS);
+      }));
       return MG_OK;
     }
   }
@@ -1079,8 +1114,10 @@ static int smooth_post(mg_ctx *c, int l, const TR *rin, vec_t<P> *x, int nrhs, h
       // x = P e_c + sum a_k r_k of the deferred pre-smoothing
       Level &L = c->lev[0], &Lc = c->lev[1];
       const MrqList<TR> rs = mrq_list<TR>(c, rin, c->p.pre);
-      HIPK((prolong_fine_mma<typename P::S, TR>(L.g, Lc.g, L.nv, P_of<P>(L), w.x[1], x, nrhs, 0, st, &rs,
-                                                c->p.pre, c->csc + MRQ_ABASE)));
+      HIPK(with_transfer_P<P>(c, L, [&](auto Pp) -> hipError_t {
+        return prolong_fine_mma<stor_t<decltype(Pp)>, TR>(L.g, Lc.g, L.nv, Pp, w.x[1], x, nrhs, 0, st, &rs,
+                                                          c->p.pre, c->csc + MRQ_ABASE);
+      }));
     }
   } else {
     MG_TRY(transfer_prolong<P>(c, l, w.x[l + 1], x, nrhs, 1, st));

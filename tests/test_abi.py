@@ -68,3 +68,8 @@ def test_setup_parameter_errors_without_gpu():
         p = params(group, iters)
         rc = lib.mg_setup(ctypes.byref(lat), ctypes.c_void_p(1), -0.3, ctypes.byref(p), ctypes.byref(h), None)
         assert rc == -1 and msg in lib.mg_last_error(), (group, iters, lib.mg_last_error())
+    # a transfer storage outside MG_F64..MG_F16 is refused the same way
+    p = params(0, 5)
+    p.transfer_prec = 7
+    rc = lib.mg_setup(ctypes.byref(lat), ctypes.c_void_p(1), -0.3, ctypes.byref(p), ctypes.byref(h), None)
+    assert rc == -6 and b"transfer_prec" in lib.mg_last_error(), lib.mg_last_error()  # MG_ENOTSUP

@@ -585,6 +585,57 @@ def test_vcycle_mr_q_recursion(cuda, pre, post):
 
 
 @pytest.mark.parametrize("case", ["2-level 8^4", "3-level 8^4"])
+def test_transfer_prec_f16(cuda, case):
+    """transfer_prec = MG_F16: the FP32 preconditioner's restrictions and
+    prolongations read the binary16 copy of P (FP32 arithmetic).  The cycle
+    against the oracle's within the FP16-storage bound (2e-3) and away from
+    the all-FP32 cycle by more than FP32 rounding (so the binary16 P is what
+    ran), for 1 and 3 right-hand sides with the vector and the matrix-core
+    transfers; the solve meets 1e-10 at the oracle's iteration count (within
+    one).  An unknown transfer_prec is refused."""
+    import paper_1005_3043_amd as mgwd
+    L, blocks, nv, eps, m, seed = _CYCLE_CASES[case]
+    U = W.gauge_field(L, eps, seed)
+    starts = W.setup_starts(L, nv[0], seed)
+    inits = [torch.from_numpy(starts).cuda()]
+    cst = None
+    if len(blocks) > 1:
+        Lc = tuple(L[mu] // blocks[0][mu] for mu in range(4))
+        cst = W.coarse_setup_starts(Lc, 2 * nv[0], nv[1], seed)
+        inits.append(torch.from_numpy(cst).cuda())
+    if case not in _CYCLE_ORACLE:
+        _CYCLE_ORACLE[case] = so.mg_setup(U, m, so.MGParams(blocks=blocks, nv=nv), starts, cst)
+    h = _CYCLE_ORACLE[case]
+    Ud = torch.from_numpy(U).cuda()
+    ctx = mgwd.MG(Ud, m, blocks, nv, inits, max_rhs=4, precond_prec="f32", transfer_prec="f16")
+    ref = mgwd.MG(Ud, m, blocks, nv, inits, max_rhs=4, precond_prec="f32")
+    try:
+        for nrhs in (1, 3):
+            r = W.gaussian_spinor(L, 23, batch=(nrhs,))
+            h.stats["cgnr_iters"] = []
+            zr = np.stack([h.vcycle(r[i], 0) for i in range(nrhs)])
+            z32, _ = ref.vcycle(torch.from_numpy(r).cuda(), "f32")
+            for var in (0, 1):
+                ctx.set_transfer_variant(var)
+                z, _ = ctx.vcycle(torch.from_numpy(r).cuda(), "f32")
+                e, d = _rel(z.cpu().numpy(), zr), _rel(z.cpu().numpy(), z32.cpu().numpy())
+                print(f"{case} {nrhs} RHS transfer variant {var}: binary16-P cycle {e:.2e} from the oracle, "
+                      f"{d:.2e} from the all-FP32 cycle")
+                assert e < 2e-3 and d > 1e-6
+        ctx.set_transfer_variant(-1)
+        b = W.gaussian_spinor(L, 1)
+        x, info, rc = ctx.solve(torch.from_numpy(b).cuda(), 1e-10)
+        res = np.linalg.norm(b - wi.apply_D(U, x.cpu().numpy(), m)) / np.linalg.norm(b)
+        _, it_ref, _, _ = so.mg_solve(h, b, 1e-10)
+        assert rc == 0 and res <= 1e-10 * 1.001 and abs(info["iters"][0] - it_ref) <= 1
+    finally:
+        ctx.close()
+        ref.close()
+    with pytest.raises(mgwd.MGError):
+        mgwd.MG(Ud, m, blocks, nv, inits, transfer_prec=7)
+
+
+@pytest.mark.parametrize("case", ["2-level 8^4", "3-level 8^4"])
 def test_vcycle_deferred_presmoothing(cuda, case):
     """With the matrix-core transfers the fine pre-smoothing (MR by the q
     recursion) leaves its combine pass to them: the restriction forms the
