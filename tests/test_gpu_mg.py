@@ -954,6 +954,29 @@ def test_graph_replay_matches_eager(cuda):
         assert torch.equal(xe, xg)
 
 
+def test_timing_probes(cuda):
+    """The timing entry points run on a context: the fine stencil in every
+    class and in the MR q-recursion form of the FP32 and FP16 classes (1 and
+    12 right-hand sides), the coarse stencil; each returns a positive mean
+    time, and the q-recursion form refuses the FP64 class."""
+    import paper_1005_3043_amd as mgwd
+    L, blocks, nv, eps, m, seed = CASES["8^4 b4^4 nv8"]
+    U = torch.from_numpy(W.gauge_field(L, eps, seed)).cuda()
+    st = torch.from_numpy(W.setup_starts(L, nv[0], seed)).cuda()
+    ctx = mgwd.MG(U, m, blocks, nv, [st], max_rhs=12)
+    try:
+        for nrhs in (1, 12):
+            for prec in ("f64", "f32", "f16"):
+                assert ctx.time_dslash(prec, nrhs, 3) > 0
+            for prec in ("f32", "f16"):
+                assert ctx.time_dslash_mrq(prec, nrhs, 3) > 0
+            assert ctx.time_coarse(1, "f32", nrhs, 3) > 0
+        with pytest.raises(mgwd.MGError):
+            ctx.time_dslash_mrq("f64", 12, 3)
+    finally:
+        ctx.close()
+
+
 def test_timing_does_not_change_results(cuda):
     import paper_1005_3043_amd as mgwd
     L, blocks, nv, eps, m, seed = CASES["8^4 b4^4 nv8"]
