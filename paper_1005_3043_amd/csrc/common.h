@@ -167,6 +167,28 @@ __host__ __device__ __forceinline__ void load_site(C (&v)[12], const h16 *__rest
   }
 }
 
+// The same with non-temporal loads, for input read once by the launch.
+template <typename C, typename T>
+__device__ __forceinline__ void load_site_nt(C (&v)[12], const T *__restrict__ f, uint32_t s) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const T *p = &f[fidx(s, c, 12)];
+    T e;
+    e.x = __builtin_nontemporal_load(&p->x);
+    e.y = __builtin_nontemporal_load(&p->y);
+    v[c] = cvt<C>(e);
+  }
+}
+template <typename C>
+__device__ __forceinline__ void load_site_nt(C (&v)[12], const h16 *__restrict__ f, uint32_t s) {
+  const float m = __builtin_nontemporal_load(reinterpret_cast<const float *>(&f[fidx(s, 12, 13)]));
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const h16 e = __builtin_bit_cast(h16, __builtin_nontemporal_load(reinterpret_cast<const float *>(&f[fidx(s, c, 13)])));
+    v[c] = mk<C>((float)e.x * m, (float)e.y * m);
+  }
+}
+
 // Stores the 12 components of site s (NT: non-temporal stores, for output
 // that the launch does not read again).  For binary16 storage the site's
 // scale is computed here and v is replaced by the values as stored (decoded),
