@@ -6,7 +6,10 @@ prolongator and Galerkin operator are checked by the oracle's own transfer,
 Wilson and coarse-stencil arithmetic on sampled vectors (D_c v = P^dag D P v,
 P^dag P = I per block).  24^3x48 with the twelve point sources in one batched
 solve, and the three-level 32^3x64 solve with twelve point sources: every
-right-hand side's true residual by the oracle's operator."""
+right-hand side's true residual by the oracle's operator.  On 32^3x64 also
+the FP32 null-vector relaxation, whose stencils are the smoother's in the
+benchmark's launch configuration (twelve right-hand sides per launch), on
+sampled vectors element by element against the oracle's relaxation."""
 import numpy as np
 import pytest
 import torch
@@ -14,6 +17,7 @@ import torch
 import workloads as W
 from oracle import coarse as co
 from oracle import cref
+from oracle import solvers as so
 from oracle import transfer as tr
 
 pytestmark = pytest.mark.gpu
@@ -97,13 +101,52 @@ def test_c2_twelve_point_sources_batched(cuda):
     assert rc == 0 and max(res) <= 1e-10 * 1.001
 
 
-def test_c3_three_level_point_sources(cuda):
-    import paper_1005_3043_amd as mgwd
+@pytest.fixture(scope="module")
+def c3(cuda):
+    """The 32^3x64 links and the 24 level-0 setup starts (host arrays)."""
     cfg = W.CONFIGS["C3"]
+    L = cfg["L"]
+    print("generating the 32^3x64 links and setup starts", flush=True)
+    return cfg, W.gauge_field(L, cfg["eps"], cfg["seed"]), W.setup_starts(L, cfg["nv"][0], cfg["seed"])
+
+
+@pytest.mark.timeout(300)
+def test_c3_fp32_relaxation_sampled(c3):
+    """Setup stage one in FP32 on 32^3x64 with the workload's 24 null vectors,
+    which the library relaxes in two batches of twelve: the FP32 stencil with
+    twelve right-hand sides per launch in its plain, MR and q-recursion
+    forms, the MR combine pass and the normalisation, all in the launch
+    configuration of the benchmark's smoothing (the lattice-chunked order of
+    the right-hand-side groups included, which small lattices do not reach).
+    One round of four MR steps; vectors 0 and 23 (first of the first batch,
+    last of the second) against the oracle's FP64 relaxation of the same
+    starts with the oracle's C operator, element by element.  Bound as on
+    the small lattices: a handful of FP32 operations per entry and step
+    after a 9-term stencil sum, about 50 u per step with u = 2^-24, so
+    4 x 50 x 6e-8 = 1.2e-5 < 1e-4; the lower bound shows FP32 arithmetic
+    ran."""
+    import paper_1005_3043_amd as mgwd
+    cfg, U_np, starts = c3
+    mass = W.mass_for("C3", 0.1)
+    ctx = mgwd.MG(torch.from_numpy(U_np).cuda(), mass, [cfg["blocks"][0]], [cfg["nv"][0]],
+                  [torch.from_numpy(starts).cuda()], setup_rounds=1, setup_mr_steps=4, setup_prec="f32",
+                  max_rhs=12)
+    Vg = ctx.export_nullvecs(0)
+    ctx.close()
+    A = lambda v: cref.apply_D(U_np, v, mass)  # noqa: E731
+    for k in (0, cfg["nv"][0] - 1):
+        Vo = so.relax_nullspace(A, starts[[k]], 1, 4)[0]
+        err = float(np.linalg.norm(Vg[k] - Vo) / np.linalg.norm(Vo))
+        print(f"32^3x64 FP32 relaxation, vector {k}: rel err {err:.2e}", flush=True)
+        assert 1e-9 < err < 1e-4
+
+
+def test_c3_three_level_point_sources(c3):
+    import paper_1005_3043_amd as mgwd
+    cfg, U_np, starts = c3
     L, blocks, nv = cfg["L"], cfg["blocks"], cfg["nv"]
-    U_np = W.gauge_field(L, cfg["eps"], cfg["seed"])
     mass = W.mass_for("C3", 0.01)
-    st = torch.from_numpy(W.setup_starts(L, nv[0], cfg["seed"])).cuda()
+    st = torch.from_numpy(starts).cuda()
     Lc = tuple(L[mu] // blocks[0][mu] for mu in range(4))
     st1 = torch.from_numpy(W.coarse_setup_starts(Lc, 2 * nv[0], nv[1], cfg["seed"])).cuda()
     ctx = mgwd.MG(torch.from_numpy(U_np).cuda(), mass, blocks, nv, [st, st1], max_rhs=12, precond_prec="f32")
