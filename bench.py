@@ -170,7 +170,11 @@ def kernel_probe(mgwd, torch, W):
     headline setup) the fine stencil with 12 right-hand sides per launch in
     each precision class, as the benchmark step launches it (the step's MR
     launches add per-tile partial sums, 24 bytes per tile and right-hand
-    side), and with one right-hand side."""
+    side), and with one right-hand side; then the coarse stencil of levels 1
+    and 2 and the fine-level restriction and prolongation with 12 right-hand
+    sides in the FP32 class (the kernels the autotuner picks for those shapes:
+    the matrix-core GEMMs; the transfers here without the V-cycle's fused
+    smoother terms)."""
     n = 1 << 27  # 1 GiB of float64
     a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
@@ -193,6 +197,21 @@ def kernel_probe(mgwd, torch, W):
     for prec in ("f32", "f16"):
         ms = ctx.time_dslash_mrq(prec, 12, 10)
         print(json.dumps({"probe": f"dslash_mrq_{prec}_12rhs", "launches": 12, "avg_ms": ms}), flush=True)
+    for level in (1, 2):
+        ms = ctx.time_coarse(level, "f32", 12, 10)
+        var, _ = ctx.coarse_variant(level, "f32", 12)
+        print(json.dumps({"probe": f"coarse_f32_level{level}_12rhs", "variant": var, "launches": 12, "avg_ms": ms}),
+              flush=True)
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    v = torch.randn((12, L[3], L[2], L[1], L[0], 4, 3), dtype=torch.complex128, device="cuda", generator=gen)
+    for _ in range(6):
+        vc = ctx.transfer(0, v, 0, "f32")
+        ctx.transfer(0, vc, 1, "f32")
+    torch.cuda.synchronize()
+    rv, pv, _ = ctx.transfer_variant("f32", 12)
+    print(json.dumps({"probe": "transfer_f32_12rhs", "restrict_variant": rv, "prolong_variant": pv, "launches": 6}),
+          flush=True)
+    del v, vc
     ctx.close()
 
 
