@@ -103,19 +103,66 @@ def test_wilson_full_size_sampled(cuda):
     assert err < 1e-12
 
 
+def _sampled_sites(L):
+    """2048 sites of L, seeded, the first eight on the lattice's corners and
+    faces (both time boundaries)."""
+    rng = np.random.default_rng(11)
+    sites = np.stack([rng.integers(0, L[mu], 2048) for mu in range(4)], 1)
+    sites[:8] = [(0, 0, 0, 0), (L[0] - 1, L[1] - 1, L[2] - 1, L[3] - 1), (0, L[1] - 1, 0, L[3] - 1),
+                 (L[0] - 1, 0, L[2] - 1, 0), (5, 0, 9, L[3] - 1), (0, 7, L[2] - 1, L[3] // 2),
+                 (L[0] - 1, L[1] - 1, 0, 1), (L[0] // 2, L[1] // 2, L[2] // 2, L[3] - 2)]
+    return sites
+
+
 def test_wilson_full_size_multi_rhs_sampled(cuda):
     """32^3 x 64 (the three-level workload lattice), five right-hand sides in
     one launch (a group of four and a ragged one): every right-hand side
     against the oracle's per-site evaluation on 2048 sampled sites."""
     L = (32, 32, 32, 64)
     U, psi, got = _run(L, 0.35, -1.05, "f64", nrhs=5)
-    rng = np.random.default_rng(11)
-    sites = np.stack([rng.integers(0, L[mu], 2048) for mu in range(4)], 1)
-    sites[:8] = [(0, 0, 0, 0), (31, 31, 31, 63), (0, 31, 0, 63), (31, 0, 31, 0), (5, 0, 9, 63),
-                 (0, 7, 31, 32), (31, 31, 0, 1), (16, 16, 16, 62)]
+    sites = _sampled_sites(L)
     ref = wi.apply_D_sites(U, psi, -1.05, sites)
     g = got[:, sites[:, 3], sites[:, 2], sites[:, 1], sites[:, 0]]
     for k in range(5):
         err = np.linalg.norm(g[k] - ref[k]) / np.linalg.norm(ref[k])
         print(f"wilson f64 32^3x64 rhs {k} sampled rel err {err:.3e}")
         assert err < 1e-12
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_wilson_full_size_twelve_rhs_sampled(cuda, prec):
+    """32^3 x 64 with twelve right-hand sides in one launch, in the FP32 and
+    FP16 classes: the launch configuration the preconditioner's plain
+    stencil takes there (two or three right-hand sides per thread, the
+    right-hand-side groups taken chunk by chunk of the lattice, which small
+    lattices do not reach), every right-hand side on 2048 sampled sites
+    against the oracle's per-site evaluation.  FP32: below 10^-6 of the FP64
+    operator (FP32 inputs, links and accumulation).  FP16 class: against the
+    oracle on the links rounded to binary16 and the input rounded as the
+    library stores it, with the bounds of the small-lattice test (the output's
+    binary16 rounding, 2^-11 in 2-norm; each entry within one binary16 unit
+    of its site's scale of the reference rounded the same way)."""
+    L = (32, 32, 32, 64)
+    print(f"32^3x64, 12 right-hand sides, {prec}", flush=True)
+    U, psi, got = _run(L, 0.35, -1.05, prec, nrhs=12)
+    sites = _sampled_sites(L)
+    g = got[:, sites[:, 3], sites[:, 2], sites[:, 1], sites[:, 0]]
+    if prec == "f32":
+        ref = wi.apply_D_sites(U, psi, -1.05, sites)
+        for k in range(12):
+            err = np.linalg.norm(g[k] - ref[k]) / np.linalg.norm(ref[k])
+            print(f"wilson f32 32^3x64 rhs {k} sampled rel err {err:.3e}")
+            assert 1e-9 < err < 1e-6
+        return
+    U16 = U.real.astype(np.float16).astype(np.float64) + 1j * U.imag.astype(np.float16).astype(np.float64)
+    xin, _ = _h16_round(psi)
+    ref = wi.apply_D_sites(U16, xin, -1.05, sites)
+    ref_r, m = _h16_round(ref)
+    for k in range(12):
+        err = np.linalg.norm(g[k] - ref[k]) / np.linalg.norm(ref[k])
+        ulp = np.max(np.abs(g[k] - ref_r[k]) / np.maximum(m[k], 1e-300)[..., None, None])
+        print(f"wilson f16 32^3x64 rhs {k} sampled rel err vs stored-input oracle {err:.2e}, "
+              f"largest entry difference {ulp * 1024:.2f} units of 2^-10 m")
+        assert 1e-6 < err < 2.0 ** -11 + 2e-6
+        assert ulp <= 2.0 ** -10 * 1.01
