@@ -756,12 +756,29 @@ __global__ __launch_bounds__(1024) void k_coarse_mma(Geom g, int n, const S *__r
   if (tid < 9) nbs[tid] = slot_site(g, s, tid);
   __syncthreads();
   {
-    const int jj = tid % n, tstep = (int)blockDim.x / n;
-    for (int t = tid / n; t < 9 * nrhs && jj < n && tid < tstep * n; t += tstep) {
-      const int r = t % nrhs, slot = t / nrhs;
-      float2 v = in[((size_t)r * g.V + nbs[slot]) * n + jj];
-      if (dagger && jj >= half) v = make_float2(-v.x, -v.y);
-      bl[(slot * n + jj) * nrhs + r] = v;
+    // A thread stages 9 nrhs / (blockDim / n) entries (up to 36): SU of
+    // them are loaded before any is stored, so that their round trips
+    // overlap instead of one load, wait and store after another (the
+    // 12-RHS level-1 stencil of 32^3 x 64: 0.400 -> 0.366 ms with SU = 8;
+    // 0.373 with 4, 0.369 with 16).
+    constexpr int SU = 8;
+    const int jj = tid % n, tstep = (int)blockDim.x / n, nt = 9 * nrhs;
+    const bool stager = tid < tstep * n;
+    for (int t0 = tid / n; stager && t0 < nt; t0 += SU * tstep) {
+      float2 v[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int t = t0 + u * tstep;
+        if (t < nt) v[u] = in[((size_t)(t % nrhs) * g.V + nbs[t / nrhs]) * n + jj];
+      }
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int t = t0 + u * tstep;
+        if (t < nt) {
+          const float2 w = (dagger && jj >= half) ? make_float2(-v[u].x, -v[u].y) : v[u];
+          bl[((t / nrhs) * n + jj) * nrhs + (t % nrhs)] = w;
+        }
+      }
     }
   }
   __syncthreads();
