@@ -20,13 +20,30 @@ static inline int sgrid(size_t n) {
 
 // --------------------------------------------------------------- finishers
 // Sum np partials of width w (stride w) for the RHS blockIdx.y into tot[0..w).
+// Each thread loads FU of its partials before adding them (fixed order), so
+// that their round trips overlap: with np = 8192 a thread takes 32, and one
+// dependent load after another made the MR step-length kernel take 16 us.
 template <int W>
 __device__ __forceinline__ void finish_sum(const double *__restrict__ part, int np, double (&tot)[W]) {
+  constexpr int FU = 8;
   __shared__ double lds[4 * W];
   part += (size_t)blockIdx.y * np * W;
 #pragma unroll
   for (int q = 0; q < W; ++q) tot[q] = 0.0;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+  const int bd = (int)blockDim.x;
+  int i = (int)threadIdx.x;
+  for (; i + (FU - 1) * bd < np; i += FU * bd) {
+    double v[FU][W];
+#pragma unroll
+    for (int u = 0; u < FU; ++u)
+#pragma unroll
+      for (int q = 0; q < W; ++q) v[u][q] = part[(size_t)(i + u * bd) * W + q];
+#pragma unroll
+    for (int u = 0; u < FU; ++u)
+#pragma unroll
+      for (int q = 0; q < W; ++q) tot[q] += v[u][q];
+  }
+  for (; i < np; i += bd) {
 #pragma unroll
     for (int q = 0; q < W; ++q) tot[q] += part[(size_t)i * W + q];
   }
