@@ -1,6 +1,6 @@
 """Parity at the workloads' full sizes, in the configurations bench.py runs.
 
-16^3x32 (the benchmark workload, FP16-stored preconditioner): the solution's
+16^3x32 (the two-level workload, FP16-stored preconditioner): the solution's
 true residual is recomputed by the oracle's operator; the exported
 prolongator and Galerkin operator are checked by the oracle's own transfer,
 Wilson and coarse-stencil arithmetic on sampled vectors (D_c v = P^dag D P v,
